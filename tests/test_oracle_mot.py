@@ -1,0 +1,117 @@
+"""Pins of the oracle's marching scheme (Sec. IV-B, V)."""
+import numpy as np
+import pytest
+
+from oracle import excitation as E
+from oracle import mot
+from oracle import operators as O
+from oracle.mie import mie_pec_rcs, rcs_from_current
+from workloads import meshes, waves
+
+
+def _wave(f0, diameter, k=(0.0, 0.0, -1.0), p=(1.0, 0.0, 0.0)):
+    return waves.Wave(k, p, 1.0, waves.mod_gauss_t0(f0, diameter), 0, 0.0, f0, f0)
+
+
+def test_march_is_block_forward_substitution():
+    xyz, tri = meshes.icosphere(0)
+    a = O.Assembly(xyz, tri, 0.2)
+    T = a.build()
+    r = E.rhs(a, _wave(0.1, a.D), 40)
+    y = mot.march(T, r)
+    yb = mot.block_solve(T, r)
+    assert np.abs(y - yb).max() < 1e-11 * np.abs(yb).max()
+
+
+def test_post_processing_from_q_basis():
+    """eq. post_processing equals (P^{LH} + d~_t P^Sigma) y(t) at t_i, with y
+    expanded in h_i P^{LH} + q_i P^Sigma and q_i' from the Sec. IV-A q_0."""
+    rng = np.random.default_rng(3)
+    n, N, dt, T0 = 5, 12, 0.3, 2.0
+    PS = rng.standard_normal((n, n))
+    PS = PS @ PS.T
+    PLH = np.eye(n) - 0.1 * PS
+    y = rng.standard_normal((N, n))
+
+    def q0p(t):  # derivative of q_0 written from its definition
+        x = t / dt
+        return np.where((t >= -dt) & (t < 0), (x + 1) / dt,
+                        np.where((t >= 0) & (t < dt), (1 - 2 * x) / dt,
+                                 np.where((t >= dt) & (t <= 2 * dt), (x - 2) / dt, 0.0)))
+
+    j = mot.currents(PLH, PS, dt / T0, y)
+    for i in range(1, N + 1):
+        ti = i * dt
+        direct = PLH @ y[i - 1] + sum(T0 * q0p(ti - l * dt) * (PS @ y[l - 1]) for l in range(1, N + 1))
+        assert np.abs(direct - j[i - 1]).max() < 1e-12 * (1 + np.abs(direct).max())
+
+
+def test_late_time_decay_sphere():
+    """qHP TD-CFIE on a sphere: after the pulse the current keeps decaying
+    with no floor (Sec. V-A)."""
+    xyz, tri = meshes.icosphere(1)
+    a = O.Assembly(xyz, tri, 0.1)
+    T = a.build()
+    r = E.rhs(a, _wave(0.1, a.D), 1500)
+    j = mot.currents(a.proj.PLH, a.proj.PS, a.dtn, mot.march(T, r))
+    nj = np.linalg.norm(j, axis=1)
+    peak = nj.max()
+    assert nj[-1] < 1e-20 * peak
+    blocks = nj[300:].reshape(-1, 100).max(1)
+    assert np.all(np.diff(np.log10(blocks)) < 0.5)  # no sustained growth
+
+
+def test_no_growth_torus():
+    """Torus (two global loops): solution stays bounded and decays over
+    thousands of steps (Sec. V-B)."""
+    xyz, tri = meshes.torus(1.0, 0.4, 12, 6)
+    a = O.Assembly(xyz, tri, 0.1)
+    T = a.build()
+    r = E.rhs(a, _wave(0.1, a.D), 3000)
+    j = mot.currents(a.proj.PLH, a.proj.PS, a.dtn, mot.march(T, r))
+    nj = np.linalg.norm(j, axis=1)
+    assert nj[-500:].max() < 1e-12 * nj.max()
+    blocks = nj[500:].reshape(-1, 250).max(1)
+    assert np.all(blocks[1:] < 10 * blocks[:-1])
+
+
+def test_companion_spectrum_inside_unit_circle():
+    """Polynomial eigenvalues of the marching system lie strictly inside the
+    unit circle (Sec. V-A, qHP TD-CFIE)."""
+    xyz, tri = meshes.icosphere(0)
+    a = O.Assembly(xyz, tri, 0.25)
+    T = a.build()
+    K, n = T.shape[0] - 1, T.shape[1]
+    T0i = np.linalg.inv(T[0])
+    comp = np.zeros((K * n, K * n))
+    for k in range(1, K + 1):
+        comp[:n, (k - 1) * n:k * n] = -T0i @ T[k]
+    comp[n:, :-n] = np.eye((K - 1) * n)
+    rho = np.abs(np.linalg.eigvals(comp)).max()
+    assert rho < 1.0
+
+
+def test_far_field_against_mie_series():
+    """Sphere, ka ~ 1: the transient current's far field at an in-band
+    frequency matches the Mie series (Sec. V-A, Fig. farfield)."""
+    xyz, tri = meshes.icosphere(2)
+    dt = 0.05
+    a = O.Assembly(xyz, tri, dt)
+    T = a.build()
+    f0 = waves.hz_to_per_m(50e6)
+    w = _wave(f0, a.D)
+    n_steps = 600
+    r = E.rhs(a, w, n_steps)
+    j = mot.currents(a.proj.PLH, a.proj.PS, a.dtn, mot.march(T, r))
+    th = np.linspace(0.05, np.pi - 0.05, 13)
+    kdir = np.array(w.k_hat)
+    pdir = np.array(w.pol)
+    hdir = np.cross(kdir, pdir)
+    dE = np.array([np.cos(t) * kdir + np.sin(t) * pdir for t in th])
+    dH = np.array([np.cos(t) * kdir + np.sin(t) * hdir for t in th])
+    sE = rcs_from_current(a, j, w, f0, dE)
+    sH = rcs_from_current(a, j, w, f0, dH)
+    mE, mH = mie_pec_rcs(2 * np.pi * f0, th)
+    errE = np.sqrt(np.mean((sE - mE) ** 2) / np.mean(mE ** 2))
+    errH = np.sqrt(np.mean((sH - mH) ** 2) / np.mean(mH ** 2))
+    assert errE < 0.05 and errH < 0.05, (errE, errH)
