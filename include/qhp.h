@@ -1,0 +1,166 @@
+/*
+ * qhp.h -- C ABI of the MI355X (gfx950) marching-on-in-time solver for the
+ * quasi-Helmholtz-projector stabilised time-domain combined field integral
+ * equation (qHP TD-CFIE) of Le, Cordel, Andriulli and Cools, arXiv 2312.06367.
+ *
+ * Units are normalised: c = 1 (time is measured as c*t in metres) and the
+ * background impedance eta = 1.  Hence T0 = D (scatterer diameter),
+ * kappa = 1/dt and dt~ = dt/D (Sec. II-B, III-A).
+ *
+ * Conventions for every entry point:
+ *   - return value: QHP_OK (0) or a negative QHP_E* code; qhp_last_error()
+ *     then holds a message.  A failed call leaves the context in the state it
+ *     had before the call, except that a failed qhp_step/qhp_run stops the
+ *     march (further steps return QHP_ESTATE until qhp_set_incident).
+ *   - host pointers are read or written during the call only; the library
+ *     keeps no caller pointer.  Pointers documented as "device" must be device
+ *     memory of the context's GPU; the library orders its use on the
+ *     context's stream and the call returns when the work is complete.
+ *   - the context owns all of its device memory (hipMalloc) and frees it in
+ *     qhp_destroy.  All work is issued on params.stream (NULL: null stream).
+ *   - order: create -> mesh -> assemble -> set_incident -> step/run; other
+ *     orders return QHP_ESTATE.  set_incident may be repeated (restarts the
+ *     march at step 0).  Contexts are not thread-safe.
+ *   - dense matrices are row-major.
+ */
+#ifndef QHP_H
+#define QHP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    QHP_OK = 0,
+    QHP_EINVAL = -1,    /* bad argument                                       */
+    QHP_EMESH = -2,     /* open, non-manifold, inconsistently oriented or
+                           disconnected mesh, or a zero-area triangle          */
+    QHP_ESTATE = -3,    /* call out of order                                  */
+    QHP_ENOMEM = -4,    /* device allocation failed                           */
+    QHP_EDEVICE = -5,   /* HIP runtime error                                  */
+    QHP_ESINGULAR = -6, /* zero pivot in an LU factorisation                  */
+    QHP_ENOCONV = -7,   /* reserved for iterative solvers                     */
+    QHP_EUNSTABLE = -8  /* non-finite value in the marching solution          */
+};
+
+/* storage of the lag blocks T_k, k >= 1 (T_0 is always kept in FP64) */
+enum { QHP_F64 = 0, QHP_F32 = 1, QHP_BF16 = 2 };
+
+/* per-step solve with T_0 (the paper writes only T_0^{-1}, Sec. IV-B) */
+enum {
+    QHP_SOLVE_LU = 0, /* LU with partial pivoting once, two triangular solves per step */
+    QHP_SOLVE_INV = 1 /* inverse formed once from that LU, one product per step       */
+};
+
+typedef struct qhp_ctx qhp_ctx;
+
+typedef struct {
+    double dt;         /* c*dt in metres, > 0                                     */
+    double eta_c;      /* coupling of eq. qHP_TDCFIE (the paper's eta^2; 1 here)  */
+    int32_t precision; /* QHP_F64 / QHP_F32 / QHP_BF16                             */
+    int32_t solver;    /* QHP_SOLVE_LU / QHP_SOLVE_INV                            */
+    int32_t n_psi;     /* angular Gauss points per sub-interval; <= 0 means 10    */
+    int32_t device;    /* HIP device ordinal                                       */
+    void *stream;      /* hipStream_t, or NULL                                     */
+} qhp_params;
+
+/* One incident plane wave (Sec. V); u = t - t0 - k_hat . r
+ *   pulse 0: amplitude pol cos(2 pi f0 u) exp(-u^2/(2 sig^2)), sig = 1/(2 pi bw)
+ *   pulse 1: (4 amplitude/(w sqrt(pi))) pol exp(-((4/w) u)^2)   (the paper's)
+ * f0, bw in cycles per metre of c*t; h_in = k_hat x e_in (eta = 1). */
+typedef struct {
+    double k_hat[3];
+    double pol[3];
+    double amplitude;
+    double t0;
+    int32_t pulse;
+    double w;
+    double f0;
+    double bw;
+} qhp_wave;
+
+typedef struct {
+    int64_t nv, ne, nc;  /* vertices, edges (= unknowns), triangles          */
+    int64_t n_harmonic;  /* 2 - Euler characteristic (global loops)          */
+    int64_t K;           /* T_k = 0 for k > K                                */
+    int64_t n_rhs;       /* right-hand sides after set_incident              */
+    int64_t n_steps;     /* steps with a right-hand side                     */
+    int64_t step;        /* steps done since set_incident                    */
+    int64_t ld;          /* row stride (elements) of the stored slabs        */
+    double diameter;     /* D = largest vertex-vertex distance               */
+    size_t slab_bytes;   /* device bytes of the stored T_1..T_K              */
+} qhp_info;
+
+/* Create a context (no device work beyond selecting params->device).
+ * *out receives the handle; QHP_EINVAL for dt <= 0 or an unknown enum. */
+int qhp_create(const qhp_params *params, qhp_ctx **out);
+
+/* Mesh of the scatterer surface Gamma (Sec. II-A: closed, connected,
+ * orientable), host arrays: xyz [nv][3] metres, tri [nc][3] vertex indices,
+ * counter-clockwise seen from outside.  Builds the edge numbering (edges
+ * sorted by (min, max) vertex, oriented min -> max; c+ is the triangle whose
+ * vertex cycle runs v- -> v+), Lambda and Sigma (Sec. II-D), the barycentric
+ * refinement and the BC coefficients (Sec. II-C).  QHP_EMESH on an invalid
+ * mesh. */
+int qhp_mesh(qhp_ctx *ctx, const double *xyz, int64_t nv, const int32_t *tri, int64_t nc);
+
+/* Assemble on the GPU: projectors (Sec. II-D, FP64), Gram, Yukawa operators
+ * (Sec. II-C), Z~ and X~ (Sec. III-B, III-C), the lag blocks T_0..T_K of eq.
+ * dis_TD_CFIE (Sec. IV-A) by semi-analytic quadrature, stores T_1..T_K in the
+ * chosen precision and factorises T_0 (FP64 LU).  QHP_ESINGULAR on a zero
+ * pivot, QHP_ENOMEM when the slabs do not fit. */
+int qhp_assemble(qhp_ctx *ctx);
+
+/* Right-hand sides r_k = -Z~ G^-T e~(t_k) + eta_c X~ G^-1 h(t_k), k = 1..n_steps
+ * (Sec. IV-A), for n_rhs waves (host array).  Resets the march to step 0. */
+int qhp_set_incident(qhp_ctx *ctx, const qhp_wave *waves, int32_t n_rhs, int32_t n_steps);
+
+/* One marching step (Sec. IV-B): y_i = T_0^{-1}(r_i - sum_{k=1}^{K} T_k y_{i-k})
+ * and j_i = P^{LH} y_i + dt~^{-1} P^Sigma (y_i - y_{i-1}) (eq. post_processing).
+ * j_out: device [ne][n_rhs] FP64 or NULL.  QHP_EUNSTABLE on a non-finite
+ * value; QHP_ESTATE past n_steps. */
+int qhp_step(qhp_ctx *ctx, double *j_out);
+
+/* n_steps marching steps.  j_hist / y_hist: device [n_steps][ne][n_rhs] FP64
+ * or NULL (step i of the call at index i). */
+int qhp_run(qhp_ctx *ctx, int32_t n_steps, double *j_hist, double *y_hist);
+
+int qhp_query(const qhp_ctx *ctx, qhp_info *info);
+
+/* Host arrays: edges [ne][2] = (v-, v+), cells [ne][2] = (c+, c-). */
+int qhp_edges(const qhp_ctx *ctx, int32_t *edges, int32_t *cells);
+
+/* Copy an assembled FP64 matrix to host memory out [ne][ne] (parity checks):
+ *   which = QHP_MAT_*; k is the lag for the slab and raw lag matrices (raw
+ *   lag matrices A_k, B_k, C_k only if qhp_keep_raw(ctx, 1) preceded
+ *   qhp_assemble).  Slabs stored in F32/BF16 are returned dequantised. */
+enum {
+    QHP_MAT_GRAM = 0, QHP_MAT_ZS = 1, QHP_MAT_ZH = 2, QHP_MAT_M = 3,
+    QHP_MAT_PSIGMA = 4, QHP_MAT_PLAMBDA = 5, QHP_MAT_PE = 6, QHP_MAT_PM = 7,
+    QHP_MAT_SLAB = 8, QHP_MAT_A = 9, QHP_MAT_B = 10, QHP_MAT_C = 11
+};
+int qhp_get_matrix(const qhp_ctx *ctx, int32_t which, int32_t k, double *out);
+int qhp_keep_raw(qhp_ctx *ctx, int32_t keep);
+
+/* The per-step history sum on caller buffers (all device, on `stream`):
+ *   b = r - sum_{k=1}^{kmax} T_k y_{i-k}              (Sec. IV-B)
+ * slabs: [kmax][ne][ld] in `precision` (T_k at index k-1), ld >= ne, a
+ *   multiple of 8; scales: [kmax] FP32 per-slab factors for QHP_BF16 (T_k =
+ *   scale * stored), else NULL;
+ * ring: [n_slots][ne][nrhs] FP64 for QHP_F64, FP32 otherwise; y_{i-k} is slot
+ *   (head + k - 1) mod n_slots, n_slots >= kmax;
+ * r, b: [ne][nrhs] FP64.  nrhs >= 1.  The library owns no buffer here. */
+int qhp_history_sum(void *stream, int32_t precision, int64_t ne, int64_t ld, int64_t nrhs,
+                    int64_t kmax, const void *slabs, const float *scales, const void *ring,
+                    int64_t n_slots, int64_t head, const double *r, double *b);
+
+const char *qhp_last_error(const qhp_ctx *ctx);
+void qhp_destroy(qhp_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,197 @@
+"""MI355X (gfx950) marching-on-in-time solver for the qHP TD-CFIE.
+
+Thin ctypes binding of ``libqhp.so`` (C ABI in ``include/qhp.h``): argument
+marshalling only; every step of the method runs in the library's HIP kernels.
+PyTorch supplies device memory and the stream.  Importing this package fails
+loudly when the shared library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqhp.so")
+
+QHP_F64, QHP_F32, QHP_BF16 = 0, 1, 2
+QHP_SOLVE_LU, QHP_SOLVE_INV = 0, 1
+MAT = {"gram": 0, "zs": 1, "zh": 2, "m": 3, "psigma": 4, "plambda": 5, "pe": 6, "pm": 7,
+       "slab": 8, "a": 9, "b": 10, "c": 11}
+ERRORS = {0: "OK", -1: "EINVAL", -2: "EMESH", -3: "ESTATE", -4: "ENOMEM", -5: "EDEVICE",
+          -6: "ESINGULAR", -7: "ENOCONV", -8: "EUNSTABLE"}
+PRECISIONS = {"f64": QHP_F64, "f32": QHP_F32, "bf16": QHP_BF16}
+SOLVERS = {"lu": QHP_SOLVE_LU, "inv": QHP_SOLVE_INV}
+
+
+class QhpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (ERRORS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("eta_c", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("solver", ctypes.c_int32), ("n_psi", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
+
+
+class _Wave(ctypes.Structure):
+    _fields_ = [("k_hat", ctypes.c_double * 3), ("pol", ctypes.c_double * 3), ("amplitude", ctypes.c_double),
+                ("t0", ctypes.c_double), ("pulse", ctypes.c_int32), ("w", ctypes.c_double),
+                ("f0", ctypes.c_double), ("bw", ctypes.c_double)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("nv", ctypes.c_int64), ("ne", ctypes.c_int64), ("nc", ctypes.c_int64),
+                ("n_harmonic", ctypes.c_int64), ("K", ctypes.c_int64), ("n_rhs", ctypes.c_int64),
+                ("n_steps", ctypes.c_int64), ("step", ctypes.c_int64), ("ld", ctypes.c_int64),
+                ("diameter", ctypes.c_double), ("slab_bytes", ctypes.c_size_t)]
+
+
+EXPORTS = ["qhp_create", "qhp_mesh", "qhp_assemble", "qhp_set_incident", "qhp_step", "qhp_run",
+           "qhp_query", "qhp_edges", "qhp_get_matrix", "qhp_keep_raw", "qhp_history_sum",
+           "qhp_last_error", "qhp_destroy"]
+
+_lib = None
+
+
+def lib():
+    """Load libqhp.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libqhp.so not built: run `python -m paper_2312_06367_amd.build` "
+                              "(or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        L.qhp_create.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(vp)]
+        L.qhp_mesh.argtypes = [vp, vp, i64, vp, i64]
+        L.qhp_assemble.argtypes = [vp]
+        L.qhp_set_incident.argtypes = [vp, ctypes.POINTER(_Wave), i32, i32]
+        L.qhp_step.argtypes = [vp, vp]
+        L.qhp_run.argtypes = [vp, i32, vp, vp]
+        L.qhp_query.argtypes = [vp, ctypes.POINTER(_Info)]
+        L.qhp_edges.argtypes = [vp, vp, vp]
+        L.qhp_get_matrix.argtypes = [vp, i32, i32, vp]
+        L.qhp_keep_raw.argtypes = [vp, i32]
+        L.qhp_history_sum.argtypes = [vp, i32, i64, i64, i64, i64, vp, vp, vp, i64, i64, vp, vp]
+        L.qhp_last_error.argtypes = [vp]
+        L.qhp_last_error.restype = ctypes.c_char_p
+        L.qhp_destroy.argtypes = [vp]
+        L.qhp_destroy.restype = None
+        for name in EXPORTS[:-2]:
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def to_cwave(w) -> _Wave:
+    cw = _Wave()
+    g = (lambda k: w[k]) if isinstance(w, dict) else (lambda k: getattr(w, k))
+    for i in range(3):
+        cw.k_hat[i] = float(g("k_hat")[i])
+        cw.pol[i] = float(g("pol")[i])
+    cw.amplitude, cw.t0, cw.pulse = float(g("amplitude")), float(g("t0")), int(g("pulse"))
+    cw.w, cw.f0, cw.bw = float(g("w")), float(g("f0")), float(g("bw"))
+    return cw
+
+
+class Solver:
+    """One scatterer and time step on one GPU (see include/qhp.h)."""
+
+    def __init__(self, dt: float, precision: str = "f64", solver: str = "lu", n_psi: int = 10,
+                 eta_c: float = 1.0, device: int = 0, stream=None):
+        import torch
+        self.L = lib()
+        torch.cuda.set_device(device)
+        p = _Params(float(dt), float(eta_c), PRECISIONS[precision], SOLVERS[solver], int(n_psi),
+                    int(device), stream if stream is not None else _stream())
+        self._p = p
+        h = ctypes.c_void_p()
+        self._check(self.L.qhp_create(ctypes.byref(p), ctypes.byref(h)), None)
+        self.h = h
+        self.device = device
+        self.precision = precision
+
+    def _check(self, rc, h="self"):
+        if rc != 0:
+            hh = self.h if h == "self" else h
+            msg = self.L.qhp_last_error(hh).decode() if hh else ""
+            raise QhpError(rc, msg)
+
+    def mesh(self, xyz, tri):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        tri = np.ascontiguousarray(tri, dtype=np.int32)
+        self._check(self.L.qhp_mesh(self.h, xyz.ctypes.data, len(xyz), tri.ctypes.data, len(tri)))
+
+    def keep_raw(self, flag=True):
+        self._check(self.L.qhp_keep_raw(self.h, int(bool(flag))))
+
+    def assemble(self):
+        self._check(self.L.qhp_assemble(self.h))
+
+    def set_incident(self, waves, n_steps: int):
+        arr = (_Wave * len(waves))(*[to_cwave(w) for w in waves])
+        self._check(self.L.qhp_set_incident(self.h, arr, len(waves), int(n_steps)))
+
+    def step(self, j_out=None):
+        self._check(self.L.qhp_step(self.h, _ptr(j_out)))
+
+    def run(self, n_steps: int, j_hist=None, y_hist=None):
+        self._check(self.L.qhp_run(self.h, int(n_steps), _ptr(j_hist), _ptr(y_hist)))
+
+    def info(self) -> dict:
+        inf = _Info()
+        self._check(self.L.qhp_query(self.h, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in _Info._fields_}
+
+    def edges(self):
+        ne = self.info()["ne"]
+        e = np.zeros((ne, 2), dtype=np.int32)
+        c = np.zeros((ne, 2), dtype=np.int32)
+        self._check(self.L.qhp_edges(self.h, e.ctypes.data, c.ctypes.data))
+        return e, c
+
+    def get_matrix(self, which: str, k: int = 0) -> np.ndarray:
+        ne = self.info()["ne"]
+        out = np.zeros((ne, ne), dtype=np.float64)
+        self._check(self.L.qhp_get_matrix(self.h, MAT[which], int(k), out.ctypes.data))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.qhp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def history_sum(precision: str, slabs, scales, ring, head: int, r, b, kmax: int | None = None):
+    """b = r - sum_{k=1}^{kmax} T_k y_{i-k} on caller tensors (see qhp_history_sum).
+
+    slabs: [kmax, ne, ld] (float64 / float32 / bfloat16), scales: float32 [kmax]
+    (bfloat16 only), ring: [n_slots, ld, nrhs] float64 (f64) or float32,
+    r, b: float64 [ne, nrhs]."""
+    L = lib()
+    kmax = slabs.shape[0] if kmax is None else kmax
+    ne, ld = slabs.shape[1], slabs.shape[2]
+    nrhs = r.shape[1] if r.dim() == 2 else 1
+    rc = L.qhp_history_sum(_stream(), PRECISIONS[precision], ne, ld, nrhs, kmax, _ptr(slabs), _ptr(scales),
+                           _ptr(ring), ring.shape[0], int(head), _ptr(r), _ptr(b))
+    if rc != 0:
+        raise QhpError(rc, "qhp_history_sum")

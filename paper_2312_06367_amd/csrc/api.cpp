@@ -1,0 +1,749 @@
+// C ABI of the qHP TD-CFIE marching solver: context, state machine and the
+// orchestration of the gfx950 kernels (see include/qhp.h for the contract).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "assembly.h"
+#include "linalg.h"
+#include "march.h"
+#include "qhp_internal.h"
+
+namespace {
+
+struct Fail {
+    int code;
+    std::string msg;
+};
+
+void hip_check(hipError_t e, const char *what)
+{
+    if (e != hipSuccess) throw Fail{e == hipErrorOutOfMemory ? QHP_ENOMEM : QHP_EDEVICE,
+                                    std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+// device allocation owned by a context
+struct DBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    void alloc(size_t n)
+    {
+        release();
+        if (n == 0) n = 8;
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            throw Fail{QHP_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed"};
+        }
+        bytes = n;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T>
+    T *as() const { return (T *)p; }
+    ~DBuf() { release(); }
+};
+
+template <class T>
+void upload(DBuf &b, const std::vector<T> &v, hipStream_t s)
+{
+    b.alloc(sizeof(T) * std::max<size_t>(v.size(), 1));
+    if (!v.empty()) hip_check(hipMemcpyAsync(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s), "upload");
+}
+
+// Gauss-Legendre nodes on [-1, 1] by Newton iteration on P_n.
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
+{
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(pi * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 1; k < n; ++k) {
+                double p2 = ((2.0 * k + 1.0) * z * p1 - k * p0) / (k + 1.0);
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        x[n - 1 - i] = z;
+        w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+}  // namespace
+
+struct qhp_ctx {
+    qhp_params p{};
+    hipStream_t s = nullptr;
+    int state = 0;  // 0 created, 1 meshed, 2 assembled, 3 incident set
+    std::string err;
+    bool keep_raw = false;
+    qhp::Mesh mesh;
+    int64_t K = 0, ld = 0;
+    double T0 = 0, dtn = 0, kappa = 0;
+    // device tables
+    DBuf t_xyz, t_tri, t_edges, t_cells, t_tri_edge, t_tri_sign, t_area, t_valence, t_fxyz, t_ftri, t_fparent,
+        t_fowner, t_bc_off, t_bc_edge, t_bc_local, t_bc_flux, t_vcell_off, t_vcell_tri, t_vedge_off, t_vedge,
+        t_bct_off, t_bct_entry, t_bc_tri;
+    qhp::AsmArgs args{};
+    // assembled operators (FP64, row-major)
+    DBuf G, Zs, Zh, M, PS, PPL, Pcat, LSp;
+    DBuf slabs, scales_d, T0raw, LU0, ipiv0, perm0, Linv, Uinv, Tinv;
+    std::vector<float> scales;
+    std::vector<std::vector<double>> rawA, rawB, rawC;
+    // march state
+    int32_t nrhs = 0;
+    int64_t n_steps = 0, step = 0, head = 0;
+    bool broken = false;
+    DBuf waves_d, rhs, ring64, ring32, bvec, zvec, yvec, partial, sv, zc, flags, epoch, errflag;
+    int nsplit = 1;
+};
+
+using qhp::AsmArgs;
+
+static int guard(qhp_ctx *ctx, int code, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+#define API_TRY try {
+#define API_CATCH(ctx)                                          \
+    }                                                           \
+    catch (const Fail &f) { return guard(ctx, f.code, f.msg); } \
+    catch (const std::bad_alloc &) { return guard(ctx, QHP_ENOMEM, "host allocation failed"); }
+
+extern "C" int qhp_create(const qhp_params *params, qhp_ctx **out)
+{
+    if (!params || !out) return QHP_EINVAL;
+    if (!(params->dt > 0.0) || params->precision < QHP_F64 || params->precision > QHP_BF16 ||
+        params->solver < QHP_SOLVE_LU || params->solver > QHP_SOLVE_INV || params->n_psi > 32)
+        return QHP_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || params->device < 0 || params->device >= ndev)
+        return QHP_EDEVICE;
+    qhp_ctx *c = new qhp_ctx();
+    c->p = *params;
+    if (c->p.n_psi <= 0) c->p.n_psi = 10;
+    if (!(c->p.eta_c > 0.0)) c->p.eta_c = 1.0;
+    c->s = (hipStream_t)params->stream;
+    if (hipSetDevice(params->device) != hipSuccess) {
+        delete c;
+        return QHP_EDEVICE;
+    }
+    *out = c;
+    return QHP_OK;
+}
+
+extern "C" void qhp_destroy(qhp_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->p.device);
+    if (ctx->s) (void)hipStreamSynchronize(ctx->s);
+    else (void)hipDeviceSynchronize();
+    delete ctx;
+}
+
+extern "C" const char *qhp_last_error(const qhp_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+extern "C" int qhp_keep_raw(qhp_ctx *ctx, int32_t keep)
+{
+    if (!ctx) return QHP_EINVAL;
+    ctx->keep_raw = keep != 0;
+    return QHP_OK;
+}
+
+extern "C" int qhp_mesh(qhp_ctx *ctx, const double *xyz, int64_t nv, const int32_t *tri, int64_t nc)
+{
+    if (!ctx || !xyz || !tri) return guard(ctx, QHP_EINVAL, "null argument");
+    if (ctx->state != 0) return guard(ctx, QHP_ESTATE, "mesh already set");
+    API_TRY
+    qhp::Mesh m;
+    std::string err;
+    int rc = qhp::build_mesh(xyz, nv, tri, nc, m, err);
+    if (rc != QHP_OK) return guard(ctx, rc, err);
+    for (int64_t v = 0; v < m.nv; ++v)
+        if (m.valence[v] > qhp::kMaxValence) return guard(ctx, QHP_EMESH, "vertex valence above the supported maximum");
+    ctx->mesh = std::move(m);
+    ctx->state = 1;
+    return QHP_OK;
+    API_CATCH(ctx)
+}
+
+static void upload_tables(qhp_ctx *c)
+{
+    const qhp::Mesh &m = c->mesh;
+    hipStream_t s = c->s;
+    upload(c->t_xyz, m.xyz, s);
+    upload(c->t_tri, m.tri, s);
+    upload(c->t_edges, m.edges, s);
+    upload(c->t_cells, m.cells, s);
+    upload(c->t_tri_edge, m.tri_edge, s);
+    upload(c->t_tri_sign, m.tri_sign, s);
+    upload(c->t_area, m.area, s);
+    upload(c->t_valence, m.valence, s);
+    upload(c->t_fxyz, m.fxyz, s);
+    upload(c->t_ftri, m.ftri, s);
+    upload(c->t_fparent, m.fparent, s);
+    upload(c->t_fowner, m.fowner, s);
+    upload(c->t_bc_off, m.bc_off, s);
+    upload(c->t_bc_edge, m.bc_edge, s);
+    upload(c->t_bc_local, m.bc_local, s);
+    upload(c->t_bc_flux, m.bc_flux, s);
+    upload(c->t_vcell_off, m.vcell_off, s);
+    upload(c->t_vcell_tri, m.vcell_tri, s);
+    upload(c->t_vedge_off, m.vedge_off, s);
+    upload(c->t_vedge, m.vedge, s);
+    // transposed BC table: entries of each BC function, and entry -> fine triangle
+    std::vector<int32_t> cnt(m.ne + 1, 0), bc_tri(m.bc_edge.size());
+    for (int64_t t = 0; t < m.nf; ++t)
+        for (int32_t e = m.bc_off[t]; e < m.bc_off[t + 1]; ++e) {
+            bc_tri[e] = (int32_t)t;
+            cnt[m.bc_edge[e] + 1]++;
+        }
+    for (int64_t i = 0; i < m.ne; ++i) cnt[i + 1] += cnt[i];
+    std::vector<int32_t> fillp(cnt.begin(), cnt.end() - 1), ent(m.bc_edge.size());
+    for (size_t e = 0; e < m.bc_edge.size(); ++e) ent[fillp[m.bc_edge[e]]++] = (int32_t)e;
+    upload(c->t_bct_off, cnt, s);
+    upload(c->t_bct_entry, ent, s);
+    upload(c->t_bc_tri, bc_tri, s);
+    AsmArgs &a = c->args;
+    a.nv = m.nv; a.ne = m.ne; a.nc = m.nc; a.nf = m.nf;
+    a.xyz = c->t_xyz.as<double>(); a.tri = c->t_tri.as<int32_t>(); a.edges = c->t_edges.as<int32_t>();
+    a.cells = c->t_cells.as<int32_t>(); a.tri_edge = c->t_tri_edge.as<int32_t>();
+    a.tri_sign = c->t_tri_sign.as<int32_t>(); a.area = c->t_area.as<double>();
+    a.valence = c->t_valence.as<int32_t>(); a.fxyz = c->t_fxyz.as<double>(); a.ftri = c->t_ftri.as<int32_t>();
+    a.fparent = c->t_fparent.as<int32_t>(); a.fowner = c->t_fowner.as<int32_t>();
+    a.bc_off = c->t_bc_off.as<int32_t>(); a.bc_edge = c->t_bc_edge.as<int32_t>();
+    a.bc_local = c->t_bc_local.as<int32_t>(); a.bc_flux = c->t_bc_flux.as<double>();
+    a.vcell_off = c->t_vcell_off.as<int32_t>(); a.vcell_tri = c->t_vcell_tri.as<int32_t>();
+    a.vedge_off = c->t_vedge_off.as<int32_t>(); a.vedge = c->t_vedge.as<int32_t>();
+    a.bct_off = c->t_bct_off.as<int32_t>(); a.bct_entry = c->t_bct_entry.as<int32_t>();
+    a.bc_tri = c->t_bc_tri.as<int32_t>();
+    a.dt = c->p.dt;
+    a.coplanar_tol = 1e-12;
+    a.ng = c->p.n_psi;
+}
+
+static void zero(DBuf &b, hipStream_t s) { hip_check(hipMemsetAsync(b.p, 0, b.bytes, s), "memset"); }
+
+// (L + 11^T/n)^{-1} - 11^T/n for the graph Laplacian held (with 1/n added) in L
+static void laplacian_pinv(qhp_ctx *c, int64_t n, DBuf &L, DBuf &out)
+{
+    DBuf piv, info;
+    piv.alloc(sizeof(int32_t) * n);
+    info.alloc(sizeof(int));
+    int rc = qhp::getrf_f64(c->s, n, L.as<double>(), n, piv.as<int32_t>(), info.as<int>());
+    if (rc != 0) throw Fail{QHP_ESINGULAR, "graph Laplacian factorisation hit a zero pivot"};
+    out.alloc(sizeof(double) * n * n);
+    qhp::eye_plus(c->s, n, 1.0, 0.0, L.as<double>(), out.as<double>());
+    qhp::getrs_f64(c->s, false, n, n, L.as<double>(), n, piv.as<int32_t>(), out.as<double>(), n);
+    qhp::launch_sub_const(c->s, n, out.as<double>());
+}
+
+extern "C" int qhp_assemble(qhp_ctx *ctx)
+{
+    if (!ctx) return QHP_EINVAL;
+    if (ctx->state != 1) return guard(ctx, QHP_ESTATE, ctx->state == 0 ? "no mesh" : "already assembled");
+    API_TRY
+    qhp_ctx *c = ctx;
+    hip_check(hipSetDevice(c->p.device), "hipSetDevice");
+    hipStream_t s = c->s;
+    const qhp::Mesh &m = c->mesh;
+    const int64_t ne = m.ne, nc = m.nc, nv = m.nv;
+    const size_t nn = (size_t)ne * ne;
+    c->K = qhp::n_lags(m.diameter, c->p.dt);
+    c->T0 = m.diameter;
+    c->dtn = c->p.dt / c->T0;
+    c->kappa = 1.0 / c->p.dt;
+    c->ld = (ne + 511) / 512 * 512;
+    const double dtn = c->dtn, kappa = c->kappa;
+    upload_tables(c);
+    {
+        std::vector<double> gx, gw;
+        gauss_legendre(c->p.n_psi, gx, gw);
+        qhp::set_gauss(gx.data(), gw.data(), c->p.n_psi);
+    }
+    AsmArgs &a = c->args;
+    // ---- projectors (Sec. II-D), FP64
+    {
+        DBuf LS, LL, LLp;
+        LS.alloc(sizeof(double) * nc * nc);
+        LL.alloc(sizeof(double) * nv * nv);
+        qhp::launch_laplacians(s, a, LS.as<double>(), LL.as<double>());
+        laplacian_pinv(c, nc, LS, c->LSp);
+        laplacian_pinv(c, nv, LL, LLp);
+        c->PS.alloc(sizeof(double) * nn);
+        c->PPL.alloc(sizeof(double) * nn);
+        qhp::launch_proj(s, ne, a.cells, c->LSp.as<double>(), nc, c->PS.as<double>());
+        qhp::launch_proj(s, ne, a.edges, LLp.as<double>(), nv, c->PPL.as<double>());
+    }
+    // ---- Gram and Yukawa operators (Sec. II-C)
+    c->G.alloc(sizeof(double) * nn);
+    zero(c->G, s);
+    qhp::launch_gram(s, a, c->G.as<double>());
+    c->Zs.alloc(sizeof(double) * nn);
+    c->Zh.alloc(sizeof(double) * nn);
+    c->M.alloc(sizeof(double) * nn);
+    {
+        DBuf D;
+        D.alloc(sizeof(double) * nv * nv);
+        zero(c->Zs, s);
+        zero(D, s);
+        qhp::launch_yuk_bcbc(s, a, kappa, c->Zs.as<double>(), D.as<double>());
+        qhp::symmetrize(s, ne, c->Zs.as<double>());
+        qhp::symmetrize(s, nv, D.as<double>());
+        qhp::scale_f64(s, ne, ne, -kappa, c->Zs.as<double>(), ne);  // Z^s = -kappa int int g.g G
+        qhp::launch_zh(s, a, kappa, D.as<double>(), c->Zh.as<double>());
+        zero(c->M, s);
+        qhp::launch_yuk_mfie(s, a, kappa, c->M.as<double>());
+    }
+    hip_check(hipStreamSynchronize(s), "static operators");
+    // ---- Z~ (Sec. III-B), X~ (Sec. III-C), preconditioners
+    {
+        DBuf left, right, t1, t2, Zt, Xt, Glu, Gpiv, info, Y;
+        left.alloc(sizeof(double) * nn);
+        right.alloc(sizeof(double) * nn);
+        t1.alloc(sizeof(double) * nn);
+        t2.alloc(sizeof(double) * nn);
+        Zt.alloc(sizeof(double) * nn);
+        Xt.alloc(sizeof(double) * nn);
+        qhp::eye_plus(s, ne, dtn, 1.0 - dtn, c->PPL.as<double>(), left.as<double>());         // dt~ PP^SH + PP^L
+        qhp::eye_plus(s, ne, 1.0, 1.0 / dtn - 1.0, c->PPL.as<double>(), right.as<double>());  // PP^SH + PP^L/dt~
+        qhp::gemm_f64(s, false, false, ne, ne, ne, 1.0, c->Zs.as<double>(), ne, right.as<double>(), ne, 0.0, t1.as<double>(), ne);
+        qhp::gemm_f64(s, false, false, ne, ne, ne, 1.0, left.as<double>(), ne, t1.as<double>(), ne, 0.0, Zt.as<double>(), ne);
+        qhp::gemm_f64(s, false, false, ne, ne, ne, 1.0, c->PPL.as<double>(), ne, c->Zh.as<double>(), ne, 0.0, t2.as<double>(), ne);
+        qhp::gemm_f64(s, false, false, ne, ne, ne, 1.0 / dtn, t2.as<double>(), ne, c->PPL.as<double>(), ne, 1.0, Zt.as<double>(), ne);
+        qhp::axpby(s, (int64_t)nn, 0.5, c->G.as<double>(), -1.0, c->M.as<double>(), t1.as<double>());  // G/2 - M
+        qhp::gemm_f64(s, false, false, ne, ne, ne, 1.0, left.as<double>(), ne, t1.as<double>(), ne, 0.0, Xt.as<double>(), ne);
+        // LU of the Gram matrix
+        Glu.alloc(sizeof(double) * nn);
+        hip_check(hipMemcpyAsync(Glu.p, c->G.p, sizeof(double) * nn, hipMemcpyDeviceToDevice, s), "copy");
+        Gpiv.alloc(sizeof(int32_t) * ne);
+        info.alloc(sizeof(int));
+        if (qhp::getrf_f64(s, ne, Glu.as<double>(), ne, Gpiv.as<int32_t>(), info.as<int>()) != 0)
+            throw Fail{QHP_ESINGULAR, "Gram matrix is singular"};
+        // P_E = Z~ G^-T (dt~ P^LH + P^Sigma):  Y = G^-1 Z~^T, P_E = Y^T (dt~ I + (1 - dt~) P^Sigma)
+        Y.alloc(sizeof(double) * nn);
+        qhp::transpose_f64(s, ne, ne, Zt.as<double>(), ne, Y.as<double>(), ne);
+        qhp::getrs_f64(s, false, ne, ne, Glu.as<double>(), ne, Gpiv.as<int32_t>(), Y.as<double>(), ne);
+        qhp::eye_plus(s, ne, dtn, 1.0 - dtn, c->PS.as<double>(), right.as<double>());
+        c->Pcat.alloc(sizeof(double) * nn * 2);
+        qhp::gemm_f64(s, true, false, ne, ne, ne, 1.0, Y.as<double>(), ne, right.as<double>(), ne, 0.0,
+                      c->Pcat.as<double>(), 2 * ne);
+        // P_M = eta_c X~ G^-1:  Y = G^-T X~^T, P_M = eta_c Y^T
+        qhp::transpose_f64(s, ne, ne, Xt.as<double>(), ne, Y.as<double>(), ne);
+        qhp::getrs_f64(s, true, ne, ne, Glu.as<double>(), ne, Gpiv.as<int32_t>(), Y.as<double>(), ne);
+        qhp::transpose_f64(s, ne, ne, Y.as<double>(), ne, t1.as<double>(), ne);
+        qhp::scale_f64(s, ne, ne, c->p.eta_c, t1.as<double>(), ne);
+        hip_check(hipMemcpy2DAsync(c->Pcat.as<double>() + ne, sizeof(double) * 2 * ne, t1.p, sizeof(double) * ne,
+                                   sizeof(double) * ne, ne, hipMemcpyDeviceToDevice, s), "copy P_M");
+        hip_check(hipStreamSynchronize(s), "preconditioners");
+    }
+    // ---- lag blocks T_0..T_K (Sec. IV-A) in chunks of lags
+    const int64_t K = c->K;
+    const int32_t prec = c->p.precision;
+    const size_t esz = prec == QHP_F64 ? 8 : (prec == QHP_F32 ? 4 : 2);
+    c->slabs.alloc(esz * (size_t)K * ne * c->ld);
+    c->scales.assign(K, 1.0f);
+    c->T0raw.alloc(sizeof(double) * nn);
+    if (c->keep_raw) {
+        c->rawA.assign(K + 1, {});
+        c->rawB.assign(K + 1, {});
+        c->rawC.assign(K + 1, {});
+    }
+    {
+        const size_t per_shell = sizeof(double) * (2 * nn + 3 * (size_t)nc * nc);
+        const size_t budget = (size_t)24 << 30;
+        int64_t ch = (int64_t)(budget / per_shell) - 2;
+        ch = std::max<int64_t>(1, std::min<int64_t>(ch, K + 1));
+        DBuf V, N, S, Ak, Ck, Ap, Cp, Bk, E, Wst, Tt, amax;
+        V.alloc(sizeof(double) * nn * (ch + 2));
+        N.alloc(sizeof(double) * nn * (ch + 2));
+        S.alloc(sizeof(double) * 3 * (size_t)nc * nc * (ch + 2));
+        Ak.alloc(sizeof(double) * nn); Ck.alloc(sizeof(double) * nn);
+        Ap.alloc(sizeof(double) * nn); Cp.alloc(sizeof(double) * nn);
+        Bk.alloc(sizeof(double) * nn); E.alloc(sizeof(double) * nn);
+        Wst.alloc(sizeof(double) * nn * 2); Tt.alloc(sizeof(double) * nn);
+        amax.alloc(sizeof(unsigned long long));
+        zero(Ap, s);
+        zero(Cp, s);
+        for (int64_t k0 = 0; k0 <= K; k0 += ch) {
+            int64_t k1 = std::min<int64_t>(k0 + ch - 1, K);
+            int64_t j0 = std::max<int64_t>(k0 - 2, 0), j1 = std::min<int64_t>(k1, K - 1);
+            zero(V, s);
+            zero(N, s);
+            zero(S, s);
+            if (j1 >= j0) {
+                qhp::launch_ret_coarse(s, a, j0, j1, V.as<double>(), S.as<double>());
+                qhp::launch_ret_bc(s, a, j0, j1, N.as<double>());
+                for (int64_t j = j0; j <= j1; ++j) {
+                    qhp::symmetrize(s, ne, V.as<double>() + (j - j0) * nn);
+                    qhp::launch_sym_s(s, nc, S.as<double>() + (j - j0) * 3 * (size_t)nc * nc);
+                }
+            }
+            auto shellV = [&](int64_t j) -> const double * {
+                return (j >= j0 && j <= j1) ? V.as<double>() + (j - j0) * nn : nullptr;
+            };
+            auto shellN = [&](int64_t j) -> const double * {
+                return (j >= j0 && j <= j1) ? N.as<double>() + (j - j0) * nn : nullptr;
+            };
+            auto shellS = [&](int64_t j) -> const double * {
+                return (j >= j0 && j <= j1) ? S.as<double>() + (j - j0) * 3 * (size_t)nc * nc : nullptr;
+            };
+            for (int64_t k = k0; k <= k1; ++k) {
+                qhp::launch_lag_ac(s, (int64_t)nn, k, c->p.dt, shellV(k), shellV(k - 1), shellN(k), shellN(k - 1),
+                                   c->G.as<double>(), Ak.as<double>(), Ck.as<double>());
+                qhp::launch_bk(s, a, shellS(k), shellS(k - 1), shellS(k - 2), c->T0, Bk.as<double>());
+                if (c->keep_raw) {
+                    c->rawA[k].resize(nn);
+                    c->rawB[k].resize(nn);
+                    c->rawC[k].resize(nn);
+                    hip_check(hipMemcpyAsync(c->rawA[k].data(), Ak.p, sizeof(double) * nn, hipMemcpyDeviceToHost, s), "raw");
+                    hip_check(hipMemcpyAsync(c->rawB[k].data(), Bk.p, sizeof(double) * nn, hipMemcpyDeviceToHost, s), "raw");
+                    hip_check(hipMemcpyAsync(c->rawC[k].data(), Ck.p, sizeof(double) * nn, hipMemcpyDeviceToHost, s), "raw");
+                }
+                // W^E = A_k + B_k + ((1/dt~ - 1) A_k - A_{k-1}/dt~) P^Sigma (top half of Wst)
+                double *WE = Wst.as<double>(), *WM = Wst.as<double>() + nn;
+                qhp::axpby(s, (int64_t)nn, 1.0, Ak.as<double>(), 1.0, Bk.as<double>(), WE);
+                qhp::axpby(s, (int64_t)nn, 1.0 / dtn - 1.0, Ak.as<double>(), -1.0 / dtn, Ap.as<double>(), E.as<double>());
+                qhp::gemm_f64(s, false, false, ne, ne, ne, 1.0, E.as<double>(), ne, c->PS.as<double>(), ne, 1.0, WE, ne);
+                // W^M = C_k + ((1/dt~ - 1) C_k - C_{k-1}/dt~) P^Sigma
+                hip_check(hipMemcpyAsync(WM, Ck.p, sizeof(double) * nn, hipMemcpyDeviceToDevice, s), "copy");
+                qhp::axpby(s, (int64_t)nn, 1.0 / dtn - 1.0, Ck.as<double>(), -1.0 / dtn, Cp.as<double>(), E.as<double>());
+                qhp::gemm_f64(s, false, false, ne, ne, ne, 1.0, E.as<double>(), ne, c->PS.as<double>(), ne, 1.0, WM, ne);
+                // T_k = [P_E P_M] [W^E; W^M]
+                qhp::gemm_f64(s, false, false, ne, ne, 2 * ne, 1.0, c->Pcat.as<double>(), 2 * ne, Wst.as<double>(), ne,
+                              0.0, Tt.as<double>(), ne);
+                if (k == 0) {
+                    hip_check(hipMemcpyAsync(c->T0raw.p, Tt.p, sizeof(double) * nn, hipMemcpyDeviceToDevice, s), "copy");
+                } else {
+                    float inv_scale = 1.0f;
+                    if (prec == QHP_BF16) {
+                        unsigned long long bits = 0;
+                        zero(amax, s);
+                        qhp::launch_absmax(s, (int64_t)nn, Tt.as<double>(), amax.as<unsigned long long>());
+                        hip_check(hipMemcpyAsync(&bits, amax.p, 8, hipMemcpyDeviceToHost, s), "absmax");
+                        hip_check(hipStreamSynchronize(s), "absmax");
+                        double mx;
+                        std::memcpy(&mx, &bits, 8);
+                        float sc = mx > 0.0 ? (float)mx : 1.0f;
+                        c->scales[k - 1] = sc;
+                        inv_scale = 1.0f / sc;
+                    }
+                    qhp::launch_store_slab(s, ne, c->ld, Tt.as<double>(), prec, inv_scale,
+                                           (char *)c->slabs.p + esz * (size_t)(k - 1) * ne * c->ld);
+                }
+                std::swap(Ap.p, Ak.p);
+                std::swap(Cp.p, Ck.p);
+            }
+            hip_check(hipStreamSynchronize(s), "lag blocks");
+        }
+    }
+    upload(c->scales_d, c->scales, s);
+    // ---- T_0: FP64 LU, diagonal-block inverses, optional explicit inverse
+    {
+        c->LU0.alloc(sizeof(double) * nn);
+        hip_check(hipMemcpyAsync(c->LU0.p, c->T0raw.p, sizeof(double) * nn, hipMemcpyDeviceToDevice, s), "copy");
+        c->ipiv0.alloc(sizeof(int32_t) * ne);
+        DBuf info;
+        info.alloc(sizeof(int));
+        if (qhp::getrf_f64(s, ne, c->LU0.as<double>(), ne, c->ipiv0.as<int32_t>(), info.as<int>()) != 0)
+            throw Fail{QHP_ESINGULAR, "T_0 is singular"};
+        std::vector<int32_t> ipiv(ne), perm(ne);
+        hip_check(hipMemcpy(ipiv.data(), c->ipiv0.p, sizeof(int32_t) * ne, hipMemcpyDeviceToHost), "ipiv");
+        for (int64_t i = 0; i < ne; ++i) perm[i] = (int32_t)i;
+        for (int64_t j = 0; j < ne; ++j) std::swap(perm[j], perm[ipiv[j]]);
+        upload(c->perm0, perm, s);
+        int64_t nb = (ne + 63) / 64;
+        c->Linv.alloc(sizeof(double) * nb * 64 * 64);
+        c->Uinv.alloc(sizeof(double) * nb * 64 * 64);
+        qhp::launch_diag_inv(s, ne, c->LU0.as<double>(), 0, c->Linv.as<double>());
+        qhp::launch_diag_inv(s, ne, c->LU0.as<double>(), 1, c->Uinv.as<double>());
+        if (c->p.solver == QHP_SOLVE_INV) {
+            c->Tinv.alloc(sizeof(double) * nn);
+            qhp::eye_plus(s, ne, 1.0, 0.0, c->LU0.as<double>(), c->Tinv.as<double>());
+            qhp::getrs_f64(s, false, ne, ne, c->LU0.as<double>(), ne, c->ipiv0.as<int32_t>(), c->Tinv.as<double>(), ne);
+        }
+        hip_check(hipStreamSynchronize(s), "T_0 factorisation");
+    }
+    c->state = 2;
+    return QHP_OK;
+    API_CATCH(ctx)
+}
+
+extern "C" int qhp_set_incident(qhp_ctx *ctx, const qhp_wave *waves, int32_t n_rhs, int32_t n_steps)
+{
+    if (!ctx) return QHP_EINVAL;
+    if (ctx->state < 2) return guard(ctx, QHP_ESTATE, "assemble first");
+    if (!waves || n_rhs < 1 || n_steps < 1) return guard(ctx, QHP_EINVAL, "bad waves / n_rhs / n_steps");
+    API_TRY
+    qhp_ctx *c = ctx;
+    hip_check(hipSetDevice(c->p.device), "hipSetDevice");
+    hipStream_t s = c->s;
+    const qhp::Mesh &m = c->mesh;
+    const int64_t ne = m.ne, nc = m.nc, nf = m.nf;
+    c->nrhs = n_rhs;
+    c->n_steps = n_steps;
+    std::vector<qhp_wave> wv(waves, waves + n_rhs);
+    upload(c->waves_d, wv, s);
+    c->rhs.alloc(sizeof(double) * (size_t)n_steps * ne * n_rhs);
+    {
+        int64_t ncols_max = std::max<int64_t>(n_rhs, 2048);
+        int64_t ns_chunk = std::max<int64_t>(1, ncols_max / n_rhs);
+        ns_chunk = std::min<int64_t>(ns_chunk, n_steps);
+        int64_t ncols = ns_chunk * n_rhs;
+        DBuf eloc, hloc, EH, R;
+        eloc.alloc(sizeof(double) * ncols * nc * 3);
+        hloc.alloc(sizeof(double) * ncols * nf * 3);
+        EH.alloc(sizeof(double) * ncols * 2 * ne);
+        R.alloc(sizeof(double) * ncols * ne);
+        for (int64_t s0 = 0; s0 < n_steps; s0 += ns_chunk) {
+            int64_t ns = std::min<int64_t>(ns_chunk, n_steps - s0);
+            int64_t nco = ns * n_rhs;
+            qhp::launch_exc_local(s, nc, c->args.xyz, c->args.tri, c->args.tri_sign, c->waves_d.as<qhp_wave>(),
+                                  n_rhs, s0, ns, c->p.dt, 0, eloc.as<double>());
+            qhp::launch_exc_local(s, nf, c->args.fxyz, c->args.ftri, nullptr, c->waves_d.as<qhp_wave>(), n_rhs,
+                                  s0, ns, c->p.dt, 1, hloc.as<double>());
+            qhp::launch_exc_gather(s, ne, nc, nf, nco, c->args.cells, c->args.tri_edge, eloc.as<double>(),
+                                   hloc.as<double>(), c->args.bct_off, c->args.bct_entry, c->args.bc_tri,
+                                   c->args.bc_flux, EH.as<double>());
+            qhp::gemm_f64(s, false, true, nco, ne, 2 * ne, 1.0, EH.as<double>(), 2 * ne, c->Pcat.as<double>(),
+                          2 * ne, 0.0, R.as<double>(), ne);
+            qhp::launch_permute_rhs(s, ne, ns, n_rhs, R.as<double>(), c->rhs.as<double>() + s0 * ne * n_rhs);
+        }
+        hip_check(hipStreamSynchronize(s), "right-hand sides");
+    }
+    const int64_t K = c->K, ld = c->ld;
+    c->ring64.alloc(sizeof(double) * K * ld * n_rhs);
+    zero(c->ring64, s);
+    if (c->p.precision != QHP_F64) {
+        c->ring32.alloc(sizeof(float) * K * ld * n_rhs);
+        zero(c->ring32, s);
+    }
+    c->bvec.alloc(sizeof(double) * ne * n_rhs);
+    c->zvec.alloc(sizeof(double) * ne * n_rhs);
+    c->yvec.alloc(sizeof(double) * ne * n_rhs);
+    c->nsplit = qhp::hist_splits(ne, K, n_rhs);
+    c->partial.alloc(sizeof(double) * c->nsplit * ne * n_rhs);
+    c->sv.alloc(sizeof(double) * nc * n_rhs);
+    c->zc.alloc(sizeof(double) * nc * n_rhs);
+    c->flags.alloc(sizeof(int) * 2 * ((ne + 63) / 64));
+    zero(c->flags, s);
+    c->epoch.alloc(sizeof(int));
+    zero(c->epoch, s);
+    c->errflag.alloc(sizeof(int));
+    zero(c->errflag, s);
+    hip_check(hipStreamSynchronize(s), "march buffers");
+    c->step = 0;
+    c->head = 0;
+    c->broken = false;
+    c->state = 3;
+    return QHP_OK;
+    API_CATCH(ctx)
+}
+
+// one marching step; no host synchronisation
+static void do_step(qhp_ctx *c, double *j_out, double *y_out)
+{
+    hipStream_t s = c->s;
+    const qhp::Mesh &m = c->mesh;
+    const int64_t ne = m.ne, nc = m.nc, nr = c->nrhs, K = c->K, ld = c->ld;
+    const int64_t i = c->step + 1;
+    const double *r_i = c->rhs.as<double>() + (i - 1) * ne * nr;
+    const bool f64 = c->p.precision == QHP_F64;
+    qhp::launch_history(s, c->p.precision, ne, ld, nr, K, c->slabs.p, f64 || c->p.precision == QHP_F32 ? nullptr : c->scales_d.as<float>(),
+                        f64 ? c->ring64.p : c->ring32.p, K, c->head, r_i, c->bvec.as<double>(), c->partial.p,
+                        c->nsplit);
+    double *y = c->yvec.as<double>();
+    if (c->p.solver == QHP_SOLVE_INV) {
+        if (nr == 1) qhp::launch_gemv_f64(s, ne, c->Tinv.as<double>(), c->bvec.as<double>(), y);
+        else qhp::gemm_f64(s, false, false, ne, nr, ne, 1.0, c->Tinv.as<double>(), ne, c->bvec.as<double>(), nr, 0.0, y, nr);
+    } else if (nr == 1) {
+        int64_t nb = (ne + 63) / 64;
+        qhp::launch_bump(s, c->epoch.as<int>());
+        qhp::launch_trsv_lu(s, ne, c->LU0.as<double>(), c->Linv.as<double>(), c->perm0.as<int32_t>(),
+                            c->bvec.as<double>(), c->zvec.as<double>(), c->flags.as<int>(), c->epoch.as<int>(), 0,
+                            c->errflag.as<int>());
+        qhp::launch_trsv_lu(s, ne, c->LU0.as<double>(), c->Uinv.as<double>(), c->perm0.as<int32_t>(),
+                            c->zvec.as<double>(), y, c->flags.as<int>() + nb, c->epoch.as<int>(), 1,
+                            c->errflag.as<int>());
+    } else {
+        hip_check(hipMemcpyAsync(y, c->bvec.p, sizeof(double) * ne * nr, hipMemcpyDeviceToDevice, s), "copy");
+        qhp::getrs_f64(s, false, ne, nr, c->LU0.as<double>(), ne, c->ipiv0.as<int32_t>(), y, nr);
+    }
+    const int64_t slot = (c->head - 1 + K) % K;
+    double *slot64 = c->ring64.as<double>() + slot * ld * nr;
+    float *slot32 = f64 ? nullptr : c->ring32.as<float>() + slot * ld * nr;
+    const double *yprev = i > 1 ? c->ring64.as<double>() + c->head * ld * nr : nullptr;
+    if (j_out) {
+        qhp::launch_post_a(s, nc, nr, c->dtn, c->args.tri_edge, c->args.tri_sign, y, yprev, c->sv.as<double>());
+        if (nr == 1) qhp::launch_gemv_f64(s, nc, c->LSp.as<double>(), c->sv.as<double>(), c->zc.as<double>());
+        else qhp::gemm_f64(s, false, false, nc, nr, nc, 1.0, c->LSp.as<double>(), nc, c->sv.as<double>(), nr, 0.0, c->zc.as<double>(), nr);
+        qhp::launch_post_b(s, ne, nr, c->args.cells, y, c->zc.as<double>(), j_out);
+    }
+    qhp::launch_store_y(s, ne * nr, y, slot64, slot32, y_out, c->errflag.as<int>());
+    c->head = slot;
+    c->step = i;
+}
+
+static int finish_run(qhp_ctx *c)
+{
+    hip_check(hipStreamSynchronize(c->s), "march");
+    hip_check(hipGetLastError(), "march launch");
+    int e = 0;
+    hip_check(hipMemcpy(&e, c->errflag.p, sizeof(int), hipMemcpyDeviceToHost), "error flag");
+    if (e == 2) {
+        c->broken = true;
+        return guard(c, QHP_EUNSTABLE, "non-finite value in the marching solution");
+    }
+    if (e == 1) {
+        c->broken = true;
+        return guard(c, QHP_EDEVICE, "triangular solve wait exceeded its bound");
+    }
+    return QHP_OK;
+}
+
+extern "C" int qhp_step(qhp_ctx *ctx, double *j_out)
+{
+    if (!ctx) return QHP_EINVAL;
+    if (ctx->state != 3 || ctx->broken) return guard(ctx, QHP_ESTATE, "set_incident first");
+    if (ctx->step >= ctx->n_steps) return guard(ctx, QHP_ESTATE, "no right-hand side left");
+    API_TRY
+    do_step(ctx, j_out, nullptr);
+    return finish_run(ctx);
+    API_CATCH(ctx)
+}
+
+extern "C" int qhp_run(qhp_ctx *ctx, int32_t n_steps, double *j_hist, double *y_hist)
+{
+    if (!ctx) return QHP_EINVAL;
+    if (ctx->state != 3 || ctx->broken) return guard(ctx, QHP_ESTATE, "set_incident first");
+    if (n_steps < 0 || ctx->step + n_steps > ctx->n_steps) return guard(ctx, QHP_EINVAL, "past the last right-hand side");
+    API_TRY
+    const int64_t stride = ctx->mesh.ne * ctx->nrhs;
+    for (int32_t t = 0; t < n_steps; ++t)
+        do_step(ctx, j_hist ? j_hist + t * stride : nullptr, y_hist ? y_hist + t * stride : nullptr);
+    return finish_run(ctx);
+    API_CATCH(ctx)
+}
+
+extern "C" int qhp_query(const qhp_ctx *ctx, qhp_info *info)
+{
+    if (!ctx || !info) return QHP_EINVAL;
+    std::memset(info, 0, sizeof(*info));
+    if (ctx->state < 1) return QHP_ESTATE;
+    const qhp::Mesh &m = ctx->mesh;
+    info->nv = m.nv;
+    info->ne = m.ne;
+    info->nc = m.nc;
+    info->n_harmonic = m.n_harmonic;
+    info->diameter = m.diameter;
+    info->K = qhp::n_lags(m.diameter, ctx->p.dt);
+    info->ld = ctx->ld;
+    info->slab_bytes = ctx->slabs.p ? ctx->slabs.bytes : 0;
+    info->n_rhs = ctx->nrhs;
+    info->n_steps = ctx->n_steps;
+    info->step = ctx->step;
+    return QHP_OK;
+}
+
+extern "C" int qhp_edges(const qhp_ctx *ctx, int32_t *edges, int32_t *cells)
+{
+    if (!ctx || ctx->state < 1) return QHP_ESTATE;
+    if (edges) std::memcpy(edges, ctx->mesh.edges.data(), sizeof(int32_t) * ctx->mesh.edges.size());
+    if (cells) std::memcpy(cells, ctx->mesh.cells.data(), sizeof(int32_t) * ctx->mesh.cells.size());
+    return QHP_OK;
+}
+
+extern "C" int qhp_get_matrix(const qhp_ctx *cc, int32_t which, int32_t k, double *out)
+{
+    qhp_ctx *ctx = const_cast<qhp_ctx *>(cc);
+    if (!ctx || !out) return QHP_EINVAL;
+    if (ctx->state < 2) return guard(ctx, QHP_ESTATE, "assemble first");
+    API_TRY
+    const int64_t ne = ctx->mesh.ne;
+    const size_t nn = (size_t)ne * ne;
+    const DBuf *src = nullptr;
+    switch (which) {
+    case QHP_MAT_GRAM: src = &ctx->G; break;
+    case QHP_MAT_ZS: src = &ctx->Zs; break;
+    case QHP_MAT_ZH: src = &ctx->Zh; break;
+    case QHP_MAT_M: src = &ctx->M; break;
+    case QHP_MAT_PSIGMA: src = &ctx->PS; break;
+    case QHP_MAT_PLAMBDA: src = &ctx->PPL; break;
+    case QHP_MAT_PE:
+    case QHP_MAT_PM: {
+        const double *base = ctx->Pcat.as<double>() + (which == QHP_MAT_PM ? ne : 0);
+        hip_check(hipMemcpy2D(out, sizeof(double) * ne, base, sizeof(double) * 2 * ne, sizeof(double) * ne, ne,
+                              hipMemcpyDeviceToHost), "copy");
+        return QHP_OK;
+    }
+    case QHP_MAT_SLAB: {
+        if (k < 0 || k > ctx->K) return guard(ctx, QHP_EINVAL, "lag out of range");
+        if (k == 0) { src = &ctx->T0raw; break; }
+        DBuf tmp;
+        tmp.alloc(sizeof(double) * nn);
+        const int32_t prec = ctx->p.precision;
+        const size_t esz = prec == QHP_F64 ? 8 : (prec == QHP_F32 ? 4 : 2);
+        qhp::launch_load_slab(ctx->s, ne, ctx->ld, (const char *)ctx->slabs.p + esz * (size_t)(k - 1) * ne * ctx->ld,
+                              prec, ctx->scales[k - 1], tmp.as<double>());
+        hip_check(hipStreamSynchronize(ctx->s), "dequantise");
+        hip_check(hipMemcpy(out, tmp.p, sizeof(double) * nn, hipMemcpyDeviceToHost), "copy");
+        return QHP_OK;
+    }
+    case QHP_MAT_A:
+    case QHP_MAT_B:
+    case QHP_MAT_C: {
+        auto &vv = which == QHP_MAT_A ? ctx->rawA : (which == QHP_MAT_B ? ctx->rawB : ctx->rawC);
+        if (k < 0 || k >= (int64_t)vv.size() || vv[k].empty())
+            return guard(ctx, QHP_ESTATE, "raw lag matrices not kept (qhp_keep_raw before assemble)");
+        std::memcpy(out, vv[k].data(), sizeof(double) * nn);
+        return QHP_OK;
+    }
+    default: return guard(ctx, QHP_EINVAL, "unknown matrix");
+    }
+    hip_check(hipStreamSynchronize(ctx->s), "sync");
+    hip_check(hipMemcpy(out, src->p, sizeof(double) * nn, hipMemcpyDeviceToHost), "copy");
+    return QHP_OK;
+    API_CATCH(ctx)
+}
+
+extern "C" int qhp_history_sum(void *stream, int32_t precision, int64_t ne, int64_t ld, int64_t nrhs, int64_t kmax,
+                               const void *slabs, const float *scales, const void *ring, int64_t n_slots, int64_t head,
+                               const double *r, double *b)
+{
+    if (precision < QHP_F64 || precision > QHP_BF16 || ne < 1 || ld < ne || ld % 8 != 0 || nrhs < 1 || kmax < 0 ||
+        n_slots < kmax || head < 0 || (kmax > 0 && (!slabs || !ring)) || !r || !b)
+        return QHP_EINVAL;
+    if (precision == QHP_BF16 && !scales) return QHP_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int nsplit = qhp::hist_splits(ne, std::max<int64_t>(kmax, 1), nrhs);
+    void *partial = nullptr;
+    if (hipMalloc(&partial, sizeof(double) * nsplit * ne * nrhs) != hipSuccess) {
+        (void)hipGetLastError();
+        return QHP_ENOMEM;
+    }
+    qhp::launch_history(s, precision, ne, ld, nrhs, kmax, slabs, precision == QHP_BF16 ? scales : nullptr, ring,
+                        n_slots, head, r, b, partial, nsplit);
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipGetLastError();
+    (void)hipFree(partial);
+    return e == hipSuccess ? QHP_OK : QHP_EDEVICE;
+}

@@ -1,0 +1,42 @@
+// Launchers of the per-step kernels (history sum, solve, post-processing)
+// and of the tested incident fields.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/qhp.h"
+
+namespace qhp {
+
+int hist_splits(int64_t ne, int64_t kmax, int64_t nrhs);
+// partial: scratch of nsplit * ne * nrhs accumulators (FP64 for QHP_F64 with
+// nrhs == 1, FP32 otherwise)
+void launch_history(hipStream_t s, int32_t precision, int64_t ne, int64_t ld, int64_t nrhs, int64_t kmax,
+                    const void *slabs, const float *scales, const void *ring, int64_t n_slots, int64_t head,
+                    const double *r, double *b, void *partial, int nsplit);
+void launch_gemv_f64(hipStream_t s, int64_t n, const double *A, const double *x, double *y);
+void launch_trsv_lu(hipStream_t s, int64_t n, const double *LU, const double *Dinv, const int32_t *perm,
+                    const double *b, double *x, int *flags, const int *epoch, int upper, int *err);
+void launch_bump(hipStream_t s, int *epoch);
+void launch_diag_inv(hipStream_t s, int64_t n, const double *LU, int upper, double *Dinv);
+void launch_store_y(hipStream_t s, int64_t n, const double *y, double *slot64, float *slot32, double *yhist,
+                    int *err);
+void launch_post_a(hipStream_t s, int64_t nc, int64_t nrhs, double dtn, const int32_t *tri_edge,
+                   const int32_t *tri_sign, const double *y, const double *yprev, double *sv);
+void launch_post_b(hipStream_t s, int64_t ne, int64_t nrhs, const int32_t *cells, const double *y, const double *z,
+                   double *j);
+void launch_store_slab(hipStream_t s, int64_t ne, int64_t ld, const double *T, int32_t precision, float inv_scale,
+                       void *out);
+void launch_absmax(hipStream_t s, int64_t n, const double *T, unsigned long long *out);
+void launch_load_slab(hipStream_t s, int64_t ne, int64_t ld, const void *in, int32_t precision, float scale,
+                      double *T);
+void launch_exc_local(hipStream_t s, int64_t ntri, const double *xyz, const int32_t *tri, const int32_t *sgn,
+                      const qhp_wave *waves, int32_t nrhs, int64_t s0, int64_t ns, double dt, int mode, double *out);
+void launch_exc_gather(hipStream_t s, int64_t ne, int64_t nc, int64_t nf, int64_t ncols, const int32_t *cells,
+                       const int32_t *tri_edge, const double *eloc, const double *hloc, const int32_t *bct_off,
+                       const int32_t *bct_entry, const int32_t *bc_tri, const double *bc_flux, double *EH);
+void launch_permute_rhs(hipStream_t s, int64_t ne, int64_t ns, int32_t nrhs, const double *R, double *r);
+
+}  // namespace qhp

@@ -1,0 +1,662 @@
+// Per-step kernels of the marching-on-in-time scheme (Sec. IV-B) on gfx950:
+// the retarded history sum over the time-banded blocks T_k, the T_0 solve,
+// the post-processing of eq. post_processing, and the tested incident fields.
+#include "march.h"
+
+#include "linalg.h"
+
+#include <cstring>
+
+namespace qhp {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+static unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// ---------------------------------------------------------------- pulses
+__device__ __forceinline__ double pulse(const qhp_wave &w, double u)
+{
+    if (w.pulse == 0) {
+        double sig = 1.0 / (6.283185307179586476925286766559 * w.bw);
+        return w.amplitude * cos(6.283185307179586476925286766559 * w.f0 * u) * exp(-u * u / (2.0 * sig * sig));
+    }
+    double a = 4.0 / w.w * u;
+    return 4.0 * w.amplitude / (w.w * 1.7724538509055160272981674833411) * exp(-a * a);
+}
+
+__device__ __forceinline__ void radon7(int q, double &l0, double &l1, double &l2, double &w)
+{
+    const double s15 = 3.872983346207416885179265399782;
+    const double a1 = (9.0 - 2.0 * s15) / 21.0, b1 = (6.0 + s15) / 21.0;
+    const double a2 = (9.0 + 2.0 * s15) / 21.0, b2 = (6.0 - s15) / 21.0;
+    const double w1 = (155.0 + s15) / 1200.0, w2 = (155.0 - s15) / 1200.0;
+    switch (q) {
+    case 0: l0 = l1 = l2 = 1.0 / 3.0; w = 9.0 / 40.0; break;
+    case 1: l0 = a1; l1 = b1; l2 = b1; w = w1; break;
+    case 2: l0 = b1; l1 = a1; l2 = b1; w = w1; break;
+    case 3: l0 = b1; l1 = b1; l2 = a1; w = w1; break;
+    case 4: l0 = a2; l1 = b2; l2 = b2; w = w2; break;
+    case 5: l0 = b2; l1 = a2; l2 = b2; w = w2; break;
+    default: l0 = b2; l1 = b2; l2 = a2; w = w2; break;
+    }
+}
+
+// Local tested moments of e_in (coarse, RWG sign included) or h_in (fine,
+// unsigned RT0 functions) on each triangle: out[col][tri][a], col = s*nrhs+b.
+// mode 0: e on coarse triangles; mode 1: h = k x e on fine triangles.
+__global__ void k_exc_local(int64_t ntri, const double *xyz, const int32_t *tri, const int32_t *sgn,
+                            const qhp_wave *waves, int32_t nrhs, int64_t s0, int64_t ns, double dt,
+                            int mode, double *out)
+{
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= ntri * ns * nrhs) return;
+    int64_t t = idx % ntri;
+    int64_t col = idx / ntri;  // s_local * nrhs + b
+    int b = (int)(col % nrhs);
+    int64_t sl = col / nrhs;
+    const qhp_wave w = waves[b];
+    double P[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k) P[i][k] = xyz[3 * tri[3 * t + i] + k];
+    double e1[3], e2[3];
+    for (int k = 0; k < 3; ++k) { e1[k] = P[1][k] - P[0][k]; e2[k] = P[2][k] - P[0][k]; }
+    double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2], cz = e1[0] * e2[1] - e1[1] * e2[0];
+    double A = 0.5 * sqrt(cx * cx + cy * cy + cz * cz);
+    double tk = (double)(s0 + sl + 1) * dt;
+    // field direction: p for e, k x p for h
+    double dir[3];
+    if (mode == 0) {
+        for (int k = 0; k < 3; ++k) dir[k] = w.pol[k];
+    } else {
+        dir[0] = w.k_hat[1] * w.pol[2] - w.k_hat[2] * w.pol[1];
+        dir[1] = w.k_hat[2] * w.pol[0] - w.k_hat[0] * w.pol[2];
+        dir[2] = w.k_hat[0] * w.pol[1] - w.k_hat[1] * w.pol[0];
+    }
+    double acc[3] = {0, 0, 0};
+    for (int q = 0; q < 7; ++q) {
+        double l0, l1, l2, wq;
+        radon7(q, l0, l1, l2, wq);
+        double r[3];
+        for (int k = 0; k < 3; ++k) r[k] = l0 * P[0][k] + l1 * P[1][k] + l2 * P[2][k];
+        double u = tk - w.t0 - (r[0] * w.k_hat[0] + r[1] * w.k_hat[1] + r[2] * w.k_hat[2]);
+        double amp = pulse(w, u) * wq * A / (2.0 * A);
+        for (int a = 0; a < 3; ++a) {
+            double d = 0.0;
+            for (int k = 0; k < 3; ++k) d += (r[k] - P[a][k]) * dir[k];
+            acc[a] += amp * d;
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        double s = (mode == 0) ? (double)sgn[3 * t + a] : 1.0;
+        out[(col * ntri + t) * 3 + a] = s * acc[a];
+    }
+}
+
+// EH[col][m] = -e_m, EH[col][ne + m] = h_m
+__global__ void k_exc_gather(int64_t ne, int64_t nc, int64_t nf, int64_t ncols, const int32_t *cells,
+                             const int32_t *tri_edge, const double *eloc, const double *hloc,
+                             const int32_t *bct_off, const int32_t *bct_entry, const int32_t *bc_tri,
+                             const double *bc_flux, double *EH)
+{
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= ne * ncols) return;
+    int64_t m = idx % ne, col = idx / ne;
+    double e = 0.0;
+    for (int q = 0; q < 2; ++q) {
+        int64_t c = cells[2 * m + q];
+        for (int a = 0; a < 3; ++a)
+            if (tri_edge[3 * c + a] == m) e += eloc[(col * nc + c) * 3 + a];
+    }
+    double h = 0.0;
+    for (int q = bct_off[m]; q < bct_off[m + 1]; ++q) {
+        int32_t en = bct_entry[q];
+        int64_t t = bc_tri[en];
+        const double *F = bc_flux + 3 * en;
+        const double *hl = hloc + (col * nf + t) * 3;
+        h += F[0] * hl[0] + F[1] * hl[1] + F[2] * hl[2];
+    }
+    EH[col * 2 * ne + m] = -e;
+    EH[col * 2 * ne + ne + m] = h;
+}
+
+// r[s][m][b] = R[s*nrhs + b][m]
+__global__ void k_permute_rhs(int64_t ne, int64_t ns, int32_t nrhs, const double *R, double *r)
+{
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= ne * ns * nrhs) return;
+    int b = (int)(idx % nrhs);
+    int64_t m = (idx / nrhs) % ne, s = idx / (nrhs * ne);
+    r[idx] = R[(s * nrhs + b) * ne + m];
+}
+
+void launch_exc_local(hipStream_t s, int64_t ntri, const double *xyz, const int32_t *tri, const int32_t *sgn,
+                      const qhp_wave *waves, int32_t nrhs, int64_t s0, int64_t ns, double dt, int mode, double *out)
+{
+    int64_t n = ntri * ns * nrhs;
+    hipLaunchKernelGGL(k_exc_local, dim3(nblk(n, 128)), dim3(128), 0, s, ntri, xyz, tri, sgn, waves, nrhs, s0, ns, dt, mode, out);
+}
+void launch_exc_gather(hipStream_t s, int64_t ne, int64_t nc, int64_t nf, int64_t ncols, const int32_t *cells,
+                       const int32_t *tri_edge, const double *eloc, const double *hloc, const int32_t *bct_off,
+                       const int32_t *bct_entry, const int32_t *bc_tri, const double *bc_flux, double *EH)
+{
+    hipLaunchKernelGGL(k_exc_gather, dim3(nblk(ne * ncols, 256)), dim3(256), 0, s, ne, nc, nf, ncols, cells,
+                       tri_edge, eloc, hloc, bct_off, bct_entry, bc_tri, bc_flux, EH);
+}
+void launch_permute_rhs(hipStream_t s, int64_t ne, int64_t ns, int32_t nrhs, const double *R, double *r)
+{
+    hipLaunchKernelGGL(k_permute_rhs, dim3(nblk(ne * ns * nrhs, 256)), dim3(256), 0, s, ne, ns, nrhs, R, r);
+}
+
+// ------------------------------------------------------------ history sum
+// Single right-hand side: partial[split][row] = sum over the split's lags of
+// T_k[row] . y_{i-k}.  Block = 256 threads = 4 waves, 16 rows per block (4 per
+// wave).  Each lane streams 16-byte vectors of a row; the y vector chunk is
+// loaded once per lane and reused for the wave's 4 rows.
+template <typename T>
+struct Vec;
+template <>
+struct Vec<double> {
+    static constexpr int N = 2;
+    typedef double acc_t;
+    typedef double y_t;
+};
+template <>
+struct Vec<float> {
+    static constexpr int N = 4;
+    typedef float acc_t;
+    typedef float y_t;
+};
+template <>
+struct Vec<uint16_t> {  // bf16 storage
+    static constexpr int N = 8;
+    typedef float acc_t;
+    typedef float y_t;
+};
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h)
+{
+    return __uint_as_float(((uint32_t)h) << 16);
+}
+
+template <typename T>
+__device__ __forceinline__ void load_vec(const T *p, typename Vec<T>::acc_t *out);
+template <>
+__device__ __forceinline__ void load_vec<double>(const double *p, double *out)
+{
+    double2 v = *reinterpret_cast<const double2 *>(p);
+    out[0] = v.x;
+    out[1] = v.y;
+}
+template <>
+__device__ __forceinline__ void load_vec<float>(const float *p, float *out)
+{
+    float4 v = *reinterpret_cast<const float4 *>(p);
+    out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
+}
+template <>
+__device__ __forceinline__ void load_vec<uint16_t>(const uint16_t *p, float *out)
+{
+    uint4 v = *reinterpret_cast<const uint4 *>(p);
+    uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    for (int i = 0; i < 4; ++i) {
+        out[2 * i] = __uint_as_float(w[i] << 16);
+        out[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+    }
+}
+template <typename Y>
+__device__ __forceinline__ void load_y(const Y *p, int n, Y *out)
+{
+    if (n == 2) {
+        double2 v = *reinterpret_cast<const double2 *>(p);
+        out[0] = v.x;
+        out[1] = v.y;
+    } else {
+        for (int q = 0; q < n; q += 4) {
+            float4 v = *reinterpret_cast<const float4 *>(p + q);
+            out[q] = v.x; out[q + 1] = v.y; out[q + 2] = v.z; out[q + 3] = v.w;
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_hist_gemv(int64_t ne, int64_t ld, int64_t kmax, int64_t lags_per_split,
+                                                   const T *__restrict__ slabs, const float *__restrict__ scales,
+                                                   const typename Vec<T>::y_t *__restrict__ ring, int64_t n_slots,
+                                                   int64_t head, typename Vec<T>::acc_t *__restrict__ partial)
+{
+    typedef typename Vec<T>::acc_t acc_t;
+    typedef typename Vec<T>::y_t y_t;
+    constexpr int VN = Vec<T>::N;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t row0 = (int64_t)blockIdx.x * 16 + wave * 4;
+    const int64_t k_begin = 1 + (int64_t)blockIdx.y * lags_per_split;
+    int64_t k_end = k_begin + lags_per_split;
+    if (k_end > kmax + 1) k_end = kmax + 1;
+    acc_t acc[4] = {0, 0, 0, 0};
+    const bool full_rows = row0 + 3 < ne;
+    for (int64_t k = k_begin; k < k_end; ++k) {
+        int64_t slot = (head + k - 1) % n_slots;
+        const y_t *y = ring + slot * ld;
+        const T *Tk = slabs + (k - 1) * ne * ld;
+        acc_t part[4] = {0, 0, 0, 0};
+        for (int64_t c0 = (int64_t)lane * VN; c0 < ne; c0 += 64 * VN) {
+            y_t yv[VN];
+            load_y<y_t>(y + c0, VN, yv);
+            if (c0 + VN > ne) {
+                for (int q = 0; q < VN; ++q)
+                    if (c0 + q >= ne) yv[q] = 0;
+            }
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                if (!full_rows && row0 + rr >= ne) continue;
+                acc_t tv[VN];
+                load_vec<T>(Tk + (row0 + rr) * ld + c0, tv);
+                if (c0 + VN > ne) {
+                    for (int q = 0; q < VN; ++q)
+                        if (c0 + q >= ne) tv[q] = 0;
+                }
+#pragma unroll
+                for (int q = 0; q < VN; ++q) part[rr] += tv[q] * (acc_t)yv[q];
+            }
+        }
+        acc_t sc = scales ? (acc_t)scales[k - 1] : (acc_t)1;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) acc[rr] += sc * part[rr];
+    }
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+        acc_t v = acc[rr];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        acc[rr] = v;
+    }
+    if (lane == 0) {
+        for (int rr = 0; rr < 4; ++rr)
+            if (row0 + rr < ne) partial[(int64_t)blockIdx.y * ne + row0 + rr] = acc[rr];
+    }
+}
+
+// b[row] = r[row] - sum_s partial[s][row]   (FP64 result)
+template <typename A>
+__global__ void k_hist_finish(int64_t n, int64_t nsplit, const A *partial, const double *r, double *b)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int64_t q = 0; q < nsplit; ++q) s += (double)partial[q * n + i];
+    b[i] = r[i] - s;
+}
+
+// Batched right-hand sides: C[row][rhs] partials with FP32 MFMA
+// (v_mfma_f32_32x32x2f32: lane l holds A[l%32][l/32], B[l/32][l%32];
+// result D[8*(r/4) + 4*(l/32) + r%4][l%32] in register r).
+// Block tile 64 rows x 64 rhs, k-tile 32, 4 waves of 32x32.
+template <typename T>
+__global__ __launch_bounds__(256) void k_hist_gemm(int64_t ne, int64_t ld, int64_t nrhs, int64_t kmax,
+                                                   int64_t lags_per_split, const T *__restrict__ slabs,
+                                                   const float *__restrict__ scales,
+                                                   const float *__restrict__ ring, int64_t n_slots,
+                                                   int64_t head, float *__restrict__ partial)
+{
+    __shared__ float As[32][64 + 4];  // [kk][row]
+    __shared__ float Bs[32][64 + 4];  // [kk][rhs]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * 64, c0 = (int64_t)blockIdx.z * 64;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    const int64_t k_begin = 1 + (int64_t)blockIdx.y * lags_per_split;
+    int64_t k_end = k_begin + lags_per_split;
+    if (k_end > kmax + 1) k_end = kmax + 1;
+    f16v acc;
+    for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+    for (int64_t k = k_begin; k < k_end; ++k) {
+        const float sc = scales ? scales[k - 1] : 1.f;
+        const T *Tk = slabs + (k - 1) * ne * ld;
+        const float *Y = ring + ((head + k - 1) % n_slots) * ld * nrhs;
+        for (int64_t kk0 = 0; kk0 < ne; kk0 += 32) {
+            // A tile: 64 rows x 32 cols of T_k (scaled), B tile: 32 rows x 64 rhs of y
+            for (int e = tid; e < 64 * 32; e += 256) {
+                int rr = e >> 5, kk = e & 31;
+                int64_t gr = r0 + rr, gk = kk0 + kk;
+                float v = 0.f;
+                if (gr < ne && gk < ne) {
+                    if constexpr (sizeof(T) == 2) v = __uint_as_float(((uint32_t)Tk[gr * ld + gk]) << 16);
+                    else v = (float)Tk[gr * ld + gk];
+                }
+                As[kk][rr] = v * sc;
+                int kb = e >> 6, cc = e & 63;
+                int64_t gkb = kk0 + kb, gc = c0 + cc;
+                Bs[kb][cc] = (gkb < ne && gc < nrhs) ? Y[gkb * nrhs + gc] : 0.f;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int kq = 0; kq < 32; kq += 2) {
+                float a = As[kq + (lane >> 5)][wr + (lane & 31)];
+                float b = Bs[kq + (lane >> 5)][wc + (lane & 31)];
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+            }
+            __syncthreads();
+        }
+    }
+    float *out = partial + (int64_t)blockIdx.y * ne * nrhs;
+    for (int rg = 0; rg < 16; ++rg) {
+        int64_t gr = r0 + wr + 8 * (rg >> 2) + 4 * (lane >> 5) + (rg & 3);
+        int64_t gc = c0 + wc + (lane & 31);
+        if (gr < ne && gc < nrhs) out[gr * nrhs + gc] = acc[rg];
+    }
+}
+
+int hist_splits(int64_t ne, int64_t kmax, int64_t nrhs)
+{
+    // enough blocks to fill 256 CUs several times over
+    int64_t rowblocks = nrhs == 1 ? (ne + 15) / 16 : ((ne + 63) / 64) * ((nrhs + 63) / 64);
+    int64_t want = (8 * 256 + rowblocks - 1) / rowblocks;
+    if (want < 1) want = 1;
+    if (want > kmax) want = kmax;
+    return (int)want;
+}
+
+void launch_history(hipStream_t s, int32_t precision, int64_t ne, int64_t ld, int64_t nrhs, int64_t kmax,
+                    const void *slabs, const float *scales, const void *ring, int64_t n_slots, int64_t head,
+                    const double *r, double *b, void *partial, int nsplit)
+{
+    if (kmax <= 0) {
+        (void)hipMemcpyAsync(b, r, sizeof(double) * ne * nrhs, hipMemcpyDeviceToDevice, s);
+        return;
+    }
+    int64_t lps = (kmax + nsplit - 1) / nsplit;
+    if (nrhs == 1) {
+        dim3 grid(nblk(ne, 16), (unsigned)nsplit);
+        if (precision == QHP_F64) {
+            hipLaunchKernelGGL(k_hist_gemv<double>, grid, dim3(256), 0, s, ne, ld, kmax, lps, (const double *)slabs,
+                               scales, (const double *)ring, n_slots, head, (double *)partial);
+            hipLaunchKernelGGL(k_hist_finish<double>, dim3(nblk(ne, 256)), dim3(256), 0, s, ne, (int64_t)nsplit,
+                               (const double *)partial, r, b);
+        } else if (precision == QHP_F32) {
+            hipLaunchKernelGGL(k_hist_gemv<float>, grid, dim3(256), 0, s, ne, ld, kmax, lps, (const float *)slabs,
+                               scales, (const float *)ring, n_slots, head, (float *)partial);
+            hipLaunchKernelGGL(k_hist_finish<float>, dim3(nblk(ne, 256)), dim3(256), 0, s, ne, (int64_t)nsplit,
+                               (const float *)partial, r, b);
+        } else {
+            hipLaunchKernelGGL(k_hist_gemv<uint16_t>, grid, dim3(256), 0, s, ne, ld, kmax, lps,
+                               (const uint16_t *)slabs, scales, (const float *)ring, n_slots, head, (float *)partial);
+            hipLaunchKernelGGL(k_hist_finish<float>, dim3(nblk(ne, 256)), dim3(256), 0, s, ne, (int64_t)nsplit,
+                               (const float *)partial, r, b);
+        }
+        return;
+    }
+    if (precision == QHP_F64) {
+        // FP64 batched: one FP64 MFMA GEMM per lag into the partial buffer
+        double *acc = (double *)partial;
+        for (int64_t k = 1; k <= kmax; ++k) {
+            const double *Tk = (const double *)slabs + (k - 1) * ne * ld;
+            const double *Y = (const double *)ring + ((head + k - 1) % n_slots) * ld * nrhs;
+            gemm_f64(s, false, false, ne, nrhs, ne, 1.0, Tk, ld, Y, nrhs, k == 1 ? 0.0 : 1.0, acc, nrhs);
+        }
+        hipLaunchKernelGGL(k_hist_finish<double>, dim3(nblk(ne * nrhs, 256)), dim3(256), 0, s, ne * nrhs,
+                           (int64_t)1, (const double *)acc, r, b);
+        return;
+    }
+    dim3 grid(nblk(ne, 64), (unsigned)nsplit, nblk(nrhs, 64));
+    if (precision == QHP_BF16)
+        hipLaunchKernelGGL(k_hist_gemm<uint16_t>, grid, dim3(256), 0, s, ne, ld, nrhs, kmax, lps,
+                           (const uint16_t *)slabs, scales, (const float *)ring, n_slots, head, (float *)partial);
+    else
+        hipLaunchKernelGGL(k_hist_gemm<float>, grid, dim3(256), 0, s, ne, ld, nrhs, kmax, lps, (const float *)slabs,
+                           scales, (const float *)ring, n_slots, head, (float *)partial);
+    hipLaunchKernelGGL(k_hist_finish<float>, dim3(nblk(ne * nrhs, 256)), dim3(256), 0, s, ne * nrhs,
+                       (int64_t)nsplit, (const float *)partial, r, b);
+}
+
+// ------------------------------------------------------------------ solve
+// y = Tinv b (dense FP64 inverse), one row per wave.
+__global__ __launch_bounds__(256) void k_gemv_f64(int64_t n, const double *__restrict__ A,
+                                                  const double *__restrict__ x, double *__restrict__ y)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= n) return;
+    double s = 0.0;
+    for (int64_t c = lane; c < n; c += 64) s += A[row * n + c] * x[c];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) y[row] = s;
+}
+void launch_gemv_f64(hipStream_t s, int64_t n, const double *A, const double *x, double *y)
+{
+    hipLaunchKernelGGL(k_gemv_f64, dim3(nblk(n, 4)), dim3(256), 0, s, n, A, x, y);
+}
+
+// Triangular solves with the LU of T_0, one workgroup per 64-row block,
+// ordered by per-block flags (epoch counter) instead of a grid barrier.
+// Forward: L z = P b (unit lower); backward: U x = z.  Each block first
+// accumulates the off-diagonal products as the earlier blocks publish their
+// pieces, then applies the precomputed inverse of its diagonal block.
+// Every wait is bounded: after spin_limit polls the block records an error
+// and exits, so the grid always drains.
+__device__ __forceinline__ int flag_load(const int *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void flag_store(int *p, int v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(256) void k_trsv_lu(int64_t n, const double *__restrict__ LU,
+                                                 const double *__restrict__ Dinv, const int32_t *__restrict__ perm,
+                                                 const double *b, double *x, int *flags, const int *epoch_ptr,
+                                                 int upper, int64_t spin_limit, int *err)
+{
+    const int epoch = *epoch_ptr;
+    __shared__ double red[4][64];
+    __shared__ double vin[64];
+    __shared__ double xin[64];
+    __shared__ int abort_flag;
+    const int nb = 64;
+    const int64_t nblocks = (n + nb - 1) / nb;
+    const int64_t jb = upper ? nblocks - 1 - (int64_t)blockIdx.x : (int64_t)blockIdx.x;
+    const int64_t r0 = jb * nb;
+    const int rows = (int)((n - r0) < nb ? (n - r0) : nb);
+    const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6;  // q: which 16-column quarter
+    if (tid == 0) abort_flag = 0;
+    double acc = 0.0;  // lane owns row r0 + lane (quarter q of the columns)
+    // sources: blocks ib < jb (forward) or ib > jb (backward), in dependency order
+    for (int64_t step = 0; step < (upper ? nblocks - 1 - jb : jb); ++step) {
+        int64_t ib = upper ? nblocks - 1 - step : step;
+        if (tid == 0) {
+            int64_t polls = 0;
+            while (flag_load(&flags[ib]) < epoch) {
+                if (++polls > spin_limit) { abort_flag = 1; atomicExch(err, 1); break; }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __syncthreads();
+        if (abort_flag) return;
+        const int64_t c0 = ib * nb;
+        const int cols = (int)((n - c0) < nb ? (n - c0) : nb);
+        if (tid < cols) xin[tid] = __hip_atomic_load(&x[c0 + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        if (lane < rows) {
+            const double *Arow = LU + (r0 + lane) * n + c0;
+            for (int c = q * 16; c < q * 16 + 16 && c < cols; ++c) acc += Arow[c] * xin[c];
+        }
+        __syncthreads();
+    }
+    red[q][lane] = acc;
+    __syncthreads();
+    if (tid < 64) {
+        double rhs = 0.0;
+        if (lane < rows) {
+            int64_t gi = r0 + lane;
+            double bv = upper ? b[gi] : b[perm[gi]];
+            rhs = bv - (red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane]);
+        }
+        vin[lane] = rhs;
+    }
+    __syncthreads();
+    // x_j = Dinv_j * vin
+    double s = 0.0;
+    if (lane < rows) {
+        const double *Drow = Dinv + (jb * nb + lane) * nb;
+        for (int c = q * 16; c < q * 16 + 16 && c < rows; ++c) s += Drow[c] * vin[c];
+    }
+    red[q][lane] = s;
+    __syncthreads();
+    if (tid < 64 && lane < rows) {
+        double v = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+        __hip_atomic_store(&x[r0 + lane], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    if (tid == 0) flag_store(&flags[jb], epoch);
+}
+
+void launch_trsv_lu(hipStream_t s, int64_t n, const double *LU, const double *Dinv, const int32_t *perm,
+                    const double *b, double *x, int *flags, const int *epoch, int upper, int *err)
+{
+    int64_t nb = (n + 63) / 64;
+    hipLaunchKernelGGL(k_trsv_lu, dim3((unsigned)nb), dim3(256), 0, s, n, LU, Dinv, perm, b, x, flags, epoch,
+                       upper, (int64_t)(1 << 26), err);
+}
+__global__ void k_bump(int *epoch) { *epoch += 1; }
+void launch_bump(hipStream_t s, int *epoch) { hipLaunchKernelGGL(k_bump, dim3(1), dim3(1), 0, s, epoch); }
+
+// Inverses of the 64x64 diagonal blocks of L (unit lower) and U (upper),
+// Dinv[blk][r][c], by forward/back substitution against the identity.
+__global__ void k_diag_inv(int64_t n, const double *LU, int upper, double *Dinv)
+{
+    const int nb = 64;
+    int64_t jb = blockIdx.x;
+    int col = threadIdx.x;  // column of the identity
+    int64_t r0 = jb * nb;
+    int rows = (int)((n - r0) < nb ? (n - r0) : nb);
+    if (col >= nb) return;
+    double xv[64];
+    for (int r = 0; r < nb; ++r) xv[r] = 0.0;
+    if (col < rows) {
+        if (!upper) {
+            for (int r = 0; r < rows; ++r) {
+                double v = (r == col) ? 1.0 : 0.0;
+                for (int c = 0; c < r; ++c) v -= LU[(r0 + r) * n + r0 + c] * xv[c];
+                xv[r] = v;
+            }
+        } else {
+            for (int r = rows - 1; r >= 0; --r) {
+                double v = (r == col) ? 1.0 : 0.0;
+                for (int c = r + 1; c < rows; ++c) v -= LU[(r0 + r) * n + r0 + c] * xv[c];
+                xv[r] = v / LU[(r0 + r) * n + r0 + r];
+            }
+        }
+    }
+    for (int r = 0; r < nb; ++r) Dinv[(jb * nb + r) * nb + col] = xv[r];
+}
+void launch_diag_inv(hipStream_t s, int64_t n, const double *LU, int upper, double *Dinv)
+{
+    hipLaunchKernelGGL(k_diag_inv, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, n, LU, upper, Dinv);
+}
+
+// --------------------------------------------------------- post-process
+// y_i stored: FP64 master copy into the ring slot and FP32 shadow for the
+// reduced-precision history; non-finite values raise the error flag.
+__global__ void k_store_y(int64_t n, const double *y, double *slot64, float *slot32, double *yhist, int *err)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double v = y[i];
+    if (!isfinite(v)) atomicExch(err, 2);
+    if (slot64) slot64[i] = v;
+    if (slot32) slot32[i] = (float)v;
+    if (yhist) yhist[i] = v;
+}
+void launch_store_y(hipStream_t s, int64_t n, const double *y, double *slot64, float *slot32, double *yhist, int *err)
+{
+    hipLaunchKernelGGL(k_store_y, dim3(nblk(n, 256)), dim3(256), 0, s, n, y, slot64, slot32, yhist, err);
+}
+
+// w = (1/dtn - 1) y_i - y_{i-1}/dtn ; s_c = sum_a sign(c,a) w[edge(c,a)]
+__global__ void k_post_a(int64_t nc, int64_t nrhs, double dtn, const int32_t *tri_edge, const int32_t *tri_sign,
+                         const double *y, const double *yprev, double *sv)
+{
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nc * nrhs) return;
+    int64_t c = idx / nrhs, b = idx % nrhs;
+    double acc = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        int64_t m = tri_edge[3 * c + a];
+        double w = (1.0 / dtn - 1.0) * y[m * nrhs + b] - (yprev ? yprev[m * nrhs + b] : 0.0) / dtn;
+        acc += tri_sign[3 * c + a] * w;
+    }
+    sv[idx] = acc;
+}
+// j = y + Sigma z
+__global__ void k_post_b(int64_t ne, int64_t nrhs, const int32_t *cells, const double *y, const double *z, double *j)
+{
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= ne * nrhs) return;
+    int64_t m = idx / nrhs, b = idx % nrhs;
+    j[idx] = y[idx] + z[cells[2 * m] * nrhs + b] - z[cells[2 * m + 1] * nrhs + b];
+}
+void launch_post_a(hipStream_t s, int64_t nc, int64_t nrhs, double dtn, const int32_t *tri_edge,
+                   const int32_t *tri_sign, const double *y, const double *yprev, double *sv)
+{
+    hipLaunchKernelGGL(k_post_a, dim3(nblk(nc * nrhs, 256)), dim3(256), 0, s, nc, nrhs, dtn, tri_edge, tri_sign, y,
+                       yprev, sv);
+}
+void launch_post_b(hipStream_t s, int64_t ne, int64_t nrhs, const int32_t *cells, const double *y, const double *z,
+                   double *j)
+{
+    hipLaunchKernelGGL(k_post_b, dim3(nblk(ne * nrhs, 256)), dim3(256), 0, s, ne, nrhs, cells, y, z, j);
+}
+
+// quantise T (FP64, [ne][ne]) into the slab store [ne][ld] with scale
+__global__ void k_store_slab(int64_t ne, int64_t ld, const double *T, int32_t precision, float inv_scale, void *out)
+{
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= ne * ld) return;
+    int64_t i = idx / ld, j = idx % ld;
+    double v = j < ne ? T[i * ne + j] : 0.0;
+    if (precision == QHP_F64) ((double *)out)[idx] = v;
+    else if (precision == QHP_F32) ((float *)out)[idx] = (float)v;
+    else {
+        float f = (float)v * inv_scale;
+        uint32_t u = __float_as_uint(f);
+        uint32_t rounding = 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+        ((uint16_t *)out)[idx] = (uint16_t)((u + rounding) >> 16);
+    }
+}
+void launch_store_slab(hipStream_t s, int64_t ne, int64_t ld, const double *T, int32_t precision, float inv_scale,
+                       void *out)
+{
+    hipLaunchKernelGGL(k_store_slab, dim3(nblk(ne * ld, 256)), dim3(256), 0, s, ne, ld, T, precision, inv_scale, out);
+}
+// max |T|
+__global__ void k_absmax(int64_t n, const double *T, unsigned long long *out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double v = 0.0;
+    for (; i < n; i += (int64_t)gridDim.x * blockDim.x) v = fmax(v, fabs(T[i]));
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(v));
+}
+void launch_absmax(hipStream_t s, int64_t n, const double *T, unsigned long long *out)
+{
+    hipLaunchKernelGGL(k_absmax, dim3(1024), dim3(256), 0, s, n, T, out);
+}
+// dequantise a stored slab into FP64 [ne][ne]
+__global__ void k_load_slab(int64_t ne, int64_t ld, const void *in, int32_t precision, float scale, double *T)
+{
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= ne * ne) return;
+    int64_t i = idx / ne, j = idx % ne;
+    int64_t o = i * ld + j;
+    double v;
+    if (precision == QHP_F64) v = ((const double *)in)[o];
+    else if (precision == QHP_F32) v = ((const float *)in)[o];
+    else v = (double)(bf16_to_f32(((const uint16_t *)in)[o]) * scale);
+    T[idx] = v;
+}
+void launch_load_slab(hipStream_t s, int64_t ne, int64_t ld, const void *in, int32_t precision, float scale,
+                      double *T)
+{
+    hipLaunchKernelGGL(k_load_slab, dim3(nblk(ne * ne, 256)), dim3(256), 0, s, ne, ld, in, precision, scale, T);
+}
+
+}  // namespace qhp
