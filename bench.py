@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark of the qHP TD-CFIE marching-on-in-time hot path on one MI355X.
+
+Default workload: PEC sphere r = 1 m, icosphere level 4 (7680 edges),
+c*dt = 0.02 m (K = 101 lag blocks), one x-polarised wave along -z with a
+150 MHz modulated Gaussian pulse; synthetic, seeded, no dataset.
+
+A step is one pass of the whole hot path: history sum over T_1..T_K, the FP64
+T_0 solve, the FP64 post-processing to the current j_i.  The FP64 path is
+marched first (plain FP64 slabs), then the same assembly is re-stored in the
+requested precision (default FP32) and marched again; `value` is the steps/s
+of that second march, `rel_err_vs_fp64` compares its currents with the FP64
+march.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="sphere-large", choices=["sphere-large", "sphere-small", "torus-batched"])
+    ap.add_argument("--precision", default="f32", choices=["f32", "bf16", "f64"])
+    ap.add_argument("--solver", default="lu", choices=["lu", "inv"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference march")
+    ap.add_argument("--n-dirs", type=int, default=64, help="directions for torus-batched")
+    return ap.parse_args()
+
+
+def workload(name, n_dirs):
+    from workloads import waves
+    if name == "sphere-large":
+        return waves.sphere_large()
+    if name == "sphere-small":
+        return waves.sphere_small()
+    return waves.torus_batched(n_dirs)
+
+
+def traffic_from_profile(kernel_file, kernel_name, launches_bytes):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+        src = open(os.path.join(ROOT, "paper_2312_06367_amd", "csrc", kernel_file), "rb").read()
+        if rec.get("source_sha256") != hashlib.sha256(src).hexdigest():
+            return None
+        ent = rec.get("kernels", {}).get(kernel_name)
+        if not ent:
+            return None
+        return ent["fetch_bytes_per_launch"] + ent["write_bytes_per_launch"]
+    except Exception:
+        return None
+
+
+def cpu_baseline(ne, K, budget_s=20.0):
+    """Oracle marching step (history sum + LU solve) on host cores, on a
+    bounded sample of the same shape: K_s of the K lag blocks (random FP64
+    data, ne x ne), scaled to K lags."""
+    import numpy as np
+    import scipy.linalg as sla
+    from oracle import mot
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info() if p.get("user_api") == "blas"] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    rng = np.random.default_rng(0)
+    ks = 6
+    T = rng.standard_normal((ks + 1, ne, ne))
+    T[0] += ne * np.eye(ne)
+    ring = [rng.standard_normal(ne) for _ in range(ks)]
+    lu = sla.lu_factor(T[0])
+    r = rng.standard_normal(ne)
+    times = []
+    t_end = time.perf_counter() + budget_s
+    for _ in range(6):
+        t0 = time.perf_counter()
+        h = mot.history_sum(T, ring, ks + 1)
+        t1 = time.perf_counter()
+        sla.lu_solve(lu, r - h)
+        t2 = time.perf_counter()
+        times.append(((t1 - t0) * K / ks) + (t2 - t1))
+        if time.perf_counter() > t_end:
+            break
+    step_s = sorted(times)[len(times) // 2]
+    return {"value": 1.0 / step_s, "unit": "MOT steps/s", "cores": int(threads), "kind": "oracle",
+            "sample": "oracle history sum over %d of the %d lag blocks (FP64 %dx%d, random data) + LU solve, "
+                      "median of %d steps, history time scaled by %d/%d" % (ks, K, ne, ne, len(times), K, ks)}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py measures one GPU only: this build runs the marching solver on a single MI355X "
+              "(--gpus %d is not supported)" % a.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_2312_06367_amd as qhp
+
+    torch.cuda.set_device(0)
+    cfg = workload(a.workload, a.n_dirs)
+    xyz, tri = cfg.mesh
+    n_rhs = len(cfg.waves)
+    n_total = a.warmup + a.steps
+    t0 = time.perf_counter()
+    s = qhp.Solver(cfg.dt, precision="f64", solver=a.solver)
+    s.mesh(xyz, tri)
+    s.assemble()
+    torch.cuda.synchronize()
+    t_asm = time.perf_counter() - t0
+    inf = s.info()
+    ne, K = inf["ne"], inf["K"]
+    print("[bench] %s: ne=%d K=%d n_rhs=%d assembly %.1f s" % (cfg.name, ne, K, n_rhs, t_asm), file=sys.stderr, flush=True)
+
+    def march(tag):
+        s.set_incident(cfg.waves, n_total)
+        jh = torch.zeros((n_total, ne, n_rhs), dtype=torch.float64, device="cuda")
+        s.run(a.warmup, jh[: a.warmup])
+        torch.cuda.synchronize()
+        s.profile(True)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        tw0 = time.perf_counter()
+        ev0.record()
+        s.run(a.steps, jh[a.warmup:])
+        ev1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - tw0
+        ms_hist, launches = s.hist_time()
+        s.profile(False)
+        print("[bench] %s march: %d steps in %.3f s (%.1f steps/s), history kernel %.3f ms avg"
+              % (tag, a.steps, wall, a.steps / wall, ms_hist / max(launches, 1)), file=sys.stderr, flush=True)
+        return jh, wall, ms_hist / max(launches, 1)
+
+    j64 = None
+    fp64 = None
+    if a.precision == "f64" or not a.no_fp64:
+        j64, wall64, hist64 = march("f64")
+        fp64 = {"steps_per_s": a.steps / wall64, "hist_ms": hist64}
+    if a.precision != "f64":
+        s.set_precision(a.precision)
+        jp, wall, hist_ms = march(a.precision)
+    else:
+        jp, wall, hist_ms = j64, wall64, hist64
+    rel_err = None
+    if j64 is not None and jp is not j64:
+        d = torch.linalg.vector_norm(jp - j64, dim=1).max().item()
+        n = torch.linalg.vector_norm(j64, dim=1).max().item()
+        rel_err = d / n
+    esz = {"f64": 8, "f32": 4, "bf16": 2}[a.precision]
+    ysz = 8 if a.precision == "f64" else 4
+    bytes_per_launch = K * ne * ne * esz + K * ne * n_rhs * ysz
+    flops_per_launch = 2.0 * K * ne * ne * n_rhs
+    kname = {"f64": "k_hist_gemv<double>", "f32": "k_hist_gemv<float>", "bf16": "k_hist_gemv<unsigned short>"}[a.precision]
+    if n_rhs == 1:
+        achieved = bytes_per_launch / (hist_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBPS,
+                "traffic": traffic_from_profile("march.hip", kname, bytes_per_launch),
+                "kernel": kname, "algorithmic_bytes_per_launch": bytes_per_launch}
+    else:
+        achieved = flops_per_launch / (hist_ms * 1e-3) / 1e12
+        kname = kname.replace("gemv", "gemm")
+        roof = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
+                "traffic": traffic_from_profile("march.hip", kname, bytes_per_launch),
+                "kernel": kname, "algorithmic_flops_per_launch": flops_per_launch}
+    out = {
+        "metric": "MOT steps/s & history-sum HBM GB/s, batched FP32 vs plain FP64, rel err",
+        "value": a.steps / wall,
+        "unit": "MOT steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * wall / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": a.precision,
+        "data": "synthetic",
+        "config": {"workload": cfg.name, "ne": ne, "K": K, "c_dt_m": cfg.dt, "n_rhs": n_rhs,
+                   "slab_storage": a.precision, "solve": "fp64-" + a.solver, "post_processing": "fp64"},
+        "history_gbps": bytes_per_launch / (hist_ms * 1e-3) / 1e9,
+        "fp64_steps_per_s": fp64["steps_per_s"] if fp64 else None,
+        "fp64_history_gbps": (K * ne * ne * 8 + K * ne * n_rhs * 8) / (fp64["hist_ms"] * 1e-3) / 1e9 if fp64 else None,
+        "rel_err_vs_fp64": rel_err,
+        "assembly_s": t_asm,
+        "roofline": roof,
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(ne, K)
+    s.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

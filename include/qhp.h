@@ -114,6 +114,18 @@ int qhp_mesh(qhp_ctx *ctx, const double *xyz, int64_t nv, const int32_t *tri, in
  * pivot, QHP_ENOMEM when the slabs do not fit. */
 int qhp_assemble(qhp_ctx *ctx);
 
+/* Re-store the assembled T_1..T_K in another precision without assembling
+ * again.  Only from QHP_F64 storage (the assembly is FP64) to QHP_F32 or
+ * QHP_BF16 (per-slab scale = largest |entry|); frees the FP64 slabs.  Allowed
+ * after qhp_assemble; resets the march (call qhp_set_incident again). */
+int qhp_set_precision(qhp_ctx *ctx, int32_t precision);
+
+/* Time the history-sum kernel of every following step with HIP events on
+ * the context's stream (enable != 0), or stop.  qhp_hist_time() returns the
+ * summed kernel time in ms and the number of timed launches since enabling. */
+int qhp_profile(qhp_ctx *ctx, int32_t enable);
+int qhp_hist_time(qhp_ctx *ctx, double *ms_total, int64_t *launches);
+
 /* Right-hand sides r_k = -Z~ G^-T e~(t_k) + eta_c X~ G^-1 h(t_k), k = 1..n_steps
  * (Sec. IV-A), for n_rhs waves (host array).  Resets the march to step 0. */
 int qhp_set_incident(qhp_ctx *ctx, const qhp_wave *waves, int32_t n_rhs, int32_t n_steps);

@@ -50,9 +50,9 @@ class _Info(ctypes.Structure):
                 ("diameter", ctypes.c_double), ("slab_bytes", ctypes.c_size_t)]
 
 
-EXPORTS = ["qhp_create", "qhp_mesh", "qhp_assemble", "qhp_set_incident", "qhp_step", "qhp_run",
-           "qhp_query", "qhp_edges", "qhp_get_matrix", "qhp_keep_raw", "qhp_history_sum",
-           "qhp_last_error", "qhp_destroy"]
+EXPORTS = ["qhp_create", "qhp_mesh", "qhp_assemble", "qhp_set_precision", "qhp_profile",
+           "qhp_hist_time", "qhp_set_incident", "qhp_step", "qhp_run", "qhp_query", "qhp_edges",
+           "qhp_get_matrix", "qhp_keep_raw", "qhp_history_sum", "qhp_last_error", "qhp_destroy"]
 
 _lib = None
 
@@ -69,6 +69,9 @@ def lib():
         L.qhp_create.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(vp)]
         L.qhp_mesh.argtypes = [vp, vp, i64, vp, i64]
         L.qhp_assemble.argtypes = [vp]
+        L.qhp_set_precision.argtypes = [vp, i32]
+        L.qhp_profile.argtypes = [vp, i32]
+        L.qhp_hist_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
         L.qhp_set_incident.argtypes = [vp, ctypes.POINTER(_Wave), i32, i32]
         L.qhp_step.argtypes = [vp, vp]
         L.qhp_run.argtypes = [vp, i32, vp, vp]
@@ -140,6 +143,19 @@ class Solver:
 
     def assemble(self):
         self._check(self.L.qhp_assemble(self.h))
+
+    def set_precision(self, precision: str):
+        self._check(self.L.qhp_set_precision(self.h, PRECISIONS[precision]))
+        self.precision = precision
+
+    def profile(self, enable=True):
+        self._check(self.L.qhp_profile(self.h, int(bool(enable))))
+
+    def hist_time(self):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._check(self.L.qhp_hist_time(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
 
     def set_incident(self, waves, n_steps: int):
         arr = (_Wave * len(waves))(*[to_cwave(w) for w in waves])

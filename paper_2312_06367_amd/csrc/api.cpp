@@ -3,7 +3,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -113,6 +116,21 @@ struct qhp_ctx {
     bool broken = false;
     DBuf waves_d, rhs, ring64, ring32, bvec, zvec, yvec, partial, sv, zc, flags, epoch, errflag;
     int nsplit = 1;
+    // profiling of the history kernel
+    bool profiling = false;
+    std::vector<hipEvent_t> ev;
+    double hist_ms = 0.0;
+    int64_t hist_launches = 0;
+    bool verbose = false;
+    std::chrono::steady_clock::time_point t_stage;
+    void stage(const char *name)
+    {
+        if (!verbose) return;
+        (void)hipStreamSynchronize(s);
+        auto now = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[qhp] %-28s %9.3f s\n", name, std::chrono::duration<double>(now - t_stage).count());
+        t_stage = now;
+    }
 };
 
 using qhp::AsmArgs;
@@ -143,6 +161,8 @@ extern "C" int qhp_create(const qhp_params *params, qhp_ctx **out)
     if (c->p.n_psi <= 0) c->p.n_psi = 10;
     if (!(c->p.eta_c > 0.0)) c->p.eta_c = 1.0;
     c->s = (hipStream_t)params->stream;
+    const char *vb = std::getenv("QHP_VERBOSE");
+    c->verbose = vb && vb[0] && vb[0] != '0';
     if (hipSetDevice(params->device) != hipSuccess) {
         delete c;
         return QHP_EDEVICE;
@@ -274,6 +294,7 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
     c->kappa = 1.0 / c->p.dt;
     c->ld = (ne + 511) / 512 * 512;
     const double dtn = c->dtn, kappa = c->kappa;
+    c->t_stage = std::chrono::steady_clock::now();
     upload_tables(c);
     {
         std::vector<double> gx, gw;
@@ -294,6 +315,7 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
         qhp::launch_proj(s, ne, a.cells, c->LSp.as<double>(), nc, c->PS.as<double>());
         qhp::launch_proj(s, ne, a.edges, LLp.as<double>(), nv, c->PPL.as<double>());
     }
+    c->stage("projectors");
     // ---- Gram and Yukawa operators (Sec. II-C)
     c->G.alloc(sizeof(double) * nn);
     zero(c->G, s);
@@ -315,6 +337,7 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
         qhp::launch_yuk_mfie(s, a, kappa, c->M.as<double>());
     }
     hip_check(hipStreamSynchronize(s), "static operators");
+    c->stage("gram + yukawa quadrature");
     // ---- Z~ (Sec. III-B), X~ (Sec. III-C), preconditioners
     {
         DBuf left, right, t1, t2, Zt, Xt, Glu, Gpiv, info, Y;
@@ -356,6 +379,7 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
                                    sizeof(double) * ne, ne, hipMemcpyDeviceToDevice, s), "copy P_M");
         hip_check(hipStreamSynchronize(s), "preconditioners");
     }
+    c->stage("preconditioners P_E, P_M");
     // ---- lag blocks T_0..T_K (Sec. IV-A) in chunks of lags
     const int64_t K = c->K;
     const int32_t prec = c->p.precision;
@@ -398,6 +422,7 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
                     qhp::launch_sym_s(s, nc, S.as<double>() + (j - j0) * 3 * (size_t)nc * nc);
                 }
             }
+            c->stage("retarded shell quadrature");
             auto shellV = [&](int64_t j) -> const double * {
                 return (j >= j0 && j <= j1) ? V.as<double>() + (j - j0) * nn : nullptr;
             };
@@ -454,6 +479,7 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
                 std::swap(Cp.p, Ck.p);
             }
             hip_check(hipStreamSynchronize(s), "lag blocks");
+            c->stage("lag combination + slab GEMMs");
         }
     }
     upload(c->scales_d, c->scales, s);
@@ -483,6 +509,7 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
         }
         hip_check(hipStreamSynchronize(s), "T_0 factorisation");
     }
+    c->stage("T_0 LU");
     c->state = 2;
     return QHP_OK;
     API_CATCH(ctx)
@@ -568,9 +595,17 @@ static void do_step(qhp_ctx *c, double *j_out, double *y_out)
     const int64_t i = c->step + 1;
     const double *r_i = c->rhs.as<double>() + (i - 1) * ne * nr;
     const bool f64 = c->p.precision == QHP_F64;
-    qhp::launch_history(s, c->p.precision, ne, ld, nr, K, c->slabs.p, f64 || c->p.precision == QHP_F32 ? nullptr : c->scales_d.as<float>(),
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->profiling) {
+        hip_check(hipEventCreate(&e0), "event");
+        hip_check(hipEventCreate(&e1), "event");
+        c->ev.push_back(e0);
+        c->ev.push_back(e1);
+    }
+    qhp::launch_history(s, c->p.precision, ne, ld, nr, K, c->slabs.p,
+                        c->p.precision == QHP_BF16 ? c->scales_d.as<float>() : nullptr,
                         f64 ? c->ring64.p : c->ring32.p, K, c->head, r_i, c->bvec.as<double>(), c->partial.p,
-                        c->nsplit);
+                        c->nsplit, e0, e1);
     double *y = c->yvec.as<double>();
     if (c->p.solver == QHP_SOLVE_INV) {
         if (nr == 1) qhp::launch_gemv_f64(s, ne, c->Tinv.as<double>(), c->bvec.as<double>(), y);
@@ -603,10 +638,24 @@ static void do_step(qhp_ctx *c, double *j_out, double *y_out)
     c->step = i;
 }
 
+static void collect_events(qhp_ctx *c)
+{
+    for (size_t q = 0; q + 1 < c->ev.size(); q += 2) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->ev[q], c->ev[q + 1]) == hipSuccess) {
+            c->hist_ms += ms;
+            c->hist_launches += 1;
+        }
+    }
+    for (auto e : c->ev) (void)hipEventDestroy(e);
+    c->ev.clear();
+}
+
 static int finish_run(qhp_ctx *c)
 {
     hip_check(hipStreamSynchronize(c->s), "march");
     hip_check(hipGetLastError(), "march launch");
+    collect_events(c);
     int e = 0;
     hip_check(hipMemcpy(&e, c->errflag.p, sizeof(int), hipMemcpyDeviceToHost), "error flag");
     if (e == 2) {
@@ -641,6 +690,66 @@ extern "C" int qhp_run(qhp_ctx *ctx, int32_t n_steps, double *j_hist, double *y_
     for (int32_t t = 0; t < n_steps; ++t)
         do_step(ctx, j_hist ? j_hist + t * stride : nullptr, y_hist ? y_hist + t * stride : nullptr);
     return finish_run(ctx);
+    API_CATCH(ctx)
+}
+
+extern "C" int qhp_profile(qhp_ctx *ctx, int32_t enable)
+{
+    if (!ctx) return QHP_EINVAL;
+    ctx->profiling = enable != 0;
+    ctx->hist_ms = 0.0;
+    ctx->hist_launches = 0;
+    return QHP_OK;
+}
+
+extern "C" int qhp_hist_time(qhp_ctx *ctx, double *ms_total, int64_t *launches)
+{
+    if (!ctx || !ms_total || !launches) return QHP_EINVAL;
+    *ms_total = ctx->hist_ms;
+    *launches = ctx->hist_launches;
+    return QHP_OK;
+}
+
+extern "C" int qhp_set_precision(qhp_ctx *ctx, int32_t precision)
+{
+    if (!ctx) return QHP_EINVAL;
+    if (ctx->state < 2) return guard(ctx, QHP_ESTATE, "assemble first");
+    if (precision == ctx->p.precision) return QHP_OK;
+    if (ctx->p.precision != QHP_F64 || (precision != QHP_F32 && precision != QHP_BF16))
+        return guard(ctx, QHP_EINVAL, "only FP64 slabs can be re-stored, as FP32 or BF16");
+    API_TRY
+    hipStream_t s = ctx->s;
+    const int64_t ne = ctx->mesh.ne, ld = ctx->ld, K = ctx->K;
+    const size_t per = (size_t)ne * ld;
+    const size_t esz = precision == QHP_F32 ? 4 : 2;
+    DBuf out, amax;
+    out.alloc(esz * per * K);
+    amax.alloc(sizeof(unsigned long long));
+    for (int64_t k = 0; k < K; ++k) {
+        const double *in = ctx->slabs.as<double>() + k * per;
+        float inv_scale = 1.0f;
+        ctx->scales[k] = 1.0f;
+        if (precision == QHP_BF16) {
+            unsigned long long bits = 0;
+            zero(amax, s);
+            qhp::launch_absmax(s, (int64_t)per, in, amax.as<unsigned long long>());
+            hip_check(hipMemcpyAsync(&bits, amax.p, 8, hipMemcpyDeviceToHost, s), "absmax");
+            hip_check(hipStreamSynchronize(s), "absmax");
+            double mx;
+            std::memcpy(&mx, &bits, 8);
+            ctx->scales[k] = mx > 0.0 ? (float)mx : 1.0f;
+            inv_scale = 1.0f / ctx->scales[k];
+        }
+        qhp::launch_convert_slab(s, (int64_t)per, in, precision, inv_scale, (char *)out.p + esz * per * k);
+    }
+    hip_check(hipStreamSynchronize(s), "convert slabs");
+    std::swap(ctx->slabs.p, out.p);
+    std::swap(ctx->slabs.bytes, out.bytes);
+    upload(ctx->scales_d, ctx->scales, s);
+    ctx->p.precision = precision;
+    ctx->ring32.release();
+    ctx->state = 2;
+    return QHP_OK;
     API_CATCH(ctx)
 }
 

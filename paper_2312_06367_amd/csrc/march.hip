@@ -357,31 +357,32 @@ int hist_splits(int64_t ne, int64_t kmax, int64_t nrhs)
 
 void launch_history(hipStream_t s, int32_t precision, int64_t ne, int64_t ld, int64_t nrhs, int64_t kmax,
                     const void *slabs, const float *scales, const void *ring, int64_t n_slots, int64_t head,
-                    const double *r, double *b, void *partial, int nsplit)
+                    const double *r, double *b, void *partial, int nsplit, hipEvent_t e0, hipEvent_t e1)
 {
     if (kmax <= 0) {
         (void)hipMemcpyAsync(b, r, sizeof(double) * ne * nrhs, hipMemcpyDeviceToDevice, s);
         return;
     }
     int64_t lps = (kmax + nsplit - 1) / nsplit;
+    if (e0) (void)hipEventRecord(e0, s);
     if (nrhs == 1) {
         dim3 grid(nblk(ne, 16), (unsigned)nsplit);
-        if (precision == QHP_F64) {
+        if (precision == QHP_F64)
             hipLaunchKernelGGL(k_hist_gemv<double>, grid, dim3(256), 0, s, ne, ld, kmax, lps, (const double *)slabs,
                                scales, (const double *)ring, n_slots, head, (double *)partial);
-            hipLaunchKernelGGL(k_hist_finish<double>, dim3(nblk(ne, 256)), dim3(256), 0, s, ne, (int64_t)nsplit,
-                               (const double *)partial, r, b);
-        } else if (precision == QHP_F32) {
+        else if (precision == QHP_F32)
             hipLaunchKernelGGL(k_hist_gemv<float>, grid, dim3(256), 0, s, ne, ld, kmax, lps, (const float *)slabs,
                                scales, (const float *)ring, n_slots, head, (float *)partial);
-            hipLaunchKernelGGL(k_hist_finish<float>, dim3(nblk(ne, 256)), dim3(256), 0, s, ne, (int64_t)nsplit,
-                               (const float *)partial, r, b);
-        } else {
+        else
             hipLaunchKernelGGL(k_hist_gemv<uint16_t>, grid, dim3(256), 0, s, ne, ld, kmax, lps,
                                (const uint16_t *)slabs, scales, (const float *)ring, n_slots, head, (float *)partial);
+        if (e1) (void)hipEventRecord(e1, s);
+        if (precision == QHP_F64)
+            hipLaunchKernelGGL(k_hist_finish<double>, dim3(nblk(ne, 256)), dim3(256), 0, s, ne, (int64_t)nsplit,
+                               (const double *)partial, r, b);
+        else
             hipLaunchKernelGGL(k_hist_finish<float>, dim3(nblk(ne, 256)), dim3(256), 0, s, ne, (int64_t)nsplit,
                                (const float *)partial, r, b);
-        }
         return;
     }
     if (precision == QHP_F64) {
@@ -392,6 +393,7 @@ void launch_history(hipStream_t s, int32_t precision, int64_t ne, int64_t ld, in
             const double *Y = (const double *)ring + ((head + k - 1) % n_slots) * ld * nrhs;
             gemm_f64(s, false, false, ne, nrhs, ne, 1.0, Tk, ld, Y, nrhs, k == 1 ? 0.0 : 1.0, acc, nrhs);
         }
+        if (e1) (void)hipEventRecord(e1, s);
         hipLaunchKernelGGL(k_hist_finish<double>, dim3(nblk(ne * nrhs, 256)), dim3(256), 0, s, ne * nrhs,
                            (int64_t)1, (const double *)acc, r, b);
         return;
@@ -403,8 +405,29 @@ void launch_history(hipStream_t s, int32_t precision, int64_t ne, int64_t ld, in
     else
         hipLaunchKernelGGL(k_hist_gemm<float>, grid, dim3(256), 0, s, ne, ld, nrhs, kmax, lps, (const float *)slabs,
                            scales, (const float *)ring, n_slots, head, (float *)partial);
+    if (e1) (void)hipEventRecord(e1, s);
     hipLaunchKernelGGL(k_hist_finish<float>, dim3(nblk(ne * nrhs, 256)), dim3(256), 0, s, ne * nrhs,
                        (int64_t)nsplit, (const float *)partial, r, b);
+}
+
+// FP64 slab [ne][ld] -> another precision, same layout
+__global__ void k_convert_slab(int64_t n, const double *in, int32_t precision, float inv_scale, void *out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double v = in[i];
+    if (precision == QHP_F32) {
+        ((float *)out)[i] = (float)v;
+    } else {
+        float f = (float)v * inv_scale;
+        uint32_t u = __float_as_uint(f);
+        uint32_t rounding = 0x7fffu + ((u >> 16) & 1u);
+        ((uint16_t *)out)[i] = (uint16_t)((u + rounding) >> 16);
+    }
+}
+void launch_convert_slab(hipStream_t s, int64_t n, const double *in, int32_t precision, float inv_scale, void *out)
+{
+    hipLaunchKernelGGL(k_convert_slab, dim3(nblk(n, 256)), dim3(256), 0, s, n, in, precision, inv_scale, out);
 }
 
 // ------------------------------------------------------------------ solve
