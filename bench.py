@@ -5,12 +5,13 @@ Default workload: PEC sphere r = 1 m, icosphere level 4 (7680 edges),
 c*dt = 0.02 m (K = 101 lag blocks), one x-polarised wave along -z with a
 150 MHz modulated Gaussian pulse; synthetic, seeded, no dataset.
 
-A step is one pass of the whole hot path: history sum over T_1..T_K, the FP64
-T_0 solve, the FP64 post-processing to the current j_i.  The FP64 path is
-marched first (plain FP64 slabs), then the same assembly is re-stored in the
-requested precision (default FP32) and marched again; `value` is the steps/s
-of that second march, `rel_err_vs_fp64` compares its currents with the FP64
-march.  Prints one JSON line.
+A step is one pass of the whole hot path: the history sum over T_1..T_K, the
+FP64 T_0 solve and the FP64 post-processing to the current j_i.  The FP64
+assembly is marched first with FP64 slabs (the plain FP64 path, LU
+back-solves and the inverse product), then re-stored in the requested
+precision (default FP32) and marched again; `value` is the steps/s of that
+march, `rel_err_vs_fp64` = max_i |j_i - j_i^{FP64}| / max_i |j_i^{FP64}|.
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -34,10 +35,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="sphere-large", choices=["sphere-large", "sphere-small", "torus-batched"])
-    ap.add_argument("--precision", default="f32", choices=["f32", "bf16", "f64"])
-    ap.add_argument("--solver", default="lu", choices=["lu", "inv"])
+    ap.add_argument("--precision", default="f32", choices=["f32", "f32a", "bf16", "f64"])
+    ap.add_argument("--solver", default="inv", choices=["lu", "inv"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference march")
+    ap.add_argument("--quick", action="store_true", help="only the FP64 reference and the headline march")
     ap.add_argument("--n-dirs", type=int, default=64, help="directions for torus-batched")
     return ap.parse_args()
 
@@ -51,29 +52,27 @@ def workload(name, n_dirs):
     return waves.torus_batched(n_dirs)
 
 
-def traffic_from_profile(kernel_file, kernel_name, launches_bytes):
+def traffic_from_profile(kernel_name):
     """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel source."""
+    taken on the current kernel source (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
         rec = json.load(open(path))
-        src = open(os.path.join(ROOT, "paper_2312_06367_amd", "csrc", kernel_file), "rb").read()
+        src = open(os.path.join(ROOT, "paper_2312_06367_amd", "csrc", "march.hip"), "rb").read()
         if rec.get("source_sha256") != hashlib.sha256(src).hexdigest():
             return None
         ent = rec.get("kernels", {}).get(kernel_name)
-        if not ent:
-            return None
-        return ent["fetch_bytes_per_launch"] + ent["write_bytes_per_launch"]
+        return None if not ent else ent["fetch_bytes_per_launch"] + ent["write_bytes_per_launch"]
     except Exception:
         return None
 
 
 def cpu_baseline(ne, K, budget_s=20.0):
     """Oracle marching step (history sum + LU solve) on host cores, on a
-    bounded sample of the same shape: K_s of the K lag blocks (random FP64
-    data, ne x ne), scaled to K lags."""
+    bounded sample of the same shape: ks of the K lag blocks (random FP64
+    data, ne x ne), the history time scaled to K lags."""
     import numpy as np
     import scipy.linalg as sla
     from oracle import mot
@@ -112,7 +111,6 @@ def main():
         print("bench.py measures one GPU only: this build runs the marching solver on a single MI355X "
               "(--gpus %d is not supported)" % a.gpus, file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
     import paper_2312_06367_amd as qhp
 
@@ -122,87 +120,104 @@ def main():
     n_rhs = len(cfg.waves)
     n_total = a.warmup + a.steps
     t0 = time.perf_counter()
-    s = qhp.Solver(cfg.dt, precision="f64", solver=a.solver)
+    s = qhp.Solver(cfg.dt, precision="f64", solver="lu")
     s.mesh(xyz, tri)
     s.assemble()
     torch.cuda.synchronize()
     t_asm = time.perf_counter() - t0
     inf = s.info()
     ne, K = inf["ne"], inf["K"]
-    print("[bench] %s: ne=%d K=%d n_rhs=%d assembly %.1f s" % (cfg.name, ne, K, n_rhs, t_asm), file=sys.stderr, flush=True)
+    log = lambda *x: print("[bench]", *x, file=sys.stderr, flush=True)
+    log("%s: ne=%d K=%d n_rhs=%d assembly %.1f s" % (cfg.name, ne, K, n_rhs, t_asm))
 
-    def march(tag):
+    def march(tag, solver):
+        s.set_solver(solver)
         s.set_incident(cfg.waves, n_total)
         jh = torch.zeros((n_total, ne, n_rhs), dtype=torch.float64, device="cuda")
         s.run(a.warmup, jh[: a.warmup])
         torch.cuda.synchronize()
         s.profile(True)
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         tw0 = time.perf_counter()
-        ev0.record()
         s.run(a.steps, jh[a.warmup:])
-        ev1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - tw0
         ms_hist, launches = s.hist_time()
         s.profile(False)
-        print("[bench] %s march: %d steps in %.3f s (%.1f steps/s), history kernel %.3f ms avg"
-              % (tag, a.steps, wall, a.steps / wall, ms_hist / max(launches, 1)), file=sys.stderr, flush=True)
-        return jh, wall, ms_hist / max(launches, 1)
+        hist = ms_hist / max(launches, 1)
+        log("%-9s %-3s: %d steps %.3f s = %.1f steps/s; history kernel %.3f ms (variant %d, %d splits)"
+            % (tag, solver, a.steps, wall, a.steps / wall, hist, s.info()["hist_variant"], s.info()["hist_splits"]))
+        return {"j": jh, "steps_per_s": a.steps / wall, "wall": wall, "hist_ms": hist}
 
-    j64 = None
-    fp64 = None
-    if a.precision == "f64" or not a.no_fp64:
-        j64, wall64, hist64 = march("f64")
-        fp64 = {"steps_per_s": a.steps / wall64, "hist_ms": hist64}
+    def rel(jx, jref):
+        d = torch.linalg.vector_norm(jx - jref, dim=1).max().item()
+        return d / torch.linalg.vector_norm(jref, dim=1).max().item()
+
+    def gbps(prec, hist_ms):
+        esz = {"f64": 8, "f32": 4, "f32a": 4, "bf16": 2}[prec]
+        ysz = 8 if prec in ("f64", "f32a") else 4
+        return (K * ne * ne * esz + K * ne * n_rhs * ysz) / (hist_ms * 1e-3) / 1e9
+
+    runs = {}
+    runs["f64_lu"] = march("f64", "lu")
+    if not a.quick or a.solver == "inv":
+        runs["f64_inv"] = march("f64", "inv")
     if a.precision != "f64":
         s.set_precision(a.precision)
-        jp, wall, hist_ms = march(a.precision)
+        runs["head"] = march(a.precision, a.solver)
+        if not a.quick and a.precision == "f32":
+            runs["f32_" + ("lu" if a.solver == "inv" else "inv")] = march("f32", "lu" if a.solver == "inv" else "inv")
+            s.set_precision("f32a")
+            runs["f32a_" + a.solver] = march("f32a", a.solver)
     else:
-        jp, wall, hist_ms = j64, wall64, hist64
-    rel_err = None
-    if j64 is not None and jp is not j64:
-        d = torch.linalg.vector_norm(jp - j64, dim=1).max().item()
-        n = torch.linalg.vector_norm(j64, dim=1).max().item()
-        rel_err = d / n
-    esz = {"f64": 8, "f32": 4, "bf16": 2}[a.precision]
-    ysz = 8 if a.precision == "f64" else 4
+        runs["head"] = runs["f64_" + a.solver]
+    head = runs["head"]
+    jref = runs["f64_lu"]["j"]
+    esz = {"f64": 8, "f32": 4, "f32a": 4, "bf16": 2}[a.precision]
+    ysz = 8 if a.precision in ("f64", "f32a") else 4
     bytes_per_launch = K * ne * ne * esz + K * ne * n_rhs * ysz
     flops_per_launch = 2.0 * K * ne * ne * n_rhs
-    kname = {"f64": "k_hist_gemv<double>", "f32": "k_hist_gemv<float>", "bf16": "k_hist_gemv<unsigned short>"}[a.precision]
     if n_rhs == 1:
-        achieved = bytes_per_launch / (hist_ms * 1e-3) / 1e9
+        kname = {"f64": "k_hist_gemv<double,double,double>", "f32": "k_hist_gemv<float,float,float>",
+                 "f32a": "k_hist_gemv<float,double,double>", "bf16": "k_hist_gemv<unsigned short,float,float>"}[a.precision]
+        achieved = bytes_per_launch / (head["hist_ms"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBPS,
-                "traffic": traffic_from_profile("march.hip", kname, bytes_per_launch),
-                "kernel": kname, "algorithmic_bytes_per_launch": bytes_per_launch}
+                "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_from_profile(kname),
+                "kernel": kname, "algorithmic_bytes_per_launch": bytes_per_launch,
+                "kernel_ms_avg": head["hist_ms"]}
     else:
-        achieved = flops_per_launch / (hist_ms * 1e-3) / 1e12
-        kname = kname.replace("gemv", "gemm")
+        kname = "k_hist_gemm<%s>" % ("unsigned short" if a.precision == "bf16" else "float")
+        achieved = flops_per_launch / (head["hist_ms"] * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
-                "traffic": traffic_from_profile("march.hip", kname, bytes_per_launch),
-                "kernel": kname, "algorithmic_flops_per_launch": flops_per_launch}
+                "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "traffic": traffic_from_profile(kname),
+                "kernel": kname, "algorithmic_flops_per_launch": flops_per_launch,
+                "kernel_ms_avg": head["hist_ms"]}
+    forms = {}
+    for key, rr in runs.items():
+        if key == "head":
+            continue
+        prec = key.split("_")[0]
+        forms[key] = {"steps_per_s": rr["steps_per_s"], "history_ms": rr["hist_ms"],
+                      "history_gbps": gbps(prec, rr["hist_ms"]), "rel_err_vs_fp64_lu": rel(rr["j"], jref)}
     out = {
         "metric": "MOT steps/s & history-sum HBM GB/s, batched FP32 vs plain FP64, rel err",
-        "value": a.steps / wall,
+        "value": head["steps_per_s"],
         "unit": "MOT steps/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": 1e3 * wall / a.steps,
+        "ms_per_step": 1e3 * head["wall"] / a.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": a.precision,
+        "dtype": "f32" if a.precision in ("f32", "bf16") else ("f32-storage/f64-accumulate" if a.precision == "f32a" else "f64"),
         "data": "synthetic",
         "config": {"workload": cfg.name, "ne": ne, "K": K, "c_dt_m": cfg.dt, "n_rhs": n_rhs,
                    "slab_storage": a.precision, "solve": "fp64-" + a.solver, "post_processing": "fp64"},
-        "history_gbps": bytes_per_launch / (hist_ms * 1e-3) / 1e9,
-        "fp64_steps_per_s": fp64["steps_per_s"] if fp64 else None,
-        "fp64_history_gbps": (K * ne * ne * 8 + K * ne * n_rhs * 8) / (fp64["hist_ms"] * 1e-3) / 1e9 if fp64 else None,
-        "rel_err_vs_fp64": rel_err,
+        "history_gbps": gbps(a.precision, head["hist_ms"]),
+        "rel_err_vs_fp64": rel(head["j"], jref),
+        "fp64_steps_per_s": runs["f64_lu"]["steps_per_s"],
+        "forms": forms,
         "assembly_s": t_asm,
         "roofline": roof,
     }

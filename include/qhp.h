@@ -46,8 +46,14 @@ enum {
     QHP_EUNSTABLE = -8  /* non-finite value in the marching solution          */
 };
 
-/* storage of the lag blocks T_k, k >= 1 (T_0 is always kept in FP64) */
-enum { QHP_F64 = 0, QHP_F32 = 1, QHP_BF16 = 2 };
+/* storage of the lag blocks T_k, k >= 1, and the history-sum arithmetic
+ * (T_0, the solve and the post-processing are always FP64):
+ *   QHP_F64  FP64 blocks, FP64 products and sums
+ *   QHP_F32  FP32 blocks, FP32 copy of y, FP32 products and sums
+ *   QHP_BF16 BF16 blocks with a per-block FP32 scale, FP32 y, FP32 sums
+ *   QHP_F32A FP32 blocks, FP64 y, products and sums in FP64 (one right-hand
+ *            side only) */
+enum { QHP_F64 = 0, QHP_F32 = 1, QHP_BF16 = 2, QHP_F32A = 3 };
 
 /* per-step solve with T_0 (the paper writes only T_0^{-1}, Sec. IV-B) */
 enum {
@@ -92,6 +98,8 @@ typedef struct {
     int64_t ld;          /* row stride (elements) of the stored slabs        */
     double diameter;     /* D = largest vertex-vertex distance               */
     size_t slab_bytes;   /* device bytes of the stored T_1..T_K              */
+    int64_t hist_variant; /* autotuned history-kernel variant (-1: none)    */
+    int64_t hist_splits;  /* lag splits of the history sum                  */
 } qhp_info;
 
 /* Create a context (no device work beyond selecting params->device).
@@ -115,10 +123,15 @@ int qhp_mesh(qhp_ctx *ctx, const double *xyz, int64_t nv, const int32_t *tri, in
 int qhp_assemble(qhp_ctx *ctx);
 
 /* Re-store the assembled T_1..T_K in another precision without assembling
- * again.  Only from QHP_F64 storage (the assembly is FP64) to QHP_F32 or
- * QHP_BF16 (per-slab scale = largest |entry|); frees the FP64 slabs.  Allowed
- * after qhp_assemble; resets the march (call qhp_set_incident again). */
+ * again: from QHP_F64 storage (the assembly is FP64) to QHP_F32, QHP_F32A or
+ * QHP_BF16 (per-slab scale = largest |entry|), freeing the FP64 slabs; or
+ * between QHP_F32 and QHP_F32A, which share the FP32 storage.  Allowed after
+ * qhp_assemble; resets the march (call qhp_set_incident again). */
 int qhp_set_precision(qhp_ctx *ctx, int32_t precision);
+
+/* Switch the per-step T_0 solve (QHP_SOLVE_LU / QHP_SOLVE_INV); both use the
+ * FP64 LU of T_0 made by qhp_assemble.  Takes effect at the next step. */
+int qhp_set_solver(qhp_ctx *ctx, int32_t solver);
 
 /* Time the history-sum kernel of every following step with HIP events on
  * the context's stream (enable != 0), or stop.  qhp_hist_time() returns the

@@ -15,13 +15,13 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqhp.so")
 
-QHP_F64, QHP_F32, QHP_BF16 = 0, 1, 2
+QHP_F64, QHP_F32, QHP_BF16, QHP_F32A = 0, 1, 2, 3
 QHP_SOLVE_LU, QHP_SOLVE_INV = 0, 1
 MAT = {"gram": 0, "zs": 1, "zh": 2, "m": 3, "psigma": 4, "plambda": 5, "pe": 6, "pm": 7,
        "slab": 8, "a": 9, "b": 10, "c": 11}
 ERRORS = {0: "OK", -1: "EINVAL", -2: "EMESH", -3: "ESTATE", -4: "ENOMEM", -5: "EDEVICE",
           -6: "ESINGULAR", -7: "ENOCONV", -8: "EUNSTABLE"}
-PRECISIONS = {"f64": QHP_F64, "f32": QHP_F32, "bf16": QHP_BF16}
+PRECISIONS = {"f64": QHP_F64, "f32": QHP_F32, "bf16": QHP_BF16, "f32a": QHP_F32A}
 SOLVERS = {"lu": QHP_SOLVE_LU, "inv": QHP_SOLVE_INV}
 
 
@@ -47,10 +47,11 @@ class _Info(ctypes.Structure):
     _fields_ = [("nv", ctypes.c_int64), ("ne", ctypes.c_int64), ("nc", ctypes.c_int64),
                 ("n_harmonic", ctypes.c_int64), ("K", ctypes.c_int64), ("n_rhs", ctypes.c_int64),
                 ("n_steps", ctypes.c_int64), ("step", ctypes.c_int64), ("ld", ctypes.c_int64),
-                ("diameter", ctypes.c_double), ("slab_bytes", ctypes.c_size_t)]
+                ("diameter", ctypes.c_double), ("slab_bytes", ctypes.c_size_t),
+                ("hist_variant", ctypes.c_int64), ("hist_splits", ctypes.c_int64)]
 
 
-EXPORTS = ["qhp_create", "qhp_mesh", "qhp_assemble", "qhp_set_precision", "qhp_profile",
+EXPORTS = ["qhp_create", "qhp_mesh", "qhp_assemble", "qhp_set_precision", "qhp_set_solver", "qhp_profile",
            "qhp_hist_time", "qhp_set_incident", "qhp_step", "qhp_run", "qhp_query", "qhp_edges",
            "qhp_get_matrix", "qhp_keep_raw", "qhp_history_sum", "qhp_last_error", "qhp_destroy"]
 
@@ -70,6 +71,7 @@ def lib():
         L.qhp_mesh.argtypes = [vp, vp, i64, vp, i64]
         L.qhp_assemble.argtypes = [vp]
         L.qhp_set_precision.argtypes = [vp, i32]
+        L.qhp_set_solver.argtypes = [vp, i32]
         L.qhp_profile.argtypes = [vp, i32]
         L.qhp_hist_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
         L.qhp_set_incident.argtypes = [vp, ctypes.POINTER(_Wave), i32, i32]
@@ -147,6 +149,9 @@ class Solver:
     def set_precision(self, precision: str):
         self._check(self.L.qhp_set_precision(self.h, PRECISIONS[precision]))
         self.precision = precision
+
+    def set_solver(self, solver: str):
+        self._check(self.L.qhp_set_solver(self.h, SOLVERS[solver]))
 
     def profile(self, enable=True):
         self._check(self.L.qhp_profile(self.h, int(bool(enable))))

@@ -116,6 +116,7 @@ struct qhp_ctx {
     bool broken = false;
     DBuf waves_d, rhs, ring64, ring32, bvec, zvec, yvec, partial, sv, zc, flags, epoch, errflag;
     int nsplit = 1;
+    int hv = -1;  // autotuned variant of the single right-hand-side history kernel
     // profiling of the history kernel
     bool profiling = false;
     std::vector<hipEvent_t> ev;
@@ -150,7 +151,7 @@ static int guard(qhp_ctx *ctx, int code, const std::string &msg)
 extern "C" int qhp_create(const qhp_params *params, qhp_ctx **out)
 {
     if (!params || !out) return QHP_EINVAL;
-    if (!(params->dt > 0.0) || params->precision < QHP_F64 || params->precision > QHP_BF16 ||
+    if (!(params->dt > 0.0) || params->precision < QHP_F64 || params->precision > QHP_F32A ||
         params->solver < QHP_SOLVE_LU || params->solver > QHP_SOLVE_INV || params->n_psi > 32)
         return QHP_EINVAL;
     int ndev = 0;
@@ -383,7 +384,7 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
     // ---- lag blocks T_0..T_K (Sec. IV-A) in chunks of lags
     const int64_t K = c->K;
     const int32_t prec = c->p.precision;
-    const size_t esz = prec == QHP_F64 ? 8 : (prec == QHP_F32 ? 4 : 2);
+    const size_t esz = prec == QHP_F64 ? 8 : (prec == QHP_BF16 ? 2 : 4);
     c->slabs.alloc(esz * (size_t)K * ne * c->ld);
     c->scales.assign(K, 1.0f);
     c->T0raw.alloc(sizeof(double) * nn);
@@ -502,11 +503,10 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
         c->Uinv.alloc(sizeof(double) * nb * 64 * 64);
         qhp::launch_diag_inv(s, ne, c->LU0.as<double>(), 0, c->Linv.as<double>());
         qhp::launch_diag_inv(s, ne, c->LU0.as<double>(), 1, c->Uinv.as<double>());
-        if (c->p.solver == QHP_SOLVE_INV) {
-            c->Tinv.alloc(sizeof(double) * nn);
-            qhp::eye_plus(s, ne, 1.0, 0.0, c->LU0.as<double>(), c->Tinv.as<double>());
-            qhp::getrs_f64(s, false, ne, ne, c->LU0.as<double>(), ne, c->ipiv0.as<int32_t>(), c->Tinv.as<double>(), ne);
-        }
+        // T_0^{-1} from the same LU (used by QHP_SOLVE_INV)
+        c->Tinv.alloc(sizeof(double) * nn);
+        qhp::eye_plus(s, ne, 1.0, 0.0, c->LU0.as<double>(), c->Tinv.as<double>());
+        qhp::getrs_f64(s, false, ne, ne, c->LU0.as<double>(), ne, c->ipiv0.as<int32_t>(), c->Tinv.as<double>(), ne);
         hip_check(hipStreamSynchronize(s), "T_0 factorisation");
     }
     c->stage("T_0 LU");
@@ -515,11 +515,61 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
     API_CATCH(ctx)
 }
 
+// Pick the fastest history-kernel variant and split count on the context's
+// own slabs (timed with HIP events, two launches each after a warm-up).
+static void autotune(qhp_ctx *c)
+{
+    c->hv = -1;
+    if (c->nrhs != 1) return;
+    hipStream_t s = c->s;
+    const int64_t ne = c->mesh.ne, K = c->K;
+    const int base = c->nsplit;
+    int cand[3] = {std::max(1, base / 2), base, (int)std::min<int64_t>(2 * base, K)};
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "event");
+    hip_check(hipEventCreate(&e1), "event");
+    const void *ring = c->ring32.p ? c->ring32.p : c->ring64.p;
+    const float *sc = c->p.precision == QHP_BF16 ? c->scales_d.as<float>() : nullptr;
+    float best = 1e30f;
+    int best_v = 2, best_s = base;
+    for (int v = 0; v < qhp::gemv_variant_count(); ++v)
+        for (int q = 0; q < 3; ++q) {
+            if (q > 0 && cand[q] == cand[q - 1]) continue;
+            int ns = cand[q];
+            qhp::launch_history(s, c->p.precision, ne, c->ld, 1, K, c->slabs.p, sc, ring, K, 0, c->rhs.as<double>(),
+                                c->bvec.as<double>(), c->partial.p, ns, nullptr, nullptr, v);
+            hip_check(hipEventRecord(e0, s), "event");
+            for (int rep = 0; rep < 2; ++rep)
+                qhp::launch_history(s, c->p.precision, ne, c->ld, 1, K, c->slabs.p, sc, ring, K, 0,
+                                    c->rhs.as<double>(), c->bvec.as<double>(), c->partial.p, ns, nullptr, nullptr, v);
+            hip_check(hipEventRecord(e1, s), "event");
+            hip_check(hipEventSynchronize(e1), "event");
+            float ms = 0.f;
+            hip_check(hipEventElapsedTime(&ms, e0, e1), "event");
+            if (ms < best) {
+                best = ms;
+                best_v = v;
+                best_s = ns;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->hv = best_v;
+    c->nsplit = best_s;
+    if (c->verbose) {
+        int r, u, n;
+        qhp::gemv_variant_desc(best_v, &r, &u, &n);
+        std::fprintf(stderr, "[qhp] history kernel: %d rows/wave, %d chunks in flight, nt=%d, %d splits, %.3f ms\n", r, u,
+                     n, best_s, best / 2);
+    }
+}
+
 extern "C" int qhp_set_incident(qhp_ctx *ctx, const qhp_wave *waves, int32_t n_rhs, int32_t n_steps)
 {
     if (!ctx) return QHP_EINVAL;
     if (ctx->state < 2) return guard(ctx, QHP_ESTATE, "assemble first");
     if (!waves || n_rhs < 1 || n_steps < 1) return guard(ctx, QHP_EINVAL, "bad waves / n_rhs / n_steps");
+    if (ctx->p.precision == QHP_F32A && n_rhs != 1) return guard(ctx, QHP_EINVAL, "QHP_F32A takes one right-hand side");
     API_TRY
     qhp_ctx *c = ctx;
     hip_check(hipSetDevice(c->p.device), "hipSetDevice");
@@ -560,7 +610,7 @@ extern "C" int qhp_set_incident(qhp_ctx *ctx, const qhp_wave *waves, int32_t n_r
     const int64_t K = c->K, ld = c->ld;
     c->ring64.alloc(sizeof(double) * K * ld * n_rhs);
     zero(c->ring64, s);
-    if (c->p.precision != QHP_F64) {
+    if (c->p.precision == QHP_F32 || c->p.precision == QHP_BF16) {
         c->ring32.alloc(sizeof(float) * K * ld * n_rhs);
         zero(c->ring32, s);
     }
@@ -568,7 +618,7 @@ extern "C" int qhp_set_incident(qhp_ctx *ctx, const qhp_wave *waves, int32_t n_r
     c->zvec.alloc(sizeof(double) * ne * n_rhs);
     c->yvec.alloc(sizeof(double) * ne * n_rhs);
     c->nsplit = qhp::hist_splits(ne, K, n_rhs);
-    c->partial.alloc(sizeof(double) * c->nsplit * ne * n_rhs);
+    c->partial.alloc(sizeof(double) * std::min<int64_t>(2 * c->nsplit, K) * ne * n_rhs);
     c->sv.alloc(sizeof(double) * nc * n_rhs);
     c->zc.alloc(sizeof(double) * nc * n_rhs);
     c->flags.alloc(sizeof(int) * 2 * ((ne + 63) / 64));
@@ -578,6 +628,7 @@ extern "C" int qhp_set_incident(qhp_ctx *ctx, const qhp_wave *waves, int32_t n_r
     c->errflag.alloc(sizeof(int));
     zero(c->errflag, s);
     hip_check(hipStreamSynchronize(s), "march buffers");
+    autotune(c);
     c->step = 0;
     c->head = 0;
     c->broken = false;
@@ -604,8 +655,8 @@ static void do_step(qhp_ctx *c, double *j_out, double *y_out)
     }
     qhp::launch_history(s, c->p.precision, ne, ld, nr, K, c->slabs.p,
                         c->p.precision == QHP_BF16 ? c->scales_d.as<float>() : nullptr,
-                        f64 ? c->ring64.p : c->ring32.p, K, c->head, r_i, c->bvec.as<double>(), c->partial.p,
-                        c->nsplit, e0, e1);
+                        c->ring32.p ? c->ring32.p : c->ring64.p, K, c->head, r_i, c->bvec.as<double>(),
+                        c->partial.p, c->nsplit, e0, e1, c->hv);
     double *y = c->yvec.as<double>();
     if (c->p.solver == QHP_SOLVE_INV) {
         if (nr == 1) qhp::launch_gemv_f64(s, ne, c->Tinv.as<double>(), c->bvec.as<double>(), y);
@@ -625,7 +676,7 @@ static void do_step(qhp_ctx *c, double *j_out, double *y_out)
     }
     const int64_t slot = (c->head - 1 + K) % K;
     double *slot64 = c->ring64.as<double>() + slot * ld * nr;
-    float *slot32 = f64 ? nullptr : c->ring32.as<float>() + slot * ld * nr;
+    float *slot32 = c->ring32.p ? c->ring32.as<float>() + slot * ld * nr : nullptr;
     const double *yprev = i > 1 ? c->ring64.as<double>() + c->head * ld * nr : nullptr;
     if (j_out) {
         qhp::launch_post_a(s, nc, nr, c->dtn, c->args.tri_edge, c->args.tri_sign, y, yprev, c->sv.as<double>());
@@ -693,6 +744,14 @@ extern "C" int qhp_run(qhp_ctx *ctx, int32_t n_steps, double *j_hist, double *y_
     API_CATCH(ctx)
 }
 
+extern "C" int qhp_set_solver(qhp_ctx *ctx, int32_t solver)
+{
+    if (!ctx) return QHP_EINVAL;
+    if (solver != QHP_SOLVE_LU && solver != QHP_SOLVE_INV) return guard(ctx, QHP_EINVAL, "unknown solver");
+    ctx->p.solver = solver;
+    return QHP_OK;
+}
+
 extern "C" int qhp_profile(qhp_ctx *ctx, int32_t enable)
 {
     if (!ctx) return QHP_EINVAL;
@@ -715,13 +774,21 @@ extern "C" int qhp_set_precision(qhp_ctx *ctx, int32_t precision)
     if (!ctx) return QHP_EINVAL;
     if (ctx->state < 2) return guard(ctx, QHP_ESTATE, "assemble first");
     if (precision == ctx->p.precision) return QHP_OK;
-    if (ctx->p.precision != QHP_F64 || (precision != QHP_F32 && precision != QHP_BF16))
+    const bool fp32_pair = (precision == QHP_F32 || precision == QHP_F32A) &&
+                           (ctx->p.precision == QHP_F32 || ctx->p.precision == QHP_F32A);
+    if (fp32_pair) {  // same FP32 storage, other arithmetic
+        ctx->p.precision = precision;
+        ctx->ring32.release();
+        ctx->state = 2;
+        return QHP_OK;
+    }
+    if (ctx->p.precision != QHP_F64 || (precision != QHP_F32 && precision != QHP_BF16 && precision != QHP_F32A))
         return guard(ctx, QHP_EINVAL, "only FP64 slabs can be re-stored, as FP32 or BF16");
     API_TRY
     hipStream_t s = ctx->s;
     const int64_t ne = ctx->mesh.ne, ld = ctx->ld, K = ctx->K;
     const size_t per = (size_t)ne * ld;
-    const size_t esz = precision == QHP_F32 ? 4 : 2;
+    const size_t esz = precision == QHP_BF16 ? 2 : 4;
     DBuf out, amax;
     out.alloc(esz * per * K);
     amax.alloc(sizeof(unsigned long long));
@@ -770,6 +837,8 @@ extern "C" int qhp_query(const qhp_ctx *ctx, qhp_info *info)
     info->n_rhs = ctx->nrhs;
     info->n_steps = ctx->n_steps;
     info->step = ctx->step;
+    info->hist_variant = ctx->hv;
+    info->hist_splits = ctx->nsplit;
     return QHP_OK;
 }
 
@@ -810,7 +879,7 @@ extern "C" int qhp_get_matrix(const qhp_ctx *cc, int32_t which, int32_t k, doubl
         DBuf tmp;
         tmp.alloc(sizeof(double) * nn);
         const int32_t prec = ctx->p.precision;
-        const size_t esz = prec == QHP_F64 ? 8 : (prec == QHP_F32 ? 4 : 2);
+        const size_t esz = prec == QHP_F64 ? 8 : (prec == QHP_BF16 ? 2 : 4);
         qhp::launch_load_slab(ctx->s, ne, ctx->ld, (const char *)ctx->slabs.p + esz * (size_t)(k - 1) * ne * ctx->ld,
                               prec, ctx->scales[k - 1], tmp.as<double>());
         hip_check(hipStreamSynchronize(ctx->s), "dequantise");
@@ -838,7 +907,8 @@ extern "C" int qhp_history_sum(void *stream, int32_t precision, int64_t ne, int6
                                const void *slabs, const float *scales, const void *ring, int64_t n_slots, int64_t head,
                                const double *r, double *b)
 {
-    if (precision < QHP_F64 || precision > QHP_BF16 || ne < 1 || ld < ne || ld % 8 != 0 || nrhs < 1 || kmax < 0 ||
+    if (precision < QHP_F64 || precision > QHP_F32A || ne < 1 || ld < ne || ld % 8 != 0 || nrhs < 1 || kmax < 0 ||
+        (precision == QHP_F32A && nrhs != 1) ||
         n_slots < kmax || head < 0 || (kmax > 0 && (!slabs || !ring)) || !r || !b)
         return QHP_EINVAL;
     if (precision == QHP_BF16 && !scales) return QHP_EINVAL;

@@ -16,7 +16,9 @@ int hist_splits(int64_t ne, int64_t kmax, int64_t nrhs);
 void launch_history(hipStream_t s, int32_t precision, int64_t ne, int64_t ld, int64_t nrhs, int64_t kmax,
                     const void *slabs, const float *scales, const void *ring, int64_t n_slots, int64_t head,
                     const double *r, double *b, void *partial, int nsplit, hipEvent_t e0 = nullptr,
-                    hipEvent_t e1 = nullptr);
+                    hipEvent_t e1 = nullptr, int variant = -1);
+int gemv_variant_count();
+void gemv_variant_desc(int v, int *rpw, int *unr, int *nt);
 void launch_convert_slab(hipStream_t s, int64_t n, const double *in, int32_t precision, float inv_scale, void *out);
 void launch_gemv_f64(hipStream_t s, int64_t n, const double *A, const double *x, double *y);
 void launch_trsv_lu(hipStream_t s, int64_t n, const double *LU, const double *Dinv, const int32_t *perm,

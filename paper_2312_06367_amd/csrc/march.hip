@@ -150,28 +150,27 @@ void launch_permute_rhs(hipStream_t s, int64_t ne, int64_t ns, int32_t nrhs, con
 
 // ------------------------------------------------------------ history sum
 // Single right-hand side: partial[split][row] = sum over the split's lags of
-// T_k[row] . y_{i-k}.  Block = 256 threads = 4 waves, 16 rows per block (4 per
-// wave).  Each lane streams 16-byte vectors of a row; the y vector chunk is
-// loaded once per lane and reused for the wave's 4 rows.
+// T_k[row] . y_{i-k}.  Block = 256 threads = 4 waves; each wave owns RPW rows.
+// Each lane streams 16-byte vectors of the rows (UNR column chunks in flight),
+// loading the matching y chunk once and reusing it for the wave's rows.  The
+// slab stream is read with non-temporal loads (NT) so that the y vectors stay
+// cached.  T = slab storage, Y = ring element, A = accumulation type.
 template <typename T>
-struct Vec;
+struct St;
 template <>
-struct Vec<double> {
+struct St<double> {
     static constexpr int N = 2;
-    typedef double acc_t;
-    typedef double y_t;
+    typedef double v_t __attribute__((ext_vector_type(2)));
 };
 template <>
-struct Vec<float> {
+struct St<float> {
     static constexpr int N = 4;
-    typedef float acc_t;
-    typedef float y_t;
+    typedef float v_t __attribute__((ext_vector_type(4)));
 };
 template <>
-struct Vec<uint16_t> {  // bf16 storage
+struct St<uint16_t> {  // bf16 storage
     static constexpr int N = 8;
-    typedef float acc_t;
-    typedef float y_t;
+    typedef uint32_t v_t __attribute__((ext_vector_type(4)));
 };
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h)
@@ -179,99 +178,131 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t h)
     return __uint_as_float(((uint32_t)h) << 16);
 }
 
-template <typename T>
-__device__ __forceinline__ void load_vec(const T *p, typename Vec<T>::acc_t *out);
-template <>
-__device__ __forceinline__ void load_vec<double>(const double *p, double *out)
+template <typename T, bool NT>
+__device__ __forceinline__ typename St<T>::v_t ldv(const T *p)
 {
-    double2 v = *reinterpret_cast<const double2 *>(p);
-    out[0] = v.x;
-    out[1] = v.y;
+    typedef typename St<T>::v_t V;
+    if (NT) return __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
+    return *reinterpret_cast<const V *>(p);
 }
-template <>
-__device__ __forceinline__ void load_vec<float>(const float *p, float *out)
+
+template <typename A>
+__device__ __forceinline__ void unpack(const St<double>::v_t &v, A *o)
 {
-    float4 v = *reinterpret_cast<const float4 *>(p);
-    out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
+    o[0] = (A)v[0];
+    o[1] = (A)v[1];
 }
-template <>
-__device__ __forceinline__ void load_vec<uint16_t>(const uint16_t *p, float *out)
+template <typename A>
+__device__ __forceinline__ void unpack(const St<float>::v_t &v, A *o)
 {
-    uint4 v = *reinterpret_cast<const uint4 *>(p);
-    uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    o[0] = (A)v[0]; o[1] = (A)v[1]; o[2] = (A)v[2]; o[3] = (A)v[3];
+}
+template <typename A>
+__device__ __forceinline__ void unpack(const St<uint16_t>::v_t &v, A *o)
+{
+#pragma unroll
     for (int i = 0; i < 4; ++i) {
-        out[2 * i] = __uint_as_float(w[i] << 16);
-        out[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+        o[2 * i] = (A)__uint_as_float(v[i] << 16);
+        o[2 * i + 1] = (A)__uint_as_float(v[i] & 0xffff0000u);
     }
 }
-template <typename Y>
-__device__ __forceinline__ void load_y(const Y *p, int n, Y *out)
+
+// y chunk of N elements of type Y starting at p, converted to A
+template <typename Y, typename A, int N>
+__device__ __forceinline__ void load_y(const Y *p, A *o)
 {
-    if (n == 2) {
-        double2 v = *reinterpret_cast<const double2 *>(p);
-        out[0] = v.x;
-        out[1] = v.y;
+    if constexpr (sizeof(Y) == 8) {
+#pragma unroll
+        for (int q = 0; q < N; q += 2) {
+            double2 v = *reinterpret_cast<const double2 *>(p + q);
+            o[q] = (A)v.x;
+            o[q + 1] = (A)v.y;
+        }
     } else {
-        for (int q = 0; q < n; q += 4) {
+#pragma unroll
+        for (int q = 0; q < N; q += 4) {
             float4 v = *reinterpret_cast<const float4 *>(p + q);
-            out[q] = v.x; out[q + 1] = v.y; out[q + 2] = v.z; out[q + 3] = v.w;
+            o[q] = (A)v.x; o[q + 1] = (A)v.y; o[q + 2] = (A)v.z; o[q + 3] = (A)v.w;
         }
     }
 }
 
-template <typename T>
+template <typename T, typename Y, typename A, int RPW, int UNR, bool NT>
 __global__ __launch_bounds__(256) void k_hist_gemv(int64_t ne, int64_t ld, int64_t kmax, int64_t lags_per_split,
                                                    const T *__restrict__ slabs, const float *__restrict__ scales,
-                                                   const typename Vec<T>::y_t *__restrict__ ring, int64_t n_slots,
-                                                   int64_t head, typename Vec<T>::acc_t *__restrict__ partial)
+                                                   const Y *__restrict__ ring, int64_t n_slots, int64_t head,
+                                                   A *__restrict__ partial)
 {
-    typedef typename Vec<T>::acc_t acc_t;
-    typedef typename Vec<T>::y_t y_t;
-    constexpr int VN = Vec<T>::N;
+    constexpr int VN = St<T>::N;
+    constexpr int STEP = 64 * VN;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t row0 = (int64_t)blockIdx.x * 16 + wave * 4;
+    const int64_t row0 = (int64_t)blockIdx.x * (4 * RPW) + wave * RPW;
     const int64_t k_begin = 1 + (int64_t)blockIdx.y * lags_per_split;
     int64_t k_end = k_begin + lags_per_split;
     if (k_end > kmax + 1) k_end = kmax + 1;
-    acc_t acc[4] = {0, 0, 0, 0};
-    const bool full_rows = row0 + 3 < ne;
+    A acc[RPW];
+#pragma unroll
+    for (int rr = 0; rr < RPW; ++rr) acc[rr] = 0;
+    const bool full_rows = row0 + RPW <= ne;
+    int64_t rows_here = ne - row0;
+    if (rows_here > RPW) rows_here = RPW;
     for (int64_t k = k_begin; k < k_end; ++k) {
-        int64_t slot = (head + k - 1) % n_slots;
-        const y_t *y = ring + slot * ld;
-        const T *Tk = slabs + (k - 1) * ne * ld;
-        acc_t part[4] = {0, 0, 0, 0};
-        for (int64_t c0 = (int64_t)lane * VN; c0 < ne; c0 += 64 * VN) {
-            y_t yv[VN];
-            load_y<y_t>(y + c0, VN, yv);
-            if (c0 + VN > ne) {
-                for (int q = 0; q < VN; ++q)
-                    if (c0 + q >= ne) yv[q] = 0;
+        const Y *y = ring + ((head + k - 1) % n_slots) * ld;
+        const T *Tk = slabs + (k - 1) * ne * ld + row0 * ld;
+        A part[RPW];
+#pragma unroll
+        for (int rr = 0; rr < RPW; ++rr) part[rr] = 0;
+        for (int64_t c0 = (int64_t)lane * VN; c0 < ne; c0 += STEP * UNR) {
+            A yv[UNR][VN];
+            bool ok[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                const int64_t cu = c0 + u * STEP;
+                ok[u] = cu < ne;
+                if (ok[u]) {
+                    load_y<Y, A, VN>(y + cu, yv[u]);
+                    if (cu + VN > ne) {
+#pragma unroll
+                        for (int q = 0; q < VN; ++q)
+                            if (cu + q >= ne) yv[u][q] = 0;
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < VN; ++q) yv[u][q] = 0;
+                }
             }
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-                if (!full_rows && row0 + rr >= ne) continue;
-                acc_t tv[VN];
-                load_vec<T>(Tk + (row0 + rr) * ld + c0, tv);
-                if (c0 + VN > ne) {
-                    for (int q = 0; q < VN; ++q)
-                        if (c0 + q >= ne) tv[q] = 0;
-                }
+            for (int rr = 0; rr < RPW; ++rr) {
+                if (!full_rows && rr >= rows_here) continue;
 #pragma unroll
-                for (int q = 0; q < VN; ++q) part[rr] += tv[q] * (acc_t)yv[q];
+                for (int u = 0; u < UNR; ++u) {
+                    if (!ok[u]) continue;
+                    const int64_t cu = c0 + u * STEP;
+                    A tv[VN];
+                    unpack<A>(ldv<T, NT>(Tk + rr * ld + cu), tv);
+                    if (cu + VN > ne) {
+#pragma unroll
+                        for (int q = 0; q < VN; ++q)
+                            if (cu + q >= ne) tv[q] = 0;
+                    }
+#pragma unroll
+                    for (int q = 0; q < VN; ++q) part[rr] += tv[q] * yv[u][q];
+                }
             }
         }
-        acc_t sc = scales ? (acc_t)scales[k - 1] : (acc_t)1;
+        const A sc = scales ? (A)scales[k - 1] : (A)1;
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) acc[rr] += sc * part[rr];
+        for (int rr = 0; rr < RPW; ++rr) acc[rr] += sc * part[rr];
     }
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-        acc_t v = acc[rr];
+    for (int rr = 0; rr < RPW; ++rr) {
+        A v = acc[rr];
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
         acc[rr] = v;
     }
     if (lane == 0) {
-        for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+        for (int rr = 0; rr < RPW; ++rr)
             if (row0 + rr < ne) partial[(int64_t)blockIdx.y * ne + row0 + rr] = acc[rr];
     }
 }
@@ -285,6 +316,44 @@ __global__ void k_hist_finish(int64_t n, int64_t nsplit, const A *partial, const
     double s = 0.0;
     for (int64_t q = 0; q < nsplit; ++q) s += (double)partial[q * n + i];
     b[i] = r[i] - s;
+}
+
+// variant table of the single right-hand-side kernel (autotuned per context)
+struct GemvVariant {
+    int rpw, unr, nt;
+};
+static const GemvVariant kGemvVariants[] = {{4, 1, 0}, {4, 2, 0}, {4, 2, 1}, {8, 1, 1}, {8, 2, 1}, {2, 4, 1}, {4, 4, 1}};
+constexpr int kNumGemvVariants = sizeof(kGemvVariants) / sizeof(kGemvVariants[0]);
+int gemv_variant_count() { return kNumGemvVariants; }
+void gemv_variant_desc(int v, int *rpw, int *unr, int *nt)
+{
+    *rpw = kGemvVariants[v].rpw;
+    *unr = kGemvVariants[v].unr;
+    *nt = kGemvVariants[v].nt;
+}
+
+template <typename T, typename Y, typename A>
+static void gemv_dispatch(int v, hipStream_t s, int64_t ne, int64_t ld, int64_t kmax, int64_t lps, int nsplit,
+                          const void *slabs, const float *scales, const void *ring, int64_t n_slots, int64_t head,
+                          void *partial)
+{
+#define QHP_GEMV_CASE(IDX, R, U, N)                                                                          \
+    case IDX:                                                                                                  \
+        hipLaunchKernelGGL((k_hist_gemv<T, Y, A, R, U, N>), dim3(nblk(ne, 4 * R), (unsigned)nsplit), dim3(256), \
+                           0, s, ne, ld, kmax, lps, (const T *)slabs, scales, (const Y *)ring, n_slots, head,    \
+                           (A *)partial);                                                                      \
+        break;
+    switch (v) {
+        QHP_GEMV_CASE(0, 4, 1, false)
+        QHP_GEMV_CASE(1, 4, 2, false)
+        QHP_GEMV_CASE(2, 4, 2, true)
+        QHP_GEMV_CASE(3, 8, 1, true)
+        QHP_GEMV_CASE(4, 8, 2, true)
+        QHP_GEMV_CASE(5, 2, 4, true)
+        default:
+        QHP_GEMV_CASE(6, 4, 4, true)
+    }
+#undef QHP_GEMV_CASE
 }
 
 // Batched right-hand sides: C[row][rhs] partials with FP32 MFMA
@@ -357,7 +426,8 @@ int hist_splits(int64_t ne, int64_t kmax, int64_t nrhs)
 
 void launch_history(hipStream_t s, int32_t precision, int64_t ne, int64_t ld, int64_t nrhs, int64_t kmax,
                     const void *slabs, const float *scales, const void *ring, int64_t n_slots, int64_t head,
-                    const double *r, double *b, void *partial, int nsplit, hipEvent_t e0, hipEvent_t e1)
+                    const double *r, double *b, void *partial, int nsplit, hipEvent_t e0, hipEvent_t e1,
+                    int variant)
 {
     if (kmax <= 0) {
         (void)hipMemcpyAsync(b, r, sizeof(double) * ne * nrhs, hipMemcpyDeviceToDevice, s);
@@ -366,18 +436,21 @@ void launch_history(hipStream_t s, int32_t precision, int64_t ne, int64_t ld, in
     int64_t lps = (kmax + nsplit - 1) / nsplit;
     if (e0) (void)hipEventRecord(e0, s);
     if (nrhs == 1) {
-        dim3 grid(nblk(ne, 16), (unsigned)nsplit);
+        if (variant < 0 || variant >= kNumGemvVariants) variant = 2;
         if (precision == QHP_F64)
-            hipLaunchKernelGGL(k_hist_gemv<double>, grid, dim3(256), 0, s, ne, ld, kmax, lps, (const double *)slabs,
-                               scales, (const double *)ring, n_slots, head, (double *)partial);
+            gemv_dispatch<double, double, double>(variant, s, ne, ld, kmax, lps, nsplit, slabs, scales, ring, n_slots,
+                                                  head, partial);
         else if (precision == QHP_F32)
-            hipLaunchKernelGGL(k_hist_gemv<float>, grid, dim3(256), 0, s, ne, ld, kmax, lps, (const float *)slabs,
-                               scales, (const float *)ring, n_slots, head, (float *)partial);
+            gemv_dispatch<float, float, float>(variant, s, ne, ld, kmax, lps, nsplit, slabs, scales, ring, n_slots,
+                                               head, partial);
+        else if (precision == QHP_F32A)
+            gemv_dispatch<float, double, double>(variant, s, ne, ld, kmax, lps, nsplit, slabs, scales, ring, n_slots,
+                                                 head, partial);
         else
-            hipLaunchKernelGGL(k_hist_gemv<uint16_t>, grid, dim3(256), 0, s, ne, ld, kmax, lps,
-                               (const uint16_t *)slabs, scales, (const float *)ring, n_slots, head, (float *)partial);
+            gemv_dispatch<uint16_t, float, float>(variant, s, ne, ld, kmax, lps, nsplit, slabs, scales, ring, n_slots,
+                                                  head, partial);
         if (e1) (void)hipEventRecord(e1, s);
-        if (precision == QHP_F64)
+        if (precision == QHP_F64 || precision == QHP_F32A)
             hipLaunchKernelGGL(k_hist_finish<double>, dim3(nblk(ne, 256)), dim3(256), 0, s, ne, (int64_t)nsplit,
                                (const double *)partial, r, b);
         else
@@ -416,7 +489,7 @@ __global__ void k_convert_slab(int64_t n, const double *in, int32_t precision, f
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double v = in[i];
-    if (precision == QHP_F32) {
+    if (precision == QHP_F32 || precision == QHP_F32A) {
         ((float *)out)[i] = (float)v;
     } else {
         float f = (float)v * inv_scale;
@@ -637,7 +710,7 @@ __global__ void k_store_slab(int64_t ne, int64_t ld, const double *T, int32_t pr
     int64_t i = idx / ld, j = idx % ld;
     double v = j < ne ? T[i * ne + j] : 0.0;
     if (precision == QHP_F64) ((double *)out)[idx] = v;
-    else if (precision == QHP_F32) ((float *)out)[idx] = (float)v;
+    else if (precision == QHP_F32 || precision == QHP_F32A) ((float *)out)[idx] = (float)v;
     else {
         float f = (float)v * inv_scale;
         uint32_t u = __float_as_uint(f);
@@ -672,7 +745,7 @@ __global__ void k_load_slab(int64_t ne, int64_t ld, const void *in, int32_t prec
     int64_t o = i * ld + j;
     double v;
     if (precision == QHP_F64) v = ((const double *)in)[o];
-    else if (precision == QHP_F32) v = ((const float *)in)[o];
+    else if (precision == QHP_F32 || precision == QHP_F32A) v = ((const float *)in)[o];
     else v = (double)(bf16_to_f32(((const uint16_t *)in)[o]) * scale);
     T[idx] = v;
 }

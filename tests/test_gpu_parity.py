@@ -106,3 +106,174 @@ def test_march_parity_f64(small):
     ey = float(np.linalg.norm(y - small["y"], axis=1).max() / np.linalg.norm(small["y"], axis=1).max())
     _say("[small] march f64: current err %.3e, y err %.3e" % (ej, ey))
     assert ej < 1e-10 and ey < 1e-10
+
+
+def test_march_parity_inverse_solve(small):
+    """QHP_SOLVE_INV (T_0^{-1} formed once from the LU) vs the oracle."""
+    s = small["s"]
+    n = small["n_steps"]
+    ne = small["asm"].topo.ne
+    s.set_solver("inv")
+    s.set_incident([small["w"]], n)
+    jh = torch.zeros((n, ne, 1), dtype=torch.float64, device="cuda")
+    s.run(n, jh)
+    s.set_solver("lu")
+    j = jh[:, :, 0].cpu().numpy()
+    err = float(np.linalg.norm(j - small["j"], axis=1).max() / np.linalg.norm(small["j"], axis=1).max())
+    _say("[small] march f64 inverse solve: current err %.3e" % err)
+    assert err < 1e-10
+
+
+def _march_gpu(xyz, tri, dt, waves, n, precision, solver="lu"):
+    import paper_2312_06367_amd as qhp
+    s = qhp.Solver(dt, precision="f64", solver=solver)
+    s.mesh(xyz, tri)
+    s.assemble()
+    if precision != "f64":
+        s.set_precision(precision)
+    ne = s.info()["ne"]
+    s.set_incident(waves, n)
+    jh = torch.zeros((n, ne, len(waves)), dtype=torch.float64, device="cuda")
+    s.run(n, jh)
+    out = jh.cpu().numpy()
+    s.close()
+    return out
+
+
+# stated bounds (relative to the peak current) of the reduced-precision forms
+# on the 120-edge sphere, 300 steps
+BOUNDS = {"f32a": 1e-6, "f32": 1e-3, "bf16": 1e-1}
+
+
+@pytest.mark.parametrize("precision", ["f32a", "f32", "bf16"])
+def test_march_reduced_precision_bounds(small, precision):
+    j = _march_gpu(small["xyz"], small["tri"], small["dt"], [small["w"]], small["n_steps"], precision)[:, :, 0]
+    err = float(np.linalg.norm(j - small["j"], axis=1).max() / np.linalg.norm(small["j"], axis=1).max())
+    _say("[small] march %s: current err %.3e (bound %.0e)" % (precision, err, BOUNDS[precision]))
+    assert err < BOUNDS[precision]
+
+
+def test_batched_march_parity():
+    """Three waves (a ragged tile of the batched history kernel), FP64 and
+    FP32 storage, torus with two global loops."""
+    from oracle import operators as O, excitation as E, mot
+    from workloads import meshes, waves
+    xyz, tri = meshes.torus(1.0, 0.4, 12, 6)
+    dt, n = 0.12, 150
+    asm = O.Assembly(xyz, tri, dt)
+    asm.build()
+    ws = waves.batched_waves(2, 5, 0.1, 0.1, asm.D)[:3]
+    r = np.stack([E.rhs(asm, w, n) for w in ws], axis=-1)
+    y = mot.march(asm.T, r)
+    jref = mot.currents(asm.proj.PLH, asm.proj.PS, asm.dtn, y)
+    for precision, bound in (("f64", 1e-10), ("f32", 1e-3)):
+        j = _march_gpu(xyz, tri, dt, ws, n, precision)
+        err = float(np.abs(j - jref).max() / np.abs(jref).max())
+        _say("[torus batched] %s: current err %.3e" % (precision, err))
+        assert err < bound
+
+
+def test_sphere_480_parity_f64():
+    """The 480-edge sphere workload (c dt = 0.05 m, 400 steps), FP64."""
+    from oracle import excitation as E, mot, operators as O
+    from workloads import waves
+    cfg = waves.sphere_small()
+    xyz, tri = cfg.mesh
+    asm = O.Assembly(xyz, tri, cfg.dt)
+    asm.build()
+    jref = mot.currents(asm.proj.PLH, asm.proj.PS, asm.dtn, mot.march(asm.T, E.rhs(asm, cfg.waves[0], cfg.n_steps)))
+    j = _march_gpu(xyz, tri, cfg.dt, cfg.waves, cfg.n_steps, "f64")[:, :, 0]
+    err = float(np.linalg.norm(j - jref, axis=1).max() / np.linalg.norm(jref, axis=1).max())
+    _say("[sphere 480] f64 current err %.3e" % err)
+    assert err < 1e-10
+
+
+def _bf16_round(x):
+    t = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(torch.bfloat16)
+    return t, t.to(torch.float64).numpy()
+
+
+@pytest.mark.parametrize("precision,nrhs", [("f64", 1), ("f32", 1), ("f32a", 1), ("bf16", 1),
+                                            ("f64", 70), ("f32", 70), ("bf16", 70)])
+def test_history_sum_kernel_ragged(precision, nrhs):
+    """b = r - sum_k T_k y_{i-k} through qhp_history_sum: ragged sizes (rows
+    not a multiple of any tile), padded rows with garbage in the padding,
+    circular ring with a head offset."""
+    import paper_2312_06367_amd as qhp
+    rng = np.random.default_rng(11)
+    ne, ld, kmax, n_slots, head = 1003, 1016, 5, 7, 3
+    T = rng.standard_normal((kmax, ne, ld))
+    T[:, :, ne:] = 1e6  # padding must be ignored
+    Y = rng.standard_normal((n_slots, ld, nrhs))
+    Y[:, ne:, :] = 1e6
+    r = rng.standard_normal((ne, nrhs))
+    dev = "cuda"
+    if precision == "bf16":
+        scales = np.abs(T[:, :, :ne]).max(axis=(1, 2)).astype(np.float32)
+        tq, tdq = _bf16_round(T / scales[:, None, None])
+        slabs = tq.to(dev)
+        Teff = tdq * scales[:, None, None].astype(np.float64)
+        sc = torch.from_numpy(scales).to(dev)
+    else:
+        dt_ = torch.float64 if precision == "f64" else torch.float32
+        slabs = torch.from_numpy(T).to(dt_).to(dev)
+        Teff = slabs.to(torch.float64).cpu().numpy()
+        sc = None
+    ydt = torch.float64 if precision in ("f64", "f32a") else torch.float32
+    ring = torch.from_numpy(Y).to(ydt).to(dev)
+    Yeff = ring.to(torch.float64).cpu().numpy()
+    rt = torch.from_numpy(r).to(dev)
+    b = torch.zeros_like(rt)
+    qhp.history_sum(precision, slabs, sc, ring, head, rt, b, kmax=kmax)
+    torch.cuda.synchronize()
+    ref = r.copy()
+    for k in range(1, kmax + 1):
+        ref -= Teff[k - 1][:, :ne] @ Yeff[(head + k - 1) % n_slots][:ne]
+    err = float(np.abs(b.cpu().numpy() - ref).max() / np.abs(ref).max())
+    bound = {"f64": 1e-13, "f32a": 1e-13, "f32": 2e-5, "bf16": 2e-5}[precision]
+    _say("[history_sum %s nrhs=%d] err %.3e" % (precision, nrhs, err))
+    assert err < bound
+
+
+def test_history_sum_full_size_sampled():
+    """The single right-hand-side history kernel at the 7680-edge sphere shape
+    (K = 101 FP32 blocks, 23.8 GB) on random data: sampled rows against an
+    FP64 evaluation of the same rows."""
+    import paper_2312_06367_amd as qhp
+    ne, K = 7680, 101
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3)
+    slabs = torch.randn((K, ne, ne), dtype=torch.float32, device="cuda", generator=g)
+    ring = torch.randn((K, ne, 1), dtype=torch.float32, device="cuda", generator=g)
+    r = torch.randn((ne, 1), dtype=torch.float64, device="cuda", generator=g)
+    b = torch.zeros_like(r)
+    head = 17
+    qhp.history_sum("f32", slabs, None, ring, head, r, b)
+    torch.cuda.synchronize()
+    rows = torch.from_numpy(np.random.default_rng(0).choice(ne, 48, replace=False)).cuda()
+    ref = r[rows, 0].clone()
+    for k in range(1, K + 1):
+        yk = ring[(head + k - 1) % K, :, 0].to(torch.float64)
+        ref -= slabs[k - 1][rows].to(torch.float64) @ yk
+    err = (b[rows, 0] - ref).abs().max().item() / ref.abs().max().item()
+    _say("[history_sum full size] sampled-row err %.3e" % err)
+    del slabs
+    torch.cuda.empty_cache()
+    assert err < 1e-5
+
+
+def test_error_paths():
+    import paper_2312_06367_amd as qhp
+    from workloads import meshes
+    xyz, tri = meshes.icosphere(1)
+    s = qhp.Solver(0.1)
+    with pytest.raises(qhp.QhpError) as e:
+        s.mesh(xyz, tri[:-1])  # open surface
+    assert e.value.code == -2
+    s2 = qhp.Solver(0.1)
+    s2.mesh(xyz, tri)
+    with pytest.raises(qhp.QhpError) as e:
+        s2.set_incident([dict(k_hat=(0, 0, -1), pol=(1, 0, 0), amplitude=1, t0=5, pulse=0, w=0, f0=.1, bw=.1)], 5)
+    assert e.value.code == -3
+    s.close()
+    s2.close()
