@@ -35,7 +35,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="sphere-large", choices=["sphere-large", "sphere-small", "torus-batched"])
-    ap.add_argument("--precision", default="f32", choices=["f32", "f32a", "bf16", "f64"])
+    ap.add_argument("--precision", default="f32a", choices=["f32", "f32a", "bf16", "f64"],
+                    help="slab storage / history arithmetic: f32a = FP32 blocks with FP64 y and sums")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a 4 GiB device copy first (reference for profiler byte counters)")
     ap.add_argument("--solver", default="inv", choices=["lu", "inv"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="only the FP64 reference and the headline march")
@@ -158,17 +161,32 @@ def main():
         ysz = 8 if prec in ("f64", "f32a") else 4
         return (K * ne * ne * esz + K * ne * n_rhs * ysz) / (hist_ms * 1e-3) / 1e9
 
+    if a.calibrate_copy:
+        # plain device copy of known size, for scaling HBM counters of the profiler
+        nbytes = 1 << 32
+        src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: %d bytes read, %d bytes written" % (nbytes, nbytes))
+        del src, dst
+        torch.cuda.empty_cache()
+
     runs = {}
+    other = {"lu": "inv", "inv": "lu"}[a.solver]
     runs["f64_lu"] = march("f64", "lu")
     if not a.quick or a.solver == "inv":
         runs["f64_inv"] = march("f64", "inv")
     if a.precision != "f64":
         s.set_precision(a.precision)
         runs["head"] = march(a.precision, a.solver)
-        if not a.quick and a.precision == "f32":
-            runs["f32_" + ("lu" if a.solver == "inv" else "inv")] = march("f32", "lu" if a.solver == "inv" else "inv")
-            s.set_precision("f32a")
-            runs["f32a_" + a.solver] = march("f32a", a.solver)
+        runs["%s_%s" % (a.precision, a.solver)] = runs["head"]
+        if not a.quick:
+            runs["%s_%s" % (a.precision, other)] = march(a.precision, other)
+            if a.precision in ("f32", "f32a"):
+                twin = "f32" if a.precision == "f32a" else "f32a"
+                s.set_precision(twin)
+                runs["%s_%s" % (twin, a.solver)] = march(twin, a.solver)
     else:
         runs["head"] = runs["f64_" + a.solver]
     head = runs["head"]
@@ -194,7 +212,7 @@ def main():
                 "kernel_ms_avg": head["hist_ms"]}
     forms = {}
     for key, rr in runs.items():
-        if key == "head":
+        if key == "head" or key in forms:
             continue
         prec = key.split("_")[0]
         forms[key] = {"steps_per_s": rr["steps_per_s"], "history_ms": rr["hist_ms"],
@@ -210,7 +228,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if a.precision in ("f32", "bf16") else ("f32-storage/f64-accumulate" if a.precision == "f32a" else "f64"),
+        "dtype": {"f32": "f32", "bf16": "bf16-storage/f32", "f32a": "f32-storage/f64-accumulate", "f64": "f64"}[a.precision],
         "data": "synthetic",
         "config": {"workload": cfg.name, "ne": ne, "K": K, "c_dt_m": cfg.dt, "n_rhs": n_rhs,
                    "slab_storage": a.precision, "solve": "fp64-" + a.solver, "post_processing": "fp64"},
