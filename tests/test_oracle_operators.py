@@ -50,7 +50,15 @@ def test_static_mfie_property(asm):
     G = asm.G
     prod = (0.5 * G - M0) @ np.linalg.inv(G) @ (0.5 * G + M0)
     proj = asm.proj.PPSH @ prod @ asm.proj.PLH
-    assert np.linalg.norm(proj) < 0.05 * np.linalg.norm(prod)
+    r1 = np.linalg.norm(proj) / np.linalg.norm(prod)
+    assert r1 < 1e-3
+    # ... and the residual shrinks under refinement (level 1 -> level 2)
+    xyz, tri = meshes.icosphere(2)
+    a2 = O.Assembly(xyz, tri, 0.05, K=1)
+    G2, M2 = a2.gram(), a2._mfie_only(0.0)
+    prod2 = (0.5 * G2 - M2) @ np.linalg.inv(G2) @ (0.5 * G2 + M2)
+    r2 = np.linalg.norm(a2.proj.PPSH @ prod2 @ a2.proj.PLH) / np.linalg.norm(prod2)
+    assert r2 < 0.7 * r1
 
 
 def test_lag_sums_and_projector_structure(asm):
