@@ -185,6 +185,29 @@ int qhp_history_sum(void *stream, int32_t precision, int64_t ne, int64_t ld, int
 const char *qhp_last_error(const qhp_ctx *ctx);
 void qhp_destroy(qhp_ctx *ctx);
 
+/* ---- many scatterers marched together ---------------------------------
+ * The marching scheme of Sec. IV-B applied to n independent scatterers of
+ * uneven size at once: every step is one replay of a HIP graph of grouped
+ * kernels (history sums of all scatterers through one work queue of
+ * 16-row tiles weighted by block size, then the T_0 products, the ring
+ * updates and the post-processing of all scatterers); the per-scatterer step
+ * and ring head live in device memory.
+ * qhp_batch_create: ctxs[i] must all have had qhp_set_incident, share the
+ *   device, precision (F64, F32 or F32A) and n_rhs (1, 2, 4 or 8); each
+ *   continues from its current step.  The T_0 product uses the FP64 inverse.
+ *   The batch keeps the context pointers: destroy it before them.
+ * qhp_batch_run: n_steps steps of every scatterer; j_hists is a host array
+ *   of n device pointers [n_steps][ne_i][n_rhs] FP64 (or NULL entries / a NULL
+ *   array for no output).  QHP_EUNSTABLE on a non-finite value.
+ * qhp_batch_step_times: the per-step times (ms, HIP events around each graph
+ *   replay) of the last run, into host ms[n]. */
+typedef struct qhp_batch qhp_batch;
+int qhp_batch_create(qhp_ctx *const *ctxs, int32_t n, qhp_batch **out);
+int qhp_batch_run(qhp_batch *b, int32_t n_steps, double *const *j_hists);
+int qhp_batch_step_times(const qhp_batch *b, float *ms, int32_t n);
+const char *qhp_batch_last_error(const qhp_batch *b);
+void qhp_batch_destroy(qhp_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

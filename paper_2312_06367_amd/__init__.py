@@ -53,7 +53,9 @@ class _Info(ctypes.Structure):
 
 EXPORTS = ["qhp_create", "qhp_mesh", "qhp_assemble", "qhp_set_precision", "qhp_set_solver", "qhp_profile",
            "qhp_hist_time", "qhp_set_incident", "qhp_step", "qhp_run", "qhp_query", "qhp_edges",
-           "qhp_get_matrix", "qhp_keep_raw", "qhp_history_sum", "qhp_last_error", "qhp_destroy"]
+           "qhp_get_matrix", "qhp_keep_raw", "qhp_history_sum", "qhp_batch_create", "qhp_batch_run",
+           "qhp_batch_step_times", "qhp_batch_last_error", "qhp_batch_destroy", "qhp_last_error",
+           "qhp_destroy"]
 
 _lib = None
 
@@ -82,12 +84,20 @@ def lib():
         L.qhp_get_matrix.argtypes = [vp, i32, i32, vp]
         L.qhp_keep_raw.argtypes = [vp, i32]
         L.qhp_history_sum.argtypes = [vp, i32, i64, i64, i64, i64, vp, vp, vp, i64, i64, vp, vp]
+        L.qhp_batch_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]
+        L.qhp_batch_run.argtypes = [vp, i32, ctypes.POINTER(vp)]
+        L.qhp_batch_step_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32]
+        L.qhp_batch_last_error.argtypes = [vp]
+        L.qhp_batch_last_error.restype = ctypes.c_char_p
+        L.qhp_batch_destroy.argtypes = [vp]
+        L.qhp_batch_destroy.restype = None
         L.qhp_last_error.argtypes = [vp]
         L.qhp_last_error.restype = ctypes.c_char_p
         L.qhp_destroy.argtypes = [vp]
         L.qhp_destroy.restype = None
-        for name in EXPORTS[:-2]:
-            getattr(L, name).restype = ctypes.c_int
+        for name in EXPORTS:
+            if name not in ("qhp_last_error", "qhp_destroy", "qhp_batch_last_error", "qhp_batch_destroy"):
+                getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -216,3 +226,42 @@ def history_sum(precision: str, slabs, scales, ring, head: int, r, b, kmax: int 
                            _ptr(ring), ring.shape[0], int(head), _ptr(r), _ptr(b))
     if rc != 0:
         raise QhpError(rc, "qhp_history_sum")
+
+
+class Batch:
+    """Many scatterers marched together, one graph replay per step
+    (qhp_batch_*).  Keeps the solvers alive while it exists."""
+
+    def __init__(self, solvers):
+        self.L = lib()
+        self.solvers = list(solvers)
+        arr = (ctypes.c_void_p * len(self.solvers))(*[s.h.value for s in self.solvers])
+        h = ctypes.c_void_p()
+        rc = self.L.qhp_batch_create(arr, len(self.solvers), ctypes.byref(h))
+        if rc != 0:
+            raise QhpError(rc, self.L.qhp_last_error(self.solvers[0].h).decode())
+        self.h = h
+
+    def run(self, n_steps: int, j_hists=None):
+        ptrs = None
+        if j_hists is not None:
+            ptrs = (ctypes.c_void_p * len(self.solvers))(*[(None if t is None else t.data_ptr()) for t in j_hists])
+        rc = self.L.qhp_batch_run(self.h, int(n_steps), ptrs)
+        if rc != 0:
+            raise QhpError(rc, self.L.qhp_batch_last_error(self.h).decode())
+
+    def step_times(self, n: int):
+        out = (ctypes.c_float * n)()
+        self.L.qhp_batch_step_times(self.h, out, n)
+        return np.array(out[:], dtype=np.float64)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.qhp_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

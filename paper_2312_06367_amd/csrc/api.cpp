@@ -926,3 +926,263 @@ extern "C" int qhp_history_sum(void *stream, int32_t precision, int64_t ne, int6
     (void)hipFree(partial);
     return e == hipSuccess ? QHP_OK : QHP_EDEVICE;
 }
+
+// ------------------------------------------------------------------ batch
+// Many scatterers marched together: one graph per step, grouped kernels.
+#include "batch.h"
+
+struct qhp_batch {
+    std::vector<qhp_ctx *> ctxs;
+    hipStream_t s = nullptr;
+    int kind = 0, nrhs = 1, n = 0;
+    bool acc_double = true;
+    std::string err;
+    DBuf d_hist, d_solve, d_post, f_hist, f_solve, f_post, st, po, steps, heads, nslots, counter, errflag;
+    std::vector<DBuf> part_h, part_s, part_p, bvec, yvec, sv, zc, tinv, lsp;
+    int64_t tiles_h = 0, tiles_s = 0, tiles_p = 0, max_ne = 0, max_nc = 0;
+    std::vector<qhp::GPost> post_host;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    std::vector<float> step_ms;
+    ~qhp_batch()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (s) (void)hipStreamDestroy(s);
+    }
+};
+
+static int bguard(qhp_batch *b, int code, const std::string &msg)
+{
+    if (b) b->err = msg;
+    return code;
+}
+
+// split count so that a tile (16 rows x cols x lags/split) holds ~ 2M elements
+static int64_t group_splits(int64_t cols, int64_t nlags)
+{
+    const int64_t target = (int64_t)2 << 20;
+    int64_t per_lag = 16 * cols;
+    int64_t lags = std::max<int64_t>(1, target / per_lag);
+    int64_t ns = (nlags + lags - 1) / lags;
+    return std::max<int64_t>(1, std::min<int64_t>(ns, nlags));
+}
+
+static void build_batch(qhp_batch *b)
+{
+    const int n = b->n;
+    hipStream_t s = b->s;
+    const qhp_ctx *c0 = b->ctxs[0];
+    const int nr = b->nrhs;
+    b->part_h.resize(n); b->part_s.resize(n); b->part_p.resize(n); b->bvec.resize(n); b->yvec.resize(n);
+    b->sv.resize(n); b->zc.resize(n); b->tinv.resize(n); b->lsp.resize(n);
+    // work-queue order: biggest history first
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int x, int y) {
+        const qhp_ctx *a = b->ctxs[x], *q = b->ctxs[y];
+        return a->K * a->mesh.ne * a->mesh.ne > q->K * q->mesh.ne * q->mesh.ne;
+    });
+    std::vector<qhp::GDesc> dh(n), ds(n), dp(n);
+    std::vector<qhp::GFin> fh(n), fs(n), fp(n);
+    std::vector<qhp::GStore> gs(n);
+    b->post_host.assign(n, qhp::GPost{});
+    std::vector<int64_t> st0(n), hd0(n), nsl(n);
+    const size_t asz = b->acc_double ? 8 : 4;
+    int64_t t_h = 0, t_s = 0, t_p = 0;
+    b->errflag.alloc(sizeof(int));
+    zero(b->errflag, s);
+    b->steps.alloc(sizeof(int64_t) * n);
+    b->heads.alloc(sizeof(int64_t) * n);
+    b->nslots.alloc(sizeof(int64_t) * n);
+    for (int q = 0; q < n; ++q) {
+        const int i = order[q];
+        qhp_ctx *c = b->ctxs[i];
+        const int64_t ne = c->mesh.ne, nc = c->mesh.nc, K = c->K, ld = c->ld;
+        b->max_ne = std::max(b->max_ne, ne * nr);
+        b->max_nc = std::max(b->max_nc, nc * nr);
+        st0[i] = c->step;
+        hd0[i] = c->head;
+        nsl[i] = K;
+        const int64_t *dstep = b->steps.as<int64_t>() + i, *dhead = b->heads.as<int64_t>() + i;
+        // history group
+        int64_t ns_h = group_splits(ne, K);
+        b->part_h[i].alloc(asz * ns_h * ne * nr);
+        qhp::GDesc g{};
+        g.A = c->slabs.p; g.rows = ne; g.cols = ne; g.ld = ld; g.lag_stride = ne * ld; g.nlags = K;
+        g.scales = nullptr;
+        g.x = c->ring32.p ? c->ring32.p : c->ring64.p;
+        g.x_slot_stride = ld * nr; g.n_slots = K; g.head = dhead;
+        g.partial = b->part_h[i].p; g.nsplit = ns_h; g.rowblocks = (ne + 15) / 16; g.tile0 = t_h;
+        t_h += g.rowblocks * ns_h;
+        dh[q] = g;
+        b->bvec[i].alloc(sizeof(double) * ne * nr);
+        fh[i] = qhp::GFin{b->part_h[i].p, ns_h, ne * nr, c->rhs.as<double>(), dstep, b->bvec[i].as<double>()};
+        // solve group: y = T_0^{-1} b (FP64, padded copy of the inverse)
+        b->tinv[i].alloc(sizeof(double) * ne * ld);
+        zero(b->tinv[i], s);
+        hip_check(hipMemcpy2DAsync(b->tinv[i].p, sizeof(double) * ld, c->Tinv.p, sizeof(double) * ne,
+                                   sizeof(double) * ne, ne, hipMemcpyDeviceToDevice, s), "copy");
+        int64_t ns_s = std::max<int64_t>(1, std::min<int64_t>(8, (ne + 2047) / 2048));
+        (void)ns_s;
+        b->part_s[i].alloc(sizeof(double) * ne * nr);
+        qhp::GDesc gsv{};
+        gsv.A = b->tinv[i].p; gsv.rows = ne; gsv.cols = ne; gsv.ld = ld; gsv.lag_stride = 0; gsv.nlags = 1;
+        gsv.x = b->bvec[i].p; gsv.x_slot_stride = 0; gsv.n_slots = 1; gsv.head = nullptr;
+        gsv.partial = b->part_s[i].p; gsv.nsplit = 1; gsv.rowblocks = (ne + 15) / 16; gsv.tile0 = t_s;
+        t_s += gsv.rowblocks;
+        ds[q] = gsv;
+        b->yvec[i].alloc(sizeof(double) * ne * nr);
+        fs[i] = qhp::GFin{b->part_s[i].p, 1, ne * nr, nullptr, dstep, b->yvec[i].as<double>()};
+        gs[i] = qhp::GStore{b->yvec[i].as<double>(), c->ring64.as<double>(), c->ring32.as<float>(), ld * nr, K,
+                            ne * nr, dhead, b->errflag.as<int>()};
+        // post-processing product z = L_Sigma^+ s (padded copy)
+        const int64_t ldc = (nc + 7) / 8 * 8;
+        b->lsp[i].alloc(sizeof(double) * nc * ldc);
+        zero(b->lsp[i], s);
+        hip_check(hipMemcpy2DAsync(b->lsp[i].p, sizeof(double) * ldc, c->LSp.p, sizeof(double) * nc,
+                                   sizeof(double) * nc, nc, hipMemcpyDeviceToDevice, s), "copy");
+        b->sv[i].alloc(sizeof(double) * nc * nr);
+        b->part_p[i].alloc(sizeof(double) * nc * nr);
+        b->zc[i].alloc(sizeof(double) * nc * nr);
+        qhp::GDesc gp{};
+        gp.A = b->lsp[i].p; gp.rows = nc; gp.cols = nc; gp.ld = ldc; gp.lag_stride = 0; gp.nlags = 1;
+        gp.x = b->sv[i].p; gp.x_slot_stride = 0; gp.n_slots = 1; gp.head = nullptr;
+        gp.partial = b->part_p[i].p; gp.nsplit = 1; gp.rowblocks = (nc + 15) / 16; gp.tile0 = t_p;
+        t_p += gp.rowblocks;
+        dp[q] = gp;
+        fp[i] = qhp::GFin{b->part_p[i].p, 1, nc * nr, nullptr, dstep, b->zc[i].as<double>()};
+        qhp::GPost pp{};
+        pp.ne = ne; pp.nc = nc; pp.nrhs = nr; pp.dtn = c->dtn;
+        pp.tri_edge = c->args.tri_edge; pp.tri_sign = c->args.tri_sign; pp.cells = c->args.cells;
+        pp.ring64 = c->ring64.as<double>(); pp.slot_stride = ld * nr; pp.n_slots = K;
+        pp.head = dhead; pp.step = dstep; pp.sv = b->sv[i].as<double>(); pp.z = b->zc[i].as<double>();
+        pp.jhist = nullptr;
+        b->post_host[i] = pp;
+    }
+    b->tiles_h = t_h;
+    b->tiles_s = t_s;
+    b->tiles_p = t_p;
+    upload(b->d_hist, dh, s);
+    upload(b->d_solve, ds, s);
+    upload(b->d_post, dp, s);
+    upload(b->f_hist, fh, s);
+    upload(b->f_solve, fs, s);
+    upload(b->f_post, fp, s);
+    upload(b->st, gs, s);
+    upload(b->po, b->post_host, s);
+    upload(b->nslots, nsl, s);
+    hip_check(hipMemcpyAsync(b->steps.p, st0.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s), "state");
+    hip_check(hipMemcpyAsync(b->heads.p, hd0.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s), "state");
+    b->counter.alloc(sizeof(unsigned long long));
+    hip_check(hipStreamSynchronize(s), "batch set-up");
+}
+
+static void enqueue_batch_step(qhp_batch *b)
+{
+    hipStream_t s = b->s;
+    const int n = b->n, nr = b->nrhs;
+    qhp::launch_grouped_gemv(s, b->kind, nr, b->d_hist.as<qhp::GDesc>(), n, b->tiles_h, b->counter.as<unsigned long long>());
+    qhp::launch_grouped_finish(s, b->acc_double, b->f_hist.as<qhp::GFin>(), n, b->max_ne, 0);
+    qhp::launch_grouped_gemv(s, qhp::GK_F64, nr, b->d_solve.as<qhp::GDesc>(), n, b->tiles_s, b->counter.as<unsigned long long>());
+    qhp::launch_grouped_finish(s, true, b->f_solve.as<qhp::GFin>(), n, b->max_ne, 1);
+    qhp::launch_grouped_store(s, b->st.as<qhp::GStore>(), n, b->max_ne);
+    qhp::launch_grouped_post(s, 0, b->po.as<qhp::GPost>(), n, b->max_nc);
+    qhp::launch_grouped_gemv(s, qhp::GK_F64, nr, b->d_post.as<qhp::GDesc>(), n, b->tiles_p, b->counter.as<unsigned long long>());
+    qhp::launch_grouped_finish(s, true, b->f_post.as<qhp::GFin>(), n, b->max_nc, 1);
+    qhp::launch_grouped_post(s, 1, b->po.as<qhp::GPost>(), n, b->max_ne);
+    qhp::launch_grouped_advance(s, b->steps.as<int64_t>(), b->heads.as<int64_t>(), b->nslots.as<int64_t>(), n);
+}
+
+extern "C" int qhp_batch_create(qhp_ctx *const *ctxs, int32_t n, qhp_batch **out)
+{
+    if (!ctxs || n < 1 || !out) return QHP_EINVAL;
+    qhp_ctx *c0 = ctxs[0];
+    for (int i = 0; i < n; ++i) {
+        qhp_ctx *c = ctxs[i];
+        if (!c || c->state != 3 || c->broken) return guard(c0, QHP_ESTATE, "every context needs set_incident");
+        if (c->p.device != c0->p.device || c->p.precision != c0->p.precision || c->nrhs != c0->nrhs)
+            return guard(c0, QHP_EINVAL, "batch contexts must share device, precision and n_rhs");
+    }
+    if (c0->p.precision == QHP_BF16) return guard(c0, QHP_EINVAL, "the batch kernels take F64, F32 or F32A blocks");
+    if (c0->nrhs != 1 && c0->nrhs != 2 && c0->nrhs != 4 && c0->nrhs != 8)
+        return guard(c0, QHP_EINVAL, "batch n_rhs must be 1, 2, 4 or 8");
+    qhp_batch *b = new qhp_batch();
+    try {
+        hip_check(hipSetDevice(c0->p.device), "hipSetDevice");
+        b->ctxs.assign(ctxs, ctxs + n);
+        b->n = n;
+        b->nrhs = c0->nrhs;
+        b->kind = c0->p.precision == QHP_F64 ? qhp::GK_F64 : (c0->p.precision == QHP_F32 ? qhp::GK_F32 : qhp::GK_F32A);
+        b->acc_double = b->kind != qhp::GK_F32;
+        hip_check(hipStreamCreateWithFlags(&b->s, hipStreamNonBlocking), "stream");
+        for (int i = 0; i < n; ++i) hip_check(hipStreamSynchronize(ctxs[i]->s), "sync");
+        build_batch(b);
+        // capture one step; every per-step quantity is read from device state
+        hip_check(hipStreamBeginCapture(b->s, hipStreamCaptureModeThreadLocal), "capture");
+        enqueue_batch_step(b);
+        hip_check(hipStreamEndCapture(b->s, &b->graph), "capture");
+        hip_check(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "instantiate");
+    } catch (const Fail &f) {
+        delete b;
+        return guard(c0, f.code, f.msg);
+    }
+    *out = b;
+    return QHP_OK;
+}
+
+extern "C" int qhp_batch_run(qhp_batch *b, int32_t n_steps, double *const *j_hists)
+{
+    if (!b || n_steps < 0) return QHP_EINVAL;
+    for (qhp_ctx *c : b->ctxs)
+        if (c->step + n_steps > c->n_steps) return bguard(b, QHP_EINVAL, "past the last right-hand side");
+    try {
+        hipStream_t s = b->s;
+        // per-run output pointers: step s of the context writes j_hists[i] + (s - step0) * ne * nrhs
+        for (int i = 0; i < b->n; ++i) {
+            qhp_ctx *c = b->ctxs[i];
+            const int64_t stride = c->mesh.ne * b->nrhs;
+            b->post_host[i].jhist = (j_hists && j_hists[i]) ? j_hists[i] - c->step * stride : nullptr;
+        }
+        hip_check(hipMemcpyAsync(b->po.p, b->post_host.data(), sizeof(qhp::GPost) * b->n, hipMemcpyHostToDevice, s), "post");
+        std::vector<hipEvent_t> ev(n_steps + 1);
+        for (auto &e : ev) hip_check(hipEventCreate(&e), "event");
+        hip_check(hipEventRecord(ev[0], s), "event");
+        for (int t = 0; t < n_steps; ++t) {
+            hip_check(hipGraphLaunch(b->exec, s), "graph launch");
+            hip_check(hipEventRecord(ev[t + 1], s), "event");
+        }
+        hip_check(hipStreamSynchronize(s), "batch march");
+        b->step_ms.resize(n_steps);
+        for (int t = 0; t < n_steps; ++t) hip_check(hipEventElapsedTime(&b->step_ms[t], ev[t], ev[t + 1]), "event");
+        for (auto e : ev) (void)hipEventDestroy(e);
+        std::vector<int64_t> heads(b->n);
+        hip_check(hipMemcpy(heads.data(), b->heads.p, sizeof(int64_t) * b->n, hipMemcpyDeviceToHost), "state");
+        int e = 0;
+        hip_check(hipMemcpy(&e, b->errflag.p, sizeof(int), hipMemcpyDeviceToHost), "flag");
+        for (int i = 0; i < b->n; ++i) {
+            b->ctxs[i]->step += n_steps;
+            b->ctxs[i]->head = heads[i];
+        }
+        if (e) return bguard(b, QHP_EUNSTABLE, "non-finite value in a batch member");
+    } catch (const Fail &f) {
+        return bguard(b, f.code, f.msg);
+    }
+    return QHP_OK;
+}
+
+extern "C" int qhp_batch_step_times(const qhp_batch *b, float *ms, int32_t n)
+{
+    if (!b || !ms) return QHP_EINVAL;
+    for (int i = 0; i < n && i < (int)b->step_ms.size(); ++i) ms[i] = b->step_ms[i];
+    return QHP_OK;
+}
+
+extern "C" const char *qhp_batch_last_error(const qhp_batch *b) { return b ? b->err.c_str() : "null batch"; }
+
+extern "C" void qhp_batch_destroy(qhp_batch *b)
+{
+    if (!b) return;
+    (void)hipStreamSynchronize(b->s);
+    delete b;
+}

@@ -1,0 +1,68 @@
+// Grouped kernels for marching many scatterers together (descriptor tables,
+// device-side step and head counters, graph-capturable).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace qhp {
+
+enum { GK_F64 = 0, GK_F32 = 1, GK_F32A = 2 };
+
+// One multi-right-hand-side product group: partial[split][row][rhs] =
+// sum over the split's lags k of A_k[row][:] . x_{(head + k) mod n_slots}[:][rhs]
+struct GDesc {
+    const void *A;          // lag 0 matrix, row stride ld (elements), ld % 8 == 0
+    int64_t rows, cols, ld;
+    int64_t lag_stride;     // elements between consecutive lag matrices
+    int64_t nlags;
+    const float *scales;    // per-lag factor or null
+    const void *x;          // ring base: slot s at x + s * x_slot_stride, [cols][nrhs]
+    int64_t x_slot_stride;
+    int64_t n_slots;
+    const int64_t *head;    // device slot of lag 0 (null: 0)
+    void *partial;          // [nsplit][rows][nrhs]
+    int64_t nsplit;
+    int64_t tile0;          // first work tile of this group
+    int64_t rowblocks;      // 16-row blocks; tiles = rowblocks * nsplit
+};
+
+// out[i] = r[step][i] - sum partial (r may be null; negate: + sum)
+struct GFin {
+    const void *partial;
+    int64_t nsplit, n;
+    const double *r;
+    const int64_t *step;
+    double *out;
+};
+
+struct GStore {
+    const double *y;
+    double *ring64;
+    float *ring32;
+    int64_t slot_stride, n_slots, n;
+    const int64_t *head;
+    int *err;
+};
+
+struct GPost {
+    int64_t ne, nc, nrhs;
+    double dtn;
+    const int32_t *tri_edge, *tri_sign, *cells;
+    const double *ring64;
+    int64_t slot_stride, n_slots;
+    const int64_t *head, *step;
+    double *sv;
+    const double *z;
+    double *jhist;  // base such that step s writes jhist + s * ne * nrhs (or null)
+};
+
+void launch_grouped_gemv(hipStream_t s, int kind, int nrhs, const GDesc *gd, int ngroups, int64_t total_tiles,
+                         unsigned long long *counter);
+void launch_grouped_finish(hipStream_t s, bool acc_double, const GFin *gf, int ngroups, int64_t max_n, int negate);
+void launch_grouped_store(hipStream_t s, const GStore *gs, int ngroups, int64_t max_n);
+void launch_grouped_post(hipStream_t s, int part, const GPost *gp, int ngroups, int64_t max_n);
+void launch_grouped_advance(hipStream_t s, int64_t *steps, int64_t *heads, const int64_t *nslots, int ngroups);
+
+}  // namespace qhp

@@ -1,0 +1,242 @@
+// Grouped per-step kernels for a batch of independent scatterers (uneven
+// sizes) marched together: every kernel covers all scatterers through a
+// descriptor table, reads the per-scatterer step and ring head from device
+// memory, and can therefore be captured once in a HIP graph and replayed
+// every step.  The products are of the multi-right-hand-side streaming GEMV
+// form of the single-scatterer history kernel (Sec. IV-B: b_i = r_i -
+// sum_k T_k y_{i-k}; y_i = T_0^{-1} b_i; eq. post_processing).
+#include "batch.h"
+
+namespace qhp {
+
+static unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+template <typename T>
+struct GSt;
+template <>
+struct GSt<double> {
+    static constexpr int N = 2;
+    typedef double v_t __attribute__((ext_vector_type(2)));
+};
+template <>
+struct GSt<float> {
+    static constexpr int N = 4;
+    typedef float v_t __attribute__((ext_vector_type(4)));
+};
+
+// Work-queue GEMV over all groups.  A tile is (group, block of 16 rows, lag
+// split); tiles are taken from a device counter so that large scatterers do
+// not leave CUs idle.  partial[split][row][rhs] += over the split's lags of
+// A_k[row] . x_{slot(k)}[.][rhs].
+template <typename T, typename Y, typename A, int NR>
+__global__ __launch_bounds__(256) void k_grouped_gemv(const GDesc *__restrict__ gd, int ngroups, int64_t total_tiles,
+                                                      unsigned long long *counter)
+{
+    constexpr int VN = GSt<T>::N;
+    constexpr int RPW = 4;
+    typedef typename GSt<T>::v_t V;
+    __shared__ int64_t s_tile;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(counter, 1ull);
+        __syncthreads();
+        const int64_t tile = s_tile;
+        __syncthreads();
+        if (tile >= total_tiles) return;
+        int g = 0;
+        while (g + 1 < ngroups && gd[g + 1].tile0 <= tile) ++g;
+        const GDesc d = gd[g];
+        const int64_t local = tile - d.tile0;
+        const int64_t rb = local % d.rowblocks, sp = local / d.rowblocks;
+        const int64_t row0 = rb * 16 + wave * RPW;
+        const int64_t lps = (d.nlags + d.nsplit - 1) / d.nsplit;
+        const int64_t k0 = sp * lps;
+        const int64_t k1 = (k0 + lps < d.nlags) ? k0 + lps : d.nlags;
+        const int64_t head = d.head ? *d.head : 0;
+        A acc[RPW][NR];
+#pragma unroll
+        for (int rr = 0; rr < RPW; ++rr)
+#pragma unroll
+            for (int b = 0; b < NR; ++b) acc[rr][b] = 0;
+        for (int64_t k = k0; k < k1; ++k) {
+            const Y *x = (const Y *)d.x + ((head + k) % d.n_slots) * d.x_slot_stride;
+            const T *Ak = (const T *)d.A + k * d.lag_stride;
+            A part[RPW][NR];
+#pragma unroll
+            for (int rr = 0; rr < RPW; ++rr)
+#pragma unroll
+                for (int b = 0; b < NR; ++b) part[rr][b] = 0;
+            for (int64_t c0 = (int64_t)lane * VN; c0 < d.cols; c0 += 64 * VN) {
+                A xv[VN][NR];
+#pragma unroll
+                for (int q = 0; q < VN; ++q)
+#pragma unroll
+                    for (int b = 0; b < NR; ++b)
+                        xv[q][b] = (c0 + q < d.cols) ? (A)x[(c0 + q) * NR + b] : (A)0;
+#pragma unroll
+                for (int rr = 0; rr < RPW; ++rr) {
+                    if (row0 + rr >= d.rows) continue;
+                    V v = __builtin_nontemporal_load(reinterpret_cast<const V *>(Ak + (row0 + rr) * d.ld + c0));
+#pragma unroll
+                    for (int q = 0; q < VN; ++q) {
+                        A t = (c0 + q < d.cols) ? (A)v[q] : (A)0;
+#pragma unroll
+                        for (int b = 0; b < NR; ++b) part[rr][b] += t * xv[q][b];
+                    }
+                }
+            }
+            const A sc = d.scales ? (A)d.scales[k] : (A)1;
+#pragma unroll
+            for (int rr = 0; rr < RPW; ++rr)
+#pragma unroll
+                for (int b = 0; b < NR; ++b) acc[rr][b] += sc * part[rr][b];
+        }
+#pragma unroll
+        for (int rr = 0; rr < RPW; ++rr)
+#pragma unroll
+            for (int b = 0; b < NR; ++b) {
+                A v = acc[rr][b];
+                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+                acc[rr][b] = v;
+            }
+        if (lane == 0) {
+            A *out = (A *)d.partial + sp * d.rows * NR;
+#pragma unroll
+            for (int rr = 0; rr < RPW; ++rr)
+                if (row0 + rr < d.rows)
+#pragma unroll
+                    for (int b = 0; b < NR; ++b) out[(row0 + rr) * NR + b] = acc[rr][b];
+        }
+    }
+}
+
+__global__ void k_reset_counter(unsigned long long *c) { *c = 0ull; }
+
+// out[g][row][rhs] = sign_r * r_g[step][row][rhs] - sum_s partial_g[s][row][rhs]
+// (r is skipped when null): the history finish (sign_r = 1) and the solve
+// accumulation (r null, result negated back with sign -1).
+template <typename A>
+__global__ void k_grouped_finish(const GFin *__restrict__ gf, int ngroups, int64_t max_n, int negate)
+{
+    const int g = blockIdx.y;
+    if (g >= ngroups) return;
+    const GFin f = gf[g];
+    const int64_t n = f.n;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int64_t q = 0; q < f.nsplit; ++q) s += (double)((const A *)f.partial)[q * n + i];
+        double v = negate ? s : -s;
+        if (f.r) v += f.r[(*f.step) * n + i];
+        f.out[i] = v;
+    }
+    (void)max_n;
+}
+
+// store y_i into the ring (FP64 master, optional FP32 shadow) at the new head
+// slot (head - 1 mod K), optional history copy, and the non-finite check
+__global__ void k_grouped_store(const GStore *__restrict__ gs, int ngroups)
+{
+    const int g = blockIdx.y;
+    if (g >= ngroups) return;
+    const GStore d = gs[g];
+    const int64_t n = d.n;
+    const int64_t slot = (*d.head - 1 + d.n_slots) % d.n_slots;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double v = d.y[i];
+        if (!isfinite(v)) atomicExch(d.err, 2);
+        d.ring64[slot * d.slot_stride + i] = v;
+        if (d.ring32) d.ring32[slot * d.slot_stride + i] = (float)v;
+    }
+}
+
+// post-processing part a: s_c = sum_a sign w[edge], w = (1/dtn - 1) y_i - y_{i-1}/dtn
+__global__ void k_grouped_post_a(const GPost *__restrict__ gp, int ngroups)
+{
+    const int g = blockIdx.y;
+    if (g >= ngroups) return;
+    const GPost d = gp[g];
+    const int64_t n = d.nc * d.nrhs;
+    const int64_t step = *d.step;  // steps done before this one
+    const int64_t slot_new = (*d.head - 1 + d.n_slots) % d.n_slots;
+    const double *y = d.ring64 + slot_new * d.slot_stride;
+    const double *yp = step > 0 ? d.ring64 + (*d.head) * d.slot_stride : nullptr;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t c = idx / d.nrhs, b = idx % d.nrhs;
+        double acc = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            int64_t m = d.tri_edge[3 * c + a];
+            double w = (1.0 / d.dtn - 1.0) * y[m * d.nrhs + b] - (yp ? yp[m * d.nrhs + b] : 0.0) / d.dtn;
+            acc += d.tri_sign[3 * c + a] * w;
+        }
+        d.sv[idx] = acc;
+    }
+}
+// part b: j = y + Sigma z into j_hist[step] (if any); then advance step and head
+__global__ void k_grouped_post_b(const GPost *__restrict__ gp, int ngroups)
+{
+    const int g = blockIdx.y;
+    if (g >= ngroups) return;
+    const GPost d = gp[g];
+    const int64_t n = d.ne * d.nrhs;
+    const int64_t step = *d.step;
+    const int64_t slot_new = (*d.head - 1 + d.n_slots) % d.n_slots;
+    const double *y = d.ring64 + slot_new * d.slot_stride;
+    if (!d.jhist) return;
+    double *j = d.jhist + step * n;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t m = idx / d.nrhs, b = idx % d.nrhs;
+        j[idx] = y[idx] + d.z[d.cells[2 * m] * d.nrhs + b] - d.z[d.cells[2 * m + 1] * d.nrhs + b];
+    }
+}
+__global__ void k_grouped_advance(int64_t *steps, int64_t *heads, const int64_t *nslots, int ngroups)
+{
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ngroups) return;
+    steps[g] += 1;
+    heads[g] = (heads[g] - 1 + nslots[g]) % nslots[g];
+}
+
+void launch_grouped_gemv(hipStream_t s, int kind, int nrhs, const GDesc *gd, int ngroups, int64_t total_tiles,
+                         unsigned long long *counter)
+{
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
+    unsigned grid = (unsigned)(total_tiles < 4096 ? total_tiles : 4096);
+    if (grid == 0) return;
+#define QHP_G(T, Y, A, NR) \
+    hipLaunchKernelGGL((k_grouped_gemv<T, Y, A, NR>), dim3(grid), dim3(256), 0, s, gd, ngroups, total_tiles, counter)
+#define QHP_GN(T, Y, A)            \
+    switch (nrhs) {                \
+    case 1: QHP_G(T, Y, A, 1); break; \
+    case 2: QHP_G(T, Y, A, 2); break; \
+    case 4: QHP_G(T, Y, A, 4); break; \
+    default: QHP_G(T, Y, A, 8); break; \
+    }
+    if (kind == GK_F64) { QHP_GN(double, double, double) }
+    else if (kind == GK_F32) { QHP_GN(float, float, float) }
+    else { QHP_GN(float, double, double) }
+#undef QHP_GN
+#undef QHP_G
+}
+void launch_grouped_finish(hipStream_t s, bool acc_double, const GFin *gf, int ngroups, int64_t max_n, int negate)
+{
+    dim3 grid(nblk(max_n, 256) < 1024 ? nblk(max_n, 256) : 1024, (unsigned)ngroups);
+    if (acc_double) hipLaunchKernelGGL(k_grouped_finish<double>, grid, dim3(256), 0, s, gf, ngroups, max_n, negate);
+    else hipLaunchKernelGGL(k_grouped_finish<float>, grid, dim3(256), 0, s, gf, ngroups, max_n, negate);
+}
+void launch_grouped_store(hipStream_t s, const GStore *gs, int ngroups, int64_t max_n)
+{
+    dim3 grid(nblk(max_n, 256) < 1024 ? nblk(max_n, 256) : 1024, (unsigned)ngroups);
+    hipLaunchKernelGGL(k_grouped_store, grid, dim3(256), 0, s, gs, ngroups);
+}
+void launch_grouped_post(hipStream_t s, int part, const GPost *gp, int ngroups, int64_t max_n)
+{
+    dim3 grid(nblk(max_n, 256) < 1024 ? nblk(max_n, 256) : 1024, (unsigned)ngroups);
+    if (part == 0) hipLaunchKernelGGL(k_grouped_post_a, grid, dim3(256), 0, s, gp, ngroups);
+    else hipLaunchKernelGGL(k_grouped_post_b, grid, dim3(256), 0, s, gp, ngroups);
+}
+void launch_grouped_advance(hipStream_t s, int64_t *steps, int64_t *heads, const int64_t *nslots, int ngroups)
+{
+    hipLaunchKernelGGL(k_grouped_advance, dim3(nblk(ngroups, 64)), dim3(64), 0, s, steps, heads, nslots, ngroups);
+}
+
+}  // namespace qhp

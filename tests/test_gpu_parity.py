@@ -277,3 +277,76 @@ def test_error_paths():
     assert e.value.code == -3
     s.close()
     s2.close()
+
+
+def test_batch_uneven_graph_replay():
+    """Three scatterers of different size (sphere, torus, cube), two waves
+    each, marched together by graph replays of the grouped kernels, in three
+    chunks with eager work and synchronisation between them; every step of
+    every scatterer against its own eager march (same arithmetic form)."""
+    import paper_2312_06367_amd as qhp
+    from workloads import meshes, waves
+    dt, n = 0.12, 90
+    cases = [meshes.icosphere(1), meshes.torus(1.0, 0.4, 12, 6), meshes.cube(1.5, 2)]
+    for precision, bound in (("f64", 1e-12), ("f32a", 1e-9), ("f32", 2e-4)):
+        solvers, eager = [], []
+        for xyz, tri in cases:
+            s = qhp.Solver(dt, precision="f64", solver="inv")
+            s.mesh(xyz, tri)
+            s.assemble()
+            if precision != "f64":
+                s.set_precision(precision)
+            ws = waves.batched_waves(1, 7, 0.1, 0.1, s.info()["diameter"])
+            if precision == "f32a":
+                ws = ws[:1]  # the single-scatterer F32A form takes one right-hand side
+            ne = s.info()["ne"]
+            s.set_incident(ws, n)
+            jh = torch.zeros((n, ne, len(ws)), dtype=torch.float64, device="cuda")
+            s.run(n, jh)
+            eager.append(jh.cpu().numpy())
+            s.set_incident(ws, n)  # restart for the batch
+            solvers.append(s)
+        outs = [torch.zeros((n, s.info()["ne"], s.info()["n_rhs"]), dtype=torch.float64, device="cuda")
+                for s in solvers]
+        b = qhp.Batch(solvers)
+        for c0 in range(0, n, 30):
+            b.run(30, [o[c0:] for o in outs])
+            torch.cuda.synchronize()
+            _ = (torch.ones(1000, device="cuda") * 2).sum().item()  # eager work between replays
+        times = b.step_times(30)
+        b.close()
+        for i, (o, e) in enumerate(zip(outs, eager)):
+            err = float(np.abs(o.cpu().numpy() - e).max() / np.abs(e).max())
+            _say("[batch %s] scatterer %d (ne=%d): err vs eager %.3e; step p50 %.3f ms"
+                 % (precision, i, e.shape[1], err, float(np.median(times))))
+            assert err < bound
+        for s in solvers:
+            s.close()
+
+
+def test_dc_stability_10k_steps_large_sphere():
+    """7680-edge sphere, FP32 blocks with FP64 sums: 10^4 steps, the current
+    decays after the pulse and never grows (late-time dc stability)."""
+    import paper_2312_06367_amd as qhp
+    from workloads import waves
+    cfg = waves.sphere_large()
+    xyz, tri = cfg.mesh
+    n = 10000
+    s = qhp.Solver(cfg.dt, precision="f64", solver="inv")
+    s.mesh(xyz, tri)
+    s.assemble()
+    s.set_precision("f32a")
+    s.set_incident(cfg.waves, n)
+    ne = s.info()["ne"]
+    norms = []
+    jh = torch.zeros((1000, ne, 1), dtype=torch.float64, device="cuda")
+    for c in range(0, n, 1000):
+        s.run(1000, jh)
+        norms.append(torch.linalg.vector_norm(jh[:, :, 0], dim=1).cpu().numpy())
+    s.close()
+    nj = np.concatenate(norms)
+    peak = nj.max()
+    blocks = nj.reshape(-1, 500).max(1) / peak
+    _say("[dc 10k] block maxima / peak: " + " ".join("%.1e" % v for v in blocks))
+    assert nj[-1000:].max() < 1e-3 * peak
+    assert blocks[-1] <= 10 * blocks[len(blocks) // 2] + 1e-12  # no late growth

@@ -126,3 +126,36 @@ def small_case(kind: str = "ico1"):
     if kind == "cube":
         return meshes.cube(1.5, 2)
     raise ValueError(kind)
+
+
+def uneven_batch(n: int = 32, seed: int = 0, n_dirs: int = 8):
+    """32 seeded scatterers of uneven size marched together: type uniform over
+    {sphere r = 1 m, cube of edge 1.5 m, torus (1 m, 0.3 m)}, edge count
+    log-uniform in [500, 12000] (realised by the nearest geodesic frequency,
+    cube grid or torus grid), 8 directions each with the first polarisation
+    rule, 50 MHz pulse, c*dt = 0.05 m, 1500 steps."""
+    rng = np.random.default_rng(seed)
+    kinds = rng.integers(0, 3, size=n)
+    sizes = np.exp(rng.uniform(np.log(500.0), np.log(12000.0), size=n))
+    f0 = bw = hz_to_per_m(50e6)
+    out = []
+    for i, (kind, ne) in enumerate(zip(kinds, sizes)):
+        if kind == 0:
+            nu = max(4, int(round(np.sqrt(ne / 30.0))))
+            xyz, tri = meshes.geodesic_sphere(nu, 1.0)
+            diam, name = 2.0, "sphere-g%d" % nu
+        elif kind == 1:
+            m = max(5, int(round(np.sqrt(ne / 18.0))))
+            xyz, tri = meshes.cube(1.5, m)
+            diam, name = 1.5 * np.sqrt(3.0), "cube-%d" % m
+        else:
+            nv = max(4, int(round(np.sqrt(ne / (3.0 * 3.3)))))
+            nu = max(8, int(round(3.3 * nv)))
+            xyz, tri = meshes.torus(1.0, 0.3, nu, nv)
+            diam, name = 2.6, "torus-%dx%d" % (nu, nv)
+        t0 = mod_gauss_t0(bw, diam)
+        ws = []
+        for k in seeded_directions(n_dirs, 100 + i):
+            ws.append(Wave(tuple(k), tuple(pol_p1(k)), 1.0, t0, 0, 0.0, f0, bw))
+        out.append(Config(name, (xyz, tri), 0.05, 1500, ws))
+    return out
