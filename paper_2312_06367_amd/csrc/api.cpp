@@ -278,6 +278,26 @@ static void laplacian_pinv(qhp_ctx *c, int64_t n, DBuf &L, DBuf &out)
     qhp::launch_sub_const(c->s, n, out.as<double>());
 }
 
+// Store T_k (rows of stride ldt, FP64) into its block in the stored precision
+// with lag-carried rounding; returns the per-block scale (BF16: max |T_k + c|).
+static float store_lag(hipStream_t s, int64_t ne, int64_t ld, const double *T, int64_t ldt, double *carry,
+                       int32_t prec, DBuf &amax, void *out)
+{
+    float sc = 1.0f;
+    if (prec == QHP_BF16) {
+        unsigned long long bits = 0;
+        zero(amax, s);
+        qhp::launch_absmax(s, ne, T, ldt, carry, amax.as<unsigned long long>());
+        hip_check(hipMemcpyAsync(&bits, amax.p, 8, hipMemcpyDeviceToHost, s), "absmax");
+        hip_check(hipStreamSynchronize(s), "absmax");
+        double mx;
+        std::memcpy(&mx, &bits, 8);
+        sc = mx > 0.0 ? (float)mx : 1.0f;
+    }
+    qhp::launch_quantise_slab(s, ne, ld, T, ldt, prec == QHP_F64 ? nullptr : carry, prec, sc, out);
+    return sc;
+}
+
 extern "C" int qhp_assemble(qhp_ctx *ctx)
 {
     if (!ctx) return QHP_EINVAL;
@@ -407,6 +427,11 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
         Bk.alloc(sizeof(double) * nn); E.alloc(sizeof(double) * nn);
         Wst.alloc(sizeof(double) * nn * 2); Tt.alloc(sizeof(double) * nn);
         amax.alloc(sizeof(unsigned long long));
+        DBuf carry;  // rounding carried from lag to lag (reduced precisions only)
+        if (prec != QHP_F64) {
+            carry.alloc(sizeof(double) * nn);
+            zero(carry, s);
+        }
         zero(Ap, s);
         zero(Cp, s);
         for (int64_t k0 = 0; k0 <= K; k0 += ch) {
@@ -460,21 +485,8 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
                 if (k == 0) {
                     hip_check(hipMemcpyAsync(c->T0raw.p, Tt.p, sizeof(double) * nn, hipMemcpyDeviceToDevice, s), "copy");
                 } else {
-                    float inv_scale = 1.0f;
-                    if (prec == QHP_BF16) {
-                        unsigned long long bits = 0;
-                        zero(amax, s);
-                        qhp::launch_absmax(s, (int64_t)nn, Tt.as<double>(), amax.as<unsigned long long>());
-                        hip_check(hipMemcpyAsync(&bits, amax.p, 8, hipMemcpyDeviceToHost, s), "absmax");
-                        hip_check(hipStreamSynchronize(s), "absmax");
-                        double mx;
-                        std::memcpy(&mx, &bits, 8);
-                        float sc = mx > 0.0 ? (float)mx : 1.0f;
-                        c->scales[k - 1] = sc;
-                        inv_scale = 1.0f / sc;
-                    }
-                    qhp::launch_store_slab(s, ne, c->ld, Tt.as<double>(), prec, inv_scale,
-                                           (char *)c->slabs.p + esz * (size_t)(k - 1) * ne * c->ld);
+                    c->scales[k - 1] = store_lag(s, ne, c->ld, Tt.as<double>(), ne, carry.as<double>(), prec, amax,
+                                                 (char *)c->slabs.p + esz * (size_t)(k - 1) * ne * c->ld);
                 }
                 std::swap(Ap.p, Ak.p);
                 std::swap(Cp.p, Ck.p);
@@ -789,26 +801,14 @@ extern "C" int qhp_set_precision(qhp_ctx *ctx, int32_t precision)
     const int64_t ne = ctx->mesh.ne, ld = ctx->ld, K = ctx->K;
     const size_t per = (size_t)ne * ld;
     const size_t esz = precision == QHP_BF16 ? 2 : 4;
-    DBuf out, amax;
+    DBuf out, amax, carry;
     out.alloc(esz * per * K);
     amax.alloc(sizeof(unsigned long long));
-    for (int64_t k = 0; k < K; ++k) {
-        const double *in = ctx->slabs.as<double>() + k * per;
-        float inv_scale = 1.0f;
-        ctx->scales[k] = 1.0f;
-        if (precision == QHP_BF16) {
-            unsigned long long bits = 0;
-            zero(amax, s);
-            qhp::launch_absmax(s, (int64_t)per, in, amax.as<unsigned long long>());
-            hip_check(hipMemcpyAsync(&bits, amax.p, 8, hipMemcpyDeviceToHost, s), "absmax");
-            hip_check(hipStreamSynchronize(s), "absmax");
-            double mx;
-            std::memcpy(&mx, &bits, 8);
-            ctx->scales[k] = mx > 0.0 ? (float)mx : 1.0f;
-            inv_scale = 1.0f / ctx->scales[k];
-        }
-        qhp::launch_convert_slab(s, (int64_t)per, in, precision, inv_scale, (char *)out.p + esz * per * k);
-    }
+    carry.alloc(sizeof(double) * ne * ne);
+    zero(carry, s);
+    for (int64_t k = 0; k < K; ++k)
+        ctx->scales[k] = store_lag(s, ne, ld, ctx->slabs.as<double>() + k * per, ld, carry.as<double>(), precision, amax,
+                                   (char *)out.p + esz * per * k);
     hip_check(hipStreamSynchronize(s), "convert slabs");
     std::swap(ctx->slabs.p, out.p);
     std::swap(ctx->slabs.bytes, out.bytes);

@@ -19,7 +19,6 @@ void launch_history(hipStream_t s, int32_t precision, int64_t ne, int64_t ld, in
                     hipEvent_t e1 = nullptr, int variant = -1);
 int gemv_variant_count();
 void gemv_variant_desc(int v, int *rpw, int *unr, int *nt);
-void launch_convert_slab(hipStream_t s, int64_t n, const double *in, int32_t precision, float inv_scale, void *out);
 void launch_gemv_f64(hipStream_t s, int64_t n, const double *A, const double *x, double *y);
 void launch_trsv_lu(hipStream_t s, int64_t n, const double *LU, const double *Dinv, const int32_t *perm,
                     const double *b, double *x, int *flags, const int *epoch, int upper, int *err);
@@ -31,9 +30,11 @@ void launch_post_a(hipStream_t s, int64_t nc, int64_t nrhs, double dtn, const in
                    const int32_t *tri_sign, const double *y, const double *yprev, double *sv);
 void launch_post_b(hipStream_t s, int64_t ne, int64_t nrhs, const int32_t *cells, const double *y, const double *z,
                    double *j);
-void launch_store_slab(hipStream_t s, int64_t ne, int64_t ld, const double *T, int32_t precision, float inv_scale,
-                       void *out);
-void launch_absmax(hipStream_t s, int64_t n, const double *T, unsigned long long *out);
+// lag-carried rounding of T_k (rows of stride ldt) into the stored block [ne][ld]
+void launch_quantise_slab(hipStream_t s, int64_t ne, int64_t ld, const double *T, int64_t ldt, double *carry,
+                          int32_t precision, float scale, void *out);
+void launch_absmax(hipStream_t s, int64_t ne, const double *T, int64_t ldt, const double *carry,
+                   unsigned long long *out);
 void launch_load_slab(hipStream_t s, int64_t ne, int64_t ld, const void *in, int32_t precision, float scale,
                       double *T);
 void launch_exc_local(hipStream_t s, int64_t ntri, const double *xyz, const int32_t *tri, const int32_t *sgn,

@@ -483,26 +483,6 @@ void launch_history(hipStream_t s, int32_t precision, int64_t ne, int64_t ld, in
                        (int64_t)nsplit, (const float *)partial, r, b);
 }
 
-// FP64 slab [ne][ld] -> another precision, same layout
-__global__ void k_convert_slab(int64_t n, const double *in, int32_t precision, float inv_scale, void *out)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double v = in[i];
-    if (precision == QHP_F32 || precision == QHP_F32A) {
-        ((float *)out)[i] = (float)v;
-    } else {
-        float f = (float)v * inv_scale;
-        uint32_t u = __float_as_uint(f);
-        uint32_t rounding = 0x7fffu + ((u >> 16) & 1u);
-        ((uint16_t *)out)[i] = (uint16_t)((u + rounding) >> 16);
-    }
-}
-void launch_convert_slab(hipStream_t s, int64_t n, const double *in, int32_t precision, float inv_scale, void *out)
-{
-    hipLaunchKernelGGL(k_convert_slab, dim3(nblk(n, 256)), dim3(256), 0, s, n, in, precision, inv_scale, out);
-}
-
 // ------------------------------------------------------------------ solve
 // y = Tinv b (dense FP64 inverse), one row per wave.
 __global__ __launch_bounds__(256) void k_gemv_f64(int64_t n, const double *__restrict__ A,
@@ -703,38 +683,67 @@ void launch_post_b(hipStream_t s, int64_t ne, int64_t nrhs, const int32_t *cells
 }
 
 // quantise T (FP64, [ne][ne]) into the slab store [ne][ld] with scale
-__global__ void k_store_slab(int64_t ne, int64_t ld, const double *T, int32_t precision, float inv_scale, void *out)
+// Lag-carried rounding of one lag block into its stored precision.  The value
+// rounded is T_k + c_{k-1}, and c_k = (T_k + c_{k-1}) - stored_k is carried to
+// the next lag (c_0 = 0), so every prefix sum over lags of the stored blocks is
+// within one rounding of the exact prefix sum.  The history sum then sees the
+// rounding error only through differences y_{i-k-1} - y_{i-k}.
+// T: [ne] rows of stride ldt (FP64); carry: [ne][ne] FP64 or null; out: [ne][ld].
+__global__ void k_quantise_slab(int64_t ne, int64_t ld, const double *T, int64_t ldt, double *carry,
+                                int32_t precision, float scale, float inv_scale, void *out)
 {
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= ne * ld) return;
     int64_t i = idx / ld, j = idx % ld;
-    double v = j < ne ? T[i * ne + j] : 0.0;
-    if (precision == QHP_F64) ((double *)out)[idx] = v;
-    else if (precision == QHP_F32 || precision == QHP_F32A) ((float *)out)[idx] = (float)v;
-    else {
+    if (j >= ne) {
+        if (precision == QHP_F64) ((double *)out)[idx] = 0.0;
+        else if (precision == QHP_BF16) ((uint16_t *)out)[idx] = 0;
+        else ((float *)out)[idx] = 0.0f;
+        return;
+    }
+    double v = T[i * ldt + j];
+    if (carry) v += carry[i * ne + j];
+    double kept;
+    if (precision == QHP_F64) {
+        ((double *)out)[idx] = v;
+        kept = v;
+    } else if (precision == QHP_F32 || precision == QHP_F32A) {
+        float f = (float)v;
+        ((float *)out)[idx] = f;
+        kept = (double)f;
+    } else {
         float f = (float)v * inv_scale;
         uint32_t u = __float_as_uint(f);
         uint32_t rounding = 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
-        ((uint16_t *)out)[idx] = (uint16_t)((u + rounding) >> 16);
+        uint16_t h = (uint16_t)((u + rounding) >> 16);
+        ((uint16_t *)out)[idx] = h;
+        kept = (double)__uint_as_float((uint32_t)h << 16) * (double)scale;
     }
+    if (carry) carry[i * ne + j] = v - kept;
 }
-void launch_store_slab(hipStream_t s, int64_t ne, int64_t ld, const double *T, int32_t precision, float inv_scale,
-                       void *out)
+void launch_quantise_slab(hipStream_t s, int64_t ne, int64_t ld, const double *T, int64_t ldt, double *carry,
+                          int32_t precision, float scale, void *out)
 {
-    hipLaunchKernelGGL(k_store_slab, dim3(nblk(ne * ld, 256)), dim3(256), 0, s, ne, ld, T, precision, inv_scale, out);
+    hipLaunchKernelGGL(k_quantise_slab, dim3(nblk(ne * ld, 256)), dim3(256), 0, s, ne, ld, T, ldt, carry, precision,
+                       scale, 1.0f / scale, out);
 }
-// max |T|
-__global__ void k_absmax(int64_t n, const double *T, unsigned long long *out)
+// max |T + carry| over an [ne] x [ne] block whose rows have stride ldt
+__global__ void k_absmax(int64_t ne, const double *T, int64_t ldt, const double *carry, unsigned long long *out)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double v = 0.0;
-    for (; i < n; i += (int64_t)gridDim.x * blockDim.x) v = fmax(v, fabs(T[i]));
+    for (; idx < ne * ne; idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t i = idx / ne, j = idx % ne;
+        double t = T[i * ldt + j] + (carry ? carry[idx] : 0.0);
+        v = fmax(v, fabs(t));
+    }
     for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
     if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(v));
 }
-void launch_absmax(hipStream_t s, int64_t n, const double *T, unsigned long long *out)
+void launch_absmax(hipStream_t s, int64_t ne, const double *T, int64_t ldt, const double *carry,
+                   unsigned long long *out)
 {
-    hipLaunchKernelGGL(k_absmax, dim3(1024), dim3(256), 0, s, n, T, out);
+    hipLaunchKernelGGL(k_absmax, dim3(1024), dim3(256), 0, s, ne, T, ldt, carry, out);
 }
 // dequantise a stored slab into FP64 [ne][ne]
 __global__ void k_load_slab(int64_t ne, int64_t ld, const void *in, int32_t precision, float scale, double *T)
@@ -746,7 +755,7 @@ __global__ void k_load_slab(int64_t ne, int64_t ld, const void *in, int32_t prec
     double v;
     if (precision == QHP_F64) v = ((const double *)in)[o];
     else if (precision == QHP_F32 || precision == QHP_F32A) v = ((const float *)in)[o];
-    else v = (double)(bf16_to_f32(((const uint16_t *)in)[o]) * scale);
+    else v = (double)bf16_to_f32(((const uint16_t *)in)[o]) * (double)scale;  // exact product
     T[idx] = v;
 }
 void launch_load_slab(hipStream_t s, int64_t ne, int64_t ld, const void *in, int32_t precision, float scale,

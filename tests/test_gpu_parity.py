@@ -1,8 +1,8 @@
 """Parity of the HIP path with the CPU FP64 oracle (MI355X only).
 
 Every comparison is relative to the largest magnitude of the oracle's
-result: FP64 path <= 1e-10, FP32 slabs <= 1e-5, BF16 slabs <= 5e-2 on the
-current (the bound for each form is stated in its test)."""
+result: FP64 path <= 1e-10; the reduced-precision forms each have the bound
+stated in their test."""
 import sys
 
 import numpy as np
@@ -92,6 +92,44 @@ def test_raw_lag_and_slab_parity(small):
     assert worst < 1e-10
 
 
+@pytest.mark.parametrize("precision,unit", [("f32", 2.0 ** -24 * (1 + 1e-9)), ("bf16", 2.0 ** -8 * 1.001 + 2.0 ** -22)])
+def test_lag_carried_rounding(small, precision, unit):
+    """Stored reduced-precision blocks carry each block's rounding into the
+    next lag: with c_0 = 0 and c_k = (T_k + c_{k-1}) - stored_k, every carry
+    is at most one rounding of T_k + c_{k-1} (half an ulp: 2^-24 relative in
+    FP32, 2^-8 in BF16 with its 8-bit significand, plus the FP32 scaling of
+    the BF16 form), so each prefix sum over lags of
+    the stored blocks stays within one rounding of the FP64 prefix sum.
+    Checked for blocks re-stored from FP64 and for blocks assembled directly
+    in the reduced precision."""
+    import paper_2312_06367_amd as qhp
+    xyz, tri, dt = small["xyz"], small["tri"], small["dt"]
+    K = small["asm"].K
+    for direct in (False, True):
+        s = qhp.Solver(dt, precision=precision if direct else "f64")
+        s.mesh(xyz, tri)
+        s.assemble()
+        if direct:
+            T = [None] + [small["s"].get_matrix("slab", k) for k in range(1, K + 1)]
+        else:
+            T = [None] + [s.get_matrix("slab", k) for k in range(1, K + 1)]
+            s.set_precision(precision)
+        slack = 1e-12 * max(np.abs(T[k]).max() for k in range(1, K + 1)) if direct else 0.0
+        c = np.zeros_like(T[1])
+        worst, plain = 0.0, 0.0
+        for k in range(1, K + 1):
+            stored = s.get_matrix("slab", k)
+            cn = (T[k] + c) - stored
+            ratio = np.abs(cn) / (unit * np.abs(T[k] + c) + slack + 1e-300)
+            worst = max(worst, float(ratio.max()))
+            plain = max(plain, float(np.abs(cn).max() / np.abs(T[k]).max()))
+            c = cn
+        s.close()
+        _say("[carry %s %s] max |c_k| / one rounding %.3f; max |c_k| / max |T_k| %.2e"
+             % (precision, "direct" if direct else "re-stored", worst, plain))
+        assert worst <= 1.0
+
+
 def test_march_parity_f64(small):
     s = small["s"]
     n = small["n_steps"]
@@ -142,7 +180,7 @@ def _march_gpu(xyz, tri, dt, waves, n, precision, solver="lu"):
 
 # stated bounds (relative to the peak current) of the reduced-precision forms
 # on the 120-edge sphere, 300 steps
-BOUNDS = {"f32a": 1e-6, "f32": 1e-3, "bf16": 1e-1}
+BOUNDS = {"f32a": 1e-7, "f32": 1e-5, "bf16": 5e-3}
 
 
 @pytest.mark.parametrize("precision", ["f32a", "f32", "bf16"])
@@ -166,7 +204,7 @@ def test_batched_march_parity():
     r = np.stack([E.rhs(asm, w, n) for w in ws], axis=-1)
     y = mot.march(asm.T, r)
     jref = mot.currents(asm.proj.PLH, asm.proj.PS, asm.dtn, y)
-    for precision, bound in (("f64", 1e-10), ("f32", 1e-3)):
+    for precision, bound in (("f64", 1e-10), ("f32", 5e-4), ("bf16", 6e-2)):
         j = _march_gpu(xyz, tri, dt, ws, n, precision)
         err = float(np.abs(j - jref).max() / np.abs(jref).max())
         _say("[torus batched] %s: current err %.3e" % (precision, err))
