@@ -42,7 +42,7 @@ enum {
     QHP_ENOMEM = -4,    /* device allocation failed                           */
     QHP_EDEVICE = -5,   /* HIP runtime error                                  */
     QHP_ESINGULAR = -6, /* zero pivot in an LU factorisation                  */
-    QHP_ENOCONV = -7,   /* reserved for iterative solvers                     */
+    QHP_ENOCONV = -7,   /* iterative solve did not reach its tolerance        */
     QHP_EUNSTABLE = -8  /* non-finite value in the marching solution          */
 };
 
@@ -57,8 +57,19 @@ enum { QHP_F64 = 0, QHP_F32 = 1, QHP_BF16 = 2, QHP_F32A = 3 };
 
 /* per-step solve with T_0 (the paper writes only T_0^{-1}, Sec. IV-B) */
 enum {
-    QHP_SOLVE_LU = 0, /* LU with partial pivoting once, two triangular solves per step */
-    QHP_SOLVE_INV = 1 /* inverse formed once from that LU, one product per step       */
+    QHP_SOLVE_LU = 0,   /* LU with partial pivoting once, two triangular solves per step */
+    QHP_SOLVE_INV = 1,  /* inverse formed once from that LU, one product per step       */
+    QHP_SOLVE_GMRES = 2 /* restarted GMRES, FP32 Arnoldi inside FP64 residual
+                           refinement, started from a warm-start guess (set with
+                           qhp_set_gmres after assembly; one right-hand side)     */
+};
+
+/* start vector of the iterative solve of step i */
+enum {
+    QHP_WARM_COLD = 0,   /* zero                                               */
+    QHP_WARM_PREV = 1,   /* y_{i-1}                                            */
+    QHP_WARM_EXTRAP = 2, /* 2 y_{i-1} - y_{i-2}                                */
+    QHP_WARM_MLP = 3     /* the attached perceptron's guess from y_{i-1..i-4}  */
 };
 
 typedef struct qhp_ctx qhp_ctx;
@@ -67,7 +78,7 @@ typedef struct {
     double dt;         /* c*dt in metres, > 0                                     */
     double eta_c;      /* coupling of eq. qHP_TDCFIE (the paper's eta^2; 1 here)  */
     int32_t precision; /* QHP_F64 / QHP_F32 / QHP_BF16                             */
-    int32_t solver;    /* QHP_SOLVE_LU / QHP_SOLVE_INV                            */
+    int32_t solver;    /* QHP_SOLVE_LU / QHP_SOLVE_INV (GMRES: qhp_set_gmres)      */
     int32_t n_psi;     /* angular Gauss points per sub-interval; <= 0 means 10    */
     int32_t device;    /* HIP device ordinal                                       */
     void *stream;      /* hipStream_t, or NULL                                     */
@@ -130,7 +141,9 @@ int qhp_assemble(qhp_ctx *ctx);
 int qhp_set_precision(qhp_ctx *ctx, int32_t precision);
 
 /* Switch the per-step T_0 solve (QHP_SOLVE_LU / QHP_SOLVE_INV); both use the
- * FP64 LU of T_0 made by qhp_assemble.  Takes effect at the next step. */
+ * FP64 LU of T_0 made by qhp_assemble.  QHP_SOLVE_GMRES keeps the parameters
+ * of the last qhp_set_gmres (defaults: tol 1e-10, 40 iterations, 4 inner
+ * solves, cold start).  Takes effect at the next step. */
 int qhp_set_solver(qhp_ctx *ctx, int32_t solver);
 
 /* Time the history-sum kernel of every following step with HIP events on
@@ -207,6 +220,85 @@ int qhp_batch_run(qhp_batch *b, int32_t n_steps, double *const *j_hists);
 int qhp_batch_step_times(const qhp_batch *b, float *ms, int32_t n);
 const char *qhp_batch_last_error(const qhp_batch *b);
 void qhp_batch_destroy(qhp_batch *b);
+
+/* ---------------------------------------------------------------------------
+ * Iterative T_0 solve and learned warm start (an extension: the paper only
+ * writes T_0^{-1} in the update of Sec. IV-B).
+ *
+ * qhp_set_gmres: switch the context's per-step solve to restarted GMRES on
+ *   T_0.  The Arnoldi basis and the products with T_0 are FP32 (T_0 rounded
+ *   once); each inner solve reduces the FP64 residual r = b - T_0 y by up to
+ *   1e-6, and FP64 refinement repeats until |r| <= tol |b| (tol > 0, e.g.
+ *   1e-10) or max_refine inner solves of at most m_max (1..512) iterations
+ *   each have run; then the step falls back to the LU solve and counts a
+ *   fallback.  warm: QHP_WARM_*; QHP_WARM_MLP needs qhp_attach_mlp first.
+ *   Needs an assembled context and one right-hand side (QHP_EINVAL else).
+ * qhp_gmres_stats: totals since the last reset (or context creation): steps
+ *   solved, inner iterations (products with T_0), maximum per step, inner
+ *   solves, LU fallbacks; and optionally, into host iters[n] / res0[n], the
+ *   per-step iteration counts and relative residuals |b - T_0 x0| / |b| of
+ *   the start vectors, for the first n steps recorded.
+ * qhp_gmres_reset: clear those records. */
+typedef struct {
+    int64_t steps, iterations, max_iterations, refinements, fallbacks;
+} qhp_gmres_info;
+int qhp_set_gmres(qhp_ctx *ctx, double tol, int32_t m_max, int32_t max_refine, int32_t warm);
+int qhp_gmres_stats(const qhp_ctx *ctx, qhp_gmres_info *info, int32_t *iters, float *res0, int64_t n);
+int qhp_gmres_reset(qhp_ctx *ctx);
+
+/* The perceptron that predicts y_i from y_{i-1..i-4}.
+ * Coordinates (Sec. II-D decomposition of the RWG span): a vector y maps to
+ * f = [l (N_V) | s (N_C) | h (N_H)] with s = (Sigma^T Sigma)^+ Sigma^T y,
+ * l = (Lambda^T Lambda)^+ Lambda^T y and h = H^T y, H an orthonormal basis of
+ * the harmonic space (built once from the context's projectors; unique up to
+ * a rotation); N_F = N_V + N_C + N_H = N_E + 2.  Network, N_in = 4 N_F:
+ *   x = [f_{i-1}, f_{i-2}, f_{i-3}, f_{i-4}] / sigma, sigma = rms(f_{i-1}),
+ *   a1 = tanh(W1 x + b1), a2 = tanh(W2 a1 + b2), o = W3 a2 + b3,
+ *   guess f_i = 2 f_{i-1} - f_{i-2} + sigma o.
+ * Weights are used as BF16 (products on the matrix cores, FP32 sums), biases
+ * and the master copy of every parameter are FP32.  Parameter vector layout
+ * (FP32): W1 [H][N_in], b1 [H], W2 [H][H], b2 [H], W3 [N_F][H], b3 [N_F].
+ *
+ * qhp_mlp_create: for an assembled context (which must outlive it), hidden
+ *   width H, Glorot-uniform weights from splitmix64(seed), zero biases, the
+ *   output layer scaled by 0.01.
+ * qhp_mlp_dims: N_F, parameter count, H.
+ * qhp_mlp_set_params / qhp_mlp_get_params: host FP32 [n_params]; setting
+ *   also resets the Adam moments.
+ * qhp_mlp_features: device y [n][N_E] FP64 -> device f [n][N_F] FP64.
+ * qhp_mlp_reconstruct: device f [n][N_F] -> device y [n][N_E] (Lambda l +
+ *   Sigma s + H h).
+ * qhp_mlp_forward: device x [batch][N_in] FP32 -> device out [batch][N_F]
+ *   FP32 (the network output o).
+ * qhp_mlp_loss_grad: forward and backward for device x [batch][N_in] and
+ *   targets t [batch][N_F] (FP32): loss = mean over batch and outputs of
+ *   (o - t)^2 into *loss (host, may be NULL), gradient into host grad
+ *   [n_params] (may be NULL; it is also kept for qhp_mlp_adam).
+ * qhp_mlp_adam: one Adam step (bias-corrected) with the kept gradient.
+ * qhp_mlp_train: features of device y [n_steps][N_E][n_runs] FP64 (the
+ *   y_hist layout of qhp_run with n_runs right-hand sides), then `epochs`
+ *   passes over every window (run, i >= 4) in an order shuffled from seed,
+ *   minibatches of `batch`, Adam (lr, 0.9, 0.999, 1e-8) with targets
+ *   t = (f_i - 2 f_{i-1} + f_{i-2}) / sigma; host epoch_loss[epochs] (may be
+ *   NULL) receives each pass's mean minibatch loss.  Device memory:
+ *   8 n_steps n_runs N_F bytes of features for the call.
+ * qhp_attach_mlp: use m (NULL: none) for QHP_WARM_MLP on ctx.
+ * qhp_mlp_destroy: frees m (detaching it from its context). */
+typedef struct qhp_mlp qhp_mlp;
+int qhp_mlp_create(qhp_ctx *ctx, int32_t hidden, uint64_t seed, qhp_mlp **out);
+int qhp_mlp_dims(const qhp_mlp *m, int64_t *n_features, int64_t *n_params, int64_t *hidden);
+int qhp_mlp_set_params(qhp_mlp *m, const float *params);
+int qhp_mlp_get_params(const qhp_mlp *m, float *params);
+int qhp_mlp_features(qhp_mlp *m, const double *y, int64_t n, double *f);
+int qhp_mlp_reconstruct(qhp_mlp *m, const double *f, int64_t n, double *y);
+int qhp_mlp_forward(qhp_mlp *m, const float *x, int32_t batch, float *out);
+int qhp_mlp_loss_grad(qhp_mlp *m, const float *x, const float *t, int32_t batch, double *loss, float *grad);
+int qhp_mlp_adam(qhp_mlp *m, double lr, double beta1, double beta2, double eps);
+int qhp_mlp_train(qhp_mlp *m, const double *y, int64_t n_runs, int64_t n_steps, int32_t epochs, int32_t batch,
+                  double lr, uint64_t seed, double *epoch_loss);
+int qhp_attach_mlp(qhp_ctx *ctx, qhp_mlp *m);
+const char *qhp_mlp_last_error(const qhp_mlp *m);
+void qhp_mlp_destroy(qhp_mlp *m);
 
 #ifdef __cplusplus
 }

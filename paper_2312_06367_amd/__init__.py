@@ -16,13 +16,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqhp.so")
 
 QHP_F64, QHP_F32, QHP_BF16, QHP_F32A = 0, 1, 2, 3
-QHP_SOLVE_LU, QHP_SOLVE_INV = 0, 1
+QHP_SOLVE_LU, QHP_SOLVE_INV, QHP_SOLVE_GMRES = 0, 1, 2
+WARM = {"cold": 0, "prev": 1, "extrap": 2, "mlp": 3}
 MAT = {"gram": 0, "zs": 1, "zh": 2, "m": 3, "psigma": 4, "plambda": 5, "pe": 6, "pm": 7,
        "slab": 8, "a": 9, "b": 10, "c": 11}
 ERRORS = {0: "OK", -1: "EINVAL", -2: "EMESH", -3: "ESTATE", -4: "ENOMEM", -5: "EDEVICE",
           -6: "ESINGULAR", -7: "ENOCONV", -8: "EUNSTABLE"}
 PRECISIONS = {"f64": QHP_F64, "f32": QHP_F32, "bf16": QHP_BF16, "f32a": QHP_F32A}
-SOLVERS = {"lu": QHP_SOLVE_LU, "inv": QHP_SOLVE_INV}
+SOLVERS = {"lu": QHP_SOLVE_LU, "inv": QHP_SOLVE_INV, "gmres": QHP_SOLVE_GMRES}
 
 
 class QhpError(RuntimeError):
@@ -43,6 +44,11 @@ class _Wave(ctypes.Structure):
                 ("f0", ctypes.c_double), ("bw", ctypes.c_double)]
 
 
+class _GmresInfo(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("iterations", ctypes.c_int64), ("max_iterations", ctypes.c_int64),
+                ("refinements", ctypes.c_int64), ("fallbacks", ctypes.c_int64)]
+
+
 class _Info(ctypes.Structure):
     _fields_ = [("nv", ctypes.c_int64), ("ne", ctypes.c_int64), ("nc", ctypes.c_int64),
                 ("n_harmonic", ctypes.c_int64), ("K", ctypes.c_int64), ("n_rhs", ctypes.c_int64),
@@ -55,7 +61,12 @@ EXPORTS = ["qhp_create", "qhp_mesh", "qhp_assemble", "qhp_set_precision", "qhp_s
            "qhp_hist_time", "qhp_set_incident", "qhp_step", "qhp_run", "qhp_query", "qhp_edges",
            "qhp_get_matrix", "qhp_keep_raw", "qhp_history_sum", "qhp_batch_create", "qhp_batch_run",
            "qhp_batch_step_times", "qhp_batch_last_error", "qhp_batch_destroy", "qhp_last_error",
-           "qhp_destroy"]
+           "qhp_destroy", "qhp_set_gmres", "qhp_gmres_stats", "qhp_gmres_reset", "qhp_mlp_create",
+           "qhp_mlp_dims", "qhp_mlp_set_params", "qhp_mlp_get_params", "qhp_mlp_features", "qhp_mlp_reconstruct",
+           "qhp_mlp_forward", "qhp_mlp_loss_grad", "qhp_mlp_adam", "qhp_mlp_train", "qhp_attach_mlp",
+           "qhp_mlp_last_error", "qhp_mlp_destroy"]
+_NO_RC = ("qhp_last_error", "qhp_destroy", "qhp_batch_last_error", "qhp_batch_destroy", "qhp_mlp_last_error",
+          "qhp_mlp_destroy")
 
 _lib = None
 
@@ -95,8 +106,27 @@ def lib():
         L.qhp_last_error.restype = ctypes.c_char_p
         L.qhp_destroy.argtypes = [vp]
         L.qhp_destroy.restype = None
+        dbl, u64 = ctypes.c_double, ctypes.c_uint64
+        L.qhp_set_gmres.argtypes = [vp, dbl, i32, i32, i32]
+        L.qhp_gmres_stats.argtypes = [vp, ctypes.POINTER(_GmresInfo), vp, vp, i64]
+        L.qhp_gmres_reset.argtypes = [vp]
+        L.qhp_mlp_create.argtypes = [vp, i32, u64, ctypes.POINTER(vp)]
+        L.qhp_mlp_dims.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.qhp_mlp_set_params.argtypes = [vp, vp]
+        L.qhp_mlp_get_params.argtypes = [vp, vp]
+        L.qhp_mlp_features.argtypes = [vp, vp, i64, vp]
+        L.qhp_mlp_reconstruct.argtypes = [vp, vp, i64, vp]
+        L.qhp_mlp_forward.argtypes = [vp, vp, i32, vp]
+        L.qhp_mlp_loss_grad.argtypes = [vp, vp, vp, i32, ctypes.POINTER(dbl), vp]
+        L.qhp_mlp_adam.argtypes = [vp, dbl, dbl, dbl, dbl]
+        L.qhp_mlp_train.argtypes = [vp, vp, i64, i64, i32, i32, dbl, u64, vp]
+        L.qhp_attach_mlp.argtypes = [vp, vp]
+        L.qhp_mlp_last_error.argtypes = [vp]
+        L.qhp_mlp_last_error.restype = ctypes.c_char_p
+        L.qhp_mlp_destroy.argtypes = [vp]
+        L.qhp_mlp_destroy.restype = None
         for name in EXPORTS:
-            if name not in ("qhp_last_error", "qhp_destroy", "qhp_batch_last_error", "qhp_batch_destroy"):
+            if name not in _NO_RC:
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -182,6 +212,26 @@ class Solver:
     def run(self, n_steps: int, j_hist=None, y_hist=None):
         self._check(self.L.qhp_run(self.h, int(n_steps), _ptr(j_hist), _ptr(y_hist)))
 
+    def set_gmres(self, tol: float = 1e-10, m_max: int = 40, max_refine: int = 4, warm: str = "cold"):
+        self._check(self.L.qhp_set_gmres(self.h, float(tol), int(m_max), int(max_refine), WARM[warm]))
+
+    def gmres_stats(self, n: int = 0):
+        """Totals since the last reset, and the first n per-step iteration
+        counts and start-vector residuals."""
+        inf = _GmresInfo()
+        it = np.zeros(max(n, 1), dtype=np.int32)
+        r0 = np.zeros(max(n, 1), dtype=np.float32)
+        self._check(self.L.qhp_gmres_stats(self.h, ctypes.byref(inf), it.ctypes.data, r0.ctypes.data, int(n)))
+        out = {k: getattr(inf, k) for k, _ in _GmresInfo._fields_}
+        out["iters"], out["res0"] = it[:n], r0[:n]
+        return out
+
+    def gmres_reset(self):
+        self._check(self.L.qhp_gmres_reset(self.h))
+
+    def attach_mlp(self, mlp):
+        self._check(self.L.qhp_attach_mlp(self.h, None if mlp is None else mlp.h))
+
     def info(self) -> dict:
         inf = _Info()
         self._check(self.L.qhp_query(self.h, ctypes.byref(inf)))
@@ -258,6 +308,100 @@ class Batch:
     def close(self):
         if getattr(self, "h", None):
             self.L.qhp_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MLP:
+    """The warm-start perceptron of a solver's mesh (qhp_mlp_*)."""
+
+    def __init__(self, solver: Solver, hidden: int = 256, seed: int = 0):
+        self.L = lib()
+        self.solver = solver
+        h = ctypes.c_void_p()
+        rc = self.L.qhp_mlp_create(solver.h, int(hidden), int(seed), ctypes.byref(h))
+        if rc != 0:
+            raise QhpError(rc, self.L.qhp_last_error(solver.h).decode())
+        self.h = h
+        nf, npar, hid = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self.L.qhp_mlp_dims(h, ctypes.byref(nf), ctypes.byref(npar), ctypes.byref(hid))
+        self.nf, self.n_params, self.hidden = nf.value, npar.value, hid.value
+        self.n_in = 4 * self.nf
+
+    def _check(self, rc):
+        if rc != 0:
+            raise QhpError(rc, self.L.qhp_mlp_last_error(self.h).decode())
+
+    def layout(self):
+        """(name, shape) of the parameter vector's segments, in order."""
+        H, ni, nf = self.hidden, self.n_in, self.nf
+        return [("W1", (H, ni)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)), ("W3", (nf, H)), ("b3", (nf,))]
+
+    def unpack(self, flat):
+        out, o = {}, 0
+        for name, shape in self.layout():
+            n = int(np.prod(shape))
+            out[name] = flat[o:o + n].reshape(shape)
+            o += n
+        return out
+
+    def pack(self, params: dict) -> np.ndarray:
+        return np.concatenate([np.asarray(params[k], dtype=np.float32).reshape(-1) for k, _ in self.layout()])
+
+    def set_params(self, params):
+        flat = np.ascontiguousarray(self.pack(params) if isinstance(params, dict) else params, dtype=np.float32)
+        self._check(self.L.qhp_mlp_set_params(self.h, flat.ctypes.data))
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(self.n_params, dtype=np.float32)
+        self._check(self.L.qhp_mlp_get_params(self.h, out.ctypes.data))
+        return out
+
+    def features(self, y):
+        import torch
+        f = torch.empty((y.shape[0], self.nf), dtype=torch.float64, device=y.device)
+        self._check(self.L.qhp_mlp_features(self.h, _ptr(y), y.shape[0], _ptr(f)))
+        return f
+
+    def reconstruct(self, f):
+        import torch
+        ne = self.solver.info()["ne"]
+        y = torch.empty((f.shape[0], ne), dtype=torch.float64, device=f.device)
+        self._check(self.L.qhp_mlp_reconstruct(self.h, _ptr(f), f.shape[0], _ptr(y)))
+        return y
+
+    def forward(self, x):
+        import torch
+        out = torch.empty((x.shape[0], self.nf), dtype=torch.float32, device=x.device)
+        self._check(self.L.qhp_mlp_forward(self.h, _ptr(x), x.shape[0], _ptr(out)))
+        return out
+
+    def loss_grad(self, x, t):
+        loss = ctypes.c_double()
+        g = np.zeros(self.n_params, dtype=np.float32)
+        self._check(self.L.qhp_mlp_loss_grad(self.h, _ptr(x), _ptr(t), x.shape[0], ctypes.byref(loss),
+                                             g.ctypes.data))
+        return loss.value, g
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._check(self.L.qhp_mlp_adam(self.h, lr, beta1, beta2, eps))
+
+    def train(self, y_hist, epochs: int, batch: int = 512, lr: float = 1e-3, seed: int = 0):
+        """y_hist: device float64 [n_steps, ne, n_runs]; returns the per-epoch losses."""
+        losses = np.zeros(epochs, dtype=np.float64)
+        n_steps, _, n_runs = y_hist.shape
+        self._check(self.L.qhp_mlp_train(self.h, _ptr(y_hist), n_runs, n_steps, int(epochs), int(batch),
+                                         float(lr), int(seed), losses.ctypes.data))
+        return losses
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.qhp_mlp_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -15,53 +15,15 @@
 #include "linalg.h"
 #include "march.h"
 #include "qhp_internal.h"
+#include "ctx.h"
+
+using qhp::DBuf;
+using qhp::Fail;
+using qhp::hip_check;
+using qhp::upload;
+using qhp::zero;
 
 namespace {
-
-struct Fail {
-    int code;
-    std::string msg;
-};
-
-void hip_check(hipError_t e, const char *what)
-{
-    if (e != hipSuccess) throw Fail{e == hipErrorOutOfMemory ? QHP_ENOMEM : QHP_EDEVICE,
-                                    std::string(what) + ": " + hipGetErrorString(e)};
-}
-
-// device allocation owned by a context
-struct DBuf {
-    void *p = nullptr;
-    size_t bytes = 0;
-    void alloc(size_t n)
-    {
-        release();
-        if (n == 0) n = 8;
-        hipError_t e = hipMalloc(&p, n);
-        if (e != hipSuccess) {
-            p = nullptr;
-            (void)hipGetLastError();
-            throw Fail{QHP_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed"};
-        }
-        bytes = n;
-    }
-    void release()
-    {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
-    template <class T>
-    T *as() const { return (T *)p; }
-    ~DBuf() { release(); }
-};
-
-template <class T>
-void upload(DBuf &b, const std::vector<T> &v, hipStream_t s)
-{
-    b.alloc(sizeof(T) * std::max<size_t>(v.size(), 1));
-    if (!v.empty()) hip_check(hipMemcpyAsync(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s), "upload");
-}
 
 // Gauss-Legendre nodes on [-1, 1] by Newton iteration on P_n.
 void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
@@ -91,52 +53,9 @@ void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
 
 }  // namespace
 
-struct qhp_ctx {
-    qhp_params p{};
-    hipStream_t s = nullptr;
-    int state = 0;  // 0 created, 1 meshed, 2 assembled, 3 incident set
-    std::string err;
-    bool keep_raw = false;
-    qhp::Mesh mesh;
-    int64_t K = 0, ld = 0;
-    double T0 = 0, dtn = 0, kappa = 0;
-    // device tables
-    DBuf t_xyz, t_tri, t_edges, t_cells, t_tri_edge, t_tri_sign, t_area, t_valence, t_fxyz, t_ftri, t_fparent,
-        t_fowner, t_bc_off, t_bc_edge, t_bc_local, t_bc_flux, t_vcell_off, t_vcell_tri, t_vedge_off, t_vedge,
-        t_bct_off, t_bct_entry, t_bc_tri;
-    qhp::AsmArgs args{};
-    // assembled operators (FP64, row-major)
-    DBuf G, Zs, Zh, M, PS, PPL, Pcat, LSp;
-    DBuf slabs, scales_d, T0raw, LU0, ipiv0, perm0, Linv, Uinv, Tinv;
-    std::vector<float> scales;
-    std::vector<std::vector<double>> rawA, rawB, rawC;
-    // march state
-    int32_t nrhs = 0;
-    int64_t n_steps = 0, step = 0, head = 0;
-    bool broken = false;
-    DBuf waves_d, rhs, ring64, ring32, bvec, zvec, yvec, partial, sv, zc, flags, epoch, errflag;
-    int nsplit = 1;
-    int hv = -1;  // autotuned variant of the single right-hand-side history kernel
-    // profiling of the history kernel
-    bool profiling = false;
-    std::vector<hipEvent_t> ev;
-    double hist_ms = 0.0;
-    int64_t hist_launches = 0;
-    bool verbose = false;
-    std::chrono::steady_clock::time_point t_stage;
-    void stage(const char *name)
-    {
-        if (!verbose) return;
-        (void)hipStreamSynchronize(s);
-        auto now = std::chrono::steady_clock::now();
-        std::fprintf(stderr, "[qhp] %-28s %9.3f s\n", name, std::chrono::duration<double>(now - t_stage).count());
-        t_stage = now;
-    }
-};
-
 using qhp::AsmArgs;
 
-static int guard(qhp_ctx *ctx, int code, const std::string &msg)
+int guard(qhp_ctx *ctx, int code, const std::string &msg)
 {
     if (ctx) ctx->err = msg;
     return code;
@@ -262,7 +181,6 @@ static void upload_tables(qhp_ctx *c)
     a.ng = c->p.n_psi;
 }
 
-static void zero(DBuf &b, hipStream_t s) { hip_check(hipMemsetAsync(b.p, 0, b.bytes, s), "memset"); }
 
 // (L + 11^T/n)^{-1} - 11^T/n for the graph Laplacian held (with 1/n added) in L
 static void laplacian_pinv(qhp_ctx *c, int64_t n, DBuf &L, DBuf &out)
@@ -325,16 +243,16 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
     AsmArgs &a = c->args;
     // ---- projectors (Sec. II-D), FP64
     {
-        DBuf LS, LL, LLp;
+        DBuf LS, LL;
         LS.alloc(sizeof(double) * nc * nc);
         LL.alloc(sizeof(double) * nv * nv);
         qhp::launch_laplacians(s, a, LS.as<double>(), LL.as<double>());
         laplacian_pinv(c, nc, LS, c->LSp);
-        laplacian_pinv(c, nv, LL, LLp);
+        laplacian_pinv(c, nv, LL, c->LLp);
         c->PS.alloc(sizeof(double) * nn);
         c->PPL.alloc(sizeof(double) * nn);
         qhp::launch_proj(s, ne, a.cells, c->LSp.as<double>(), nc, c->PS.as<double>());
-        qhp::launch_proj(s, ne, a.edges, LLp.as<double>(), nv, c->PPL.as<double>());
+        qhp::launch_proj(s, ne, a.edges, c->LLp.as<double>(), nv, c->PPL.as<double>());
     }
     c->stage("projectors");
     // ---- Gram and Yukawa operators (Sec. II-C)
@@ -582,6 +500,7 @@ extern "C" int qhp_set_incident(qhp_ctx *ctx, const qhp_wave *waves, int32_t n_r
     if (ctx->state < 2) return guard(ctx, QHP_ESTATE, "assemble first");
     if (!waves || n_rhs < 1 || n_steps < 1) return guard(ctx, QHP_EINVAL, "bad waves / n_rhs / n_steps");
     if (ctx->p.precision == QHP_F32A && n_rhs != 1) return guard(ctx, QHP_EINVAL, "QHP_F32A takes one right-hand side");
+    if (ctx->p.solver == QHP_SOLVE_GMRES && n_rhs != 1) return guard(ctx, QHP_EINVAL, "GMRES takes one right-hand side");
     API_TRY
     qhp_ctx *c = ctx;
     hip_check(hipSetDevice(c->p.device), "hipSetDevice");
@@ -643,6 +562,7 @@ extern "C" int qhp_set_incident(qhp_ctx *ctx, const qhp_wave *waves, int32_t n_r
     autotune(c);
     c->step = 0;
     c->head = 0;
+    c->feat_n = 0;
     c->broken = false;
     c->state = 3;
     return QHP_OK;
@@ -670,7 +590,19 @@ static void do_step(qhp_ctx *c, double *j_out, double *y_out)
                         c->ring32.p ? c->ring32.p : c->ring64.p, K, c->head, r_i, c->bvec.as<double>(),
                         c->partial.p, c->nsplit, e0, e1, c->hv);
     double *y = c->yvec.as<double>();
-    if (c->p.solver == QHP_SOLVE_INV) {
+    if (c->p.solver == QHP_SOLVE_GMRES) {
+        qhp::warm_start(c, y);
+        int32_t it = 0;
+        float r0 = 0.f;
+        const bool ok = qhp::gmres_solve(c, c->bvec.as<double>(), y, &it, &r0);
+        c->gm_iters.push_back(it);
+        c->gm_res0.push_back(r0);
+        if (!ok) {  // the LU solve decides the step
+            c->gm_fallbacks += 1;
+            hip_check(hipMemcpyAsync(y, c->bvec.p, sizeof(double) * ne, hipMemcpyDeviceToDevice, s), "copy");
+            qhp::getrs_f64(s, false, ne, 1, c->LU0.as<double>(), ne, c->ipiv0.as<int32_t>(), y, 1);
+        }
+    } else if (c->p.solver == QHP_SOLVE_INV) {
         if (nr == 1) qhp::launch_gemv_f64(s, ne, c->Tinv.as<double>(), c->bvec.as<double>(), y);
         else qhp::gemm_f64(s, false, false, ne, nr, ne, 1.0, c->Tinv.as<double>(), ne, c->bvec.as<double>(), nr, 0.0, y, nr);
     } else if (nr == 1) {
@@ -697,6 +629,7 @@ static void do_step(qhp_ctx *c, double *j_out, double *y_out)
         qhp::launch_post_b(s, ne, nr, c->args.cells, y, c->zc.as<double>(), j_out);
     }
     qhp::launch_store_y(s, ne * nr, y, slot64, slot32, y_out, c->errflag.as<int>());
+    if (c->p.solver == QHP_SOLVE_GMRES) qhp::warm_record(c, y);
     c->head = slot;
     c->step = i;
 }
@@ -759,6 +692,7 @@ extern "C" int qhp_run(qhp_ctx *ctx, int32_t n_steps, double *j_hist, double *y_
 extern "C" int qhp_set_solver(qhp_ctx *ctx, int32_t solver)
 {
     if (!ctx) return QHP_EINVAL;
+    if (solver == QHP_SOLVE_GMRES) return qhp_set_gmres(ctx, ctx->gm_tol, ctx->gm_m, ctx->gm_refine, ctx->warm);
     if (solver != QHP_SOLVE_LU && solver != QHP_SOLVE_INV) return guard(ctx, QHP_EINVAL, "unknown solver");
     ctx->p.solver = solver;
     return QHP_OK;

@@ -1,0 +1,143 @@
+// Context of the C ABI shared by the library's host sources (not part of the
+// ABI): device buffers, error type and the state of one scatterer's march.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "assembly.h"
+#include "qhp_internal.h"
+
+namespace qhp {
+
+struct Fail {
+    int code;
+    std::string msg;
+};
+
+inline void hip_check(hipError_t e, const char *what)
+{
+    if (e != hipSuccess) throw Fail{e == hipErrorOutOfMemory ? QHP_ENOMEM : QHP_EDEVICE,
+                                    std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+// device allocation owned by a context
+struct DBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    void alloc(size_t n)
+    {
+        release();
+        if (n == 0) n = 8;
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            throw Fail{QHP_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed"};
+        }
+        bytes = n;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T>
+    T *as() const { return (T *)p; }
+    ~DBuf() { release(); }
+};
+
+template <class T>
+inline void upload(DBuf &b, const std::vector<T> &v, hipStream_t s)
+{
+    b.alloc(sizeof(T) * std::max<size_t>(v.size(), 1));
+    if (!v.empty()) hip_check(hipMemcpyAsync(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s), "upload");
+}
+
+inline void zero(DBuf &b, hipStream_t s) { hip_check(hipMemsetAsync(b.p, 0, b.bytes, s), "memset"); }
+
+}  // namespace qhp
+
+struct qhp_mlp;
+
+struct qhp_ctx {
+    qhp_params p{};
+    hipStream_t s = nullptr;
+    int state = 0;  // 0 created, 1 meshed, 2 assembled, 3 incident set
+    std::string err;
+    bool keep_raw = false;
+    qhp::Mesh mesh;
+    int64_t K = 0, ld = 0;
+    double T0 = 0, dtn = 0, kappa = 0;
+    // device tables
+    qhp::DBuf t_xyz, t_tri, t_edges, t_cells, t_tri_edge, t_tri_sign, t_area, t_valence, t_fxyz, t_ftri, t_fparent,
+        t_fowner, t_bc_off, t_bc_edge, t_bc_local, t_bc_flux, t_vcell_off, t_vcell_tri, t_vedge_off, t_vedge,
+        t_bct_off, t_bct_entry, t_bc_tri;
+    qhp::AsmArgs args{};
+    // assembled operators (FP64, row-major)
+    qhp::DBuf G, Zs, Zh, M, PS, PPL, Pcat, LSp;
+    qhp::DBuf slabs, scales_d, T0raw, LU0, ipiv0, perm0, Linv, Uinv, Tinv;
+    std::vector<float> scales;
+    std::vector<std::vector<double>> rawA, rawB, rawC;
+    // march state
+    int32_t nrhs = 0;
+    int64_t n_steps = 0, step = 0, head = 0;
+    bool broken = false;
+    qhp::DBuf waves_d, rhs, ring64, ring32, bvec, zvec, yvec, partial, sv, zc, flags, epoch, errflag;
+    int nsplit = 1;
+    int hv = -1;  // autotuned variant of the single right-hand-side history kernel
+    // profiling of the history kernel
+    bool profiling = false;
+    std::vector<hipEvent_t> ev;
+    double hist_ms = 0.0;
+    int64_t hist_launches = 0;
+    bool verbose = false;
+    std::chrono::steady_clock::time_point t_stage;
+    void stage(const char *name)
+    {
+        if (!verbose) return;
+        (void)hipStreamSynchronize(s);
+        auto now = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[qhp] %-28s %9.3f s\n", name, std::chrono::duration<double>(now - t_stage).count());
+        t_stage = now;
+    }
+    // iterative T_0 solve (GMRES, FP32 Arnoldi, FP64 refinement) and warm start
+    double gm_tol = 1e-10;
+    int gm_m = 40, gm_refine = 4, warm = 0;
+    qhp::DBuf T0f, gm_V, gm_w, gm_h1, gm_h2, gm_nrm, gm_R, gm_cs, gm_sn, gm_g, gm_inv, gm_y, gm_r, gm_x0;
+    double *gm_host = nullptr;  // pinned: residual estimate, |r|^2, |b|^2
+    std::vector<int32_t> gm_iters;
+    std::vector<float> gm_res0;
+    int64_t gm_refines = 0, gm_fallbacks = 0;
+    // loop/star/harmonic coordinates of the mesh (learned warm start)
+    qhp::DBuf LLp, Hb, ls_sig, ls_lam;
+    int64_t ls_nh = -1, ls_cap = 0;
+    qhp_mlp *mlp = nullptr;
+    qhp::DBuf feat;  // ring of the last four feature vectors [4][nf]
+    int64_t feat_n = 0;
+    ~qhp_ctx()
+    {
+        if (gm_host) (void)hipHostFree(gm_host);
+    }
+};
+
+// record msg as the context's last error and return code
+int guard(qhp_ctx *ctx, int code, const std::string &msg);
+
+namespace qhp {
+// loop/star/harmonic coordinates of the context's mesh (learned warm start)
+void loopstar_prepare(qhp_ctx *c);
+void loopstar_features(qhp_ctx *c, const double *Y, int64_t n, int64_t ldy, double *F, int64_t ldf);
+void loopstar_reconstruct(qhp_ctx *c, const double *F, int64_t n, int64_t ldf, double *Y, int64_t ldy);
+// iterative T_0 solve: buffers, start vector, solve, feature record
+void gmres_prepare(qhp_ctx *c);
+void warm_start(qhp_ctx *c, double *x0);
+bool gmres_solve(qhp_ctx *c, const double *b, double *x, int32_t *iters, float *res0);
+void warm_record(qhp_ctx *c, const double *y);
+}  // namespace qhp

@@ -1,0 +1,222 @@
+"""Learned warm start and iterative T_0 solve on the GPU against the oracle:
+loop/star coordinates, the perceptron's forward pass, gradient and Adam
+step, GMRES marches, and what the trained network gains over extrapolation."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _bf16(a):
+    """Round to the nearest BF16 (ties to even), returned as float64."""
+    a32 = np.ascontiguousarray(a, dtype=np.float32)
+    u = a32.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _solver(xyz, tri, dt, precision="f64"):
+    import paper_2312_06367_amd as qhp
+    s = qhp.Solver(dt, precision=precision, solver="lu")
+    s.mesh(xyz, tri)
+    s.assemble()
+    return s
+
+
+@pytest.fixture(scope="module", params=["sphere", "torus"])
+def mesh_case(request):
+    from workloads import meshes
+    if request.param == "sphere":
+        xyz, tri = meshes.icosphere(1)
+    else:
+        xyz, tri = meshes.torus(1.0, 0.4, 10, 5)
+    return request.param, xyz, tri
+
+
+def test_loopstar_coordinates(mesh_case):
+    """l and s equal the oracle's; the harmonic part agrees through H h
+    (the basis is fixed only up to a rotation); reconstruction is exact."""
+    import paper_2312_06367_amd as qhp
+    from oracle import learned as Lr
+    from oracle.topology import Topology
+    name, xyz, tri = mesh_case
+    s = _solver(xyz, tri, 0.2)
+    m = qhp.MLP(s, hidden=16, seed=1)
+    ls = Lr.LoopStar(Topology(xyz, tri))
+    assert m.nf == ls.nf
+    rng = np.random.default_rng(11)
+    Y = rng.standard_normal((7, ls.topo.ne))
+    Yd = torch.from_numpy(Y).cuda()
+    F = m.features(Yd).cpu().numpy()
+    Fo = ls.features(Y)
+    nv, nc = ls.nv, ls.nc
+    e_ls = float(np.abs(F[:, :nv + nc] - Fo[:, :nv + nc]).max() / np.abs(Fo).max())
+    Hh = lambda G: np.concatenate([np.zeros((G.shape[0], nv + nc)), G[:, nv + nc:]], axis=1)
+    h_gpu = m.reconstruct(torch.from_numpy(Hh(F)).cuda()).cpu().numpy()
+    e_h = float(np.abs(h_gpu - ls.reconstruct(Hh(Fo))).max() / np.abs(Y).max())
+    e_rt = float(np.abs(m.reconstruct(torch.from_numpy(F).cuda()).cpu().numpy() - Y).max() / np.abs(Y).max())
+    one = m.features(Yd[:1].contiguous()).cpu().numpy()  # single-vector path
+    e_one = float(np.abs(one - F[:1]).max() / np.abs(F).max())
+    _say("[loopstar %s] l,s err %.2e  H h err %.2e  round trip %.2e  single %.2e" % (name, e_ls, e_h, e_rt, e_one))
+    m.close()
+    s.close()
+    assert max(e_ls, e_h, e_rt, e_one) < 1e-11
+
+
+def _oracle_params(m, flat):
+    """The oracle's parameters as the GPU uses them: BF16 weights, FP32 biases."""
+    p = {k: v.astype(np.float64) for k, v in m.unpack(flat).items()}
+    for k in ("W1", "W2", "W3"):
+        p[k] = _bf16(p[k])
+    return p
+
+
+@pytest.mark.parametrize("hidden,batch", [(256, 70), (40, 129)])
+def test_perceptron_forward_gradient_adam(hidden, batch):
+    """Forward output, loss and every gradient block against the FP64 oracle
+    evaluated with the same BF16 weights and inputs.  Bound: each product
+    rounds its FP32 operands (activations, back-propagated errors) to BF16,
+    unit roundoff 2^-9; an output passes through up to three such roundings
+    and a gradient through up to four, so relative errors of a few 2^-9 are
+    expected: forward 1e-2, gradients 3e-2.  Adam is then checked on the
+    GPU's own gradient to FP32 accuracy over two steps."""
+    import paper_2312_06367_amd as qhp
+    from oracle import learned as Lr
+    from workloads import meshes
+    xyz, tri = meshes.icosphere(1)
+    s = _solver(xyz, tri, 0.2)
+    m = qhp.MLP(s, hidden=hidden, seed=3)
+    rng = np.random.default_rng(5)
+    p0 = Lr.init_params(m.n_in, hidden, m.nf, rng, out_scale=1.0)
+    for k in ("b1", "b2", "b3"):
+        p0[k] = 0.1 * rng.standard_normal(p0[k].shape)
+    flat = m.pack(p0)
+    m.set_params(flat)
+    X = rng.standard_normal((batch, m.n_in)).astype(np.float32)
+    T = rng.standard_normal((batch, m.nf)).astype(np.float32)
+    Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    po = _oracle_params(m, flat)
+    o_ref, _ = Lr.forward(po, _bf16(X))
+    o_gpu = m.forward(Xd).cpu().numpy()
+    e_fwd = float(np.linalg.norm(o_gpu - o_ref) / np.linalg.norm(o_ref))
+    loss, g = m.loss_grad(Xd, Td)
+    loss_ref, g_ref = Lr.loss_grad(po, _bf16(X), T.astype(np.float64))
+    gg = m.unpack(g)
+    errs = {k: float(np.linalg.norm(gg[k] - g_ref[k]) / np.linalg.norm(g_ref[k])) for k in g_ref}
+    _say("[mlp h=%d B=%d] forward %.2e loss %.3e vs %.3e grads %s" % (
+        hidden, batch, e_fwd, loss, loss_ref, " ".join("%s %.1e" % kv for kv in errs.items())))
+    assert e_fwd < 1e-2
+    assert abs(loss - loss_ref) < 1e-2 * loss_ref
+    assert max(errs.values()) < 3e-2
+    # Adam: two steps, each on the gradient the GPU computed
+    mo = {k: np.zeros_like(v) for k, v in m.unpack(flat.astype(np.float64)).items()}
+    vo = {k: np.zeros_like(v) for k, v in mo.items()}
+    pe = {k: v.copy() for k, v in m.unpack(flat.astype(np.float64)).items()}
+    for t in (1, 2):
+        if t == 2:
+            _, g = m.loss_grad(Xd, Td)
+        Lr.adam_step(pe, {k: v.astype(np.float64) for k, v in m.unpack(g).items()}, mo, vo, t, lr=1e-3)
+        m.adam(1e-3)
+        got = m.unpack(m.get_params())
+        worst = max(float(np.abs(got[k] - pe[k]).max() / 1e-3) for k in pe)
+        _say("[mlp adam step %d] max |dw| / lr = %.2e" % (t, worst))
+        assert worst < 1e-3
+        pe = {k: got[k].astype(np.float64) for k in got}  # continue from the GPU state
+    m.close()
+    s.close()
+
+
+def _march_gmres(xyz, tri, dt, wave, n, warm, precision="f64"):
+    s = _solver(xyz, tri, dt, precision)
+    s.set_gmres(1e-10, 40, 4, warm)
+    ne = s.info()["ne"]
+    s.set_incident([wave], n)
+    jh = torch.zeros((n, ne, 1), dtype=torch.float64, device="cuda")
+    s.run(n, jh)
+    st = s.gmres_stats(n)
+    s.close()
+    return jh[:, :, 0].cpu().numpy(), st
+
+
+def test_gmres_march_parity():
+    """The 120-edge sphere (c dt = 0.15 m, 300 steps) with GMRES solves of
+    relative residual 1e-10 against the oracle's LU march; every start vector
+    gives the same march, and warm starts use fewer iterations than cold."""
+    from oracle import excitation as E, mot, operators as O
+    from workloads import meshes, waves
+    xyz, tri = meshes.icosphere(1)
+    dt, n = 0.15, 300
+    asm = O.Assembly(xyz, tri, dt)
+    asm.build()
+    w = waves.Wave((0.0, 0.0, -1.0), (1.0, 0.0, 0.0), 1.0, waves.mod_gauss_t0(0.1, asm.D), 0, 0.0, 0.1, 0.1)
+    jref = mot.currents(asm.proj.PLH, asm.proj.PS, asm.dtn, mot.march(asm.T, E.rhs(asm, w, n)))
+    its = {}
+    for warm in ("cold", "prev", "extrap"):
+        j, st = _march_gmres(xyz, tri, dt, w, n, warm)
+        err = float(np.linalg.norm(j - jref, axis=1).max() / np.linalg.norm(jref, axis=1).max())
+        its[warm] = st["iterations"]
+        _say("[gmres %s] current err %.2e; iterations %d (max %d per step), inner solves %d, fallbacks %d" % (
+            warm, err, st["iterations"], st["max_iterations"], st["refinements"], st["fallbacks"]))
+        assert err < 1e-8 and st["fallbacks"] == 0 and st["steps"] == n
+    assert its["extrap"] < its["cold"] and its["prev"] < its["cold"]
+
+
+def test_warm_start_training_gain():
+    """Train the perceptron on GPU marches of 24 seeded directions (480-edge
+    sphere, 400 steps), then march 4 held-out directions: its start vectors
+    have smaller residuals than linear extrapolation and GMRES needs fewer
+    iterations; the marches agree with the LU march."""
+    import paper_2312_06367_amd as qhp
+    from workloads import waves
+    cfg = waves.sphere_small()
+    xyz, tri = cfg.mesh
+    n = cfg.n_steps
+    f0 = bw = waves.hz_to_per_m(50e6)
+    train = waves.batched_waves(24, 0, f0, bw, 2.0, both_pols=False)
+    held = waves.batched_waves(4, 1, f0, bw, 2.0, both_pols=False)
+    s = _solver(xyz, tri, cfg.dt)
+    s.set_solver("inv")
+    ne = s.info()["ne"]
+    s.set_incident(train, n)
+    yh = torch.zeros((n, ne, len(train)), dtype=torch.float64, device="cuda")
+    s.run(n, None, yh)
+    m = qhp.MLP(s, hidden=256, seed=0)
+    losses = m.train(yh, epochs=40, batch=256, lr=1e-3, seed=0)
+    _say("[warm train] loss first %.3e last %.3e" % (losses[0], losses[-1]))
+    assert losses[-1] < 0.5 * losses[0]
+    s.attach_mlp(m)
+    res = {}
+    for w in held:
+        s.set_solver("inv")
+        s.set_incident([w], n)
+        jl = torch.zeros((n, ne, 1), dtype=torch.float64, device="cuda")
+        s.run(n, jl)
+        for warm in ("extrap", "mlp"):
+            s.set_gmres(1e-10, 40, 4, warm)
+            s.gmres_reset()
+            s.set_incident([w], n)
+            jg = torch.zeros((n, ne, 1), dtype=torch.float64, device="cuda")
+            s.run(n, jg)
+            st = s.gmres_stats(n)
+            err = float((jg - jl).abs().max() / jl.abs().max())
+            assert err < 1e-8 and st["fallbacks"] == 0
+            r = res.setdefault(warm, {"it": 0, "r0": []})
+            r["it"] += st["iterations"]
+            r["r0"].append(st["res0"][8:])
+    for warm, r in res.items():
+        r["med"] = float(np.median(np.concatenate(r["r0"])))
+        _say("[warm %s] held-out iterations %d, median start residual %.2e" % (warm, r["it"], r["med"]))
+    s.attach_mlp(None)
+    m.close()
+    s.close()
+    assert res["mlp"]["med"] < res["extrap"]["med"]
+    assert res["mlp"]["it"] <= res["extrap"]["it"]
