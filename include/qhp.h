@@ -69,7 +69,8 @@ enum {
     QHP_WARM_COLD = 0,   /* zero                                               */
     QHP_WARM_PREV = 1,   /* y_{i-1}                                            */
     QHP_WARM_EXTRAP = 2, /* 2 y_{i-1} - y_{i-2}                                */
-    QHP_WARM_MLP = 3     /* the attached perceptron's guess from y_{i-1..i-4}  */
+    QHP_WARM_QUAD = 3,   /* 3 y_{i-1} - 3 y_{i-2} + y_{i-3}                    */
+    QHP_WARM_MLP = 4     /* the attached perceptron's guess from y_{i-1..i-4}  */
 };
 
 typedef struct qhp_ctx qhp_ctx;
@@ -251,10 +252,13 @@ int qhp_gmres_reset(qhp_ctx *ctx);
  * f = [l (N_V) | s (N_C) | h (N_H)] with s = (Sigma^T Sigma)^+ Sigma^T y,
  * l = (Lambda^T Lambda)^+ Lambda^T y and h = H^T y, H an orthonormal basis of
  * the harmonic space (built once from the context's projectors; unique up to
- * a rotation); N_F = N_V + N_C + N_H = N_E + 2.  Network, N_in = 4 N_F:
- *   x = [f_{i-1}, f_{i-2}, f_{i-3}, f_{i-4}] / sigma, sigma = rms(f_{i-1}),
+ * a rotation); N_F = N_V + N_C + N_H = N_E + 2.  Network, N_in = 4 N_F, on
+ * the backward differences d0 = f_{i-1}, d1 = f_{i-1} - f_{i-2},
+ * d2 = f_{i-1} - 2 f_{i-2} + f_{i-3}, d3 = f_{i-1} - 3 f_{i-2} + 3 f_{i-3} - f_{i-4}:
+ *   x = [d0 / rms(d0), d1 / rms(d1), d2 / rms(d2), d3 / rms(d3)] (0 / 0 = 0),
  *   a1 = tanh(W1 x + b1), a2 = tanh(W2 a1 + b2), o = W3 a2 + b3,
- *   guess f_i = 2 f_{i-1} - f_{i-2} + sigma o.
+ *   guess f_i = 3 f_{i-1} - 3 f_{i-2} + f_{i-3} + rms(d3) o
+ * (o = 0 is quadratic extrapolation).
  * Weights are used as BF16 (products on the matrix cores, FP32 sums), biases
  * and the master copy of every parameter are FP32.  Parameter vector layout
  * (FP32): W1 [H][N_in], b1 [H], W2 [H][H], b2 [H], W3 [N_F][H], b3 [N_F].
@@ -277,11 +281,14 @@ int qhp_gmres_reset(qhp_ctx *ctx);
  * qhp_mlp_adam: one Adam step (bias-corrected) with the kept gradient.
  * qhp_mlp_train: features of device y [n_steps][N_E][n_runs] FP64 (the
  *   y_hist layout of qhp_run with n_runs right-hand sides), then `epochs`
- *   passes over every window (run, i >= 4) in an order shuffled from seed,
- *   minibatches of `batch`, Adam (lr, 0.9, 0.999, 1e-8) with targets
- *   t = (f_i - 2 f_{i-1} + f_{i-2}) / sigma; host epoch_loss[epochs] (may be
+ *   passes over every window (run, i >= 4) with rms(d3) > 0, in an order
+ *   shuffled from seed, minibatches of `batch`, Adam (lr, 0.9, 0.999, 1e-8)
+ *   with targets t = (f_i - 3 f_{i-1} + 3 f_{i-2} - f_{i-3}) / rms(d3);
+ *   host epoch_loss[epochs] (may be
  *   NULL) receives each pass's mean minibatch loss.  Device memory:
  *   8 n_steps n_runs N_F bytes of features for the call.
+ * qhp_mlp_guess: device f [4][N_F] (rows f_{i-1}, f_{i-2}, f_{i-3}, f_{i-4})
+ *   -> device g [N_F], the guess of f_i.
  * qhp_attach_mlp: use m (NULL: none) for QHP_WARM_MLP on ctx.
  * qhp_mlp_destroy: frees m (detaching it from its context). */
 typedef struct qhp_mlp qhp_mlp;
@@ -290,6 +297,7 @@ int qhp_mlp_dims(const qhp_mlp *m, int64_t *n_features, int64_t *n_params, int64
 int qhp_mlp_set_params(qhp_mlp *m, const float *params);
 int qhp_mlp_get_params(const qhp_mlp *m, float *params);
 int qhp_mlp_features(qhp_mlp *m, const double *y, int64_t n, double *f);
+int qhp_mlp_guess(qhp_mlp *m, const double *f, double *g);
 int qhp_mlp_reconstruct(qhp_mlp *m, const double *f, int64_t n, double *y);
 int qhp_mlp_forward(qhp_mlp *m, const float *x, int32_t batch, float *out);
 int qhp_mlp_loss_grad(qhp_mlp *m, const float *x, const float *t, int32_t batch, double *loss, float *grad);

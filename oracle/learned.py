@@ -15,13 +15,16 @@ Readings fixed here, identically on the GPU side:
     P^H = I - P^Sigma - P^Lambda (N_H = 2 x genus columns).  H is fixed only up
     to a rotation, so comparisons go through H h = P^H y;
   * feature vector f = [l (N_V), s (N_C), h (N_H)], N_V + N_C + N_H = N_E + 2.
-Network (a 3-layer perceptron, tanh hidden units):
-  x = [f_{i-1}, f_{i-2}, f_{i-3}, f_{i-4}] / sigma,  sigma = rms(f_{i-1}),
+Network (a 3-layer perceptron, tanh hidden units) on backward differences
+of the features, each block scaled by its own rms:
+  d0 = f_{i-1}, d1 = d0 - f_{i-2}, d2 = d1 - (f_{i-2} - f_{i-3}),
+  d3 = f_{i-1} - 3 f_{i-2} + 3 f_{i-3} - f_{i-4},  rho_j = rms(d_j),
+  x = [d0 / rho0, d1 / rho1, d2 / rho2, d3 / rho3]   (a zero block stays 0),
   a1 = tanh(W1 x + b1),  a2 = tanh(W2 a1 + b2),  o = W3 a2 + b3,
-  guess  f_i ~ 2 f_{i-1} - f_{i-2} + sigma o   (a correction to linear
-  extrapolation; o = 0 is plain extrapolation),
+  guess  f_i ~ 3 f_{i-1} - 3 f_{i-2} + f_{i-3} + rho3 o   (a correction to
+  quadratic extrapolation; o = 0 is plain quadratic extrapolation),
   loss = mean over samples and outputs of (o - t)^2 with
-  t = (f_i - 2 f_{i-1} + f_{i-2}) / sigma.
+  t = (f_i - 3 f_{i-1} + 3 f_{i-2} - f_{i-3}) / rho3.
 Optimiser: Adam with bias correction (Kingma and Ba, ICLR 2015).
 """
 from __future__ import annotations
@@ -62,20 +65,25 @@ class LoopStar:
 
 
 # ------------------------------------------------------------ training windows
+def _rms(v: np.ndarray) -> float:
+    return float(np.sqrt(np.mean(v * v)))
+
+
 def window(F: np.ndarray, i: int):
-    """Sample for step i (0-based row of F, i >= 4): x, t, sigma."""
-    prev = F[i - 1]
-    sigma = float(np.sqrt(np.mean(prev * prev)))
-    x = np.concatenate([F[i - 1], F[i - 2], F[i - 3], F[i - 4]]) / sigma
-    t = (F[i] - 2.0 * F[i - 1] + F[i - 2]) / sigma
-    return x, t, sigma
+    """Sample for step i (0-based row of F, i >= 4): x, t, rho3."""
+    f1, f2, f3, f4 = F[i - 1], F[i - 2], F[i - 3], F[i - 4]
+    d = [f1, f1 - f2, f1 - 2.0 * f2 + f3, f1 - 3.0 * f2 + 3.0 * f3 - f4]
+    rho = [_rms(v) for v in d]
+    x = np.concatenate([v / r if r > 0.0 else np.zeros_like(v) for v, r in zip(d, rho)])
+    t = (F[i] - 3.0 * f1 + 3.0 * f2 - f3) / rho[3]
+    return x, t, rho[3]
 
 
 def guess(params, F: np.ndarray, i: int) -> np.ndarray:
     """Warm-start guess of the features of step i from rows i-1..i-4."""
-    x, _, sigma = window(F, i)
+    x, _, rho3 = window(F, i)
     o = forward(params, x[None, :])[0][0]
-    return 2.0 * F[i - 1] - F[i - 2] + sigma * o
+    return 3.0 * F[i - 1] - 3.0 * F[i - 2] + F[i - 3] + rho3 * o
 
 
 # ------------------------------------------------------------ network

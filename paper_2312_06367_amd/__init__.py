@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libqhp.so")
 
 QHP_F64, QHP_F32, QHP_BF16, QHP_F32A = 0, 1, 2, 3
 QHP_SOLVE_LU, QHP_SOLVE_INV, QHP_SOLVE_GMRES = 0, 1, 2
-WARM = {"cold": 0, "prev": 1, "extrap": 2, "mlp": 3}
+WARM = {"cold": 0, "prev": 1, "extrap": 2, "quad": 3, "mlp": 4}
 MAT = {"gram": 0, "zs": 1, "zh": 2, "m": 3, "psigma": 4, "plambda": 5, "pe": 6, "pm": 7,
        "slab": 8, "a": 9, "b": 10, "c": 11}
 ERRORS = {0: "OK", -1: "EINVAL", -2: "EMESH", -3: "ESTATE", -4: "ENOMEM", -5: "EDEVICE",
@@ -62,7 +62,7 @@ EXPORTS = ["qhp_create", "qhp_mesh", "qhp_assemble", "qhp_set_precision", "qhp_s
            "qhp_get_matrix", "qhp_keep_raw", "qhp_history_sum", "qhp_batch_create", "qhp_batch_run",
            "qhp_batch_step_times", "qhp_batch_last_error", "qhp_batch_destroy", "qhp_last_error",
            "qhp_destroy", "qhp_set_gmres", "qhp_gmres_stats", "qhp_gmres_reset", "qhp_mlp_create",
-           "qhp_mlp_dims", "qhp_mlp_set_params", "qhp_mlp_get_params", "qhp_mlp_features", "qhp_mlp_reconstruct",
+           "qhp_mlp_dims", "qhp_mlp_set_params", "qhp_mlp_get_params", "qhp_mlp_features", "qhp_mlp_guess", "qhp_mlp_reconstruct",
            "qhp_mlp_forward", "qhp_mlp_loss_grad", "qhp_mlp_adam", "qhp_mlp_train", "qhp_attach_mlp",
            "qhp_mlp_last_error", "qhp_mlp_destroy"]
 _NO_RC = ("qhp_last_error", "qhp_destroy", "qhp_batch_last_error", "qhp_batch_destroy", "qhp_mlp_last_error",
@@ -115,6 +115,7 @@ def lib():
         L.qhp_mlp_set_params.argtypes = [vp, vp]
         L.qhp_mlp_get_params.argtypes = [vp, vp]
         L.qhp_mlp_features.argtypes = [vp, vp, i64, vp]
+        L.qhp_mlp_guess.argtypes = [vp, vp, vp]
         L.qhp_mlp_reconstruct.argtypes = [vp, vp, i64, vp]
         L.qhp_mlp_forward.argtypes = [vp, vp, i32, vp]
         L.qhp_mlp_loss_grad.argtypes = [vp, vp, vp, i32, ctypes.POINTER(dbl), vp]
@@ -367,6 +368,13 @@ class MLP:
         f = torch.empty((y.shape[0], self.nf), dtype=torch.float64, device=y.device)
         self._check(self.L.qhp_mlp_features(self.h, _ptr(y), y.shape[0], _ptr(f)))
         return f
+
+    def guess(self, f4):
+        """f4: device float64 [4, nf] (f_{i-1} .. f_{i-4}) -> guess of f_i."""
+        import torch
+        g = torch.empty((self.nf,), dtype=torch.float64, device=f4.device)
+        self._check(self.L.qhp_mlp_guess(self.h, _ptr(f4), _ptr(g)))
+        return g
 
     def reconstruct(self, f):
         import torch

@@ -51,17 +51,20 @@ void launch_init_uniform(hipStream_t s, int64_t count, float a, uint64_t seed, u
 // per-row rms of F [n][nf] (FP64)
 void launch_rms(hipStream_t s, int64_t n, int64_t nf, const double *F, double *sigma);
 // training windows.  Sample b: rows r0 = base[b] of F (stride nf) with
-// f_{i-1} at r0, f_{i-2} at r0 - step, ...; f_i at r0 + step.
-//   X[b] = BF16([f_{i-1}, f_{i-2}, f_{i-3}, f_{i-4}] / sigma), sigma = rms(f_{i-1})
-//   T[b] = (f_i - 2 f_{i-1} + f_{i-2}) / sigma (FP32)
+// f_{i-1} at r0, f_{i-2} at r0 - step, ...; f_i at r0 + step.  With the
+// backward differences d0 = f_{i-1}, d1, d2, d3 of f_{i-1..i-4}:
+//   X[b] = BF16([d0 / rms(d0), d1 / rms(d1), d2 / rms(d2), d3 / rms(d3)])
+//   T[b] = (f_i - 3 f_{i-1} + 3 f_{i-2} - f_{i-3}) / rms(d3) (FP32)
 void launch_gather_windows(hipStream_t s, int64_t B, int64_t nf, const double *F, int64_t step,
                            const int64_t *base, uint16_t *X, float *T);
-// one inference window from four feature vectors (FP64): X (BF16), sigma (device)
+// rms(d3) of the window ending at each of `rows` rows (0 for rows < 3 step)
+void launch_rms_d3(hipStream_t s, int64_t rows, int64_t nf, const double *F, int64_t step, double *out);
+// one inference window from f1 = f_{i-1} .. f4 = f_{i-4}: X (BF16), rms(d3) (device)
 void launch_window_x(hipStream_t s, int64_t nf, const double *f1, const double *f2, const double *f3,
-                     const double *f4, uint16_t *X, double *sigma);
-// guess of the next feature vector: g = 2 f1 - f2 + sigma o
-void launch_guess(hipStream_t s, int64_t nf, const double *f1, const double *f2, const double *sigma,
-                  const float *o, double *g);
+                     const double *f4, uint16_t *X, double *rho3);
+// guess of the next feature vector: g = 3 f1 - 3 f2 + f3 + rho3 o
+void launch_guess(hipStream_t s, int64_t nf, const double *f1, const double *f2, const double *f3,
+                  const double *rho3, const float *o, double *g);
 
 // ---- iterative solve of T_0 (GMRES, FP32 Arnoldi, FP64 refinement)
 // w = A v, A FP32 [n][lda], v and w FP32

@@ -349,23 +349,47 @@ void launch_rms(hipStream_t s, int64_t n, int64_t nf, const double *F, double *s
     if (n > 0) hipLaunchKernelGGL(k_rms, dim3((unsigned)n), dim3(256), 0, s, n, nf, F, sigma);
 }
 
-__global__ void k_gather_windows(int64_t nf, const double *F, int64_t step, const int64_t *base, uint16_t *X, float *T)
+// Backward differences of four consecutive feature rows f1 (newest) .. f4:
+// d0 = f1, d1 = f1 - f2, d2 = f1 - 2 f2 + f3, d3 = f1 - 3 f2 + 3 f3 - f4,
+// written as BF16(d_j / rms(d_j)) (a zero block stays 0); returns rms(d3).
+__device__ double window_blocks(int64_t nf, const double *f1, const double *f2, const double *f3, const double *f4,
+                                uint16_t *x)
 {
     __shared__ double sh[4];
-    const int64_t b = blockIdx.x;
-    const double *f1 = F + base[b] * nf;
-    double acc = 0.0;
-    for (int64_t q = threadIdx.x; q < nf; q += blockDim.x) acc += f1[q] * f1[q];
-    acc = block_sum(acc, sh);
-    const double inv = acc > 0.0 ? 1.0 / sqrt(acc / (double)nf) : 0.0;
-    uint16_t *x = X + b * 4 * nf;
-    for (int j = 0; j < 4; ++j) {
-        const double *fj = f1 - (int64_t)j * step * nf;
-        for (int64_t q = threadIdx.x; q < nf; q += blockDim.x) x[j * nf + q] = f2bf((float)(fj[q] * inv));
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int64_t q = threadIdx.x; q < nf; q += blockDim.x) {
+        const double a = f1[q], b = f2[q], c = f3[q], d = f4[q];
+        const double d1 = a - b, d2 = a - 2.0 * b + c, d3 = a - 3.0 * b + 3.0 * c - d;
+        s0 += a * a;
+        s1 += d1 * d1;
+        s2 += d2 * d2;
+        s3 += d3 * d3;
     }
-    const double *f0 = f1 + step * nf, *f2 = f1 - step * nf;
+    double r[4] = {block_sum(s0, sh), block_sum(s1, sh), block_sum(s2, sh), block_sum(s3, sh)};
+    double inv[4];
+    for (int j = 0; j < 4; ++j) {
+        r[j] = sqrt(r[j] / (double)nf);
+        inv[j] = r[j] > 0.0 ? 1.0 / r[j] : 0.0;
+    }
+    for (int64_t q = threadIdx.x; q < nf; q += blockDim.x) {
+        const double a = f1[q], b = f2[q], c = f3[q], d = f4[q];
+        x[q] = f2bf((float)(a * inv[0]));
+        x[nf + q] = f2bf((float)((a - b) * inv[1]));
+        x[2 * nf + q] = f2bf((float)((a - 2.0 * b + c) * inv[2]));
+        x[3 * nf + q] = f2bf((float)((a - 3.0 * b + 3.0 * c - d) * inv[3]));
+    }
+    return r[3];
+}
+
+__global__ void k_gather_windows(int64_t nf, const double *F, int64_t step, const int64_t *base, uint16_t *X, float *T)
+{
+    const int64_t b = blockIdx.x;
+    const double *f1 = F + base[b] * nf, *f2 = f1 - step * nf, *f3 = f2 - step * nf, *f4 = f3 - step * nf;
+    const double *f0 = f1 + step * nf;
+    const double rho3 = window_blocks(nf, f1, f2, f3, f4, X + b * 4 * nf);
+    const double inv = rho3 > 0.0 ? 1.0 / rho3 : 0.0;
     for (int64_t q = threadIdx.x; q < nf; q += blockDim.x)
-        T[b * nf + q] = (float)((f0[q] - 2.0 * f1[q] + f2[q]) * inv);
+        T[b * nf + q] = (float)((f0[q] - 3.0 * f1[q] + 3.0 * f2[q] - f3[q]) * inv);
 }
 void launch_gather_windows(hipStream_t s, int64_t B, int64_t nf, const double *F, int64_t step,
                            const int64_t *base, uint16_t *X, float *T)
@@ -373,35 +397,51 @@ void launch_gather_windows(hipStream_t s, int64_t B, int64_t nf, const double *F
     if (B > 0) hipLaunchKernelGGL(k_gather_windows, dim3((unsigned)B), dim3(256), 0, s, nf, F, step, base, X, T);
 }
 
-__global__ void k_window_x(int64_t nf, const double *f1, const double *f2, const double *f3, const double *f4,
-                           uint16_t *X, double *sigma)
+// rms of the third backward difference ending at each row (0 for rows < 3 step)
+__global__ void k_rms_d3(int64_t nf, const double *F, int64_t step, double *out)
 {
     __shared__ double sh[4];
+    const int64_t r = blockIdx.x;
+    if (r < 3 * step) {
+        if (threadIdx.x == 0) out[r] = 0.0;
+        return;
+    }
+    const double *f1 = F + r * nf, *f2 = f1 - step * nf, *f3 = f2 - step * nf, *f4 = f3 - step * nf;
     double acc = 0.0;
-    for (int64_t q = threadIdx.x; q < nf; q += blockDim.x) acc += f1[q] * f1[q];
+    for (int64_t q = threadIdx.x; q < nf; q += blockDim.x) {
+        const double d3 = f1[q] - 3.0 * f2[q] + 3.0 * f3[q] - f4[q];
+        acc += d3 * d3;
+    }
     acc = block_sum(acc, sh);
-    const double sg = sqrt(acc / (double)nf);
-    const double inv = sg > 0.0 ? 1.0 / sg : 0.0;
-    if (threadIdx.x == 0) *sigma = sg;
-    const double *fs[4] = {f1, f2, f3, f4};
-    for (int j = 0; j < 4; ++j)
-        for (int64_t q = threadIdx.x; q < nf; q += blockDim.x) X[j * nf + q] = f2bf((float)(fs[j][q] * inv));
+    if (threadIdx.x == 0) out[r] = sqrt(acc / (double)nf);
 }
-void launch_window_x(hipStream_t s, int64_t nf, const double *f1, const double *f2, const double *f3,
-                     const double *f4, uint16_t *X, double *sigma)
+void launch_rms_d3(hipStream_t s, int64_t rows, int64_t nf, const double *F, int64_t step, double *out)
 {
-    hipLaunchKernelGGL(k_window_x, dim3(1), dim3(256), 0, s, nf, f1, f2, f3, f4, X, sigma);
+    if (rows > 0) hipLaunchKernelGGL(k_rms_d3, dim3((unsigned)rows), dim3(256), 0, s, nf, F, step, out);
 }
 
-__global__ void k_guess(int64_t nf, const double *f1, const double *f2, const double *sigma, const float *o, double *g)
+__global__ void k_window_x(int64_t nf, const double *f1, const double *f2, const double *f3, const double *f4,
+                           uint16_t *X, double *rho3)
+{
+    const double r = window_blocks(nf, f1, f2, f3, f4, X);
+    if (threadIdx.x == 0) *rho3 = r;
+}
+void launch_window_x(hipStream_t s, int64_t nf, const double *f1, const double *f2, const double *f3,
+                     const double *f4, uint16_t *X, double *rho3)
+{
+    hipLaunchKernelGGL(k_window_x, dim3(1), dim3(256), 0, s, nf, f1, f2, f3, f4, X, rho3);
+}
+
+__global__ void k_guess(int64_t nf, const double *f1, const double *f2, const double *f3, const double *rho3,
+                        const float *o, double *g)
 {
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < nf) g[q] = 2.0 * f1[q] - f2[q] + *sigma * (double)o[q];
+    if (q < nf) g[q] = 3.0 * f1[q] - 3.0 * f2[q] + f3[q] + *rho3 * (double)o[q];
 }
-void launch_guess(hipStream_t s, int64_t nf, const double *f1, const double *f2, const double *sigma,
-                  const float *o, double *g)
+void launch_guess(hipStream_t s, int64_t nf, const double *f1, const double *f2, const double *f3,
+                  const double *rho3, const float *o, double *g)
 {
-    hipLaunchKernelGGL(k_guess, dim3(nblk(nf, 256)), dim3(256), 0, s, nf, f1, f2, sigma, o, g);
+    hipLaunchKernelGGL(k_guess, dim3(nblk(nf, 256)), dim3(256), 0, s, nf, f1, f2, f3, rho3, o, g);
 }
 
 }  // namespace qhp

@@ -216,6 +216,15 @@ static void mlp_adam(qhp_mlp *m, double lr, double b1, double b2, double eps)
                      (float)lr_t, (float)b1, (float)b2, (float)(eps * c2), m->Pb.as<uint16_t>());
 }
 
+// guess of f_i from f1 = f_{i-1} .. f4 = f_{i-4} (device FP64) into g
+static void mlp_guess(qhp_mlp *m, const double *f1, const double *f2, const double *f3, const double *f4, double *g)
+{
+    hipStream_t s = m->s;
+    qhp::launch_window_x(s, m->nf, f1, f2, f3, f4, m->X.as<uint16_t>(), m->sig.as<double>());
+    mlp_forward(m, 1, qhp::MT_BF16, m->X.p);
+    qhp::launch_guess(s, m->nf, f1, f2, f3, m->sig.as<double>(), m->O.as<float>(), g);
+}
+
 extern "C" int qhp_mlp_create(qhp_ctx *ctx, int32_t hidden, uint64_t seed, qhp_mlp **out)
 {
     if (!ctx || !out || hidden < 1) return QHP_EINVAL;
@@ -352,6 +361,19 @@ extern "C" int qhp_mlp_adam(qhp_mlp *m, double lr, double beta1, double beta2, d
     return hipStreamSynchronize(m->s) == hipSuccess ? QHP_OK : QHP_EDEVICE;
 }
 
+extern "C" int qhp_mlp_guess(qhp_mlp *m, const double *f, double *g)
+{
+    if (!m || !f || !g) return QHP_EINVAL;
+    try {
+        const int64_t nf = m->nf;
+        mlp_guess(m, f, f + nf, f + 2 * nf, f + 3 * nf, g);
+        hip_check(hipStreamSynchronize(m->s), "guess");
+    } catch (const Fail &e) {
+        return mguard(m, e.code, e.msg);
+    }
+    return QHP_OK;
+}
+
 extern "C" int qhp_mlp_features(qhp_mlp *m, const double *y, int64_t n, double *f)
 {
     if (!m || !y || !f || n < 1) return QHP_EINVAL;
@@ -397,11 +419,12 @@ extern "C" int qhp_mlp_train(qhp_mlp *m, const double *y, int64_t n_runs, int64_
             qhp::loopstar_features(c, Yt.as<double>(), nt * n_runs, ne, F.as<double>() + t0 * n_runs * nf, nf);
         }
         sig.alloc(sizeof(double) * n_steps * n_runs);
-        qhp::launch_rms(s, n_steps * n_runs, nf, F.as<double>(), sig.as<double>());
+        qhp::launch_rms_d3(s, n_steps * n_runs, nf, F.as<double>(), n_runs, sig.as<double>());
         std::vector<double> hs(n_steps * n_runs);
         hip_check(hipMemcpyAsync(hs.data(), sig.p, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, s), "rms");
         hip_check(hipStreamSynchronize(s), "rms");
-        // sample (run, i): target step i >= 4 (0-based), window rows i-1..i-4
+        // sample (run, i): target step i >= 4 (0-based), window rows i-1..i-4,
+        // kept when the third difference of the window is not zero
         std::vector<int64_t> samples;
         for (int64_t i = 4; i < n_steps; ++i)
             for (int64_t r = 0; r < n_runs; ++r) {
@@ -497,8 +520,10 @@ void warm_start(qhp_ctx *c, double *x0)
     hipStream_t s = c->s;
     const int64_t ne = c->mesh.ne;
     const double *y1 = ring_y(c, 1), *y2 = ring_y(c, 2);
+    const double *y3 = ring_y(c, 3);
     int mode = c->warm;
-    if (mode == QHP_WARM_MLP && (!c->mlp || c->feat_n < 4)) mode = QHP_WARM_EXTRAP;
+    if (mode == QHP_WARM_MLP && (!c->mlp || c->feat_n < 4)) mode = QHP_WARM_QUAD;
+    if (mode == QHP_WARM_QUAD && !y3) mode = QHP_WARM_EXTRAP;
     if (mode == QHP_WARM_EXTRAP && !y2) mode = QHP_WARM_PREV;
     if (mode == QHP_WARM_PREV && !y1) mode = QHP_WARM_COLD;
     switch (mode) {
@@ -507,15 +532,16 @@ void warm_start(qhp_ctx *c, double *x0)
         hip_check(hipMemcpyAsync(x0, y1, sizeof(double) * ne, hipMemcpyDeviceToDevice, s), "warm start");
         break;
     case QHP_WARM_EXTRAP: axpby(s, ne, 2.0, y1, -1.0, y2, x0); break;
+    case QHP_WARM_QUAD:
+        axpby(s, ne, 3.0, y1, -3.0, y2, x0);
+        axpby(s, ne, 1.0, x0, 1.0, y3, x0);
+        break;
     default: {
         qhp_mlp *m = c->mlp;
         const int64_t nf = m->nf, n = c->feat_n;
         const double *F = c->feat.as<double>();
-        const double *f1 = F + ((n - 1) % 4) * nf, *f2 = F + ((n - 2) % 4) * nf, *f3 = F + ((n - 3) % 4) * nf,
-                     *f4 = F + ((n - 4) % 4) * nf;
-        launch_window_x(s, nf, f1, f2, f3, f4, m->X.as<uint16_t>(), m->sig.as<double>());
-        mlp_forward(m, 1, MT_BF16, m->X.p);
-        launch_guess(s, nf, f1, f2, m->sig.as<double>(), m->O.as<float>(), m->fg.as<double>());
+        mlp_guess(m, F + ((n - 1) % 4) * nf, F + ((n - 2) % 4) * nf, F + ((n - 3) % 4) * nf, F + ((n - 4) % 4) * nf,
+                  m->fg.as<double>());
         loopstar_reconstruct(c, m->fg.as<double>(), 1, nf, x0, ne);
     }
     }

@@ -135,6 +135,37 @@ def test_perceptron_forward_gradient_adam(hidden, batch):
     s.close()
 
 
+def test_perceptron_guess_parity():
+    """The warm-start guess of f_i from four feature rows (backward
+    differences, per-block scaling, network correction of quadratic
+    extrapolation) against the oracle with the same BF16 weights and inputs;
+    the network part carries the BF16 bound of the forward test."""
+    import paper_2312_06367_amd as qhp
+    from oracle import learned as Lr
+    from workloads import meshes
+    xyz, tri = meshes.icosphere(1)
+    s = _solver(xyz, tri, 0.2)
+    m = qhp.MLP(s, hidden=256, seed=3)
+    rng = np.random.default_rng(6)
+    p0 = Lr.init_params(m.n_in, 256, m.nf, rng, out_scale=1.0)
+    flat = m.pack(p0)
+    m.set_params(flat)
+    po = _oracle_params(m, flat)
+    # a smooth sequence plus noise: the four differences have distinct scales
+    k = np.arange(5.0)[:, None]
+    F = np.cos(0.3 * k + rng.uniform(0, 6, m.nf)) + 1e-3 * rng.standard_normal((5, m.nf))
+    x, _, rho3 = Lr.window(F, 4)
+    o = Lr.forward(po, _bf16(x)[None, :])[0][0]
+    g_ref = 3 * F[3] - 3 * F[2] + F[1] + rho3 * o
+    f4 = torch.from_numpy(np.ascontiguousarray(F[3::-1])).cuda()  # rows f_{i-1} .. f_{i-4}
+    g = m.guess(f4).cpu().numpy()
+    err = float(np.abs(g - g_ref).max() / (rho3 * np.abs(o).max()))
+    _say("[mlp guess] error / |network correction| %.2e" % err)
+    m.close()
+    s.close()
+    assert err < 1e-2
+
+
 def _march_gmres(xyz, tri, dt, wave, n, warm, precision="f64"):
     s = _solver(xyz, tri, dt, precision)
     s.set_gmres(1e-10, 40, 4, warm)
@@ -160,21 +191,21 @@ def test_gmres_march_parity():
     w = waves.Wave((0.0, 0.0, -1.0), (1.0, 0.0, 0.0), 1.0, waves.mod_gauss_t0(0.1, asm.D), 0, 0.0, 0.1, 0.1)
     jref = mot.currents(asm.proj.PLH, asm.proj.PS, asm.dtn, mot.march(asm.T, E.rhs(asm, w, n)))
     its = {}
-    for warm in ("cold", "prev", "extrap"):
+    for warm in ("cold", "prev", "extrap", "quad"):
         j, st = _march_gmres(xyz, tri, dt, w, n, warm)
         err = float(np.linalg.norm(j - jref, axis=1).max() / np.linalg.norm(jref, axis=1).max())
         its[warm] = st["iterations"]
         _say("[gmres %s] current err %.2e; iterations %d (max %d per step), inner solves %d, fallbacks %d" % (
             warm, err, st["iterations"], st["max_iterations"], st["refinements"], st["fallbacks"]))
         assert err < 1e-8 and st["fallbacks"] == 0 and st["steps"] == n
-    assert its["extrap"] < its["cold"] and its["prev"] < its["cold"]
+    assert its["quad"] < its["extrap"] < its["cold"] and its["prev"] < its["cold"]
 
 
 def test_warm_start_training_gain():
     """Train the perceptron on GPU marches of 24 seeded directions (480-edge
     sphere, 400 steps), then march 4 held-out directions: its start vectors
-    have smaller residuals than linear extrapolation and GMRES needs fewer
-    iterations; the marches agree with the LU march."""
+    have smaller residuals than linear and quadratic extrapolation and GMRES
+    needs fewer iterations; every march agrees with the inverse-solve march."""
     import paper_2312_06367_amd as qhp
     from workloads import waves
     cfg = waves.sphere_small()
@@ -200,7 +231,7 @@ def test_warm_start_training_gain():
         s.set_incident([w], n)
         jl = torch.zeros((n, ne, 1), dtype=torch.float64, device="cuda")
         s.run(n, jl)
-        for warm in ("extrap", "mlp"):
+        for warm in ("extrap", "quad", "mlp"):
             s.set_gmres(1e-10, 40, 4, warm)
             s.gmres_reset()
             s.set_incident([w], n)
@@ -218,5 +249,5 @@ def test_warm_start_training_gain():
     s.attach_mlp(None)
     m.close()
     s.close()
-    assert res["mlp"]["med"] < res["extrap"]["med"]
-    assert res["mlp"]["it"] <= res["extrap"]["it"]
+    assert res["mlp"]["med"] < res["quad"]["med"] < res["extrap"]["med"]
+    assert res["mlp"]["it"] <= res["quad"]["it"]

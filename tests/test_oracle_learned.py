@@ -91,12 +91,27 @@ def test_gradient_matches_central_differences():
             assert abs(fd - g[k].reshape(-1)[idx]) < 1e-7 * max(1.0, abs(fd)), (k, idx)
 
 
-def test_zero_output_layer_is_linear_extrapolation():
+def test_zero_output_layer_is_quadratic_extrapolation():
     rng = np.random.default_rng(8)
     p = Lr.init_params(4 * 7, 6, 7, rng)
     p["W3"][:] = 0.0
     F = rng.standard_normal((9, 7))
-    assert np.allclose(Lr.guess(p, F, 6), 2 * F[5] - F[4], atol=1e-14)
+    assert np.allclose(Lr.guess(p, F, 6), 3 * F[5] - 3 * F[4] + F[3], atol=1e-13)
+
+
+def test_window_of_a_cubic_sequence():
+    """Features following a cubic in the step index have constant third
+    differences, so the target is exactly the normalised third difference
+    and the input blocks are the normalised backward differences."""
+    rng = np.random.default_rng(9)
+    c = rng.standard_normal((4, 5))
+    F = np.array([c[0] + c[1] * k + c[2] * k ** 2 + c[3] * k ** 3 for k in range(8)])
+    x, t, rho3 = Lr.window(F, 6)
+    d3 = 6.0 * c[3]  # third difference of a cubic
+    assert np.isclose(rho3, np.sqrt(np.mean(d3 ** 2)))
+    assert np.allclose(t, d3 / rho3)
+    assert np.allclose(x[15:], d3 / rho3)
+    assert np.allclose(x[:5], F[5] / np.sqrt(np.mean(F[5] ** 2)))
 
 
 def test_adam_first_step_closed_form():
