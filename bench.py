@@ -34,7 +34,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="sphere-large", choices=["sphere-large", "sphere-small", "torus-batched"])
+    ap.add_argument("--workload", default="sphere-large",
+                    choices=["sphere-large", "sphere-small", "torus-batched", "uneven-batch", "warm-start"])
+    ap.add_argument("--mesh", default="sphere", choices=["sphere", "torus"], help="warm-start mesh")
+    ap.add_argument("--train-dirs", type=int, default=256, help="warm-start training directions")
+    ap.add_argument("--train-steps", type=int, default=2000, help="warm-start training march length")
+    ap.add_argument("--epochs", type=int, default=8, help="warm-start training passes")
+    ap.add_argument("--eval-dirs", type=int, default=2, help="warm-start held-out directions")
     ap.add_argument("--precision", default="f32a", choices=["f32", "f32a", "bf16", "f64"],
                     help="slab storage / history arithmetic: f32a = FP32 blocks with FP64 y and sums")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -72,25 +78,29 @@ def traffic_from_profile(kernel_name):
         return None
 
 
-def cpu_baseline(ne, K, budget_s=20.0):
-    """Oracle marching step (history sum + LU solve) on host cores, on a
-    bounded sample of the same shape: ks of the K lag blocks (random FP64
-    data, ne x ne), the history time scaled to K lags."""
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return int(max([p.get("num_threads", 1) for p in threadpool_info() if p.get("user_api") == "blas"] or [1]))
+    except Exception:
+        return os.cpu_count() or 1
+
+
+def oracle_step_seconds(ne, K, nrhs=1, budget_s=20.0):
+    """Median seconds of one oracle marching step (history sum + LU solve) on
+    host cores, from a bounded sample of the same shape: ks of the K lag
+    blocks (random FP64 data, ne x ne, nrhs right-hand sides), the history
+    time scaled to K lags.  Returns (seconds, ks, samples)."""
     import numpy as np
     import scipy.linalg as sla
     from oracle import mot
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info() if p.get("user_api") == "blas"] or [1])
-    except Exception:
-        threads = os.cpu_count() or 1
     rng = np.random.default_rng(0)
-    ks = 6
+    ks = min(6, K)
     T = rng.standard_normal((ks + 1, ne, ne))
     T[0] += ne * np.eye(ne)
-    ring = [rng.standard_normal(ne) for _ in range(ks)]
+    ring = [rng.standard_normal((ne, nrhs)) if nrhs > 1 else rng.standard_normal(ne) for _ in range(ks)]
     lu = sla.lu_factor(T[0])
-    r = rng.standard_normal(ne)
+    r = rng.standard_normal((ne, nrhs)) if nrhs > 1 else rng.standard_normal(ne)
     times = []
     t_end = time.perf_counter() + budget_s
     for _ in range(6):
@@ -102,10 +112,204 @@ def cpu_baseline(ne, K, budget_s=20.0):
         times.append(((t1 - t0) * K / ks) + (t2 - t1))
         if time.perf_counter() > t_end:
             break
-    step_s = sorted(times)[len(times) // 2]
-    return {"value": 1.0 / step_s, "unit": "MOT steps/s", "cores": int(threads), "kind": "oracle",
+    return sorted(times)[len(times) // 2], ks, len(times)
+
+
+def cpu_baseline(ne, K, budget_s=20.0):
+    """The oracle's steps/s on the workload's shape (bounded sample)."""
+    step_s, ks, n = oracle_step_seconds(ne, K, 1, budget_s)
+    return {"value": 1.0 / step_s, "unit": "MOT steps/s", "cores": blas_threads(), "kind": "oracle",
             "sample": "oracle history sum over %d of the %d lag blocks (FP64 %dx%d, random data) + LU solve, "
-                      "median of %d steps, history time scaled by %d/%d" % (ks, K, ne, ne, len(times), K, ks)}
+                      "median of %d steps, history time scaled by %d/%d" % (ks, K, ne, ne, n, K, ks)}
+
+
+def log(*x):
+    print("[bench]", *x, file=sys.stderr, flush=True)
+
+
+def bench_uneven(a):
+    """32 seeded scatterers of uneven size (spheres, cubes, tori; 500-12000
+    edges), 8 waves each, FP32 blocks and arithmetic, marched together: one
+    graph replay per step of grouped work-queue kernels."""
+    import numpy as np
+    import torch
+    import paper_2312_06367_amd as qhp
+    from workloads import waves
+    cfgs = waves.uneven_batch()
+    n_total = cfgs[0].n_steps
+    steps = min(a.steps, n_total - a.warmup)
+    prec = "f32" if a.precision in ("f32", "f32a") else a.precision
+    order = sorted(range(len(cfgs)), key=lambda i: -len(cfgs[i].mesh[1]))  # largest first: lowest memory peak
+    solvers = [None] * len(cfgs)
+    t0 = time.perf_counter()
+    hist_bytes = 0
+    work = []
+    for i in order:
+        c = cfgs[i]
+        sv = qhp.Solver(c.dt, precision=prec, solver="inv")
+        sv.mesh(*c.mesh)
+        sv.assemble()
+        sv.set_incident(c.waves, n_total)
+        sv.release_assembly()
+        inf = sv.info()
+        solvers[i] = sv
+        esz = {"f64": 8, "f32": 4}[prec]
+        hist_bytes += inf["K"] * inf["ne"] * inf["ne"] * esz
+        work.append((inf["ne"], inf["K"], i))
+        log("scatterer %2d %-14s ne=%5d K=%3d slabs %.2f GB (%.0f s)" % (
+            i, c.name, inf["ne"], inf["K"], inf["slab_bytes"] / 1e9, time.perf_counter() - t0))
+    t_asm = time.perf_counter() - t0
+    b = qhp.Batch(solvers)
+    # outputs for the two smallest scatterers, checked against FP64 eager marches
+    small = [w[2] for w in sorted(work)[:2]]
+    nes = {w[2]: w[0] for w in work}
+    jh = [None] * len(cfgs)
+    for i in small:
+        jh[i] = torch.zeros((n_total, nes[i], len(cfgs[i].waves)), dtype=torch.float64, device="cuda")
+    b.run(a.warmup, [None if t is None else t[: a.warmup] for t in jh])
+    torch.cuda.synchronize()
+    tw = time.perf_counter()
+    b.run(steps, [None if t is None else t[a.warmup: a.warmup + steps] for t in jh])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - tw
+    ms = b.step_times(steps)
+    p50, p99 = float(np.percentile(ms, 50)), float(np.percentile(ms, 99))
+    log("batch: %d steps %.2f s, p50 %.3f ms, p99 %.3f ms" % (steps, wall, p50, p99))
+    b.close()
+    for sv in solvers:
+        sv.close()
+    torch.cuda.empty_cache()
+    errs = {}
+    for i in small:
+        c = cfgs[i]
+        sv = qhp.Solver(c.dt, precision="f64", solver="lu")
+        sv.mesh(*c.mesh)
+        sv.assemble()
+        sv.set_incident(c.waves, n_total)
+        ref = torch.zeros_like(jh[i])
+        sv.run(a.warmup + steps, ref[: a.warmup + steps])
+        sv.close()
+        d = torch.linalg.vector_norm(jh[i][: a.warmup + steps] - ref[: a.warmup + steps], dim=1).max()
+        errs[cfgs[i].name] = float(d / torch.linalg.vector_norm(ref, dim=1).max())
+        log("scatterer %d (%s): current err vs FP64 eager %.2e" % (i, cfgs[i].name, errs[cfgs[i].name]))
+    achieved = hist_bytes / (p50 * 1e-3) / 1e9
+    out = {
+        "metric": "MOT steps/s & history-sum HBM GB/s, batched FP32 vs plain FP64, rel err",
+        "value": len(cfgs) * steps / wall,
+        "unit": "scatterer MOT steps/s (32 scatterers per batch step)",
+        "n_gpus": 1, "steps": steps, "warmup": a.warmup, "ms_per_step": 1e3 * wall / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": prec, "data": "synthetic",
+        "config": {"workload": "uneven-batch-32", "n_scatterers": len(cfgs), "n_rhs_each": 8, "c_dt_m": 0.05,
+                   "ne": [cfgs[i].name for i in range(len(cfgs))], "slab_bytes_total": hist_bytes},
+        "p50_step_ms": p50, "p99_step_ms": p99,
+        "rel_err_vs_fp64": errs,
+        "assembly_s": t_asm,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "kernel": "whole batch step (graph replay), lag-block bytes only",
+                     "algorithmic_bytes_per_launch": hist_bytes, "kernel_ms_avg": p50},
+    }
+    if not a.no_cpu_baseline:
+        sub = sorted(work)[:4] + sorted(work)[-1:]
+        secs = [oracle_step_seconds(ne, K, 8, 8.0)[0] for ne, K, _ in sub]
+        sub_work = sum(K * ne * ne for ne, K, _ in sub)
+        all_work = sum(K * ne * ne for ne, K, _ in work)
+        batch_s = sum(secs) * all_work / sub_work
+        out["cpu_baseline"] = {
+            "value": len(cfgs) / batch_s, "unit": out["unit"], "cores": blas_threads(), "kind": "oracle",
+            "sample": "oracle steps (history over 6 lag blocks scaled to K, 8 right-hand sides, LU solve, random "
+                      "FP64 data) of the 4 smallest and the largest scatterer, scaled to all 32 by K ne^2"}
+    print(json.dumps(out), flush=True)
+
+
+def bench_warm(a):
+    """Learned warm start: train the perceptron on GPU marches of seeded
+    directions, then march held-out directions with GMRES started cold, from
+    y_{i-1}, by linear and quadratic extrapolation and by the network; LU and
+    the explicit inverse beside them."""
+    import numpy as np
+    import torch
+    import paper_2312_06367_amd as qhp
+    from workloads import waves
+    cfg = waves.sphere_large() if a.mesh == "sphere" else waves.torus_batched(1)
+    xyz, tri = cfg.mesh
+    w0 = cfg.waves[0]
+    D = 2.0 if a.mesh == "sphere" else 2.6
+    train = waves.batched_waves(a.train_dirs, 0, w0.f0, w0.bw, D, both_pols=False)
+    held = waves.batched_waves(a.eval_dirs, 1, w0.f0, w0.bw, D, both_pols=False)
+    t0 = time.perf_counter()
+    sv = qhp.Solver(cfg.dt, precision="f64", solver="inv")
+    sv.mesh(xyz, tri)
+    sv.assemble()
+    inf = sv.info()
+    ne, K = inf["ne"], inf["K"]
+    log("%s: ne=%d K=%d assembly %.1f s" % (cfg.name, ne, K, time.perf_counter() - t0))
+    sv.set_precision("f32")
+    n_tr = a.train_steps
+    sv.set_incident(train, n_tr)
+    yh = torch.zeros((n_tr, ne, len(train)), dtype=torch.float64, device="cuda")
+    t0 = time.perf_counter()
+    for c0 in range(0, n_tr, 100):
+        c1 = min(n_tr, c0 + 100)
+        sv.run(c1 - c0, None, yh[c0:c1])
+        torch.cuda.synchronize()
+        log("training marches: %d / %d steps (%.0f s)" % (c1, n_tr, time.perf_counter() - t0))
+    t_data = time.perf_counter() - t0
+    m = qhp.MLP(sv, hidden=256, seed=0)
+    t0 = time.perf_counter()
+    losses = [float(v) for v in m.train(yh, epochs=a.epochs, batch=512, lr=1e-3, seed=0)]
+    t_train = time.perf_counter() - t0
+    log("training: %d epochs %.1f s, loss %s" % (a.epochs, t_train, " ".join("%.3e" % v for v in losses)))
+    del yh
+    torch.cuda.empty_cache()
+    sv.set_precision("f32a")
+    sv.attach_mlp(m)
+    n_ev = a.steps
+    modes = {}
+
+    def march(tag, setup):
+        setup()
+        tot_it, r0s, wall = 0, [], 0.0
+        for w in held:
+            sv.gmres_reset()
+            sv.set_incident([w], n_ev)
+            torch.cuda.synchronize()
+            tt = time.perf_counter()
+            sv.run(n_ev)
+            torch.cuda.synchronize()
+            wall += time.perf_counter() - tt
+            if tag.startswith("gmres"):
+                st = sv.gmres_stats(n_ev)
+                tot_it += st["iterations"]
+                r0s.append(st["res0"][8:])
+        rec = {"steps_per_s": len(held) * n_ev / wall}
+        if r0s:
+            r = np.concatenate(r0s)
+            rec.update({"iterations_per_step": tot_it / (len(held) * n_ev),
+                        "median_start_residual": float(np.median(r[r > 0])) if (r > 0).any() else 0.0})
+        modes[tag] = rec
+        log("%-14s %s" % (tag, json.dumps(rec)))
+
+    march("lu", lambda: sv.set_solver("lu"))
+    march("inv", lambda: sv.set_solver("inv"))
+    for warm in ("cold", "prev", "extrap", "quad", "mlp"):
+        march("gmres-" + warm, lambda warm=warm: sv.set_gmres(1e-10, 40, 4, warm))
+    sv.attach_mlp(None)
+    m.close()
+    sv.close()
+    head = modes["gmres-mlp"]
+    out = {
+        "metric": "MOT steps/s & history-sum HBM GB/s, batched FP32 vs plain FP64, rel err",
+        "value": head["steps_per_s"], "unit": "MOT steps/s",
+        "n_gpus": 1, "steps": n_ev, "warmup": 0, "ms_per_step": 1e3 / head["steps_per_s"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32-storage/f64-accumulate; perceptron bf16/f32", "data": "synthetic",
+        "config": {"workload": "warm-start-" + cfg.name, "ne": ne, "K": K, "train_dirs": len(train),
+                   "train_steps": n_tr, "epochs": a.epochs, "eval_dirs": len(held), "hidden": 256,
+                   "gmres": {"tol": 1e-10, "m_max": 40, "max_refine": 4}},
+        "modes": modes, "train_losses": losses, "training_data_s": t_data, "training_s": t_train,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -118,6 +322,10 @@ def main():
     import paper_2312_06367_amd as qhp
 
     torch.cuda.set_device(0)
+    if a.workload == "uneven-batch":
+        return bench_uneven(a)
+    if a.workload == "warm-start":
+        return bench_warm(a)
     cfg = workload(a.workload, a.n_dirs)
     xyz, tri = cfg.mesh
     n_rhs = len(cfg.waves)
@@ -130,7 +338,6 @@ def main():
     t_asm = time.perf_counter() - t0
     inf = s.info()
     ne, K = inf["ne"], inf["K"]
-    log = lambda *x: print("[bench]", *x, file=sys.stderr, flush=True)
     log("%s: ne=%d K=%d n_rhs=%d assembly %.1f s" % (cfg.name, ne, K, n_rhs, t_asm))
 
     def march(tag, solver):

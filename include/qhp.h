@@ -147,6 +147,16 @@ int qhp_set_precision(qhp_ctx *ctx, int32_t precision);
  * solves, cold start).  Takes effect at the next step. */
 int qhp_set_solver(qhp_ctx *ctx, int32_t solver);
 
+/* Free the FP64 assembly operators that marching no longer needs (Gram,
+ * Yukawa and MFIE operators, projectors, preconditioners, raw lag matrices,
+ * and the FP64 T_0 and its LU where the chosen solver does not use them),
+ * keeping the stored lag blocks, T_0^{-1}, the right-hand sides and the march
+ * state: for many scatterers held at once.  Needs qhp_set_incident first;
+ * afterwards qhp_set_incident, qhp_set_precision, qhp_get_matrix of a freed
+ * operator and switching to a solver whose factors were freed return
+ * QHP_ESTATE. */
+int qhp_release_assembly(qhp_ctx *ctx);
+
 /* Time the history-sum kernel of every following step with HIP events on
  * the context's stream (enable != 0), or stop.  qhp_hist_time() returns the
  * summed kernel time in ms and the number of timed launches since enabling. */

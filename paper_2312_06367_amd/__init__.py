@@ -61,7 +61,7 @@ EXPORTS = ["qhp_create", "qhp_mesh", "qhp_assemble", "qhp_set_precision", "qhp_s
            "qhp_hist_time", "qhp_set_incident", "qhp_step", "qhp_run", "qhp_query", "qhp_edges",
            "qhp_get_matrix", "qhp_keep_raw", "qhp_history_sum", "qhp_batch_create", "qhp_batch_run",
            "qhp_batch_step_times", "qhp_batch_last_error", "qhp_batch_destroy", "qhp_last_error",
-           "qhp_destroy", "qhp_set_gmres", "qhp_gmres_stats", "qhp_gmres_reset", "qhp_mlp_create",
+           "qhp_destroy", "qhp_release_assembly", "qhp_set_gmres", "qhp_gmres_stats", "qhp_gmres_reset", "qhp_mlp_create",
            "qhp_mlp_dims", "qhp_mlp_set_params", "qhp_mlp_get_params", "qhp_mlp_features", "qhp_mlp_guess", "qhp_mlp_reconstruct",
            "qhp_mlp_forward", "qhp_mlp_loss_grad", "qhp_mlp_adam", "qhp_mlp_train", "qhp_attach_mlp",
            "qhp_mlp_last_error", "qhp_mlp_destroy"]
@@ -108,6 +108,7 @@ def lib():
         L.qhp_destroy.restype = None
         dbl, u64 = ctypes.c_double, ctypes.c_uint64
         L.qhp_set_gmres.argtypes = [vp, dbl, i32, i32, i32]
+        L.qhp_release_assembly.argtypes = [vp]
         L.qhp_gmres_stats.argtypes = [vp, ctypes.POINTER(_GmresInfo), vp, vp, i64]
         L.qhp_gmres_reset.argtypes = [vp]
         L.qhp_mlp_create.argtypes = [vp, i32, u64, ctypes.POINTER(vp)]
@@ -212,6 +213,9 @@ class Solver:
 
     def run(self, n_steps: int, j_hist=None, y_hist=None):
         self._check(self.L.qhp_run(self.h, int(n_steps), _ptr(j_hist), _ptr(y_hist)))
+
+    def release_assembly(self):
+        self._check(self.L.qhp_release_assembly(self.h))
 
     def set_gmres(self, tol: float = 1e-10, m_max: int = 40, max_refine: int = 4, warm: str = "cold"):
         self._check(self.L.qhp_set_gmres(self.h, float(tol), int(m_max), int(max_refine), WARM[warm]))

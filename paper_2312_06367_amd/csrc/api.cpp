@@ -498,6 +498,7 @@ extern "C" int qhp_set_incident(qhp_ctx *ctx, const qhp_wave *waves, int32_t n_r
 {
     if (!ctx) return QHP_EINVAL;
     if (ctx->state < 2) return guard(ctx, QHP_ESTATE, "assemble first");
+    if (ctx->released) return guard(ctx, QHP_ESTATE, "assembly operators were released");
     if (!waves || n_rhs < 1 || n_steps < 1) return guard(ctx, QHP_EINVAL, "bad waves / n_rhs / n_steps");
     if (ctx->p.precision == QHP_F32A && n_rhs != 1) return guard(ctx, QHP_EINVAL, "QHP_F32A takes one right-hand side");
     if (ctx->p.solver == QHP_SOLVE_GMRES && n_rhs != 1) return guard(ctx, QHP_EINVAL, "GMRES takes one right-hand side");
@@ -689,9 +690,32 @@ extern "C" int qhp_run(qhp_ctx *ctx, int32_t n_steps, double *j_hist, double *y_
     API_CATCH(ctx)
 }
 
+extern "C" int qhp_release_assembly(qhp_ctx *ctx)
+{
+    if (!ctx) return QHP_EINVAL;
+    if (ctx->state != 3) return guard(ctx, QHP_ESTATE, "set_incident first");
+    if (ctx->released) return QHP_OK;
+    if (hipStreamSynchronize(ctx->s) != hipSuccess) return guard(ctx, QHP_EDEVICE, "synchronise");
+    for (DBuf *b : {&ctx->G, &ctx->Zs, &ctx->Zh, &ctx->M, &ctx->PS, &ctx->PPL, &ctx->Pcat, &ctx->LLp})
+        b->release();
+    if (ctx->p.solver != QHP_SOLVE_GMRES) ctx->T0raw.release();
+    if (ctx->p.solver != QHP_SOLVE_LU && ctx->p.solver != QHP_SOLVE_GMRES) {
+        ctx->LU0.release();
+        ctx->Linv.release();
+        ctx->Uinv.release();
+    }
+    ctx->rawA.clear();
+    ctx->rawB.clear();
+    ctx->rawC.clear();
+    ctx->released = true;
+    return QHP_OK;
+}
+
 extern "C" int qhp_set_solver(qhp_ctx *ctx, int32_t solver)
 {
     if (!ctx) return QHP_EINVAL;
+    if (ctx->released && solver == QHP_SOLVE_LU && !ctx->LU0.p)
+        return guard(ctx, QHP_ESTATE, "the LU of T_0 was released");
     if (solver == QHP_SOLVE_GMRES) return qhp_set_gmres(ctx, ctx->gm_tol, ctx->gm_m, ctx->gm_refine, ctx->warm);
     if (solver != QHP_SOLVE_LU && solver != QHP_SOLVE_INV) return guard(ctx, QHP_EINVAL, "unknown solver");
     ctx->p.solver = solver;
@@ -719,6 +743,7 @@ extern "C" int qhp_set_precision(qhp_ctx *ctx, int32_t precision)
 {
     if (!ctx) return QHP_EINVAL;
     if (ctx->state < 2) return guard(ctx, QHP_ESTATE, "assemble first");
+    if (ctx->released) return guard(ctx, QHP_ESTATE, "assembly operators were released");
     if (precision == ctx->p.precision) return QHP_OK;
     const bool fp32_pair = (precision == QHP_F32 || precision == QHP_F32A) &&
                            (ctx->p.precision == QHP_F32 || ctx->p.precision == QHP_F32A);
@@ -802,6 +827,7 @@ extern "C" int qhp_get_matrix(const qhp_ctx *cc, int32_t which, int32_t k, doubl
     case QHP_MAT_PLAMBDA: src = &ctx->PPL; break;
     case QHP_MAT_PE:
     case QHP_MAT_PM: {
+        if (!ctx->Pcat.p) return guard(ctx, QHP_ESTATE, "operator released");
         const double *base = ctx->Pcat.as<double>() + (which == QHP_MAT_PM ? ne : 0);
         hip_check(hipMemcpy2D(out, sizeof(double) * ne, base, sizeof(double) * 2 * ne, sizeof(double) * ne, ne,
                               hipMemcpyDeviceToHost), "copy");
@@ -831,6 +857,7 @@ extern "C" int qhp_get_matrix(const qhp_ctx *cc, int32_t which, int32_t k, doubl
     }
     default: return guard(ctx, QHP_EINVAL, "unknown matrix");
     }
+    if (!src->p) return guard(ctx, QHP_ESTATE, "operator released");
     hip_check(hipStreamSynchronize(ctx->s), "sync");
     hip_check(hipMemcpy(out, src->p, sizeof(double) * nn, hipMemcpyDeviceToHost), "copy");
     return QHP_OK;

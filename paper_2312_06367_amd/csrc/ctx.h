@@ -119,6 +119,7 @@ struct qhp_ctx {
     qhp::DBuf LLp, Hb, ls_sig, ls_lam;
     int64_t ls_nh = -1, ls_cap = 0;
     qhp_mlp *mlp = nullptr;
+    bool released = false;  // FP64 assembly operators freed (qhp_release_assembly)
     qhp::DBuf feat;  // ring of the last four feature vectors [4][nf]
     int64_t feat_n = 0;
     ~qhp_ctx()

@@ -388,3 +388,34 @@ def test_dc_stability_10k_steps_large_sphere():
     _say("[dc 10k] block maxima / peak: " + " ".join("%.1e" % v for v in blocks))
     assert nj[-1000:].max() < 1e-3 * peak
     assert blocks[-1] <= 10 * blocks[len(blocks) // 2] + 1e-12  # no late growth
+
+
+def test_release_assembly_keeps_the_march():
+    """After qhp_release_assembly the march continues unchanged (same kernels
+    on the kept blocks, inverse and state); calls that need a freed operator
+    return QHP_ESTATE."""
+    import paper_2312_06367_amd as qhp
+    from workloads import meshes
+    xyz, tri = meshes.icosphere(1)
+    w = _wave(0.1, 2.0)
+    outs = []
+    for release in (False, True):
+        s = qhp.Solver(0.15, precision="f32", solver="inv")
+        s.mesh(xyz, tri)
+        s.assemble()
+        s.set_incident([w], 120)
+        jh = torch.zeros((120, s.info()["ne"], 1), dtype=torch.float64, device="cuda")
+        s.run(60, jh[:60])
+        if release:
+            s.release_assembly()
+            for call in (lambda: s.set_incident([w], 10), lambda: s.get_matrix("gram"),
+                         lambda: s.set_precision("bf16"), lambda: s.set_solver("lu")):
+                with pytest.raises(qhp.QhpError) as e:
+                    call()
+                assert e.value.code == -3
+        s.run(60, jh[60:])
+        outs.append(jh.cpu().numpy())
+        s.close()
+    err = float(np.abs(outs[0] - outs[1]).max() / np.abs(outs[0]).max())
+    _say("[release] march difference %.2e" % err)
+    assert err < 1e-13
