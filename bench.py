@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--train-steps", type=int, default=2000, help="warm-start training march length")
     ap.add_argument("--epochs", type=int, default=8, help="warm-start training passes")
     ap.add_argument("--eval-dirs", type=int, default=2, help="warm-start held-out directions")
+    ap.add_argument("--scatterers", type=int, default=32, help="uneven-batch: march the first N of the 32")
     ap.add_argument("--precision", default="f32a", choices=["f32", "f32a", "bf16", "f64"],
                     help="slab storage / history arithmetic: f32a = FP32 blocks with FP64 y and sums")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -135,7 +136,7 @@ def bench_uneven(a):
     import torch
     import paper_2312_06367_amd as qhp
     from workloads import waves
-    cfgs = waves.uneven_batch()
+    cfgs = waves.uneven_batch()[: a.scatterers]
     n_total = cfgs[0].n_steps
     steps = min(a.steps, n_total - a.warmup)
     prec = "f32" if a.precision in ("f32", "f32a") else a.precision
@@ -196,10 +197,10 @@ def bench_uneven(a):
     out = {
         "metric": "MOT steps/s & history-sum HBM GB/s, batched FP32 vs plain FP64, rel err",
         "value": len(cfgs) * steps / wall,
-        "unit": "scatterer MOT steps/s (32 scatterers per batch step)",
+        "unit": "scatterer MOT steps/s (%d scatterers per batch step)" % len(cfgs),
         "n_gpus": 1, "steps": steps, "warmup": a.warmup, "ms_per_step": 1e3 * wall / steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": prec, "data": "synthetic",
-        "config": {"workload": "uneven-batch-32", "n_scatterers": len(cfgs), "n_rhs_each": 8, "c_dt_m": 0.05,
+        "config": {"workload": "uneven-batch-%d" % len(cfgs), "n_scatterers": len(cfgs), "n_rhs_each": 8, "c_dt_m": 0.05,
                    "ne": [cfgs[i].name for i in range(len(cfgs))], "slab_bytes_total": hist_bytes},
         "p50_step_ms": p50, "p99_step_ms": p99,
         "rel_err_vs_fp64": errs,

@@ -899,7 +899,7 @@ struct qhp_batch {
     bool acc_double = true;
     std::string err;
     DBuf d_hist, d_solve, d_post, f_hist, f_solve, f_post, st, po, steps, heads, nslots, counter, errflag;
-    std::vector<DBuf> part_h, part_s, part_p, bvec, yvec, sv, zc, tinv, lsp;
+    std::vector<DBuf> part_h, part_s, part_p, bvec, yvec, sv, zc, tinv, lsp, ringt;
     int64_t tiles_h = 0, tiles_s = 0, tiles_p = 0, max_ne = 0, max_nc = 0;
     std::vector<qhp::GPost> post_host;
     hipGraphExec_t exec = nullptr;
@@ -919,11 +919,11 @@ static int bguard(qhp_batch *b, int code, const std::string &msg)
     return code;
 }
 
-// split count so that a tile (16 rows x cols x lags/split) holds ~ 2M elements
-static int64_t group_splits(int64_t cols, int64_t nlags)
+// split count so that a tile (rows x cols x lags/split) holds ~ 2M elements
+static int64_t group_splits(int64_t rows, int64_t cols, int64_t nlags)
 {
     const int64_t target = (int64_t)2 << 20;
-    int64_t per_lag = 16 * cols;
+    int64_t per_lag = rows * cols;
     int64_t lags = std::max<int64_t>(1, target / per_lag);
     int64_t ns = (nlags + lags - 1) / lags;
     return std::max<int64_t>(1, std::min<int64_t>(ns, nlags));
@@ -936,7 +936,8 @@ static void build_batch(qhp_batch *b)
     const qhp_ctx *c0 = b->ctxs[0];
     const int nr = b->nrhs;
     b->part_h.resize(n); b->part_s.resize(n); b->part_p.resize(n); b->bvec.resize(n); b->yvec.resize(n);
-    b->sv.resize(n); b->zc.resize(n); b->tinv.resize(n); b->lsp.resize(n);
+    b->sv.resize(n); b->zc.resize(n); b->tinv.resize(n); b->lsp.resize(n); b->ringt.resize(n);
+    const bool trans = qhp::grouped_ring_transposed(b->kind, nr);
     // work-queue order: biggest history first
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
@@ -967,14 +968,21 @@ static void build_batch(qhp_batch *b)
         nsl[i] = K;
         const int64_t *dstep = b->steps.as<int64_t>() + i, *dhead = b->heads.as<int64_t>() + i;
         // history group
-        int64_t ns_h = group_splits(ne, K);
+        const int64_t rt_h = qhp::grouped_rows_per_tile(b->kind, nr), rt_f = qhp::grouped_rows_per_tile(qhp::GK_F64, nr);
+        int64_t ns_h = group_splits(rt_h, ne, K);
         b->part_h[i].alloc(asz * ns_h * ne * nr);
         qhp::GDesc g{};
         g.A = c->slabs.p; g.rows = ne; g.cols = ne; g.ld = ld; g.lag_stride = ne * ld; g.nlags = K;
         g.scales = nullptr;
         g.x = c->ring32.p ? c->ring32.p : c->ring64.p;
-        g.x_slot_stride = ld * nr; g.n_slots = K; g.head = dhead;
-        g.partial = b->part_h[i].p; g.nsplit = ns_h; g.rowblocks = (ne + 15) / 16; g.tile0 = t_h;
+        g.x_slot_stride = ld * nr; g.n_slots = K; g.head = dhead; g.x_ld = 0;
+        if (trans) {  // FP32 ring kept transposed as well, from the current state
+            b->ringt[i].alloc(sizeof(float) * K * nr * ld);
+            qhp::launch_ring_transpose(s, K, ld, nr, c->ring32.as<float>(), b->ringt[i].as<float>());
+            g.x = b->ringt[i].p;
+            g.x_ld = ld;
+        }
+        g.partial = b->part_h[i].p; g.nsplit = ns_h; g.rowblocks = (ne + rt_h - 1) / rt_h; g.tile0 = t_h;
         t_h += g.rowblocks * ns_h;
         dh[q] = g;
         b->bvec[i].alloc(sizeof(double) * ne * nr);
@@ -984,19 +992,17 @@ static void build_batch(qhp_batch *b)
         zero(b->tinv[i], s);
         hip_check(hipMemcpy2DAsync(b->tinv[i].p, sizeof(double) * ld, c->Tinv.p, sizeof(double) * ne,
                                    sizeof(double) * ne, ne, hipMemcpyDeviceToDevice, s), "copy");
-        int64_t ns_s = std::max<int64_t>(1, std::min<int64_t>(8, (ne + 2047) / 2048));
-        (void)ns_s;
         b->part_s[i].alloc(sizeof(double) * ne * nr);
         qhp::GDesc gsv{};
         gsv.A = b->tinv[i].p; gsv.rows = ne; gsv.cols = ne; gsv.ld = ld; gsv.lag_stride = 0; gsv.nlags = 1;
         gsv.x = b->bvec[i].p; gsv.x_slot_stride = 0; gsv.n_slots = 1; gsv.head = nullptr;
-        gsv.partial = b->part_s[i].p; gsv.nsplit = 1; gsv.rowblocks = (ne + 15) / 16; gsv.tile0 = t_s;
+        gsv.partial = b->part_s[i].p; gsv.nsplit = 1; gsv.rowblocks = (ne + rt_f - 1) / rt_f; gsv.tile0 = t_s;
         t_s += gsv.rowblocks;
         ds[q] = gsv;
         b->yvec[i].alloc(sizeof(double) * ne * nr);
         fs[i] = qhp::GFin{b->part_s[i].p, 1, ne * nr, nullptr, dstep, b->yvec[i].as<double>()};
         gs[i] = qhp::GStore{b->yvec[i].as<double>(), c->ring64.as<double>(), c->ring32.as<float>(), ld * nr, K,
-                            ne * nr, dhead, b->errflag.as<int>()};
+                            ne * nr, dhead, b->errflag.as<int>(), trans ? b->ringt[i].as<float>() : nullptr, ld, nr};
         // post-processing product z = L_Sigma^+ s (padded copy)
         const int64_t ldc = (nc + 7) / 8 * 8;
         b->lsp[i].alloc(sizeof(double) * nc * ldc);
@@ -1009,7 +1015,7 @@ static void build_batch(qhp_batch *b)
         qhp::GDesc gp{};
         gp.A = b->lsp[i].p; gp.rows = nc; gp.cols = nc; gp.ld = ldc; gp.lag_stride = 0; gp.nlags = 1;
         gp.x = b->sv[i].p; gp.x_slot_stride = 0; gp.n_slots = 1; gp.head = nullptr;
-        gp.partial = b->part_p[i].p; gp.nsplit = 1; gp.rowblocks = (nc + 15) / 16; gp.tile0 = t_p;
+        gp.partial = b->part_p[i].p; gp.nsplit = 1; gp.rowblocks = (nc + rt_f - 1) / rt_f; gp.tile0 = t_p;
         t_p += gp.rowblocks;
         dp[q] = gp;
         fp[i] = qhp::GFin{b->part_p[i].p, 1, nc * nr, nullptr, dstep, b->zc[i].as<double>()};

@@ -13,19 +13,21 @@ enum { GK_F64 = 0, GK_F32 = 1, GK_F32A = 2 };
 // One multi-right-hand-side product group: partial[split][row][rhs] =
 // sum over the split's lags k of A_k[row][:] . x_{(head + k) mod n_slots}[:][rhs]
 struct GDesc {
-    const void *A;          // lag 0 matrix, row stride ld (elements), ld % 8 == 0
+    const void *A;          // lag 0 matrix, row stride ld (elements), ld % 8 == 0, columns [cols, ld) zero
     int64_t rows, cols, ld;
     int64_t lag_stride;     // elements between consecutive lag matrices
     int64_t nlags;
     const float *scales;    // per-lag factor or null
     const void *x;          // ring base: slot s at x + s * x_slot_stride, [cols][nrhs]
+                            // (or [nrhs][x_ld] when x_ld > 0)
     int64_t x_slot_stride;
+    int64_t x_ld;           // row stride of the transposed ring layout, or 0
     int64_t n_slots;
     const int64_t *head;    // device slot of lag 0 (null: 0)
     void *partial;          // [nsplit][rows][nrhs]
     int64_t nsplit;
     int64_t tile0;          // first work tile of this group
-    int64_t rowblocks;      // 16-row blocks; tiles = rowblocks * nsplit
+    int64_t rowblocks;      // row blocks of grouped_rows_per_tile rows; tiles = rowblocks * nsplit
 };
 
 // out[i] = r[step][i] - sum partial (r may be null; negate: + sum)
@@ -44,6 +46,8 @@ struct GStore {
     int64_t slot_stride, n_slots, n;
     const int64_t *head;
     int *err;
+    float *ring32t;  // optional transposed FP32 ring [slot][nrhs][ldt]
+    int64_t ldt, nrhs;
 };
 
 struct GPost {
@@ -58,6 +62,12 @@ struct GPost {
     double *jhist;  // base such that step s writes jhist + s * ne * nrhs (or null)
 };
 
+// rows of one work tile of launch_grouped_gemv for this kind and nrhs
+int64_t grouped_rows_per_tile(int kind, int nrhs);
+// whether launch_grouped_gemv of this kind and nrhs reads the ring transposed
+bool grouped_ring_transposed(int kind, int nrhs);
+// ring [n_slots][ld][nrhs] (FP32) -> [n_slots][nrhs][ld]
+void launch_ring_transpose(hipStream_t s, int64_t n_slots, int64_t ld, int64_t nrhs, const float *in, float *out);
 void launch_grouped_gemv(hipStream_t s, int kind, int nrhs, const GDesc *gd, int ngroups, int64_t total_tiles,
                          unsigned long long *counter);
 void launch_grouped_finish(hipStream_t s, bool acc_double, const GFin *gf, int ngroups, int64_t max_n, int negate);

@@ -110,6 +110,237 @@ __global__ __launch_bounds__(256) void k_grouped_gemv(const GDesc *__restrict__ 
     }
 }
 
+// Multi-right-hand-side form of the same work-queue product: a tile is
+// 4 * RW rows (RW per wave); the (lag, column chunk) steps of the tile are
+// walked as one sequence of chunks of 64 * VN columns.  For each chunk the x
+// values of all NR right-hand sides are staged once in LDS and shared by
+// every row of the tile; each lane keeps one vector of columns of each of its
+// rows.  Software pipeline: while chunk t is multiplied, the lag-block
+// vectors and the x values of chunk t + 1 are already in flight (registers),
+// and the x values land in the other half of a double-buffered LDS area, so
+// one barrier per chunk suffices.  The LDS copy is padded by 16 bytes per
+// lane block so that the 16-byte reads of a lane group fall in distinct banks.
+// Requires the columns [cols, ld) of every block to hold finite values (the
+// library keeps them zero).
+template <typename T, typename Y, typename A, int NR, int RW, int MINB = (sizeof(A) == 8 ? 2 : 3)>
+__global__ __launch_bounds__(256, MINB) void k_grouped_mrhs(const GDesc *__restrict__ gd, int ngroups,
+                                                      int64_t total_tiles, unsigned long long *counter)
+{
+    constexpr int VN = GSt<T>::N;
+    constexpr int CH = 64 * VN;
+    constexpr int ROWS = 4 * RW;
+    constexpr int PAD = 16 / sizeof(Y);
+    constexpr int LB = VN * NR + PAD;   // LDS elements per lane block of VN columns
+    constexpr int XPT = CH * NR / 256;  // x elements staged per thread and chunk
+    typedef typename GSt<T>::v_t V;
+    __shared__ Y xs[2][64 * LB];
+    __shared__ int64_t s_tile;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (;;) {
+        __syncthreads();  // the previous tile's last chunk has been read
+        if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(counter, 1ull);
+        __syncthreads();
+        const int64_t tile = s_tile;
+        if (tile >= total_tiles) return;
+        int g = 0;
+        while (g + 1 < ngroups && gd[g + 1].tile0 <= tile) ++g;
+        const GDesc d = gd[g];
+        const int64_t local = tile - d.tile0;
+        const int64_t rb = local % d.rowblocks, sp = local / d.rowblocks;
+        const int64_t row0 = rb * ROWS + wave * RW;
+        const int64_t lps = (d.nlags + d.nsplit - 1) / d.nsplit;
+        const int64_t k0 = sp * lps;
+        const int64_t k1 = (k0 + lps < d.nlags) ? k0 + lps : d.nlags;
+        const int64_t head = d.head ? *d.head : 0;
+        const int64_t nch = (d.cols + CH - 1) / CH;
+        const int64_t total = (k1 > k0 ? k1 - k0 : 0) * nch;
+        A acc[RW][NR];
+#pragma unroll
+        for (int rr = 0; rr < RW; ++rr)
+#pragma unroll
+            for (int b = 0; b < NR; ++b) acc[rr][b] = 0;
+        V v[RW];
+        Y xr[XPT];
+        // x values of chunk t (lag k0 + t / nch, columns (t % nch) * CH + ...)
+        auto load_x = [&](int64_t t) {
+            const int64_t k = k0 + t / nch, c0 = (t % nch) * CH;
+            const Y *x = (const Y *)d.x + ((head + k) % d.n_slots) * d.x_slot_stride + c0 * NR;
+            const int64_t nel = (d.cols - c0 < CH ? d.cols - c0 : CH) * NR;
+#pragma unroll
+            for (int j = 0; j < XPT; ++j) {
+                const int e = threadIdx.x + 256 * j;
+                xr[j] = e < nel ? x[e] : (Y)0;
+            }
+        };
+        // lag-block vector of row rr in chunk t (zero past the last column)
+        auto load_row = [&](int64_t t, int rr) {
+            const int64_t k = k0 + t / nch, c = (t % nch) * CH + (int64_t)lane * VN;
+            if (c < d.cols && row0 + rr < d.rows)
+                v[rr] = __builtin_nontemporal_load(
+                    reinterpret_cast<const V *>((const T *)d.A + k * d.lag_stride + (row0 + rr) * d.ld + c));
+            else
+                v[rr] = V{};
+        };
+        auto stage = [&](int buf) {
+#pragma unroll
+            for (int j = 0; j < XPT; ++j) {
+                const int e = threadIdx.x + 256 * j;
+                const int cc = e / NR, b = e % NR;
+                xs[buf][(cc / VN) * LB + (cc % VN) * NR + b] = xr[j];
+            }
+        };
+        if (total > 0) {
+            load_x(0);
+#pragma unroll
+            for (int rr = 0; rr < RW; ++rr) load_row(0, rr);
+            stage(0);
+        }
+        __syncthreads();
+        for (int64_t t = 0; t < total; ++t) {
+            const int buf = (int)(t & 1);
+            const bool more = t + 1 < total;
+            if (more) load_x(t + 1);
+            A xv[VN][NR];
+#pragma unroll
+            for (int q = 0; q < VN; ++q)
+#pragma unroll
+                for (int b = 0; b < NR; ++b) xv[q][b] = (A)xs[buf][lane * LB + q * NR + b];
+            // columns past the last one hold zeros in both operands (zero padding
+            // of the blocks, zero-filled x), so no masking is needed here
+#pragma unroll
+            for (int rr = 0; rr < RW; ++rr) {
+#pragma unroll
+                for (int q = 0; q < VN; ++q) {
+                    const A tv = (A)v[rr][q];
+#pragma unroll
+                    for (int b = 0; b < NR; ++b) acc[rr][b] += tv * xv[q][b];
+                }
+                if (more) load_row(t + 1, rr);  // the register is free again
+            }
+            if (more) stage(buf ^ 1);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int rr = 0; rr < RW; ++rr)
+#pragma unroll
+            for (int b = 0; b < NR; ++b) {
+                A x = acc[rr][b];
+                for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+                acc[rr][b] = x;
+            }
+        if (lane == 0) {
+            A *out = (A *)d.partial + sp * d.rows * NR;
+#pragma unroll
+            for (int rr = 0; rr < RW; ++rr)
+                if (row0 + rr < d.rows)
+#pragma unroll
+                    for (int b = 0; b < NR; ++b) out[(row0 + rr) * NR + b] = acc[rr][b];
+        }
+    }
+}
+
+// FP32 multi-right-hand-side form on a transposed ring ([nrhs][x_ld] per
+// slot): for each chunk of 256 columns a lane loads one 16-byte vector of
+// each of its RW rows and one 16-byte vector of each right-hand side, all
+// fully coalesced, with no LDS and no barrier in the streaming loop.  Columns
+// past the last one are zero in both operands.
+template <int NR, int RW>
+__global__ __launch_bounds__(256) void k_grouped_mrhs_t(const GDesc *__restrict__ gd, int ngroups,
+                                                        int64_t total_tiles, unsigned long long *counter)
+{
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    constexpr int ROWS = 4 * RW;
+    __shared__ int64_t s_tile;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(counter, 1ull);
+        __syncthreads();
+        const int64_t tile = s_tile;
+        __syncthreads();
+        if (tile >= total_tiles) return;
+        int g = 0;
+        while (g + 1 < ngroups && gd[g + 1].tile0 <= tile) ++g;
+        const GDesc d = gd[g];
+        const int64_t local = tile - d.tile0;
+        const int64_t rb = local % d.rowblocks, sp = local / d.rowblocks;
+        const int64_t row0 = rb * ROWS + wave * RW;
+        const int64_t lps = (d.nlags + d.nsplit - 1) / d.nsplit;
+        const int64_t k0 = sp * lps;
+        const int64_t k1 = (k0 + lps < d.nlags) ? k0 + lps : d.nlags;
+        const int64_t head = d.head ? *d.head : 0;
+        float acc[RW][NR];
+#pragma unroll
+        for (int rr = 0; rr < RW; ++rr)
+#pragma unroll
+            for (int b = 0; b < NR; ++b) acc[rr][b] = 0.f;
+        for (int64_t k = k0; k < k1; ++k) {
+            const float *x = (const float *)d.x + ((head + k) % d.n_slots) * d.x_slot_stride;
+            const float *Ak = (const float *)d.A + k * d.lag_stride;
+            for (int64_t c = 4 * (int64_t)lane; c < d.cols; c += 256) {
+                f4 xv[NR], v[RW];
+#pragma unroll
+                for (int b = 0; b < NR; ++b) xv[b] = *reinterpret_cast<const f4 *>(x + b * d.x_ld + c);
+#pragma unroll
+                for (int rr = 0; rr < RW; ++rr)
+                    v[rr] = row0 + rr < d.rows
+                                ? __builtin_nontemporal_load(reinterpret_cast<const f4 *>(Ak + (row0 + rr) * d.ld + c))
+                                : f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int rr = 0; rr < RW; ++rr)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+#pragma unroll
+                        for (int b = 0; b < NR; ++b) acc[rr][b] += v[rr][q] * xv[b][q];
+            }
+        }
+#pragma unroll
+        for (int rr = 0; rr < RW; ++rr)
+#pragma unroll
+            for (int b = 0; b < NR; ++b) {
+                float x = acc[rr][b];
+                for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+                acc[rr][b] = x;
+            }
+        if (lane == 0) {
+            float *out = (float *)d.partial + sp * d.rows * NR;
+#pragma unroll
+            for (int rr = 0; rr < RW; ++rr)
+                if (row0 + rr < d.rows)
+#pragma unroll
+                    for (int b = 0; b < NR; ++b) out[(row0 + rr) * NR + b] = acc[rr][b];
+        }
+    }
+}
+
+__global__ void k_ring_transpose(int64_t n_slots, int64_t ld, int64_t nrhs, const float *in, float *out)
+{
+    const int64_t n = n_slots * ld * nrhs;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = idx / (ld * nrhs), rem = idx % (ld * nrhs), i = rem / nrhs, b = rem % nrhs;
+        out[(s * nrhs + b) * ld + i] = in[idx];
+    }
+}
+void launch_ring_transpose(hipStream_t s, int64_t n_slots, int64_t ld, int64_t nrhs, const float *in, float *out)
+{
+    hipLaunchKernelGGL(k_ring_transpose, dim3(1024), dim3(256), 0, s, n_slots, ld, nrhs, in, out);
+}
+
+constexpr int kTransRW = 8;  // rows per wave of the transposed-ring kernel
+
+// rows per wave of the multi-right-hand-side kernel: as many as keep the
+// accumulators, the in-flight block vectors and the staged x of one lane
+// within the register budget of three waves per SIMD
+constexpr int mrhs_rw(int kind, int nrhs) { return (kind == GK_F32 && nrhs <= 2) ? 8 : 4; }
+
+bool grouped_ring_transposed(int kind, int nrhs) { return kind == GK_F32 && nrhs >= 2; }
+
+int64_t grouped_rows_per_tile(int kind, int nrhs)
+{
+    if (nrhs == 1) return 16;
+    if (grouped_ring_transposed(kind, nrhs)) return 4 * kTransRW;
+    return 4 * mrhs_rw(kind, nrhs);
+}
+
 __global__ void k_reset_counter(unsigned long long *c) { *c = 0ull; }
 
 // out[g][row][rhs] = sign_r * r_g[step][row][rhs] - sum_s partial_g[s][row][rhs]
@@ -146,6 +377,7 @@ __global__ void k_grouped_store(const GStore *__restrict__ gs, int ngroups)
         if (!isfinite(v)) atomicExch(d.err, 2);
         d.ring64[slot * d.slot_stride + i] = v;
         if (d.ring32) d.ring32[slot * d.slot_stride + i] = (float)v;
+        if (d.ring32t) d.ring32t[(slot * d.nrhs + i % d.nrhs) * d.ldt + i / d.nrhs] = (float)v;
     }
 }
 
@@ -202,20 +434,34 @@ void launch_grouped_gemv(hipStream_t s, int kind, int nrhs, const GDesc *gd, int
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
     unsigned grid = (unsigned)(total_tiles < 4096 ? total_tiles : 4096);
     if (grid == 0) return;
-#define QHP_G(T, Y, A, NR) \
-    hipLaunchKernelGGL((k_grouped_gemv<T, Y, A, NR>), dim3(grid), dim3(256), 0, s, gd, ngroups, total_tiles, counter)
-#define QHP_GN(T, Y, A)            \
-    switch (nrhs) {                \
-    case 1: QHP_G(T, Y, A, 1); break; \
-    case 2: QHP_G(T, Y, A, 2); break; \
-    case 4: QHP_G(T, Y, A, 4); break; \
-    default: QHP_G(T, Y, A, 8); break; \
+#define QHP_G1(T, Y, A) \
+    hipLaunchKernelGGL((k_grouped_gemv<T, Y, A, 1>), dim3(grid), dim3(256), 0, s, gd, ngroups, total_tiles, counter)
+#define QHP_GM(T, Y, A, NR, RW)                                                                                 \
+    hipLaunchKernelGGL((k_grouped_mrhs<T, Y, A, NR, RW>), dim3(grid), dim3(256), 0, s, gd, ngroups, total_tiles, \
+                       counter)
+#define QHP_GN(T, Y, A, K)                                 \
+    switch (nrhs) {                                        \
+    case 1: QHP_G1(T, Y, A); break;                        \
+    case 2: QHP_GM(T, Y, A, 2, mrhs_rw(K, 2)); break;      \
+    case 4: QHP_GM(T, Y, A, 4, mrhs_rw(K, 4)); break;      \
+    default: QHP_GM(T, Y, A, 8, mrhs_rw(K, 8)); break;     \
     }
-    if (kind == GK_F64) { QHP_GN(double, double, double) }
-    else if (kind == GK_F32) { QHP_GN(float, float, float) }
-    else { QHP_GN(float, double, double) }
+#define QHP_GF(NR) \
+    hipLaunchKernelGGL((k_grouped_mrhs_t<NR, kTransRW>), dim3(grid), dim3(256), 0, s, gd, ngroups, total_tiles, counter)
+    if (kind == GK_F64) { QHP_GN(double, double, double, GK_F64) }
+    else if (kind == GK_F32) {
+        switch (nrhs) {
+        case 1: QHP_G1(float, float, float); break;
+        case 2: QHP_GF(2); break;
+        case 4: QHP_GF(4); break;
+        default: QHP_GF(8); break;
+        }
+    }
+    else { QHP_GN(float, double, double, GK_F32A) }
+#undef QHP_GF
 #undef QHP_GN
-#undef QHP_G
+#undef QHP_GM
+#undef QHP_G1
 }
 void launch_grouped_finish(hipStream_t s, bool acc_double, const GFin *gf, int ngroups, int64_t max_n, int negate)
 {
