@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0
 
 
 def parse():
@@ -42,7 +43,7 @@ def parse():
     ap.add_argument("--epochs", type=int, default=8, help="warm-start training passes")
     ap.add_argument("--eval-dirs", type=int, default=2, help="warm-start held-out directions")
     ap.add_argument("--scatterers", type=int, default=32, help="uneven-batch: march the first N of the 32")
-    ap.add_argument("--precision", default="f32a", choices=["f32", "f32a", "bf16", "f64"],
+    ap.add_argument("--precision", default="f32a", choices=["f32", "f32a", "bf16", "bf16x2", "f64"],
                     help="slab storage / history arithmetic: f32a = FP32 blocks with FP64 y and sums")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 4 GiB device copy first (reference for profiler byte counters)")
@@ -339,9 +340,11 @@ def main():
     t_asm = time.perf_counter() - t0
     inf = s.info()
     ne, K = inf["ne"], inf["K"]
+    state = {"s": s}
     log("%s: ne=%d K=%d n_rhs=%d assembly %.1f s" % (cfg.name, ne, K, n_rhs, t_asm))
 
-    def march(tag, solver):
+    def march(tag, solver, sv=None):
+        s = sv if sv is not None else state["s"]
         s.set_solver(solver)
         s.set_incident(cfg.waves, n_total)
         jh = torch.zeros((n_total, ne, n_rhs), dtype=torch.float64, device="cuda")
@@ -365,7 +368,7 @@ def main():
         return d / torch.linalg.vector_norm(jref, dim=1).max().item()
 
     def gbps(prec, hist_ms):
-        esz = {"f64": 8, "f32": 4, "f32a": 4, "bf16": 2}[prec]
+        esz = {"f64": 8, "f32": 4, "f32a": 4, "bf16": 2, "bf16x2": 4}[prec]
         ysz = 8 if prec in ("f64", "f32a") else 4
         return (K * ne * ne * esz + K * ne * n_rhs * ysz) / (hist_ms * 1e-3) / 1e9
 
@@ -395,11 +398,20 @@ def main():
                 twin = "f32" if a.precision == "f32a" else "f32a"
                 s.set_precision(twin)
                 runs["%s_%s" % (twin, a.solver)] = march(twin, a.solver)
+            if n_rhs > 1:  # the other multi-right-hand-side forms, each assembled in its own storage
+                for p in ("f32", "bf16", "bf16x2"):
+                    if p == a.precision:
+                        continue
+                    sv = qhp.Solver(cfg.dt, precision=p, solver=a.solver)
+                    sv.mesh(xyz, tri)
+                    sv.assemble()
+                    runs["%s_%s" % (p, a.solver)] = march(p, a.solver, sv)
+                    sv.close()
     else:
         runs["head"] = runs["f64_" + a.solver]
     head = runs["head"]
     jref = runs["f64_lu"]["j"]
-    esz = {"f64": 8, "f32": 4, "f32a": 4, "bf16": 2}[a.precision]
+    esz = {"f64": 8, "f32": 4, "f32a": 4, "bf16": 2, "bf16x2": 4}[a.precision]
     ysz = 8 if a.precision in ("f64", "f32a") else 4
     bytes_per_launch = K * ne * ne * esz + K * ne * n_rhs * ysz
     flops_per_launch = 2.0 * K * ne * ne * n_rhs
@@ -411,8 +423,21 @@ def main():
                 "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_from_profile(kname),
                 "kernel": kname, "algorithmic_bytes_per_launch": bytes_per_launch,
                 "kernel_ms_avg": head["hist_ms"]}
+    elif a.precision in ("bf16", "bf16x2"):
+        # BF16 matrix cores: five (pair) or two BF16 products per term; the
+        # streamed block bytes bound the kernel
+        kname = "k_hist_mfma<%s>" % ("true" if a.precision == "bf16x2" else "false")
+        achieved = bytes_per_launch / (head["hist_ms"] * 1e-3) / 1e9
+        products = 5 if a.precision == "bf16x2" else 2
+        executed = products * flops_per_launch / (head["hist_ms"] * 1e-3) / 1e12
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_from_profile(kname),
+                "kernel": kname, "algorithmic_bytes_per_launch": bytes_per_launch,
+                "kernel_ms_avg": head["hist_ms"],
+                "bf16_mfma_executed_tflops": executed, "bf16_mfma_frac": executed / BF16_MFMA_PEAK_TFLOPS,
+                "fp32_equivalent_tflops": flops_per_launch / (head["hist_ms"] * 1e-3) / 1e12}
     else:
-        kname = "k_hist_gemm<%s>" % ("unsigned short" if a.precision == "bf16" else "float")
+        kname = "k_hist_gemm<float>"
         achieved = flops_per_launch / (head["hist_ms"] * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "traffic": traffic_from_profile(kname),
@@ -436,7 +461,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f32": "f32", "bf16": "bf16-storage/f32", "f32a": "f32-storage/f64-accumulate", "f64": "f64"}[a.precision],
+        "dtype": {"f32": "f32", "bf16": "bf16-storage/f32", "f32a": "f32-storage/f64-accumulate", "f64": "f64",
+                  "bf16x2": "bf16-pair-storage/bf16-mfma/f32-accumulate"}[a.precision],
         "data": "synthetic",
         "config": {"workload": cfg.name, "ne": ne, "K": K, "c_dt_m": cfg.dt, "n_rhs": n_rhs,
                    "slab_storage": a.precision, "solve": "fp64-" + a.solver, "post_processing": "fp64"},

@@ -48,12 +48,21 @@ enum {
 
 /* storage of the lag blocks T_k, k >= 1, and the history-sum arithmetic
  * (T_0, the solve and the post-processing are always FP64):
- *   QHP_F64  FP64 blocks, FP64 products and sums
- *   QHP_F32  FP32 blocks, FP32 copy of y, FP32 products and sums
- *   QHP_BF16 BF16 blocks with a per-block FP32 scale, FP32 y, FP32 sums
- *   QHP_F32A FP32 blocks, FP64 y, products and sums in FP64 (one right-hand
- *            side only) */
-enum { QHP_F64 = 0, QHP_F32 = 1, QHP_BF16 = 2, QHP_F32A = 3 };
+ *   QHP_F64    FP64 blocks, FP64 products and sums
+ *   QHP_F32    FP32 blocks, FP32 copy of y, FP32 products and sums
+ *   QHP_BF16   BF16 blocks with a per-block FP32 scale, FP32 sums; y as FP32
+ *              (one right-hand side) or, with several right-hand sides, as
+ *              two BF16 terms (hi + mid) on the BF16 matrix cores
+ *   QHP_F32A   FP32 blocks, FP64 y, products and sums in FP64 (one right-hand
+ *              side only)
+ *   QHP_BF16X2 each block as a BF16 pair T_hi + T_lo (4 bytes per entry), y
+ *              as three BF16 terms, the five products of weight >= 2^-16
+ *              on the BF16 matrix cores with FP32 sums (two or more
+ *              right-hand sides)
+ * Reduced-precision blocks are rounded lag by lag with the rounding error of
+ * each block carried into the next one (c_k = T_k + c_{k-1} - stored_k), so
+ * every prefix sum over lags is within one rounding of the FP64 one. */
+enum { QHP_F64 = 0, QHP_F32 = 1, QHP_BF16 = 2, QHP_F32A = 3, QHP_BF16X2 = 4 };
 
 /* per-step solve with T_0 (the paper writes only T_0^{-1}, Sec. IV-B) */
 enum {
@@ -185,7 +194,8 @@ int qhp_edges(const qhp_ctx *ctx, int32_t *edges, int32_t *cells);
 /* Copy an assembled FP64 matrix to host memory out [ne][ne] (parity checks):
  *   which = QHP_MAT_*; k is the lag for the slab and raw lag matrices (raw
  *   lag matrices A_k, B_k, C_k only if qhp_keep_raw(ctx, 1) preceded
- *   qhp_assemble).  Slabs stored in F32/BF16 are returned dequantised. */
+ *   qhp_assemble).  Slabs stored in a reduced precision are returned as the
+ *   exact values of what is stored. */
 enum {
     QHP_MAT_GRAM = 0, QHP_MAT_ZS = 1, QHP_MAT_ZH = 2, QHP_MAT_M = 3,
     QHP_MAT_PSIGMA = 4, QHP_MAT_PLAMBDA = 5, QHP_MAT_PE = 6, QHP_MAT_PM = 7,
@@ -196,12 +206,25 @@ int qhp_keep_raw(qhp_ctx *ctx, int32_t keep);
 
 /* The per-step history sum on caller buffers (all device, on `stream`):
  *   b = r - sum_{k=1}^{kmax} T_k y_{i-k}              (Sec. IV-B)
- * slabs: [kmax][ne][ld] in `precision` (T_k at index k-1), ld >= ne, a
- *   multiple of 8; scales: [kmax] FP32 per-slab factors for QHP_BF16 (T_k =
- *   scale * stored), else NULL;
- * ring: [n_slots][ne][nrhs] FP64 for QHP_F64, FP32 otherwise; y_{i-k} is slot
- *   (head + k - 1) mod n_slots, n_slots >= kmax;
- * r, b: [ne][nrhs] FP64.  nrhs >= 1.  The library owns no buffer here. */
+ * slabs: [kmax][ne][ld] in `precision` (T_k at index k-1), ld >= ne a
+ *   multiple of 8, columns [ne, ld) ignored; for QHP_BF16X2 ld is a multiple
+ *   of 32 and each block holds its hi and lo BF16 planes in matrix-core
+ *   operand order, [ceil(ne / 16)][ld / 32][2][512] with entry (i, j) of
+ *   plane p at ((i / 16 * ld / 32 + j / 32) * 2 + p) * 512
+ *   + (i % 16 + 16 * (j % 32 / 8)) * 8 + j % 8, rows >= ne and columns >= ne
+ *   zero; scales: [kmax] FP32 per-slab factors for QHP_BF16 (T_k = scale *
+ *   stored), else NULL;
+ * ring: y_{i-k} is slot (head + k - 1) mod n_slots, n_slots >= kmax; a slot
+ *   is [ld][nrhs] FP64 for QHP_F64 and QHP_F32A, [ld][nrhs] FP32 for QHP_F32
+ *   and for QHP_BF16 with nrhs = 1, and for QHP_BF16 with nrhs > 1 and for
+ *   QHP_BF16X2 (ld a multiple of 32) three BF16 terms y ~ hi + mid + lo, each
+ *   the rounding of what the previous ones leave, in the same operand order
+ *   with y^T [nrp][ld] as the matrix ([nrp / 16][ld / 32][3][512], nrp = nrhs
+ *   rounded up to 16; entries of columns >= ne are ignored, right-hand sides
+ *   >= nrhs must be zero; QHP_BF16 reads hi and mid only);
+ * r, b: [ne][nrhs] FP64.  nrhs >= 1 (>= 2 for QHP_BF16X2, 1 for QHP_F32A).
+ * The call allocates and frees a scratch buffer of partial sums (QHP_ENOMEM
+ * if it cannot) and returns when the stream has finished the work. */
 int qhp_history_sum(void *stream, int32_t precision, int64_t ne, int64_t ld, int64_t nrhs,
                     int64_t kmax, const void *slabs, const float *scales, const void *ring,
                     int64_t n_slots, int64_t head, const double *r, double *b);

@@ -15,14 +15,14 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqhp.so")
 
-QHP_F64, QHP_F32, QHP_BF16, QHP_F32A = 0, 1, 2, 3
+QHP_F64, QHP_F32, QHP_BF16, QHP_F32A, QHP_BF16X2 = 0, 1, 2, 3, 4
 QHP_SOLVE_LU, QHP_SOLVE_INV, QHP_SOLVE_GMRES = 0, 1, 2
 WARM = {"cold": 0, "prev": 1, "extrap": 2, "quad": 3, "mlp": 4}
 MAT = {"gram": 0, "zs": 1, "zh": 2, "m": 3, "psigma": 4, "plambda": 5, "pe": 6, "pm": 7,
        "slab": 8, "a": 9, "b": 10, "c": 11}
 ERRORS = {0: "OK", -1: "EINVAL", -2: "EMESH", -3: "ESTATE", -4: "ENOMEM", -5: "EDEVICE",
           -6: "ESINGULAR", -7: "ENOCONV", -8: "EUNSTABLE"}
-PRECISIONS = {"f64": QHP_F64, "f32": QHP_F32, "bf16": QHP_BF16, "f32a": QHP_F32A}
+PRECISIONS = {"f64": QHP_F64, "f32": QHP_F32, "bf16": QHP_BF16, "f32a": QHP_F32A, "bf16x2": QHP_BF16X2}
 SOLVERS = {"lu": QHP_SOLVE_LU, "inv": QHP_SOLVE_INV, "gmres": QHP_SOLVE_GMRES}
 
 
@@ -270,12 +270,17 @@ class Solver:
 def history_sum(precision: str, slabs, scales, ring, head: int, r, b, kmax: int | None = None):
     """b = r - sum_{k=1}^{kmax} T_k y_{i-k} on caller tensors (see qhp_history_sum).
 
-    slabs: [kmax, ne, ld] (float64 / float32 / bfloat16), scales: float32 [kmax]
-    (bfloat16 only), ring: [n_slots, ld, nrhs] float64 (f64) or float32,
-    r, b: float64 [ne, nrhs]."""
+    slabs: [kmax, ne, ld] (float64 / float32 / bfloat16) or, for bf16x2,
+    [kmax, ceil(ne/16), ld/32, 2, 512] bfloat16 in matrix-core operand order;
+    scales: float32 [kmax] (bf16 only); ring: [n_slots, ld, nrhs] float64
+    (f64, f32a) or float32, or [n_slots, nrp/16, ld/32, 3, 512] bfloat16
+    (bf16 with nrhs > 1, bf16x2); r, b: float64 [ne, nrhs]."""
     L = lib()
     kmax = slabs.shape[0] if kmax is None else kmax
-    ne, ld = slabs.shape[1], slabs.shape[2]
+    if precision == "bf16x2":  # operand-ordered planes: ld from the tile count, ne from r
+        ne, ld = r.shape[0], slabs.shape[2] * 32
+    else:
+        ne, ld = slabs.shape[-2], slabs.shape[-1]
     nrhs = r.shape[1] if r.dim() == 2 else 1
     rc = L.qhp_history_sum(_stream(), PRECISIONS[precision], ne, ld, nrhs, kmax, _ptr(slabs), _ptr(scales),
                            _ptr(ring), ring.shape[0], int(head), _ptr(r), _ptr(b))

@@ -70,7 +70,7 @@ int guard(qhp_ctx *ctx, int code, const std::string &msg)
 extern "C" int qhp_create(const qhp_params *params, qhp_ctx **out)
 {
     if (!params || !out) return QHP_EINVAL;
-    if (!(params->dt > 0.0) || params->precision < QHP_F64 || params->precision > QHP_F32A ||
+    if (!(params->dt > 0.0) || params->precision < QHP_F64 || params->precision > QHP_BF16X2 ||
         params->solver < QHP_SOLVE_LU || params->solver > QHP_SOLVE_INV || params->n_psi > 32)
         return QHP_EINVAL;
     int ndev = 0;
@@ -323,7 +323,8 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
     const int64_t K = c->K;
     const int32_t prec = c->p.precision;
     const size_t esz = prec == QHP_F64 ? 8 : (prec == QHP_BF16 ? 2 : 4);
-    c->slabs.alloc(esz * (size_t)K * ne * c->ld);
+    const size_t blk = (size_t)qhp::slab_rows(prec, ne) * c->ld;  // entries of one stored block
+    c->slabs.alloc(esz * (size_t)K * blk);
     c->scales.assign(K, 1.0f);
     c->T0raw.alloc(sizeof(double) * nn);
     if (c->keep_raw) {
@@ -404,7 +405,7 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
                     hip_check(hipMemcpyAsync(c->T0raw.p, Tt.p, sizeof(double) * nn, hipMemcpyDeviceToDevice, s), "copy");
                 } else {
                     c->scales[k - 1] = store_lag(s, ne, c->ld, Tt.as<double>(), ne, carry.as<double>(), prec, amax,
-                                                 (char *)c->slabs.p + esz * (size_t)(k - 1) * ne * c->ld);
+                                                 (char *)c->slabs.p + esz * (size_t)(k - 1) * blk);
                 }
                 std::swap(Ap.p, Ak.p);
                 std::swap(Cp.p, Ck.p);
@@ -502,6 +503,8 @@ extern "C" int qhp_set_incident(qhp_ctx *ctx, const qhp_wave *waves, int32_t n_r
     if (!waves || n_rhs < 1 || n_steps < 1) return guard(ctx, QHP_EINVAL, "bad waves / n_rhs / n_steps");
     if (ctx->p.precision == QHP_F32A && n_rhs != 1) return guard(ctx, QHP_EINVAL, "QHP_F32A takes one right-hand side");
     if (ctx->p.solver == QHP_SOLVE_GMRES && n_rhs != 1) return guard(ctx, QHP_EINVAL, "GMRES takes one right-hand side");
+    if (ctx->p.precision == QHP_BF16X2 && n_rhs < 2)
+        return guard(ctx, QHP_EINVAL, "QHP_BF16X2 takes two or more right-hand sides");
     API_TRY
     qhp_ctx *c = ctx;
     hip_check(hipSetDevice(c->p.device), "hipSetDevice");
@@ -542,14 +545,19 @@ extern "C" int qhp_set_incident(qhp_ctx *ctx, const qhp_wave *waves, int32_t n_r
     const int64_t K = c->K, ld = c->ld;
     c->ring64.alloc(sizeof(double) * K * ld * n_rhs);
     zero(c->ring64, s);
-    if (c->p.precision == QHP_F32 || c->p.precision == QHP_BF16) {
+    if (c->p.precision == QHP_F32 || (c->p.precision == QHP_BF16 && n_rhs == 1)) {
         c->ring32.alloc(sizeof(float) * K * ld * n_rhs);
         zero(c->ring32, s);
+    }
+    c->ringb.release();
+    if ((c->p.precision == QHP_BF16 || c->p.precision == QHP_BF16X2) && n_rhs > 1) {
+        c->ringb.alloc(sizeof(uint16_t) * K * 3 * qhp::ring_bf16_rows(n_rhs) * ld);
+        zero(c->ringb, s);
     }
     c->bvec.alloc(sizeof(double) * ne * n_rhs);
     c->zvec.alloc(sizeof(double) * ne * n_rhs);
     c->yvec.alloc(sizeof(double) * ne * n_rhs);
-    c->nsplit = qhp::hist_splits(ne, K, n_rhs);
+    c->nsplit = qhp::hist_splits(ne, K, n_rhs, c->p.precision);
     c->partial.alloc(sizeof(double) * std::min<int64_t>(2 * c->nsplit, K) * ne * n_rhs);
     c->sv.alloc(sizeof(double) * nc * n_rhs);
     c->zc.alloc(sizeof(double) * nc * n_rhs);
@@ -588,8 +596,8 @@ static void do_step(qhp_ctx *c, double *j_out, double *y_out)
     }
     qhp::launch_history(s, c->p.precision, ne, ld, nr, K, c->slabs.p,
                         c->p.precision == QHP_BF16 ? c->scales_d.as<float>() : nullptr,
-                        c->ring32.p ? c->ring32.p : c->ring64.p, K, c->head, r_i, c->bvec.as<double>(),
-                        c->partial.p, c->nsplit, e0, e1, c->hv);
+                        c->ringb.p ? c->ringb.p : (c->ring32.p ? c->ring32.p : c->ring64.p), K, c->head, r_i,
+                        c->bvec.as<double>(), c->partial.p, c->nsplit, e0, e1, c->hv);
     double *y = c->yvec.as<double>();
     if (c->p.solver == QHP_SOLVE_GMRES) {
         qhp::warm_start(c, y);
@@ -630,6 +638,10 @@ static void do_step(qhp_ctx *c, double *j_out, double *y_out)
         qhp::launch_post_b(s, ne, nr, c->args.cells, y, c->zc.as<double>(), j_out);
     }
     qhp::launch_store_y(s, ne * nr, y, slot64, slot32, y_out, c->errflag.as<int>());
+    if (c->ringb.p) {
+        const int64_t nrp = qhp::ring_bf16_rows(nr);
+        qhp::launch_store_ybf(s, ne, nr, nrp, ld, y, c->ringb.as<uint16_t>() + slot * 3 * nrp * ld);
+    }
     if (c->p.solver == QHP_SOLVE_GMRES) qhp::warm_record(c, y);
     c->head = slot;
     c->step = i;
@@ -750,30 +762,34 @@ extern "C" int qhp_set_precision(qhp_ctx *ctx, int32_t precision)
     if (fp32_pair) {  // same FP32 storage, other arithmetic
         ctx->p.precision = precision;
         ctx->ring32.release();
+        ctx->ringb.release();
         ctx->state = 2;
         return QHP_OK;
     }
-    if (ctx->p.precision != QHP_F64 || (precision != QHP_F32 && precision != QHP_BF16 && precision != QHP_F32A))
-        return guard(ctx, QHP_EINVAL, "only FP64 slabs can be re-stored, as FP32 or BF16");
+    if (ctx->p.precision != QHP_F64 ||
+        (precision != QHP_F32 && precision != QHP_BF16 && precision != QHP_F32A && precision != QHP_BF16X2))
+        return guard(ctx, QHP_EINVAL, "only FP64 slabs can be re-stored, as FP32, BF16 or BF16 pairs");
     API_TRY
     hipStream_t s = ctx->s;
     const int64_t ne = ctx->mesh.ne, ld = ctx->ld, K = ctx->K;
-    const size_t per = (size_t)ne * ld;
+    const size_t per = (size_t)ne * ld;                              // FP64 source block
+    const size_t blk = (size_t)qhp::slab_rows(precision, ne) * ld;  // stored block
     const size_t esz = precision == QHP_BF16 ? 2 : 4;
     DBuf out, amax, carry;
-    out.alloc(esz * per * K);
+    out.alloc(esz * blk * K);
     amax.alloc(sizeof(unsigned long long));
     carry.alloc(sizeof(double) * ne * ne);
     zero(carry, s);
     for (int64_t k = 0; k < K; ++k)
         ctx->scales[k] = store_lag(s, ne, ld, ctx->slabs.as<double>() + k * per, ld, carry.as<double>(), precision, amax,
-                                   (char *)out.p + esz * per * k);
+                                   (char *)out.p + esz * blk * k);
     hip_check(hipStreamSynchronize(s), "convert slabs");
     std::swap(ctx->slabs.p, out.p);
     std::swap(ctx->slabs.bytes, out.bytes);
     upload(ctx->scales_d, ctx->scales, s);
     ctx->p.precision = precision;
     ctx->ring32.release();
+    ctx->ringb.release();
     ctx->state = 2;
     return QHP_OK;
     API_CATCH(ctx)
@@ -840,7 +856,8 @@ extern "C" int qhp_get_matrix(const qhp_ctx *cc, int32_t which, int32_t k, doubl
         tmp.alloc(sizeof(double) * nn);
         const int32_t prec = ctx->p.precision;
         const size_t esz = prec == QHP_F64 ? 8 : (prec == QHP_BF16 ? 2 : 4);
-        qhp::launch_load_slab(ctx->s, ne, ctx->ld, (const char *)ctx->slabs.p + esz * (size_t)(k - 1) * ne * ctx->ld,
+        qhp::launch_load_slab(ctx->s, ne, ctx->ld,
+                              (const char *)ctx->slabs.p + esz * (size_t)(k - 1) * qhp::slab_rows(prec, ne) * ctx->ld,
                               prec, ctx->scales[k - 1], tmp.as<double>());
         hip_check(hipStreamSynchronize(ctx->s), "dequantise");
         hip_check(hipMemcpy(out, tmp.p, sizeof(double) * nn, hipMemcpyDeviceToHost), "copy");
@@ -868,13 +885,14 @@ extern "C" int qhp_history_sum(void *stream, int32_t precision, int64_t ne, int6
                                const void *slabs, const float *scales, const void *ring, int64_t n_slots, int64_t head,
                                const double *r, double *b)
 {
-    if (precision < QHP_F64 || precision > QHP_F32A || ne < 1 || ld < ne || ld % 8 != 0 || nrhs < 1 || kmax < 0 ||
-        (precision == QHP_F32A && nrhs != 1) ||
+    if (precision < QHP_F64 || precision > QHP_BF16X2 || ne < 1 || ld < ne || ld % 8 != 0 || nrhs < 1 || kmax < 0 ||
+        (precision == QHP_F32A && nrhs != 1) || (precision == QHP_BF16X2 && (nrhs < 2 || ld % 32 != 0)) ||
+        (precision == QHP_BF16 && nrhs > 1 && ld % 32 != 0) ||
         n_slots < kmax || head < 0 || (kmax > 0 && (!slabs || !ring)) || !r || !b)
         return QHP_EINVAL;
     if (precision == QHP_BF16 && !scales) return QHP_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    int nsplit = qhp::hist_splits(ne, std::max<int64_t>(kmax, 1), nrhs);
+    int nsplit = qhp::hist_splits(ne, std::max<int64_t>(kmax, 1), nrhs, precision);
     void *partial = nullptr;
     if (hipMalloc(&partial, sizeof(double) * nsplit * ne * nrhs) != hipSuccess) {
         (void)hipGetLastError();
@@ -1071,7 +1089,8 @@ extern "C" int qhp_batch_create(qhp_ctx *const *ctxs, int32_t n, qhp_batch **out
         if (c->p.device != c0->p.device || c->p.precision != c0->p.precision || c->nrhs != c0->nrhs)
             return guard(c0, QHP_EINVAL, "batch contexts must share device, precision and n_rhs");
     }
-    if (c0->p.precision == QHP_BF16) return guard(c0, QHP_EINVAL, "the batch kernels take F64, F32 or F32A blocks");
+    if (c0->p.precision == QHP_BF16 || c0->p.precision == QHP_BF16X2)
+        return guard(c0, QHP_EINVAL, "the batch kernels take F64, F32 or F32A blocks");
     if (c0->nrhs != 1 && c0->nrhs != 2 && c0->nrhs != 4 && c0->nrhs != 8)
         return guard(c0, QHP_EINVAL, "batch n_rhs must be 1, 2, 4 or 8");
     qhp_batch *b = new qhp_batch();

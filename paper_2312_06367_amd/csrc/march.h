@@ -10,7 +10,18 @@
 
 namespace qhp {
 
-int hist_splits(int64_t ne, int64_t kmax, int64_t nrhs);
+int hist_splits(int64_t ne, int64_t kmax, int64_t nrhs, int32_t precision);
+// rows of one stored lag block (QHP_BF16X2 pads them to whole 16-row tiles)
+__host__ __device__ inline int64_t slab_rows(int32_t precision, int64_t ne)
+{
+    return precision == QHP_BF16X2 ? (ne + 15) / 16 * 16 : ne;
+}
+// rows of each BF16 plane of a ring slot for the matrix-core history (nrhs padded to 16)
+int64_t ring_bf16_rows(int64_t nrhs);
+// y [ne][nrhs] FP64 -> slot planes hi, mid, lo (BF16) in MFMA operand order:
+// [nrp / 16][ld / 32][3][512] (see k_hist_mfma)
+void launch_store_ybf(hipStream_t s, int64_t ne, int64_t nrhs, int64_t nrp, int64_t ld, const double *y,
+                      uint16_t *slot);
 // partial: scratch of nsplit * ne * nrhs accumulators (FP64 for QHP_F64 with
 // nrhs == 1, FP32 otherwise)
 void launch_history(hipStream_t s, int32_t precision, int64_t ne, int64_t ld, int64_t nrhs, int64_t kmax,

@@ -173,9 +173,25 @@ struct St<uint16_t> {  // bf16 storage
     typedef uint32_t v_t __attribute__((ext_vector_type(4)));
 };
 
+__device__ __forceinline__ uint16_t f32_to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    uint32_t rounding = 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+    return (uint16_t)((u + rounding) >> 16);
+}
 __device__ __forceinline__ float bf16_to_f32(uint16_t h)
 {
     return __uint_as_float(((uint32_t)h) << 16);
+}
+
+// MFMA operand order of a BF16 matrix with rows of ld entries: 16-row x
+// 32-column tiles, each plane of a tile 512 entries = 64 lanes x 8, where lane
+// r + 16 q holds row r, columns 8 q .. 8 q + 7 of the tile (the A and B
+// operand pattern of v_mfma_f32_16x16x32_bf16), tiles row-tile major.
+__device__ __forceinline__ int64_t packed_index(int64_t i, int64_t j, int64_t ld, int plane, int nplanes)
+{
+    const int64_t rt = i >> 4, r = i & 15, kc = j >> 5, w = j & 31;
+    return ((rt * (ld >> 5) + kc) * nplanes + plane) * 512 + (r + 16 * (w >> 3)) * 8 + (w & 7);
 }
 
 template <typename T, bool NT>
@@ -414,8 +430,257 @@ __global__ __launch_bounds__(256) void k_hist_gemm(int64_t ne, int64_t ld, int64
     }
 }
 
-int hist_splits(int64_t ne, int64_t kmax, int64_t nrhs)
+// Batched history on the BF16 matrix cores (v_mfma_f32_16x16x32_bf16, FP32
+// sums).  y is held per ring slot as three BF16 terms hi, mid, lo (y ~ hi +
+// mid + lo to 24 significant bits) stored in MFMA operand order ([nrp / 16]
+// [ld / 32][3][512], see packed_index), so each 16 x 32 operand tile is one
+// contiguous 1 KB piece per term.  PAIR (QHP_BF16X2): the lag block is a BF16
+// pair, hi and lo planes stored in the same operand order (one coalesced
+// 1 KB load per operand and wave), and each term takes the five products of
+// relative weight >= 2^-16, T_hi (y_hi + y_mid + y_lo) + T_lo (y_hi + y_mid).
+// Otherwise (QHP_BF16) the block is one row-major BF16 plane with a
+// per-block scale and two products T (y_hi + y_mid), the accumulators being
+// kept in units of the current block's scale (rescaled by the ratio at each
+// lag change, by the last scale at the end).
+// Work-group: 4 waves x 32 rows, 128 right-hand sides; the B tiles of each
+// 32-column step are staged in double-buffered LDS (contiguous copies), A
+// goes straight to registers DA steps ahead; one barrier per step.  Columns
+// at or past ne are masked.
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef unsigned int u4_t __attribute__((ext_vector_type(4)));
+
+// zero the BF16 entries of an 8-entry vector whose column first + j >= ne
+__device__ __forceinline__ u4_t mask_cols(u4_t v, int64_t first, int64_t ne)
 {
+    if (first + 8 <= ne) return v;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        if (first + j >= ne) v[j >> 1] &= (j & 1) ? 0x0000ffffu : 0xffff0000u;
+    return v;
+}
+
+template <bool PAIR>
+__global__ __launch_bounds__(256, 2) void k_hist_mfma(int64_t ne, int64_t ld, int64_t nrp, int64_t nrhs, int64_t kmax,
+                                                      int64_t lps, const uint16_t *__restrict__ slabs,
+                                                      const float *__restrict__ scales,
+                                                      const uint16_t *__restrict__ ringb, int64_t n_slots,
+                                                      int64_t head, float *__restrict__ partial)
+{
+    constexpr int NB = 8, KS = 32;
+    constexpr int NP = PAIR ? 3 : 2;         // y terms used
+    constexpr int BPT = NB * NP * 64 / 256;  // 16-byte B pieces staged per thread
+    constexpr int DA = 2;                    // A steps in registers
+    constexpr int JB = 4;                    // n tiles per product-major group
+    __shared__ u4_t Bs[2][NP][NB][64];       // [buf][term][n tile][lane]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int64_t r0 = (int64_t)blockIdx.x * 128 + wave * 32;
+    const int64_t jt0 = (int64_t)blockIdx.z * NB;  // first 16-wide n tile
+    const int64_t k_begin = 1 + (int64_t)blockIdx.y * lps;
+    const int64_t k_end = (k_begin + lps < kmax + 1) ? k_begin + lps : kmax + 1;
+    const int64_t nks = (ne + KS - 1) / KS;
+    const int64_t nkc = ld / KS;
+    const int64_t total = (k_end > k_begin ? k_end - k_begin : 0) * nks;
+    const int64_t slot_elems = (nrp / 16) * nkc * 3 * 512;
+    const int64_t lag_stride = PAIR ? ((ne + 15) / 16) * 16 * ld * 2 : ne * ld;
+    f4_t acc[2][NB];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc[rt][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+    u4_t ah[DA][2], al[DA][2], breg[BPT];
+    // step cursors (lag, 32-column chunk), advanced without divisions
+    struct Cur {
+        int64_t k, kc;
+    };
+    auto advance = [&](Cur &c) {
+        if (++c.kc == nks) {
+            c.kc = 0;
+            ++c.k;
+        }
+    };
+    auto load_a = [&](const Cur &c, u4_t *h, u4_t *l) {
+        const uint16_t *Tk = slabs + (c.k - 1) * lag_stride;
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) {
+            const int64_t row0 = r0 + 16 * rt;
+            if (c.k < k_end && row0 < ne) {
+                if constexpr (PAIR) {
+                    const uint16_t *tile = Tk + (((row0 >> 4) * nkc + c.kc) * 2) * 512 + lane * 8;
+                    h[rt] = __builtin_nontemporal_load(reinterpret_cast<const u4_t *>(tile));
+                    l[rt] = __builtin_nontemporal_load(reinterpret_cast<const u4_t *>(tile + 512));
+                } else {
+                    const int64_t row = row0 + lr, col = c.kc * KS + 8 * lk;
+                    h[rt] = (row < ne && col < ne)
+                                ? mask_cols(__builtin_nontemporal_load(reinterpret_cast<const u4_t *>(Tk + row * ld + col)),
+                                            col, ne)
+                                : u4_t{0u, 0u, 0u, 0u};
+                }
+            } else {
+                h[rt] = u4_t{0u, 0u, 0u, 0u};
+                if (PAIR) l[rt] = u4_t{0u, 0u, 0u, 0u};
+            }
+        }
+    };
+    int64_t yslot_k = -1;
+    const uint16_t *Y = ringb;
+    auto load_b = [&](const Cur &c) {
+        if (c.k != yslot_k) {  // lag change: ring slot of y_{i-k}
+            yslot_k = c.k;
+            Y = ringb + ((head + c.k - 1) % n_slots) * slot_elems;
+        }
+#pragma unroll
+        for (int q = 0; q < BPT; ++q) {
+            const int e = tid + 256 * q, j = e / (NP * 64), p = (e / 64) % NP, ln = e % 64;
+            const int64_t jt = jt0 + j, first = c.kc * KS + 8 * (ln >> 4);
+            breg[q] = (jt < nrp / 16 && first < ne)
+                          ? mask_cols(*reinterpret_cast<const u4_t *>(Y + ((jt * nkc + c.kc) * 3 + p) * 512 + ln * 8),
+                                      first, ne)
+                          : u4_t{0u, 0u, 0u, 0u};
+        }
+    };
+    auto store_b = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < BPT; ++q) {
+            const int e = tid + 256 * q, j = e / (NP * 64), p = (e / 64) % NP, ln = e % 64;
+            Bs[buf][p][j][ln] = breg[q];
+        }
+    };
+    Cur ca{k_begin, 0}, cb{k_begin, 0};
+    if (total > 0) {
+#pragma unroll
+        for (int u = 0; u < DA; ++u) {
+            load_a(ca, ah[u], al[u]);
+            advance(ca);
+        }
+        load_b(cb);
+        advance(cb);
+        store_b(0);
+    }
+    __syncthreads();
+    int64_t kcur = k_begin, kccur = 0;  // step being multiplied
+    for (int64_t t0 = 0; t0 < total; t0 += DA) {
+#pragma unroll
+        for (int u = 0; u < DA; ++u) {
+            const int64_t t = t0 + u;
+            if (t >= total) break;
+            const int buf = (int)(t & 1);
+            const bool more = t + 1 < total;
+            if (more) {
+                load_b(cb);
+                advance(cb);
+            }
+            if (!PAIR && scales && t > 0 && kccur == 0) {  // lag change: keep units of the current scale
+                const float ratio = scales[kcur - 2] / scales[kcur - 1];
+#pragma unroll
+                for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) acc[rt][j] *= ratio;
+            }
+            bf8_t a_h[2], a_l[2];
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt) {
+                a_h[rt] = __builtin_bit_cast(bf8_t, ah[u][rt]);
+                if (PAIR) a_l[rt] = __builtin_bit_cast(bf8_t, al[u][rt]);
+            }
+            // product-major order over groups of JB n tiles: 2 * JB independent
+            // accumulators between two products into the same one
+#pragma unroll
+            for (int jb = 0; jb < NB; jb += JB) {
+                bf8_t b_h[JB], b_m[JB], b_l[JB];
+#pragma unroll
+                for (int jj = 0; jj < JB; ++jj) {
+                    b_h[jj] = __builtin_bit_cast(bf8_t, Bs[buf][0][jb + jj][lane]);
+                    b_m[jj] = __builtin_bit_cast(bf8_t, Bs[buf][1][jb + jj][lane]);
+                    if (PAIR) b_l[jj] = __builtin_bit_cast(bf8_t, Bs[buf][2][jb + jj][lane]);
+                }
+#pragma unroll
+                for (int jj = 0; jj < JB; ++jj)
+#pragma unroll
+                    for (int rt = 0; rt < 2; ++rt)
+                        acc[rt][jb + jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h[rt], b_h[jj], acc[rt][jb + jj], 0, 0, 0);
+#pragma unroll
+                for (int jj = 0; jj < JB; ++jj)
+#pragma unroll
+                    for (int rt = 0; rt < 2; ++rt)
+                        acc[rt][jb + jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h[rt], b_m[jj], acc[rt][jb + jj], 0, 0, 0);
+                if constexpr (PAIR) {
+#pragma unroll
+                    for (int jj = 0; jj < JB; ++jj)
+#pragma unroll
+                        for (int rt = 0; rt < 2; ++rt)
+                            acc[rt][jb + jj] =
+                                __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_l[rt], b_h[jj], acc[rt][jb + jj], 0, 0, 0);
+#pragma unroll
+                    for (int jj = 0; jj < JB; ++jj)
+#pragma unroll
+                        for (int rt = 0; rt < 2; ++rt)
+                            acc[rt][jb + jj] =
+                                __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h[rt], b_l[jj], acc[rt][jb + jj], 0, 0, 0);
+#pragma unroll
+                    for (int jj = 0; jj < JB; ++jj)
+#pragma unroll
+                        for (int rt = 0; rt < 2; ++rt)
+                            acc[rt][jb + jj] =
+                                __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_l[rt], b_m[jj], acc[rt][jb + jj], 0, 0, 0);
+                }
+            }
+            load_a(ca, ah[u], al[u]);  // this stage's registers are free again
+            advance(ca);
+            if (more) store_b(buf ^ 1);
+            if (++kccur == nks) {
+                kccur = 0;
+                ++kcur;
+            }
+            __syncthreads();
+        }
+    }
+    const float last = (!PAIR && scales && total > 0) ? scales[k_end - 2] : 1.f;
+    float *out = partial + (int64_t)blockIdx.y * ne * nrhs;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = r0 + 16 * rt + 4 * lk + r, n = 16 * (jt0 + j) + lr;
+                if (row < ne && n < nrhs) out[row * nrhs + n] = last * acc[rt][j][r];
+            }
+}
+
+// y [ne][nrhs] (FP64) -> the slot's three BF16 terms hi, mid, lo, each the
+// rounding of what the previous ones leave, in MFMA operand order
+__global__ void k_store_ybf(int64_t ne, int64_t nrhs, int64_t nrp, int64_t ld, const double *y, uint16_t *slot)
+{
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= ne * nrhs) return;
+    const int64_t i = idx / nrhs, n = idx % nrhs;
+    double v = y[idx];
+    for (int p = 0; p < 3; ++p) {
+        const uint16_t h = f32_to_bf16((float)v);
+        slot[packed_index(n, i, ld, p, 3)] = h;
+        v -= (double)bf16_to_f32(h);
+    }
+    (void)nrp;
+}
+void launch_store_ybf(hipStream_t s, int64_t ne, int64_t nrhs, int64_t nrp, int64_t ld, const double *y,
+                      uint16_t *slot)
+{
+    hipLaunchKernelGGL(k_store_ybf, dim3(nblk(ne * nrhs, 256)), dim3(256), 0, s, ne, nrhs, nrp, ld, y, slot);
+}
+
+int64_t ring_bf16_rows(int64_t nrhs) { return (nrhs + 15) / 16 * 16; }
+
+int hist_splits(int64_t ne, int64_t kmax, int64_t nrhs, int32_t precision)
+{
+    if (nrhs > 1 && (precision == QHP_BF16 || precision == QHP_BF16X2)) {
+        // matrix-core tiles of 128 rows x 128 right-hand sides: about eight
+        // rounds of two resident work-groups per CU keep the last round short
+        const int64_t tiles = ((ne + 127) / 128) * ((ring_bf16_rows(nrhs) + 127) / 128);
+        int64_t want = (8 * 512 + tiles - 1) / tiles;
+        return (int)(want < 1 ? 1 : (want > kmax ? kmax : want));
+    }
     // enough blocks to fill 256 CUs several times over
     int64_t rowblocks = nrhs == 1 ? (ne + 15) / 16 : ((ne + 63) / 64) * ((nrhs + 63) / 64);
     int64_t want = (8 * 256 + rowblocks - 1) / rowblocks;
@@ -471,13 +736,20 @@ void launch_history(hipStream_t s, int32_t precision, int64_t ne, int64_t ld, in
                            (int64_t)1, (const double *)acc, r, b);
         return;
     }
-    dim3 grid(nblk(ne, 64), (unsigned)nsplit, nblk(nrhs, 64));
-    if (precision == QHP_BF16)
-        hipLaunchKernelGGL(k_hist_gemm<uint16_t>, grid, dim3(256), 0, s, ne, ld, nrhs, kmax, lps,
-                           (const uint16_t *)slabs, scales, (const float *)ring, n_slots, head, (float *)partial);
-    else
+    if (precision == QHP_BF16 || precision == QHP_BF16X2) {
+        const int64_t nrp = ring_bf16_rows(nrhs);
+        dim3 gm(nblk(ne, 128), (unsigned)nsplit, nblk(nrp, 128));
+        if (precision == QHP_BF16X2)
+            hipLaunchKernelGGL(k_hist_mfma<true>, gm, dim3(256), 0, s, ne, ld, nrp, nrhs, kmax, lps,
+                               (const uint16_t *)slabs, nullptr, (const uint16_t *)ring, n_slots, head, (float *)partial);
+        else
+            hipLaunchKernelGGL(k_hist_mfma<false>, gm, dim3(256), 0, s, ne, ld, nrp, nrhs, kmax, lps,
+                               (const uint16_t *)slabs, scales, (const uint16_t *)ring, n_slots, head, (float *)partial);
+    } else {
+        dim3 grid(nblk(ne, 64), (unsigned)nsplit, nblk(nrhs, 64));
         hipLaunchKernelGGL(k_hist_gemm<float>, grid, dim3(256), 0, s, ne, ld, nrhs, kmax, lps, (const float *)slabs,
                            scales, (const float *)ring, n_slots, head, (float *)partial);
+    }
     if (e1) (void)hipEventRecord(e1, s);
     hipLaunchKernelGGL(k_hist_finish<float>, dim3(nblk(ne * nrhs, 256)), dim3(256), 0, s, ne * nrhs,
                        (int64_t)nsplit, (const float *)partial, r, b);
@@ -693,11 +965,13 @@ __global__ void k_quantise_slab(int64_t ne, int64_t ld, const double *T, int64_t
                                 int32_t precision, float scale, float inv_scale, void *out)
 {
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= ne * ld) return;
+    if (idx >= slab_rows(precision, ne) * ld) return;
     int64_t i = idx / ld, j = idx % ld;
-    if (j >= ne) {
+    if (j >= ne || i >= ne) {
         if (precision == QHP_F64) ((double *)out)[idx] = 0.0;
         else if (precision == QHP_BF16) ((uint16_t *)out)[idx] = 0;
+        else if (precision == QHP_BF16X2)
+            ((uint16_t *)out)[packed_index(i, j, ld, 0, 2)] = ((uint16_t *)out)[packed_index(i, j, ld, 1, 2)] = 0;
         else ((float *)out)[idx] = 0.0f;
         return;
     }
@@ -711,21 +985,25 @@ __global__ void k_quantise_slab(int64_t ne, int64_t ld, const double *T, int64_t
         float f = (float)v;
         ((float *)out)[idx] = f;
         kept = (double)f;
+    } else if (precision == QHP_BF16X2) {  // hi and lo planes, in MFMA operand order
+        const uint16_t h = f32_to_bf16((float)v);
+        const double hv = (double)bf16_to_f32(h);
+        const uint16_t l = f32_to_bf16((float)(v - hv));
+        ((uint16_t *)out)[packed_index(i, j, ld, 0, 2)] = h;
+        ((uint16_t *)out)[packed_index(i, j, ld, 1, 2)] = l;
+        kept = hv + (double)bf16_to_f32(l);
     } else {
-        float f = (float)v * inv_scale;
-        uint32_t u = __float_as_uint(f);
-        uint32_t rounding = 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
-        uint16_t h = (uint16_t)((u + rounding) >> 16);
+        const uint16_t h = f32_to_bf16((float)v * inv_scale);
         ((uint16_t *)out)[idx] = h;
-        kept = (double)__uint_as_float((uint32_t)h << 16) * (double)scale;
+        kept = (double)bf16_to_f32(h) * (double)scale;
     }
     if (carry) carry[i * ne + j] = v - kept;
 }
 void launch_quantise_slab(hipStream_t s, int64_t ne, int64_t ld, const double *T, int64_t ldt, double *carry,
                           int32_t precision, float scale, void *out)
 {
-    hipLaunchKernelGGL(k_quantise_slab, dim3(nblk(ne * ld, 256)), dim3(256), 0, s, ne, ld, T, ldt, carry, precision,
-                       scale, 1.0f / scale, out);
+    hipLaunchKernelGGL(k_quantise_slab, dim3(nblk(slab_rows(precision, ne) * ld, 256)), dim3(256), 0, s, ne, ld, T,
+                       ldt, carry, precision, scale, 1.0f / scale, out);
 }
 // max |T + carry| over an [ne] x [ne] block whose rows have stride ldt
 __global__ void k_absmax(int64_t ne, const double *T, int64_t ldt, const double *carry, unsigned long long *out)
@@ -755,6 +1033,9 @@ __global__ void k_load_slab(int64_t ne, int64_t ld, const void *in, int32_t prec
     double v;
     if (precision == QHP_F64) v = ((const double *)in)[o];
     else if (precision == QHP_F32 || precision == QHP_F32A) v = ((const float *)in)[o];
+    else if (precision == QHP_BF16X2)
+        v = (double)bf16_to_f32(((const uint16_t *)in)[packed_index(i, j, ld, 0, 2)]) +
+            (double)bf16_to_f32(((const uint16_t *)in)[packed_index(i, j, ld, 1, 2)]);
     else v = (double)bf16_to_f32(((const uint16_t *)in)[o]) * (double)scale;  // exact product
     T[idx] = v;
 }

@@ -192,8 +192,8 @@ def test_march_reduced_precision_bounds(small, precision):
 
 
 def test_batched_march_parity():
-    """Three waves (a ragged tile of the batched history kernel), FP64 and
-    FP32 storage, torus with two global loops."""
+    """Three waves (a ragged tile of the batched history kernels), FP64,
+    FP32, BF16 and BF16-pair storage, torus with two global loops."""
     from oracle import operators as O, excitation as E, mot
     from workloads import meshes, waves
     xyz, tri = meshes.torus(1.0, 0.4, 12, 6)
@@ -204,7 +204,7 @@ def test_batched_march_parity():
     r = np.stack([E.rhs(asm, w, n) for w in ws], axis=-1)
     y = mot.march(asm.T, r)
     jref = mot.currents(asm.proj.PLH, asm.proj.PS, asm.dtn, y)
-    for precision, bound in (("f64", 1e-10), ("f32", 5e-4), ("bf16", 6e-2)):
+    for precision, bound in (("f64", 1e-10), ("f32", 5e-4), ("bf16", 6e-2), ("bf16x2", 5e-4)):
         j = _march_gpu(xyz, tri, dt, ws, n, precision)
         err = float(np.abs(j - jref).max() / np.abs(jref).max())
         _say("[torus batched] %s: current err %.3e" % (precision, err))
@@ -231,44 +231,83 @@ def _bf16_round(x):
     return t, t.to(torch.float64).numpy()
 
 
+def _pack_operand(planes):
+    """[P][R][ld] BF16 planes (R a multiple of 16, ld of 32) -> the matrix-core
+    operand order [R / 16][ld / 32][P][512]: lane r + 16 q of a 16 x 32 tile
+    holds row r, columns 8 q .. 8 q + 7."""
+    P, R, ld = planes.shape
+    x = planes.reshape(P, R // 16, 16, ld // 32, 4, 8)      # p, rt, r, kc, q, e
+    return x.permute(1, 3, 0, 4, 2, 5).contiguous().reshape(R // 16, ld // 32, P, 512)
+
+
 @pytest.mark.parametrize("precision,nrhs", [("f64", 1), ("f32", 1), ("f32a", 1), ("bf16", 1),
-                                            ("f64", 70), ("f32", 70), ("bf16", 70)])
+                                            ("f64", 70), ("f32", 70), ("bf16", 70), ("bf16x2", 70),
+                                            ("bf16x2", 130)])
 def test_history_sum_kernel_ragged(precision, nrhs):
     """b = r - sum_k T_k y_{i-k} through qhp_history_sum: ragged sizes (rows
     not a multiple of any tile), padded rows with garbage in the padding,
     circular ring with a head offset."""
     import paper_2312_06367_amd as qhp
     rng = np.random.default_rng(11)
-    ne, ld, kmax, n_slots, head = 1003, 1016, 5, 7, 3
+    ne, ld, kmax, n_slots, head = 1003, 1024 if precision == "bf16x2" or (precision == "bf16" and nrhs > 1) else 1016, 5, 7, 3
     T = rng.standard_normal((kmax, ne, ld))
     T[:, :, ne:] = 1e6  # padding must be ignored
     Y = rng.standard_normal((n_slots, ld, nrhs))
     Y[:, ne:, :] = 1e6
     r = rng.standard_normal((ne, nrhs))
     dev = "cuda"
+    Tlo = np.zeros_like(T)
     if precision == "bf16":
         scales = np.abs(T[:, :, :ne]).max(axis=(1, 2)).astype(np.float32)
         tq, tdq = _bf16_round(T / scales[:, None, None])
         slabs = tq.to(dev)
         Teff = tdq * scales[:, None, None].astype(np.float64)
         sc = torch.from_numpy(scales).to(dev)
+    elif precision == "bf16x2":  # hi and lo planes of each block, operand order, zero padding
+        T[:, :, ne:] = 0.0
+        thi, thi64 = _bf16_round(T)
+        tlo, tlo64 = _bf16_round(T - thi64)
+        rp = (ne + 15) // 16 * 16
+        pl = torch.zeros((kmax, 2, rp, ld), dtype=torch.bfloat16)
+        pl[:, 0, :ne] = thi
+        pl[:, 1, :ne] = tlo
+        slabs = torch.stack([_pack_operand(pl[k]) for k in range(kmax)]).to(dev)
+        Teff, Tlo = thi64, tlo64
+        sc = None
     else:
         dt_ = torch.float64 if precision == "f64" else torch.float32
         slabs = torch.from_numpy(T).to(dt_).to(dev)
         Teff = slabs.to(torch.float64).cpu().numpy()
         sc = None
-    ydt = torch.float64 if precision in ("f64", "f32a") else torch.float32
-    ring = torch.from_numpy(Y).to(ydt).to(dev)
-    Yeff = ring.to(torch.float64).cpu().numpy()
+    Ylo = np.zeros_like(Y)
+    if precision in ("bf16x2",) or (precision == "bf16" and nrhs > 1):
+        # y as two transposed BF16 planes per slot, right-hand sides padded to 16
+        nrp = (nrhs + 15) // 16 * 16
+        yhi, yhi64 = _bf16_round(Y)
+        ymid, ymid64 = _bf16_round(Y - yhi64)
+        ylo, ylo64 = _bf16_round(Y - yhi64 - ymid64)
+        planes = torch.zeros((n_slots, 3, nrp, ld), dtype=torch.bfloat16)
+        for p_, t_ in enumerate((yhi, ymid, ylo)):
+            planes[:, p_, :nrhs, :] = t_.permute(0, 2, 1)
+        ring = torch.stack([_pack_operand(planes[q]) for q in range(n_slots)]).to(dev)
+        # products kept: T_hi (hi + mid + lo) + T_lo (hi + mid); BF16: T (hi + mid)
+        Yeff, Ylo = yhi64 + ymid64 + ylo64, yhi64 + ymid64
+        if precision == "bf16":
+            Yeff, Ylo = yhi64 + ymid64, np.zeros_like(Y)
+    else:
+        ydt = torch.float64 if precision in ("f64", "f32a") else torch.float32
+        ring = torch.from_numpy(Y).to(ydt).to(dev)
+        Yeff = ring.to(torch.float64).cpu().numpy()
     rt = torch.from_numpy(r).to(dev)
     b = torch.zeros_like(rt)
     qhp.history_sum(precision, slabs, sc, ring, head, rt, b, kmax=kmax)
     torch.cuda.synchronize()
     ref = r.copy()
     for k in range(1, kmax + 1):
-        ref -= Teff[k - 1][:, :ne] @ Yeff[(head + k - 1) % n_slots][:ne]
+        s_ = (head + k - 1) % n_slots
+        ref -= Teff[k - 1][:, :ne] @ Yeff[s_][:ne] + Tlo[k - 1][:, :ne] @ Ylo[s_][:ne]
     err = float(np.abs(b.cpu().numpy() - ref).max() / np.abs(ref).max())
-    bound = {"f64": 1e-13, "f32a": 1e-13, "f32": 2e-5, "bf16": 2e-5}[precision]
+    bound = {"f64": 1e-13, "f32a": 1e-13, "f32": 2e-5, "bf16": 2e-5, "bf16x2": 2e-5}[precision]
     _say("[history_sum %s nrhs=%d] err %.3e" % (precision, nrhs, err))
     assert err < bound
 
