@@ -239,32 +239,45 @@ def bench_warm(a):
     D = 2.0 if a.mesh == "sphere" else 2.6
     train = waves.batched_waves(a.train_dirs, 0, w0.f0, w0.bw, D, both_pols=False)
     held = waves.batched_waves(a.eval_dirs, 1, w0.f0, w0.bw, D, both_pols=False)
+    # training marches: BF16-pair blocks on the matrix cores, all directions at once
     t0 = time.perf_counter()
-    sv = qhp.Solver(cfg.dt, precision="f64", solver="inv")
-    sv.mesh(xyz, tri)
-    sv.assemble()
-    inf = sv.info()
+    st = qhp.Solver(cfg.dt, precision="bf16x2", solver="inv")
+    st.mesh(xyz, tri)
+    st.assemble()
+    inf = st.info()
     ne, K = inf["ne"], inf["K"]
-    log("%s: ne=%d K=%d assembly %.1f s" % (cfg.name, ne, K, time.perf_counter() - t0))
-    sv.set_precision("f32")
+    log("%s: ne=%d K=%d assembly (BF16 pairs) %.1f s" % (cfg.name, ne, K, time.perf_counter() - t0))
     n_tr = a.train_steps
-    sv.set_incident(train, n_tr)
+    st.set_incident(train, n_tr)
     yh = torch.zeros((n_tr, ne, len(train)), dtype=torch.float64, device="cuda")
     t0 = time.perf_counter()
     for c0 in range(0, n_tr, 100):
         c1 = min(n_tr, c0 + 100)
-        sv.run(c1 - c0, None, yh[c0:c1])
+        st.run(c1 - c0, None, yh[c0:c1])
         torch.cuda.synchronize()
         log("training marches: %d / %d steps (%.0f s)" % (c1, n_tr, time.perf_counter() - t0))
     t_data = time.perf_counter() - t0
-    m = qhp.MLP(sv, hidden=256, seed=0)
+    mt = qhp.MLP(st, hidden=256, seed=0)
     t0 = time.perf_counter()
-    losses = [float(v) for v in m.train(yh, epochs=a.epochs, batch=512, lr=1e-3, seed=0)]
+    losses = []
+    for e0 in range(0, a.epochs, 2):  # two passes per call, progress between calls
+        losses += [float(v) for v in mt.train(yh, epochs=min(2, a.epochs - e0), batch=512, lr=1e-3, seed=e0)]
+        log("training: %d / %d epochs (%.0f s), loss %s" % (len(losses), a.epochs, time.perf_counter() - t0,
+                                                           " ".join("%.3e" % v for v in losses)))
     t_train = time.perf_counter() - t0
-    log("training: %d epochs %.1f s, loss %s" % (a.epochs, t_train, " ".join("%.3e" % v for v in losses)))
+    params = mt.get_params()
+    mt.close()
+    st.close()
     del yh
     torch.cuda.empty_cache()
-    sv.set_precision("f32a")
+    # held-out marches: FP32 blocks with FP64 sums, one wave at a time
+    t0 = time.perf_counter()
+    sv = qhp.Solver(cfg.dt, precision="f32a", solver="inv")
+    sv.mesh(xyz, tri)
+    sv.assemble()
+    log("assembly (FP32) %.1f s" % (time.perf_counter() - t0))
+    m = qhp.MLP(sv, hidden=256, seed=0)
+    m.set_params(params)
     sv.attach_mlp(m)
     n_ev = a.steps
     modes = {}
