@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0
+INT8_MFMA_PEAK_TOPS = 5000.0  # dense int8 matrix-core peak of the MI355X
 
 
 def parse():
@@ -43,7 +44,7 @@ def parse():
     ap.add_argument("--epochs", type=int, default=8, help="warm-start training passes")
     ap.add_argument("--eval-dirs", type=int, default=2, help="warm-start held-out directions")
     ap.add_argument("--scatterers", type=int, default=32, help="uneven-batch: march the first N of the 32")
-    ap.add_argument("--precision", default="f32a", choices=["f32", "f32a", "bf16", "bf16x2", "f64"],
+    ap.add_argument("--precision", default="f32a", choices=["f32", "f32a", "bf16", "bf16x2", "i8x4", "f64"],
                     help="slab storage / history arithmetic: f32a = FP32 blocks with FP64 y and sums")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 4 GiB device copy first (reference for profiler byte counters)")
@@ -381,7 +382,7 @@ def main():
         return d / torch.linalg.vector_norm(jref, dim=1).max().item()
 
     def gbps(prec, hist_ms):
-        esz = {"f64": 8, "f32": 4, "f32a": 4, "bf16": 2, "bf16x2": 4}[prec]
+        esz = {"f64": 8, "f32": 4, "f32a": 4, "bf16": 2, "bf16x2": 4, "i8x4": 4}[prec]
         ysz = 8 if prec in ("f64", "f32a") else 4
         return (K * ne * ne * esz + K * ne * n_rhs * ysz) / (hist_ms * 1e-3) / 1e9
 
@@ -412,7 +413,7 @@ def main():
                 s.set_precision(twin)
                 runs["%s_%s" % (twin, a.solver)] = march(twin, a.solver)
             if n_rhs > 1:  # the other multi-right-hand-side forms, each assembled in its own storage
-                for p in ("f32", "bf16", "bf16x2"):
+                for p in ("f32", "bf16", "bf16x2", "i8x4"):
                     if p == a.precision:
                         continue
                     sv = qhp.Solver(cfg.dt, precision=p, solver=a.solver)
@@ -424,7 +425,7 @@ def main():
         runs["head"] = runs["f64_" + a.solver]
     head = runs["head"]
     jref = runs["f64_lu"]["j"]
-    esz = {"f64": 8, "f32": 4, "f32a": 4, "bf16": 2, "bf16x2": 4}[a.precision]
+    esz = {"f64": 8, "f32": 4, "f32a": 4, "bf16": 2, "bf16x2": 4, "i8x4": 4}[a.precision]
     ysz = 8 if a.precision in ("f64", "f32a") else 4
     bytes_per_launch = K * ne * ne * esz + K * ne * n_rhs * ysz
     flops_per_launch = 2.0 * K * ne * ne * n_rhs
@@ -449,6 +450,19 @@ def main():
                 "kernel_ms_avg": head["hist_ms"],
                 "bf16_mfma_executed_tflops": executed, "bf16_mfma_frac": executed / BF16_MFMA_PEAK_TFLOPS,
                 "fp32_equivalent_tflops": flops_per_launch / (head["hist_ms"] * 1e-3) / 1e12}
+    elif a.precision == "i8x4":
+        # int8 matrix cores: 13 digit products per term, exact int32 sums per lag
+        kname = "k_hist_i8"
+        ops = 13 * flops_per_launch
+        achieved = ops / (head["hist_ms"] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": INT8_MFMA_PEAK_TOPS, "unit": "TOP/s",
+                "frac": achieved / INT8_MFMA_PEAK_TOPS, "traffic": traffic_from_profile(kname),
+                "kernel": kname, "algorithmic_int8_ops_per_launch": ops,
+                "kernel_ms_avg": head["hist_ms"],
+                "hbm_gbps": bytes_per_launch / (head["hist_ms"] * 1e-3) / 1e9,
+                "fp32_equivalent_tflops": flops_per_launch / (head["hist_ms"] * 1e-3) / 1e12,
+                "fp32_equivalent_frac_of_fp32_mfma_peak":
+                    flops_per_launch / (head["hist_ms"] * 1e-3) / 1e12 / FP32_MFMA_PEAK_TFLOPS}
     else:
         kname = "k_hist_gemm<float>"
         achieved = flops_per_launch / (head["hist_ms"] * 1e-3) / 1e12
@@ -475,7 +489,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"f32": "f32", "bf16": "bf16-storage/f32", "f32a": "f32-storage/f64-accumulate", "f64": "f64",
-                  "bf16x2": "bf16-pair-storage/bf16-mfma/f32-accumulate"}[a.precision],
+                  "bf16x2": "bf16-pair-storage/bf16-mfma/f32-accumulate",
+                  "i8x4": "int8-digit-storage/int8-mfma/exact-int32-per-lag/f64-across-lags"}[a.precision],
         "data": "synthetic",
         "config": {"workload": cfg.name, "ne": ne, "K": K, "c_dt_m": cfg.dt, "n_rhs": n_rhs,
                    "slab_storage": a.precision, "solve": "fp64-" + a.solver, "post_processing": "fp64"},

@@ -59,10 +59,18 @@ enum {
  *              as three BF16 terms, the five products of weight >= 2^-16
  *              on the BF16 matrix cores with FP32 sums (two or more
  *              right-hand sides)
+ *   QHP_I8X4   each block as four signed 8-bit digits of a 28-bit fixed-point
+ *              value per row, T_k(i, j) ~ s_ki (t0 + t1 2^-7 + t2 2^-14 +
+ *              t3 2^-21) with the FP64 row scale s_ki = max_j |T_k(i, j) + c|
+ *              / 127 (4 bytes per entry); y_{i-k} as four digits per column
+ *              with an FP64 column scale; the 13 digit products of weight
+ *              >= 2^-28 on the int8 matrix cores with exact int32 sums over
+ *              each lag, scaled and summed over lags in FP64 (two or more
+ *              right-hand sides, N_E <= 65536)
  * Reduced-precision blocks are rounded lag by lag with the rounding error of
  * each block carried into the next one (c_k = T_k + c_{k-1} - stored_k), so
  * every prefix sum over lags is within one rounding of the FP64 one. */
-enum { QHP_F64 = 0, QHP_F32 = 1, QHP_BF16 = 2, QHP_F32A = 3, QHP_BF16X2 = 4 };
+enum { QHP_F64 = 0, QHP_F32 = 1, QHP_BF16 = 2, QHP_F32A = 3, QHP_BF16X2 = 4, QHP_I8X4 = 5 };
 
 /* per-step solve with T_0 (the paper writes only T_0^{-1}, Sec. IV-B) */
 enum {
@@ -212,7 +220,13 @@ int qhp_keep_raw(qhp_ctx *ctx, int32_t keep);
  *   operand order, [ceil(ne / 16)][ld / 32][2][512] with entry (i, j) of
  *   plane p at ((i / 16 * ld / 32 + j / 32) * 2 + p) * 512
  *   + (i % 16 + 16 * (j % 32 / 8)) * 8 + j % 8, rows >= ne and columns >= ne
- *   zero; scales: [kmax] FP32 per-slab factors for QHP_BF16 (T_k = scale *
+ *   zero; for QHP_I8X4 ld is a multiple of 64 and each block is
+ *   R * ld * 4 bytes of digit planes followed by R FP64 row scales
+ *   (R = ne rounded up to 16): digit a (0..3, t0 first) of entry (i, j) is
+ *   the byte ((i / 16 * ld / 64 + j / 64) * 4 + a) * 1024
+ *   + (i % 16 + 16 * (j % 64 / 16)) * 16 + j % 16, digits of rows >= ne and
+ *   columns >= ne zero, t0 in [-127, 127], t1..t3 in [-64, 64];
+ *   scales: [kmax] FP32 per-slab factors for QHP_BF16 (T_k = scale *
  *   stored), else NULL;
  * ring: y_{i-k} is slot (head + k - 1) mod n_slots, n_slots >= kmax; a slot
  *   is [ld][nrhs] FP64 for QHP_F64 and QHP_F32A, [ld][nrhs] FP32 for QHP_F32
@@ -221,8 +235,13 @@ int qhp_keep_raw(qhp_ctx *ctx, int32_t keep);
  *   the rounding of what the previous ones leave, in the same operand order
  *   with y^T [nrp][ld] as the matrix ([nrp / 16][ld / 32][3][512], nrp = nrhs
  *   rounded up to 16; entries of columns >= ne are ignored, right-hand sides
- *   >= nrhs must be zero; QHP_BF16 reads hi and mid only);
- * r, b: [ne][nrhs] FP64.  nrhs >= 1 (>= 2 for QHP_BF16X2, 1 for QHP_F32A).
+ *   >= nrhs must be zero; QHP_BF16 reads hi and mid only); for QHP_I8X4 a
+ *   slot is P * ld * 4 bytes of digit planes of y^T (P = nrhs rounded up to
+ *   16; entry (n, j) placed as entry (i, j) of a block) followed by P FP64
+ *   column scales, y(j, n) ~ scale_n (u0 + u1 2^-7 + u2 2^-14 + u3 2^-21),
+ *   digits of columns j >= ne and of right-hand sides >= nrhs zero;
+ * r, b: [ne][nrhs] FP64.  nrhs >= 1 (>= 2 for QHP_BF16X2 and QHP_I8X4, 1 for
+ * QHP_F32A).
  * The call allocates and frees a scratch buffer of partial sums (QHP_ENOMEM
  * if it cannot) and returns when the stream has finished the work. */
 int qhp_history_sum(void *stream, int32_t precision, int64_t ne, int64_t ld, int64_t nrhs,

@@ -15,14 +15,15 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqhp.so")
 
-QHP_F64, QHP_F32, QHP_BF16, QHP_F32A, QHP_BF16X2 = 0, 1, 2, 3, 4
+QHP_F64, QHP_F32, QHP_BF16, QHP_F32A, QHP_BF16X2, QHP_I8X4 = 0, 1, 2, 3, 4, 5
 QHP_SOLVE_LU, QHP_SOLVE_INV, QHP_SOLVE_GMRES = 0, 1, 2
 WARM = {"cold": 0, "prev": 1, "extrap": 2, "quad": 3, "mlp": 4}
 MAT = {"gram": 0, "zs": 1, "zh": 2, "m": 3, "psigma": 4, "plambda": 5, "pe": 6, "pm": 7,
        "slab": 8, "a": 9, "b": 10, "c": 11}
 ERRORS = {0: "OK", -1: "EINVAL", -2: "EMESH", -3: "ESTATE", -4: "ENOMEM", -5: "EDEVICE",
           -6: "ESINGULAR", -7: "ENOCONV", -8: "EUNSTABLE"}
-PRECISIONS = {"f64": QHP_F64, "f32": QHP_F32, "bf16": QHP_BF16, "f32a": QHP_F32A, "bf16x2": QHP_BF16X2}
+PRECISIONS = {"f64": QHP_F64, "f32": QHP_F32, "bf16": QHP_BF16, "f32a": QHP_F32A, "bf16x2": QHP_BF16X2,
+              "i8x4": QHP_I8X4}
 SOLVERS = {"lu": QHP_SOLVE_LU, "inv": QHP_SOLVE_INV, "gmres": QHP_SOLVE_GMRES}
 
 
@@ -271,14 +272,20 @@ def history_sum(precision: str, slabs, scales, ring, head: int, r, b, kmax: int 
     """b = r - sum_{k=1}^{kmax} T_k y_{i-k} on caller tensors (see qhp_history_sum).
 
     slabs: [kmax, ne, ld] (float64 / float32 / bfloat16) or, for bf16x2,
-    [kmax, ceil(ne/16), ld/32, 2, 512] bfloat16 in matrix-core operand order;
-    scales: float32 [kmax] (bf16 only); ring: [n_slots, ld, nrhs] float64
-    (f64, f32a) or float32, or [n_slots, nrp/16, ld/32, 3, 512] bfloat16
-    (bf16 with nrhs > 1, bf16x2); r, b: float64 [ne, nrhs]."""
+    [kmax, ceil(ne/16), ld/32, 2, 512] bfloat16 in matrix-core operand order,
+    or, for i8x4, [kmax, block bytes] int8 (digit planes then FP64 row
+    scales); scales: float32 [kmax] (bf16 only); ring: [n_slots, ld, nrhs]
+    float64 (f64, f32a) or float32, [n_slots, nrp/16, ld/32, 3, 512]
+    bfloat16 (bf16 with nrhs > 1, bf16x2) or [n_slots, slot bytes] int8
+    (i8x4); r, b: float64 [ne, nrhs]."""
     L = lib()
     kmax = slabs.shape[0] if kmax is None else kmax
     if precision == "bf16x2":  # operand-ordered planes: ld from the tile count, ne from r
         ne, ld = r.shape[0], slabs.shape[2] * 32
+    elif precision == "i8x4":  # block bytes = R * ld * 4 + R * 8, R = ne rounded up to 16
+        ne = r.shape[0]
+        R = (ne + 15) // 16 * 16
+        ld = (slabs.shape[-1] - 8 * R) // (4 * R)
     else:
         ne, ld = slabs.shape[-2], slabs.shape[-1]
     nrhs = r.shape[1] if r.dim() == 2 else 1

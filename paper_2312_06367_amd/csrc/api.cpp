@@ -70,7 +70,7 @@ int guard(qhp_ctx *ctx, int code, const std::string &msg)
 extern "C" int qhp_create(const qhp_params *params, qhp_ctx **out)
 {
     if (!params || !out) return QHP_EINVAL;
-    if (!(params->dt > 0.0) || params->precision < QHP_F64 || params->precision > QHP_BF16X2 ||
+    if (!(params->dt > 0.0) || params->precision < QHP_F64 || params->precision > QHP_I8X4 ||
         params->solver < QHP_SOLVE_LU || params->solver > QHP_SOLVE_INV || params->n_psi > 32)
         return QHP_EINVAL;
     int ndev = 0;
@@ -202,6 +202,10 @@ static float store_lag(hipStream_t s, int64_t ne, int64_t ld, const double *T, i
                        int32_t prec, DBuf &amax, void *out)
 {
     float sc = 1.0f;
+    if (prec == QHP_I8X4) {
+        qhp::launch_i8_quantise(s, ne, ld, T, ldt, carry, (int8_t *)out);
+        return sc;
+    }
     if (prec == QHP_BF16) {
         unsigned long long bits = 0;
         zero(amax, s);
@@ -322,9 +326,8 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
     // ---- lag blocks T_0..T_K (Sec. IV-A) in chunks of lags
     const int64_t K = c->K;
     const int32_t prec = c->p.precision;
-    const size_t esz = prec == QHP_F64 ? 8 : (prec == QHP_BF16 ? 2 : 4);
-    const size_t blk = (size_t)qhp::slab_rows(prec, ne) * c->ld;  // entries of one stored block
-    c->slabs.alloc(esz * (size_t)K * blk);
+    const size_t blk = (size_t)qhp::slab_bytes(prec, ne, c->ld);  // bytes of one stored block
+    c->slabs.alloc((size_t)K * blk);
     c->scales.assign(K, 1.0f);
     c->T0raw.alloc(sizeof(double) * nn);
     if (c->keep_raw) {
@@ -405,7 +408,7 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
                     hip_check(hipMemcpyAsync(c->T0raw.p, Tt.p, sizeof(double) * nn, hipMemcpyDeviceToDevice, s), "copy");
                 } else {
                     c->scales[k - 1] = store_lag(s, ne, c->ld, Tt.as<double>(), ne, carry.as<double>(), prec, amax,
-                                                 (char *)c->slabs.p + esz * (size_t)(k - 1) * blk);
+                                                 (char *)c->slabs.p + (size_t)(k - 1) * blk);
                 }
                 std::swap(Ap.p, Ak.p);
                 std::swap(Cp.p, Ck.p);
@@ -505,6 +508,10 @@ extern "C" int qhp_set_incident(qhp_ctx *ctx, const qhp_wave *waves, int32_t n_r
     if (ctx->p.solver == QHP_SOLVE_GMRES && n_rhs != 1) return guard(ctx, QHP_EINVAL, "GMRES takes one right-hand side");
     if (ctx->p.precision == QHP_BF16X2 && n_rhs < 2)
         return guard(ctx, QHP_EINVAL, "QHP_BF16X2 takes two or more right-hand sides");
+    if (ctx->p.precision == QHP_I8X4 && n_rhs < 2)
+        return guard(ctx, QHP_EINVAL, "QHP_I8X4 takes two or more right-hand sides");
+    if (ctx->p.precision == QHP_I8X4 && ctx->mesh.ne > 65536)
+        return guard(ctx, QHP_EINVAL, "QHP_I8X4 takes at most 65536 edges (int32 sums)");
     API_TRY
     qhp_ctx *c = ctx;
     hip_check(hipSetDevice(c->p.device), "hipSetDevice");
@@ -554,6 +561,11 @@ extern "C" int qhp_set_incident(qhp_ctx *ctx, const qhp_wave *waves, int32_t n_r
         c->ringb.alloc(sizeof(uint16_t) * K * 3 * qhp::ring_bf16_rows(n_rhs) * ld);
         zero(c->ringb, s);
     }
+    c->ring8.release();
+    if (c->p.precision == QHP_I8X4) {
+        c->ring8.alloc((size_t)K * qhp::i8_slot_bytes(n_rhs, ld));
+        zero(c->ring8, s);
+    }
     c->bvec.alloc(sizeof(double) * ne * n_rhs);
     c->zvec.alloc(sizeof(double) * ne * n_rhs);
     c->yvec.alloc(sizeof(double) * ne * n_rhs);
@@ -596,7 +608,8 @@ static void do_step(qhp_ctx *c, double *j_out, double *y_out)
     }
     qhp::launch_history(s, c->p.precision, ne, ld, nr, K, c->slabs.p,
                         c->p.precision == QHP_BF16 ? c->scales_d.as<float>() : nullptr,
-                        c->ringb.p ? c->ringb.p : (c->ring32.p ? c->ring32.p : c->ring64.p), K, c->head, r_i,
+                        c->ring8.p ? c->ring8.p : (c->ringb.p ? c->ringb.p : (c->ring32.p ? c->ring32.p : c->ring64.p)),
+                        K, c->head, r_i,
                         c->bvec.as<double>(), c->partial.p, c->nsplit, e0, e1, c->hv);
     double *y = c->yvec.as<double>();
     if (c->p.solver == QHP_SOLVE_GMRES) {
@@ -642,6 +655,7 @@ static void do_step(qhp_ctx *c, double *j_out, double *y_out)
         const int64_t nrp = qhp::ring_bf16_rows(nr);
         qhp::launch_store_ybf(s, ne, nr, nrp, ld, y, c->ringb.as<uint16_t>() + slot * 3 * nrp * ld);
     }
+    if (c->ring8.p) qhp::launch_i8_store_y(s, ne, nr, ld, y, c->ring8.as<int8_t>() + slot * qhp::i8_slot_bytes(nr, ld));
     if (c->p.solver == QHP_SOLVE_GMRES) qhp::warm_record(c, y);
     c->head = slot;
     c->step = i;
@@ -763,26 +777,26 @@ extern "C" int qhp_set_precision(qhp_ctx *ctx, int32_t precision)
         ctx->p.precision = precision;
         ctx->ring32.release();
         ctx->ringb.release();
+        ctx->ring8.release();
         ctx->state = 2;
         return QHP_OK;
     }
-    if (ctx->p.precision != QHP_F64 ||
-        (precision != QHP_F32 && precision != QHP_BF16 && precision != QHP_F32A && precision != QHP_BF16X2))
-        return guard(ctx, QHP_EINVAL, "only FP64 slabs can be re-stored, as FP32, BF16 or BF16 pairs");
+    if (ctx->p.precision != QHP_F64 || (precision != QHP_F32 && precision != QHP_BF16 && precision != QHP_F32A &&
+                                        precision != QHP_BF16X2 && precision != QHP_I8X4))
+        return guard(ctx, QHP_EINVAL, "only FP64 slabs can be re-stored, as FP32, BF16, BF16 pairs or int8 digits");
     API_TRY
     hipStream_t s = ctx->s;
     const int64_t ne = ctx->mesh.ne, ld = ctx->ld, K = ctx->K;
-    const size_t per = (size_t)ne * ld;                              // FP64 source block
-    const size_t blk = (size_t)qhp::slab_rows(precision, ne) * ld;  // stored block
-    const size_t esz = precision == QHP_BF16 ? 2 : 4;
+    const size_t per = (size_t)ne * ld;                               // FP64 source block
+    const size_t blk = (size_t)qhp::slab_bytes(precision, ne, ld);  // bytes of one stored block
     DBuf out, amax, carry;
-    out.alloc(esz * blk * K);
+    out.alloc(blk * K);
     amax.alloc(sizeof(unsigned long long));
     carry.alloc(sizeof(double) * ne * ne);
     zero(carry, s);
     for (int64_t k = 0; k < K; ++k)
         ctx->scales[k] = store_lag(s, ne, ld, ctx->slabs.as<double>() + k * per, ld, carry.as<double>(), precision, amax,
-                                   (char *)out.p + esz * blk * k);
+                                   (char *)out.p + blk * k);
     hip_check(hipStreamSynchronize(s), "convert slabs");
     std::swap(ctx->slabs.p, out.p);
     std::swap(ctx->slabs.bytes, out.bytes);
@@ -790,6 +804,7 @@ extern "C" int qhp_set_precision(qhp_ctx *ctx, int32_t precision)
     ctx->p.precision = precision;
     ctx->ring32.release();
     ctx->ringb.release();
+    ctx->ring8.release();
     ctx->state = 2;
     return QHP_OK;
     API_CATCH(ctx)
@@ -855,10 +870,9 @@ extern "C" int qhp_get_matrix(const qhp_ctx *cc, int32_t which, int32_t k, doubl
         DBuf tmp;
         tmp.alloc(sizeof(double) * nn);
         const int32_t prec = ctx->p.precision;
-        const size_t esz = prec == QHP_F64 ? 8 : (prec == QHP_BF16 ? 2 : 4);
-        qhp::launch_load_slab(ctx->s, ne, ctx->ld,
-                              (const char *)ctx->slabs.p + esz * (size_t)(k - 1) * qhp::slab_rows(prec, ne) * ctx->ld,
-                              prec, ctx->scales[k - 1], tmp.as<double>());
+        const char *blk = (const char *)ctx->slabs.p + (size_t)(k - 1) * qhp::slab_bytes(prec, ne, ctx->ld);
+        if (prec == QHP_I8X4) qhp::launch_i8_load(ctx->s, ne, ctx->ld, (const int8_t *)blk, tmp.as<double>());
+        else qhp::launch_load_slab(ctx->s, ne, ctx->ld, blk, prec, ctx->scales[k - 1], tmp.as<double>());
         hip_check(hipStreamSynchronize(ctx->s), "dequantise");
         hip_check(hipMemcpy(out, tmp.p, sizeof(double) * nn, hipMemcpyDeviceToHost), "copy");
         return QHP_OK;
@@ -885,8 +899,9 @@ extern "C" int qhp_history_sum(void *stream, int32_t precision, int64_t ne, int6
                                const void *slabs, const float *scales, const void *ring, int64_t n_slots, int64_t head,
                                const double *r, double *b)
 {
-    if (precision < QHP_F64 || precision > QHP_BF16X2 || ne < 1 || ld < ne || ld % 8 != 0 || nrhs < 1 || kmax < 0 ||
+    if (precision < QHP_F64 || precision > QHP_I8X4 || ne < 1 || ld < ne || ld % 8 != 0 || nrhs < 1 || kmax < 0 ||
         (precision == QHP_F32A && nrhs != 1) || (precision == QHP_BF16X2 && (nrhs < 2 || ld % 32 != 0)) ||
+        (precision == QHP_I8X4 && (nrhs < 2 || ld % 64 != 0 || ne > 65536)) ||
         (precision == QHP_BF16 && nrhs > 1 && ld % 32 != 0) ||
         n_slots < kmax || head < 0 || (kmax > 0 && (!slabs || !ring)) || !r || !b)
         return QHP_EINVAL;
@@ -1089,7 +1104,7 @@ extern "C" int qhp_batch_create(qhp_ctx *const *ctxs, int32_t n, qhp_batch **out
         if (c->p.device != c0->p.device || c->p.precision != c0->p.precision || c->nrhs != c0->nrhs)
             return guard(c0, QHP_EINVAL, "batch contexts must share device, precision and n_rhs");
     }
-    if (c0->p.precision == QHP_BF16 || c0->p.precision == QHP_BF16X2)
+    if (c0->p.precision == QHP_BF16 || c0->p.precision == QHP_BF16X2 || c0->p.precision == QHP_I8X4)
         return guard(c0, QHP_EINVAL, "the batch kernels take F64, F32 or F32A blocks");
     if (c0->nrhs != 1 && c0->nrhs != 2 && c0->nrhs != 4 && c0->nrhs != 8)
         return guard(c0, QHP_EINVAL, "batch n_rhs must be 1, 2, 4 or 8");

@@ -89,7 +89,7 @@ struct qhp_ctx {
     int32_t nrhs = 0;
     int64_t n_steps = 0, step = 0, head = 0;
     bool broken = false;
-    qhp::DBuf waves_d, rhs, ring64, ring32, ringb, bvec, zvec, yvec, partial, sv, zc, flags, epoch, errflag;
+    qhp::DBuf waves_d, rhs, ring64, ring32, ringb, ring8, bvec, zvec, yvec, partial, sv, zc, flags, epoch, errflag;
     int nsplit = 1;
     int hv = -1;  // autotuned variant of the single right-hand-side history kernel
     // profiling of the history kernel

@@ -7,6 +7,7 @@
 #include <cstdint>
 
 #include "../../include/qhp.h"
+#include "digits.h"
 
 namespace qhp {
 
@@ -16,14 +17,21 @@ __host__ __device__ inline int64_t slab_rows(int32_t precision, int64_t ne)
 {
     return precision == QHP_BF16X2 ? (ne + 15) / 16 * 16 : ne;
 }
+// bytes of one stored lag block
+__host__ __device__ inline int64_t slab_bytes(int32_t precision, int64_t ne, int64_t ld)
+{
+    if (precision == QHP_I8X4) return i8_block_bytes(ne, ld);
+    const int64_t esz = precision == QHP_F64 ? 8 : (precision == QHP_BF16 ? 2 : 4);
+    return esz * slab_rows(precision, ne) * ld;
+}
 // rows of each BF16 plane of a ring slot for the matrix-core history (nrhs padded to 16)
 int64_t ring_bf16_rows(int64_t nrhs);
 // y [ne][nrhs] FP64 -> slot planes hi, mid, lo (BF16) in MFMA operand order:
 // [nrp / 16][ld / 32][3][512] (see k_hist_mfma)
 void launch_store_ybf(hipStream_t s, int64_t ne, int64_t nrhs, int64_t nrp, int64_t ld, const double *y,
                       uint16_t *slot);
-// partial: scratch of nsplit * ne * nrhs accumulators (FP64 for QHP_F64 with
-// nrhs == 1, FP32 otherwise)
+// partial: scratch of nsplit * ne * nrhs accumulators (FP64 for QHP_F64,
+// QHP_F32A and QHP_I8X4, FP32 otherwise)
 void launch_history(hipStream_t s, int32_t precision, int64_t ne, int64_t ld, int64_t nrhs, int64_t kmax,
                     const void *slabs, const float *scales, const void *ring, int64_t n_slots, int64_t head,
                     const double *r, double *b, void *partial, int nsplit, hipEvent_t e0 = nullptr,

@@ -674,6 +674,7 @@ int64_t ring_bf16_rows(int64_t nrhs) { return (nrhs + 15) / 16 * 16; }
 
 int hist_splits(int64_t ne, int64_t kmax, int64_t nrhs, int32_t precision)
 {
+    if (precision == QHP_I8X4) return i8_hist_splits(ne, kmax, nrhs);
     if (nrhs > 1 && (precision == QHP_BF16 || precision == QHP_BF16X2)) {
         // matrix-core tiles of 128 rows x 128 right-hand sides: about eight
         // rounds of two resident work-groups per CU keep the last round short
@@ -700,6 +701,14 @@ void launch_history(hipStream_t s, int32_t precision, int64_t ne, int64_t ld, in
     }
     int64_t lps = (kmax + nsplit - 1) / nsplit;
     if (e0) (void)hipEventRecord(e0, s);
+    if (precision == QHP_I8X4) {
+        launch_hist_i8(s, ne, ld, nrhs, kmax, nsplit, (const int8_t *)slabs, (const int8_t *)ring, n_slots, head,
+                       (double *)partial);
+        if (e1) (void)hipEventRecord(e1, s);
+        hipLaunchKernelGGL(k_hist_finish<double>, dim3(nblk(ne * nrhs, 256)), dim3(256), 0, s, ne * nrhs,
+                           (int64_t)nsplit, (const double *)partial, r, b);
+        return;
+    }
     if (nrhs == 1) {
         if (variant < 0 || variant >= kNumGemvVariants) variant = 2;
         if (precision == QHP_F64)
