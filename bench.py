@@ -44,15 +44,19 @@ def parse():
     ap.add_argument("--epochs", type=int, default=8, help="warm-start training passes")
     ap.add_argument("--eval-dirs", type=int, default=2, help="warm-start held-out directions")
     ap.add_argument("--scatterers", type=int, default=32, help="uneven-batch: march the first N of the 32")
-    ap.add_argument("--precision", default="f32a", choices=["f32", "f32a", "bf16", "bf16x2", "i8x4", "f64"],
-                    help="slab storage / history arithmetic: f32a = FP32 blocks with FP64 y and sums")
+    ap.add_argument("--precision", default=None, choices=["f32", "f32a", "bf16", "bf16x2", "i8x4", "f64"],
+                    help="slab storage / history arithmetic (default: f32a = FP32 blocks with FP64 y and "
+                         "sums for one wave, i8x4 = int8 digit blocks on the int8 matrix cores for torus-batched)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 4 GiB device copy first (reference for profiler byte counters)")
     ap.add_argument("--solver", default="inv", choices=["lu", "inv"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="only the FP64 reference and the headline march")
     ap.add_argument("--n-dirs", type=int, default=64, help="directions for torus-batched")
-    return ap.parse_args()
+    a = ap.parse_args()
+    if a.precision is None:
+        a.precision = "i8x4" if a.workload == "torus-batched" else "f32a"
+    return a
 
 
 def workload(name, n_dirs):
@@ -72,11 +76,13 @@ def traffic_from_profile(kernel_name):
         return None
     try:
         rec = json.load(open(path))
-        src = open(os.path.join(ROOT, "paper_2312_06367_amd", "csrc", "march.hip"), "rb").read()
-        if rec.get("source_sha256") != hashlib.sha256(src).hexdigest():
-            return None
         ent = rec.get("kernels", {}).get(kernel_name)
-        return None if not ent else ent["fetch_bytes_per_launch"] + ent["write_bytes_per_launch"]
+        if not ent:
+            return None
+        src = open(os.path.join(ROOT, "paper_2312_06367_amd", "csrc", ent["source"]), "rb").read()
+        if ent.get("source_sha256") != hashlib.sha256(src).hexdigest():
+            return None
+        return ent["fetch_bytes_per_launch"] + ent["write_bytes_per_launch"]
     except Exception:
         return None
 

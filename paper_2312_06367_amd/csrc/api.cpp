@@ -451,9 +451,48 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
 
 // Pick the fastest history-kernel variant and split count on the context's
 // own slabs (timed with HIP events, two launches each after a warm-up).
+static void autotune_i8(qhp_ctx *c)
+{
+    hipStream_t s = c->s;
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "event");
+    hip_check(hipEventCreate(&e1), "event");
+    float best = 1e30f;
+    int best_v = -1;
+    for (int v = 0; v < qhp::i8_variant_count(); ++v) {
+        auto run = [&]() {
+            qhp::launch_history(s, QHP_I8X4, c->mesh.ne, c->ld, c->nrhs, c->K, c->slabs.p, nullptr, c->ring8.p, c->K,
+                                0, c->rhs.as<double>(), c->bvec.as<double>(), c->partial.p, c->nsplit, nullptr,
+                                nullptr, v);
+        };
+        run();
+        hip_check(hipEventRecord(e0, s), "event");
+        run();
+        run();
+        hip_check(hipEventRecord(e1, s), "event");
+        hip_check(hipEventSynchronize(e1), "event");
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, e0, e1), "event");
+        if (c->verbose)
+            std::fprintf(stderr, "[qhp] int8 history kernel, %d steps prefetched: %.3f ms\n",
+                         qhp::i8_variant_prefetch(v), ms / 2);
+        if (ms < best) {
+            best = ms;
+            best_v = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->hv = best_v;
+    if (c->verbose)
+        std::fprintf(stderr, "[qhp] int8 history kernel: %d steps prefetched, %d splits, %.3f ms\n",
+                     qhp::i8_variant_prefetch(best_v), c->nsplit, best / 2);
+}
+
 static void autotune(qhp_ctx *c)
 {
     c->hv = -1;
+    if (c->p.precision == QHP_I8X4) return autotune_i8(c);
     if (c->nrhs != 1) return;
     hipStream_t s = c->s;
     const int64_t ne = c->mesh.ne, K = c->K;

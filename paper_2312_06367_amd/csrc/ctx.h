@@ -91,7 +91,7 @@ struct qhp_ctx {
     bool broken = false;
     qhp::DBuf waves_d, rhs, ring64, ring32, ringb, ring8, bvec, zvec, yvec, partial, sv, zc, flags, epoch, errflag;
     int nsplit = 1;
-    int hv = -1;  // autotuned variant of the single right-hand-side history kernel
+    int hv = -1;  // autotuned variant of the history kernel (single right-hand side, or int8 digits)
     // profiling of the history kernel
     bool profiling = false;
     std::vector<hipEvent_t> ev;

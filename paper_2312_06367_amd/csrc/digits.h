@@ -37,8 +37,12 @@ void launch_i8_load(hipStream_t s, int64_t ne, int64_t ld, const int8_t *block, 
 void launch_i8_store_y(hipStream_t s, int64_t ne, int64_t nrhs, int64_t ld, const double *y, int8_t *slot);
 // split count of the int8 history kernel
 int i8_hist_splits(int64_t ne, int64_t kmax, int64_t nrhs);
-// partial: [nsplit][ne][nrhs] FP64 sums of each split's lags
+// partial: [nsplit][ne][nrhs] FP64 sums of each split's lags; variant in
+// [0, i8_variant_count()) (out of range: the default)
 void launch_hist_i8(hipStream_t s, int64_t ne, int64_t ld, int64_t nrhs, int64_t kmax, int nsplit,
-                    const int8_t *slabs, const int8_t *ring, int64_t n_slots, int64_t head, double *partial);
+                    const int8_t *slabs, const int8_t *ring, int64_t n_slots, int64_t head, double *partial,
+                    int variant = -1);
+int i8_variant_count();
+int i8_variant_prefetch(int v);
 
 }  // namespace qhp

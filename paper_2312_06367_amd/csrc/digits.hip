@@ -196,6 +196,7 @@ void launch_i8_store_y(hipStream_t s, int64_t ne, int64_t nrhs, int64_t ld, cons
 // XCDs in turn) runs a contiguous range of (split, row tile, rhs tile) in
 // that order: work-groups resident together on one XCD share the lag's y
 // digits and, pairwise, the block rows in that XCD's L2.
+template <int PF>
 __global__ __launch_bounds__(512, 1) void k_hist_i8(int64_t ne, int64_t ld, int64_t nrhs, int64_t kmax,
                                                     int64_t lps, int64_t nsplit, const int8_t *__restrict__ slabs,
                                                     const int8_t *__restrict__ ring, int64_t n_slots, int64_t head,
@@ -236,29 +237,32 @@ __global__ __launch_bounds__(512, 1) void k_hist_i8(int64_t ne, int64_t ld, int6
         for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
             for (int j = 0; j < 2; ++j) acc[w][rt][j] = i4_t{0, 0, 0, 0};
-    i4_t sa[4], sb[2];
-    // staging: piece p = tid + 512 q is 16 bytes (p % 256) of tile p / 256
-    auto load = [&](int64_t k, int64_t kc) {
+    // staging registers: PF sets, step s held in set s % PF; piece p = tid + 512 q
+    // is 16 bytes (p % 256) of tile p / 256
+    i4_t sa[PF][4], sb[PF][2];
+    auto load = [&](int set, int64_t k, int64_t kc) {
         const int8_t *Ab = slabs + (k - 1) * blk;
         const int8_t *Bb = ring + ((head + k - 1) % n_slots) * slot_bytes;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int p = tid + 512 * q, off = (p & 255) * 16;
             const int64_t rt = rt0 + (p >> 8);
-            sa[q] = rt < nrt ? *reinterpret_cast<const i4_t *>(Ab + (rt * nkc + kc) * 4096 + off) : i4_t{0, 0, 0, 0};
+            sa[set][q] =
+                rt < nrt ? *reinterpret_cast<const i4_t *>(Ab + (rt * nkc + kc) * 4096 + off) : i4_t{0, 0, 0, 0};
         }
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int p = tid + 512 * q, off = (p & 255) * 16;
             const int64_t jt = jt0 + (p >> 8);
-            sb[q] = jt < nnt ? *reinterpret_cast<const i4_t *>(Bb + (jt * nkc + kc) * 4096 + off) : i4_t{0, 0, 0, 0};
+            sb[set][q] =
+                jt < nnt ? *reinterpret_cast<const i4_t *>(Bb + (jt * nkc + kc) * 4096 + off) : i4_t{0, 0, 0, 0};
         }
     };
-    auto store = [&](int buf) {
+    auto store = [&](int set, int buf) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) As[buf][tid + 512 * q] = sa[q];
+        for (int q = 0; q < 4; ++q) As[buf][tid + 512 * q] = sa[set][q];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) Bs[buf][tid + 512 * q] = sb[q];
+        for (int q = 0; q < 2; ++q) Bs[buf][tid + 512 * q] = sb[set][q];
     };
     auto flush = [&](int64_t k, bool first) {
         const double *srow = reinterpret_cast<const double *>(slabs + (k - 1) * blk + R * ld * 4);
@@ -295,52 +299,63 @@ __global__ __launch_bounds__(512, 1) void k_hist_i8(int64_t ne, int64_t ld, int6
             ++lk;
         }
     };
-    load(lk, lkc);
+    // steps 0 .. PF - 1 in flight, step 0 in LDS buffer 0
+    load(0, lk, lkc);
     advance();
-    store(0);
-    __syncthreads();
-    int64_t kcur = k_begin, kccur = 0;
-    for (int64_t t = 0; t < total; ++t) {
-        const int buf = (int)(t & 1);
-        const bool more = t + 1 < total;
-        if (more) {
-            load(lk, lkc);
+#pragma unroll
+    for (int q = 1; q < PF; ++q)
+        if (q < total) {
+            load(q, lk, lkc);
             advance();
         }
-        i4_t a[2][4], b[2][4];
+    store(0, 0);
+    __syncthreads();
+    int64_t kcur = k_begin, kccur = 0;
+    // two steps per iteration so that buffer and register-set indices are static
+    for (int64_t t0 = 0; t0 < total; t0 += 2) {
 #pragma unroll
-        for (int rt = 0; rt < 2; ++rt)
+        for (int u = 0; u < 2; ++u) {
+            const int64_t t = t0 + u;
+            if (t >= total) break;
+            if (t + PF < total) {  // the set of step t is free again (stored one step ago)
+                load((u + PF) % PF, lk, lkc);
+                advance();
+            }
+            i4_t a[2][4], b[2][4];
 #pragma unroll
-            for (int d = 0; d < 4; ++d) a[rt][d] = As[buf][(2 * wr + rt) * 256 + d * 64 + lane];
+            for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+                for (int d = 0; d < 4; ++d) a[rt][d] = As[u][(2 * wr + rt) * 256 + d * 64 + lane];
 #pragma unroll
-            for (int d = 0; d < 4; ++d) b[j][d] = Bs[buf][(2 * wn + j) * 256 + d * 64 + lane];
-        // digit pairs (a, b) with a + b <= 4, ordered to space the products into one accumulator
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int d = 0; d < 4; ++d) b[j][d] = Bs[u][(2 * wn + j) * 256 + d * 64 + lane];
+            // digit pairs (a, b) with a + b <= 4, ordered to space the products into one accumulator
 #define QHP_I8_PAIR(A_, B_)                                                                   \
     _Pragma("unroll") for (int rt = 0; rt < 2; ++rt) _Pragma("unroll") for (int j = 0; j < 2; ++j) \
         acc[A_ + B_][rt][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[rt][A_], b[j][B_], acc[A_ + B_][rt][j], 0, 0, 0);
-        QHP_I8_PAIR(0, 0)
-        QHP_I8_PAIR(0, 1)
-        QHP_I8_PAIR(0, 2)
-        QHP_I8_PAIR(0, 3)
-        QHP_I8_PAIR(1, 3)
-        QHP_I8_PAIR(1, 0)
-        QHP_I8_PAIR(1, 1)
-        QHP_I8_PAIR(1, 2)
-        QHP_I8_PAIR(2, 2)
-        QHP_I8_PAIR(2, 0)
-        QHP_I8_PAIR(2, 1)
-        QHP_I8_PAIR(3, 1)
-        QHP_I8_PAIR(3, 0)
+            QHP_I8_PAIR(0, 0)
+            QHP_I8_PAIR(0, 1)
+            QHP_I8_PAIR(0, 2)
+            QHP_I8_PAIR(0, 3)
+            QHP_I8_PAIR(1, 3)
+            QHP_I8_PAIR(1, 0)
+            QHP_I8_PAIR(1, 1)
+            QHP_I8_PAIR(1, 2)
+            QHP_I8_PAIR(2, 2)
+            QHP_I8_PAIR(2, 0)
+            QHP_I8_PAIR(2, 1)
+            QHP_I8_PAIR(3, 1)
+            QHP_I8_PAIR(3, 0)
 #undef QHP_I8_PAIR
-        if (more) store(buf ^ 1);
-        if (++kccur == nks) {
-            flush(kcur, kcur == k_begin);
-            kccur = 0;
-            ++kcur;
+            if (t + 1 < total) store((u + 1) % PF, u ^ 1);
+            if (++kccur == nks) {
+                flush(kcur, kcur == k_begin);
+                kccur = 0;
+                ++kcur;
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
@@ -362,13 +377,24 @@ int i8_hist_splits(int64_t ne, int64_t kmax, int64_t nrhs)
     return (int)((kmax + best_l - 1) / best_l);
 }
 
+// variants of the int8 history kernel: steps prefetched into registers
+static const int kI8Prefetch[] = {1, 2};
+int i8_variant_count() { return (int)(sizeof(kI8Prefetch) / sizeof(kI8Prefetch[0])); }
+int i8_variant_prefetch(int v) { return kI8Prefetch[v]; }
+
 void launch_hist_i8(hipStream_t s, int64_t ne, int64_t ld, int64_t nrhs, int64_t kmax, int nsplit,
-                    const int8_t *slabs, const int8_t *ring, int64_t n_slots, int64_t head, double *partial)
+                    const int8_t *slabs, const int8_t *ring, int64_t n_slots, int64_t head, double *partial,
+                    int variant)
 {
     const int64_t lps = (kmax + nsplit - 1) / nsplit;
     const int64_t nwg = (int64_t)nblk8(i8_rows(ne) / 16, 8) * nblk8(i8_rows(nrhs) / 16, 4) * nsplit;
-    hipLaunchKernelGGL(k_hist_i8, dim3((unsigned)nwg), dim3(512), 0, s, ne, ld, nrhs, kmax, lps, (int64_t)nsplit,
-                       slabs, ring, n_slots, head, partial);
+    if (variant < 0 || variant >= i8_variant_count()) variant = 1;
+    if (kI8Prefetch[variant] == 1)
+        hipLaunchKernelGGL(k_hist_i8<1>, dim3((unsigned)nwg), dim3(512), 0, s, ne, ld, nrhs, kmax, lps,
+                           (int64_t)nsplit, slabs, ring, n_slots, head, partial);
+    else
+        hipLaunchKernelGGL(k_hist_i8<2>, dim3((unsigned)nwg), dim3(512), 0, s, ne, ld, nrhs, kmax, lps,
+                           (int64_t)nsplit, slabs, ring, n_slots, head, partial);
 }
 
 }  // namespace qhp

@@ -703,7 +703,7 @@ void launch_history(hipStream_t s, int32_t precision, int64_t ne, int64_t ld, in
     if (e0) (void)hipEventRecord(e0, s);
     if (precision == QHP_I8X4) {
         launch_hist_i8(s, ne, ld, nrhs, kmax, nsplit, (const int8_t *)slabs, (const int8_t *)ring, n_slots, head,
-                       (double *)partial);
+                       (double *)partial, variant);
         if (e1) (void)hipEventRecord(e1, s);
         hipLaunchKernelGGL(k_hist_finish<double>, dim3(nblk(ne * nrhs, 256)), dim3(256), 0, s, ne * nrhs,
                            (int64_t)nsplit, (const double *)partial, r, b);
