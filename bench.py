@@ -381,7 +381,8 @@ def main():
         hist = ms_hist / max(launches, 1)
         log("%-9s %-3s: %d steps %.3f s = %.1f steps/s; history kernel %.3f ms (variant %d, %d splits)"
             % (tag, solver, a.steps, wall, a.steps / wall, hist, s.info()["hist_variant"], s.info()["hist_splits"]))
-        return {"j": jh, "steps_per_s": a.steps / wall, "wall": wall, "hist_ms": hist}
+        return {"j": jh, "steps_per_s": a.steps / wall, "wall": wall, "hist_ms": hist,
+                "variant": s.info()["hist_variant"]}
 
     def rel(jx, jref):
         d = torch.linalg.vector_norm(jx - jref, dim=1).max().item()
@@ -457,8 +458,9 @@ def main():
                 "bf16_mfma_executed_tflops": executed, "bf16_mfma_frac": executed / BF16_MFMA_PEAK_TFLOPS,
                 "fp32_equivalent_tflops": flops_per_launch / (head["hist_ms"] * 1e-3) / 1e12}
     elif a.precision == "i8x4":
-        # int8 matrix cores: 13 digit products per term, exact int32 sums per lag
-        kname = "k_hist_i8"
+        # int8 matrix cores: 13 digit products per term, exact int32 sums per lag;
+        # the kernel is the autotuned variant (the library's variant table, in order)
+        kname = ["k_hist_i8<2,2,4,2,2>", "k_hist_i8d<2,2,4,2,2>", "k_hist_i8d<2,2,4,2,3>"][head["variant"]]
         ops = 13 * flops_per_launch
         achieved = ops / (head["hist_ms"] * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": INT8_MFMA_PEAK_TOPS, "unit": "TOP/s",

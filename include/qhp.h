@@ -248,6 +248,17 @@ int qhp_history_sum(void *stream, int32_t precision, int64_t ne, int64_t ld, int
                     int64_t kmax, const void *slabs, const float *scales, const void *ring,
                     int64_t n_slots, int64_t head, const double *r, double *b);
 
+/* The same sum with the kernel variant fixed (0 <= variant <
+ * qhp_history_variants(precision, nrhs); -1 = the default), for callers that
+ * tune or test the variants the march's autotuner chooses from.  Every
+ * variant computes the same products; they differ in tiling and scheduling.
+ * QHP_EINVAL for a variant out of range. */
+int qhp_history_sum_variant(void *stream, int32_t precision, int64_t ne, int64_t ld, int64_t nrhs,
+                            int64_t kmax, const void *slabs, const float *scales, const void *ring,
+                            int64_t n_slots, int64_t head, const double *r, double *b, int32_t variant);
+/* number of history-kernel variants for a precision and right-hand-side count */
+int qhp_history_variants(int32_t precision, int64_t nrhs);
+
 const char *qhp_last_error(const qhp_ctx *ctx);
 void qhp_destroy(qhp_ctx *ctx);
 

@@ -60,7 +60,8 @@ class _Info(ctypes.Structure):
 
 EXPORTS = ["qhp_create", "qhp_mesh", "qhp_assemble", "qhp_set_precision", "qhp_set_solver", "qhp_profile",
            "qhp_hist_time", "qhp_set_incident", "qhp_step", "qhp_run", "qhp_query", "qhp_edges",
-           "qhp_get_matrix", "qhp_keep_raw", "qhp_history_sum", "qhp_batch_create", "qhp_batch_run",
+           "qhp_get_matrix", "qhp_keep_raw", "qhp_history_sum", "qhp_history_sum_variant", "qhp_history_variants",
+           "qhp_batch_create", "qhp_batch_run",
            "qhp_batch_step_times", "qhp_batch_last_error", "qhp_batch_destroy", "qhp_last_error",
            "qhp_destroy", "qhp_release_assembly", "qhp_set_gmres", "qhp_gmres_stats", "qhp_gmres_reset", "qhp_mlp_create",
            "qhp_mlp_dims", "qhp_mlp_set_params", "qhp_mlp_get_params", "qhp_mlp_features", "qhp_mlp_guess", "qhp_mlp_reconstruct",
@@ -96,6 +97,8 @@ def lib():
         L.qhp_get_matrix.argtypes = [vp, i32, i32, vp]
         L.qhp_keep_raw.argtypes = [vp, i32]
         L.qhp_history_sum.argtypes = [vp, i32, i64, i64, i64, i64, vp, vp, vp, i64, i64, vp, vp]
+        L.qhp_history_sum_variant.argtypes = [vp, i32, i64, i64, i64, i64, vp, vp, vp, i64, i64, vp, vp, i32]
+        L.qhp_history_variants.argtypes = [i32, i64]
         L.qhp_batch_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]
         L.qhp_batch_run.argtypes = [vp, i32, ctypes.POINTER(vp)]
         L.qhp_batch_step_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32]
@@ -268,7 +271,12 @@ class Solver:
             pass
 
 
-def history_sum(precision: str, slabs, scales, ring, head: int, r, b, kmax: int | None = None):
+def history_variants(precision: str, nrhs: int) -> int:
+    """number of history-kernel variants (qhp_history_variants)"""
+    return lib().qhp_history_variants(PRECISIONS[precision], int(nrhs))
+
+
+def history_sum(precision: str, slabs, scales, ring, head: int, r, b, kmax: int | None = None, variant: int = -1):
     """b = r - sum_{k=1}^{kmax} T_k y_{i-k} on caller tensors (see qhp_history_sum).
 
     slabs: [kmax, ne, ld] (float64 / float32 / bfloat16) or, for bf16x2,
@@ -289,8 +297,8 @@ def history_sum(precision: str, slabs, scales, ring, head: int, r, b, kmax: int 
     else:
         ne, ld = slabs.shape[-2], slabs.shape[-1]
     nrhs = r.shape[1] if r.dim() == 2 else 1
-    rc = L.qhp_history_sum(_stream(), PRECISIONS[precision], ne, ld, nrhs, kmax, _ptr(slabs), _ptr(scales),
-                           _ptr(ring), ring.shape[0], int(head), _ptr(r), _ptr(b))
+    rc = L.qhp_history_sum_variant(_stream(), PRECISIONS[precision], ne, ld, nrhs, kmax, _ptr(slabs), _ptr(scales),
+                                   _ptr(ring), ring.shape[0], int(head), _ptr(r), _ptr(b), int(variant))
     if rc != 0:
         raise QhpError(rc, "qhp_history_sum")
 

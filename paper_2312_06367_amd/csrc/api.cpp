@@ -458,12 +458,12 @@ static void autotune_i8(qhp_ctx *c)
     hip_check(hipEventCreate(&e0), "event");
     hip_check(hipEventCreate(&e1), "event");
     float best = 1e30f;
-    int best_v = -1;
+    int best_v = -1, best_s = c->nsplit;
     for (int v = 0; v < qhp::i8_variant_count(); ++v) {
+        const int ns = qhp::i8_hist_splits(c->mesh.ne, c->K, c->nrhs, v);
         auto run = [&]() {
             qhp::launch_history(s, QHP_I8X4, c->mesh.ne, c->ld, c->nrhs, c->K, c->slabs.p, nullptr, c->ring8.p, c->K,
-                                0, c->rhs.as<double>(), c->bvec.as<double>(), c->partial.p, c->nsplit, nullptr,
-                                nullptr, v);
+                                0, c->rhs.as<double>(), c->bvec.as<double>(), c->partial.p, ns, nullptr, nullptr, v);
         };
         run();
         hip_check(hipEventRecord(e0, s), "event");
@@ -473,20 +473,22 @@ static void autotune_i8(qhp_ctx *c)
         hip_check(hipEventSynchronize(e1), "event");
         float ms = 0.f;
         hip_check(hipEventElapsedTime(&ms, e0, e1), "event");
-        if (c->verbose)
-            std::fprintf(stderr, "[qhp] int8 history kernel, %d steps prefetched: %.3f ms\n",
-                         qhp::i8_variant_prefetch(v), ms / 2);
+        if (c->verbose) {
+            int rows, cols, waves, pf, dma;
+            qhp::i8_variant_desc(v, &rows, &cols, &waves, &pf, &dma);
+            std::fprintf(stderr, "[qhp] int8 history kernel %d (%d x %d per work-group, %d waves, %d steps in flight%s, "
+                         "%d splits): %.3f ms\n", v, rows, cols, waves, pf, dma ? " straight to LDS" : "", ns, ms / 2);
+        }
         if (ms < best) {
             best = ms;
             best_v = v;
+            best_s = ns;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     c->hv = best_v;
-    if (c->verbose)
-        std::fprintf(stderr, "[qhp] int8 history kernel: %d steps prefetched, %d splits, %.3f ms\n",
-                     qhp::i8_variant_prefetch(best_v), c->nsplit, best / 2);
+    c->nsplit = best_s;
 }
 
 static void autotune(qhp_ctx *c)
@@ -609,7 +611,11 @@ extern "C" int qhp_set_incident(qhp_ctx *ctx, const qhp_wave *waves, int32_t n_r
     c->zvec.alloc(sizeof(double) * ne * n_rhs);
     c->yvec.alloc(sizeof(double) * ne * n_rhs);
     c->nsplit = qhp::hist_splits(ne, K, n_rhs, c->p.precision);
-    c->partial.alloc(sizeof(double) * std::min<int64_t>(2 * c->nsplit, K) * ne * n_rhs);
+    int64_t max_split = std::min<int64_t>(2 * c->nsplit, K);
+    if (c->p.precision == QHP_I8X4)  // every variant the autotuner tries
+        for (int v = 0; v < qhp::i8_variant_count(); ++v)
+            max_split = std::max<int64_t>(max_split, qhp::i8_hist_splits(ne, K, n_rhs, v));
+    c->partial.alloc(sizeof(double) * max_split * ne * n_rhs);
     c->sv.alloc(sizeof(double) * nc * n_rhs);
     c->zc.alloc(sizeof(double) * nc * n_rhs);
     c->flags.alloc(sizeof(int) * 2 * ((ne + 63) / 64));
@@ -934,30 +940,48 @@ extern "C" int qhp_get_matrix(const qhp_ctx *cc, int32_t which, int32_t k, doubl
     API_CATCH(ctx)
 }
 
-extern "C" int qhp_history_sum(void *stream, int32_t precision, int64_t ne, int64_t ld, int64_t nrhs, int64_t kmax,
-                               const void *slabs, const float *scales, const void *ring, int64_t n_slots, int64_t head,
-                               const double *r, double *b)
+extern "C" int qhp_history_variants(int32_t precision, int64_t nrhs)
+{
+    if (precision < QHP_F64 || precision > QHP_I8X4 || nrhs < 1) return 0;
+    if (precision == QHP_I8X4) return qhp::i8_variant_count();
+    return nrhs == 1 ? qhp::gemv_variant_count() : 1;
+}
+
+extern "C" int qhp_history_sum_variant(void *stream, int32_t precision, int64_t ne, int64_t ld, int64_t nrhs,
+                                       int64_t kmax, const void *slabs, const float *scales, const void *ring,
+                                       int64_t n_slots, int64_t head, const double *r, double *b, int32_t variant)
 {
     if (precision < QHP_F64 || precision > QHP_I8X4 || ne < 1 || ld < ne || ld % 8 != 0 || nrhs < 1 || kmax < 0 ||
         (precision == QHP_F32A && nrhs != 1) || (precision == QHP_BF16X2 && (nrhs < 2 || ld % 32 != 0)) ||
         (precision == QHP_I8X4 && (nrhs < 2 || ld % 64 != 0 || ne > 65536)) ||
         (precision == QHP_BF16 && nrhs > 1 && ld % 32 != 0) ||
-        n_slots < kmax || head < 0 || (kmax > 0 && (!slabs || !ring)) || !r || !b)
+        n_slots < kmax || head < 0 || (kmax > 0 && (!slabs || !ring)) || !r || !b ||
+        variant < -1 || variant >= qhp_history_variants(precision, nrhs))
         return QHP_EINVAL;
     if (precision == QHP_BF16 && !scales) return QHP_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    int nsplit = qhp::hist_splits(ne, std::max<int64_t>(kmax, 1), nrhs, precision);
+    const int64_t km = std::max<int64_t>(kmax, 1);
+    int nsplit = precision == QHP_I8X4 ? qhp::i8_hist_splits(ne, km, nrhs, variant)
+                                       : qhp::hist_splits(ne, km, nrhs, precision);
     void *partial = nullptr;
     if (hipMalloc(&partial, sizeof(double) * nsplit * ne * nrhs) != hipSuccess) {
         (void)hipGetLastError();
         return QHP_ENOMEM;
     }
     qhp::launch_history(s, precision, ne, ld, nrhs, kmax, slabs, precision == QHP_BF16 ? scales : nullptr, ring,
-                        n_slots, head, r, b, partial, nsplit);
+                        n_slots, head, r, b, partial, nsplit, nullptr, nullptr, variant);
     hipError_t e = hipStreamSynchronize(s);
     if (e == hipSuccess) e = hipGetLastError();
     (void)hipFree(partial);
     return e == hipSuccess ? QHP_OK : QHP_EDEVICE;
+}
+
+extern "C" int qhp_history_sum(void *stream, int32_t precision, int64_t ne, int64_t ld, int64_t nrhs, int64_t kmax,
+                               const void *slabs, const float *scales, const void *ring, int64_t n_slots, int64_t head,
+                               const double *r, double *b)
+{
+    return qhp_history_sum_variant(stream, precision, ne, ld, nrhs, kmax, slabs, scales, ring, n_slots, head, r, b,
+                                   -1);
 }
 
 // ------------------------------------------------------------------ batch

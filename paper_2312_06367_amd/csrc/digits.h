@@ -35,14 +35,16 @@ void launch_i8_quantise(hipStream_t s, int64_t ne, int64_t ld, const double *T, 
 void launch_i8_load(hipStream_t s, int64_t ne, int64_t ld, const int8_t *block, double *T);
 // y [ne][nrhs] FP64 -> one ring slot (all of it rewritten)
 void launch_i8_store_y(hipStream_t s, int64_t ne, int64_t nrhs, int64_t ld, const double *y, int8_t *slot);
-// split count of the int8 history kernel
-int i8_hist_splits(int64_t ne, int64_t kmax, int64_t nrhs);
+// split count of the int8 history kernel for a variant (-1: the default)
+int i8_hist_splits(int64_t ne, int64_t kmax, int64_t nrhs, int variant = -1);
 // partial: [nsplit][ne][nrhs] FP64 sums of each split's lags; variant in
 // [0, i8_variant_count()) (out of range: the default)
 void launch_hist_i8(hipStream_t s, int64_t ne, int64_t ld, int64_t nrhs, int64_t kmax, int nsplit,
                     const int8_t *slabs, const int8_t *ring, int64_t n_slots, int64_t head, double *partial,
                     int variant = -1);
 int i8_variant_count();
-int i8_variant_prefetch(int v);
+// rows x right-hand sides per work-group, waves per work-group, steps in
+// flight, and whether the pieces go straight from memory into LDS
+void i8_variant_desc(int v, int *rows, int *cols, int *waves, int *pf, int *dma);
 
 }  // namespace qhp
