@@ -192,3 +192,41 @@ def test_history_sum_i8x4_full_size_sampled():
     del slabs, ring
     torch.cuda.empty_cache()
     assert max(errs) < 1e-12
+
+
+def test_torus_i8x4_2000_steps_and_dc_10k():
+    """The batched torus workload (6000 edges, c dt = 0.03 m, K = 88) with 8
+    of its waves: the digit march against the FP64 march over the full 2000
+    steps (bound 1e-5 relative to the peak current), then 10^4 steps of the
+    digit march: the current decays after the pulse and never grows."""
+    import paper_2312_06367_amd as qhp
+    from workloads import waves
+    cfg = waves.torus_batched(4)
+    xyz, tri = cfg.mesh
+    s = qhp.Solver(cfg.dt, precision="f64", solver="inv")
+    s.mesh(xyz, tri)
+    s.assemble()
+    ne, nw = s.info()["ne"], len(cfg.waves)
+    n_ref = 2000
+    s.set_incident(cfg.waves, n_ref)
+    ref = torch.zeros((n_ref, ne, nw), dtype=torch.float64, device="cuda")
+    s.run(n_ref, ref)
+    s.set_precision("i8x4")
+    n = 10000
+    s.set_incident(cfg.waves, n)
+    jh = torch.zeros((1000, ne, nw), dtype=torch.float64, device="cuda")
+    norms, err = [], 0.0
+    peak = torch.linalg.vector_norm(ref, dim=1).max().item()
+    for c in range(0, n, 1000):
+        s.run(1000, jh)
+        if c < n_ref:
+            err = max(err, torch.linalg.vector_norm(jh - ref[c:c + 1000], dim=1).max().item() / peak)
+        norms.append(torch.linalg.vector_norm(jh, dim=1).max(dim=1).values.cpu().numpy())
+    s.close()
+    nj = np.concatenate(norms)
+    blocks = nj.reshape(-1, 500).max(1) / nj.max()
+    _say("[torus i8x4] 2000-step current err %.3e; dc 10k block maxima / peak: %s"
+         % (err, " ".join("%.1e" % v for v in blocks)))
+    assert err < 1e-5
+    assert nj[-1000:].max() < 1e-3 * nj.max()
+    assert blocks[-1] <= 10 * blocks[len(blocks) // 2] + 1e-12  # no late growth
