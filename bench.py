@@ -46,7 +46,8 @@ def parse():
     ap.add_argument("--scatterers", type=int, default=32, help="uneven-batch: march the first N of the 32")
     ap.add_argument("--precision", default=None, choices=["f32", "f32a", "bf16", "bf16x2", "i8x4", "f64"],
                     help="slab storage / history arithmetic (default: f32a = FP32 blocks with FP64 y and "
-                         "sums for one wave, i8x4 = int8 digit blocks on the int8 matrix cores for torus-batched)")
+                         "sums for one wave, i8x4 = int8 digit blocks on the int8 matrix cores for torus-batched, "
+                         "f32 for uneven-batch)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 4 GiB device copy first (reference for profiler byte counters)")
     ap.add_argument("--solver", default="inv", choices=["lu", "inv"])
@@ -55,7 +56,7 @@ def parse():
     ap.add_argument("--n-dirs", type=int, default=64, help="directions for torus-batched")
     a = ap.parse_args()
     if a.precision is None:
-        a.precision = "i8x4" if a.workload == "torus-batched" else "f32a"
+        a.precision = {"torus-batched": "i8x4", "uneven-batch": "f32"}.get(a.workload, "f32a")
     return a
 
 
@@ -138,8 +139,9 @@ def log(*x):
 
 def bench_uneven(a):
     """32 seeded scatterers of uneven size (spheres, cubes, tori; 500-12000
-    edges), 8 waves each, FP32 blocks and arithmetic, marched together: one
-    graph replay per step of grouped work-queue kernels."""
+    edges), 8 waves each, FP32 blocks (FP32 arithmetic, or FP64 y and sums
+    with --precision f32a), marched together: one graph replay per step of
+    grouped work-queue kernels."""
     import numpy as np
     import torch
     import paper_2312_06367_amd as qhp
@@ -147,7 +149,7 @@ def bench_uneven(a):
     cfgs = waves.uneven_batch()[: a.scatterers]
     n_total = cfgs[0].n_steps
     steps = min(a.steps, n_total - a.warmup)
-    prec = "f32" if a.precision in ("f32", "f32a") else a.precision
+    prec = a.precision if a.precision in ("f32", "f32a", "f64") else "f32"
     order = sorted(range(len(cfgs)), key=lambda i: -len(cfgs[i].mesh[1]))  # largest first: lowest memory peak
     solvers = [None] * len(cfgs)
     t0 = time.perf_counter()
@@ -162,7 +164,7 @@ def bench_uneven(a):
         sv.release_assembly()
         inf = sv.info()
         solvers[i] = sv
-        esz = {"f64": 8, "f32": 4}[prec]
+        esz = {"f64": 8, "f32": 4, "f32a": 4}[prec]
         hist_bytes += inf["K"] * inf["ne"] * inf["ne"] * esz
         work.append((inf["ne"], inf["K"], i))
         log("scatterer %2d %-14s ne=%5d K=%3d slabs %.2f GB (%.0f s)" % (

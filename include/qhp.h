@@ -53,8 +53,8 @@ enum {
  *   QHP_BF16   BF16 blocks with a per-block FP32 scale, FP32 sums; y as FP32
  *              (one right-hand side) or, with several right-hand sides, as
  *              two BF16 terms (hi + mid) on the BF16 matrix cores
- *   QHP_F32A   FP32 blocks, FP64 y, products and sums in FP64 (one right-hand
- *              side only)
+ *   QHP_F32A   FP32 blocks, FP64 y, products and sums in FP64 (1, 2, 4 or 8
+ *              right-hand sides; qhp_history_sum takes one)
  *   QHP_BF16X2 each block as a BF16 pair T_hi + T_lo (4 bytes per entry), y
  *              as three BF16 terms, the five products of weight >= 2^-16
  *              on the BF16 matrix cores with FP32 sums (two or more

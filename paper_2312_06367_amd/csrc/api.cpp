@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "assembly.h"
+#include "batch.h"
 #include "linalg.h"
 #include "march.h"
 #include "qhp_internal.h"
@@ -451,6 +452,8 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
 
 // Pick the fastest history-kernel variant and split count on the context's
 // own slabs (timed with HIP events, two launches each after a warm-up).
+static int64_t group_splits(int64_t rows, int64_t cols, int64_t nlags);
+
 static void autotune_i8(qhp_ctx *c)
 {
     hipStream_t s = c->s;
@@ -545,7 +548,8 @@ extern "C" int qhp_set_incident(qhp_ctx *ctx, const qhp_wave *waves, int32_t n_r
     if (ctx->state < 2) return guard(ctx, QHP_ESTATE, "assemble first");
     if (ctx->released) return guard(ctx, QHP_ESTATE, "assembly operators were released");
     if (!waves || n_rhs < 1 || n_steps < 1) return guard(ctx, QHP_EINVAL, "bad waves / n_rhs / n_steps");
-    if (ctx->p.precision == QHP_F32A && n_rhs != 1) return guard(ctx, QHP_EINVAL, "QHP_F32A takes one right-hand side");
+    if (ctx->p.precision == QHP_F32A && n_rhs != 1 && n_rhs != 2 && n_rhs != 4 && n_rhs != 8)
+        return guard(ctx, QHP_EINVAL, "QHP_F32A takes 1, 2, 4 or 8 right-hand sides");
     if (ctx->p.solver == QHP_SOLVE_GMRES && n_rhs != 1) return guard(ctx, QHP_EINVAL, "GMRES takes one right-hand side");
     if (ctx->p.precision == QHP_BF16X2 && n_rhs < 2)
         return guard(ctx, QHP_EINVAL, "QHP_BF16X2 takes two or more right-hand sides");
@@ -615,7 +619,27 @@ extern "C" int qhp_set_incident(qhp_ctx *ctx, const qhp_wave *waves, int32_t n_r
     if (c->p.precision == QHP_I8X4)  // every variant the autotuner tries
         for (int v = 0; v < qhp::i8_variant_count(); ++v)
             max_split = std::max<int64_t>(max_split, qhp::i8_hist_splits(ne, K, n_rhs, v));
+    const bool grouped = c->p.precision == QHP_F32A && n_rhs > 1;
+    if (grouped) {
+        c->mr_splits = group_splits(ne, ne, K);
+        max_split = std::max<int64_t>(max_split, c->mr_splits);
+    }
     c->partial.alloc(sizeof(double) * max_split * ne * n_rhs);
+    c->mr_desc.release();
+    if (grouped) {  // one group of the grouped multi-right-hand-side kernel (FP32 blocks, FP64 y and sums)
+        c->mr_head.alloc(sizeof(int64_t));
+        c->mr_counter.alloc(sizeof(unsigned long long));
+        const int64_t rpt = qhp::grouped_rows_per_tile(qhp::GK_F32A, (int)n_rhs);
+        qhp::GDesc g{};
+        g.A = c->slabs.p; g.rows = ne; g.cols = ne; g.ld = ld; g.lag_stride = ne * ld; g.nlags = K;
+        g.scales = nullptr;
+        g.x = c->ring64.p; g.x_slot_stride = ld * n_rhs; g.x_ld = 0; g.n_slots = K;
+        g.head = c->mr_head.as<int64_t>();
+        g.partial = c->partial.p; g.nsplit = c->mr_splits; g.tile0 = 0; g.rowblocks = (ne + rpt - 1) / rpt;
+        c->mr_tiles = g.rowblocks * c->mr_splits;
+        c->mr_desc.alloc(sizeof(qhp::GDesc));
+        hip_check(hipMemcpy(c->mr_desc.p, &g, sizeof(g), hipMemcpyHostToDevice), "descriptor");
+    }
     c->sv.alloc(sizeof(double) * nc * n_rhs);
     c->zc.alloc(sizeof(double) * nc * n_rhs);
     c->flags.alloc(sizeof(int) * 2 * ((ne + 63) / 64));
@@ -651,11 +675,20 @@ static void do_step(qhp_ctx *c, double *j_out, double *y_out)
         c->ev.push_back(e0);
         c->ev.push_back(e1);
     }
-    qhp::launch_history(s, c->p.precision, ne, ld, nr, K, c->slabs.p,
-                        c->p.precision == QHP_BF16 ? c->scales_d.as<float>() : nullptr,
-                        c->ring8.p ? c->ring8.p : (c->ringb.p ? c->ringb.p : (c->ring32.p ? c->ring32.p : c->ring64.p)),
-                        K, c->head, r_i,
-                        c->bvec.as<double>(), c->partial.p, c->nsplit, e0, e1, c->hv);
+    if (c->mr_desc.p) {  // FP32 blocks, FP64 y and sums, several right-hand sides: the grouped kernel
+        qhp::launch_set_i64(s, c->mr_head.as<int64_t>(), c->head);
+        if (e0) hip_check(hipEventRecord(e0, s), "event");
+        qhp::launch_grouped_gemv(s, qhp::GK_F32A, (int)nr, c->mr_desc.as<qhp::GDesc>(), 1, c->mr_tiles,
+                                 c->mr_counter.as<unsigned long long>());
+        if (e1) hip_check(hipEventRecord(e1, s), "event");
+        qhp::launch_hist_finish_f64(s, ne * nr, c->mr_splits, c->partial.as<double>(), r_i, c->bvec.as<double>());
+    } else {
+        qhp::launch_history(s, c->p.precision, ne, ld, nr, K, c->slabs.p,
+                            c->p.precision == QHP_BF16 ? c->scales_d.as<float>() : nullptr,
+                            c->ring8.p ? c->ring8.p
+                                       : (c->ringb.p ? c->ringb.p : (c->ring32.p ? c->ring32.p : c->ring64.p)),
+                            K, c->head, r_i, c->bvec.as<double>(), c->partial.p, c->nsplit, e0, e1, c->hv);
+    }
     double *y = c->yvec.as<double>();
     if (c->p.solver == QHP_SOLVE_GMRES) {
         qhp::warm_start(c, y);

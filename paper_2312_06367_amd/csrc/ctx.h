@@ -90,6 +90,10 @@ struct qhp_ctx {
     int64_t n_steps = 0, step = 0, head = 0;
     bool broken = false;
     qhp::DBuf waves_d, rhs, ring64, ring32, ringb, ring8, bvec, zvec, yvec, partial, sv, zc, flags, epoch, errflag;
+    // FP32 blocks with FP64 y and sums for 2, 4 or 8 right-hand sides: one
+    // group of the grouped work-queue kernel (descriptor, device head, counter)
+    qhp::DBuf mr_desc, mr_head, mr_counter;
+    int64_t mr_tiles = 0, mr_splits = 0;
     int nsplit = 1;
     int hv = -1;  // autotuned variant of the history kernel (single right-hand side, or int8 digits)
     // profiling of the history kernel

@@ -211,6 +211,27 @@ def test_batched_march_parity():
         assert err < bound
 
 
+def test_f32a_several_waves():
+    """FP32 blocks with FP64 y and sums for 2, 4 and 8 waves (the grouped
+    multi-right-hand-side kernel) on the torus with two global loops, against
+    the FP64 oracle march.  The bound is that of FP32 storage with carried
+    rounding on this mesh (the numpy model of it gives 1.8e-6)."""
+    from oracle import operators as O, excitation as E, mot
+    from workloads import meshes, waves
+    xyz, tri = meshes.torus(1.0, 0.4, 12, 6)
+    dt, n = 0.12, 150
+    asm = O.Assembly(xyz, tri, dt)
+    asm.build()
+    ws = waves.batched_waves(4, 5, 0.1, 0.1, asm.D)
+    r = np.stack([E.rhs(asm, w, n) for w in ws], axis=-1)
+    jref = mot.currents(asm.proj.PLH, asm.proj.PS, asm.dtn, mot.march(asm.T, r))
+    for nw in (2, 4, 8):
+        j = _march_gpu(xyz, tri, dt, ws[:nw], n, "f32a")
+        err = float(np.abs(j - jref[:, :, :nw]).max() / np.abs(jref[:, :, :nw]).max())
+        _say("[torus f32a x%d] current err %.3e" % (nw, err))
+        assert err < 5e-6
+
+
 def test_sphere_480_parity_f64():
     """The 480-edge sphere workload (c dt = 0.05 m, 400 steps), FP64."""
     from oracle import excitation as E, mot, operators as O
@@ -357,6 +378,7 @@ def test_error_paths():
 
 
 @pytest.mark.parametrize("precision,n_rhs,bound", [("f64", 2, 1e-12), ("f64", 8, 1e-12), ("f32a", 1, 1e-9),
+                                                   ("f32a", 4, 1e-9), ("f32a", 8, 1e-9),
                                                    ("f32", 1, 2e-4), ("f32", 4, 2e-4), ("f32", 8, 2e-4)])
 def test_batch_uneven_graph_replay(precision, n_rhs, bound):
     """Three scatterers of different size (sphere, torus, cube), n_rhs waves
