@@ -679,9 +679,9 @@ static void do_step(qhp_ctx *c, double *j_out, double *y_out)
         qhp::launch_set_i64(s, c->mr_head.as<int64_t>(), c->head);
         if (e0) hip_check(hipEventRecord(e0, s), "event");
         qhp::launch_grouped_gemv(s, qhp::GK_F32A, (int)nr, c->mr_desc.as<qhp::GDesc>(), 1, c->mr_tiles,
-                                 c->mr_counter.as<unsigned long long>());
+                                 c->mr_counter.as<unsigned long long>(), false);
         if (e1) hip_check(hipEventRecord(e1, s), "event");
-        qhp::launch_hist_finish_f64(s, ne * nr, c->mr_splits, c->partial.as<double>(), r_i, c->bvec.as<double>());
+        qhp::launch_partial_finish_f64(s, ne * nr, c->mr_splits, c->partial.as<double>(), r_i, c->bvec.as<double>());
     } else {
         qhp::launch_history(s, c->p.precision, ne, ld, nr, K, c->slabs.p,
                             c->p.precision == QHP_BF16 ? c->scales_d.as<float>() : nullptr,
@@ -1105,9 +1105,11 @@ static void build_batch(qhp_batch *b)
         g.scales = nullptr;
         g.x = c->ring32.p ? c->ring32.p : c->ring64.p;
         g.x_slot_stride = ld * nr; g.n_slots = K; g.head = dhead; g.x_ld = 0;
-        if (trans) {  // FP32 ring kept transposed as well, from the current state
-            b->ringt[i].alloc(sizeof(float) * K * nr * ld);
-            qhp::launch_ring_transpose(s, K, ld, nr, c->ring32.as<float>(), b->ringt[i].as<float>());
+        const bool t64 = trans && b->kind == qhp::GK_F32A;
+        if (trans) {  // ring kept transposed as well (FP32 or, for FP64 y, FP64), from the current state
+            b->ringt[i].alloc((t64 ? sizeof(double) : sizeof(float)) * K * nr * ld);
+            if (t64) qhp::launch_ring_transpose(s, K, ld, nr, c->ring64.as<double>(), b->ringt[i].as<double>());
+            else qhp::launch_ring_transpose(s, K, ld, nr, c->ring32.as<float>(), b->ringt[i].as<float>());
             g.x = b->ringt[i].p;
             g.x_ld = ld;
         }
@@ -1131,7 +1133,8 @@ static void build_batch(qhp_batch *b)
         b->yvec[i].alloc(sizeof(double) * ne * nr);
         fs[i] = qhp::GFin{b->part_s[i].p, 1, ne * nr, nullptr, dstep, b->yvec[i].as<double>()};
         gs[i] = qhp::GStore{b->yvec[i].as<double>(), c->ring64.as<double>(), c->ring32.as<float>(), ld * nr, K,
-                            ne * nr, dhead, b->errflag.as<int>(), trans ? b->ringt[i].as<float>() : nullptr, ld, nr};
+                            ne * nr, dhead, b->errflag.as<int>(), (trans && !t64) ? b->ringt[i].as<float>() : nullptr,
+                            ld, nr, t64 ? b->ringt[i].as<double>() : nullptr};
         // post-processing product z = L_Sigma^+ s (padded copy)
         const int64_t ldc = (nc + 7) / 8 * 8;
         b->lsp[i].alloc(sizeof(double) * nc * ldc);
@@ -1178,13 +1181,16 @@ static void enqueue_batch_step(qhp_batch *b)
 {
     hipStream_t s = b->s;
     const int n = b->n, nr = b->nrhs;
-    qhp::launch_grouped_gemv(s, b->kind, nr, b->d_hist.as<qhp::GDesc>(), n, b->tiles_h, b->counter.as<unsigned long long>());
+    qhp::launch_grouped_gemv(s, b->kind, nr, b->d_hist.as<qhp::GDesc>(), n, b->tiles_h, b->counter.as<unsigned long long>(),
+                             qhp::grouped_ring_transposed(b->kind, nr));
     qhp::launch_grouped_finish(s, b->acc_double, b->f_hist.as<qhp::GFin>(), n, b->max_ne, 0);
-    qhp::launch_grouped_gemv(s, qhp::GK_F64, nr, b->d_solve.as<qhp::GDesc>(), n, b->tiles_s, b->counter.as<unsigned long long>());
+    qhp::launch_grouped_gemv(s, qhp::GK_F64, nr, b->d_solve.as<qhp::GDesc>(), n, b->tiles_s, b->counter.as<unsigned long long>(),
+                             false);
     qhp::launch_grouped_finish(s, true, b->f_solve.as<qhp::GFin>(), n, b->max_ne, 1);
     qhp::launch_grouped_store(s, b->st.as<qhp::GStore>(), n, b->max_ne);
     qhp::launch_grouped_post(s, 0, b->po.as<qhp::GPost>(), n, b->max_nc);
-    qhp::launch_grouped_gemv(s, qhp::GK_F64, nr, b->d_post.as<qhp::GDesc>(), n, b->tiles_p, b->counter.as<unsigned long long>());
+    qhp::launch_grouped_gemv(s, qhp::GK_F64, nr, b->d_post.as<qhp::GDesc>(), n, b->tiles_p, b->counter.as<unsigned long long>(),
+                             false);
     qhp::launch_grouped_finish(s, true, b->f_post.as<qhp::GFin>(), n, b->max_nc, 1);
     qhp::launch_grouped_post(s, 1, b->po.as<qhp::GPost>(), n, b->max_ne);
     qhp::launch_grouped_advance(s, b->steps.as<int64_t>(), b->heads.as<int64_t>(), b->nslots.as<int64_t>(), n);

@@ -48,6 +48,7 @@ struct GStore {
     int *err;
     float *ring32t;  // optional transposed FP32 ring [slot][nrhs][ldt]
     int64_t ldt, nrhs;
+    double *ring64t;  // optional transposed FP64 ring [slot][nrhs][ldt]
 };
 
 struct GPost {
@@ -66,13 +67,21 @@ struct GPost {
 int64_t grouped_rows_per_tile(int kind, int nrhs);
 // whether launch_grouped_gemv of this kind and nrhs reads the ring transposed
 bool grouped_ring_transposed(int kind, int nrhs);
-// ring [n_slots][ld][nrhs] (FP32) -> [n_slots][nrhs][ld]
+// ring [n_slots][ld][nrhs] -> [n_slots][nrhs][ld]
 void launch_ring_transpose(hipStream_t s, int64_t n_slots, int64_t ld, int64_t nrhs, const float *in, float *out);
+void launch_ring_transpose(hipStream_t s, int64_t n_slots, int64_t ld, int64_t nrhs, const double *in, double *out);
+// transposed: the groups' rings are [nrhs][x_ld] per slot (the batch, for the
+// kinds grouped_ring_transposed names) or [cols][nrhs] (one context's own ring)
 void launch_grouped_gemv(hipStream_t s, int kind, int nrhs, const GDesc *gd, int ngroups, int64_t total_tiles,
-                         unsigned long long *counter);
+                         unsigned long long *counter, bool transposed);
 void launch_grouped_finish(hipStream_t s, bool acc_double, const GFin *gf, int ngroups, int64_t max_n, int negate);
 void launch_grouped_store(hipStream_t s, const GStore *gs, int ngroups, int64_t max_n);
 void launch_grouped_post(hipStream_t s, int part, const GPost *gp, int ngroups, int64_t max_n);
 void launch_grouped_advance(hipStream_t s, int64_t *steps, int64_t *heads, const int64_t *nslots, int ngroups);
+// single-group use of the grouped kernels by one context: *p = v on the stream,
+// and b = r - sum of nsplit FP64 partial sums of n entries
+void launch_set_i64(hipStream_t s, int64_t *p, int64_t v);
+void launch_partial_finish_f64(hipStream_t s, int64_t n, int64_t nsplit, const double *partial, const double *r,
+                               double *b);
 
 }  // namespace qhp

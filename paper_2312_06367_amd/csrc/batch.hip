@@ -239,16 +239,18 @@ __global__ __launch_bounds__(256, MINB) void k_grouped_mrhs(const GDesc *__restr
     }
 }
 
-// FP32 multi-right-hand-side form on a transposed ring ([nrhs][x_ld] per
-// slot): for each chunk of 256 columns a lane loads one 16-byte vector of
-// each of its RW rows and one 16-byte vector of each right-hand side, all
-// fully coalesced, with no LDS and no barrier in the streaming loop.  Columns
-// past the last one are zero in both operands.
-template <int NR, int RW>
+// Multi-right-hand-side form with FP32 blocks on a transposed ring ([nrhs]
+// [x_ld] per slot, Y = float for FP32 sums, double for FP64 y and sums): for
+// each chunk of 256 columns a lane loads one 16-byte vector of each of its RW
+// rows and the four matching entries of each right-hand side, all fully
+// coalesced, with no LDS and no barrier in the streaming loop.  Columns past
+// the last one are zero in both operands.
+template <typename Y, typename A, int NR, int RW>
 __global__ __launch_bounds__(256) void k_grouped_mrhs_t(const GDesc *__restrict__ gd, int ngroups,
                                                         int64_t total_tiles, unsigned long long *counter)
 {
     typedef float f4 __attribute__((ext_vector_type(4)));
+    typedef Y y4 __attribute__((ext_vector_type(4)));
     constexpr int ROWS = 4 * RW;
     __shared__ int64_t s_tile;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -268,18 +270,19 @@ __global__ __launch_bounds__(256) void k_grouped_mrhs_t(const GDesc *__restrict_
         const int64_t k0 = sp * lps;
         const int64_t k1 = (k0 + lps < d.nlags) ? k0 + lps : d.nlags;
         const int64_t head = d.head ? *d.head : 0;
-        float acc[RW][NR];
+        A acc[RW][NR];
 #pragma unroll
         for (int rr = 0; rr < RW; ++rr)
 #pragma unroll
-            for (int b = 0; b < NR; ++b) acc[rr][b] = 0.f;
+            for (int b = 0; b < NR; ++b) acc[rr][b] = 0;
         for (int64_t k = k0; k < k1; ++k) {
-            const float *x = (const float *)d.x + ((head + k) % d.n_slots) * d.x_slot_stride;
+            const Y *x = (const Y *)d.x + ((head + k) % d.n_slots) * d.x_slot_stride;
             const float *Ak = (const float *)d.A + k * d.lag_stride;
             for (int64_t c = 4 * (int64_t)lane; c < d.cols; c += 256) {
-                f4 xv[NR], v[RW];
+                y4 xv[NR];
+                f4 v[RW];
 #pragma unroll
-                for (int b = 0; b < NR; ++b) xv[b] = *reinterpret_cast<const f4 *>(x + b * d.x_ld + c);
+                for (int b = 0; b < NR; ++b) xv[b] = *reinterpret_cast<const y4 *>(x + b * d.x_ld + c);
 #pragma unroll
                 for (int rr = 0; rr < RW; ++rr)
                     v[rr] = row0 + rr < d.rows
@@ -290,19 +293,19 @@ __global__ __launch_bounds__(256) void k_grouped_mrhs_t(const GDesc *__restrict_
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
 #pragma unroll
-                        for (int b = 0; b < NR; ++b) acc[rr][b] += v[rr][q] * xv[b][q];
+                        for (int b = 0; b < NR; ++b) acc[rr][b] += (A)v[rr][q] * (A)xv[b][q];
             }
         }
 #pragma unroll
         for (int rr = 0; rr < RW; ++rr)
 #pragma unroll
             for (int b = 0; b < NR; ++b) {
-                float x = acc[rr][b];
+                A x = acc[rr][b];
                 for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
                 acc[rr][b] = x;
             }
         if (lane == 0) {
-            float *out = (float *)d.partial + sp * d.rows * NR;
+            A *out = (A *)d.partial + sp * d.rows * NR;
 #pragma unroll
             for (int rr = 0; rr < RW; ++rr)
                 if (row0 + rr < d.rows)
@@ -312,7 +315,8 @@ __global__ __launch_bounds__(256) void k_grouped_mrhs_t(const GDesc *__restrict_
     }
 }
 
-__global__ void k_ring_transpose(int64_t n_slots, int64_t ld, int64_t nrhs, const float *in, float *out)
+template <typename T>
+__global__ void k_ring_transpose(int64_t n_slots, int64_t ld, int64_t nrhs, const T *in, T *out)
 {
     const int64_t n = n_slots * ld * nrhs;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
@@ -320,24 +324,45 @@ __global__ void k_ring_transpose(int64_t n_slots, int64_t ld, int64_t nrhs, cons
         out[(s * nrhs + b) * ld + i] = in[idx];
     }
 }
+__global__ void k_set_i64(int64_t *p, int64_t v) { *p = v; }
+void launch_set_i64(hipStream_t s, int64_t *p, int64_t v) { hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, p, v); }
+__global__ void k_partial_finish_f64(int64_t n, int64_t nsplit, const double *partial, const double *r, double *b)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int64_t q = 0; q < nsplit; ++q) acc += partial[q * n + i];
+    b[i] = r[i] - acc;
+}
+void launch_partial_finish_f64(hipStream_t s, int64_t n, int64_t nsplit, const double *partial, const double *r,
+                               double *b)
+{
+    hipLaunchKernelGGL(k_partial_finish_f64, dim3(nblk(n, 256)), dim3(256), 0, s, n, nsplit, partial, r, b);
+}
 void launch_ring_transpose(hipStream_t s, int64_t n_slots, int64_t ld, int64_t nrhs, const float *in, float *out)
 {
-    hipLaunchKernelGGL(k_ring_transpose, dim3(1024), dim3(256), 0, s, n_slots, ld, nrhs, in, out);
+    hipLaunchKernelGGL(k_ring_transpose<float>, dim3(1024), dim3(256), 0, s, n_slots, ld, nrhs, in, out);
+}
+void launch_ring_transpose(hipStream_t s, int64_t n_slots, int64_t ld, int64_t nrhs, const double *in, double *out)
+{
+    hipLaunchKernelGGL(k_ring_transpose<double>, dim3(1024), dim3(256), 0, s, n_slots, ld, nrhs, in, out);
 }
 
-constexpr int kTransRW = 8;  // rows per wave of the transposed-ring kernel
+// rows per wave of the transposed-ring kernel (FP32 sums; FP64 y and sums)
+constexpr int kTransRW = 8, kTransRWA = 4;
 
 // rows per wave of the multi-right-hand-side kernel: as many as keep the
 // accumulators, the in-flight block vectors and the staged x of one lane
 // within the register budget of three waves per SIMD
 constexpr int mrhs_rw(int kind, int nrhs) { return (kind == GK_F32 && nrhs <= 2) ? 8 : 4; }
 
-bool grouped_ring_transposed(int kind, int nrhs) { return kind == GK_F32 && nrhs >= 2; }
+bool grouped_ring_transposed(int kind, int nrhs) { return (kind == GK_F32 || kind == GK_F32A) && nrhs >= 2; }
 
+// the F32A kernels on either ring layout take 16 rows (4 x mrhs_rw, 4 x kTransRWA)
 int64_t grouped_rows_per_tile(int kind, int nrhs)
 {
     if (nrhs == 1) return 16;
-    if (grouped_ring_transposed(kind, nrhs)) return 4 * kTransRW;
+    if (kind == GK_F32) return 4 * kTransRW;
     return 4 * mrhs_rw(kind, nrhs);
 }
 
@@ -378,6 +403,7 @@ __global__ void k_grouped_store(const GStore *__restrict__ gs, int ngroups)
         d.ring64[slot * d.slot_stride + i] = v;
         if (d.ring32) d.ring32[slot * d.slot_stride + i] = (float)v;
         if (d.ring32t) d.ring32t[(slot * d.nrhs + i % d.nrhs) * d.ldt + i / d.nrhs] = (float)v;
+        if (d.ring64t) d.ring64t[(slot * d.nrhs + i % d.nrhs) * d.ldt + i / d.nrhs] = v;
     }
 }
 
@@ -429,7 +455,7 @@ __global__ void k_grouped_advance(int64_t *steps, int64_t *heads, const int64_t 
 }
 
 void launch_grouped_gemv(hipStream_t s, int kind, int nrhs, const GDesc *gd, int ngroups, int64_t total_tiles,
-                         unsigned long long *counter)
+                         unsigned long long *counter, bool transposed)
 {
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
     unsigned grid = (unsigned)(total_tiles < 4096 ? total_tiles : 4096);
@@ -447,7 +473,11 @@ void launch_grouped_gemv(hipStream_t s, int kind, int nrhs, const GDesc *gd, int
     default: QHP_GM(T, Y, A, 8, mrhs_rw(K, 8)); break;     \
     }
 #define QHP_GF(NR) \
-    hipLaunchKernelGGL((k_grouped_mrhs_t<NR, kTransRW>), dim3(grid), dim3(256), 0, s, gd, ngroups, total_tiles, counter)
+    hipLaunchKernelGGL((k_grouped_mrhs_t<float, float, NR, kTransRW>), dim3(grid), dim3(256), 0, s, gd, ngroups, \
+                       total_tiles, counter)
+#define QHP_GFA(NR) \
+    hipLaunchKernelGGL((k_grouped_mrhs_t<double, double, NR, kTransRWA>), dim3(grid), dim3(256), 0, s, gd, ngroups, \
+                       total_tiles, counter)
     if (kind == GK_F64) { QHP_GN(double, double, double, GK_F64) }
     else if (kind == GK_F32) {
         switch (nrhs) {
@@ -457,7 +487,15 @@ void launch_grouped_gemv(hipStream_t s, int kind, int nrhs, const GDesc *gd, int
         default: QHP_GF(8); break;
         }
     }
+    else if (transposed && nrhs >= 2) {
+        switch (nrhs) {
+        case 2: QHP_GFA(2); break;
+        case 4: QHP_GFA(4); break;
+        default: QHP_GFA(8); break;
+        }
+    }
     else { QHP_GN(float, double, double, GK_F32A) }
+#undef QHP_GFA
 #undef QHP_GF
 #undef QHP_GN
 #undef QHP_GM

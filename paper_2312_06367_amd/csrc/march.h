@@ -42,9 +42,6 @@ void launch_gemv_f64(hipStream_t s, int64_t n, const double *A, const double *x,
 void launch_trsv_lu(hipStream_t s, int64_t n, const double *LU, const double *Dinv, const int32_t *perm,
                     const double *b, double *x, int *flags, const int *epoch, int upper, int *err);
 void launch_bump(hipStream_t s, int *epoch);
-void launch_set_i64(hipStream_t s, int64_t *p, int64_t v);
-// b = r - sum over nsplit partial sums of n entries (FP64)
-void launch_hist_finish_f64(hipStream_t s, int64_t n, int64_t nsplit, const double *partial, const double *r, double *b);
 void launch_diag_inv(hipStream_t s, int64_t n, const double *LU, int upper, double *Dinv);
 void launch_store_y(hipStream_t s, int64_t n, const double *y, double *slot64, float *slot32, double *yhist,
                     int *err);

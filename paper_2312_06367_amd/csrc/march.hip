@@ -875,12 +875,6 @@ void launch_trsv_lu(hipStream_t s, int64_t n, const double *LU, const double *Di
 }
 __global__ void k_bump(int *epoch) { *epoch += 1; }
 void launch_bump(hipStream_t s, int *epoch) { hipLaunchKernelGGL(k_bump, dim3(1), dim3(1), 0, s, epoch); }
-__global__ void k_set_i64(int64_t *p, int64_t v) { *p = v; }
-void launch_set_i64(hipStream_t s, int64_t *p, int64_t v) { hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, p, v); }
-void launch_hist_finish_f64(hipStream_t s, int64_t n, int64_t nsplit, const double *partial, const double *r, double *b)
-{
-    hipLaunchKernelGGL(k_hist_finish<double>, dim3(nblk(n, 256)), dim3(256), 0, s, n, nsplit, partial, r, b);
-}
 
 // Inverses of the 64x64 diagonal blocks of L (unit lower) and U (upper),
 // Dinv[blk][r][c], by forward/back substitution against the identity.
