@@ -1024,7 +1024,7 @@ extern "C" int qhp_history_sum(void *stream, int32_t precision, int64_t ne, int6
 struct qhp_batch {
     std::vector<qhp_ctx *> ctxs;
     hipStream_t s = nullptr;
-    int kind = 0, nrhs = 1, n = 0;
+    int kind = 0, nrhs = 1, n = 0, hv = 0;  // hv: autotuned history tile shape
     bool acc_double = true;
     std::string err;
     DBuf d_hist, d_solve, d_post, f_hist, f_solve, f_post, st, po, steps, heads, nslots, counter, errflag;
@@ -1074,8 +1074,9 @@ static void build_batch(qhp_batch *b)
         const qhp_ctx *a = b->ctxs[x], *q = b->ctxs[y];
         return a->K * a->mesh.ne * a->mesh.ne > q->K * q->mesh.ne * q->mesh.ne;
     });
-    std::vector<qhp::GDesc> dh(n), ds(n), dp(n);
+    std::vector<qhp::GDesc> dh(n), ds(n), dp(n), hist_base(n);
     std::vector<qhp::GFin> fh(n), fs(n), fp(n);
+    const int nvar = qhp::grouped_hist_variants(b->kind, nr, trans);
     std::vector<qhp::GStore> gs(n);
     b->post_host.assign(n, qhp::GPost{});
     std::vector<int64_t> st0(n), hd0(n), nsl(n);
@@ -1097,9 +1098,11 @@ static void build_batch(qhp_batch *b)
         nsl[i] = K;
         const int64_t *dstep = b->steps.as<int64_t>() + i, *dhead = b->heads.as<int64_t>() + i;
         // history group
-        const int64_t rt_h = qhp::grouped_rows_per_tile(b->kind, nr), rt_f = qhp::grouped_rows_per_tile(qhp::GK_F64, nr);
-        int64_t ns_h = group_splits(rt_h, ne, K);
-        b->part_h[i].alloc(asz * ns_h * ne * nr);
+        const int64_t rt_f = qhp::grouped_rows_per_tile(qhp::GK_F64, nr);
+        int64_t ns_max = 1;  // partial sums for the largest split count of any tile shape
+        for (int v = 0; v < nvar; ++v)
+            ns_max = std::max<int64_t>(ns_max, group_splits(qhp::grouped_rows_per_tile(b->kind, nr, trans, v), ne, K));
+        b->part_h[i].alloc(asz * ns_max * ne * nr);
         qhp::GDesc g{};
         g.A = c->slabs.p; g.rows = ne; g.cols = ne; g.ld = ld; g.lag_stride = ne * ld; g.nlags = K;
         g.scales = nullptr;
@@ -1113,11 +1116,9 @@ static void build_batch(qhp_batch *b)
             g.x = b->ringt[i].p;
             g.x_ld = ld;
         }
-        g.partial = b->part_h[i].p; g.nsplit = ns_h; g.rowblocks = (ne + rt_h - 1) / rt_h; g.tile0 = t_h;
-        t_h += g.rowblocks * ns_h;
-        dh[q] = g;
+        g.partial = b->part_h[i].p;
+        hist_base[q] = g;  // rowblocks, nsplit and tile0 per tile shape below
         b->bvec[i].alloc(sizeof(double) * ne * nr);
-        fh[i] = qhp::GFin{b->part_h[i].p, ns_h, ne * nr, c->rhs.as<double>(), dstep, b->bvec[i].as<double>()};
         // solve group: y = T_0^{-1} b (FP64, padded copy of the inverse)
         b->tinv[i].alloc(sizeof(double) * ne * ld);
         zero(b->tinv[i], s);
@@ -1159,6 +1160,61 @@ static void build_batch(qhp_batch *b)
         pp.jhist = nullptr;
         b->post_host[i] = pp;
     }
+    // history descriptors of one tile shape (rows per tile, splits, tile offsets)
+    auto hist_tables = [&](int v) {
+        int64_t t = 0;
+        for (int q = 0; q < n; ++q) {
+            const int i = order[q];
+            const qhp_ctx *c = b->ctxs[i];
+            const int64_t ne = c->mesh.ne, rt = qhp::grouped_rows_per_tile(b->kind, nr, trans, v);
+            qhp::GDesc g = hist_base[q];
+            g.nsplit = group_splits(rt, ne, c->K);
+            g.rowblocks = (ne + rt - 1) / rt;
+            g.tile0 = t;
+            t += g.rowblocks * g.nsplit;
+            dh[q] = g;
+            fh[i] = qhp::GFin{b->part_h[i].p, g.nsplit, ne * nr, c->rhs.as<double>(), b->steps.as<int64_t>() + i,
+                              b->bvec[i].as<double>()};
+        }
+        return t;
+    };
+    b->counter.alloc(sizeof(unsigned long long));
+    // march state first: the autotuning launches read the ring heads
+    hip_check(hipMemcpyAsync(b->steps.p, st0.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s), "state");
+    hip_check(hipMemcpyAsync(b->heads.p, hd0.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s), "state");
+    b->hv = 0;
+    if (nvar > 1) {  // autotune the history tile shape on the batch's own blocks
+        hipEvent_t e0, e1;
+        hip_check(hipEventCreate(&e0), "event");
+        hip_check(hipEventCreate(&e1), "event");
+        float best = 1e30f;
+        for (int v = 0; v < nvar; ++v) {
+            const int64_t tiles = hist_tables(v);
+            upload(b->d_hist, dh, s);
+            auto run = [&]() {
+                qhp::launch_grouped_gemv(s, b->kind, nr, b->d_hist.as<qhp::GDesc>(), n, tiles,
+                                         b->counter.as<unsigned long long>(), trans, v);
+            };
+            run();
+            hip_check(hipEventRecord(e0, s), "event");
+            run();
+            run();
+            hip_check(hipEventRecord(e1, s), "event");
+            hip_check(hipEventSynchronize(e1), "event");
+            float ms = 0.f;
+            hip_check(hipEventElapsedTime(&ms, e0, e1), "event");
+            if (c0->verbose)
+                std::fprintf(stderr, "[qhp] batch history, %lld rows per tile: %.3f ms\n",
+                             (long long)qhp::grouped_rows_per_tile(b->kind, nr, trans, v), ms / 2);
+            if (ms < best) {
+                best = ms;
+                b->hv = v;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    t_h = hist_tables(b->hv);
     b->tiles_h = t_h;
     b->tiles_s = t_s;
     b->tiles_p = t_p;
@@ -1171,9 +1227,6 @@ static void build_batch(qhp_batch *b)
     upload(b->st, gs, s);
     upload(b->po, b->post_host, s);
     upload(b->nslots, nsl, s);
-    hip_check(hipMemcpyAsync(b->steps.p, st0.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s), "state");
-    hip_check(hipMemcpyAsync(b->heads.p, hd0.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s), "state");
-    b->counter.alloc(sizeof(unsigned long long));
     hip_check(hipStreamSynchronize(s), "batch set-up");
 }
 
@@ -1182,7 +1235,7 @@ static void enqueue_batch_step(qhp_batch *b)
     hipStream_t s = b->s;
     const int n = b->n, nr = b->nrhs;
     qhp::launch_grouped_gemv(s, b->kind, nr, b->d_hist.as<qhp::GDesc>(), n, b->tiles_h, b->counter.as<unsigned long long>(),
-                             qhp::grouped_ring_transposed(b->kind, nr));
+                             qhp::grouped_ring_transposed(b->kind, nr), b->hv);
     qhp::launch_grouped_finish(s, b->acc_double, b->f_hist.as<qhp::GFin>(), n, b->max_ne, 0);
     qhp::launch_grouped_gemv(s, qhp::GK_F64, nr, b->d_solve.as<qhp::GDesc>(), n, b->tiles_s, b->counter.as<unsigned long long>(),
                              false);

@@ -63,8 +63,11 @@ struct GPost {
     double *jhist;  // base such that step s writes jhist + s * ne * nrhs (or null)
 };
 
-// rows of one work tile of launch_grouped_gemv for this kind and nrhs
-int64_t grouped_rows_per_tile(int kind, int nrhs);
+// history tile shapes the batch autotunes over (1 where there is no choice)
+int grouped_hist_variants(int kind, int nrhs, bool transposed);
+// rows of one work tile of launch_grouped_gemv for this kind, nrhs, ring
+// layout and variant
+int64_t grouped_rows_per_tile(int kind, int nrhs, bool transposed = false, int variant = 0);
 // whether launch_grouped_gemv of this kind and nrhs reads the ring transposed
 bool grouped_ring_transposed(int kind, int nrhs);
 // ring [n_slots][ld][nrhs] -> [n_slots][nrhs][ld]
@@ -73,7 +76,7 @@ void launch_ring_transpose(hipStream_t s, int64_t n_slots, int64_t ld, int64_t n
 // transposed: the groups' rings are [nrhs][x_ld] per slot (the batch, for the
 // kinds grouped_ring_transposed names) or [cols][nrhs] (one context's own ring)
 void launch_grouped_gemv(hipStream_t s, int kind, int nrhs, const GDesc *gd, int ngroups, int64_t total_tiles,
-                         unsigned long long *counter, bool transposed);
+                         unsigned long long *counter, bool transposed, int variant = 0);
 void launch_grouped_finish(hipStream_t s, bool acc_double, const GFin *gf, int ngroups, int64_t max_n, int negate);
 void launch_grouped_store(hipStream_t s, const GStore *gs, int ngroups, int64_t max_n);
 void launch_grouped_post(hipStream_t s, int part, const GPost *gp, int ngroups, int64_t max_n);

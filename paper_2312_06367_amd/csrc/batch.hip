@@ -348,8 +348,10 @@ void launch_ring_transpose(hipStream_t s, int64_t n_slots, int64_t ld, int64_t n
     hipLaunchKernelGGL(k_ring_transpose<double>, dim3(1024), dim3(256), 0, s, n_slots, ld, nrhs, in, out);
 }
 
-// rows per wave of the transposed-ring kernel (FP32 sums; FP64 y and sums)
-constexpr int kTransRW = 8, kTransRWA = 4;
+// rows per wave of the transposed-ring kernel: the tile shapes the batch's
+// autotuner chooses from (FP32 sums; FP64 y and sums)
+constexpr int kTransRWs[] = {8, 4, 16};
+constexpr int kTransRWAs[] = {4, 2, 8};
 
 // rows per wave of the multi-right-hand-side kernel: as many as keep the
 // accumulators, the in-flight block vectors and the staged x of one lane
@@ -358,11 +360,17 @@ constexpr int mrhs_rw(int kind, int nrhs) { return (kind == GK_F32 && nrhs <= 2)
 
 bool grouped_ring_transposed(int kind, int nrhs) { return (kind == GK_F32 || kind == GK_F32A) && nrhs >= 2; }
 
-// the F32A kernels on either ring layout take 16 rows (4 x mrhs_rw, 4 x kTransRWA)
-int64_t grouped_rows_per_tile(int kind, int nrhs)
+int grouped_hist_variants(int kind, int nrhs, bool transposed)
+{
+    return (transposed && nrhs >= 2 && kind != GK_F64) ? 3 : 1;
+}
+
+// rows of one work tile (4 waves): variant 0 is the default shape
+int64_t grouped_rows_per_tile(int kind, int nrhs, bool transposed, int variant)
 {
     if (nrhs == 1) return 16;
-    if (kind == GK_F32) return 4 * kTransRW;
+    if (transposed && kind == GK_F32) return 4 * kTransRWs[variant < 0 || variant > 2 ? 0 : variant];
+    if (transposed && kind == GK_F32A) return 4 * kTransRWAs[variant < 0 || variant > 2 ? 0 : variant];
     return 4 * mrhs_rw(kind, nrhs);
 }
 
@@ -455,8 +463,9 @@ __global__ void k_grouped_advance(int64_t *steps, int64_t *heads, const int64_t 
 }
 
 void launch_grouped_gemv(hipStream_t s, int kind, int nrhs, const GDesc *gd, int ngroups, int64_t total_tiles,
-                         unsigned long long *counter, bool transposed)
+                         unsigned long long *counter, bool transposed, int variant)
 {
+    if (variant < 0 || variant >= grouped_hist_variants(kind, nrhs, transposed)) variant = 0;
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
     unsigned grid = (unsigned)(total_tiles < 4096 ? total_tiles : 4096);
     if (grid == 0) return;
@@ -472,12 +481,22 @@ void launch_grouped_gemv(hipStream_t s, int kind, int nrhs, const GDesc *gd, int
     case 4: QHP_GM(T, Y, A, 4, mrhs_rw(K, 4)); break;      \
     default: QHP_GM(T, Y, A, 8, mrhs_rw(K, 8)); break;     \
     }
-#define QHP_GF(NR) \
-    hipLaunchKernelGGL((k_grouped_mrhs_t<float, float, NR, kTransRW>), dim3(grid), dim3(256), 0, s, gd, ngroups, \
-                       total_tiles, counter)
-#define QHP_GFA(NR) \
-    hipLaunchKernelGGL((k_grouped_mrhs_t<double, double, NR, kTransRWA>), dim3(grid), dim3(256), 0, s, gd, ngroups, \
-                       total_tiles, counter)
+#define QHP_GT(Y, NR, RWS)                                                                                      \
+    switch (variant) {                                                                                          \
+    case 1:                                                                                                     \
+        hipLaunchKernelGGL((k_grouped_mrhs_t<Y, Y, NR, RWS[1]>), dim3(grid), dim3(256), 0, s, gd, ngroups,      \
+                           total_tiles, counter);                                                               \
+        break;                                                                                                  \
+    case 2:                                                                                                     \
+        hipLaunchKernelGGL((k_grouped_mrhs_t<Y, Y, NR, RWS[2]>), dim3(grid), dim3(256), 0, s, gd, ngroups,      \
+                           total_tiles, counter);                                                               \
+        break;                                                                                                  \
+    default:                                                                                                    \
+        hipLaunchKernelGGL((k_grouped_mrhs_t<Y, Y, NR, RWS[0]>), dim3(grid), dim3(256), 0, s, gd, ngroups,      \
+                           total_tiles, counter);                                                               \
+    }
+#define QHP_GF(NR) QHP_GT(float, NR, kTransRWs)
+#define QHP_GFA(NR) QHP_GT(double, NR, kTransRWAs)
     if (kind == GK_F64) { QHP_GN(double, double, double, GK_F64) }
     else if (kind == GK_F32) {
         switch (nrhs) {
@@ -497,6 +516,7 @@ void launch_grouped_gemv(hipStream_t s, int kind, int nrhs, const GDesc *gd, int
     else { QHP_GN(float, double, double, GK_F32A) }
 #undef QHP_GFA
 #undef QHP_GF
+#undef QHP_GT
 #undef QHP_GN
 #undef QHP_GM
 #undef QHP_G1
