@@ -338,7 +338,8 @@ __global__ void k_hist_finish(int64_t n, int64_t nsplit, const A *partial, const
 struct GemvVariant {
     int rpw, unr, nt;
 };
-static const GemvVariant kGemvVariants[] = {{4, 1, 0}, {4, 2, 0}, {4, 2, 1}, {8, 1, 1}, {8, 2, 1}, {2, 4, 1}, {4, 4, 1}};
+static const GemvVariant kGemvVariants[] = {{4, 1, 0}, {4, 2, 0}, {4, 2, 1}, {8, 1, 1}, {8, 2, 1}, {2, 4, 1}, {4, 4, 1},
+                                             {2, 8, 1}, {8, 4, 1}};
 constexpr int kNumGemvVariants = sizeof(kGemvVariants) / sizeof(kGemvVariants[0]);
 int gemv_variant_count() { return kNumGemvVariants; }
 void gemv_variant_desc(int v, int *rpw, int *unr, int *nt)
@@ -366,8 +367,10 @@ static void gemv_dispatch(int v, hipStream_t s, int64_t ne, int64_t ld, int64_t 
         QHP_GEMV_CASE(3, 8, 1, true)
         QHP_GEMV_CASE(4, 8, 2, true)
         QHP_GEMV_CASE(5, 2, 4, true)
-        default:
         QHP_GEMV_CASE(6, 4, 4, true)
+        QHP_GEMV_CASE(7, 2, 8, true)
+        default:
+        QHP_GEMV_CASE(8, 8, 4, true)
     }
 #undef QHP_GEMV_CASE
 }
