@@ -517,6 +517,14 @@ def main():
         "forms": forms,
         "assembly_s": t_asm,
         "roofline": roof,
+        # the byte floor of the factored form (raw shell-sparse lag matrices
+        # with 32-bit indices, then the two dense preconditioners once per
+        # step), against the dense FP32 blocks this build streams
+        "factored_history_floor": {
+            "raw_nnz": inf["raw_nnz"],
+            "bytes_fp32": inf["raw_nnz"] * (4 + 4) + 2 * ne * ne * 4,
+            "dense_slab_bytes_fp32": K * ne * ne * 4,
+            "dense_over_floor": K * ne * ne * 4 / (inf["raw_nnz"] * (4 + 4) + 2 * ne * ne * 4)},
     }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ne, K)

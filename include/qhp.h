@@ -129,6 +129,9 @@ typedef struct {
     size_t slab_bytes;   /* device bytes of the stored T_1..T_K              */
     int64_t hist_variant; /* autotuned history-kernel variant (-1: none)    */
     int64_t hist_splits;  /* lag splits of the history sum                  */
+    int64_t raw_nnz;      /* nonzeros of the raw lag matrices A_k, B_k, C_k,
+                             k = 1..K (Sec. IV-A): the shell-sparse operands
+                             a factored history would stream instead of T_k */
 } qhp_info;
 
 /* Create a context (no device work beyond selecting params->device).

@@ -55,7 +55,7 @@ class _Info(ctypes.Structure):
                 ("n_harmonic", ctypes.c_int64), ("K", ctypes.c_int64), ("n_rhs", ctypes.c_int64),
                 ("n_steps", ctypes.c_int64), ("step", ctypes.c_int64), ("ld", ctypes.c_int64),
                 ("diameter", ctypes.c_double), ("slab_bytes", ctypes.c_size_t),
-                ("hist_variant", ctypes.c_int64), ("hist_splits", ctypes.c_int64)]
+                ("hist_variant", ctypes.c_int64), ("hist_splits", ctypes.c_int64), ("raw_nnz", ctypes.c_int64)]
 
 
 EXPORTS = ["qhp_create", "qhp_mesh", "qhp_assemble", "qhp_set_precision", "qhp_set_solver", "qhp_profile",

@@ -350,6 +350,9 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
         Bk.alloc(sizeof(double) * nn); E.alloc(sizeof(double) * nn);
         Wst.alloc(sizeof(double) * nn * 2); Tt.alloc(sizeof(double) * nn);
         amax.alloc(sizeof(unsigned long long));
+        DBuf nnz;  // nonzeros of the raw lag matrices, k >= 1
+        nnz.alloc(sizeof(unsigned long long));
+        zero(nnz, s);
         DBuf carry;  // rounding carried from lag to lag (reduced precisions only)
         if (prec != QHP_F64) {
             carry.alloc(sizeof(double) * nn);
@@ -385,6 +388,9 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
                 qhp::launch_lag_ac(s, (int64_t)nn, k, c->p.dt, shellV(k), shellV(k - 1), shellN(k), shellN(k - 1),
                                    c->G.as<double>(), Ak.as<double>(), Ck.as<double>());
                 qhp::launch_bk(s, a, shellS(k), shellS(k - 1), shellS(k - 2), c->T0, Bk.as<double>());
+                if (k >= 1)
+                    for (const DBuf *m : {&Ak, &Bk, &Ck})
+                        qhp::count_nonzero(s, (int64_t)nn, m->as<double>(), nnz.as<unsigned long long>());
                 if (c->keep_raw) {
                     c->rawA[k].resize(nn);
                     c->rawB[k].resize(nn);
@@ -417,6 +423,9 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
             hip_check(hipStreamSynchronize(s), "lag blocks");
             c->stage("lag combination + slab GEMMs");
         }
+        unsigned long long cnt = 0;
+        hip_check(hipMemcpy(&cnt, nnz.p, sizeof(cnt), hipMemcpyDeviceToHost), "nonzero count");
+        c->raw_nnz = (int64_t)cnt;
     }
     upload(c->scales_d, c->scales, s);
     // ---- T_0: FP64 LU, diagonal-block inverses, optional explicit inverse
@@ -907,6 +916,7 @@ extern "C" int qhp_query(const qhp_ctx *ctx, qhp_info *info)
     info->step = ctx->step;
     info->hist_variant = ctx->hv;
     info->hist_splits = ctx->nsplit;
+    info->raw_nnz = ctx->raw_nnz;
     return QHP_OK;
 }
 

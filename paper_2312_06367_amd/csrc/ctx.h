@@ -95,6 +95,7 @@ struct qhp_ctx {
     qhp::DBuf mr_desc, mr_head, mr_counter;
     int64_t mr_tiles = 0, mr_splits = 0;
     int nsplit = 1;
+    int64_t raw_nnz = 0;  // nonzeros of A_k, B_k, C_k, k = 1..K
     int hv = -1;  // autotuned variant of the history kernel (single right-hand side, or int8 digits)
     // profiling of the history kernel
     bool profiling = false;

@@ -17,6 +17,8 @@ void axpby(hipStream_t s, int64_t n, double a, const double *x, double b, const 
 void transpose_f64(hipStream_t s, int64_t rows, int64_t cols, const double *in, int64_t ldi,
                    double *out, int64_t ldo);
 void symmetrize(hipStream_t s, int64_t n, double *A);
+// count += number of nonzero entries of x [n] (device counter)
+void count_nonzero(hipStream_t s, int64_t n, const double *x, unsigned long long *count);
 // In-place LU with partial pivoting (P A = L U, unit L); ipiv is device
 // [n] (0-based row swapped with row j at step j).  Returns 0 or j+1 of the
 // first zero pivot.  Synchronises the stream.

@@ -398,4 +398,17 @@ void getrs_f64(hipStream_t s, bool trans, int64_t n, int64_t nrhs, const double 
     }
 }
 
+__global__ void k_count_nonzero(int64_t n, const double *x, unsigned long long *count)
+{
+    unsigned long long c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        c += x[i] != 0.0;
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, c);
+}
+void count_nonzero(hipStream_t s, int64_t n, const double *x, unsigned long long *count)
+{
+    hipLaunchKernelGGL(k_count_nonzero, dim3(1024), dim3(256), 0, s, n, x, count);
+}
+
 }  // namespace qhp

@@ -92,6 +92,18 @@ def test_raw_lag_and_slab_parity(small):
     assert worst < 1e-10
 
 
+def test_raw_nonzero_count(small):
+    """The count of nonzeros of the raw lag matrices A_k, B_k, C_k (k >= 1)
+    that the library reports (the operands of a factored history) equals
+    the oracle's count on the same mesh to within entries that round to zero
+    on one side only."""
+    asm, s = small["asm"], small["s"]
+    want = sum(int(np.count_nonzero(M[k])) for M in (asm.A, asm.B, asm.C) for k in range(1, asm.K + 1))
+    got = s.info()["raw_nnz"]
+    _say("[small] raw nonzeros: library %d, oracle %d, dense %d" % (got, want, 3 * asm.K * asm.topo.ne ** 2))
+    assert abs(got - want) <= 0.005 * want
+
+
 @pytest.mark.parametrize("precision,unit", [("f32", 2.0 ** -24 * (1 + 1e-9)), ("bf16", 2.0 ** -8 * 1.001 + 2.0 ** -22)])
 def test_lag_carried_rounding(small, precision, unit):
     """Stored reduced-precision blocks carry each block's rounding into the
