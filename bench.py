@@ -293,7 +293,7 @@ def bench_warm(a):
 
     def march(tag, setup):
         setup()
-        tot_it, r0s, wall = 0, [], 0.0
+        tot_it, r0s, wall, net = 0, [], 0.0, 0
         for w in held:
             sv.gmres_reset()
             sv.set_incident([w], n_ev)
@@ -305,18 +305,21 @@ def bench_warm(a):
             if tag.startswith("gmres"):
                 st = sv.gmres_stats(n_ev)
                 tot_it += st["iterations"]
+                net += st["network_starts"]
                 r0s.append(st["res0"][8:])
         rec = {"steps_per_s": len(held) * n_ev / wall}
         if r0s:
             r = np.concatenate(r0s)
             rec.update({"iterations_per_step": tot_it / (len(held) * n_ev),
                         "median_start_residual": float(np.median(r[r > 0])) if (r > 0).any() else 0.0})
+            if tag == "gmres-best":
+                rec["network_start_fraction"] = net / (len(held) * n_ev)
         modes[tag] = rec
         log("%-14s %s" % (tag, json.dumps(rec)))
 
     march("lu", lambda: sv.set_solver("lu"))
     march("inv", lambda: sv.set_solver("inv"))
-    for warm in ("cold", "prev", "extrap", "quad", "mlp"):
+    for warm in ("cold", "prev", "extrap", "quad", "mlp", "best"):
         march("gmres-" + warm, lambda warm=warm: sv.set_gmres(1e-10, 40, 4, warm))
     sv.attach_mlp(None)
     m.close()

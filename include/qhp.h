@@ -87,7 +87,10 @@ enum {
     QHP_WARM_PREV = 1,   /* y_{i-1}                                            */
     QHP_WARM_EXTRAP = 2, /* 2 y_{i-1} - y_{i-2}                                */
     QHP_WARM_QUAD = 3,   /* 3 y_{i-1} - 3 y_{i-2} + y_{i-3}                    */
-    QHP_WARM_MLP = 4     /* the attached perceptron's guess from y_{i-1..i-4}  */
+    QHP_WARM_MLP = 4,    /* the attached perceptron's guess from y_{i-1..i-4}  */
+    QHP_WARM_BEST = 5    /* the perceptron's guess or quadratic extrapolation,
+                            whichever has the smaller FP64 residual against
+                            this step's right-hand side (two residuals per step) */
 };
 
 typedef struct qhp_ctx qhp_ctx;
@@ -298,7 +301,8 @@ void qhp_batch_destroy(qhp_batch *b);
  *   1e-6, and FP64 refinement repeats until |r| <= tol |b| (tol > 0, e.g.
  *   1e-10) or max_refine inner solves of at most m_max (1..512) iterations
  *   each have run; then the step falls back to the LU solve and counts a
- *   fallback.  warm: QHP_WARM_*; QHP_WARM_MLP needs qhp_attach_mlp first.
+ *   fallback.  warm: QHP_WARM_*; QHP_WARM_MLP and QHP_WARM_BEST need
+ *   qhp_attach_mlp first.
  *   Needs an assembled context and one right-hand side (QHP_EINVAL else).
  * qhp_gmres_stats: totals since the last reset (or context creation): steps
  *   solved, inner iterations (products with T_0), maximum per step, inner
@@ -308,6 +312,7 @@ void qhp_batch_destroy(qhp_batch *b);
  * qhp_gmres_reset: clear those records. */
 typedef struct {
     int64_t steps, iterations, max_iterations, refinements, fallbacks;
+    int64_t network_starts; /* QHP_WARM_BEST steps that started from the perceptron */
 } qhp_gmres_info;
 int qhp_set_gmres(qhp_ctx *ctx, double tol, int32_t m_max, int32_t max_refine, int32_t warm);
 int qhp_gmres_stats(const qhp_ctx *ctx, qhp_gmres_info *info, int32_t *iters, float *res0, int64_t n);

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libqhp.so")
 
 QHP_F64, QHP_F32, QHP_BF16, QHP_F32A, QHP_BF16X2, QHP_I8X4 = 0, 1, 2, 3, 4, 5
 QHP_SOLVE_LU, QHP_SOLVE_INV, QHP_SOLVE_GMRES = 0, 1, 2
-WARM = {"cold": 0, "prev": 1, "extrap": 2, "quad": 3, "mlp": 4}
+WARM = {"cold": 0, "prev": 1, "extrap": 2, "quad": 3, "mlp": 4, "best": 5}
 MAT = {"gram": 0, "zs": 1, "zh": 2, "m": 3, "psigma": 4, "plambda": 5, "pe": 6, "pm": 7,
        "slab": 8, "a": 9, "b": 10, "c": 11}
 ERRORS = {0: "OK", -1: "EINVAL", -2: "EMESH", -3: "ESTATE", -4: "ENOMEM", -5: "EDEVICE",
@@ -47,7 +47,7 @@ class _Wave(ctypes.Structure):
 
 class _GmresInfo(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("iterations", ctypes.c_int64), ("max_iterations", ctypes.c_int64),
-                ("refinements", ctypes.c_int64), ("fallbacks", ctypes.c_int64)]
+                ("refinements", ctypes.c_int64), ("fallbacks", ctypes.c_int64), ("network_starts", ctypes.c_int64)]
 
 
 class _Info(ctypes.Structure):

@@ -700,7 +700,7 @@ static void do_step(qhp_ctx *c, double *j_out, double *y_out)
     }
     double *y = c->yvec.as<double>();
     if (c->p.solver == QHP_SOLVE_GMRES) {
-        qhp::warm_start(c, y);
+        qhp::warm_start(c, c->bvec.as<double>(), y);
         int32_t it = 0;
         float r0 = 0.f;
         const bool ok = qhp::gmres_solve(c, c->bvec.as<double>(), y, &it, &r0);

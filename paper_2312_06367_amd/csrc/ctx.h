@@ -116,10 +116,10 @@ struct qhp_ctx {
     double gm_tol = 1e-10;
     int gm_m = 40, gm_refine = 4, warm = 0;
     qhp::DBuf T0f, gm_V, gm_w, gm_h1, gm_h2, gm_nrm, gm_R, gm_cs, gm_sn, gm_g, gm_inv, gm_y, gm_r, gm_x0;
-    double *gm_host = nullptr;  // pinned: residual estimate, |r|^2, |b|^2
+    double *gm_host = nullptr;  // pinned: residual estimate, |r|^2, |b|^2, the two start residuals
     std::vector<int32_t> gm_iters;
     std::vector<float> gm_res0;
-    int64_t gm_refines = 0, gm_fallbacks = 0;
+    int64_t gm_refines = 0, gm_fallbacks = 0, gm_net_starts = 0;
     // loop/star/harmonic coordinates of the mesh (learned warm start)
     qhp::DBuf LLp, Hb, ls_sig, ls_lam;
     int64_t ls_nh = -1, ls_cap = 0;
@@ -143,7 +143,7 @@ void loopstar_features(qhp_ctx *c, const double *Y, int64_t n, int64_t ldy, doub
 void loopstar_reconstruct(qhp_ctx *c, const double *F, int64_t n, int64_t ldf, double *Y, int64_t ldy);
 // iterative T_0 solve: buffers, start vector, solve, feature record
 void gmres_prepare(qhp_ctx *c);
-void warm_start(qhp_ctx *c, double *x0);
+void warm_start(qhp_ctx *c, const double *b, double *x0);
 bool gmres_solve(qhp_ctx *c, const double *b, double *x, int32_t *iters, float *res0);
 void warm_record(qhp_ctx *c, const double *y);
 }  // namespace qhp

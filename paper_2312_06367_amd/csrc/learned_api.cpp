@@ -497,10 +497,10 @@ void gmres_prepare(qhp_ctx *c)
     c->gm_x0.alloc(sizeof(double) * ne);
     if (!c->gm_host) {
         void *p = nullptr;
-        hip_check(hipHostMalloc(&p, 4 * sizeof(double), hipHostMallocDefault), "pinned scalars");
+        hip_check(hipHostMalloc(&p, 6 * sizeof(double), hipHostMallocDefault), "pinned scalars");
         c->gm_host = (double *)p;
     }
-    if (c->warm == QHP_WARM_MLP) {
+    if (c->warm == QHP_WARM_MLP || c->warm == QHP_WARM_BEST) {
         if (!c->mlp) throw Fail{QHP_ESTATE, "no perceptron attached"};
         c->feat.alloc(sizeof(double) * 4 * c->mlp->nf);
     }
@@ -515,14 +515,39 @@ static const double *ring_y(qhp_ctx *c, int back)
     return c->ring64.as<double>() + slot * c->ld;
 }
 
-void warm_start(qhp_ctx *c, double *x0)
+static void warm_guess(qhp_ctx *c, int mode, const double *y1, const double *y2, const double *y3, double *x0);
+
+void warm_start(qhp_ctx *c, const double *b, double *x0)
 {
     hipStream_t s = c->s;
     const int64_t ne = c->mesh.ne;
     const double *y1 = ring_y(c, 1), *y2 = ring_y(c, 2);
     const double *y3 = ring_y(c, 3);
     int mode = c->warm;
-    if (mode == QHP_WARM_MLP && (!c->mlp || c->feat_n < 4)) mode = QHP_WARM_QUAD;
+    if ((mode == QHP_WARM_MLP || mode == QHP_WARM_BEST) && (!c->mlp || c->feat_n < 4)) mode = QHP_WARM_QUAD;
+    if (mode == QHP_WARM_BEST) {  // both guesses, the one with the smaller FP64 residual
+        warm_guess(c, QHP_WARM_MLP, y1, y2, y3, x0);
+        double *xq = c->gm_x0.as<double>();
+        warm_guess(c, QHP_WARM_QUAD, y1, y2, y3, xq);
+        launch_gm_residual(s, ne, c->T0raw.as<double>(), x0, b, c->gm_r.as<double>(), c->gm_nrm.as<double>(),
+                           c->gm_host + 4);
+        launch_gm_residual(s, ne, c->T0raw.as<double>(), xq, b, c->gm_r.as<double>(), c->gm_nrm.as<double>(),
+                           c->gm_host + 5);
+        hip_check(hipStreamSynchronize(s), "warm start");
+        volatile double *hv = c->gm_host;
+        if (hv[5] < hv[4])
+            hip_check(hipMemcpyAsync(x0, xq, sizeof(double) * ne, hipMemcpyDeviceToDevice, s), "warm start");
+        else
+            c->gm_net_starts += 1;
+        return;
+    }
+    warm_guess(c, mode, y1, y2, y3, x0);
+}
+
+static void warm_guess(qhp_ctx *c, int mode, const double *y1, const double *y2, const double *y3, double *x0)
+{
+    hipStream_t s = c->s;
+    const int64_t ne = c->mesh.ne;
     if (mode == QHP_WARM_QUAD && !y3) mode = QHP_WARM_EXTRAP;
     if (mode == QHP_WARM_EXTRAP && !y2) mode = QHP_WARM_PREV;
     if (mode == QHP_WARM_PREV && !y1) mode = QHP_WARM_COLD;
@@ -549,7 +574,7 @@ void warm_start(qhp_ctx *c, double *x0)
 
 void warm_record(qhp_ctx *c, const double *y)
 {
-    if (c->warm != QHP_WARM_MLP || !c->mlp) return;
+    if ((c->warm != QHP_WARM_MLP && c->warm != QHP_WARM_BEST) || !c->mlp) return;
     const int64_t nf = c->mlp->nf;
     loopstar_features(c, y, 1, c->mesh.ne, c->feat.as<double>() + (c->feat_n % 4) * nf, nf);
     c->feat_n += 1;
@@ -617,11 +642,12 @@ bool gmres_solve(qhp_ctx *c, const double *b, double *x, int32_t *iters, float *
 extern "C" int qhp_set_gmres(qhp_ctx *ctx, double tol, int32_t m_max, int32_t max_refine, int32_t warm)
 {
     if (!ctx) return QHP_EINVAL;
-    if (!(tol > 0.0) || m_max < 1 || m_max > 512 || max_refine < 1 || warm < QHP_WARM_COLD || warm > QHP_WARM_MLP)
+    if (!(tol > 0.0) || m_max < 1 || m_max > 512 || max_refine < 1 || warm < QHP_WARM_COLD || warm > QHP_WARM_BEST)
         return guard(ctx, QHP_EINVAL, "bad GMRES parameters");
     if (ctx->state < 2) return guard(ctx, QHP_ESTATE, "assemble first");
     if (ctx->state == 3 && ctx->nrhs != 1) return guard(ctx, QHP_EINVAL, "GMRES takes one right-hand side");
-    if (warm == QHP_WARM_MLP && !ctx->mlp) return guard(ctx, QHP_ESTATE, "attach a perceptron first");
+    if ((warm == QHP_WARM_MLP || warm == QHP_WARM_BEST) && !ctx->mlp)
+        return guard(ctx, QHP_ESTATE, "attach a perceptron first");
     try {
         hip_check(hipSetDevice(ctx->p.device), "hipSetDevice");
         ctx->gm_tol = tol;
@@ -648,6 +674,7 @@ extern "C" int qhp_gmres_stats(const qhp_ctx *ctx, qhp_gmres_info *info, int32_t
     }
     info->refinements = ctx->gm_refines;
     info->fallbacks = ctx->gm_fallbacks;
+    info->network_starts = ctx->gm_net_starts;
     for (int64_t i = 0; i < n && i < ns; ++i) {
         if (iters) iters[i] = ctx->gm_iters[i];
         if (res0) res0[i] = ctx->gm_res0[i];
@@ -662,5 +689,6 @@ extern "C" int qhp_gmres_reset(qhp_ctx *ctx)
     ctx->gm_res0.clear();
     ctx->gm_refines = 0;
     ctx->gm_fallbacks = 0;
+    ctx->gm_net_starts = 0;
     return QHP_OK;
 }
