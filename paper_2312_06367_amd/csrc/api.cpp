@@ -1214,8 +1214,9 @@ static void build_batch(qhp_batch *b)
             float ms = 0.f;
             hip_check(hipEventElapsedTime(&ms, e0, e1), "event");
             if (c0->verbose)
-                std::fprintf(stderr, "[qhp] batch history, %lld rows per tile: %.3f ms\n",
-                             (long long)qhp::grouped_rows_per_tile(b->kind, nr, trans, v), ms / 2);
+                std::fprintf(stderr, "[qhp] batch history, %lld rows per tile (%s): %.3f ms\n",
+                             (long long)qhp::grouped_rows_per_tile(b->kind, nr, trans, v),
+                             qhp::grouped_variant_name(b->kind, nr, trans, v), ms / 2);
             if (ms < best) {
                 best = ms;
                 b->hv = v;

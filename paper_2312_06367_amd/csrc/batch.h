@@ -68,6 +68,8 @@ int grouped_hist_variants(int kind, int nrhs, bool transposed);
 // rows of one work tile of launch_grouped_gemv for this kind, nrhs, ring
 // layout and variant
 int64_t grouped_rows_per_tile(int kind, int nrhs, bool transposed = false, int variant = 0);
+// short description of a history tile shape (for logs)
+const char *grouped_variant_name(int kind, int nrhs, bool transposed, int variant);
 // whether launch_grouped_gemv of this kind and nrhs reads the ring transposed
 bool grouped_ring_transposed(int kind, int nrhs);
 // ring [n_slots][ld][nrhs] -> [n_slots][nrhs][ld]

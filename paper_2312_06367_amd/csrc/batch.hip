@@ -240,20 +240,24 @@ __global__ __launch_bounds__(256, MINB) void k_grouped_mrhs(const GDesc *__restr
 }
 
 // Multi-right-hand-side form with FP32 blocks on a transposed ring ([nrhs]
-// [x_ld] per slot, Y = float for FP32 sums, double for FP64 y and sums): for
-// each chunk of 256 columns a lane loads one 16-byte vector of each of its RW
-// rows and the four matching entries of each right-hand side, all fully
-// coalesced, with no LDS and no barrier in the streaming loop.  Columns past
-// the last one are zero in both operands.
-template <typename Y, typename A, int NR, int RW>
+// [x_ld] per slot, Y = float for FP32 sums, double for FP64 y and sums),
+// staged in registers: the 64 lanes of a wave are CG column lanes times
+// 64 / CG row groups of RW rows.  For each chunk of 4 CG columns a lane loads
+// one 16-byte vector of each of its rows and the four matching entries of
+// each right-hand side, fully coalesced, with no LDS and no barrier in the
+// streaming loop; the 64 / CG row groups of a wave ask for the same entries
+// of the right-hand sides, so fewer distinct cache lines are read per load
+// when CG < 64.  Columns past the last one are zero in both operands.
+template <typename Y, typename A, int NR, int RW, int CG>
 __global__ __launch_bounds__(256) void k_grouped_mrhs_t(const GDesc *__restrict__ gd, int ngroups,
                                                         int64_t total_tiles, unsigned long long *counter)
 {
     typedef float f4 __attribute__((ext_vector_type(4)));
     typedef Y y4 __attribute__((ext_vector_type(4)));
-    constexpr int ROWS = 4 * RW;
+    constexpr int ROWS_W = (64 / CG) * RW, ROWS = 4 * ROWS_W;
     __shared__ int64_t s_tile;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int cg = lane % CG, rg = lane / CG;
     for (;;) {
         if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(counter, 1ull);
         __syncthreads();
@@ -265,7 +269,7 @@ __global__ __launch_bounds__(256) void k_grouped_mrhs_t(const GDesc *__restrict_
         const GDesc d = gd[g];
         const int64_t local = tile - d.tile0;
         const int64_t rb = local % d.rowblocks, sp = local / d.rowblocks;
-        const int64_t row0 = rb * ROWS + wave * RW;
+        const int64_t row0 = rb * ROWS + wave * ROWS_W + rg * RW;
         const int64_t lps = (d.nlags + d.nsplit - 1) / d.nsplit;
         const int64_t k0 = sp * lps;
         const int64_t k1 = (k0 + lps < d.nlags) ? k0 + lps : d.nlags;
@@ -278,7 +282,7 @@ __global__ __launch_bounds__(256) void k_grouped_mrhs_t(const GDesc *__restrict_
         for (int64_t k = k0; k < k1; ++k) {
             const Y *x = (const Y *)d.x + ((head + k) % d.n_slots) * d.x_slot_stride;
             const float *Ak = (const float *)d.A + k * d.lag_stride;
-            for (int64_t c = 4 * (int64_t)lane; c < d.cols; c += 256) {
+            for (int64_t c = 4 * (int64_t)cg; c < d.cols; c += 4 * CG) {
                 y4 xv[NR];
                 f4 v[RW];
 #pragma unroll
@@ -301,11 +305,143 @@ __global__ __launch_bounds__(256) void k_grouped_mrhs_t(const GDesc *__restrict_
 #pragma unroll
             for (int b = 0; b < NR; ++b) {
                 A x = acc[rr][b];
-                for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+                for (int off = CG / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
                 acc[rr][b] = x;
             }
-        if (lane == 0) {
+        if (cg == 0) {
             A *out = (A *)d.partial + sp * d.rows * NR;
+#pragma unroll
+            for (int rr = 0; rr < RW; ++rr)
+                if (row0 + rr < d.rows)
+#pragma unroll
+                    for (int b = 0; b < NR; ++b) out[(row0 + rr) * NR + b] = acc[rr][b];
+        }
+    }
+}
+
+// The same product staged in LDS.  A tile's steps are (lag, chunk of 64
+// columns); each step's block rows (4 rows x 256 bytes per 1 KB piece) and
+// right-hand-side entries are copied straight from memory into one of NB LDS
+// buffers (global_load_lds, 16 bytes a lane), NB - 1 steps ahead of the
+// arithmetic, so a wave keeps the copies in flight without holding them in
+// registers.  Each wave waits only for its own copies of the next step
+// (vmcnt counts them exactly: no other vector memory access is issued in the
+// loop), then one barrier makes every wave's copies visible.  Lanes are 16
+// column lanes times 4 row groups of RW rows; the 4 row groups read the same
+// right-hand-side entries (an LDS broadcast).  Columns past the last one are
+// zero in both operands; rows past the last one are clamped in the copies
+// and never written.  One work-group per tile (no work queue: the tiles are
+// in the queue's order, biggest scatterer first, and the dispatcher starts
+// them in that order), so that no copy of one tile is pending in the next.
+template <typename Y, int NR, int RW, int NB, int MINW>
+__global__ __launch_bounds__(256, MINW) void k_grouped_mrhs_d(const GDesc *__restrict__ gd, int ngroups,
+                                                              int64_t total_tiles)
+{
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    typedef int i4 __attribute__((ext_vector_type(4)));
+    constexpr int CG = 16, ROWS_W = 4 * RW, ROWS = 4 * ROWS_W;
+    constexpr int AP = ROWS / 4;                                   // block pieces of a step
+    constexpr int YP = (NR * 64 * (int)sizeof(Y) + 1023) / 1024;  // right-hand-side pieces
+    constexpr int PIECES = (AP + YP + 3) / 4 * 4, PW = PIECES / 4, PF = NB - 1;
+    // vmcnt(PW (PF - 1)) with the other counters left alone (gfx9 encoding)
+    constexpr int WAIT_INFLIGHT = ((PW * (PF - 1)) & 15) | (7 << 4) | (15 << 8) | (((PW * (PF - 1)) >> 4) << 14);
+    static_assert(NB >= 2 && PW * (PF - 1) < 64, "steps in flight");
+    __shared__ i4 S[NB][PIECES * 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int cg = lane % CG, rg = lane / CG;
+    {
+        const int64_t tile = blockIdx.x;
+        if (tile >= total_tiles) return;
+        int g = 0;
+        while (g + 1 < ngroups && gd[g + 1].tile0 <= tile) ++g;
+        const GDesc d = gd[g];
+        const int64_t local = tile - d.tile0;
+        const int64_t rb = local % d.rowblocks, sp = local / d.rowblocks;
+        const int64_t trow0 = rb * ROWS;
+        const int64_t lps = (d.nlags + d.nsplit - 1) / d.nsplit;
+        const int64_t k0 = sp * lps;
+        const int64_t k1 = (k0 + lps < d.nlags) ? k0 + lps : d.nlags;
+        const int64_t head = d.head ? *d.head : 0;
+        const int64_t nch = (d.cols + 63) / 64;  // ld is a multiple of 64
+        const int64_t total = (k1 > k0 ? k1 - k0 : 0) * nch;
+        Y acc[RW][NR];
+#pragma unroll
+        for (int rr = 0; rr < RW; ++rr)
+#pragma unroll
+            for (int b = 0; b < NR; ++b) acc[rr][b] = 0;
+        if (total > 0) {
+            int64_t lk = k0, lc = 0;  // copy cursor; past the end it repeats the last step
+            auto load = [&](int buf) {
+                const bool in = lk < k1;
+                const int64_t k = in ? lk : k1 - 1, c0 = 64 * (in ? lc : nch - 1);
+                const float *Ak = (const float *)d.A + k * d.lag_stride;
+                const Y *xs = (const Y *)d.x + ((head + k) % d.n_slots) * d.x_slot_stride;
+#pragma unroll
+                for (int q = 0; q < PW; ++q) {
+                    const int pc = wave + 4 * q;
+                    const void *src;
+                    if (pc < AP) {
+                        int64_t row = trow0 + 4 * pc + (lane >> 4);
+                        row = row < d.rows ? row : d.rows - 1;
+                        src = Ak + row * d.ld + c0 + 4 * (lane & 15);
+                    } else {  // right-hand sides [b][64 columns]; padding pieces repeat the first
+                        const int off = (pc < AP + YP ? pc - AP : 0) * 1024 + lane * 16;
+                        int b = off / (64 * (int)sizeof(Y));
+                        const int col = (off % (64 * (int)sizeof(Y))) / (int)sizeof(Y);
+                        b = b < NR ? b : NR - 1;
+                        src = xs + b * d.x_ld + c0 + col;
+                    }
+                    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(&S[buf][pc * 64]),
+                                                     16, 0, 0);
+                }
+                if (++lc == nch) {
+                    lc = 0;
+                    ++lk;
+                }
+            };
+#pragma unroll
+            for (int q = 0; q < PF; ++q) load(q);
+            __builtin_amdgcn_s_waitcnt(WAIT_INFLIGHT);  // step 0 is in
+            __builtin_amdgcn_s_barrier();
+            for (int64_t t0 = 0; t0 < total; t0 += NB) {
+#pragma unroll
+                for (int u = 0; u < NB; ++u) {
+                    if (t0 + u >= total) break;
+                    // step t + PF into the buffer read one step ago (every wave is past it)
+                    load((u + PF) % NB);
+                    const float *Sa = reinterpret_cast<const float *>(&S[u][0]);
+                    const Y *Sy = reinterpret_cast<const Y *>(&S[u][AP * 64]);
+                    f4 va[RW];
+#pragma unroll
+                    for (int rr = 0; rr < RW; ++rr)
+                        va[rr] = *reinterpret_cast<const f4 *>(Sa + (wave * ROWS_W + rg * RW + rr) * 64 + 4 * cg);
+#pragma unroll
+                    for (int b = 0; b < NR; ++b) {
+                        Y yv[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) yv[q] = Sy[b * 64 + 4 * cg + q];
+#pragma unroll
+                        for (int rr = 0; rr < RW; ++rr)
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) acc[rr][b] += (Y)va[rr][q] * yv[q];
+                    }
+                    // this wave's copies of step t + 1 are in; then every wave's are
+                    __builtin_amdgcn_s_waitcnt(WAIT_INFLIGHT);
+                    __builtin_amdgcn_s_barrier();
+                }
+            }
+        }
+#pragma unroll
+        for (int rr = 0; rr < RW; ++rr)
+#pragma unroll
+            for (int b = 0; b < NR; ++b) {
+                Y x = acc[rr][b];
+                for (int off = CG / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+                acc[rr][b] = x;
+            }
+        if (cg == 0) {
+            const int64_t row0 = trow0 + wave * ROWS_W + rg * RW;
+            Y *out = (Y *)d.partial + sp * d.rows * NR;
 #pragma unroll
             for (int rr = 0; rr < RW; ++rr)
                 if (row0 + rr < d.rows)
@@ -348,10 +484,20 @@ void launch_ring_transpose(hipStream_t s, int64_t n_slots, int64_t ld, int64_t n
     hipLaunchKernelGGL(k_ring_transpose<double>, dim3(1024), dim3(256), 0, s, n_slots, ld, nrhs, in, out);
 }
 
-// rows per wave of the transposed-ring kernel: the tile shapes the batch's
-// autotuner chooses from (FP32 sums; FP64 y and sums)
-constexpr int kTransRWs[] = {8, 4, 16};
-constexpr int kTransRWAs[] = {4, 2, 8};
+// tile shapes of the transposed-ring kernels that the batch's autotuner
+// chooses from (FP32 sums; FP64 y and sums), the default first.  form 0:
+// registers, 64 column lanes; 1: registers, 16 column lanes x 4 row groups;
+// 2: LDS-staged (nb buffers, minw work-groups per CU)
+struct TransVariant {
+    int form, rw, nb, minw;
+};
+static const TransVariant kTransF32[] = {{1, 16, 0, 0}, {1, 8, 0, 0}, {0, 16, 0, 0},
+                                         {0, 8, 0, 0},  {2, 8, 2, 2}, {2, 4, 3, 2}};
+static const TransVariant kTransF32A[] = {{2, 4, 3, 2}, {2, 4, 4, 1}, {2, 8, 3, 1},
+                                          {1, 8, 0, 0}, {0, 4, 0, 0}, {0, 8, 0, 0}};
+constexpr int kNumTrans = 6;
+static_assert(sizeof(kTransF32) / sizeof(kTransF32[0]) == kNumTrans, "variant table");
+static_assert(sizeof(kTransF32A) / sizeof(kTransF32A[0]) == kNumTrans, "variant table");
 
 // rows per wave of the multi-right-hand-side kernel: as many as keep the
 // accumulators, the in-flight block vectors and the staged x of one lane
@@ -362,16 +508,38 @@ bool grouped_ring_transposed(int kind, int nrhs) { return (kind == GK_F32 || kin
 
 int grouped_hist_variants(int kind, int nrhs, bool transposed)
 {
-    return (transposed && nrhs >= 2 && kind != GK_F64) ? 3 : 1;
+    return (transposed && nrhs >= 2 && kind != GK_F64) ? kNumTrans : 1;
+}
+
+static const TransVariant &trans_variant(int kind, int variant)
+{
+    if (variant < 0 || variant >= kNumTrans) variant = 0;
+    return kind == GK_F32 ? kTransF32[variant] : kTransF32A[variant];
 }
 
 // rows of one work tile (4 waves): variant 0 is the default shape
 int64_t grouped_rows_per_tile(int kind, int nrhs, bool transposed, int variant)
 {
     if (nrhs == 1) return 16;
-    if (transposed && kind == GK_F32) return 4 * kTransRWs[variant < 0 || variant > 2 ? 0 : variant];
-    if (transposed && kind == GK_F32A) return 4 * kTransRWAs[variant < 0 || variant > 2 ? 0 : variant];
+    if (transposed && (kind == GK_F32 || kind == GK_F32A)) {
+        const TransVariant &t = trans_variant(kind, variant);
+        return t.form == 0 ? 4 * t.rw : 16 * t.rw;
+    }
     return 4 * mrhs_rw(kind, nrhs);
+}
+
+const char *grouped_variant_name(int kind, int nrhs, bool transposed, int variant)
+{
+    if (!(transposed && nrhs >= 2 && (kind == GK_F32 || kind == GK_F32A))) return "plain";
+    static const char *names[2][kNumTrans] = {
+        {"registers, 16 column lanes, 16 rows", "registers, 16 column lanes, 8 rows",
+         "registers, 64 column lanes, 16 rows", "registers, 64 column lanes, 8 rows",
+         "LDS-staged, 8 rows, 2 buffers, 2 groups per CU", "LDS-staged, 4 rows, 3 buffers, 2 groups per CU"},
+        {"LDS-staged, 4 rows, 3 buffers, 2 groups per CU", "LDS-staged, 4 rows, 4 buffers",
+         "LDS-staged, 8 rows, 3 buffers", "registers, 16 column lanes, 8 rows", "registers, 64 column lanes, 4 rows",
+         "registers, 64 column lanes, 8 rows"}};
+    if (variant < 0 || variant >= kNumTrans) variant = 0;
+    return names[kind == GK_F32 ? 0 : 1][variant];
 }
 
 __global__ void k_reset_counter(unsigned long long *c) { *c = 0ull; }
@@ -481,22 +649,30 @@ void launch_grouped_gemv(hipStream_t s, int kind, int nrhs, const GDesc *gd, int
     case 4: QHP_GM(T, Y, A, 4, mrhs_rw(K, 4)); break;      \
     default: QHP_GM(T, Y, A, 8, mrhs_rw(K, 8)); break;     \
     }
-#define QHP_GT(Y, NR, RWS)                                                                                      \
-    switch (variant) {                                                                                          \
-    case 1:                                                                                                     \
-        hipLaunchKernelGGL((k_grouped_mrhs_t<Y, Y, NR, RWS[1]>), dim3(grid), dim3(256), 0, s, gd, ngroups,      \
-                           total_tiles, counter);                                                               \
-        break;                                                                                                  \
-    case 2:                                                                                                     \
-        hipLaunchKernelGGL((k_grouped_mrhs_t<Y, Y, NR, RWS[2]>), dim3(grid), dim3(256), 0, s, gd, ngroups,      \
-                           total_tiles, counter);                                                               \
-        break;                                                                                                  \
-    default:                                                                                                    \
-        hipLaunchKernelGGL((k_grouped_mrhs_t<Y, Y, NR, RWS[0]>), dim3(grid), dim3(256), 0, s, gd, ngroups,      \
-                           total_tiles, counter);                                                               \
+#define QHP_GTR(Y, NR, RW, CG)                                                                              \
+    hipLaunchKernelGGL((k_grouped_mrhs_t<Y, Y, NR, RW, CG>), dim3(grid), dim3(256), 0, s, gd, ngroups, total_tiles, \
+                       counter)
+#define QHP_GTD(Y, NR, RW, NB, MINW)                                                                        \
+    hipLaunchKernelGGL((k_grouped_mrhs_d<Y, NR, RW, NB, MINW>), dim3((unsigned)total_tiles), dim3(256), 0, s, gd, \
+                       ngroups, total_tiles)
+#define QHP_GF(NR)                                  \
+    switch (variant) {                              \
+    case 1: QHP_GTR(float, NR, 8, 16); break;       \
+    case 2: QHP_GTR(float, NR, 16, 64); break;      \
+    case 3: QHP_GTR(float, NR, 8, 64); break;       \
+    case 4: QHP_GTD(float, NR, 8, 2, 2); break;     \
+    case 5: QHP_GTD(float, NR, 4, 3, 2); break;     \
+    default: QHP_GTR(float, NR, 16, 16); break;     \
     }
-#define QHP_GF(NR) QHP_GT(float, NR, kTransRWs)
-#define QHP_GFA(NR) QHP_GT(double, NR, kTransRWAs)
+#define QHP_GFA(NR)                                 \
+    switch (variant) {                              \
+    case 1: QHP_GTD(double, NR, 4, 4, 1); break;    \
+    case 2: QHP_GTD(double, NR, 8, 3, 1); break;    \
+    case 3: QHP_GTR(double, NR, 8, 16); break;      \
+    case 4: QHP_GTR(double, NR, 4, 64); break;      \
+    case 5: QHP_GTR(double, NR, 8, 64); break;      \
+    default: QHP_GTD(double, NR, 4, 3, 2); break;   \
+    }
     if (kind == GK_F64) { QHP_GN(double, double, double, GK_F64) }
     else if (kind == GK_F32) {
         switch (nrhs) {
@@ -516,7 +692,8 @@ void launch_grouped_gemv(hipStream_t s, int kind, int nrhs, const GDesc *gd, int
     else { QHP_GN(float, double, double, GK_F32A) }
 #undef QHP_GFA
 #undef QHP_GF
-#undef QHP_GT
+#undef QHP_GTR
+#undef QHP_GTD
 #undef QHP_GN
 #undef QHP_GM
 #undef QHP_G1
