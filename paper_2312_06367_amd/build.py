@@ -34,6 +34,13 @@ def build(verbose: bool = False) -> str:
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
+    # every symbol of the library's own namespace must be defined inside it: a
+    # kernel template whose host pass is dropped links but cannot be loaded
+    und = subprocess.run(["nm", "-D", "--undefined-only", tmp], check=True, capture_output=True, text=True).stdout
+    missing = [ln.split()[-1] for ln in und.splitlines() if "_ZN3qhp" in ln]
+    if missing:
+        os.remove(tmp)
+        raise RuntimeError("libqhp.so leaves %d symbols of namespace qhp undefined, e.g. %s" % (len(missing), missing[0]))
     os.replace(tmp, LIB)
     return LIB
 

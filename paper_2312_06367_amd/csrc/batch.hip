@@ -322,7 +322,8 @@ __global__ __launch_bounds__(256) void k_grouped_mrhs_t(const GDesc *__restrict_
 // The same product staged in LDS.  A tile's steps are (lag, chunk of 64
 // columns); each step's block rows (4 rows x 256 bytes per 1 KB piece) and
 // right-hand-side entries are copied straight from memory into one of NB LDS
-// buffers (global_load_lds, 16 bytes a lane), NB - 1 steps ahead of the
+// buffers (global_load_lds, 16 bytes a lane; the block rows with the
+// nontemporal cache policy, as they are read once), NB - 1 steps ahead of the
 // arithmetic, so a wave keeps the copies in flight without holding them in
 // registers.  Each wave waits only for its own copies of the next step
 // (vmcnt counts them exactly: no other vector memory access is issued in the
@@ -379,20 +380,22 @@ __global__ __launch_bounds__(256, MINW) void k_grouped_mrhs_d(const GDesc *__res
 #pragma unroll
                 for (int q = 0; q < PW; ++q) {
                     const int pc = wave + 4 * q;
-                    const void *src;
-                    if (pc < AP) {
+                    if (pc < AP) {  // block rows: read once per step, so nontemporal (cache policy nt)
                         int64_t row = trow0 + 4 * pc + (lane >> 4);
                         row = row < d.rows ? row : d.rows - 1;
-                        src = Ak + row * d.ld + c0 + 4 * (lane & 15);
-                    } else {  // right-hand sides [b][64 columns]; padding pieces repeat the first
+                        __builtin_amdgcn_global_load_lds((const void *)(Ak + row * d.ld + c0 + 4 * (lane & 15)),
+                                                         (__attribute__((address_space(3))) void *)(&S[buf][pc * 64]),
+                                                         16, 0, 2);
+                    } else {  // right-hand sides [b][64 columns], re-read by every row block; padding
+                              // pieces repeat the first
                         const int off = (pc < AP + YP ? pc - AP : 0) * 1024 + lane * 16;
                         int b = off / (64 * (int)sizeof(Y));
                         const int col = (off % (64 * (int)sizeof(Y))) / (int)sizeof(Y);
                         b = b < NR ? b : NR - 1;
-                        src = xs + b * d.x_ld + c0 + col;
+                        __builtin_amdgcn_global_load_lds((const void *)(xs + b * d.x_ld + c0 + col),
+                                                         (__attribute__((address_space(3))) void *)(&S[buf][pc * 64]),
+                                                         16, 0, 0);
                     }
-                    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(&S[buf][pc * 64]),
-                                                     16, 0, 0);
                 }
                 if (++lc == nch) {
                     lc = 0;
