@@ -271,14 +271,22 @@ void qhp_destroy(qhp_ctx *ctx);
 /* ---- many scatterers marched together ---------------------------------
  * The marching scheme of Sec. IV-B applied to n independent scatterers of
  * uneven size at once: every step is one replay of a HIP graph of grouped
- * kernels (history sums of all scatterers through one work queue of
- * 16-row tiles weighted by block size, then the T_0 products, the ring
+ * kernels (history sums of all scatterers over work tiles of (scatterer,
+ * row block, lag split), biggest scatterer first, then the T_0 products, the ring
  * updates and the post-processing of all scatterers); the per-scatterer step
  * and ring head live in device memory.
  * qhp_batch_create: ctxs[i] must all have had qhp_set_incident, share the
  *   device, precision (F64, F32 or F32A) and n_rhs (1, 2, 4 or 8); each
  *   continues from its current step.  The T_0 product uses the FP64 inverse.
- *   The batch keeps the context pointers: destroy it before them.
+ *   The batch keeps the context pointers: destroy it before them.  The tile
+ *   shape of the history product is autotuned on the batch's own blocks.
+ * qhp_batch_create_variant: the same with the history tile shape fixed to
+ *   variant in [0, qhp_batch_variants(precision, n_rhs)); -1 autotunes.
+ *   QHP_EINVAL for any other value.
+ * qhp_batch_variants: the number of history tile shapes for F32 or F32A
+ *   blocks (QHP_F32, QHP_F32A) with n_rhs right-hand sides (1 where there
+ *   is no choice, 0 for an unsupported precision or n_rhs).
+ * qhp_batch_history_variant: the tile shape the batch uses (-1 for NULL).
  * qhp_batch_run: n_steps steps of every scatterer; j_hists is a host array
  *   of n device pointers [n_steps][ne_i][n_rhs] FP64 (or NULL entries / a NULL
  *   array for no output).  QHP_EUNSTABLE on a non-finite value.
@@ -286,6 +294,9 @@ void qhp_destroy(qhp_ctx *ctx);
  *   replay) of the last run, into host ms[n]. */
 typedef struct qhp_batch qhp_batch;
 int qhp_batch_create(qhp_ctx *const *ctxs, int32_t n, qhp_batch **out);
+int qhp_batch_create_variant(qhp_ctx *const *ctxs, int32_t n, int32_t variant, qhp_batch **out);
+int qhp_batch_variants(int32_t precision, int32_t n_rhs);
+int qhp_batch_history_variant(const qhp_batch *b);
 int qhp_batch_run(qhp_batch *b, int32_t n_steps, double *const *j_hists);
 int qhp_batch_step_times(const qhp_batch *b, float *ms, int32_t n);
 const char *qhp_batch_last_error(const qhp_batch *b);

@@ -61,7 +61,8 @@ class _Info(ctypes.Structure):
 EXPORTS = ["qhp_create", "qhp_mesh", "qhp_assemble", "qhp_set_precision", "qhp_set_solver", "qhp_profile",
            "qhp_hist_time", "qhp_set_incident", "qhp_step", "qhp_run", "qhp_query", "qhp_edges",
            "qhp_get_matrix", "qhp_keep_raw", "qhp_history_sum", "qhp_history_sum_variant", "qhp_history_variants",
-           "qhp_batch_create", "qhp_batch_run",
+           "qhp_batch_create", "qhp_batch_create_variant", "qhp_batch_variants", "qhp_batch_history_variant",
+           "qhp_batch_run",
            "qhp_batch_step_times", "qhp_batch_last_error", "qhp_batch_destroy", "qhp_last_error",
            "qhp_destroy", "qhp_release_assembly", "qhp_set_gmres", "qhp_gmres_stats", "qhp_gmres_reset", "qhp_mlp_create",
            "qhp_mlp_dims", "qhp_mlp_set_params", "qhp_mlp_get_params", "qhp_mlp_features", "qhp_mlp_guess", "qhp_mlp_reconstruct",
@@ -100,6 +101,11 @@ def lib():
         L.qhp_history_sum_variant.argtypes = [vp, i32, i64, i64, i64, i64, vp, vp, vp, i64, i64, vp, vp, i32]
         L.qhp_history_variants.argtypes = [i32, i64]
         L.qhp_batch_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]
+        L.qhp_batch_create_variant.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.POINTER(vp)]
+        L.qhp_batch_variants.argtypes = [i32, i32]
+        L.qhp_batch_variants.restype = i32
+        L.qhp_batch_history_variant.argtypes = [vp]
+        L.qhp_batch_history_variant.restype = i32
         L.qhp_batch_run.argtypes = [vp, i32, ctypes.POINTER(vp)]
         L.qhp_batch_step_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32]
         L.qhp_batch_last_error.argtypes = [vp]
@@ -276,6 +282,11 @@ def history_variants(precision: str, nrhs: int) -> int:
     return lib().qhp_history_variants(PRECISIONS[precision], int(nrhs))
 
 
+def batch_variants(precision: str, nrhs: int) -> int:
+    """number of history tile shapes of a batch (qhp_batch_variants)"""
+    return lib().qhp_batch_variants(PRECISIONS[precision], int(nrhs))
+
+
 def history_sum(precision: str, slabs, scales, ring, head: int, r, b, kmax: int | None = None, variant: int = -1):
     """b = r - sum_{k=1}^{kmax} T_k y_{i-k} on caller tensors (see qhp_history_sum).
 
@@ -307,15 +318,22 @@ class Batch:
     """Many scatterers marched together, one graph replay per step
     (qhp_batch_*).  Keeps the solvers alive while it exists."""
 
-    def __init__(self, solvers):
+    def __init__(self, solvers, variant: int = -1):
+        """variant: history tile shape in [0, batch_variants(precision, n_rhs)),
+        or -1 to autotune it."""
         self.L = lib()
         self.solvers = list(solvers)
         arr = (ctypes.c_void_p * len(self.solvers))(*[s.h.value for s in self.solvers])
         h = ctypes.c_void_p()
-        rc = self.L.qhp_batch_create(arr, len(self.solvers), ctypes.byref(h))
+        rc = self.L.qhp_batch_create_variant(arr, len(self.solvers), int(variant), ctypes.byref(h))
         if rc != 0:
             raise QhpError(rc, self.L.qhp_last_error(self.solvers[0].h).decode())
         self.h = h
+
+    @property
+    def variant(self) -> int:
+        """the history tile shape in use"""
+        return int(self.L.qhp_batch_history_variant(self.h))
 
     def run(self, n_steps: int, j_hists=None):
         ptrs = None

@@ -1068,7 +1068,8 @@ static int64_t group_splits(int64_t rows, int64_t cols, int64_t nlags)
     return std::max<int64_t>(1, std::min<int64_t>(ns, nlags));
 }
 
-static void build_batch(qhp_batch *b)
+// variant: history tile shape, or -1 to autotune it
+static void build_batch(qhp_batch *b, int variant)
 {
     const int n = b->n;
     hipStream_t s = b->s;
@@ -1192,8 +1193,8 @@ static void build_batch(qhp_batch *b)
     // march state first: the autotuning launches read the ring heads
     hip_check(hipMemcpyAsync(b->steps.p, st0.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s), "state");
     hip_check(hipMemcpyAsync(b->heads.p, hd0.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s), "state");
-    b->hv = 0;
-    if (nvar > 1) {  // autotune the history tile shape on the batch's own blocks
+    b->hv = variant >= 0 ? variant : 0;
+    if (nvar > 1 && variant < 0) {  // autotune the history tile shape on the batch's own blocks
         hipEvent_t e0, e1;
         hip_check(hipEventCreate(&e0), "event");
         hip_check(hipEventCreate(&e1), "event");
@@ -1260,7 +1261,27 @@ static void enqueue_batch_step(qhp_batch *b)
     qhp::launch_grouped_advance(s, b->steps.as<int64_t>(), b->heads.as<int64_t>(), b->nslots.as<int64_t>(), n);
 }
 
+static int batch_kind(int32_t precision)
+{
+    return precision == QHP_F64 ? qhp::GK_F64 : (precision == QHP_F32 ? qhp::GK_F32 : qhp::GK_F32A);
+}
+
+extern "C" int qhp_batch_variants(int32_t precision, int32_t n_rhs)
+{
+    if (precision != QHP_F64 && precision != QHP_F32 && precision != QHP_F32A) return 0;
+    if (n_rhs != 1 && n_rhs != 2 && n_rhs != 4 && n_rhs != 8) return 0;
+    const int kind = batch_kind(precision);
+    return qhp::grouped_hist_variants(kind, n_rhs, qhp::grouped_ring_transposed(kind, n_rhs));
+}
+
+extern "C" int qhp_batch_history_variant(const qhp_batch *b) { return b ? b->hv : -1; }
+
 extern "C" int qhp_batch_create(qhp_ctx *const *ctxs, int32_t n, qhp_batch **out)
+{
+    return qhp_batch_create_variant(ctxs, n, -1, out);
+}
+
+extern "C" int qhp_batch_create_variant(qhp_ctx *const *ctxs, int32_t n, int32_t variant, qhp_batch **out)
 {
     if (!ctxs || n < 1 || !out) return QHP_EINVAL;
     qhp_ctx *c0 = ctxs[0];
@@ -1274,17 +1295,19 @@ extern "C" int qhp_batch_create(qhp_ctx *const *ctxs, int32_t n, qhp_batch **out
         return guard(c0, QHP_EINVAL, "the batch kernels take F64, F32 or F32A blocks");
     if (c0->nrhs != 1 && c0->nrhs != 2 && c0->nrhs != 4 && c0->nrhs != 8)
         return guard(c0, QHP_EINVAL, "batch n_rhs must be 1, 2, 4 or 8");
+    if (variant < -1 || variant >= qhp_batch_variants(c0->p.precision, c0->nrhs))
+        return guard(c0, QHP_EINVAL, "no such history tile shape for this precision and n_rhs");
     qhp_batch *b = new qhp_batch();
     try {
         hip_check(hipSetDevice(c0->p.device), "hipSetDevice");
         b->ctxs.assign(ctxs, ctxs + n);
         b->n = n;
         b->nrhs = c0->nrhs;
-        b->kind = c0->p.precision == QHP_F64 ? qhp::GK_F64 : (c0->p.precision == QHP_F32 ? qhp::GK_F32 : qhp::GK_F32A);
+        b->kind = batch_kind(c0->p.precision);
         b->acc_double = b->kind != qhp::GK_F32;
         hip_check(hipStreamCreateWithFlags(&b->s, hipStreamNonBlocking), "stream");
         for (int i = 0; i < n; ++i) hip_check(hipStreamSynchronize(ctxs[i]->s), "sync");
-        build_batch(b);
+        build_batch(b, variant);
         // capture one step; every per-step quantity is read from device state
         hip_check(hipStreamBeginCapture(b->s, hipStreamCaptureModeThreadLocal), "capture");
         enqueue_batch_step(b);

@@ -29,3 +29,20 @@ def test_library_exports_every_declared_symbol():
     for name in declared_symbols():
         assert hasattr(L, name), name
     assert set(declared_symbols()) == set(pkg.EXPORTS)
+
+
+def test_batch_tile_shape_counts():
+    """qhp_batch_variants is host logic: six history tile shapes for FP32 or
+    FP32-block/FP64-sum batches with 2, 4 or 8 right-hand sides, one where
+    there is no choice, none for unsupported precisions or counts."""
+    import paper_2312_06367_amd as pkg
+    if not os.path.exists(pkg.LIB_PATH):
+        pytest.skip("libqhp.so not built")
+    for p in ("f32", "f32a"):
+        for n in (2, 4, 8):
+            assert pkg.batch_variants(p, n) == 6
+        assert pkg.batch_variants(p, 1) == 1
+        assert pkg.batch_variants(p, 3) == 0
+    assert pkg.batch_variants("f64", 8) == 1
+    assert pkg.batch_variants("bf16", 4) == 0
+    assert pkg.batch_variants("i8x4", 8) == 0

@@ -435,6 +435,52 @@ def test_batch_uneven_graph_replay(precision, n_rhs, bound):
             s.close()
 
 
+@pytest.mark.parametrize("precision,bound", [("f32a", 1e-9), ("f32", 2e-4)])
+def test_batch_every_tile_shape(precision, bound):
+    """Every history tile shape of the batch (register forms with 64 or 16
+    column lanes, LDS-staged forms), pinned in turn, for 2, 4 and 8 waves:
+    three scatterers of different size marched by graph replays, every step
+    against their eager marches.  The eager marches are computed once per
+    wave count and reused for every shape."""
+    import paper_2312_06367_amd as qhp
+    from workloads import meshes, waves
+    dt, n = 0.12, 40
+    cases = [meshes.icosphere(1), meshes.torus(1.0, 0.4, 12, 6), meshes.cube(1.5, 2)]
+    for n_rhs in (2, 4, 8):
+        nvar = qhp.batch_variants(precision, n_rhs)
+        assert nvar == 6
+        solvers, eager, wss = [], [], []
+        for xyz, tri in cases:
+            s = qhp.Solver(dt, precision="f64", solver="inv")
+            s.mesh(xyz, tri)
+            s.assemble()
+            s.set_precision(precision)
+            ws = waves.batched_waves(max(1, n_rhs // 2), 11, 0.1, 0.1, s.info()["diameter"])[:n_rhs]
+            s.set_incident(ws, n)
+            jh = torch.zeros((n, s.info()["ne"], len(ws)), dtype=torch.float64, device="cuda")
+            s.run(n, jh)
+            eager.append(jh.cpu().numpy())
+            solvers.append(s)
+            wss.append(ws)
+        for v in range(nvar):
+            for s, ws in zip(solvers, wss):
+                s.set_incident(ws, n)  # restart
+            outs = [torch.zeros((n, s.info()["ne"], n_rhs), dtype=torch.float64, device="cuda") for s in solvers]
+            b = qhp.Batch(solvers, variant=v)
+            assert b.variant == v
+            b.run(n, outs)
+            torch.cuda.synchronize()
+            b.close()
+            errs = [float(np.abs(o.cpu().numpy() - e).max() / np.abs(e).max()) for o, e in zip(outs, eager)]
+            _say("[batch %s x%d shape %d] err vs eager %s" % (precision, n_rhs, v, " ".join("%.2e" % x for x in errs)))
+            assert max(errs) < bound
+        with pytest.raises(qhp.QhpError) as e:
+            qhp.Batch(solvers, variant=nvar)
+        assert e.value.code == -1
+        for s in solvers:
+            s.close()
+
+
 def test_dc_stability_10k_steps_large_sphere():
     """7680-edge sphere, FP32 blocks with FP64 sums: 10^4 steps, the current
     decays after the pulse and never grows (late-time dc stability)."""
