@@ -1201,6 +1201,7 @@ static void build_batch(qhp_batch *b, int variant)
         float best = 1e30f;
         for (int v = 0; v < nvar; ++v) {
             const int64_t tiles = hist_tables(v);
+            if (tiles >= ((int64_t)1 << 24)) continue;  // beyond one work-group per tile
             upload(b->d_hist, dh, s);
             auto run = [&]() {
                 qhp::launch_grouped_gemv(s, b->kind, nr, b->d_hist.as<qhp::GDesc>(), n, tiles,
@@ -1227,6 +1228,8 @@ static void build_batch(qhp_batch *b, int variant)
         (void)hipEventDestroy(e1);
     }
     t_h = hist_tables(b->hv);
+    // the LDS-staged history kernels launch one 256-lane work-group per tile
+    if (t_h >= ((int64_t)1 << 24)) throw Fail{QHP_EINVAL, "batch history has too many work tiles"};
     b->tiles_h = t_h;
     b->tiles_s = t_s;
     b->tiles_p = t_p;
