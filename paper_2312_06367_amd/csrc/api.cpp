@@ -16,6 +16,7 @@
 #include "linalg.h"
 #include "march.h"
 #include "qhp_internal.h"
+#include "solve.h"
 #include "ctx.h"
 
 using qhp::DBuf;
@@ -442,11 +443,6 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
         for (int64_t i = 0; i < ne; ++i) perm[i] = (int32_t)i;
         for (int64_t j = 0; j < ne; ++j) std::swap(perm[j], perm[ipiv[j]]);
         upload(c->perm0, perm, s);
-        int64_t nb = (ne + 63) / 64;
-        c->Linv.alloc(sizeof(double) * nb * 64 * 64);
-        c->Uinv.alloc(sizeof(double) * nb * 64 * 64);
-        qhp::launch_diag_inv(s, ne, c->LU0.as<double>(), 0, c->Linv.as<double>());
-        qhp::launch_diag_inv(s, ne, c->LU0.as<double>(), 1, c->Uinv.as<double>());
         // T_0^{-1} from the same LU (used by QHP_SOLVE_INV)
         c->Tinv.alloc(sizeof(double) * nn);
         qhp::eye_plus(s, ne, 1.0, 0.0, c->LU0.as<double>(), c->Tinv.as<double>());
@@ -651,10 +647,6 @@ extern "C" int qhp_set_incident(qhp_ctx *ctx, const qhp_wave *waves, int32_t n_r
     }
     c->sv.alloc(sizeof(double) * nc * n_rhs);
     c->zc.alloc(sizeof(double) * nc * n_rhs);
-    c->flags.alloc(sizeof(int) * 2 * ((ne + 63) / 64));
-    zero(c->flags, s);
-    c->epoch.alloc(sizeof(int));
-    zero(c->epoch, s);
     c->errflag.alloc(sizeof(int));
     zero(c->errflag, s);
     hip_check(hipStreamSynchronize(s), "march buffers");
@@ -714,18 +706,16 @@ static void do_step(qhp_ctx *c, double *j_out, double *y_out)
     } else if (c->p.solver == QHP_SOLVE_INV) {
         if (nr == 1) qhp::launch_gemv_f64(s, ne, c->Tinv.as<double>(), c->bvec.as<double>(), y);
         else qhp::gemm_f64(s, false, false, ne, nr, ne, 1.0, c->Tinv.as<double>(), ne, c->bvec.as<double>(), nr, 0.0, y, nr);
-    } else if (nr == 1) {
-        int64_t nb = (ne + 63) / 64;
-        qhp::launch_bump(s, c->epoch.as<int>());
-        qhp::launch_trsv_lu(s, ne, c->LU0.as<double>(), c->Linv.as<double>(), c->perm0.as<int32_t>(),
-                            c->bvec.as<double>(), c->zvec.as<double>(), c->flags.as<int>(), c->epoch.as<int>(), 0,
-                            c->errflag.as<int>());
-        qhp::launch_trsv_lu(s, ne, c->LU0.as<double>(), c->Uinv.as<double>(), c->perm0.as<int32_t>(),
-                            c->zvec.as<double>(), y, c->flags.as<int>() + nb, c->epoch.as<int>(), 1,
-                            c->errflag.as<int>());
-    } else {
-        hip_check(hipMemcpyAsync(y, c->bvec.p, sizeof(double) * ne * nr, hipMemcpyDeviceToDevice, s), "copy");
-        qhp::getrs_f64(s, false, ne, nr, c->LU0.as<double>(), ne, c->ipiv0.as<int32_t>(), y, nr);
+    } else {  // LU back-solves, factors in block-inverse form (built on the first LU step)
+        if (!c->Wsv.p) {
+            c->Wsv.alloc(sizeof(double) * qhp::solve_w_elems(ne));
+            c->Dlsv.alloc(sizeof(double) * qhp::solve_d_elems(ne));
+            c->Dusv.alloc(sizeof(double) * qhp::solve_d_elems(ne));
+            qhp::build_block_solve(s, ne, c->LU0.as<double>(), ne, c->Wsv.as<double>(), c->Dlsv.as<double>(),
+                                   c->Dusv.as<double>());
+        }
+        qhp::launch_block_solve(s, ne, nr, c->Wsv.as<double>(), c->Dlsv.as<double>(), c->Dusv.as<double>(),
+                                c->perm0.as<int32_t>(), c->bvec.as<double>(), c->zvec.as<double>(), y);
     }
     const int64_t slot = (c->head - 1 + K) % K;
     double *slot64 = c->ring64.as<double>() + slot * ld * nr;
@@ -814,8 +804,9 @@ extern "C" int qhp_release_assembly(qhp_ctx *ctx)
     if (ctx->p.solver != QHP_SOLVE_GMRES) ctx->T0raw.release();
     if (ctx->p.solver != QHP_SOLVE_LU && ctx->p.solver != QHP_SOLVE_GMRES) {
         ctx->LU0.release();
-        ctx->Linv.release();
-        ctx->Uinv.release();
+        ctx->Wsv.release();
+        ctx->Dlsv.release();
+        ctx->Dusv.release();
     }
     ctx->rawA.clear();
     ctx->rawB.clear();

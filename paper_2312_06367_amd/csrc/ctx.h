@@ -82,14 +82,15 @@ struct qhp_ctx {
     qhp::AsmArgs args{};
     // assembled operators (FP64, row-major)
     qhp::DBuf G, Zs, Zh, M, PS, PPL, Pcat, LSp;
-    qhp::DBuf slabs, scales_d, T0raw, LU0, ipiv0, perm0, Linv, Uinv, Tinv;
+    qhp::DBuf slabs, scales_d, T0raw, LU0, ipiv0, perm0, Tinv;
+    qhp::DBuf Wsv, Dlsv, Dusv;  // LU factors of T_0 in block-inverse form (first LU step)
     std::vector<float> scales;
     std::vector<std::vector<double>> rawA, rawB, rawC;
     // march state
     int32_t nrhs = 0;
     int64_t n_steps = 0, step = 0, head = 0;
     bool broken = false;
-    qhp::DBuf waves_d, rhs, ring64, ring32, ringb, ring8, bvec, zvec, yvec, partial, sv, zc, flags, epoch, errflag;
+    qhp::DBuf waves_d, rhs, ring64, ring32, ringb, ring8, bvec, zvec, yvec, partial, sv, zc, errflag;
     // FP32 blocks with FP64 y and sums for 2, 4 or 8 right-hand sides: one
     // group of the grouped work-queue kernel (descriptor, device head, counter)
     qhp::DBuf mr_desc, mr_head, mr_counter;

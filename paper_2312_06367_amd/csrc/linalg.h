@@ -23,6 +23,10 @@ void count_nonzero(hipStream_t s, int64_t n, const double *x, unsigned long long
 // [n] (0-based row swapped with row j at step j).  Returns 0 or j+1 of the
 // first zero pivot.  Synchronises the stream.
 int getrf_f64(hipStream_t s, int64_t n, double *A, int64_t lda, int32_t *ipiv, int *info_dev);
+// Solve T X = B for the unit lower (upper = false) or the upper (upper =
+// true) triangle T of an n x n LU factor, no pivoting; B [n][nrhs] overwritten.
+void trsm_f64(hipStream_t s, bool upper, int64_t n, int64_t nrhs, const double *T, int64_t lda, double *B,
+              int64_t ldb);
 // Solve A X = B (trans = false) or A^T X = B, B [n][nrhs] overwritten.
 void getrs_f64(hipStream_t s, bool trans, int64_t n, int64_t nrhs, const double *LU, int64_t lda,
                const int32_t *ipiv, double *B, int64_t ldb);

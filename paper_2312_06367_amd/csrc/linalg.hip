@@ -357,6 +357,30 @@ __global__ __launch_bounds__(256) void k_trsm_blk(int64_t b0, int nb, const doub
     for (int r = 0; r < nb; ++r) B[(b0 + r) * ldb + col] = x[r];
 }
 
+void trsm_f64(hipStream_t s, bool upper, int64_t n, int64_t nrhs, const double *T, int64_t lda, double *B,
+              int64_t ldb)
+{
+    const int NB = 64;
+    dim3 g1((unsigned)((nrhs + 255) / 256));
+    if (!upper) {
+        for (int64_t b0 = 0; b0 < n; b0 += NB) {  // L y = b
+            int nb = (int)std::min<int64_t>(NB, n - b0);
+            hipLaunchKernelGGL(k_trsm_blk, g1, dim3(256), 0, s, b0, nb, T, lda, B, ldb, nrhs, 0);
+            int64_t rest = n - b0 - nb;
+            if (rest > 0)
+                gemm_f64(s, false, false, rest, nrhs, nb, -1.0, T + (b0 + nb) * lda + b0, lda,
+                         B + b0 * ldb, ldb, 1.0, B + (b0 + nb) * ldb, ldb);
+        }
+    } else {
+        for (int64_t b0 = ((n - 1) / NB) * NB; b0 >= 0; b0 -= NB) {  // U x = y
+            int nb = (int)std::min<int64_t>(NB, n - b0);
+            hipLaunchKernelGGL(k_trsm_blk, g1, dim3(256), 0, s, b0, nb, T, lda, B, ldb, nrhs, 1);
+            if (b0 > 0)
+                gemm_f64(s, false, false, b0, nrhs, nb, -1.0, T + b0, lda, B + b0 * ldb, ldb, 1.0, B, ldb);
+        }
+    }
+}
+
 void getrs_f64(hipStream_t s, bool trans, int64_t n, int64_t nrhs, const double *LU, int64_t lda,
                const int32_t *ipiv, double *B, int64_t ldb)
 {
@@ -364,20 +388,8 @@ void getrs_f64(hipStream_t s, bool trans, int64_t n, int64_t nrhs, const double 
     dim3 g1((unsigned)((nrhs + 255) / 256));
     if (!trans) {
         hipLaunchKernelGGL(k_rowswap, g1, dim3(256), 0, s, n, nrhs, B, ldb, ipiv, 0);
-        for (int64_t b0 = 0; b0 < n; b0 += NB) {  // L y = b
-            int nb = (int)std::min<int64_t>(NB, n - b0);
-            hipLaunchKernelGGL(k_trsm_blk, g1, dim3(256), 0, s, b0, nb, LU, lda, B, ldb, nrhs, 0);
-            int64_t rest = n - b0 - nb;
-            if (rest > 0)
-                gemm_f64(s, false, false, rest, nrhs, nb, -1.0, LU + (b0 + nb) * lda + b0, lda,
-                         B + b0 * ldb, ldb, 1.0, B + (b0 + nb) * ldb, ldb);
-        }
-        for (int64_t b0 = ((n - 1) / NB) * NB; b0 >= 0; b0 -= NB) {  // U x = y
-            int nb = (int)std::min<int64_t>(NB, n - b0);
-            hipLaunchKernelGGL(k_trsm_blk, g1, dim3(256), 0, s, b0, nb, LU, lda, B, ldb, nrhs, 1);
-            if (b0 > 0)
-                gemm_f64(s, false, false, b0, nrhs, nb, -1.0, LU + b0, lda, B + b0 * ldb, ldb, 1.0, B, ldb);
-        }
+        trsm_f64(s, false, n, nrhs, LU, lda, B, ldb);
+        trsm_f64(s, true, n, nrhs, LU, lda, B, ldb);
     } else {
         for (int64_t b0 = 0; b0 < n; b0 += NB) {  // U^T z = b (lower)
             int nb = (int)std::min<int64_t>(NB, n - b0);

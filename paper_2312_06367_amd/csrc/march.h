@@ -39,10 +39,6 @@ void launch_history(hipStream_t s, int32_t precision, int64_t ne, int64_t ld, in
 int gemv_variant_count();
 void gemv_variant_desc(int v, int *rpw, int *unr, int *nt);
 void launch_gemv_f64(hipStream_t s, int64_t n, const double *A, const double *x, double *y);
-void launch_trsv_lu(hipStream_t s, int64_t n, const double *LU, const double *Dinv, const int32_t *perm,
-                    const double *b, double *x, int *flags, const int *epoch, int upper, int *err);
-void launch_bump(hipStream_t s, int *epoch);
-void launch_diag_inv(hipStream_t s, int64_t n, const double *LU, int upper, double *Dinv);
 void launch_store_y(hipStream_t s, int64_t n, const double *y, double *slot64, float *slot32, double *yhist,
                     int *err);
 void launch_post_a(hipStream_t s, int64_t nc, int64_t nrhs, double dtn, const int32_t *tri_edge,

@@ -785,134 +785,6 @@ void launch_gemv_f64(hipStream_t s, int64_t n, const double *A, const double *x,
     hipLaunchKernelGGL(k_gemv_f64, dim3(nblk(n, 4)), dim3(256), 0, s, n, A, x, y);
 }
 
-// Triangular solves with the LU of T_0, one workgroup per 64-row block,
-// ordered by per-block flags (epoch counter) instead of a grid barrier.
-// Forward: L z = P b (unit lower); backward: U x = z.  Each block first
-// accumulates the off-diagonal products as the earlier blocks publish their
-// pieces, then applies the precomputed inverse of its diagonal block.
-// Every wait is bounded: after spin_limit polls the block records an error
-// and exits, so the grid always drains.
-__device__ __forceinline__ int flag_load(const int *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void flag_store(int *p, int v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__global__ __launch_bounds__(256) void k_trsv_lu(int64_t n, const double *__restrict__ LU,
-                                                 const double *__restrict__ Dinv, const int32_t *__restrict__ perm,
-                                                 const double *b, double *x, int *flags, const int *epoch_ptr,
-                                                 int upper, int64_t spin_limit, int *err)
-{
-    const int epoch = *epoch_ptr;
-    __shared__ double red[4][64];
-    __shared__ double vin[64];
-    __shared__ double xin[64];
-    __shared__ int abort_flag;
-    const int nb = 64;
-    const int64_t nblocks = (n + nb - 1) / nb;
-    const int64_t jb = upper ? nblocks - 1 - (int64_t)blockIdx.x : (int64_t)blockIdx.x;
-    const int64_t r0 = jb * nb;
-    const int rows = (int)((n - r0) < nb ? (n - r0) : nb);
-    const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6;  // q: which 16-column quarter
-    if (tid == 0) abort_flag = 0;
-    double acc = 0.0;  // lane owns row r0 + lane (quarter q of the columns)
-    // sources: blocks ib < jb (forward) or ib > jb (backward), in dependency order
-    for (int64_t step = 0; step < (upper ? nblocks - 1 - jb : jb); ++step) {
-        int64_t ib = upper ? nblocks - 1 - step : step;
-        if (tid == 0) {
-            int64_t polls = 0;
-            while (flag_load(&flags[ib]) < epoch) {
-                if (++polls > spin_limit) { abort_flag = 1; atomicExch(err, 1); break; }
-                __builtin_amdgcn_s_sleep(1);
-            }
-        }
-        __syncthreads();
-        if (abort_flag) return;
-        const int64_t c0 = ib * nb;
-        const int cols = (int)((n - c0) < nb ? (n - c0) : nb);
-        if (tid < cols) xin[tid] = __hip_atomic_load(&x[c0 + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        if (lane < rows) {
-            const double *Arow = LU + (r0 + lane) * n + c0;
-            for (int c = q * 16; c < q * 16 + 16 && c < cols; ++c) acc += Arow[c] * xin[c];
-        }
-        __syncthreads();
-    }
-    red[q][lane] = acc;
-    __syncthreads();
-    if (tid < 64) {
-        double rhs = 0.0;
-        if (lane < rows) {
-            int64_t gi = r0 + lane;
-            double bv = upper ? b[gi] : b[perm[gi]];
-            rhs = bv - (red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane]);
-        }
-        vin[lane] = rhs;
-    }
-    __syncthreads();
-    // x_j = Dinv_j * vin
-    double s = 0.0;
-    if (lane < rows) {
-        const double *Drow = Dinv + (jb * nb + lane) * nb;
-        for (int c = q * 16; c < q * 16 + 16 && c < rows; ++c) s += Drow[c] * vin[c];
-    }
-    red[q][lane] = s;
-    __syncthreads();
-    if (tid < 64 && lane < rows) {
-        double v = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
-        __hip_atomic_store(&x[r0 + lane], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-    if (tid == 0) flag_store(&flags[jb], epoch);
-}
-
-void launch_trsv_lu(hipStream_t s, int64_t n, const double *LU, const double *Dinv, const int32_t *perm,
-                    const double *b, double *x, int *flags, const int *epoch, int upper, int *err)
-{
-    int64_t nb = (n + 63) / 64;
-    hipLaunchKernelGGL(k_trsv_lu, dim3((unsigned)nb), dim3(256), 0, s, n, LU, Dinv, perm, b, x, flags, epoch,
-                       upper, (int64_t)(1 << 26), err);
-}
-__global__ void k_bump(int *epoch) { *epoch += 1; }
-void launch_bump(hipStream_t s, int *epoch) { hipLaunchKernelGGL(k_bump, dim3(1), dim3(1), 0, s, epoch); }
-
-// Inverses of the 64x64 diagonal blocks of L (unit lower) and U (upper),
-// Dinv[blk][r][c], by forward/back substitution against the identity.
-__global__ void k_diag_inv(int64_t n, const double *LU, int upper, double *Dinv)
-{
-    const int nb = 64;
-    int64_t jb = blockIdx.x;
-    int col = threadIdx.x;  // column of the identity
-    int64_t r0 = jb * nb;
-    int rows = (int)((n - r0) < nb ? (n - r0) : nb);
-    if (col >= nb) return;
-    double xv[64];
-    for (int r = 0; r < nb; ++r) xv[r] = 0.0;
-    if (col < rows) {
-        if (!upper) {
-            for (int r = 0; r < rows; ++r) {
-                double v = (r == col) ? 1.0 : 0.0;
-                for (int c = 0; c < r; ++c) v -= LU[(r0 + r) * n + r0 + c] * xv[c];
-                xv[r] = v;
-            }
-        } else {
-            for (int r = rows - 1; r >= 0; --r) {
-                double v = (r == col) ? 1.0 : 0.0;
-                for (int c = r + 1; c < rows; ++c) v -= LU[(r0 + r) * n + r0 + c] * xv[c];
-                xv[r] = v / LU[(r0 + r) * n + r0 + r];
-            }
-        }
-    }
-    for (int r = 0; r < nb; ++r) Dinv[(jb * nb + r) * nb + col] = xv[r];
-}
-void launch_diag_inv(hipStream_t s, int64_t n, const double *LU, int upper, double *Dinv)
-{
-    hipLaunchKernelGGL(k_diag_inv, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, n, LU, upper, Dinv);
-}
-
 // --------------------------------------------------------- post-process
 // y_i stored: FP64 master copy into the ring slot and FP32 shadow for the
 // reduced-precision history; non-finite values raise the error flag.
