@@ -8,10 +8,8 @@
 
 namespace qhp {
 
-namespace {
-
 // D [rows][ld] = identity in its first rows x rows entries
-__global__ void k_eye(int64_t rows, int64_t ld, double *D)
+__global__ void k_solve_eye(int64_t rows, int64_t ld, double *D)
 {
     const int64_t n = rows * ld;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
@@ -20,14 +18,14 @@ __global__ void k_eye(int64_t rows, int64_t ld, double *D)
     }
 }
 
-__global__ void k_zero(int64_t n, double *p)
+__global__ void k_solve_zero(int64_t n, double *p)
 {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
         p[e] = 0.0;
 }
 
 // out[n][nrhs] rows gathered: out[i] = b[perm[i]]
-__global__ void k_gather_rows(int64_t n, int64_t nrhs, const int32_t *perm, const double *b, double *out)
+__global__ void k_solve_gather(int64_t n, int64_t nrhs, const int32_t *perm, const double *b, double *out)
 {
     const int64_t total = n * nrhs;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
@@ -36,7 +34,7 @@ __global__ void k_gather_rows(int64_t n, int64_t nrhs, const int32_t *perm, cons
     }
 }
 
-__device__ __forceinline__ double dot_range(const double *__restrict__ a, const double *__restrict__ x, int64_t m,
+__device__ __forceinline__ double solve_dot(const double *__restrict__ a, const double *__restrict__ x, int64_t m,
                                             int tid)
 {
     // 256 lanes over pairs of columns (16-byte loads of a row that starts on
@@ -60,7 +58,7 @@ __device__ __forceinline__ double dot_range(const double *__restrict__ a, const 
 // right-hand side (read through perm when perm is not null: xd[perm[pofs + c]]);
 // Wr: the block's off-diagonal rows (row stride ldw, m columns), xo the
 // solution pieces they multiply.
-__global__ __launch_bounds__(256) void k_block_row(int64_t rows, const double *__restrict__ D, int64_t ldd,
+__global__ __launch_bounds__(256) void k_solve_row(int64_t rows, const double *__restrict__ D, int64_t ldd,
                                                    const double *__restrict__ xd, const int32_t *__restrict__ perm,
                                                    int64_t pofs, const double *__restrict__ Wr, int64_t ldw,
                                                    const double *__restrict__ xo, int64_t m, double *out)
@@ -73,26 +71,24 @@ __global__ __launch_bounds__(256) void k_block_row(int64_t rows, const double *_
     if (perm) {
         for (int64_t c = tid; c < rows; c += 256) s += D[r * ldd + c] * xd[perm[pofs + c]];
     } else {
-        s += dot_range(D + r * ldd, xd, rows, tid);
+        s += solve_dot(D + r * ldd, xd, rows, tid);
     }
-    if (m > 0) s -= dot_range(Wr + r * ldw, xo, m, tid);
+    if (m > 0) s -= solve_dot(Wr + r * ldw, xo, m, tid);
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
     if (lane == 0) red[wave] = s;
     __syncthreads();
     if (tid == 0) out[r] = red[0] + red[1] + red[2] + red[3];
 }
 
-}  // namespace
-
 void build_block_solve(hipStream_t s, int64_t n, const double *LU, int64_t lda, double *W, double *Dl, double *Du)
 {
     const int64_t B = kSolveBlock, nb = (n + B - 1) / B, ldw = solve_ldw(n);
-    hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, s, solve_w_elems(n), W);
+    hipLaunchKernelGGL(k_solve_zero, dim3(1024), dim3(256), 0, s, solve_w_elems(n), W);
     for (int64_t I = 0; I < nb; ++I) {
         const int64_t o = I * B, bi = std::min(B, n - o);
         double *dl = Dl + I * B * B, *du = Du + I * B * B;
-        hipLaunchKernelGGL(k_eye, dim3(256), dim3(256), 0, s, B, B, dl);
-        hipLaunchKernelGGL(k_eye, dim3(256), dim3(256), 0, s, B, B, du);
+        hipLaunchKernelGGL(k_solve_eye, dim3(256), dim3(256), 0, s, B, B, dl);
+        hipLaunchKernelGGL(k_solve_eye, dim3(256), dim3(256), 0, s, B, B, du);
         trsm_f64(s, false, bi, bi, LU + o * lda + o, lda, dl, B);  // L_II^{-1}
         trsm_f64(s, true, bi, bi, LU + o * lda + o, lda, du, B);   // U_II^{-1}
         if (o > 0)  // W[I][0:o] = Dl_I L[I][0:o]
@@ -110,19 +106,19 @@ void launch_block_solve(hipStream_t s, int64_t n, int64_t nrhs, const double *W,
     if (nrhs == 1) {
         for (int64_t I = 0; I < nb; ++I) {  // z_I = Dl_I (P b)_I - W[I][0:o] z[0:o]
             const int64_t o = I * B, bi = std::min(B, n - o);
-            hipLaunchKernelGGL(k_block_row, dim3((unsigned)bi), dim3(256), 0, s, bi, Dl + I * B * B, B, b, perm, o,
+            hipLaunchKernelGGL(k_solve_row, dim3((unsigned)bi), dim3(256), 0, s, bi, Dl + I * B * B, B, b, perm, o,
                                W + o * ldw, ldw, z, o, z + o);
         }
         for (int64_t I = nb - 1; I >= 0; --I) {  // y_I = Du_I z_I - W[I][o+bi:n] y[o+bi:n]
             const int64_t o = I * B, bi = std::min(B, n - o), e = o + bi;
-            hipLaunchKernelGGL(k_block_row, dim3((unsigned)bi), dim3(256), 0, s, bi, Du + I * B * B, B, z + o,
+            hipLaunchKernelGGL(k_solve_row, dim3((unsigned)bi), dim3(256), 0, s, bi, Du + I * B * B, B, z + o,
                                (const int32_t *)nullptr, (int64_t)0, W + o * ldw + e, ldw, y + e, n - e, y + o);
         }
         return;
     }
     // several right-hand sides: the same blocks as matrix products; y holds
     // P b until the backward pass overwrites it block by block
-    hipLaunchKernelGGL(k_gather_rows, dim3(1024), dim3(256), 0, s, n, nrhs, perm, b, y);
+    hipLaunchKernelGGL(k_solve_gather, dim3(1024), dim3(256), 0, s, n, nrhs, perm, b, y);
     for (int64_t I = 0; I < nb; ++I) {
         const int64_t o = I * B, bi = std::min(B, n - o);
         gemm_f64(s, false, false, bi, nrhs, bi, 1.0, Dl + I * B * B, B, y + o * nrhs, nrhs, 0.0, z + o * nrhs, nrhs);
