@@ -46,8 +46,8 @@ def parse():
     ap.add_argument("--scatterers", type=int, default=32, help="uneven-batch: march the first N of the 32")
     ap.add_argument("--precision", default=None, choices=["f32", "f32a", "bf16", "bf16x2", "i8x4", "f64"],
                     help="slab storage / history arithmetic (default: f32a = FP32 blocks with FP64 y and "
-                         "sums for one wave, i8x4 = int8 digit blocks on the int8 matrix cores for torus-batched, "
-                         "f32 for uneven-batch)")
+                         "sums, for one wave and for uneven-batch; i8x4 = int8 digit blocks on the int8 matrix "
+                         "cores for torus-batched)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 4 GiB device copy first (reference for profiler byte counters)")
     ap.add_argument("--solver", default="inv", choices=["lu", "inv"])
@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--n-dirs", type=int, default=64, help="directions for torus-batched")
     a = ap.parse_args()
     if a.precision is None:
-        a.precision = {"torus-batched": "i8x4", "uneven-batch": "f32"}.get(a.workload, "f32a")
+        a.precision = {"torus-batched": "i8x4"}.get(a.workload, "f32a")
     return a
 
 
