@@ -119,6 +119,7 @@ struct qhp_ctx {
     qhp::DBuf T0f, gm_V, gm_w, gm_h1, gm_h2, gm_nrm, gm_R, gm_cs, gm_sn, gm_g, gm_inv, gm_y, gm_r, gm_x0;
     double *gm_host = nullptr;  // pinned: residual estimate, |r|^2, |b|^2, the two start residuals
     std::vector<int32_t> gm_iters;
+    std::vector<int> gm_pred;  // inner iterations of the last solve per refinement pass
     std::vector<float> gm_res0;
     int64_t gm_refines = 0, gm_fallbacks = 0, gm_net_starts = 0;
     // loop/star/harmonic coordinates of the mesh (learned warm start)

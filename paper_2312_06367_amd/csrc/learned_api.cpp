@@ -610,6 +610,9 @@ bool gmres_solve(qhp_ctx *c, const double *b, double *x, int32_t *iters, float *
         // FP32 inner solve of T_0 d = r to a relative reduction tau
         const double tau = std::max(0.5 * c->gm_tol * nb / beta, 1e-6);
         launch_gm_start(s, ne, m, c->gm_r.as<double>(), c->gm_nrm.as<double>(), V, c->gm_g.as<double>());
+        // the previous solve's count for this pass, less one, runs without
+        // waiting for the residual estimate (more iterations only lower it)
+        const int p = outer < (int)c->gm_pred.size() ? std::max(0, c->gm_pred[outer] - 1) : 0;
         int k = 0;
         for (int j = 0; j < m; ++j) {
             float *w = c->gm_w.as<float>();
@@ -625,12 +628,14 @@ bool gmres_solve(qhp_ctx *c, const double *b, double *x, int32_t *iters, float *
                              c->gm_R.as<double>(), c->gm_cs.as<double>(), c->gm_sn.as<double>(), c->gm_g.as<double>(),
                              c->gm_inv.as<double>(), c->gm_host);
             launch_gm_scale(s, ne, w, c->gm_inv.as<double>(), V + (int64_t)(j + 1) * ld);
-            hip_check(hipStreamSynchronize(s), "GMRES");
             *iters += 1;
             k = j + 1;
+            if (k < p) continue;
+            hip_check(hipStreamSynchronize(s), "GMRES");
             const double res = hv[0];
             if (!(res > tau * beta)) break;
         }
+        if (outer < (int)c->gm_pred.size()) c->gm_pred[outer] = k;
         launch_gm_solution(s, ne, k, m, c->gm_R.as<double>(), c->gm_g.as<double>(), c->gm_y.as<double>(), V, ld, x);
         c->gm_refines += 1;
     }
@@ -653,6 +658,7 @@ extern "C" int qhp_set_gmres(qhp_ctx *ctx, double tol, int32_t m_max, int32_t ma
         ctx->gm_tol = tol;
         ctx->gm_m = m_max;
         ctx->gm_refine = max_refine;
+        ctx->gm_pred.assign(max_refine + 1, 0);
         ctx->warm = warm;
         qhp::gmres_prepare(ctx);
         ctx->p.solver = QHP_SOLVE_GMRES;
