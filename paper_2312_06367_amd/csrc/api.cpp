@@ -459,6 +459,64 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
 // own slabs (timed with HIP events, two launches each after a warm-up).
 static int64_t group_splits(int64_t rows, int64_t cols, int64_t nlags);
 
+// descriptor of a context's grouped history (FP32 blocks, FP64 y and sums,
+// several right-hand sides, transposed FP64 ring) for tile shape v
+static void set_grouped_shape(qhp_ctx *c, int v)
+{
+    const int64_t ne = c->mesh.ne, K = c->K, ld = c->ld, nr = c->nrhs;
+    const int64_t rpt = qhp::grouped_rows_per_tile(qhp::GK_F32A, (int)nr, true, v);
+    qhp::GDesc g{};
+    g.A = c->slabs.p; g.rows = ne; g.cols = ne; g.ld = ld; g.lag_stride = ne * ld; g.nlags = K;
+    g.scales = nullptr;
+    g.x = c->ring64t.p; g.x_slot_stride = ld * nr; g.x_ld = ld; g.n_slots = K;
+    g.head = c->mr_head.as<int64_t>();
+    g.partial = c->partial.p; g.nsplit = group_splits(rpt, ne, K); g.tile0 = 0; g.rowblocks = (ne + rpt - 1) / rpt;
+    c->mr_splits = g.nsplit;
+    c->mr_tiles = g.rowblocks * g.nsplit;
+    c->hv = v;
+    hip_check(hipStreamSynchronize(c->s), "descriptor");  // no launch still reads the old one
+    hip_check(hipMemcpy(c->mr_desc.p, &g, sizeof(g), hipMemcpyHostToDevice), "descriptor");
+}
+
+// the grouped history's tile shape, timed on the context's own blocks
+static void autotune_grouped(qhp_ctx *c)
+{
+    hipStream_t s = c->s;
+    const int nv = qhp::grouped_hist_variants(qhp::GK_F32A, (int)c->nrhs, true);
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "event");
+    hip_check(hipEventCreate(&e1), "event");
+    qhp::launch_set_i64(s, c->mr_head.as<int64_t>(), 0);
+    float best = 1e30f;
+    int best_v = 0;
+    for (int v = 0; v < nv; ++v) {
+        set_grouped_shape(c, v);
+        auto run = [&]() {
+            qhp::launch_grouped_gemv(s, qhp::GK_F32A, (int)c->nrhs, c->mr_desc.as<qhp::GDesc>(), 1, c->mr_tiles,
+                                     c->mr_counter.as<unsigned long long>(), true, v);
+        };
+        run();
+        hip_check(hipEventRecord(e0, s), "event");
+        run();
+        run();
+        hip_check(hipEventRecord(e1, s), "event");
+        hip_check(hipEventSynchronize(e1), "event");
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, e0, e1), "event");
+        if (c->verbose)
+            std::fprintf(stderr, "[qhp] history, %lld rows per tile (%s): %.3f ms\n",
+                         (long long)qhp::grouped_rows_per_tile(qhp::GK_F32A, (int)c->nrhs, true, v),
+                         qhp::grouped_variant_name(qhp::GK_F32A, (int)c->nrhs, true, v), ms / 2);
+        if (ms < best) {
+            best = ms;
+            best_v = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    set_grouped_shape(c, best_v);
+}
+
 static void autotune_i8(qhp_ctx *c)
 {
     hipStream_t s = c->s;
@@ -503,6 +561,7 @@ static void autotune(qhp_ctx *c)
 {
     c->hv = -1;
     if (c->p.precision == QHP_I8X4) return autotune_i8(c);
+    if (c->mr_desc.p) return autotune_grouped(c);
     if (c->nrhs != 1) return;
     hipStream_t s = c->s;
     const int64_t ne = c->mesh.ne, K = c->K;
@@ -625,25 +684,20 @@ extern "C" int qhp_set_incident(qhp_ctx *ctx, const qhp_wave *waves, int32_t n_r
         for (int v = 0; v < qhp::i8_variant_count(); ++v)
             max_split = std::max<int64_t>(max_split, qhp::i8_hist_splits(ne, K, n_rhs, v));
     const bool grouped = c->p.precision == QHP_F32A && n_rhs > 1;
-    if (grouped) {
-        c->mr_splits = group_splits(ne, ne, K);
-        max_split = std::max<int64_t>(max_split, c->mr_splits);
-    }
+    if (grouped)  // partial sums for the largest split count of any tile shape
+        for (int v = 0; v < qhp::grouped_hist_variants(qhp::GK_F32A, (int)n_rhs, true); ++v)
+            max_split = std::max<int64_t>(
+                max_split, group_splits(qhp::grouped_rows_per_tile(qhp::GK_F32A, (int)n_rhs, true, v), ne, K));
     c->partial.alloc(sizeof(double) * max_split * ne * n_rhs);
     c->mr_desc.release();
-    if (grouped) {  // one group of the grouped multi-right-hand-side kernel (FP32 blocks, FP64 y and sums)
+    c->ring64t.release();
+    if (grouped) {  // one group of the batch's history kernels on a transposed FP64 ring
         c->mr_head.alloc(sizeof(int64_t));
         c->mr_counter.alloc(sizeof(unsigned long long));
-        const int64_t rpt = qhp::grouped_rows_per_tile(qhp::GK_F32A, (int)n_rhs);
-        qhp::GDesc g{};
-        g.A = c->slabs.p; g.rows = ne; g.cols = ne; g.ld = ld; g.lag_stride = ne * ld; g.nlags = K;
-        g.scales = nullptr;
-        g.x = c->ring64.p; g.x_slot_stride = ld * n_rhs; g.x_ld = 0; g.n_slots = K;
-        g.head = c->mr_head.as<int64_t>();
-        g.partial = c->partial.p; g.nsplit = c->mr_splits; g.tile0 = 0; g.rowblocks = (ne + rpt - 1) / rpt;
-        c->mr_tiles = g.rowblocks * c->mr_splits;
+        c->ring64t.alloc(sizeof(double) * K * n_rhs * ld);
+        zero(c->ring64t, s);
         c->mr_desc.alloc(sizeof(qhp::GDesc));
-        hip_check(hipMemcpy(c->mr_desc.p, &g, sizeof(g), hipMemcpyHostToDevice), "descriptor");
+        set_grouped_shape(c, 0);
     }
     c->sv.alloc(sizeof(double) * nc * n_rhs);
     c->zc.alloc(sizeof(double) * nc * n_rhs);
@@ -680,7 +734,7 @@ static void do_step(qhp_ctx *c, double *j_out, double *y_out)
         qhp::launch_set_i64(s, c->mr_head.as<int64_t>(), c->head);
         if (e0) hip_check(hipEventRecord(e0, s), "event");
         qhp::launch_grouped_gemv(s, qhp::GK_F32A, (int)nr, c->mr_desc.as<qhp::GDesc>(), 1, c->mr_tiles,
-                                 c->mr_counter.as<unsigned long long>(), false);
+                                 c->mr_counter.as<unsigned long long>(), true, c->hv);
         if (e1) hip_check(hipEventRecord(e1, s), "event");
         qhp::launch_partial_finish_f64(s, ne * nr, c->mr_splits, c->partial.as<double>(), r_i, c->bvec.as<double>());
     } else {
@@ -728,6 +782,7 @@ static void do_step(qhp_ctx *c, double *j_out, double *y_out)
         qhp::launch_post_b(s, ne, nr, c->args.cells, y, c->zc.as<double>(), j_out);
     }
     qhp::launch_store_y(s, ne * nr, y, slot64, slot32, y_out, c->errflag.as<int>());
+    if (c->ring64t.p) qhp::launch_store_transposed(s, ne, nr, ld, y, c->ring64t.as<double>() + slot * nr * ld);
     if (c->ringb.p) {
         const int64_t nrp = qhp::ring_bf16_rows(nr);
         qhp::launch_store_ybf(s, ne, nr, nrp, ld, y, c->ringb.as<uint16_t>() + slot * 3 * nrp * ld);
@@ -906,7 +961,7 @@ extern "C" int qhp_query(const qhp_ctx *ctx, qhp_info *info)
     info->n_steps = ctx->n_steps;
     info->step = ctx->step;
     info->hist_variant = ctx->hv;
-    info->hist_splits = ctx->nsplit;
+    info->hist_splits = ctx->mr_desc.p ? ctx->mr_splits : ctx->nsplit;
     info->raw_nnz = ctx->raw_nnz;
     return QHP_OK;
 }

@@ -75,6 +75,8 @@ bool grouped_ring_transposed(int kind, int nrhs);
 // ring [n_slots][ld][nrhs] -> [n_slots][nrhs][ld]
 void launch_ring_transpose(hipStream_t s, int64_t n_slots, int64_t ld, int64_t nrhs, const float *in, float *out);
 void launch_ring_transpose(hipStream_t s, int64_t n_slots, int64_t ld, int64_t nrhs, const double *in, double *out);
+// y [ne][nrhs] FP64 -> one slot [nrhs][ldt] of a transposed ring
+void launch_store_transposed(hipStream_t s, int64_t ne, int64_t nrhs, int64_t ldt, const double *y, double *dst);
 // transposed: the groups' rings are [nrhs][x_ld] per slot (the batch, for the
 // kinds grouped_ring_transposed names) or [cols][nrhs] (one context's own ring)
 void launch_grouped_gemv(hipStream_t s, int kind, int nrhs, const GDesc *gd, int ngroups, int64_t total_tiles,

@@ -7,6 +7,8 @@
 // sum_k T_k y_{i-k}; y_i = T_0^{-1} b_i; eq. post_processing).
 #include "batch.h"
 
+#include <algorithm>
+
 namespace qhp {
 
 static unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -462,6 +464,19 @@ __global__ void k_ring_transpose(int64_t n_slots, int64_t ld, int64_t nrhs, cons
         const int64_t s = idx / (ld * nrhs), rem = idx % (ld * nrhs), i = rem / nrhs, b = rem % nrhs;
         out[(s * nrhs + b) * ld + i] = in[idx];
     }
+}
+// y [ne][nrhs] -> one slot of a transposed ring, dst[b][i] (row stride ldt);
+// entries i >= ne of the slot are left as they are (zero)
+__global__ void k_store_transposed(int64_t n, int64_t nrhs, int64_t ldt, const double *y, double *dst)
+{
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x)
+        dst[(idx % nrhs) * ldt + idx / nrhs] = y[idx];
+}
+void launch_store_transposed(hipStream_t s, int64_t ne, int64_t nrhs, int64_t ldt, const double *y, double *dst)
+{
+    const int64_t n = ne * nrhs;
+    hipLaunchKernelGGL(k_store_transposed, dim3((unsigned)std::min<int64_t>(nblk(n, 256), 1024)), dim3(256), 0, s, n,
+                       nrhs, ldt, y, dst);
 }
 __global__ void k_set_i64(int64_t *p, int64_t v) { *p = v; }
 void launch_set_i64(hipStream_t s, int64_t *p, int64_t v) { hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, p, v); }

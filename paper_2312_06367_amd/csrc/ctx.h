@@ -93,7 +93,7 @@ struct qhp_ctx {
     qhp::DBuf waves_d, rhs, ring64, ring32, ringb, ring8, bvec, zvec, yvec, partial, sv, zc, errflag;
     // FP32 blocks with FP64 y and sums for 2, 4 or 8 right-hand sides: one
     // group of the grouped work-queue kernel (descriptor, device head, counter)
-    qhp::DBuf mr_desc, mr_head, mr_counter;
+    qhp::DBuf mr_desc, mr_head, mr_counter, ring64t;  // ring64t: [K][nrhs][ld] FP64 copy of the ring
     int64_t mr_tiles = 0, mr_splits = 0;
     int nsplit = 1;
     int64_t raw_nnz = 0;  // nonzeros of A_k, B_k, C_k, k = 1..K
