@@ -759,7 +759,9 @@ static void do_step(qhp_ctx *c, double *j_out, double *y_out)
         }
     } else if (c->p.solver == QHP_SOLVE_INV) {
         if (nr == 1) qhp::launch_gemv_f64(s, ne, c->Tinv.as<double>(), c->bvec.as<double>(), y);
-        else qhp::gemm_f64(s, false, false, ne, nr, ne, 1.0, c->Tinv.as<double>(), ne, c->bvec.as<double>(), nr, 0.0, y, nr);
+        else  // the history's partial sums are consumed: their buffer takes the split-k products
+            qhp::gemm_f64_splitk(s, ne, nr, ne, 1.0, c->Tinv.as<double>(), ne, c->bvec.as<double>(), nr, 0.0, y, nr,
+                                 c->partial.as<double>(), (int64_t)(c->partial.bytes / sizeof(double)));
     } else {  // LU back-solves, factors in block-inverse form (built on the first LU step)
         if (!c->Wsv.p) {
             c->Wsv.alloc(sizeof(double) * qhp::solve_w_elems(ne));
@@ -769,7 +771,8 @@ static void do_step(qhp_ctx *c, double *j_out, double *y_out)
                                    c->Dusv.as<double>());
         }
         qhp::launch_block_solve(s, ne, nr, c->Wsv.as<double>(), c->Dlsv.as<double>(), c->Dusv.as<double>(),
-                                c->perm0.as<int32_t>(), c->bvec.as<double>(), c->zvec.as<double>(), y);
+                                c->perm0.as<int32_t>(), c->bvec.as<double>(), c->zvec.as<double>(), y,
+                                c->partial.as<double>(), (int64_t)(c->partial.bytes / sizeof(double)));
     }
     const int64_t slot = (c->head - 1 + K) % K;
     double *slot64 = c->ring64.as<double>() + slot * ld * nr;
@@ -778,7 +781,10 @@ static void do_step(qhp_ctx *c, double *j_out, double *y_out)
     if (j_out) {
         qhp::launch_post_a(s, nc, nr, c->dtn, c->args.tri_edge, c->args.tri_sign, y, yprev, c->sv.as<double>());
         if (nr == 1) qhp::launch_gemv_f64(s, nc, c->LSp.as<double>(), c->sv.as<double>(), c->zc.as<double>());
-        else qhp::gemm_f64(s, false, false, nc, nr, nc, 1.0, c->LSp.as<double>(), nc, c->sv.as<double>(), nr, 0.0, c->zc.as<double>(), nr);
+        else
+            qhp::gemm_f64_splitk(s, nc, nr, nc, 1.0, c->LSp.as<double>(), nc, c->sv.as<double>(), nr, 0.0,
+                                 c->zc.as<double>(), nr, c->partial.as<double>(),
+                                 (int64_t)(c->partial.bytes / sizeof(double)));
         qhp::launch_post_b(s, ne, nr, c->args.cells, y, c->zc.as<double>(), j_out);
     }
     qhp::launch_store_y(s, ne * nr, y, slot64, slot32, y_out, c->errflag.as<int>());

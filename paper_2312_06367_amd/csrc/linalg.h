@@ -11,6 +11,13 @@ namespace qhp {
 void gemm_f64(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
               const double *A, int64_t lda, const double *B, int64_t ldb, double beta, double *C,
               int64_t ldc);
+// C = alpha A B + beta C (no transposes) with k split over extra work-groups
+// when the tile grid alone would not fill the chip: work holds work_elems
+// doubles of partial products (at least 2 M N for a split), summed in a fixed
+// order; without room it is gemm_f64.
+void gemm_f64_splitk(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const double *A, int64_t lda,
+                     const double *B, int64_t ldb, double beta, double *C, int64_t ldc, double *work,
+                     int64_t work_elems);
 void scale_f64(hipStream_t s, int64_t M, int64_t N, double beta, double *C, int64_t ldc);
 void eye_plus(hipStream_t s, int64_t n, double a, double b, const double *P, double *out);
 void axpby(hipStream_t s, int64_t n, double a, const double *x, double b, const double *y, double *out);

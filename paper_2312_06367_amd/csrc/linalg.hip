@@ -12,16 +12,21 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------------ GEMM
 // C = alpha op(A) op(B) + beta C.  64x64 block tile, k-tile 16, four waves
-// each owning a 32x32 quadrant made of 2x2 v_mfma_f64_16x16x4 tiles.
+// each owning a 32x32 quadrant made of 2x2 v_mfma_f64_16x16x4 tiles.  With
+// work set, work-group z covers k in [z kchunk, (z + 1) kchunk) and writes
+// alpha times its partial product to work[z] ([M][N]); beta is then unused.
 // MFMA operands: lane l holds A[l%16][l/16] and B[l/16][l%16]; the result
 // lane l, register r holds D[4*r + l/16][l%16] (checked on gfx950).
 template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t K, double alpha,
                                                   const double *__restrict__ A, int64_t lda,
                                                   const double *__restrict__ B, int64_t ldb,
-                                                  double beta, double *__restrict__ C, int64_t ldc)
+                                                  double beta, double *__restrict__ C, int64_t ldc,
+                                                  int64_t kchunk, double *__restrict__ work)
 {
     __shared__ double As[2][16][66];
+    const int64_t kb = (int64_t)blockIdx.z * kchunk;
+    const int64_t ke = (kb + kchunk < K) ? kb + kchunk : K;
     __shared__ double Bs[2][16][66];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
@@ -38,12 +43,12 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t 
             int ii, kk;
             if (!TA) { ii = e >> 4; kk = e & 15; } else { kk = e >> 6; ii = e & 63; }
             int64_t gi = i0 + ii, gk = k0 + kk;
-            ra[q] = (gi < M && gk < K) ? (TA ? A[gk * lda + gi] : A[gi * lda + gk]) : 0.0;
+            ra[q] = (gi < M && gk < ke) ? (TA ? A[gk * lda + gi] : A[gi * lda + gk]) : 0.0;
             int jj;
             if (!TB) { kk = e >> 6; jj = e & 63; } else { jj = e >> 4; kk = e & 15; }
             int64_t gj = j0 + jj;
             gk = k0 + kk;
-            rb[q] = (gk < K && gj < N) ? (TB ? B[gj * ldb + gk] : B[gk * ldb + gj]) : 0.0;
+            rb[q] = (gk < ke && gj < N) ? (TB ? B[gj * ldb + gk] : B[gk * ldb + gj]) : 0.0;
         }
     };
     auto sstore = [&](int buf) {
@@ -58,11 +63,11 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t 
         }
     };
     int buf = 0;
-    gload(0);
+    gload(kb);
     sstore(0);
     __syncthreads();
-    for (int64_t k0 = 0; k0 < K; k0 += 16) {
-        const bool more = k0 + 16 < K;
+    for (int64_t k0 = kb; k0 < ke; k0 += 16) {
+        const bool more = k0 + 16 < ke;
         if (more) gload(k0 + 16);
 #pragma unroll
         for (int kq = 0; kq < 16; kq += 4) {
@@ -92,8 +97,12 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t 
                 int64_t gj = j0 + wj + 16 * tj + (lane & 15);
                 if (gi < M && gj < N) {
                     double v = alpha * acc[ti][tj][r];
-                    if (beta != 0.0) v += beta * C[gi * ldc + gj];
-                    C[gi * ldc + gj] = v;
+                    if (work) {
+                        work[((int64_t)blockIdx.z * M + gi) * N + gj] = v;
+                    } else {
+                        if (beta != 0.0) v += beta * C[gi * ldc + gj];
+                        C[gi * ldc + gj] = v;
+                    }
                 }
             }
 }
@@ -108,10 +117,44 @@ void gemm_f64(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, 
         return;
     }
     dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64));
-    if (!ta && !tb) hipLaunchKernelGGL((k_gemm_f64<false, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
-    else if (ta && !tb) hipLaunchKernelGGL((k_gemm_f64<true, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
-    else if (!ta && tb) hipLaunchKernelGGL((k_gemm_f64<false, true>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
-    else hipLaunchKernelGGL((k_gemm_f64<true, true>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    double *nw = nullptr;
+    if (!ta && !tb) hipLaunchKernelGGL((k_gemm_f64<false, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, K, nw);
+    else if (ta && !tb) hipLaunchKernelGGL((k_gemm_f64<true, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, K, nw);
+    else if (!ta && tb) hipLaunchKernelGGL((k_gemm_f64<false, true>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, K, nw);
+    else hipLaunchKernelGGL((k_gemm_f64<true, true>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, K, nw);
+}
+
+// C = beta C + sum_z work[z] (z = 0, 1, ... in order)
+__global__ void k_splitk_sum(int64_t M, int64_t N, int nz, const double *work, double beta, double *C, int64_t ldc)
+{
+    const int64_t n = M * N;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        double v = 0.0;
+        for (int z = 0; z < nz; ++z) v += work[z * n + e];
+        const int64_t i = e / N, j = e % N;
+        if (beta != 0.0) v += beta * C[i * ldc + j];
+        C[i * ldc + j] = v;
+    }
+}
+
+void gemm_f64_splitk(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const double *A, int64_t lda,
+                     const double *B, int64_t ldb, double beta, double *C, int64_t ldc, double *work,
+                     int64_t work_elems)
+{
+    if (M <= 0 || N <= 0) return;
+    const int64_t tiles = ((N + 63) / 64) * ((M + 63) / 64);
+    // enough work-groups for two per CU (256 CUs), k-ranges of at least 256
+    int64_t nz = std::min<int64_t>((512 + tiles - 1) / tiles, K / 256);
+    nz = std::min<int64_t>(nz, work_elems / (M * N));
+    if (nz < 2 || !work) return gemm_f64(s, false, false, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    const int64_t kchunk = ((K + nz - 1) / nz + 15) / 16 * 16;
+    nz = (K + kchunk - 1) / kchunk;
+    dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64), (unsigned)nz);
+    hipLaunchKernelGGL((k_gemm_f64<false, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, 0.0, C,
+                       ldc, kchunk, work);
+    const int64_t n = M * N;
+    hipLaunchKernelGGL(k_splitk_sum, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 2048)), dim3(256), 0, s, M, N,
+                       (int)nz, work, beta, C, ldc);
 }
 
 // ------------------------------------------------------------ elementwise

@@ -29,9 +29,12 @@ inline int64_t solve_d_elems(int64_t n) { return (n + kSolveBlock - 1) / kSolveB
 // the sizes above).  Synchronises nothing; work is on stream s.
 void build_block_solve(hipStream_t s, int64_t n, const double *LU, int64_t lda, double *W, double *Dl, double *Du);
 
-// y = T_0^{-1} b for b, y [n][nrhs] (nrhs >= 1); z [n][nrhs] is scratch.
-// perm[i] is the row of b that becomes row i of P b.
+// y = T_0^{-1} b for b, y [n][nrhs] (nrhs >= 1); z [n][nrhs] is scratch,
+// work (work_elems doubles, may be null) room for the split-k partial
+// products of the several-right-hand-side form.  perm[i] is the row of b that
+// becomes row i of P b.
 void launch_block_solve(hipStream_t s, int64_t n, int64_t nrhs, const double *W, const double *Dl,
-                        const double *Du, const int32_t *perm, const double *b, double *z, double *y);
+                        const double *Du, const int32_t *perm, const double *b, double *z, double *y, double *work,
+                        int64_t work_elems);
 
 }  // namespace qhp

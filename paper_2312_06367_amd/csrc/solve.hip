@@ -100,7 +100,8 @@ void build_block_solve(hipStream_t s, int64_t n, const double *LU, int64_t lda, 
 }
 
 void launch_block_solve(hipStream_t s, int64_t n, int64_t nrhs, const double *W, const double *Dl,
-                        const double *Du, const int32_t *perm, const double *b, double *z, double *y)
+                        const double *Du, const int32_t *perm, const double *b, double *z, double *y, double *work,
+                        int64_t work_elems)
 {
     const int64_t B = kSolveBlock, nb = (n + B - 1) / B, ldw = solve_ldw(n);
     if (nrhs == 1) {
@@ -121,16 +122,19 @@ void launch_block_solve(hipStream_t s, int64_t n, int64_t nrhs, const double *W,
     hipLaunchKernelGGL(k_solve_gather, dim3(1024), dim3(256), 0, s, n, nrhs, perm, b, y);
     for (int64_t I = 0; I < nb; ++I) {
         const int64_t o = I * B, bi = std::min(B, n - o);
-        gemm_f64(s, false, false, bi, nrhs, bi, 1.0, Dl + I * B * B, B, y + o * nrhs, nrhs, 0.0, z + o * nrhs, nrhs);
+        gemm_f64_splitk(s, bi, nrhs, bi, 1.0, Dl + I * B * B, B, y + o * nrhs, nrhs, 0.0, z + o * nrhs, nrhs, work,
+                        work_elems);
         if (o > 0)
-            gemm_f64(s, false, false, bi, nrhs, o, -1.0, W + o * ldw, ldw, z, nrhs, 1.0, z + o * nrhs, nrhs);
+            gemm_f64_splitk(s, bi, nrhs, o, -1.0, W + o * ldw, ldw, z, nrhs, 1.0, z + o * nrhs, nrhs, work,
+                            work_elems);
     }
     for (int64_t I = nb - 1; I >= 0; --I) {
         const int64_t o = I * B, bi = std::min(B, n - o), e = o + bi;
-        gemm_f64(s, false, false, bi, nrhs, bi, 1.0, Du + I * B * B, B, z + o * nrhs, nrhs, 0.0, y + o * nrhs, nrhs);
+        gemm_f64_splitk(s, bi, nrhs, bi, 1.0, Du + I * B * B, B, z + o * nrhs, nrhs, 0.0, y + o * nrhs, nrhs, work,
+                        work_elems);
         if (e < n)
-            gemm_f64(s, false, false, bi, nrhs, n - e, -1.0, W + o * ldw + e, ldw, y + e * nrhs, nrhs, 1.0,
-                     y + o * nrhs, nrhs);
+            gemm_f64_splitk(s, bi, nrhs, n - e, -1.0, W + o * ldw + e, ldw, y + e * nrhs, nrhs, 1.0, y + o * nrhs,
+                            nrhs, work, work_elems);
     }
 }
 
