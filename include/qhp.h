@@ -74,7 +74,11 @@ enum { QHP_F64 = 0, QHP_F32 = 1, QHP_BF16 = 2, QHP_F32A = 3, QHP_BF16X2 = 4, QHP
 
 /* per-step solve with T_0 (the paper writes only T_0^{-1}, Sec. IV-B) */
 enum {
-    QHP_SOLVE_LU = 0,   /* LU with partial pivoting once, two triangular solves per step */
+    QHP_SOLVE_LU = 0,   /* LU with partial pivoting once, two triangular solves per step
+                           (factors applied in block-inverse form: 1024-row diagonal
+                           blocks inverted, and the off-diagonal blocks multiplied by
+                           those inverses, on the first LU step; about 2 n^2 doubles
+                           of device memory more)                                    */
     QHP_SOLVE_INV = 1,  /* inverse formed once from that LU, one product per step       */
     QHP_SOLVE_GMRES = 2 /* restarted GMRES, FP32 Arnoldi inside FP64 residual
                            refinement, started from a warm-start guess (set with
