@@ -77,8 +77,8 @@ enum {
     QHP_SOLVE_LU = 0,   /* LU with partial pivoting once, two triangular solves per step
                            (factors applied in block-inverse form: 1024-row diagonal
                            blocks inverted, and the off-diagonal blocks multiplied by
-                           those inverses, on the first LU step; about 2 n^2 doubles
-                           of device memory more)                                    */
+                           those inverses, on the first LU step; device memory: n^2
+                           doubles plus 2 x 1024^2 per started 1024 rows)            */
     QHP_SOLVE_INV = 1,  /* inverse formed once from that LU, one product per step       */
     QHP_SOLVE_GMRES = 2 /* restarted GMRES, FP32 Arnoldi inside FP64 residual
                            refinement, started from a warm-start guess (set with
