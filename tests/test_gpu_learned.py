@@ -254,7 +254,10 @@ def test_warm_start_training_gain():
     s.close()
     assert res["mlp"]["med"] < res["quad"]["med"] < res["extrap"]["med"]
     assert res["mlp"]["it"] <= res["quad"]["it"]
-    # the better of the two starts by measured residual: never worse than either at the median
+    # the better of the two starts by measured residual: never worse than either at the median.
+    # The marches compared are separate GMRES solves to a 1e-10 relative residual, so
+    # their start residuals (~1e-4 of |b|) differ by ~1e-6 relative per step, and more
+    # after hundreds of steps: the margin is 1e-4.
     _say("[warm best] network starts %d of %d steps" % (res["best"]["net"], len(held) * n))
-    assert res["best"]["med"] <= min(res["mlp"]["med"], res["quad"]["med"]) * (1 + 1e-6)
+    assert res["best"]["med"] <= min(res["mlp"]["med"], res["quad"]["med"]) * (1 + 1e-4)
     assert res["best"]["it"] <= res["quad"]["it"] and res["best"]["net"] > 0
