@@ -86,14 +86,18 @@ void launch_gm_update(hipStream_t s, int64_t n, int64_t nq, const float *V, int6
     hipLaunchKernelGGL(k_gm_update, dim3(nblk(n, 256)), dim3(256), 0, s, n, nq, V, ldv, h, w, nrm2);
 }
 
-// R is column-major with leading dimension m + 1: R[q + j (m + 1)]
-__global__ void k_gm_givens(int j, int m, const double *h1, const double *h2, const double *nrm2, double *R,
-                            double *cs, double *sn, double *g, double *inv, double *host_res)
+// R is column-major with leading dimension m + 1: R[q + j (m + 1)].  The
+// accumulators h1, h2 (j + 2 entries) and nrm2 are left zero for iteration
+// j + 1 once read.
+__global__ void k_gm_givens(int j, int m, double *h1, double *h2, double *nrm2, double *R, double *cs, double *sn,
+                            double *g, double *inv, double *host_res)
 {
     if (threadIdx.x != 0) return;
     double *col = R + (int64_t)j * (m + 1);
     for (int q = 0; q <= j; ++q) col[q] = h1[q] + h2[q];
     double hn = sqrt(*nrm2);
+    for (int q = 0; q <= j + 1 && q <= m; ++q) h1[q] = h2[q] = 0.0;
+    *nrm2 = 0.0;
     col[j + 1] = hn;
     for (int q = 0; q < j; ++q) {  // earlier rotations
         double a = col[q], b = col[q + 1];
@@ -113,10 +117,22 @@ __global__ void k_gm_givens(int j, int m, const double *h1, const double *h2, co
     *inv = hn > 0.0 ? 1.0 / hn : 0.0;
     *host_res = fabs(g[j + 1]);
 }
-void launch_gm_givens(hipStream_t s, int j, int m, const double *h1, const double *h2, const double *nrm2, double *R,
-                      double *cs, double *sn, double *g, double *inv, double *host_res)
+void launch_gm_givens(hipStream_t s, int j, int m, double *h1, double *h2, double *nrm2, double *R, double *cs,
+                      double *sn, double *g, double *inv, double *host_res)
 {
     hipLaunchKernelGGL(k_gm_givens, dim3(1), dim3(64), 0, s, j, m, h1, h2, nrm2, R, cs, sn, g, inv, host_res);
+}
+
+// zero the Arnoldi accumulators h1, h2 (m + 1 entries each) and nrm2 before
+// an inner solve's first iteration
+__global__ void k_gm_clear(int m, double *h1, double *h2, double *nrm2)
+{
+    for (int q = threadIdx.x; q <= m; q += blockDim.x) h1[q] = h2[q] = 0.0;
+    if (threadIdx.x == 0) *nrm2 = 0.0;
+}
+void launch_gm_clear(hipStream_t s, int m, double *h1, double *h2, double *nrm2)
+{
+    hipLaunchKernelGGL(k_gm_clear, dim3(1), dim3(64), 0, s, m, h1, h2, nrm2);
 }
 
 __global__ void k_gm_scale(int64_t n, const float *in, const double *scale, float *out)

@@ -76,9 +76,12 @@ void launch_gm_update(hipStream_t s, int64_t n, int64_t nq, const float *V, int6
                       double *nrm2);
 // Givens step of column j: Hcol[0..j] (from h1 + h2), h_{j+1,j} = sqrt(nrm2);
 // rotations cs/sn [m], g [m+1], R column-major [m][m+1]; res = |g[j+1]|;
-// inv = 1 / h_{j+1,j}; host_res (pinned) receives res
-void launch_gm_givens(hipStream_t s, int j, int m, const double *h1, const double *h2, const double *nrm2, double *R,
-                      double *cs, double *sn, double *g, double *inv, double *host_res);
+// inv = 1 / h_{j+1,j}; host_res (pinned) receives res.  h1, h2 (j + 2
+// entries) and nrm2 are zeroed once read, ready for column j + 1.
+void launch_gm_givens(hipStream_t s, int j, int m, double *h1, double *h2, double *nrm2, double *R, double *cs,
+                      double *sn, double *g, double *inv, double *host_res);
+// h1, h2 [m + 1] and nrm2 zeroed (before an inner solve's first column)
+void launch_gm_clear(hipStream_t s, int m, double *h1, double *h2, double *nrm2);
 // out = in * (*scale) (FP32 vector, FP64 scale)
 void launch_gm_scale(hipStream_t s, int64_t n, const float *in, const double *scale, float *out);
 // solve R y = g (k columns), x += sum_q y_q V[q] (x FP64)

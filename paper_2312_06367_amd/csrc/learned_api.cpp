@@ -610,19 +610,19 @@ bool gmres_solve(qhp_ctx *c, const double *b, double *x, int32_t *iters, float *
         // FP32 inner solve of T_0 d = r to a relative reduction tau
         const double tau = std::max(0.5 * c->gm_tol * nb / beta, 1e-6);
         launch_gm_start(s, ne, m, c->gm_r.as<double>(), c->gm_nrm.as<double>(), V, c->gm_g.as<double>());
+        launch_gm_clear(s, m, c->gm_h1.as<double>(), c->gm_h2.as<double>(), c->gm_nrm.as<double>());
         // the previous solve's count for this pass, less one, runs without
         // waiting for the residual estimate (more iterations only lower it)
         const int p = outer < (int)c->gm_pred.size() ? std::max(0, c->gm_pred[outer] - 1) : 0;
         int k = 0;
         for (int j = 0; j < m; ++j) {
             float *w = c->gm_w.as<float>();
+            // h1, h2 and the norm accumulator are zero here (k_gm_clear, then
+            // each Givens step clears what it read)
             launch_gm_matvec(s, ne, c->T0f.as<float>(), ld, V + (int64_t)j * ld, w);
-            launch_fill_f64(s, j + 1, 0.0, c->gm_h1.as<double>());
             launch_gm_dots(s, ne, j + 1, V, ld, w, c->gm_h1.as<double>());
             launch_gm_update(s, ne, j + 1, V, ld, c->gm_h1.as<double>(), w, nullptr);
-            launch_fill_f64(s, j + 1, 0.0, c->gm_h2.as<double>());
             launch_gm_dots(s, ne, j + 1, V, ld, w, c->gm_h2.as<double>());
-            launch_fill_f64(s, 1, 0.0, c->gm_nrm.as<double>());
             launch_gm_update(s, ne, j + 1, V, ld, c->gm_h2.as<double>(), w, c->gm_nrm.as<double>());
             launch_gm_givens(s, j, m, c->gm_h1.as<double>(), c->gm_h2.as<double>(), c->gm_nrm.as<double>(),
                              c->gm_R.as<double>(), c->gm_cs.as<double>(), c->gm_sn.as<double>(), c->gm_g.as<double>(),
