@@ -35,6 +35,35 @@ def history_sum(T: np.ndarray, ring: list, i: int) -> np.ndarray:
     return acc
 
 
+def history_sum_factored(A, B, C, PLH, PS, dtn, PE, PM, ring: list) -> np.ndarray:
+    """sum_{k=1}^{K} T_k y_{i-k} from the raw lag matrices A_k, B_k, C_k
+    (k = 0..K) and the preconditioners, without forming T_k (Sec. IV-A:
+    T_k = P_E W^E_k + P_M W^M_k, W^E_k = A_k P^{LH} + (A_k - A_{k-1})/dt~ P^Sigma
+    + B_k, W^M_k = C_k P^{LH} + (C_k - C_{k-1})/dt~ P^Sigma).  The difference
+    of consecutive lag matrices is moved onto the history by summation by
+    parts: with u_j = P^{LH} y_j, v_j = P^Sigma y_j, d_j = v_j - v_{j-1},
+      sum_k (A_k - A_{k-1}) v_{i-k} = sum_k A_k d_{i-k} + A_K v_{i-K-1} - A_0 v_{i-1},
+    so that
+      E = sum_k [A_k (u_{i-k} + d_{i-k}/dt~) + B_k y_{i-k}] + (A_K v_{i-K-1} - A_0 v_{i-1})/dt~
+      M = sum_k C_k (u_{i-k} + d_{i-k}/dt~) + (C_K v_{i-K-1} - C_0 v_{i-1})/dt~
+    and the sum is P_E E + P_M M.  ring[k-1] = y_{i-k} for k = 1..K+1 (zero
+    vectors before the first step)."""
+    K = len(A) - 1
+    if len(ring) < K + 1:
+        raise ValueError("the factored history needs y_{i-1} .. y_{i-K-1}")
+    u = [PLH @ y for y in ring[:K + 1]]
+    v = [PS @ y for y in ring[:K + 1]]
+    E = np.zeros(A[0].shape[:1] + np.shape(ring[0])[1:])
+    M = np.zeros_like(E)
+    for k in range(1, K + 1):
+        w = u[k - 1] + (v[k - 1] - v[k]) / dtn
+        E = E + A[k] @ w + B[k] @ ring[k - 1]
+        M = M + C[k] @ w
+    E = E + (A[K] @ v[K] - A[0] @ v[0]) / dtn
+    M = M + (C[K] @ v[K] - C[0] @ v[0]) / dtn
+    return PE @ E + PM @ M
+
+
 def block_solve(T: np.ndarray, r: np.ndarray) -> np.ndarray:
     """Direct dense solve of the full block lower-triangular system."""
     K = T.shape[0] - 1

@@ -23,6 +23,30 @@ def test_march_is_block_forward_substitution():
     assert np.abs(y - yb).max() < 1e-11 * np.abs(yb).max()
 
 
+def test_factored_history_equals_the_slabs():
+    """The history sum formed from the raw lag matrices and the
+    preconditioners (no T_k, difference quotient moved onto the history by
+    summation by parts) equals sum_k T_k y_{i-k} with the assembled slabs: on
+    random histories and on the history of an actual march (where the sum
+    cancels across lags), with one and with three right-hand sides."""
+    xyz, tri = meshes.icosphere(1)
+    a = O.Assembly(xyz, tri, 0.1)
+    T = a.build()
+    K, n = T.shape[0] - 1, T.shape[1]
+    p = a.proj
+    rng = np.random.default_rng(11)
+    cases = [[rng.standard_normal(n) for _ in range(K + 1)],
+             [rng.standard_normal((n, 3)) for _ in range(K + 1)]]
+    r = E.rhs(a, _wave(0.1, a.D), 60)
+    y = mot.march(T, r)
+    i = 50  # ring[k-1] = y_{i-k}, zero before the first step
+    cases.append([y[i - k - 1] if i - k >= 1 else np.zeros(n) for k in range(1, K + 2)])
+    for ring in cases:
+        dense = sum(T[k] @ ring[k - 1] for k in range(1, K + 1))
+        fact = mot.history_sum_factored(a.A, a.B, a.C, p.PLH, p.PS, a.dtn, a.PE, a.PM, ring)
+        assert np.abs(fact - dense).max() <= 1e-11 * np.abs(dense).max()
+
+
 def test_post_processing_from_q_basis():
     """eq. post_processing equals (P^{LH} + d~_t P^Sigma) y(t) at t_i, with y
     expanded in h_i P^{LH} + q_i P^Sigma and q_i' from the Sec. IV-A q_0."""
