@@ -37,7 +37,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="sphere-large",
-                    choices=["sphere-large", "sphere-small", "torus-batched", "uneven-batch", "warm-start"])
+                    choices=["sphere-large", "sphere-small", "torus-batched", "uneven-batch", "warm-start",
+                             "spectral"])
     ap.add_argument("--mesh", default="sphere", choices=["sphere", "torus"], help="warm-start mesh")
     ap.add_argument("--train-dirs", type=int, default=256, help="warm-start training directions")
     ap.add_argument("--train-steps", type=int, default=2000, help="warm-start training march length")
@@ -339,10 +340,90 @@ def bench_warm(a):
     print(json.dumps(out), flush=True)
 
 
+def decay_radius(norms, start, window, floor=1e-200):
+    """Late-time decay rate of a march whose excitation has passed: block
+    maxima of |y_i| over windows from step start on (windows whose maximum
+    fell below floor times the first are dropped), log-linear least squares,
+    exp(slope).  The march applies the companion matrix once per step, so
+    this is power iteration for its spectral radius."""
+    import numpy as np
+    for w in (window, window // 4, 2):  # shorter windows for marches that decay within a few of them
+        nb = (len(norms) - start) // w
+        m = np.array([norms[start + b * w:start + (b + 1) * w].max() for b in range(nb)])
+        keep = (m > floor * m[0]) & (m > 1e-280)
+        if keep.sum() >= 4:
+            return float(np.exp(np.polyfit(np.arange(nb)[keep] * w, np.log(m[keep]), 1)[0]))
+    return None
+
+
+def bench_spectral(a):
+    """cond_2(T_0) (power iteration), cond_1(T_0) and the companion spectral
+    radius (from the late-time decay of an FP64 march) against mesh size and
+    against the time step on the 480-edge sphere (the conditioning study of
+    Sec. V-A, its ranges, and the small steps of the march workloads)."""
+    import numpy as np
+    import torch
+    import paper_2312_06367_amd as qhp
+    from workloads import meshes, waves
+
+    f0 = waves.hz_to_per_m(50e6)
+
+    def one(level, dt):
+        xyz, tri = meshes.icosphere(level)
+        t0 = time.perf_counter()
+        s = qhp.Solver(dt, precision="f64", solver="inv")
+        s.mesh(xyz, tri)
+        s.assemble()
+        inf = s.info()
+        cond, cond2 = s.t0_condition(800)
+        f = min(f0, 1.0 / (16.0 * dt))  # a pulse the time step resolves
+        w = waves.Wave((0.0, 0.0, -1.0), (1.0, 0.0, 0.0), 1.0, waves.mod_gauss_t0(f, inf["diameter"]), 0, 0.0, f, f)
+        # the fit starts once the pulse and two transits of the scatterer are over
+        start = max(200, int(np.ceil((w.t0 + 8.0 / f + 2.0 * inf["diameter"]) / dt)))
+        n = start + 800
+        yh = torch.zeros((n, inf["ne"], 1), dtype=torch.float64, device="cuda")
+        s.set_incident([w], n)
+        s.run(n, None, yh)
+        ny = torch.linalg.vector_norm(yh[:, :, 0], dim=1).cpu().numpy()
+        s.close()
+        del yh
+        torch.cuda.empty_cache()
+        rho = decay_radius(ny, start, 40)
+        rec = {"ne": inf["ne"], "c_dt_m": dt, "K": inf["K"], "cond2_T0": cond2, "cond1_T0": cond, "companion_radius": rho,
+               "steps": n, "fit_from_step": start, "seconds": time.perf_counter() - t0}
+        log("ne=%5d c.dt=%9.4f K=%3d cond_2(T_0)=%8.4f cond_1(T_0)=%9.3f radius=%s (%d steps, %.1f s)"
+            % (inf["ne"], dt, inf["K"], cond2, cond, "%.6f" % rho if rho is not None else "-", n, rec["seconds"]))
+        return rec
+
+    def safe(level, dt):
+        try:
+            return one(level, dt)
+        except qhp.QhpError as e:  # recorded, not hidden
+            log("ne level %d c.dt=%g: %s" % (level, dt, e))
+            return {"level": level, "c_dt_m": dt, "error": str(e)}
+
+    # the paper's two studies: mesh size at c dt = 1 m, time step on a 0.3 m mesh
+    # from 0.25 m to 2048 m; and the same two at the small steps of the march
+    # workloads (c dt = 0.05 m; 0.0125 m to 0.1 m)
+    sweep_h = [safe(level, 1.0) for level in (1, 2, 3, 4)]
+    sweep_dt = [safe(2, dt) for dt in (0.25, 1.0, 4.0, 16.0, 64.0, 256.0, 1024.0, 2048.0)]
+    sweep_h_small = [safe(level, 0.05) for level in (1, 2, 3, 4)]
+    sweep_dt_small = [safe(2, dt) for dt in (0.0125, 0.025, 0.05, 0.1)]
+    ok = [r for r in sweep_h + sweep_dt if "cond2_T0" in r]
+    out = {"metric": "cond_2(T_0) and companion spectral radius vs mesh size and time step",
+           "value": max(r["cond2_T0"] for r in ok) if ok else None,
+           "unit": "largest cond_2(T_0) over the mesh-size and time-step sweeps",
+           "n_gpus": 1, "higher_is_better": False, "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "spectral", "mesh": "icospheres, radius 1 m", "wave": "modulated Gaussian, 50 MHz"},
+           "sweep_h": sweep_h, "sweep_dt": sweep_dt, "sweep_h_small_dt": sweep_h_small,
+           "sweep_dt_small": sweep_dt_small}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py measures one GPU only: this build runs the marching solver on a single MI355X "
+        print("bench.py measures one GPU only: the marching solver runs on a single MI355X "
               "(--gpus %d is not supported)" % a.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
@@ -353,6 +434,8 @@ def main():
         return bench_uneven(a)
     if a.workload == "warm-start":
         return bench_warm(a)
+    if a.workload == "spectral":
+        return bench_spectral(a)
     cfg = workload(a.workload, a.n_dirs)
     xyz, tri = cfg.mesh
     n_rhs = len(cfg.waves)

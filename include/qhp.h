@@ -168,6 +168,19 @@ int qhp_assemble(qhp_ctx *ctx);
  * qhp_assemble; resets the march (call qhp_set_incident again). */
 int qhp_set_precision(qhp_ctx *ctx, int32_t precision);
 
+/* Conditioning of the system solved at every step (the study of Sec. V-A,
+ * condition number against mesh size and time step), in FP64 on the GPU from
+ * the assembled T_0 and the inverse formed from its LU:
+ *   *cond1 = |T_0|_1 |T_0^{-1}|_1 (largest absolute column sums, exact);
+ *   *cond2 = sigma_max(T_0) / sigma_min(T_0), each largest singular value of
+ *            T_0 and T_0^{-1} from power_iters steps of power iteration on
+ *            A^T A (a fixed start vector; converged to ~1e-8 after 400
+ *            steps on the meshes tried).
+ * Either output may be NULL (not computed; not both).  After qhp_assemble;
+ * QHP_ESTATE if qhp_release_assembly freed T_0, QHP_EINVAL for
+ * power_iters < 1 with cond2 requested. */
+int qhp_t0_condition(qhp_ctx *ctx, int32_t power_iters, double *cond1, double *cond2);
+
 /* Switch the per-step T_0 solve (QHP_SOLVE_LU / QHP_SOLVE_INV); both use the
  * FP64 LU of T_0 made by qhp_assemble.  QHP_SOLVE_GMRES keeps the parameters
  * of the last qhp_set_gmres (defaults: tol 1e-10, 40 iterations, 4 inner

@@ -64,6 +64,31 @@ def history_sum_factored(A, B, C, PLH, PS, dtn, PE, PM, ring: list) -> np.ndarra
     return PE @ E + PM @ M
 
 
+def companion_radius(T: np.ndarray) -> float:
+    """Spectral radius of the block companion matrix of the march
+    y_i = -T_0^{-1} sum_{k=1}^{K} T_k y_{i-k} (Sec. IV-B with r = 0): the
+    largest |lambda| with det(sum_k lambda^{K-k} T_k) = 0.  Dense eigenvalues;
+    small meshes only."""
+    K, n = T.shape[0] - 1, T.shape[1]
+    T0i = np.linalg.inv(T[0])
+    comp = np.zeros((K * n, K * n))
+    for k in range(1, K + 1):
+        comp[:n, (k - 1) * n:k * n] = -T0i @ T[k]
+    comp[n:, :-n] = np.eye((K - 1) * n)
+    return float(np.abs(np.linalg.eigvals(comp)).max())
+
+
+def condition_1(A: np.ndarray) -> float:
+    """1-norm condition number |A|_1 |A^{-1}|_1 (largest absolute column sum)."""
+    return float(np.abs(A).sum(axis=0).max() * np.abs(np.linalg.inv(A)).sum(axis=0).max())
+
+
+def condition_2(A: np.ndarray) -> float:
+    """2-norm condition number sigma_max / sigma_min (singular values by SVD)."""
+    sv = np.linalg.svd(A, compute_uv=False)
+    return float(sv[0] / sv[-1])
+
+
 def block_solve(T: np.ndarray, r: np.ndarray) -> np.ndarray:
     """Direct dense solve of the full block lower-triangular system."""
     K = T.shape[0] - 1

@@ -61,7 +61,7 @@ class _Info(ctypes.Structure):
 EXPORTS = ["qhp_create", "qhp_mesh", "qhp_assemble", "qhp_set_precision", "qhp_set_solver", "qhp_profile",
            "qhp_hist_time", "qhp_set_incident", "qhp_step", "qhp_run", "qhp_query", "qhp_edges",
            "qhp_get_matrix", "qhp_keep_raw", "qhp_history_sum", "qhp_history_sum_variant", "qhp_history_variants",
-           "qhp_batch_create", "qhp_batch_create_variant", "qhp_batch_variants", "qhp_batch_history_variant",
+           "qhp_t0_condition", "qhp_batch_create", "qhp_batch_create_variant", "qhp_batch_variants", "qhp_batch_history_variant",
            "qhp_batch_run",
            "qhp_batch_step_times", "qhp_batch_last_error", "qhp_batch_destroy", "qhp_last_error",
            "qhp_destroy", "qhp_release_assembly", "qhp_set_gmres", "qhp_gmres_stats", "qhp_gmres_reset", "qhp_mlp_create",
@@ -100,6 +100,7 @@ def lib():
         L.qhp_history_sum.argtypes = [vp, i32, i64, i64, i64, i64, vp, vp, vp, i64, i64, vp, vp]
         L.qhp_history_sum_variant.argtypes = [vp, i32, i64, i64, i64, i64, vp, vp, vp, i64, i64, vp, vp, i32]
         L.qhp_history_variants.argtypes = [i32, i64]
+        L.qhp_t0_condition.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.qhp_batch_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]
         L.qhp_batch_create_variant.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.POINTER(vp)]
         L.qhp_batch_variants.argtypes = [i32, i32]
@@ -204,6 +205,12 @@ class Solver:
 
     def set_solver(self, solver: str):
         self._check(self.L.qhp_set_solver(self.h, SOLVERS[solver]))
+
+    def t0_condition(self, power_iters: int = 800):
+        """(|T_0|_1 |T_0^{-1}|_1, sigma_max(T_0) / sigma_min(T_0)) (qhp_t0_condition)"""
+        c1, c2 = ctypes.c_double(), ctypes.c_double()
+        self._check(self.L.qhp_t0_condition(self.h, int(power_iters), ctypes.byref(c1), ctypes.byref(c2)))
+        return float(c1.value), float(c2.value)
 
     def profile(self, enable=True):
         self._check(self.L.qhp_profile(self.h, int(bool(enable))))

@@ -876,6 +876,43 @@ extern "C" int qhp_release_assembly(qhp_ctx *ctx)
     return QHP_OK;
 }
 
+extern "C" int qhp_t0_condition(qhp_ctx *ctx, int32_t power_iters, double *cond1, double *cond2)
+{
+    if (!ctx || (!cond1 && !cond2) || (cond2 && power_iters < 1)) return QHP_EINVAL;
+    if (ctx->state < 2) return guard(ctx, QHP_ESTATE, "assemble first");
+    if (!ctx->T0raw.p || !ctx->Tinv.p) return guard(ctx, QHP_ESTATE, "T_0 or its inverse was released");
+    API_TRY
+    hipStream_t s = ctx->s;
+    const int64_t ne = ctx->mesh.ne;
+    const DBuf *mats[2] = {&ctx->T0raw, &ctx->Tinv};
+    if (cond1) {
+        DBuf partial, colsum;
+        partial.alloc(sizeof(double) * qhp::kColChunks * ne);
+        colsum.alloc(sizeof(double) * ne);
+        std::vector<double> h(ne);
+        double norms[2] = {0.0, 0.0};
+        for (int q = 0; q < 2; ++q) {
+            qhp::launch_col_abs_sums(s, ne, mats[q]->as<double>(), ne, partial.as<double>(), colsum.as<double>());
+            hip_check(hipMemcpyAsync(h.data(), colsum.p, sizeof(double) * ne, hipMemcpyDeviceToHost, s), "column sums");
+            hip_check(hipStreamSynchronize(s), "column sums");
+            for (double v : h) norms[q] = std::max(norms[q], v);
+        }
+        *cond1 = norms[0] * norms[1];
+    }
+    if (cond2) {  // sigma_max(T_0) sigma_max(T_0^{-1}) = sigma_max / sigma_min
+        DBuf work;
+        work.alloc(sizeof(double) * qhp::power_work_elems(ne));
+        double sig[2];
+        for (int q = 0; q < 2; ++q) {
+            sig[q] = qhp::largest_singular_value(s, ne, mats[q]->as<double>(), power_iters, work.as<double>());
+            if (!(sig[q] > 0.0)) throw Fail{QHP_EDEVICE, "power iteration failed"};
+        }
+        *cond2 = sig[0] * sig[1];
+    }
+    return QHP_OK;
+    API_CATCH(ctx)
+}
+
 extern "C" int qhp_set_solver(qhp_ctx *ctx, int32_t solver)
 {
     if (!ctx) return QHP_EINVAL;

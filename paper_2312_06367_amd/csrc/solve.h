@@ -37,4 +37,15 @@ void launch_block_solve(hipStream_t s, int64_t n, int64_t nrhs, const double *W,
                         const double *Du, const int32_t *perm, const double *b, double *z, double *y, double *work,
                         int64_t work_elems);
 
+// column sums of |A| (n x n, row stride lda) into colsum [n]; partial holds
+// kColChunks * n doubles (fixed summation order)
+constexpr int64_t kColChunks = 32;
+void launch_col_abs_sums(hipStream_t s, int64_t n, const double *A, int64_t lda, double *partial, double *colsum);
+// doubles of work for largest_singular_value
+inline int64_t power_work_elems(int64_t n) { return 3 * n + 8 + kColChunks * n; }
+// largest singular value of A (n x n, row stride n) by iters steps of power
+// iteration on A^T A from a fixed start vector; work holds
+// power_work_elems(n) doubles.  Synchronises the stream; -1 on a device error.
+double largest_singular_value(hipStream_t s, int64_t n, const double *A, int iters, double *work);
+
 }  // namespace qhp

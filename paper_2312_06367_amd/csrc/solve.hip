@@ -3,8 +3,10 @@
 #include "solve.h"
 
 #include <algorithm>
+#include <cmath>
 
 #include "linalg.h"
+#include "march.h"
 
 namespace qhp {
 
@@ -78,6 +80,98 @@ __global__ __launch_bounds__(256) void k_solve_row(int64_t rows, const double *_
     if (lane == 0) red[wave] = s;
     __syncthreads();
     if (tid == 0) out[r] = red[0] + red[1] + red[2] + red[3];
+}
+
+// partial[c][j] = sum of |A[i][j]| over the rows i of chunk c (kColChunks
+// chunks); threads over columns, so every row is read coalesced
+__global__ void k_col_abs_partial(int64_t n, const double *A, int64_t lda, int64_t rows_per_chunk, double *partial)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t c = blockIdx.y;
+    if (j >= n) return;
+    const int64_t i0 = c * rows_per_chunk, i1 = (i0 + rows_per_chunk < n) ? i0 + rows_per_chunk : n;
+    double acc = 0.0;
+    for (int64_t i = i0; i < i1; ++i) acc += fabs(A[i * lda + j]);
+    partial[c * n + j] = acc;
+}
+// partial[c][j] = sum over the rows i of chunk c of A[i][j] x[i]  (A^T x)
+__global__ void k_gemvT_partial(int64_t n, const double *A, int64_t lda, const double *x, int64_t rows_per_chunk,
+                                double *partial)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t c = blockIdx.y;
+    if (j >= n) return;
+    const int64_t i0 = c * rows_per_chunk, i1 = (i0 + rows_per_chunk < n) ? i0 + rows_per_chunk : n;
+    double acc = 0.0;
+    for (int64_t i = i0; i < i1; ++i) acc += A[i * lda + j] * x[i];
+    partial[c * n + j] = acc;
+}
+// out[j] = sum over the chunks c of partial[c][j] (in chunk order)
+__global__ void k_chunk_sum(int64_t n, int nchunks, const double *partial, double *out)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double acc = 0.0;
+    for (int c = 0; c < nchunks; ++c) acc += partial[c * n + j];
+    out[j] = acc;
+}
+// *out = |v|^2 (one work-group)
+__global__ __launch_bounds__(1024) void k_sumsq(int64_t n, const double *v, double *out)
+{
+    __shared__ double red[16];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) acc += v[i] * v[i];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+        *out = t;
+    }
+}
+// v = w / sqrt(*nrm2)
+__global__ void k_scale_rsqrt(int64_t n, const double *w, const double *nrm2, double *v)
+{
+    const double f = 1.0 / sqrt(*nrm2);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        v[i] = w[i] * f;
+}
+// a fixed start vector with no special direction
+__global__ void k_power_start(int64_t n, double *v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        v[i] = cos(0.7 * (double)i + 0.3) + 1.5;
+}
+
+void launch_col_abs_sums(hipStream_t s, int64_t n, const double *A, int64_t lda, double *partial, double *colsum)
+{
+    const int64_t rpc = (n + kColChunks - 1) / kColChunks;
+    const unsigned gx = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_col_abs_partial, dim3(gx, (unsigned)kColChunks), dim3(256), 0, s, n, A, lda, rpc, partial);
+    hipLaunchKernelGGL(k_chunk_sum, dim3(gx), dim3(256), 0, s, n, (int)kColChunks, partial, colsum);
+}
+
+double largest_singular_value(hipStream_t s, int64_t n, const double *A, int iters, double *work)
+{
+    double *v = work, *w = work + n, *t = work + 2 * n, *nrm = work + 3 * n, *partial = work + 3 * n + 8;
+    const int64_t rpc = (n + kColChunks - 1) / kColChunks;
+    const unsigned gx = (unsigned)((n + 255) / 256), gs = (unsigned)std::min<int64_t>(gx, 1024);
+    hipLaunchKernelGGL(k_power_start, dim3(gs), dim3(256), 0, s, n, v);
+    hipLaunchKernelGGL(k_sumsq, dim3(1), dim3(1024), 0, s, n, v, nrm);
+    hipLaunchKernelGGL(k_scale_rsqrt, dim3(gs), dim3(256), 0, s, n, v, nrm, v);
+    for (int it = 0; it < iters; ++it) {  // v <- A^T A v / |A^T A v|
+        launch_gemv_f64(s, n, A, v, w);
+        hipLaunchKernelGGL(k_gemvT_partial, dim3(gx, (unsigned)kColChunks), dim3(256), 0, s, n, A, n, w, rpc, partial);
+        hipLaunchKernelGGL(k_chunk_sum, dim3(gx), dim3(256), 0, s, n, (int)kColChunks, partial, t);
+        hipLaunchKernelGGL(k_sumsq, dim3(1), dim3(1024), 0, s, n, t, nrm);
+        hipLaunchKernelGGL(k_scale_rsqrt, dim3(gs), dim3(256), 0, s, n, t, nrm, v);
+    }
+    double h = 0.0;
+    if (hipMemcpyAsync(&h, nrm, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return -1.0;
+    return std::sqrt(std::sqrt(h));  // |A^T A v| -> sigma_max^2 at convergence
 }
 
 void build_block_solve(hipStream_t s, int64_t n, const double *LU, int64_t lda, double *W, double *Dl, double *Du)

@@ -509,6 +509,52 @@ def test_lu_block_solve_two_blocks_odd_size(n_rhs):
     assert err < 1e-10
 
 
+def _decay_radius(norms, start, window):
+    """late-time decay rate of a free march: block maxima of |y_i| over
+    windows from step start on, log-linear least-squares fit, exp(slope)"""
+    nb = (len(norms) - start) // window
+    m = np.array([norms[start + b * window:start + (b + 1) * window].max() for b in range(nb)])
+    return float(np.exp(np.polyfit(np.arange(nb) * window, np.log(m), 1)[0]))
+
+
+@pytest.mark.parametrize("mesh,dt", [(0, 0.25), (0, 0.1), (1, 0.2)])
+def test_t0_condition_and_companion_radius(mesh, dt):
+    """Spectral diagnostics on the GPU against the oracle: |T_0|_1 |T_0^-1|_1
+    from the library equals the oracle's (1e-10); sigma_max / sigma_min by
+    800 steps of power iteration equals the oracle's SVD ratio (1e-6); the
+    spectral radius of the
+    block companion matrix, estimated from the late-time decay of a GPU FP64
+    march (the march applies the companion matrix once per step, so this is
+    power iteration), equals the oracle's dense polynomial-eigenvalue radius
+    to 1e-3."""
+    import paper_2312_06367_amd as qhp
+    from oracle import mot, operators as O
+    from workloads import meshes, waves
+    xyz, tri = meshes.icosphere(mesh)
+    a = O.Assembly(xyz, tri, dt)
+    T = a.build()
+    rho_ref, c_ref, c2_ref = mot.companion_radius(T), mot.condition_1(T[0]), mot.condition_2(T[0])
+    s = qhp.Solver(dt, precision="f64", solver="inv")
+    s.mesh(xyz, tri)
+    s.assemble()
+    c, c2 = s.t0_condition(800)
+    f0 = waves.hz_to_per_m(50e6)
+    w = waves.Wave((0.0, 0.0, -1.0), (1.0, 0.0, 0.0), 1.0, waves.mod_gauss_t0(f0, a.D), 0, 0.0, f0, f0)
+    n = 1500
+    s.set_incident([w], n)
+    ne = s.info()["ne"]
+    yh = torch.zeros((n, ne, 1), dtype=torch.float64, device="cuda")
+    s.run(n, None, yh)
+    s.close()
+    ny = torch.linalg.vector_norm(yh[:, :, 0], dim=1).cpu().numpy()
+    rho = _decay_radius(ny, 800, 40)
+    _say("[spectral ico%d dt %.2f] cond_1(T_0) %.6f (oracle %.6f); cond_2 %.8f (oracle %.8f); radius from decay "
+         "%.6f (oracle %.6f)" % (mesh, dt, c, c_ref, c2, c2_ref, rho, rho_ref))
+    assert abs(c - c_ref) <= 1e-10 * c_ref
+    assert abs(c2 - c2_ref) <= 1e-6 * c2_ref
+    assert abs(rho - rho_ref) < 1e-3
+
+
 def test_dc_stability_10k_steps_large_sphere():
     """7680-edge sphere, FP32 blocks with FP64 sums: 10^4 steps, the current
     decays after the pulse and never grows (late-time dc stability)."""

@@ -105,14 +105,41 @@ def test_companion_spectrum_inside_unit_circle():
     xyz, tri = meshes.icosphere(0)
     a = O.Assembly(xyz, tri, 0.25)
     T = a.build()
-    K, n = T.shape[0] - 1, T.shape[1]
-    T0i = np.linalg.inv(T[0])
-    comp = np.zeros((K * n, K * n))
-    for k in range(1, K + 1):
-        comp[:n, (k - 1) * n:k * n] = -T0i @ T[k]
-    comp[n:, :-n] = np.eye((K - 1) * n)
-    rho = np.abs(np.linalg.eigvals(comp)).max()
-    assert rho < 1.0
+    assert mot.companion_radius(T) < 1.0
+
+
+def test_companion_radius_closed_forms():
+    """Scalar recurrences: t0 y_i + t1 y_{i-1} = 0 decays by |t1/t0|; a
+    two-lag recurrence whose characteristic polynomial
+    lambda^2 - 2 r cos(theta) lambda + r^2 has the roots r e^{+-i theta};
+    decoupled unknowns give the largest radius of the two."""
+    T = np.array([[[2.0]], [[-1.5]]])
+    assert abs(mot.companion_radius(T) - 0.75) < 1e-14
+    # lambda^2 + (t1/t0) lambda + (t2/t0) = 0 with roots 0.6 e^{+-i 0.4}
+    r, th = 0.6, 0.4
+    T2 = np.array([[[1.0]], [[-2 * r * np.cos(th)]], [[r * r]]])
+    assert abs(mot.companion_radius(T2) - r) < 1e-14
+    # two decoupled unknowns: radius of the slower one
+    Tb = np.zeros((2, 2, 2))
+    Tb[0] = np.diag([1.0, 4.0])
+    Tb[1] = np.diag([-0.3, -3.6])
+    assert abs(mot.companion_radius(Tb) - 0.9) < 1e-14
+
+
+def test_condition_1_closed_forms():
+    """cond_1 of a diagonal matrix is max|d| / min|d|; of a 2x2 rotation,
+    (|c| + |s|)^2.  cond_2 of a diagonal matrix is max|d| / min|d|, of a
+    rotation 1, of the shear [[1, e], [0, 1]] the ratio of its singular values
+    (sqrt(e^2 + 4) +- e) / 2."""
+    assert abs(mot.condition_1(np.diag([2.0, -8.0, 0.5])) - 16.0) < 1e-12
+    c, s_ = np.cos(0.3), np.sin(0.3)
+    R = np.array([[c, -s_], [s_, c]])
+    assert abs(mot.condition_1(R) - (abs(c) + abs(s_)) ** 2) < 1e-12
+    assert abs(mot.condition_2(np.diag([2.0, -8.0, 0.5])) - 16.0) < 1e-12
+    assert abs(mot.condition_2(R) - 1.0) < 1e-12
+    e = 3.0
+    hi, lo = (np.sqrt(e * e + 4) + e) / 2, (np.sqrt(e * e + 4) - e) / 2
+    assert abs(mot.condition_2(np.array([[1.0, e], [0.0, 1.0]])) - hi / lo) < 1e-12
 
 
 def test_far_field_against_mie_series():
