@@ -606,11 +606,17 @@ def main():
         # the byte floor of the factored form (raw shell-sparse lag matrices
         # with 32-bit indices, then the two dense preconditioners once per
         # step), against the dense FP32 blocks this build streams
+        # bytes per step of a history that streams the raw lag matrices
+        # instead of the dense blocks: with a 4-byte index per nonzero and
+        # the two preconditioner products, or lag-banded per edge pair (no
+        # index per nonzero) with the four dense products of that form
         "factored_history_floor": {
             "raw_nnz": inf["raw_nnz"],
             "bytes_fp32": inf["raw_nnz"] * (4 + 4) + 2 * ne * ne * 4,
+            "bytes_fp32_lag_banded": inf["raw_nnz"] * 4 + 4 * ne * ne * 4,
             "dense_slab_bytes_fp32": K * ne * ne * 4,
-            "dense_over_floor": K * ne * ne * 4 / (inf["raw_nnz"] * (4 + 4) + 2 * ne * ne * 4)},
+            "dense_over_floor": K * ne * ne * 4 / (inf["raw_nnz"] * (4 + 4) + 2 * ne * ne * 4),
+            "dense_over_lag_banded": K * ne * ne * 4 / (inf["raw_nnz"] * 4 + 4 * ne * ne * 4)},
     }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ne, K)
