@@ -603,9 +603,6 @@ def main():
         "forms": forms,
         "assembly_s": t_asm,
         "roofline": roof,
-        # the byte floor of the factored form (raw shell-sparse lag matrices
-        # with 32-bit indices, then the two dense preconditioners once per
-        # step), against the dense FP32 blocks this build streams
         # bytes per step of a history that streams the raw lag matrices
         # instead of the dense blocks: with a 4-byte index per nonzero and
         # the two preconditioner products, or lag-banded per edge pair (no
