@@ -6,6 +6,7 @@
 #include "linalg.h"
 
 #include <cstring>
+#include <type_traits>
 
 namespace qhp {
 
@@ -323,6 +324,112 @@ __global__ __launch_bounds__(256) void k_hist_gemv(int64_t ne, int64_t ld, int64
     }
 }
 
+// The single right-hand-side history with FP32 blocks staged in LDS: a
+// tile is 4 waves x RPW rows over the lags of one split; each step (lag,
+// chunk of 256 columns) copies the tile's block rows (one row = one 1 KB
+// piece, nontemporal) and the y chunk (cached: every row block reads it)
+// straight into one of NB LDS buffers, NB - 1 steps ahead (global_load_lds,
+// exact vmcnt waits, one barrier per step, one work-group per tile).  Lane l
+// reads columns 4l..4l+3 of its rows and of y.  Requires ld % 256 == 0 (whole
+// chunks stay inside a row); columns past ne are copied but masked in the
+// products, so the padding may hold anything; rows past ne are clamped in the
+// copies and never written.
+template <typename Y, typename A, int RPW, int NB, int MINW>
+__global__ __launch_bounds__(256, MINW) void k_hist_gemv_d(int64_t ne, int64_t ld, int64_t kmax,
+                                                           int64_t lags_per_split, const float *__restrict__ slabs,
+                                                           const Y *__restrict__ ring, int64_t n_slots, int64_t head,
+                                                           A *__restrict__ partial)
+{
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    typedef int i4 __attribute__((ext_vector_type(4)));
+    constexpr int AP = 4 * RPW;                          // block pieces of a step
+    constexpr int YP = (256 * (int)sizeof(Y)) / 1024;    // y pieces
+    constexpr int PIECES = (AP + YP + 3) / 4 * 4, PW = PIECES / 4, PF = NB - 1;
+    // vmcnt(PW (PF - 1)) with the other counters left alone (gfx9 encoding)
+    constexpr int WAIT_INFLIGHT = ((PW * (PF - 1)) & 15) | (7 << 4) | (15 << 8) | (((PW * (PF - 1)) >> 4) << 14);
+    static_assert(NB >= 2 && PW * (PF - 1) < 64 && YP >= 1, "pipeline shape");
+    __shared__ i4 S[NB][PIECES * 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t trow0 = (int64_t)blockIdx.x * AP;
+    const int64_t k_begin = 1 + (int64_t)blockIdx.y * lags_per_split;
+    const int64_t k_end = (k_begin + lags_per_split < kmax + 1) ? k_begin + lags_per_split : kmax + 1;
+    const int64_t nch = (ne + 255) / 256;  // chunks of 256 columns (ld is a multiple of 256)
+    const int64_t total = (k_end > k_begin ? k_end - k_begin : 0) * nch;
+    A acc[RPW];
+#pragma unroll
+    for (int rr = 0; rr < RPW; ++rr) acc[rr] = 0;
+    if (total > 0) {
+        int64_t lk = k_begin, lc = 0;  // copy cursor; past the end it repeats the last step
+        auto load = [&](int buf) {
+            const bool in = lk < k_end;
+            const int64_t k = in ? lk : k_end - 1, c0 = 256 * (in ? lc : nch - 1);
+            const float *Tk = slabs + (k - 1) * ne * ld;
+            const Y *y = ring + ((head + k - 1) % n_slots) * ld;
+#pragma unroll
+            for (int q = 0; q < PW; ++q) {
+                const int pc = wave + 4 * q;
+                if (pc < AP) {  // block row: read once, nontemporal
+                    int64_t row = trow0 + pc;
+                    row = row < ne ? row : ne - 1;
+                    __builtin_amdgcn_global_load_lds((const void *)(Tk + row * ld + c0 + 4 * lane),
+                                                     (__attribute__((address_space(3))) void *)(&S[buf][pc * 64]), 16,
+                                                     0, 2);
+                } else {  // the y chunk; padding pieces repeat its first piece
+                    const int off = (pc < AP + YP ? pc - AP : 0) * 1024 + lane * 16;
+                    __builtin_amdgcn_global_load_lds((const void *)(y + c0 + off / (int)sizeof(Y)),
+                                                     (__attribute__((address_space(3))) void *)(&S[buf][pc * 64]), 16,
+                                                     0, 0);
+                }
+            }
+            if (++lc == nch) {
+                lc = 0;
+                ++lk;
+            }
+        };
+#pragma unroll
+        for (int q = 0; q < PF; ++q) load(q);
+        __builtin_amdgcn_s_waitcnt(WAIT_INFLIGHT);  // step 0 is in
+        __builtin_amdgcn_s_barrier();
+        int64_t cc = 0;  // chunk of the step being multiplied
+        for (int64_t t0 = 0; t0 < total; t0 += NB) {
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                if (t0 + u >= total) break;
+                // step t + PF into the buffer read one step ago (every wave is past it)
+                load((u + PF) % NB);
+                const float *Sa = reinterpret_cast<const float *>(&S[u][0]);
+                const Y *Sy = reinterpret_cast<const Y *>(&S[u][AP * 64]);
+                const int64_t lim = ne - 256 * cc - 4 * lane;  // columns of this lane inside the matrix
+                A yv[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) yv[q] = q < lim ? (A)Sy[4 * lane + q] : (A)0;
+#pragma unroll
+                for (int rr = 0; rr < RPW; ++rr) {
+                    const f4 va = *reinterpret_cast<const f4 *>(Sa + (wave * RPW + rr) * 256 + 4 * lane);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc[rr] += (q < lim ? (A)va[q] : (A)0) * yv[q];
+                }
+                if (++cc == nch) cc = 0;
+                // this wave's copies of step t + 1 are in; then every wave's are
+                __builtin_amdgcn_s_waitcnt(WAIT_INFLIGHT);
+                __builtin_amdgcn_s_barrier();
+            }
+        }
+    }
+#pragma unroll
+    for (int rr = 0; rr < RPW; ++rr) {
+        A v = acc[rr];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        acc[rr] = v;
+    }
+    if (lane == 0) {
+        const int64_t row0 = trow0 + wave * RPW;
+#pragma unroll
+        for (int rr = 0; rr < RPW; ++rr)
+            if (row0 + rr < ne) partial[(int64_t)blockIdx.y * ne + row0 + rr] = acc[rr];
+    }
+}
+
 // b[row] = r[row] - sum_s partial[s][row]   (FP64 result)
 template <typename A>
 __global__ void k_hist_finish(int64_t n, int64_t nsplit, const A *partial, const double *r, double *b)
@@ -334,12 +441,16 @@ __global__ void k_hist_finish(int64_t n, int64_t nsplit, const A *partial, const
     b[i] = r[i] - s;
 }
 
-// variant table of the single right-hand-side kernel (autotuned per context)
+// variant table of the single right-hand-side kernel (autotuned per context):
+// rows per wave, column chunks in flight, nontemporal block loads; the last
+// two (unr = 0) are the LDS-staged kernel with 3 buffers (FP32 blocks without
+// per-block scales and with ld % 256 == 0; otherwise variant 2 runs in their
+// place)
 struct GemvVariant {
     int rpw, unr, nt;
 };
-static const GemvVariant kGemvVariants[] = {{4, 1, 0}, {4, 2, 0}, {4, 2, 1}, {8, 1, 1}, {8, 2, 1}, {2, 4, 1}, {4, 4, 1},
-                                             {2, 8, 1}, {8, 4, 1}};
+static const GemvVariant kGemvVariants[] = {{4, 1, 0}, {4, 2, 0}, {4, 2, 1}, {8, 1, 1}, {8, 2, 1}, {2, 4, 1},
+                                             {4, 4, 1}, {2, 8, 1}, {8, 4, 1}, {4, 0, 1}, {8, 0, 1}};
 constexpr int kNumGemvVariants = sizeof(kGemvVariants) / sizeof(kGemvVariants[0]);
 int gemv_variant_count() { return kNumGemvVariants; }
 void gemv_variant_desc(int v, int *rpw, int *unr, int *nt)
@@ -360,7 +471,23 @@ static void gemv_dispatch(int v, hipStream_t s, int64_t ne, int64_t ld, int64_t 
                            0, s, ne, ld, kmax, lps, (const T *)slabs, scales, (const Y *)ring, n_slots, head,    \
                            (A *)partial);                                                                      \
         break;
+#define QHP_GEMV_DMA(IDX, R, MINW)                                                                                  \
+    case IDX:                                                                                                      \
+        if constexpr (std::is_same<T, float>::value) {                                                             \
+            if (!scales && ld % 256 == 0) {                                                                        \
+                hipLaunchKernelGGL((k_hist_gemv_d<Y, A, R, 3, MINW>), dim3(nblk(ne, 4 * R), (unsigned)nsplit),    \
+                                   dim3(256), 0, s, ne, ld, kmax, lps, (const float *)slabs, (const Y *)ring,      \
+                                   n_slots, head, (A *)partial);                                                   \
+                break;                                                                                             \
+            }                                                                                                      \
+        }                                                                                                          \
+        hipLaunchKernelGGL((k_hist_gemv<T, Y, A, 4, 2, true>), dim3(nblk(ne, 16), (unsigned)nsplit), dim3(256), 0, \
+                           s, ne, ld, kmax, lps, (const T *)slabs, scales, (const Y *)ring, n_slots, head,         \
+                           (A *)partial);                                                                          \
+        break;
     switch (v) {
+        QHP_GEMV_DMA(9, 4, 2)
+        QHP_GEMV_DMA(10, 8, 1)
         QHP_GEMV_CASE(0, 4, 1, false)
         QHP_GEMV_CASE(1, 4, 2, false)
         QHP_GEMV_CASE(2, 4, 2, true)
@@ -373,6 +500,7 @@ static void gemv_dispatch(int v, hipStream_t s, int64_t ne, int64_t ld, int64_t 
         QHP_GEMV_CASE(8, 8, 4, true)
     }
 #undef QHP_GEMV_CASE
+#undef QHP_GEMV_DMA
 }
 
 // Batched right-hand sides: C[row][rhs] partials with FP32 MFMA

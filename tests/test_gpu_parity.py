@@ -345,6 +345,44 @@ def test_history_sum_kernel_ragged(precision, nrhs):
     assert err < bound
 
 
+@pytest.mark.parametrize("precision", ["f32a", "f32", "f64"])
+def test_history_sum_every_single_rhs_variant(precision):
+    """Every variant of the one-wave history kernel the autotuner chooses
+    from, including the LDS-staged ones (taken when ld % 256 == 0), on a
+    ragged size (1003 rows, 4 chunks of 256 columns, the last partial) with
+    NaN in the padding columns of the blocks and of the ring: each equals an
+    FP64 evaluation of the same stored values."""
+    import paper_2312_06367_amd as qhp
+    rng = np.random.default_rng(5)
+    ne, ld, kmax, n_slots, head = 1003, 1024, 6, 9, 4
+    T = rng.standard_normal((kmax, ne, ld))
+    T[:, :, ne:] = np.nan
+    Y = rng.standard_normal((n_slots, ld, 1))
+    Y[:, ne:, :] = np.nan
+    r = rng.standard_normal((ne, 1))
+    tdt = torch.float64 if precision == "f64" else torch.float32
+    ydt = torch.float32 if precision == "f32" else torch.float64
+    slabs = torch.from_numpy(T).to(tdt).cuda()
+    ring = torch.from_numpy(Y).to(ydt).cuda()
+    Teff = slabs.to(torch.float64).cpu().numpy()
+    Yeff = ring.to(torch.float64).cpu().numpy()
+    ref = r.copy()
+    for k in range(1, kmax + 1):
+        s_ = (head + k - 1) % n_slots
+        ref -= Teff[k - 1][:, :ne] @ Yeff[s_][:ne]
+    rt = torch.from_numpy(r).cuda()
+    bound = {"f64": 1e-13, "f32a": 1e-13, "f32": 2e-5}[precision]
+    nv = qhp.history_variants(precision, 1)
+    assert nv == 11
+    for v in range(nv):
+        b = torch.zeros_like(rt)
+        qhp.history_sum(precision, slabs, None, ring, head, rt, b, kmax=kmax, variant=v)
+        torch.cuda.synchronize()
+        err = float(np.abs(b.cpu().numpy() - ref).max() / np.abs(ref).max())
+        _say("[history_sum %s variant %d] err %.3e" % (precision, v, err))
+        assert np.isfinite(err) and err < bound
+
+
 def test_history_sum_full_size_sampled():
     """The single right-hand-side history kernel at the 7680-edge sphere shape
     (K = 101 FP32 blocks, 23.8 GB) on random data: sampled rows against an
