@@ -333,7 +333,9 @@ __global__ __launch_bounds__(256) void k_hist_gemv(int64_t ne, int64_t ld, int64
 // reads columns 4l..4l+3 of its rows and of y.  Requires ld % 256 == 0 (whole
 // chunks stay inside a row); columns past ne are copied but masked in the
 // products, so the padding may hold anything; rows past ne are clamped in the
-// copies and never written.
+// copies and never written.  Each lane sums a lag's products into a per-lag
+// partial and adds that to its total once the lag is done, the order of the
+// register form: with the same split count the two give identical results.
 template <typename Y, typename A, int RPW, int NB, int MINW>
 __global__ __launch_bounds__(256, MINW) void k_hist_gemv_d(int64_t ne, int64_t ld, int64_t kmax,
                                                            int64_t lags_per_split, const float *__restrict__ slabs,
@@ -355,9 +357,9 @@ __global__ __launch_bounds__(256, MINW) void k_hist_gemv_d(int64_t ne, int64_t l
     const int64_t k_end = (k_begin + lags_per_split < kmax + 1) ? k_begin + lags_per_split : kmax + 1;
     const int64_t nch = (ne + 255) / 256;  // chunks of 256 columns (ld is a multiple of 256)
     const int64_t total = (k_end > k_begin ? k_end - k_begin : 0) * nch;
-    A acc[RPW];
+    A acc[RPW], part[RPW];
 #pragma unroll
-    for (int rr = 0; rr < RPW; ++rr) acc[rr] = 0;
+    for (int rr = 0; rr < RPW; ++rr) acc[rr] = part[rr] = 0;
     if (total > 0) {
         int64_t lk = k_begin, lc = 0;  // copy cursor; past the end it repeats the last step
         auto load = [&](int buf) {
@@ -407,9 +409,16 @@ __global__ __launch_bounds__(256, MINW) void k_hist_gemv_d(int64_t ne, int64_t l
                 for (int rr = 0; rr < RPW; ++rr) {
                     const f4 va = *reinterpret_cast<const f4 *>(Sa + (wave * RPW + rr) * 256 + 4 * lane);
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) acc[rr] += (q < lim ? (A)va[q] : (A)0) * yv[q];
+                    for (int q = 0; q < 4; ++q) part[rr] += (q < lim ? (A)va[q] : (A)0) * yv[q];
                 }
-                if (++cc == nch) cc = 0;
+                if (++cc == nch) {  // the lag is done
+                    cc = 0;
+#pragma unroll
+                    for (int rr = 0; rr < RPW; ++rr) {
+                        acc[rr] += part[rr];
+                        part[rr] = 0;
+                    }
+                }
                 // this wave's copies of step t + 1 are in; then every wave's are
                 __builtin_amdgcn_s_waitcnt(WAIT_INFLIGHT);
                 __builtin_amdgcn_s_barrier();
