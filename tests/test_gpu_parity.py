@@ -651,6 +651,52 @@ def test_large_time_step_far_field_against_mie():
     assert errs[3] < errs[2] / 2.5
 
 
+def test_large_time_step_sweep_scaling():
+    """Time steps from 2 to 128 sphere diameters (K = 2, the pulse scaled
+    with the step) on the 120-edge sphere: at every step the GPU FP64 march
+    equals the oracle's (1e-10) and cond_2(T_0) equals the oracle's (1e-6);
+    over the sweep the solenoidal current stays at its magnetostatic level
+    (log-log slope 0) and the irrotational part falls as ka (slope -1), with
+    cond_2(T_0) flat (Sec. IV-A, V-A: no large-time-step breakdown)."""
+    import paper_2312_06367_amd as qhp
+    from oracle import excitation as E, mot, operators as O
+    from workloads import meshes, waves
+    xyz, tri = meshes.icosphere(1)
+    dts = np.array([4.0, 64.0, 256.0])
+    loop, star, cond = [], [], []
+    for dt in dts:
+        a = O.Assembly(xyz, tri, dt)
+        T = a.build()
+        f = 1.0 / (64.0 * dt)
+        w = waves.Wave((0.0, 0.0, -1.0), (1.0, 0.0, 0.0), 1.0, waves.mod_gauss_t0(f, a.D), 0, 0.0, f, f)
+        n = int(np.ceil((w.t0 + 12.0 / f) / dt)) + 50
+        jref = mot.currents(a.proj.PLH, a.proj.PS, a.dtn, mot.march(T, E.rhs(a, w, n)))
+        s = qhp.Solver(float(dt), precision="f64", solver="inv")
+        s.mesh(xyz, tri)
+        s.assemble()
+        assert s.info()["K"] == 2
+        _, c2 = s.t0_condition(800)
+        s.set_incident([w], n)
+        jh = torch.zeros((n, s.info()["ne"], 1), dtype=torch.float64, device="cuda")
+        s.run(n, jh)
+        s.close()
+        j = jh[:, :, 0].cpu().numpy()
+        par = float(np.abs(j - jref).max() / np.abs(jref).max())
+        c2_ref = mot.condition_2(T[0])
+        _say("[large dt sweep, c dt %.0f m] GPU march vs oracle %.3e; cond_2(T_0) %.8f (oracle %.8f)" % (dt, par, c2, c2_ref))
+        assert par < 1e-10
+        assert abs(c2 - c2_ref) <= 1e-6 * c2_ref
+        loop.append(np.abs(j @ a.proj.PLH.T).max())
+        star.append(np.abs(j @ a.proj.PS.T).max())
+        cond.append(c2)
+    s_loop = np.diff(np.log(loop)) / np.diff(np.log(dts))
+    s_star = np.diff(np.log(star)) / np.diff(np.log(dts))
+    _say("[large dt sweep] slopes: solenoidal %s, irrotational %s; cond_2 %s" % (s_loop, s_star, cond))
+    assert np.all(np.abs(s_loop) < 0.01)
+    assert np.all(np.abs(s_star + 1.0) < 0.03)
+    assert max(cond) / min(cond) < 1.1
+
+
 def test_dc_stability_10k_steps_large_sphere():
     """7680-edge sphere, FP32 blocks with FP64 sums: 10^4 steps, the current
     decays after the pulse and never grows (late-time dc stability)."""

@@ -166,3 +166,36 @@ def test_far_field_against_mie_series():
     errE = np.sqrt(np.mean((sE - mE) ** 2) / np.mean(mE ** 2))
     errH = np.sqrt(np.mean((sH - mH) ** 2) / np.mean(mH ** 2))
     assert errE < 0.05 and errH < 0.05, (errE, errH)
+
+
+def _large_dt_parts(xyz, tri, dt):
+    """Peak solenoidal and irrotational current of a march whose pulse the
+    step resolves (f = 1 / (64 dt)), and cond_2(T_0)."""
+    a = O.Assembly(xyz, tri, dt)
+    T = a.build()
+    f = 1.0 / (64.0 * dt)
+    w = _wave(f, a.D)
+    n = int(np.ceil((w.t0 + 12.0 / f) / dt)) + 50
+    j = mot.currents(a.proj.PLH, a.proj.PS, a.dtn, mot.march(T, E.rhs(a, w, n)))
+    return T.shape[0] - 1, np.abs(j @ a.proj.PLH.T).max(), np.abs(j @ a.proj.PS.T).max(), mot.condition_2(T[0])
+
+
+def test_large_time_step_scaling_exponents():
+    """Large time steps (c dt from 2 to 128 sphere diameters, K = 2, the pulse
+    scaled with the step): a PEC's low-frequency current has a solenoidal part
+    that tends to the magnetostatic limit, O(1), and an irrotational part
+    (the charge) of O(ka), so their log-log slopes against dt are 0 and -1;
+    the stabilised operator keeps cond_2(T_0) flat (Sec. IV-A, V-A: no
+    large-time-step breakdown).  Dropping the 1/dt~ of the post-processing
+    (eq. post_processing) or of the irrotational term of W^M moves a slope by
+    a whole power."""
+    xyz, tri = meshes.icosphere(1)
+    dts = np.array([4.0, 16.0, 64.0, 256.0])
+    parts = [_large_dt_parts(xyz, tri, dt) for dt in dts]
+    assert all(p[0] == 2 for p in parts)
+    loop, star, cond = (np.array([p[i] for p in parts]) for i in (1, 2, 3))
+    s_loop = np.diff(np.log(loop)) / np.diff(np.log(dts))
+    s_star = np.diff(np.log(star)) / np.diff(np.log(dts))
+    assert np.all(np.abs(s_loop) < 0.01), s_loop
+    assert np.all(np.abs(s_star + 1.0) < 0.03), s_star
+    assert cond.max() / cond.min() < 1.1 and cond.max() < 5.0, cond
