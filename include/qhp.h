@@ -45,6 +45,9 @@ enum {
     QHP_ENOCONV = -7,   /* iterative solve did not reach its tolerance        */
     QHP_EUNSTABLE = -8  /* non-finite value in the marching solution          */
 };
+/* Every call that returns int gives QHP_EINVAL for a null handle (context,
+ * batch or perceptron) without touching the device; the destroy calls accept a
+ * null handle and do nothing. */
 
 /* storage of the lag blocks T_k, k >= 1, and the history-sum arithmetic
  * (T_0, the solve and the post-processing are always FP64):

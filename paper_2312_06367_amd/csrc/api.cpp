@@ -1011,7 +1011,8 @@ extern "C" int qhp_query(const qhp_ctx *ctx, qhp_info *info)
 
 extern "C" int qhp_edges(const qhp_ctx *ctx, int32_t *edges, int32_t *cells)
 {
-    if (!ctx || ctx->state < 1) return QHP_ESTATE;
+    if (!ctx) return QHP_EINVAL;
+    if (ctx->state < 1) return QHP_ESTATE;
     if (edges) std::memcpy(edges, ctx->mesh.edges.data(), sizeof(int32_t) * ctx->mesh.edges.size());
     if (cells) std::memcpy(cells, ctx->mesh.cells.data(), sizeof(int32_t) * ctx->mesh.cells.size());
     return QHP_OK;

@@ -46,3 +46,65 @@ def test_batch_tile_shape_counts():
     assert pkg.batch_variants("f64", 8) == 1
     assert pkg.batch_variants("bf16", 4) == 0
     assert pkg.batch_variants("i8x4", 8) == 0
+
+
+# entry points whose first argument is a handle, with the other arguments
+# they take (all passed as zero / null)
+_HANDLE_CALLS = {
+    "qhp_keep_raw": 1, "qhp_mesh": 4, "qhp_assemble": 0, "qhp_set_precision": 1, "qhp_t0_condition": 3,
+    "qhp_set_solver": 1, "qhp_release_assembly": 0, "qhp_profile": 1, "qhp_hist_time": 2,
+    "qhp_set_incident": 3, "qhp_step": 1, "qhp_run": 3, "qhp_query": 1, "qhp_edges": 2, "qhp_get_matrix": 3,
+    "qhp_batch_run": 2, "qhp_batch_step_times": 2, "qhp_set_gmres": 4, "qhp_gmres_stats": 4,
+    "qhp_gmres_reset": 0, "qhp_mlp_create": 3, "qhp_mlp_dims": 3, "qhp_mlp_set_params": 1,
+    "qhp_mlp_get_params": 1, "qhp_mlp_features": 3, "qhp_mlp_guess": 2, "qhp_mlp_reconstruct": 3,
+    "qhp_mlp_forward": 3, "qhp_mlp_loss_grad": 5, "qhp_mlp_adam": 4, "qhp_mlp_train": 7, "qhp_attach_mlp": 1,
+}
+
+
+def test_null_handles_and_bad_sizes_are_rejected():
+    """Host logic of the boundary, no device touched: every call on a null
+    handle returns QHP_EINVAL and the destroy calls accept one; the history
+    sum rejects bad sizes, layouts, ring shapes and variants before it
+    allocates or launches anything."""
+    import paper_2312_06367_amd as pkg
+    if not os.path.exists(pkg.LIB_PATH):
+        pytest.skip("libqhp.so not built")
+    L = ctypes.CDLL(pkg.LIB_PATH)
+    EINVAL = -1
+    declared = set(declared_symbols())
+    for name, nargs in _HANDLE_CALLS.items():
+        assert name in declared, name
+        f = getattr(L, name)
+        f.restype = ctypes.c_int
+        f.argtypes = [ctypes.c_void_p] + [ctypes.c_int64] * nargs
+        assert f(None, *([0] * nargs)) == EINVAL, name
+    for name in ("qhp_destroy", "qhp_batch_destroy", "qhp_mlp_destroy"):
+        f = getattr(L, name)
+        f.argtypes = [ctypes.c_void_p]
+        f.restype = None
+        f(None)
+    f = L.qhp_create
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    assert f(None, None) == EINVAL
+
+    h = L.qhp_history_sum_variant
+    h.restype = ctypes.c_int
+    h.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
+    P = {"f64": 0, "f32": 1, "bf16": 2, "f32a": 3, "bf16x2": 4, "i8x4": 5}
+    assert [pkg.PRECISIONS[k] for k in P] == list(P.values())
+    fake = 4096  # never dereferenced: every case below fails its checks first
+    good = dict(p=P["f32"], ne=100, ld=128, nrhs=1, kmax=4, slabs=fake, scales=None, ring=fake, n_slots=4, head=0,
+                r=fake, b=fake, variant=-1)
+    bad = [dict(ne=0), dict(ld=96), dict(ld=100), dict(nrhs=0), dict(kmax=-1), dict(n_slots=3), dict(head=-1),
+           dict(slabs=None), dict(ring=None), dict(r=None), dict(b=None), dict(variant=11), dict(variant=-2),
+           dict(p=6), dict(p=-1), dict(p=P["f32a"], nrhs=2), dict(p=P["bf16x2"], nrhs=1),
+           dict(p=P["bf16x2"], nrhs=2, ld=136), dict(p=P["i8x4"], nrhs=1), dict(p=P["i8x4"], nrhs=2, ld=160),
+           dict(p=P["bf16"], nrhs=1), dict(p=P["f64"], nrhs=2, variant=1)]
+    for change in bad:
+        a = dict(good, **change)
+        rc = h(None, a["p"], a["ne"], a["ld"], a["nrhs"], a["kmax"], a["slabs"], a["scales"], a["ring"],
+               a["n_slots"], a["head"], a["r"], a["b"], a["variant"])
+        assert rc == EINVAL, change
