@@ -390,6 +390,52 @@ def test_history_sum_every_single_rhs_variant(precision):
         first = bh if first is None else first
 
 
+def test_degenerate_history_and_empty_runs():
+    """Degenerate calls: a history sum over no lags (kmax = 0, no blocks and
+    no ring given) returns b = r exactly in every arithmetic form and layout;
+    a run of zero steps changes nothing, so run(7), run(0), run(5) equals
+    run(12) (to rounding: each context's autotuner may split the history sum's
+    lags differently, which regroups its FP64 sums)."""
+    import paper_2312_06367_amd as qhp
+    from workloads import meshes
+    ne = 200
+    for precision, nrhs in (("f64", 1), ("f32", 1), ("f32a", 1), ("bf16", 1), ("f64", 3), ("f32", 3),
+                            ("bf16", 3), ("bf16x2", 2), ("i8x4", 2)):
+        ld = 256
+        r = torch.randn((ne, nrhs), dtype=torch.float64, device="cuda")
+        b = torch.full_like(r, float("nan"))
+        if precision == "bf16x2":
+            slabs = torch.empty((0, (ne + 15) // 16, ld // 32, 2, 512), dtype=torch.bfloat16, device="cuda")
+        elif precision == "i8x4":
+            R = (ne + 15) // 16 * 16
+            slabs = torch.empty((0, R * ld * 4 + R * 8), dtype=torch.int8, device="cuda")
+        else:
+            slabs = torch.empty((0, ne, ld), dtype=torch.float32, device="cuda")
+        scales = torch.ones(1, dtype=torch.float32, device="cuda") if precision == "bf16" else None
+        ring = torch.empty((0, ld, nrhs), dtype=torch.float64, device="cuda")
+        qhp.history_sum(precision, slabs, scales, ring, 0, r, b, kmax=0)
+        torch.cuda.synchronize()
+        _say("[degenerate] kmax = 0, %s, %d waves: b == r %s" % (precision, nrhs, bool(torch.equal(b, r))))
+        assert torch.equal(b, r)
+    xyz, tri = meshes.icosphere(1)
+    w = _wave(0.1, 2.0)
+    outs = []
+    for plan in ((7, 0, 5), (12,)):
+        s = qhp.Solver(0.15, precision="f64", solver="inv")
+        s.mesh(xyz, tri)
+        s.assemble()
+        s.set_incident([w], 12)
+        jh = torch.zeros((12, s.info()["ne"], 1), dtype=torch.float64, device="cuda")
+        at = 0
+        for n in plan:
+            s.run(n, jh[at:at + n] if n else None)
+            at += n
+        outs.append(jh.cpu().numpy())
+        s.close()
+    err = float(np.abs(outs[0] - outs[1]).max() / np.abs(outs[1]).max())
+    _say("[degenerate] run(7), run(0), run(5) vs run(12): %.2e" % err)
+    assert err < 1e-13
+
 def test_history_sum_full_size_sampled():
     """The single right-hand-side history kernel at the 7680-edge sphere shape
     (K = 101 FP32 blocks, 23.8 GB) on random data: sampled rows against an
