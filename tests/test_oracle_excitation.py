@@ -53,3 +53,30 @@ def test_tested_electric_field_against_adaptive_integration():
     for m in (0, 7, 33, 64, 101, a.topo.ne - 1):
         ref = _tested_brute(a.topo, m, wave, t)
         assert abs(e[step, m] - ref) < 1e-7 * scale, (m, e[step, m], ref)
+
+
+def test_testing_maps_integrate_a_uniform_field_exactly():
+    """For a uniform field F and a divergence-conforming function g with no
+    flux out of its support, the integral of g . F over the surface is
+    -F . (integral of r div g) (divergence theorem cell by cell, with the
+    normal flux continuous across inner edges).  Unit-flux RWG functions:
+    div f_m = +1/A on the plus cell and -1/A on the minus cell, so
+    integral f_m = centroid(minus) - centroid(plus).  BC functions on the
+    barycentric refinement: div g = (sum of the fine-cell fluxes) / A on
+    each fine cell.  The oracle's testing maps (7-point rule, exact for the
+    linear integrands here) must agree to rounding."""
+    xyz, tri = meshes.torus(1.0, 0.4, 12, 6)
+    a = O.Assembly(xyz, tri, 0.12)
+    t = a.topo
+    We, pc, Wh, pf = E._testing_matrices(a)
+    F = np.array([0.3, -1.1, 0.7])
+    e = We @ np.tile(F, pc.shape[0])
+    h = Wh @ np.tile(F, pf.shape[0])
+    int_f = t.centroid[t.cells[:, 1]] - t.centroid[t.cells[:, 0]]
+    assert np.abs(e - int_f @ F).max() < 1e-13 * np.abs(e).max()
+    fc = t.fxyz[t.ftri].mean(axis=1)
+    int_g = np.zeros((t.ne, 3))
+    for ft, lst in enumerate(t.bc_entries):
+        for m, fl in lst:
+            int_g[m] -= float(np.sum(fl)) * fc[ft]
+    assert np.abs(h - int_g @ F).max() < 1e-12 * np.abs(h).max()
