@@ -278,7 +278,11 @@ int qhp_history_sum(void *stream, int32_t precision, int64_t ne, int64_t ld, int
  * qhp_history_variants(precision, nrhs); -1 = the default), for callers that
  * tune or test the variants the march's autotuner chooses from.  Every
  * variant computes the same products; they differ in tiling and scheduling.
- * QHP_EINVAL for a variant out of range. */
+ * With one right-hand side (11 variants) every variant also sums each row in
+ * the same order, so all of them return identical results; the last two stage
+ * the blocks through LDS and need FP32 blocks (QHP_F32, QHP_F32A) with
+ * ld % 256 == 0, otherwise variant 2 runs in their place.  QHP_EINVAL for a
+ * variant out of range. */
 int qhp_history_sum_variant(void *stream, int32_t precision, int64_t ne, int64_t ld, int64_t nrhs,
                             int64_t kmax, const void *slabs, const float *scales, const void *ring,
                             int64_t n_slots, int64_t head, const double *r, double *b, int32_t variant);
