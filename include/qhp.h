@@ -16,8 +16,10 @@
  *     keeps no caller pointer.  Pointers documented as "device" must be device
  *     memory of the context's GPU; the library orders its use on the
  *     context's stream and the call returns when the work is complete.
- *   - the context owns all of its device memory (hipMalloc) and frees it in
- *     qhp_destroy.  All work is issued on params.stream (NULL: null stream).
+ *   - the context owns all of its device memory and frees it in qhp_destroy:
+ *     hipMalloc / hipFree, or the caller's params.dev_alloc / dev_free hook
+ *     when one is given.  All work is issued on params.stream (NULL: null
+ *     stream).
  *   - order: create -> mesh -> assemble -> set_incident -> step/run; other
  *     orders return QHP_ESTATE.  set_incident may be repeated (restarts the
  *     march at step 0).  Contexts are not thread-safe.
@@ -43,7 +45,8 @@ enum {
     QHP_EDEVICE = -5,   /* HIP runtime error                                  */
     QHP_ESINGULAR = -6, /* zero pivot in an LU factorisation                  */
     QHP_ENOCONV = -7,   /* iterative solve did not reach its tolerance        */
-    QHP_EUNSTABLE = -8  /* non-finite value in the marching solution          */
+    QHP_EUNSTABLE = -8  /* non-finite value in the marching solution, or its
+                           growth trip (qhp_set_growth_limit)                  */
 };
 /* Every call that returns int gives QHP_EINVAL for a null handle (context,
  * batch or perceptron) without touching the device; the destroy calls accept a
@@ -110,6 +113,18 @@ typedef struct {
     int32_t n_psi;     /* angular Gauss points per sub-interval; <= 0 means 10    */
     int32_t device;    /* HIP device ordinal                                       */
     void *stream;      /* hipStream_t, or NULL                                     */
+    /* Optional device allocator for everything the context, its batches and
+     * its perceptron allocate (both NULL: hipMalloc / hipFree; one without
+     * the other: QHP_EINVAL).  dev_alloc(bytes, alloc_user) returns device
+     * memory of params.device aligned to 256 bytes, or NULL (the call then
+     * fails with QHP_ENOMEM); dev_free(ptr, alloc_user) takes back a pointer
+     * it returned.  The library waits for the device before each dev_free,
+     * as hipFree does.  Both are called from the thread of the entry point
+     * that allocates or frees, only inside library calls; alloc_user is
+     * passed through untouched. */
+    void *(*dev_alloc)(size_t bytes, void *user);
+    void (*dev_free)(void *ptr, void *user);
+    void *alloc_user;
 } qhp_params;
 
 /* One incident plane wave (Sec. V); u = t - t0 - k_hat . r
@@ -145,8 +160,23 @@ typedef struct {
 } qhp_info;
 
 /* Create a context (no device work beyond selecting params->device).
- * *out receives the handle; QHP_EINVAL for dt <= 0 or an unknown enum. */
+ * *out receives the handle; QHP_EINVAL for dt <= 0, an unknown enum or a
+ * half-given allocator hook. */
 int qhp_create(const qhp_params *params, qhp_ctx **out);
+
+/* Check a surface mesh on the host, with no context and no device: the
+ * assumptions of Sec. II-A (closed, connected, orientable Gamma), as
+ * qhp_mesh checks them.  Returns QHP_OK, QHP_EINVAL for null or negative
+ * sizes, or QHP_EMESH for a triangle index out of range, a repeated vertex in
+ * a triangle, an edge not shared by exactly two triangles (open or
+ * non-manifold), inconsistently oriented neighbours, a disconnected surface,
+ * a zero-area triangle (area below 1e-12 of its longest edge squared, i.e.
+ * zero up to rounding), or a vertex whose triangles do not form one disc
+ * (non-manifold vertex).  On QHP_OK the optional outputs receive the edge count
+ * and the number of global loops N_H = 2 - (N_V - N_E + N_C) (Sec. II-D); if
+ * msg is not NULL, msg_len > 0 bytes of it receive the reason (NUL-ended). */
+int qhp_check_mesh(const double *xyz, int64_t nv, const int32_t *tri, int64_t nc, int64_t *n_edges,
+                   int64_t *n_harmonic, char *msg, int64_t msg_len);
 
 /* Mesh of the scatterer surface Gamma (Sec. II-A: closed, connected,
  * orientable), host arrays: xyz [nv][3] metres, tri [nc][3] vertex indices,
@@ -213,8 +243,15 @@ int qhp_set_incident(qhp_ctx *ctx, const qhp_wave *waves, int32_t n_rhs, int32_t
 /* One marching step (Sec. IV-B): y_i = T_0^{-1}(r_i - sum_{k=1}^{K} T_k y_{i-k})
  * and j_i = P^{LH} y_i + dt~^{-1} P^Sigma (y_i - y_{i-1}) (eq. post_processing).
  * j_out: device [ne][n_rhs] FP64 or NULL.  QHP_EUNSTABLE on a non-finite
- * value; QHP_ESTATE past n_steps. */
+ * value or a growth trip; QHP_ESTATE past n_steps. */
 int qhp_step(qhp_ctx *ctx, double *j_out);
+
+/* Growth trip of qhp_step / qhp_run: the march stops with QHP_EUNSTABLE when
+ * an entry of y_i exceeds limit * max_{k <= i} max |r_k| (the largest
+ * right-hand side so far; a stable march keeps |y_i| within a small multiple
+ * of it, Sec. V-A).  limit = 0 turns the check off; default 1e8.  QHP_EINVAL
+ * for a negative or non-finite limit.  Applies from the next step. */
+int qhp_set_growth_limit(qhp_ctx *ctx, double limit);
 
 /* n_steps marching steps.  j_hist / y_hist: device [n_steps][ne][n_rhs] FP64
  * or NULL (step i of the call at index i). */
@@ -302,7 +339,11 @@ void qhp_destroy(qhp_ctx *ctx);
  * qhp_batch_create: ctxs[i] must all have had qhp_set_incident, share the
  *   device, precision (F64, F32 or F32A) and n_rhs (1, 2, 4 or 8); each
  *   continues from its current step.  The T_0 product uses the FP64 inverse.
- *   The batch keeps the context pointers: destroy it before them.  The tile
+ *   The batch keeps the context pointers: destroy it before them.  While a
+ *   batch holds a context, qhp_set_incident and qhp_set_precision on it return
+ *   QHP_ESTATE (they would move the buffers the batch works on); the context
+ *   may still march on its own with qhp_step / qhp_run, and the next
+ *   qhp_batch_run continues from where it stands.  The tile
  *   shape of the history product is autotuned on the batch's own blocks.
  * qhp_batch_create_variant: the same with the history tile shape fixed to
  *   variant in [0, qhp_batch_variants(precision, n_rhs)); -1 autotunes.
@@ -313,7 +354,8 @@ void qhp_destroy(qhp_ctx *ctx);
  * qhp_batch_history_variant: the tile shape the batch uses (-1 for NULL).
  * qhp_batch_run: n_steps steps of every scatterer; j_hists is a host array
  *   of n device pointers [n_steps][ne_i][n_rhs] FP64 (or NULL entries / a NULL
- *   array for no output).  QHP_EUNSTABLE on a non-finite value.
+ *   array for no output).  QHP_EUNSTABLE on a non-finite value (the growth
+ *   trip of qhp_set_growth_limit applies to the contexts' own steps only).
  * qhp_batch_step_times: the per-step times (ms, HIP events around each graph
  *   replay) of the last run, into host ms[n]. */
 typedef struct qhp_batch qhp_batch;

@@ -33,10 +33,45 @@ class QhpError(RuntimeError):
         self.code = code
 
 
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
 class _Params(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("eta_c", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("solver", ctypes.c_int32), ("n_psi", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("dev_alloc", _ALLOC_FN), ("dev_free", _FREE_FN),
+                ("alloc_user", ctypes.c_void_p)]
+
+
+class TorchAllocator:
+    """The dev_alloc / dev_free hook of qhp_params backed by PyTorch's caching
+    allocator: the library's device buffers become uint8 tensors held here
+    until the library frees them."""
+
+    def __init__(self, device: int):
+        self.device = device
+        self.live = {}
+        self.calls = {"alloc": 0, "free": 0}
+        self.alloc_fn = _ALLOC_FN(self._alloc)
+        self.free_fn = _FREE_FN(self._free)
+
+    def _alloc(self, nbytes, user):
+        import torch
+        try:
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda:%d" % self.device)
+        except RuntimeError:
+            return None
+        self.live[t.data_ptr()] = t
+        self.calls["alloc"] += 1
+        return t.data_ptr()
+
+    def _free(self, ptr, user):
+        self.live.pop(ptr, None)
+        self.calls["free"] += 1
+
+    def bytes_held(self) -> int:
+        return sum(t.numel() for t in self.live.values())
 
 
 class _Wave(ctypes.Structure):
@@ -67,7 +102,7 @@ EXPORTS = ["qhp_create", "qhp_mesh", "qhp_assemble", "qhp_set_precision", "qhp_s
            "qhp_destroy", "qhp_release_assembly", "qhp_set_gmres", "qhp_gmres_stats", "qhp_gmres_reset", "qhp_mlp_create",
            "qhp_mlp_dims", "qhp_mlp_set_params", "qhp_mlp_get_params", "qhp_mlp_features", "qhp_mlp_guess", "qhp_mlp_reconstruct",
            "qhp_mlp_forward", "qhp_mlp_loss_grad", "qhp_mlp_adam", "qhp_mlp_train", "qhp_attach_mlp",
-           "qhp_mlp_last_error", "qhp_mlp_destroy"]
+           "qhp_mlp_last_error", "qhp_mlp_destroy", "qhp_check_mesh", "qhp_set_growth_limit"]
 _NO_RC = ("qhp_last_error", "qhp_destroy", "qhp_batch_last_error", "qhp_batch_destroy", "qhp_mlp_last_error",
           "qhp_mlp_destroy")
 
@@ -138,6 +173,8 @@ def lib():
         L.qhp_mlp_last_error.restype = ctypes.c_char_p
         L.qhp_mlp_destroy.argtypes = [vp]
         L.qhp_mlp_destroy.restype = None
+        L.qhp_check_mesh.argtypes = [vp, i64, vp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.c_char_p, i64]
+        L.qhp_set_growth_limit.argtypes = [vp, dbl]
         for name in EXPORTS:
             if name not in _NO_RC:
                 getattr(L, name).restype = ctypes.c_int
@@ -169,12 +206,19 @@ class Solver:
     """One scatterer and time step on one GPU (see include/qhp.h)."""
 
     def __init__(self, dt: float, precision: str = "f64", solver: str = "lu", n_psi: int = 10,
-                 eta_c: float = 1.0, device: int = 0, stream=None):
+                 eta_c: float = 1.0, device: int = 0, stream=None, allocator: str = "hip"):
+        """allocator: "hip" (the library's hipMalloc) or "torch" (PyTorch's
+        caching allocator through the dev_alloc / dev_free hook)."""
         import torch
         self.L = lib()
         torch.cuda.set_device(device)
+        self.allocator = TorchAllocator(device) if allocator == "torch" else None
+        if allocator not in ("hip", "torch"):
+            raise ValueError("allocator must be 'hip' or 'torch'")
         p = _Params(float(dt), float(eta_c), PRECISIONS[precision], SOLVERS[solver], int(n_psi),
                     int(device), stream if stream is not None else _stream())
+        if self.allocator is not None:
+            p.dev_alloc, p.dev_free = self.allocator.alloc_fn, self.allocator.free_fn
         self._p = p
         h = ctypes.c_void_p()
         self._check(self.L.qhp_create(ctypes.byref(p), ctypes.byref(h)), None)
@@ -211,6 +255,10 @@ class Solver:
         c1, c2 = ctypes.c_double(), ctypes.c_double()
         self._check(self.L.qhp_t0_condition(self.h, int(power_iters), ctypes.byref(c1), ctypes.byref(c2)))
         return float(c1.value), float(c2.value)
+
+    def set_growth_limit(self, limit: float):
+        """growth trip of the march (qhp_set_growth_limit; 0 turns it off)"""
+        self._check(self.L.qhp_set_growth_limit(self.h, float(limit)))
 
     def profile(self, enable=True):
         self._check(self.L.qhp_profile(self.h, int(bool(enable))))
@@ -282,6 +330,18 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def check_mesh(xyz, tri):
+    """(code, n_edges, n_harmonic, message) of qhp_check_mesh: host-only
+    validation of a closed, connected, orientable surface mesh."""
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    ne, nh = ctypes.c_int64(-1), ctypes.c_int64(-1)
+    msg = ctypes.create_string_buffer(256)
+    rc = lib().qhp_check_mesh(xyz.ctypes.data, len(xyz), tri.ctypes.data, len(tri), ctypes.byref(ne),
+                              ctypes.byref(nh), msg, 256)
+    return rc, ne.value, nh.value, msg.value.decode()
 
 
 def history_variants(precision: str, nrhs: int) -> int:

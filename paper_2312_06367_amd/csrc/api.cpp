@@ -73,7 +73,8 @@ extern "C" int qhp_create(const qhp_params *params, qhp_ctx **out)
 {
     if (!params || !out) return QHP_EINVAL;
     if (!(params->dt > 0.0) || params->precision < QHP_F64 || params->precision > QHP_I8X4 ||
-        params->solver < QHP_SOLVE_LU || params->solver > QHP_SOLVE_INV || params->n_psi > 32)
+        params->solver < QHP_SOLVE_LU || params->solver > QHP_SOLVE_INV || params->n_psi > 32 ||
+        (!params->dev_alloc) != (!params->dev_free))
         return QHP_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || params->device < 0 || params->device >= ndev)
@@ -83,6 +84,7 @@ extern "C" int qhp_create(const qhp_params *params, qhp_ctx **out)
     if (c->p.n_psi <= 0) c->p.n_psi = 10;
     if (!(c->p.eta_c > 0.0)) c->p.eta_c = 1.0;
     c->s = (hipStream_t)params->stream;
+    c->allocator = qhp::Allocator{params->dev_alloc, params->dev_free, params->alloc_user};
     const char *vb = std::getenv("QHP_VERBOSE");
     c->verbose = vb && vb[0] && vb[0] != '0';
     if (hipSetDevice(params->device) != hipSuccess) {
@@ -103,6 +105,43 @@ extern "C" void qhp_destroy(qhp_ctx *ctx)
 }
 
 extern "C" const char *qhp_last_error(const qhp_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+extern "C" int qhp_check_mesh(const double *xyz, int64_t nv, const int32_t *tri, int64_t nc, int64_t *n_edges,
+                              int64_t *n_harmonic, char *msg, int64_t msg_len)
+{
+    auto say = [&](const std::string &t) {
+        if (msg && msg_len > 0) {
+            const size_t n = std::min<size_t>(t.size(), (size_t)msg_len - 1);
+            std::memcpy(msg, t.data(), n);
+            msg[n] = 0;
+        }
+    };
+    if (!xyz || !tri || nv < 0 || nc < 0) {
+        say("null or negative argument");
+        return QHP_EINVAL;
+    }
+    try {
+        qhp::Mesh m;
+        std::string err;
+        const int rc = qhp::build_mesh(xyz, nv, tri, nc, m, err);
+        if (rc != QHP_OK) {
+            say(err);
+            return rc;
+        }
+        for (int64_t v = 0; v < m.nv; ++v)
+            if (m.valence[v] > qhp::kMaxValence) {
+                say("vertex valence above the supported maximum");
+                return QHP_EMESH;
+            }
+        if (n_edges) *n_edges = m.ne;
+        if (n_harmonic) *n_harmonic = m.n_harmonic;
+        say("");
+        return QHP_OK;
+    } catch (const std::bad_alloc &) {
+        say("host allocation failed");
+        return QHP_ENOMEM;
+    }
+}
 
 extern "C" int qhp_keep_raw(qhp_ctx *ctx, int32_t keep)
 {
@@ -224,6 +263,7 @@ static float store_lag(hipStream_t s, int64_t ne, int64_t ld, const double *T, i
 
 extern "C" int qhp_assemble(qhp_ctx *ctx)
 {
+    QHP_ALLOC_SCOPE(ctx);
     if (!ctx) return QHP_EINVAL;
     if (ctx->state != 1) return guard(ctx, QHP_ESTATE, ctx->state == 0 ? "no mesh" : "already assembled");
     API_TRY
@@ -418,8 +458,8 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
                     c->scales[k - 1] = store_lag(s, ne, c->ld, Tt.as<double>(), ne, carry.as<double>(), prec, amax,
                                                  (char *)c->slabs.p + (size_t)(k - 1) * blk);
                 }
-                std::swap(Ap.p, Ak.p);
-                std::swap(Cp.p, Ck.p);
+                Ap.swap(Ak);
+                Cp.swap(Ck);
             }
             hip_check(hipStreamSynchronize(s), "lag blocks");
             c->stage("lag combination + slab GEMMs");
@@ -608,9 +648,11 @@ static void autotune(qhp_ctx *c)
 
 extern "C" int qhp_set_incident(qhp_ctx *ctx, const qhp_wave *waves, int32_t n_rhs, int32_t n_steps)
 {
+    QHP_ALLOC_SCOPE(ctx);
     if (!ctx) return QHP_EINVAL;
     if (ctx->state < 2) return guard(ctx, QHP_ESTATE, "assemble first");
     if (ctx->released) return guard(ctx, QHP_ESTATE, "assembly operators were released");
+    if (ctx->batch_refs > 0) return guard(ctx, QHP_ESTATE, "a live batch holds the context's march buffers");
     if (!waves || n_rhs < 1 || n_steps < 1) return guard(ctx, QHP_EINVAL, "bad waves / n_rhs / n_steps");
     if (ctx->p.precision == QHP_F32A && n_rhs != 1 && n_rhs != 2 && n_rhs != 4 && n_rhs != 8)
         return guard(ctx, QHP_EINVAL, "QHP_F32A takes 1, 2, 4 or 8 right-hand sides");
@@ -656,6 +698,14 @@ extern "C" int qhp_set_incident(qhp_ctx *ctx, const qhp_wave *waves, int32_t n_r
                           2 * ne, 0.0, R.as<double>(), ne);
             qhp::launch_permute_rhs(s, ne, ns, n_rhs, R.as<double>(), c->rhs.as<double>() + s0 * ne * n_rhs);
         }
+        // bound of the growth trip: running maximum over the steps of max |r_k|
+        std::vector<double> pk(n_steps);
+        c->rpk.alloc(sizeof(double) * n_steps);
+        qhp::launch_step_absmax(s, n_steps, ne * n_rhs, c->rhs.as<double>(), c->rpk.as<double>());
+        hip_check(hipMemcpyAsync(pk.data(), c->rpk.p, sizeof(double) * n_steps, hipMemcpyDeviceToHost, s), "bound");
+        hip_check(hipStreamSynchronize(s), "right-hand sides");
+        for (int64_t k = 1; k < n_steps; ++k) pk[k] = std::max(pk[k], pk[k - 1]);
+        upload(c->rpk, pk, s);
         hip_check(hipStreamSynchronize(s), "right-hand sides");
     }
     const int64_t K = c->K, ld = c->ld;
@@ -787,7 +837,8 @@ static void do_step(qhp_ctx *c, double *j_out, double *y_out)
                                  (int64_t)(c->partial.bytes / sizeof(double)));
         qhp::launch_post_b(s, ne, nr, c->args.cells, y, c->zc.as<double>(), j_out);
     }
-    qhp::launch_store_y(s, ne * nr, y, slot64, slot32, y_out, c->errflag.as<int>());
+    qhp::launch_store_y(s, ne * nr, y, slot64, slot32, y_out, c->errflag.as<int>(), c->rpk.as<double>() + (i - 1),
+                        c->growth_limit);
     if (c->ring64t.p) qhp::launch_store_transposed(s, ne, nr, ld, y, c->ring64t.as<double>() + slot * nr * ld);
     if (c->ringb.p) {
         const int64_t nrp = qhp::ring_bf16_rows(nr);
@@ -823,6 +874,10 @@ static int finish_run(qhp_ctx *c)
         c->broken = true;
         return guard(c, QHP_EUNSTABLE, "non-finite value in the marching solution");
     }
+    if (e == 3) {
+        c->broken = true;
+        return guard(c, QHP_EUNSTABLE, "growth trip: |y_i| exceeded the growth limit times the largest |r_k| so far");
+    }
     if (e == 1) {
         c->broken = true;
         return guard(c, QHP_EDEVICE, "triangular solve wait exceeded its bound");
@@ -832,6 +887,7 @@ static int finish_run(qhp_ctx *c)
 
 extern "C" int qhp_step(qhp_ctx *ctx, double *j_out)
 {
+    QHP_ALLOC_SCOPE(ctx);
     if (!ctx) return QHP_EINVAL;
     if (ctx->state != 3 || ctx->broken) return guard(ctx, QHP_ESTATE, "set_incident first");
     if (ctx->step >= ctx->n_steps) return guard(ctx, QHP_ESTATE, "no right-hand side left");
@@ -843,6 +899,7 @@ extern "C" int qhp_step(qhp_ctx *ctx, double *j_out)
 
 extern "C" int qhp_run(qhp_ctx *ctx, int32_t n_steps, double *j_hist, double *y_hist)
 {
+    QHP_ALLOC_SCOPE(ctx);
     if (!ctx) return QHP_EINVAL;
     if (ctx->state != 3 || ctx->broken) return guard(ctx, QHP_ESTATE, "set_incident first");
     if (n_steps < 0 || ctx->step + n_steps > ctx->n_steps) return guard(ctx, QHP_EINVAL, "past the last right-hand side");
@@ -878,6 +935,7 @@ extern "C" int qhp_release_assembly(qhp_ctx *ctx)
 
 extern "C" int qhp_t0_condition(qhp_ctx *ctx, int32_t power_iters, double *cond1, double *cond2)
 {
+    QHP_ALLOC_SCOPE(ctx);
     if (!ctx || (!cond1 && !cond2) || (cond2 && power_iters < 1)) return QHP_EINVAL;
     if (ctx->state < 2) return guard(ctx, QHP_ESTATE, "assemble first");
     if (!ctx->T0raw.p || !ctx->Tinv.p) return guard(ctx, QHP_ESTATE, "T_0 or its inverse was released");
@@ -924,6 +982,14 @@ extern "C" int qhp_set_solver(qhp_ctx *ctx, int32_t solver)
     return QHP_OK;
 }
 
+extern "C" int qhp_set_growth_limit(qhp_ctx *ctx, double limit)
+{
+    if (!ctx) return QHP_EINVAL;
+    if (!(limit >= 0.0) || !std::isfinite(limit)) return guard(ctx, QHP_EINVAL, "growth limit must be finite and >= 0");
+    ctx->growth_limit = limit;
+    return QHP_OK;
+}
+
 extern "C" int qhp_profile(qhp_ctx *ctx, int32_t enable)
 {
     if (!ctx) return QHP_EINVAL;
@@ -943,9 +1009,11 @@ extern "C" int qhp_hist_time(qhp_ctx *ctx, double *ms_total, int64_t *launches)
 
 extern "C" int qhp_set_precision(qhp_ctx *ctx, int32_t precision)
 {
+    QHP_ALLOC_SCOPE(ctx);
     if (!ctx) return QHP_EINVAL;
     if (ctx->state < 2) return guard(ctx, QHP_ESTATE, "assemble first");
     if (ctx->released) return guard(ctx, QHP_ESTATE, "assembly operators were released");
+    if (ctx->batch_refs > 0) return guard(ctx, QHP_ESTATE, "a live batch holds the context's blocks");
     if (precision == ctx->p.precision) return QHP_OK;
     const bool fp32_pair = (precision == QHP_F32 || precision == QHP_F32A) &&
                            (ctx->p.precision == QHP_F32 || ctx->p.precision == QHP_F32A);
@@ -974,8 +1042,7 @@ extern "C" int qhp_set_precision(qhp_ctx *ctx, int32_t precision)
         ctx->scales[k] = store_lag(s, ne, ld, ctx->slabs.as<double>() + k * per, ld, carry.as<double>(), precision, amax,
                                    (char *)out.p + blk * k);
     hip_check(hipStreamSynchronize(s), "convert slabs");
-    std::swap(ctx->slabs.p, out.p);
-    std::swap(ctx->slabs.bytes, out.bytes);
+    ctx->slabs.swap(out);
     upload(ctx->scales_d, ctx->scales, s);
     ctx->p.precision = precision;
     ctx->ring32.release();
@@ -1021,6 +1088,7 @@ extern "C" int qhp_edges(const qhp_ctx *ctx, int32_t *edges, int32_t *cells)
 extern "C" int qhp_get_matrix(const qhp_ctx *cc, int32_t which, int32_t k, double *out)
 {
     qhp_ctx *ctx = const_cast<qhp_ctx *>(cc);
+    QHP_ALLOC_SCOPE(ctx);
     if (!ctx || !out) return QHP_EINVAL;
     if (ctx->state < 2) return guard(ctx, QHP_ESTATE, "assemble first");
     API_TRY
@@ -1080,9 +1148,10 @@ extern "C" int qhp_history_variants(int32_t precision, int64_t nrhs)
     return nrhs == 1 ? qhp::gemv_variant_count() : 1;
 }
 
-extern "C" int qhp_history_sum_variant(void *stream, int32_t precision, int64_t ne, int64_t ld, int64_t nrhs,
-                                       int64_t kmax, const void *slabs, const float *scales, const void *ring,
-                                       int64_t n_slots, int64_t head, const double *r, double *b, int32_t variant)
+// argument checks shared by the caller-buffer history sums
+bool qhp::history_args_valid(int32_t precision, int64_t ne, int64_t ld, int64_t nrhs, int64_t kmax, const void *slabs,
+                             const float *scales, const void *ring, int64_t n_slots, int64_t head, const double *r,
+                             double *b, int32_t variant)
 {
     if (precision < QHP_F64 || precision > QHP_I8X4 || ne < 1 || ld < ne || ld % 8 != 0 || nrhs < 1 || kmax < 0 ||
         (precision == QHP_F32A && nrhs != 1) || (precision == QHP_BF16X2 && (nrhs < 2 || ld % 32 != 0)) ||
@@ -1090,12 +1159,24 @@ extern "C" int qhp_history_sum_variant(void *stream, int32_t precision, int64_t 
         (precision == QHP_BF16 && nrhs > 1 && ld % 32 != 0) ||
         n_slots < kmax || head < 0 || (kmax > 0 && (!slabs || !ring)) || !r || !b ||
         variant < -1 || variant >= qhp_history_variants(precision, nrhs))
-        return QHP_EINVAL;
-    if (precision == QHP_BF16 && !scales) return QHP_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
+        return false;
+    return !(precision == QHP_BF16 && !scales);
+}
+
+int qhp::history_split_count(int32_t precision, int64_t ne, int64_t nrhs, int64_t kmax, int32_t variant)
+{
     const int64_t km = std::max<int64_t>(kmax, 1);
-    int nsplit = precision == QHP_I8X4 ? qhp::i8_hist_splits(ne, km, nrhs, variant)
-                                       : qhp::hist_splits(ne, km, nrhs, precision);
+    return precision == QHP_I8X4 ? qhp::i8_hist_splits(ne, km, nrhs, variant) : qhp::hist_splits(ne, km, nrhs, precision);
+}
+
+extern "C" int qhp_history_sum_variant(void *stream, int32_t precision, int64_t ne, int64_t ld, int64_t nrhs,
+                                       int64_t kmax, const void *slabs, const float *scales, const void *ring,
+                                       int64_t n_slots, int64_t head, const double *r, double *b, int32_t variant)
+{
+    if (!qhp::history_args_valid(precision, ne, ld, nrhs, kmax, slabs, scales, ring, n_slots, head, r, b, variant))
+        return QHP_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const int nsplit = qhp::history_split_count(precision, ne, nrhs, kmax, variant);
     void *partial = nullptr;
     if (hipMalloc(&partial, sizeof(double) * nsplit * ne * nrhs) != hipSuccess) {
         (void)hipGetLastError();
@@ -1131,11 +1212,14 @@ struct qhp_batch {
     std::vector<DBuf> part_h, part_s, part_p, bvec, yvec, sv, zc, tinv, lsp, ringt;
     int64_t tiles_h = 0, tiles_s = 0, tiles_p = 0, max_ne = 0, max_nc = 0;
     std::vector<qhp::GPost> post_host;
+    std::vector<int64_t> synced;  // each context's step when the batch's device state last matched it
+    std::vector<qhp_ctx *> held;  // contexts whose batch_refs this batch counts
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     std::vector<float> step_ms;
     ~qhp_batch()
     {
+        for (qhp_ctx *c : held) c->batch_refs -= 1;
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (s) (void)hipStreamDestroy(s);
@@ -1210,11 +1294,22 @@ static void build_batch(qhp_batch *b, int variant)
         g.x = c->ring32.p ? c->ring32.p : c->ring64.p;
         g.x_slot_stride = ld * nr; g.n_slots = K; g.head = dhead; g.x_ld = 0;
         const bool t64 = trans && b->kind == qhp::GK_F32A;
-        if (trans) {  // ring kept transposed as well (FP32 or, for FP64 y, FP64), from the current state
-            b->ringt[i].alloc((t64 ? sizeof(double) : sizeof(float)) * K * nr * ld);
-            if (t64) qhp::launch_ring_transpose(s, K, ld, nr, c->ring64.as<double>(), b->ringt[i].as<double>());
-            else qhp::launch_ring_transpose(s, K, ld, nr, c->ring32.as<float>(), b->ringt[i].as<float>());
-            g.x = b->ringt[i].p;
+        // ring kept transposed as well (FP32 or, for FP64 y, FP64).  A context
+        // that marches FP32 blocks with FP64 y on several right-hand sides
+        // keeps such a ring itself: the batch then reads and writes that one, so
+        // the context's own steps after the batch see the history the batch made.
+        double *ring_t64 = nullptr;
+        if (trans) {
+            if (t64 && c->ring64t.p) {
+                ring_t64 = c->ring64t.as<double>();
+                g.x = c->ring64t.p;
+            } else {  // a private copy, from the current state
+                b->ringt[i].alloc((t64 ? sizeof(double) : sizeof(float)) * K * nr * ld);
+                if (t64) qhp::launch_ring_transpose(s, K, ld, nr, c->ring64.as<double>(), b->ringt[i].as<double>());
+                else qhp::launch_ring_transpose(s, K, ld, nr, c->ring32.as<float>(), b->ringt[i].as<float>());
+                if (t64) ring_t64 = b->ringt[i].as<double>();
+                g.x = b->ringt[i].p;
+            }
             g.x_ld = ld;
         }
         g.partial = b->part_h[i].p;
@@ -1236,7 +1331,7 @@ static void build_batch(qhp_batch *b, int variant)
         fs[i] = qhp::GFin{b->part_s[i].p, 1, ne * nr, nullptr, dstep, b->yvec[i].as<double>()};
         gs[i] = qhp::GStore{b->yvec[i].as<double>(), c->ring64.as<double>(), c->ring32.as<float>(), ld * nr, K,
                             ne * nr, dhead, b->errflag.as<int>(), (trans && !t64) ? b->ringt[i].as<float>() : nullptr,
-                            ld, nr, t64 ? b->ringt[i].as<double>() : nullptr};
+                            ld, nr, ring_t64};
         // post-processing product z = L_Sigma^+ s (padded copy)
         const int64_t ldc = (nc + 7) / 8 * 8;
         b->lsp[i].alloc(sizeof(double) * nc * ldc);
@@ -1332,6 +1427,7 @@ static void build_batch(qhp_batch *b, int variant)
     upload(b->st, gs, s);
     upload(b->po, b->post_host, s);
     upload(b->nslots, nsl, s);
+    b->synced.assign(st0.begin(), st0.end());
     hip_check(hipStreamSynchronize(s), "batch set-up");
 }
 
@@ -1376,6 +1472,7 @@ extern "C" int qhp_batch_create(qhp_ctx *const *ctxs, int32_t n, qhp_batch **out
 
 extern "C" int qhp_batch_create_variant(qhp_ctx *const *ctxs, int32_t n, int32_t variant, qhp_batch **out)
 {
+    QHP_ALLOC_SCOPE((ctxs && n > 0) ? ctxs[0] : nullptr);
     if (!ctxs || n < 1 || !out) return QHP_EINVAL;
     qhp_ctx *c0 = ctxs[0];
     for (int i = 0; i < n; ++i) {
@@ -1410,17 +1507,38 @@ extern "C" int qhp_batch_create_variant(qhp_ctx *const *ctxs, int32_t n, int32_t
         delete b;
         return guard(c0, f.code, f.msg);
     }
+    for (qhp_ctx *c : b->ctxs) c->batch_refs += 1;
+    b->held = b->ctxs;
     *out = b;
     return QHP_OK;
 }
 
 extern "C" int qhp_batch_run(qhp_batch *b, int32_t n_steps, double *const *j_hists)
 {
+    QHP_ALLOC_SCOPE((b && !b->ctxs.empty()) ? b->ctxs[0] : nullptr);
     if (!b || n_steps < 0) return QHP_EINVAL;
     for (qhp_ctx *c : b->ctxs)
         if (c->step + n_steps > c->n_steps) return bguard(b, QHP_EINVAL, "past the last right-hand side");
     try {
         hipStream_t s = b->s;
+        // contexts that marched on their own since the batch last ran: bring
+        // the device step and ring head, and any private transposed ring, up to date
+        for (int i = 0; i < b->n; ++i) {
+            qhp_ctx *c = b->ctxs[i];
+            if (c->step == b->synced[i]) continue;
+            hip_check(hipStreamSynchronize(c->s), "sync");
+            const int64_t st = c->step, hd = c->head;
+            hip_check(hipMemcpyAsync(b->steps.as<int64_t>() + i, &st, sizeof(int64_t), hipMemcpyHostToDevice, s), "state");
+            hip_check(hipMemcpyAsync(b->heads.as<int64_t>() + i, &hd, sizeof(int64_t), hipMemcpyHostToDevice, s), "state");
+            if (b->ringt[i].p) {
+                if (b->kind == qhp::GK_F32A)
+                    qhp::launch_ring_transpose(s, c->K, c->ld, b->nrhs, c->ring64.as<double>(), b->ringt[i].as<double>());
+                else
+                    qhp::launch_ring_transpose(s, c->K, c->ld, b->nrhs, c->ring32.as<float>(), b->ringt[i].as<float>());
+            }
+            hip_check(hipStreamSynchronize(s), "state");
+            b->synced[i] = st;
+        }
         // per-run output pointers: step s of the context writes j_hists[i] + (s - step0) * ne * nrhs
         for (int i = 0; i < b->n; ++i) {
             qhp_ctx *c = b->ctxs[i];
@@ -1446,6 +1564,7 @@ extern "C" int qhp_batch_run(qhp_batch *b, int32_t n_steps, double *const *j_his
         for (int i = 0; i < b->n; ++i) {
             b->ctxs[i]->step += n_steps;
             b->ctxs[i]->head = heads[i];
+            b->synced[i] = b->ctxs[i]->step;
         }
         if (e) return bguard(b, QHP_EUNSTABLE, "non-finite value in a batch member");
     } catch (const Fail &f) {

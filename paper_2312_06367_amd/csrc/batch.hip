@@ -435,6 +435,8 @@ __global__ __launch_bounds__(256, MINW) void k_grouped_mrhs_d(const GDesc *__res
                     __builtin_amdgcn_s_barrier();
                 }
             }
+            // the copies issued past the last step land before the wave ends: vmcnt(0)
+            __builtin_amdgcn_s_waitcnt((7 << 4) | (15 << 8));
         }
 #pragma unroll
         for (int rr = 0; rr < RW; ++rr)

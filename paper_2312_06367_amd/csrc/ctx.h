@@ -26,27 +26,67 @@ inline void hip_check(hipError_t e, const char *what)
                                     std::string(what) + ": " + hipGetErrorString(e)};
 }
 
+// Caller-supplied device allocator (qhp_params.dev_alloc / dev_free).  An
+// entry point that works for a context makes its allocator current for the
+// calling thread (AllocScope); every DBuf allocated meanwhile takes its memory
+// from it and remembers it, so the buffer is returned to the same allocator
+// whenever it is released.  Without a current allocator: hipMalloc / hipFree.
+struct Allocator {
+    void *(*alloc)(size_t, void *) = nullptr;
+    void (*free)(void *, void *) = nullptr;
+    void *user = nullptr;
+};
+inline thread_local const Allocator *tl_allocator = nullptr;
+struct AllocScope {
+    const Allocator *prev;
+    explicit AllocScope(const Allocator *a) : prev(tl_allocator) { tl_allocator = (a && a->alloc) ? a : nullptr; }
+    ~AllocScope() { tl_allocator = prev; }
+};
+
 // device allocation owned by a context
 struct DBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    Allocator owner{};  // where p came from (alloc == nullptr: hipMalloc)
     void alloc(size_t n)
     {
         release();
         if (n == 0) n = 8;
-        hipError_t e = hipMalloc(&p, n);
-        if (e != hipSuccess) {
-            p = nullptr;
-            (void)hipGetLastError();
-            throw Fail{QHP_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed"};
+        if (tl_allocator) {
+            p = tl_allocator->alloc(n, tl_allocator->user);
+            if (!p) throw Fail{QHP_ENOMEM, "caller allocator refused " + std::to_string(n) + " bytes"};
+            owner = *tl_allocator;
+        } else {
+            hipError_t e = hipMalloc(&p, n);
+            if (e != hipSuccess) {
+                p = nullptr;
+                (void)hipGetLastError();
+                throw Fail{QHP_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed"};
+            }
+            owner = Allocator{};
         }
         bytes = n;
     }
     void release()
     {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (owner.alloc) {
+                // hipFree waits for the device; a caller allocator may not, so wait here
+                (void)hipDeviceSynchronize();
+                owner.free(p, owner.user);
+            } else {
+                (void)hipFree(p);
+            }
+        }
         p = nullptr;
         bytes = 0;
+        owner = Allocator{};
+    }
+    void swap(DBuf &o)
+    {
+        std::swap(p, o.p);
+        std::swap(bytes, o.bytes);
+        std::swap(owner, o.owner);
     }
     template <class T>
     T *as() const { return (T *)p; }
@@ -68,6 +108,7 @@ struct qhp_mlp;
 
 struct qhp_ctx {
     qhp_params p{};
+    qhp::Allocator allocator{};  // from p.dev_alloc / dev_free / alloc_user
     hipStream_t s = nullptr;
     int state = 0;  // 0 created, 1 meshed, 2 assembled, 3 incident set
     std::string err;
@@ -127,6 +168,10 @@ struct qhp_ctx {
     int64_t ls_nh = -1, ls_cap = 0;
     qhp_mlp *mlp = nullptr;
     bool released = false;  // FP64 assembly operators freed (qhp_release_assembly)
+    int batch_refs = 0;     // live batches holding this context (their descriptors point into its buffers)
+    // growth trip of the march: |y_i| > growth_limit * max_{k <= i} max |r_k| (0: off)
+    double growth_limit = 1e8;
+    qhp::DBuf rpk;  // [n_steps] running maximum of max |r_k|
     qhp::DBuf feat;  // ring of the last four feature vectors [4][nf]
     int64_t feat_n = 0;
     ~qhp_ctx()
@@ -134,6 +179,9 @@ struct qhp_ctx {
         if (gm_host) (void)hipHostFree(gm_host);
     }
 };
+
+// make the context's caller allocator (if any) current for this entry point
+#define QHP_ALLOC_SCOPE(c) qhp::AllocScope qhp_alloc_scope_((c) ? &(c)->allocator : nullptr)
 
 // record msg as the context's last error and return code
 int guard(qhp_ctx *ctx, int code, const std::string &msg);

@@ -525,6 +525,8 @@ __global__ __launch_bounds__(64 * WR * WN, 1) void k_hist_i8d(int64_t ne, int64_
             __builtin_amdgcn_s_barrier();
         }
     }
+    // the copies issued past the last step land before the wave ends: vmcnt(0)
+    __builtin_amdgcn_s_waitcnt((7 << 4) | (15 << 8));
 }
 
 // variants of the int8 history kernel (autotuned): wave tile, work-group

@@ -227,6 +227,7 @@ static void mlp_guess(qhp_mlp *m, const double *f1, const double *f2, const doub
 
 extern "C" int qhp_mlp_create(qhp_ctx *ctx, int32_t hidden, uint64_t seed, qhp_mlp **out)
 {
+    QHP_ALLOC_SCOPE(ctx);
     if (!ctx || !out || hidden < 1) return QHP_EINVAL;
     if (ctx->state < 2) return guard(ctx, QHP_ESTATE, "assemble first");
     qhp_mlp *m = new qhp_mlp();
@@ -297,6 +298,7 @@ extern "C" int qhp_mlp_dims(const qhp_mlp *m, int64_t *n_features, int64_t *n_pa
 
 extern "C" int qhp_mlp_set_params(qhp_mlp *m, const float *params)
 {
+    QHP_ALLOC_SCOPE(m ? m->ctx : nullptr);
     if (!m || !params) return QHP_EINVAL;
     try {
         hip_check(hipMemcpyAsync(m->P.p, params, sizeof(float) * m->nparam, hipMemcpyHostToDevice, m->s), "params");
@@ -322,6 +324,7 @@ extern "C" int qhp_mlp_get_params(const qhp_mlp *m, float *params)
 
 extern "C" int qhp_mlp_forward(qhp_mlp *m, const float *x, int32_t batch, float *out)
 {
+    QHP_ALLOC_SCOPE(m ? m->ctx : nullptr);
     if (!m || !x || !out || batch < 1) return QHP_EINVAL;
     try {
         mlp_reserve(m, batch);
@@ -337,6 +340,7 @@ extern "C" int qhp_mlp_forward(qhp_mlp *m, const float *x, int32_t batch, float 
 extern "C" int qhp_mlp_loss_grad(qhp_mlp *m, const float *x, const float *t, int32_t batch, double *loss,
                                  float *grad)
 {
+    QHP_ALLOC_SCOPE(m ? m->ctx : nullptr);
     if (!m || !x || !t || batch < 1) return QHP_EINVAL;
     try {
         mlp_reserve(m, batch);
@@ -355,6 +359,7 @@ extern "C" int qhp_mlp_loss_grad(qhp_mlp *m, const float *x, const float *t, int
 
 extern "C" int qhp_mlp_adam(qhp_mlp *m, double lr, double beta1, double beta2, double eps)
 {
+    QHP_ALLOC_SCOPE(m ? m->ctx : nullptr);
     if (!m || !(lr > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) || !(eps >= 0.0))
         return QHP_EINVAL;
     mlp_adam(m, lr, beta1, beta2, eps);
@@ -363,6 +368,7 @@ extern "C" int qhp_mlp_adam(qhp_mlp *m, double lr, double beta1, double beta2, d
 
 extern "C" int qhp_mlp_guess(qhp_mlp *m, const double *f, double *g)
 {
+    QHP_ALLOC_SCOPE(m ? m->ctx : nullptr);
     if (!m || !f || !g) return QHP_EINVAL;
     try {
         const int64_t nf = m->nf;
@@ -376,6 +382,7 @@ extern "C" int qhp_mlp_guess(qhp_mlp *m, const double *f, double *g)
 
 extern "C" int qhp_mlp_features(qhp_mlp *m, const double *y, int64_t n, double *f)
 {
+    QHP_ALLOC_SCOPE(m ? m->ctx : nullptr);
     if (!m || !y || !f || n < 1) return QHP_EINVAL;
     try {
         qhp::loopstar_features(m->ctx, y, n, m->ctx->mesh.ne, f, m->nf);
@@ -388,6 +395,7 @@ extern "C" int qhp_mlp_features(qhp_mlp *m, const double *y, int64_t n, double *
 
 extern "C" int qhp_mlp_reconstruct(qhp_mlp *m, const double *f, int64_t n, double *y)
 {
+    QHP_ALLOC_SCOPE(m ? m->ctx : nullptr);
     if (!m || !y || !f || n < 1) return QHP_EINVAL;
     try {
         qhp::loopstar_reconstruct(m->ctx, f, n, m->nf, y, m->ctx->mesh.ne);
@@ -401,6 +409,7 @@ extern "C" int qhp_mlp_reconstruct(qhp_mlp *m, const double *f, int64_t n, doubl
 extern "C" int qhp_mlp_train(qhp_mlp *m, const double *y, int64_t n_runs, int64_t n_steps, int32_t epochs,
                              int32_t batch, double lr, uint64_t seed, double *epoch_loss)
 {
+    QHP_ALLOC_SCOPE(m ? m->ctx : nullptr);
     if (!m || !y || n_runs < 1 || n_steps < 6 || epochs < 1 || batch < 1 || !(lr > 0.0)) return QHP_EINVAL;
     try {
         qhp_ctx *c = m->ctx;
@@ -464,6 +473,7 @@ extern "C" int qhp_mlp_train(qhp_mlp *m, const double *y, int64_t n_runs, int64_
 
 extern "C" int qhp_attach_mlp(qhp_ctx *ctx, qhp_mlp *m)
 {
+    QHP_ALLOC_SCOPE(ctx);
     if (!ctx) return QHP_EINVAL;
     if (m && m->ctx != ctx) return guard(ctx, QHP_EINVAL, "the perceptron was built for another context");
     ctx->mlp = m;
@@ -646,6 +656,7 @@ bool gmres_solve(qhp_ctx *c, const double *b, double *x, int32_t *iters, float *
 
 extern "C" int qhp_set_gmres(qhp_ctx *ctx, double tol, int32_t m_max, int32_t max_refine, int32_t warm)
 {
+    QHP_ALLOC_SCOPE(ctx);
     if (!ctx) return QHP_EINVAL;
     if (!(tol > 0.0) || m_max < 1 || m_max > 512 || max_refine < 1 || warm < QHP_WARM_COLD || warm > QHP_WARM_BEST)
         return guard(ctx, QHP_EINVAL, "bad GMRES parameters");
@@ -690,6 +701,7 @@ extern "C" int qhp_gmres_stats(const qhp_ctx *ctx, qhp_gmres_info *info, int32_t
 
 extern "C" int qhp_gmres_reset(qhp_ctx *ctx)
 {
+    QHP_ALLOC_SCOPE(ctx);
     if (!ctx) return QHP_EINVAL;
     ctx->gm_iters.clear();
     ctx->gm_res0.clear();

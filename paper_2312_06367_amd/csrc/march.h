@@ -36,11 +36,21 @@ void launch_history(hipStream_t s, int32_t precision, int64_t ne, int64_t ld, in
                     const void *slabs, const float *scales, const void *ring, int64_t n_slots, int64_t head,
                     const double *r, double *b, void *partial, int nsplit, hipEvent_t e0 = nullptr,
                     hipEvent_t e1 = nullptr, int variant = -1);
+// argument checks of the caller-buffer history sums (qhp_history_sum*), and
+// the lag split count they use (partial sums: split count * ne * nrhs FP64)
+bool history_args_valid(int32_t precision, int64_t ne, int64_t ld, int64_t nrhs, int64_t kmax, const void *slabs,
+                        const float *scales, const void *ring, int64_t n_slots, int64_t head, const double *r,
+                        double *b, int32_t variant);
+int history_split_count(int32_t precision, int64_t ne, int64_t nrhs, int64_t kmax, int32_t variant);
 int gemv_variant_count();
 void gemv_variant_desc(int v, int *rpw, int *unr, int *nt);
 void launch_gemv_f64(hipStream_t s, int64_t n, const double *A, const double *x, double *y);
+// bound: device pointer to this step's growth bound (the largest |r_k| so
+// far), or NULL for no growth check
 void launch_store_y(hipStream_t s, int64_t n, const double *y, double *slot64, float *slot32, double *yhist,
-                    int *err);
+                    int *err, const double *bound, double limit);
+// out[k] = max over the per entries of step k of |r|
+void launch_step_absmax(hipStream_t s, int64_t n_steps, int64_t per, const double *r, double *out);
 void launch_post_a(hipStream_t s, int64_t nc, int64_t nrhs, double dtn, const int32_t *tri_edge,
                    const int32_t *tri_sign, const double *y, const double *yprev, double *sv);
 void launch_post_b(hipStream_t s, int64_t ne, int64_t nrhs, const int32_t *cells, const double *y, const double *z,

@@ -349,6 +349,7 @@ __global__ __launch_bounds__(256, MINW) void k_hist_gemv_d(int64_t ne, int64_t l
     constexpr int PIECES = (AP + YP + 3) / 4 * 4, PW = PIECES / 4, PF = NB - 1;
     // vmcnt(PW (PF - 1)) with the other counters left alone (gfx9 encoding)
     constexpr int WAIT_INFLIGHT = ((PW * (PF - 1)) & 15) | (7 << 4) | (15 << 8) | (((PW * (PF - 1)) >> 4) << 14);
+    constexpr int WAIT_DRAINED = (7 << 4) | (15 << 8);  // vmcnt(0)
     static_assert(NB >= 2 && PW * (PF - 1) < 64 && YP >= 1, "pipeline shape");
     __shared__ i4 S[NB][PIECES * 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -424,6 +425,8 @@ __global__ __launch_bounds__(256, MINW) void k_hist_gemv_d(int64_t ne, int64_t l
                 __builtin_amdgcn_s_barrier();
             }
         }
+        // the copies issued past the last step (they repeat it) land before the wave ends
+        __builtin_amdgcn_s_waitcnt(WAIT_DRAINED);
     }
 #pragma unroll
     for (int rr = 0; rr < RPW; ++rr) {
@@ -924,20 +927,46 @@ void launch_gemv_f64(hipStream_t s, int64_t n, const double *A, const double *x,
 
 // --------------------------------------------------------- post-process
 // y_i stored: FP64 master copy into the ring slot and FP32 shadow for the
-// reduced-precision history; non-finite values raise the error flag.
-__global__ void k_store_y(int64_t n, const double *y, double *slot64, float *slot32, double *yhist, int *err)
+// reduced-precision history; non-finite values raise the error flag (2), and
+// so does growth (3): an entry above limit * bound, bound the largest |r_k|
+// of the steps so far (limit 0: no growth check).
+__global__ void k_store_y(int64_t n, const double *y, double *slot64, float *slot32, double *yhist, int *err,
+                          const double *bound, double limit)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double v = y[i];
     if (!isfinite(v)) atomicExch(err, 2);
+    else if (limit > 0.0 && fabs(v) > limit * *bound) atomicCAS(err, 0, 3);
     if (slot64) slot64[i] = v;
     if (slot32) slot32[i] = (float)v;
     if (yhist) yhist[i] = v;
 }
-void launch_store_y(hipStream_t s, int64_t n, const double *y, double *slot64, float *slot32, double *yhist, int *err)
+void launch_store_y(hipStream_t s, int64_t n, const double *y, double *slot64, float *slot32, double *yhist, int *err,
+                    const double *bound, double limit)
 {
-    hipLaunchKernelGGL(k_store_y, dim3(nblk(n, 256)), dim3(256), 0, s, n, y, slot64, slot32, yhist, err);
+    hipLaunchKernelGGL(k_store_y, dim3(nblk(n, 256)), dim3(256), 0, s, n, y, slot64, slot32, yhist, err, bound,
+                       bound ? limit : 0.0);
+}
+
+// out[k] = max |r[k][.]| over the per entries of each step (one work-group a step)
+__global__ void k_step_absmax(int64_t per, const double *r, double *out)
+{
+    __shared__ double red[256];
+    const double *rk = r + (int64_t)blockIdx.x * per;
+    double m = 0.0;
+    for (int64_t i = threadIdx.x; i < per; i += 256) m = fmax(m, fabs(rk[i]));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+void launch_step_absmax(hipStream_t s, int64_t n_steps, int64_t per, const double *r, double *out)
+{
+    if (n_steps > 0) hipLaunchKernelGGL(k_step_absmax, dim3((unsigned)n_steps), dim3(256), 0, s, per, r, out);
 }
 
 // w = (1/dtn - 1) y_i - y_{i-1}/dtn ; s_c = sum_a sign(c,a) w[edge(c,a)]

@@ -107,7 +107,11 @@ int build_mesh(const double *xyz, int64_t nv, const int32_t *tri, int64_t nc, Me
         w[1] = u[2] * v[0] - u[0] * v[2];
         w[2] = u[0] * v[1] - u[1] * v[0];
         m.area[c] = 0.5 * std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
-        if (!(m.area[c] > 0.0)) return fail(err, "zero-area triangle");
+        // zero up to rounding: below 1e-12 of the square of the longest edge
+        double l2 = 0.0;
+        for (const double *e : {u, v}) l2 = std::max(l2, e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+        l2 = std::max(l2, (u[0] - v[0]) * (u[0] - v[0]) + (u[1] - v[1]) * (u[1] - v[1]) + (u[2] - v[2]) * (u[2] - v[2]));
+        if (!(m.area[c] > 1e-12 * l2)) return fail(err, "zero-area triangle");
     }
     double dmax = 0.0;
     for (int64_t a = 0; a < nv; ++a)

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -108,3 +109,81 @@ def test_null_handles_and_bad_sizes_are_rejected():
         rc = h(None, a["p"], a["ne"], a["ld"], a["nrhs"], a["kmax"], a["slabs"], a["scales"], a["ring"],
                a["n_slots"], a["head"], a["r"], a["b"], a["variant"])
         assert rc == EINVAL, change
+
+
+def _lib_or_skip():
+    import paper_2312_06367_amd as pkg
+    if not os.path.exists(pkg.LIB_PATH):
+        pytest.skip("libqhp.so not built")
+    return pkg
+
+
+def test_check_mesh_accepts_closed_surfaces_and_counts_loops():
+    """qhp_check_mesh (host only): a closed sphere has N_H = 0 global loops,
+    a torus N_H = 2 (Sec. II-D: N_H = 2 - Euler characteristic)."""
+    pkg = _lib_or_skip()
+    from workloads import meshes
+    xyz, tri = meshes.icosphere(1)
+    assert pkg.check_mesh(xyz, tri)[:3] == (0, 120, 0)
+    xyz, tri = meshes.torus(1.0, 0.3, 12, 5)
+    rc, ne, nh, _ = pkg.check_mesh(xyz, tri)
+    assert (rc, ne, nh) == (0, 3 * 12 * 5, 2)
+
+
+def test_check_mesh_rejects_what_the_formulation_excludes():
+    """Every mesh the formulation excludes (Sec. II-A: Gamma closed, connected
+    and orientable; the bases need non-degenerate triangles) returns
+    QHP_EMESH with its reason, before any device work."""
+    pkg = _lib_or_skip()
+    from workloads import meshes
+    EMESH, EINVAL = -2, -1
+    xyz, tri = meshes.icosphere(1)
+    nv = len(xyz)
+    cases = {}
+    cases["open"] = (xyz, tri[1:])
+    cases["flipped"] = (xyz, np.concatenate([tri[:1, ::-1], tri[1:]]))
+    # two separate spheres
+    cases["disconnected"] = (np.concatenate([xyz, xyz + 3.0]), np.concatenate([tri, tri + nv]))
+    # vertex 0 and its antipode merged into one: every edge still has two
+    # consistently oriented triangles, but the triangles at vertex 0 form two discs
+    opp = int(np.argmin(np.linalg.norm(xyz + xyz[0], axis=1)))
+    keep = np.array([v for v in range(nv) if v != opp])
+    renum = np.full(nv, -1)
+    renum[keep] = np.arange(nv - 1)
+    renum[opp] = 0
+    cases["non-manifold vertex"] = (xyz[keep], renum[tri].astype(np.int32))
+    # a triangle whose three vertices are collinear: move vertex a onto the
+    # midpoint of the other two vertices of one of its triangles
+    a, b, c = tri[0]
+    xz = xyz.copy()
+    xz[a] = 0.5 * (xyz[b] + xyz[c])
+    cases["zero area"] = (xz, tri)
+    bad = tri.copy()
+    bad[0, 1] = bad[0, 0]
+    cases["repeated vertex"] = (xyz, bad)
+    bad = tri.copy()
+    bad[0, 0] = nv
+    cases["index out of range"] = (xyz, bad)
+    expect = {"open": "exactly two", "flipped": "oriented", "disconnected": "not connected",
+              "non-manifold vertex": "non-manifold vertex", "zero area": "zero-area",
+              "repeated vertex": "degenerate", "index out of range": "out of range"}
+    for name, (x, t) in cases.items():
+        rc, _, _, msg = pkg.check_mesh(x, t)
+        assert rc == EMESH, (name, rc, msg)
+        assert expect[name] in msg, (name, msg)
+    L = pkg.lib()
+    assert L.qhp_check_mesh(None, 4, None, 4, None, None, None, 0) == EINVAL
+
+
+def test_allocator_hook_and_growth_limit_argument_checks():
+    """Host logic, no device: qhp_create refuses an allocator hook with only
+    one of dev_alloc / dev_free; qhp_set_growth_limit rejects a null context."""
+    pkg = _lib_or_skip()
+    L = pkg.lib()
+    p = pkg._Params(0.1, 1.0, 0, 0, 10, 0, None)
+    alloc = pkg.TorchAllocator(0)
+    p.dev_alloc = alloc.alloc_fn  # dev_free left NULL
+    h = ctypes.c_void_p()
+    assert L.qhp_create(ctypes.byref(p), ctypes.byref(h)) == -1
+    assert not h.value
+    assert L.qhp_set_growth_limit(None, 1.0) == -1
