@@ -37,9 +37,9 @@ def ico1():
     return dict(xyz=xyz, tri=tri, dt=dt, n=n, w=w, j=j, ne=asm.topo.ne)
 
 
-def _solver(d, precision="f64", **kw):
+def _solver(d, precision="f64", solver="lu", **kw):
     import paper_2312_06367_amd as qhp
-    s = qhp.Solver(d["dt"], precision="f64", solver="lu", **kw)
+    s = qhp.Solver(d["dt"], precision="f64", solver=solver, **kw)
     s.mesh(d["xyz"], d["tri"])
     s.assemble()
     if precision != "f64":
@@ -105,20 +105,24 @@ def test_batch_holds_its_contexts_and_resumes_their_marches():
     loops: 30 steps alone, 30 in a batch, 30 alone, 30 in the batch again give
     the 120-step march of a context alone (the batch works on the context's
     own transposed ring and picks up its steps); while the batch exists the
-    context refuses qhp_set_incident and qhp_set_precision."""
+    context refuses qhp_set_incident and qhp_set_precision.  The contexts
+    solve with the FP64 inverse of T_0, as the batch does; the batch's kernels
+    sum in other orders than the context's, and this torus march amplifies
+    those roundings to ~1e-10 (the bound of the other batch-against-eager
+    tests, 1e-9); a ring left behind by either side would be off by O(1)."""
     import paper_2312_06367_amd as qhp
     from workloads import meshes, waves
     xyz, tri = meshes.torus(1.0, 0.4, 12, 6)
     dt, n = 0.12, 120
     d = dict(xyz=xyz, tri=tri, dt=dt)
     ws = waves.batched_waves(2, 5, 0.1, 0.1, 2.8)
-    ref_s = _solver(d, "f32a")
+    ref_s = _solver(d, "f32a", solver="inv")
     ne = ref_s.info()["ne"]
     ref_s.set_incident(ws, n)
     ref = torch.zeros((n, ne, 4), dtype=torch.float64, device="cuda")
     ref_s.run(n, ref)
     ref_s.close()
-    s = _solver(d, "f32a")
+    s = _solver(d, "f32a", solver="inv")
     s.set_incident(ws, n)
     j = torch.zeros((n, ne, 4), dtype=torch.float64, device="cuda")
     s.run(30, j[0:30])
@@ -138,7 +142,7 @@ def test_batch_holds_its_contexts_and_resumes_their_marches():
     s.close()
     err = float((j - ref).abs().max() / ref.abs().max())
     _say("[torus f32a x4] alone / batch / alone / batch vs alone: %.3e" % err)
-    assert err < 1e-12
+    assert err < 1e-9
 
 
 def test_torch_allocator_hook(ico1):
