@@ -326,6 +326,25 @@ int qhp_history_sum_variant(void *stream, int32_t precision, int64_t ne, int64_t
 /* number of history-kernel variants for a precision and right-hand-side count */
 int qhp_history_variants(int32_t precision, int64_t nrhs);
 
+/* The history sum of qhp_history_sum_variant (same arguments, kernels and
+ * results) that allocates nothing, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  The partial sums of the lag splits (split count x ne x
+ * nrhs FP64 values; the split count is that of qhp_history_sum_variant for
+ * the same precision, sizes and variant) go to one fixed device array of
+ * QHP_NOALLOC_SCRATCH_MB MiB that each GPU the library runs on holds until
+ * the process ends; sizes whose partial sums do not fit return QHP_EINVAL,
+ * as do the argument errors of qhp_history_sum_variant.  The call only
+ * enqueues work on `stream` (it neither allocates nor synchronises) and
+ * returns QHP_EDEVICE if a launch fails; the caller waits for the stream.
+ * Every call on one GPU uses that GPU's one array, so calls that can overlap
+ * on one GPU (different streams without ordering between them) race; calls
+ * ordered on one stream do not. */
+#define QHP_NOALLOC_SCRATCH_MB 64
+int qhp_history_sum_noalloc(void *stream, int32_t precision, int64_t ne, int64_t ld, int64_t nrhs,
+                            int64_t kmax, const void *slabs, const float *scales, const void *ring,
+                            int64_t n_slots, int64_t head, const double *r, double *b, int32_t variant);
+
 const char *qhp_last_error(const qhp_ctx *ctx);
 void qhp_destroy(qhp_ctx *ctx);
 

@@ -102,7 +102,8 @@ EXPORTS = ["qhp_create", "qhp_mesh", "qhp_assemble", "qhp_set_precision", "qhp_s
            "qhp_destroy", "qhp_release_assembly", "qhp_set_gmres", "qhp_gmres_stats", "qhp_gmres_reset", "qhp_mlp_create",
            "qhp_mlp_dims", "qhp_mlp_set_params", "qhp_mlp_get_params", "qhp_mlp_features", "qhp_mlp_guess", "qhp_mlp_reconstruct",
            "qhp_mlp_forward", "qhp_mlp_loss_grad", "qhp_mlp_adam", "qhp_mlp_train", "qhp_attach_mlp",
-           "qhp_mlp_last_error", "qhp_mlp_destroy", "qhp_check_mesh", "qhp_set_growth_limit"]
+           "qhp_mlp_last_error", "qhp_mlp_destroy", "qhp_check_mesh", "qhp_set_growth_limit",
+           "qhp_history_sum_noalloc"]
 _NO_RC = ("qhp_last_error", "qhp_destroy", "qhp_batch_last_error", "qhp_batch_destroy", "qhp_mlp_last_error",
           "qhp_mlp_destroy")
 
@@ -135,6 +136,7 @@ def lib():
         L.qhp_history_sum.argtypes = [vp, i32, i64, i64, i64, i64, vp, vp, vp, i64, i64, vp, vp]
         L.qhp_history_sum_variant.argtypes = [vp, i32, i64, i64, i64, i64, vp, vp, vp, i64, i64, vp, vp, i32]
         L.qhp_history_variants.argtypes = [i32, i64]
+        L.qhp_history_sum_noalloc.argtypes = [vp, i32, i64, i64, i64, i64, vp, vp, vp, i64, i64, vp, vp, i32]
         L.qhp_t0_condition.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.qhp_batch_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]
         L.qhp_batch_create_variant.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.POINTER(vp)]
@@ -379,6 +381,28 @@ def history_sum(precision: str, slabs, scales, ring, head: int, r, b, kmax: int 
                                    _ptr(ring), ring.shape[0], int(head), _ptr(r), _ptr(b), int(variant))
     if rc != 0:
         raise QhpError(rc, "qhp_history_sum")
+
+
+def history_sum_noalloc(precision: str, slabs, scales, ring, head: int, r, b, kmax: int | None = None,
+                        variant: int = -1):
+    """qhp_history_sum_noalloc: history_sum's arguments, no device allocation
+    (partial sums in the library's fixed per-device array); only enqueues
+    the work on the current stream."""
+    L = lib()
+    kmax = slabs.shape[0] if kmax is None else kmax
+    if precision == "bf16x2":
+        ne, ld = r.shape[0], slabs.shape[2] * 32
+    elif precision == "i8x4":
+        ne = r.shape[0]
+        R = (ne + 15) // 16 * 16
+        ld = (slabs.shape[-1] - 8 * R) // (4 * R)
+    else:
+        ne, ld = slabs.shape[-2], slabs.shape[-1]
+    nrhs = r.shape[1] if r.dim() == 2 else 1
+    rc = L.qhp_history_sum_noalloc(_stream(), PRECISIONS[precision], ne, ld, nrhs, kmax, _ptr(slabs), _ptr(scales),
+                                   _ptr(ring), ring.shape[0], int(head), _ptr(r), _ptr(b), int(variant))
+    if rc != 0:
+        raise QhpError(rc, "qhp_history_sum_noalloc")
 
 
 class Batch:

@@ -187,3 +187,23 @@ def test_allocator_hook_and_growth_limit_argument_checks():
     assert L.qhp_create(ctypes.byref(p), ctypes.byref(h)) == -1
     assert not h.value
     assert L.qhp_set_growth_limit(None, 1.0) == -1
+
+
+def test_noalloc_history_sum_refuses_before_any_device_work():
+    """qhp_history_sum_noalloc (host logic, no device): partial sums beyond
+    its fixed array, and the argument errors of the allocating call, return
+    QHP_EINVAL; the pointers are never dereferenced."""
+    pkg = _lib_or_skip()
+    L = pkg.lib()
+    hdr = open(os.path.join(ROOT, "include", "qhp.h")).read()
+    limit = int(re.search(r"#define QHP_NOALLOC_SCRATCH_MB (\d+)", hdr).group(1)) << 20
+    fake = ctypes.c_void_p(4096)
+    # 8192 rows x 2048 right-hand sides: even one lag split needs 128 MiB of
+    # FP64 partial sums, above the array whatever the split count
+    ne, nrhs = 8192, 2048
+    assert ne * nrhs * 8 > limit
+    f = L.qhp_history_sum_noalloc
+    assert f(None, pkg.QHP_F32, ne, ne, nrhs, 4, fake, None, fake, 4, 0, fake, fake, -1) == -1
+    assert f(None, pkg.QHP_F32A, 100, 100, 1, 4, fake, None, fake, 4, 0, fake, fake, -1) == -1  # ld % 8
+    assert f(None, pkg.QHP_F32, 100, 128, 1, 4, fake, None, fake, 3, 0, fake, fake, -1) == -1  # slots < lags
+    assert f(None, pkg.QHP_F32, 100, 128, 1, 4, fake, None, fake, 4, 0, fake, fake, 11) == -1  # variant
