@@ -73,10 +73,33 @@ enum {
  *              >= 2^-28 on the int8 matrix cores with exact int32 sums over
  *              each lag, scaled and summed over lags in FP64 (two or more
  *              right-hand sides, N_E <= 65536)
+ *   QHP_FAC64  factored history (Sec. IV-A: T_k = P_E W^E_k + P_M W^M_k,
+ *              the cost discussion of Sec. IV-C): no dense blocks; the raw
+ *              lag matrices A_k, C_k (edge pairs, lags 0..K) and Sq_k, the
+ *              q_0 combination of the scalar-potential shell moments
+ *              (triangle pairs, lags 1..K; B_k = -T0 Sigma diag(1/A) Sq_k
+ *              diag(1/A) Sigma^T) stored lag-banded: for each pair (row,
+ *              column) only its run of lags from the first to the last
+ *              nonzero value, 64 pairs (two rows, 32 columns) to a group
+ *              whose 64 words give each pair's first lag and run length.
+ *              With the difference quotients moved onto the history by
+ *              summation by parts, the history sum is
+ *                E = sum_k A_k j_{i-k} - A_0 P^Sigma y_{i-1} / dt~
+ *                    - T0 Sigma diag(1/A) sum_k Sq_k diag(1/A) Sigma^T y_{i-k},
+ *                M = sum_k C_k j_{i-k} - C_0 P^Sigma y_{i-1} / dt~,
+ *                sum_k T_k y_{i-k} = P_E E + P_M M
+ *              (j the current of eq. post_processing): FP64 values, sums
+ *              and P_E, P_M; one right-hand side; assembly needs A_K = C_K = 0
+ *              (true when no quadrature point pair is farther apart than
+ *              (K - 1) dt) and (K + 1) N_E^2 + K N_C^2 doubles of device
+ *              memory for the raw matrices while it runs
+ *   QHP_FAC32  the same with FP32 band values (rounding carried along each
+ *              pair's lags); P_E, P_M, x, products and sums FP64
  * Reduced-precision blocks are rounded lag by lag with the rounding error of
  * each block carried into the next one (c_k = T_k + c_{k-1} - stored_k), so
  * every prefix sum over lags is within one rounding of the FP64 one. */
-enum { QHP_F64 = 0, QHP_F32 = 1, QHP_BF16 = 2, QHP_F32A = 3, QHP_BF16X2 = 4, QHP_I8X4 = 5 };
+enum { QHP_F64 = 0, QHP_F32 = 1, QHP_BF16 = 2, QHP_F32A = 3, QHP_BF16X2 = 4, QHP_I8X4 = 5, QHP_FAC64 = 6,
+       QHP_FAC32 = 7 };
 
 /* per-step solve with T_0 (the paper writes only T_0^{-1}, Sec. IV-B) */
 enum {
@@ -195,10 +218,12 @@ int qhp_mesh(qhp_ctx *ctx, const double *xyz, int64_t nv, const int32_t *tri, in
 int qhp_assemble(qhp_ctx *ctx);
 
 /* Re-store the assembled T_1..T_K in another precision without assembling
- * again: from QHP_F64 storage (the assembly is FP64) to QHP_F32, QHP_F32A or
- * QHP_BF16 (per-slab scale = largest |entry|), freeing the FP64 slabs; or
- * between QHP_F32 and QHP_F32A, which share the FP32 storage.  Allowed after
- * qhp_assemble; resets the march (call qhp_set_incident again). */
+ * again: from QHP_F64 storage (the assembly is FP64) to QHP_F32, QHP_F32A,
+ * QHP_BF16, QHP_BF16X2 or QHP_I8X4, freeing the FP64 slabs; between QHP_F32 and
+ * QHP_F32A, which share the FP32 storage; or between QHP_FAC64 and QHP_FAC32
+ * (a factored assembly keeps both).  Dense and factored storage do not
+ * convert into each other (QHP_EINVAL).  Allowed after qhp_assemble; resets
+ * the march (call qhp_set_incident again). */
 int qhp_set_precision(qhp_ctx *ctx, int32_t precision);
 
 /* Conditioning of the system solved at every step (the study of Sec. V-A,

@@ -18,6 +18,7 @@
 #include "qhp_internal.h"
 #include "solve.h"
 #include "ctx.h"
+#include "factored.h"
 
 using qhp::DBuf;
 using qhp::Fail;
@@ -72,7 +73,7 @@ int guard(qhp_ctx *ctx, int code, const std::string &msg)
 extern "C" int qhp_create(const qhp_params *params, qhp_ctx **out)
 {
     if (!params || !out) return QHP_EINVAL;
-    if (!(params->dt > 0.0) || params->precision < QHP_F64 || params->precision > QHP_I8X4 ||
+    if (!(params->dt > 0.0) || params->precision < QHP_F64 || params->precision > QHP_FAC32 ||
         params->solver < QHP_SOLVE_LU || params->solver > QHP_SOLVE_INV || params->n_psi > 32 ||
         (!params->dev_alloc) != (!params->dev_free))
         return QHP_EINVAL;
@@ -94,6 +95,14 @@ extern "C" int qhp_create(const qhp_params *params, qhp_ctx **out)
     *out = c;
     return QHP_OK;
 }
+
+qhp_ctx::~qhp_ctx()
+{
+    delete fac;
+    if (gm_host) (void)hipHostFree(gm_host);
+}
+
+static bool is_fac(int32_t precision) { return precision == QHP_FAC64 || precision == QHP_FAC32; }
 
 extern "C" void qhp_destroy(qhp_ctx *ctx)
 {
@@ -368,8 +377,16 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
     // ---- lag blocks T_0..T_K (Sec. IV-A) in chunks of lags
     const int64_t K = c->K;
     const int32_t prec = c->p.precision;
-    const size_t blk = (size_t)qhp::slab_bytes(prec, ne, c->ld);  // bytes of one stored block
-    c->slabs.alloc((size_t)K * blk);
+    const bool fac = is_fac(prec);
+    const size_t blk = fac ? 0 : (size_t)qhp::slab_bytes(prec, ne, c->ld);  // bytes of one stored block
+    c->slabs.alloc(fac ? 8 : (size_t)K * blk);
+    // factored form: every raw lag matrix kept (FP64, dense) until the bands are built
+    qhp::DBuf Afull, Cfull, Sqfull;
+    if (fac) {
+        Afull.alloc(sizeof(double) * nn * (K + 1));
+        Cfull.alloc(sizeof(double) * nn * (K + 1));
+        Sqfull.alloc(sizeof(double) * (size_t)nc * nc * K);
+    }
     c->scales.assign(K, 1.0f);
     c->T0raw.alloc(sizeof(double) * nn);
     if (c->keep_raw) {
@@ -429,6 +446,15 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
                 qhp::launch_lag_ac(s, (int64_t)nn, k, c->p.dt, shellV(k), shellV(k - 1), shellN(k), shellN(k - 1),
                                    c->G.as<double>(), Ak.as<double>(), Ck.as<double>());
                 qhp::launch_bk(s, a, shellS(k), shellS(k - 1), shellS(k - 2), c->T0, Bk.as<double>());
+                if (fac) {
+                    hip_check(hipMemcpyAsync(Afull.as<double>() + k * nn, Ak.p, sizeof(double) * nn,
+                                             hipMemcpyDeviceToDevice, s), "raw A");
+                    hip_check(hipMemcpyAsync(Cfull.as<double>() + k * nn, Ck.p, sizeof(double) * nn,
+                                             hipMemcpyDeviceToDevice, s), "raw C");
+                    if (k >= 1)
+                        qhp::launch_sq(s, nc, shellS(k), shellS(k - 1), shellS(k - 2),
+                                       Sqfull.as<double>() + (k - 1) * (size_t)nc * nc);
+                }
                 if (k >= 1)
                     for (const DBuf *m : {&Ak, &Bk, &Ck})
                         qhp::count_nonzero(s, (int64_t)nn, m->as<double>(), nnz.as<unsigned long long>());
@@ -439,6 +465,11 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
                     hip_check(hipMemcpyAsync(c->rawA[k].data(), Ak.p, sizeof(double) * nn, hipMemcpyDeviceToHost, s), "raw");
                     hip_check(hipMemcpyAsync(c->rawB[k].data(), Bk.p, sizeof(double) * nn, hipMemcpyDeviceToHost, s), "raw");
                     hip_check(hipMemcpyAsync(c->rawC[k].data(), Ck.p, sizeof(double) * nn, hipMemcpyDeviceToHost, s), "raw");
+                }
+                if (fac && k >= 1) {  // no dense blocks: only T_0 is formed
+                    Ap.swap(Ak);
+                    Cp.swap(Ck);
+                    continue;
                 }
                 // W^E = A_k + B_k + ((1/dt~ - 1) A_k - A_{k-1}/dt~) P^Sigma (top half of Wst)
                 double *WE = Wst.as<double>(), *WM = Wst.as<double>() + nn;
@@ -467,6 +498,50 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
         unsigned long long cnt = 0;
         hip_check(hipMemcpy(&cnt, nnz.p, sizeof(cnt), hipMemcpyDeviceToHost), "nonzero count");
         c->raw_nnz = (int64_t)cnt;
+        if (fac) {
+            // summation by parts leaves A_K, C_K acting on P^Sigma y_{i-K-1}: they vanish when no
+            // quadrature point pair is farther apart than (K - 1) dt, which the bands rely on
+            zero(nnz, s);
+            qhp::count_nonzero(s, (int64_t)nn, Afull.as<double>() + K * nn, nnz.as<unsigned long long>());
+            qhp::count_nonzero(s, (int64_t)nn, Cfull.as<double>() + K * nn, nnz.as<unsigned long long>());
+            hip_check(hipMemcpy(&cnt, nnz.p, sizeof(cnt), hipMemcpyDeviceToHost), "nonzero count");
+            if (cnt) throw Fail{QHP_EINVAL, "factored history: A_K or C_K is not zero"};
+            c->fac = new qhp_ctx::FacState();
+            qhp_ctx::FacState &f = *c->fac;
+            // edges and cells stored in Morton order of their midpoints / centroids, so that
+            // a row block and a column chunk are compact patches with short lag ranges
+            std::vector<int32_t> eperm, einv, cperm, cinv;
+            qhp::morton_order(m, false, eperm, einv);
+            qhp::morton_order(m, true, cperm, cinv);
+            upload(f.eperm, eperm, s);
+            upload(f.einv, einv, s);
+            upload(f.cperm, cperm, s);
+            upload(f.cinv, cinv, s);
+            for (int fp32 = 0; fp32 < 2; ++fp32) {
+                qhp::build_band(s, 2 * ne, ne, 0, K, Afull.as<double>(), Cfull.as<double>(), ne, (int64_t)nn, ne,
+                                f.eperm.as<int32_t>(), f.eperm.as<int32_t>(), fp32 != 0, fp32 ? f.ac32 : f.ac64);
+                qhp::build_band(s, nc, nc, 1, K, Sqfull.as<double>(), Sqfull.as<double>(), nc, nc * nc, nc,
+                                f.cperm.as<int32_t>(), f.cperm.as<int32_t>(), fp32 != 0, fp32 ? f.sq32 : f.sq64);
+            }
+            // [P_E; P_M] as two padded blocks, FP64 and FP32
+            const int64_t ld = c->ld;
+            f.pem64.alloc(sizeof(double) * 2 * ne * ld);
+            f.pem32.alloc(sizeof(float) * 2 * ne * ld);
+            for (int h = 0; h < 2; ++h) {
+                const double *src = c->Pcat.as<double>() + h * ne;
+                qhp::launch_quantise_slab(s, ne, ld, src, 2 * ne, nullptr, QHP_F64, 1.0f,
+                                          f.pem64.as<double>() + h * ne * ld);
+                qhp::launch_quantise_slab(s, ne, ld, src, 2 * ne, nullptr, QHP_F32, 1.0f,
+                                          f.pem32.as<float>() + h * ne * ld);
+            }
+            hip_check(hipStreamSynchronize(s), "factored bands");
+            if (c->verbose)
+                for (const qhp::Band *b : {&f.ac64, &f.sq64, &f.ac32, &f.sq32})
+                    std::fprintf(stderr, "[qhp] band %lld x %lld: %.3f GB, %lld values, %d waves, 2 x %d KB a wave, "
+                                 "%d lags staged, %d splits\n", (long long)b->rows, (long long)b->cols, b->bytes / 1e9,
+                                 (long long)b->nnz, b->waves, b->np, b->tmax, b->nsplit);
+            c->stage("factored bands");
+        }
     }
     upload(c->scales_d, c->scales, s);
     // ---- T_0: FP64 LU, diagonal-block inverses, optional explicit inverse
@@ -597,9 +672,51 @@ static void autotune_i8(qhp_ctx *c)
     c->nsplit = best_s;
 }
 
+// the factored history's [P_E P_M] product: the single right-hand-side
+// variant and split count (1 or 2) of the dense kernels, timed
+static void autotune_fac(qhp_ctx *c)
+{
+    qhp_ctx::FacState &f = *c->fac;
+    hipStream_t s = c->s;
+    const int32_t pp = f.pem_prec;
+    const void *pem = pp == QHP_F64 ? f.pem64.p : f.pem32.p;
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "event");
+    hip_check(hipEventCreate(&e1), "event");
+    float best = 1e30f;
+    for (int v = 0; v < qhp::gemv_variant_count(); ++v)
+        for (int ns = 1; ns <= 2; ++ns) {
+            auto run = [&]() {
+                qhp::launch_history(s, pp, c->mesh.ne, c->ld, 1, 2, pem, nullptr, f.em.p, 2, 0, c->rhs.as<double>(),
+                                    c->bvec.as<double>(), c->partial.p, ns, nullptr, nullptr, v);
+            };
+            run();
+            hip_check(hipEventRecord(e0, s), "event");
+            run();
+            run();
+            hip_check(hipEventRecord(e1, s), "event");
+            hip_check(hipEventSynchronize(e1), "event");
+            float ms = 0.f;
+            hip_check(hipEventElapsedTime(&ms, e0, e1), "event");
+            if (ms < best) {
+                best = ms;
+                f.pem_variant = v;
+                f.pem_splits = ns;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->hv = f.pem_variant;
+    c->nsplit = f.pem_splits;
+    if (c->verbose)
+        std::fprintf(stderr, "[qhp] factored history: [P_E P_M] product variant %d, %d splits, %.3f ms\n",
+                     f.pem_variant, f.pem_splits, best / 2);
+}
+
 static void autotune(qhp_ctx *c)
 {
     c->hv = -1;
+    if (is_fac(c->p.precision)) return autotune_fac(c);
     if (c->p.precision == QHP_I8X4) return autotune_i8(c);
     if (c->mr_desc.p) return autotune_grouped(c);
     if (c->nrhs != 1) return;
@@ -663,6 +780,8 @@ extern "C" int qhp_set_incident(qhp_ctx *ctx, const qhp_wave *waves, int32_t n_r
         return guard(ctx, QHP_EINVAL, "QHP_I8X4 takes two or more right-hand sides");
     if (ctx->p.precision == QHP_I8X4 && ctx->mesh.ne > 65536)
         return guard(ctx, QHP_EINVAL, "QHP_I8X4 takes at most 65536 edges (int32 sums)");
+    if (is_fac(ctx->p.precision) && n_rhs != 1)
+        return guard(ctx, QHP_EINVAL, "the factored history takes one right-hand side");
     API_TRY
     qhp_ctx *c = ctx;
     hip_check(hipSetDevice(c->p.device), "hipSetDevice");
@@ -753,6 +872,20 @@ extern "C" int qhp_set_incident(qhp_ctx *ctx, const qhp_wave *waves, int32_t n_r
     c->zc.alloc(sizeof(double) * nc * n_rhs);
     c->errflag.alloc(sizeof(int));
     zero(c->errflag, s);
+    if (is_fac(c->p.precision)) {
+        qhp_ctx::FacState &f = *c->fac;
+        f.jx.alloc(sizeof(double) * (K + 1) * ld);
+        f.cq.alloc(sizeof(double) * K * nc);
+        f.zy.alloc(sizeof(double) * 2 * nc);
+        f.sv.alloc(sizeof(double) * nc);
+        f.em.alloc(sizeof(double) * 2 * ld);
+        f.pac.alloc(sizeof(double) * std::max(f.ac64.nsplit, f.ac32.nsplit) * 2 * ne);
+        f.ps.alloc(sizeof(double) * std::max(f.sq64.nsplit, f.sq32.nsplit) * nc);
+        for (qhp::DBuf *b : {&f.jx, &f.cq, &f.zy, &f.em}) zero(*b, s);
+        f.zcur = 0;
+        if (c->partial.bytes < sizeof(double) * 2 * ne)  // the [P_E P_M] product: at most two splits
+            c->partial.alloc(sizeof(double) * 2 * ne);
+    }
     hip_check(hipStreamSynchronize(s), "march buffers");
     autotune(c);
     c->step = 0;
@@ -780,7 +913,20 @@ static void do_step(qhp_ctx *c, double *j_out, double *y_out)
         c->ev.push_back(e0);
         c->ev.push_back(e1);
     }
-    if (c->mr_desc.p) {  // FP32 blocks, FP64 y and sums, several right-hand sides: the grouped kernel
+    if (c->fac) {  // factored history: banded products, E and M, then [P_E P_M]
+        qhp_ctx::FacState &f = *c->fac;
+        const bool fp32 = c->p.precision == QHP_FAC32;
+        const qhp::Band &bac = fp32 ? f.ac32 : f.ac64, &bsq = fp32 ? f.sq32 : f.sq64;
+        if (e0) hip_check(hipEventRecord(e0, s), "event");
+        qhp::launch_band(s, bac, fp32, f.jx.as<double>(), ld, K, c->head, K, f.pac.as<double>());
+        qhp::launch_band(s, bsq, fp32, f.cq.as<double>(), nc, K, c->head, 0, f.ps.as<double>());
+        qhp::launch_fac_combine(s, ne, nc, c->args.cells, c->args.area, c->T0, f.einv.as<int32_t>(),
+                                f.cinv.as<int32_t>(), f.pac.as<double>(), bac.nsplit, f.ps.as<double>(), bsq.nsplit,
+                                f.em.as<double>(), ld);
+        qhp::launch_history(s, f.pem_prec, ne, ld, 1, 2, f.pem_prec == QHP_F64 ? f.pem64.p : f.pem32.p, nullptr,
+                            f.em.p, 2, 0, r_i, c->bvec.as<double>(), c->partial.p, f.pem_splits, nullptr, e1,
+                            f.pem_variant);
+    } else if (c->mr_desc.p) {  // FP32 blocks, FP64 y and sums, several right-hand sides: the grouped kernel
         qhp::launch_set_i64(s, c->mr_head.as<int64_t>(), c->head);
         if (e0) hip_check(hipEventRecord(e0, s), "event");
         qhp::launch_grouped_gemv(s, qhp::GK_F32A, (int)nr, c->mr_desc.as<qhp::GDesc>(), 1, c->mr_tiles,
@@ -828,7 +974,16 @@ static void do_step(qhp_ctx *c, double *j_out, double *y_out)
     double *slot64 = c->ring64.as<double>() + slot * ld * nr;
     float *slot32 = c->ring32.p ? c->ring32.as<float>() + slot * ld * nr : nullptr;
     const double *yprev = i > 1 ? c->ring64.as<double>() + c->head * ld * nr : nullptr;
-    if (j_out) {
+    if (c->fac) {  // j_i and the cell charges into the rings, the lag-0 vector of the next step
+        qhp_ctx::FacState &f = *c->fac;
+        double *zc = f.zy.as<double>() + (1 - f.zcur) * nc, *zp = f.zy.as<double>() + f.zcur * nc;
+        qhp::launch_fac_post_a(s, nc, c->args.tri_edge, c->args.tri_sign, c->args.area, f.cinv.as<int32_t>(), y,
+                               f.sv.as<double>(), f.cq.as<double>() + slot * nc);
+        qhp::launch_gemv_f64(s, nc, c->LSp.as<double>(), f.sv.as<double>(), zc);
+        qhp::launch_fac_post_b(s, ne, c->dtn, c->args.cells, f.einv.as<int32_t>(), y, zc, zp,
+                               f.jx.as<double>() + slot * ld, j_out, f.jx.as<double>() + K * ld);
+        f.zcur = 1 - f.zcur;
+    } else if (j_out) {
         qhp::launch_post_a(s, nc, nr, c->dtn, c->args.tri_edge, c->args.tri_sign, y, yprev, c->sv.as<double>());
         if (nr == 1) qhp::launch_gemv_f64(s, nc, c->LSp.as<double>(), c->sv.as<double>(), c->zc.as<double>());
         else
@@ -1015,6 +1170,13 @@ extern "C" int qhp_set_precision(qhp_ctx *ctx, int32_t precision)
     if (ctx->released) return guard(ctx, QHP_ESTATE, "assembly operators were released");
     if (ctx->batch_refs > 0) return guard(ctx, QHP_ESTATE, "a live batch holds the context's blocks");
     if (precision == ctx->p.precision) return QHP_OK;
+    if (is_fac(precision) || is_fac(ctx->p.precision)) {
+        if (!(is_fac(precision) && is_fac(ctx->p.precision)))
+            return guard(ctx, QHP_EINVAL, "dense and factored storage do not convert into each other");
+        ctx->p.precision = precision;  // both band precisions are kept
+        ctx->state = 2;
+        return QHP_OK;
+    }
     const bool fp32_pair = (precision == QHP_F32 || precision == QHP_F32A) &&
                            (ctx->p.precision == QHP_F32 || ctx->p.precision == QHP_F32A);
     if (fp32_pair) {  // same FP32 storage, other arithmetic
@@ -1067,6 +1229,12 @@ extern "C" int qhp_query(const qhp_ctx *ctx, qhp_info *info)
     info->K = qhp::n_lags(m.diameter, ctx->p.dt);
     info->ld = ctx->ld;
     info->slab_bytes = ctx->slabs.p ? ctx->slabs.bytes : 0;
+    if (ctx->fac) {  // the bands and [P_E P_M] of the precision in use
+        const bool fp32 = ctx->p.precision == QHP_FAC32;
+        const qhp_ctx::FacState &f = *ctx->fac;
+        info->slab_bytes = (fp32 ? f.ac32.bytes + f.sq32.bytes : f.ac64.bytes + f.sq64.bytes) +
+                           (size_t)2 * m.ne * ctx->ld * (fp32 ? 4 : 8);
+    }
     info->n_rhs = ctx->nrhs;
     info->n_steps = ctx->n_steps;
     info->step = ctx->step;
@@ -1113,6 +1281,7 @@ extern "C" int qhp_get_matrix(const qhp_ctx *cc, int32_t which, int32_t k, doubl
     case QHP_MAT_SLAB: {
         if (k < 0 || k > ctx->K) return guard(ctx, QHP_EINVAL, "lag out of range");
         if (k == 0) { src = &ctx->T0raw; break; }
+        if (ctx->fac) return guard(ctx, QHP_ESTATE, "factored storage holds no dense blocks T_k, k >= 1");
         DBuf tmp;
         tmp.alloc(sizeof(double) * nn);
         const int32_t prec = ctx->p.precision;
@@ -1481,7 +1650,8 @@ extern "C" int qhp_batch_create_variant(qhp_ctx *const *ctxs, int32_t n, int32_t
         if (c->p.device != c0->p.device || c->p.precision != c0->p.precision || c->nrhs != c0->nrhs)
             return guard(c0, QHP_EINVAL, "batch contexts must share device, precision and n_rhs");
     }
-    if (c0->p.precision == QHP_BF16 || c0->p.precision == QHP_BF16X2 || c0->p.precision == QHP_I8X4)
+    if (c0->p.precision == QHP_BF16 || c0->p.precision == QHP_BF16X2 || c0->p.precision == QHP_I8X4 ||
+        is_fac(c0->p.precision))
         return guard(c0, QHP_EINVAL, "the batch kernels take F64, F32 or F32A blocks");
     if (c0->nrhs != 1 && c0->nrhs != 2 && c0->nrhs != 4 && c0->nrhs != 8)
         return guard(c0, QHP_EINVAL, "batch n_rhs must be 1, 2, 4 or 8");

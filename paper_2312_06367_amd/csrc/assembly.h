@@ -54,6 +54,8 @@ void launch_zh(hipStream_t s, const AsmArgs &g, double kappa, const double *D, d
 void launch_bk(hipStream_t s, const AsmArgs &g, const double *Sk, const double *Sk1, const double *Sk2,
                double T0, double *B);
 void launch_sym_s(hipStream_t s, int64_t nc, double *S);
+// Sq_k [nc][nc]: the q_0 combination of the shell moments of lag k (Sec. IV-A)
+void launch_sq(hipStream_t s, int64_t nc, const double *Sk, const double *Sk1, const double *Sk2, double *Sq);
 void launch_lag_ac(hipStream_t s, int64_t nn, int64_t k, double dt, const double *Vk, const double *Vk1,
                    const double *Nk, const double *Nk1, const double *G, double *A, double *C);
 void launch_lin3(hipStream_t s, int64_t n, double *X, double a, const double *Y, double b, const double *Z,

@@ -169,15 +169,20 @@ struct qhp_ctx {
     qhp_mlp *mlp = nullptr;
     bool released = false;  // FP64 assembly operators freed (qhp_release_assembly)
     int batch_refs = 0;     // live batches holding this context (their descriptors point into its buffers)
+    // factored history (QHP_FAC64 / QHP_FAC32): the lag-banded raw lag
+    // matrices in both value precisions, [P_E; P_M] as two padded blocks
+    // [2][ne][ld] (FP64 and FP32), and the march state: the ring of the
+    // current j (K slots) plus the lag-0 vector -P^Sigma y_{i-1}/dt~ (slot K),
+    // the ring of the cell charges Sigma^T y / A (K slots), L_Sigma^+ Sigma^T y
+    // of the last two steps, partial sums, E and M
+    struct FacState;
+    FacState *fac = nullptr;
     // growth trip of the march: |y_i| > growth_limit * max_{k <= i} max |r_k| (0: off)
     double growth_limit = 1e8;
     qhp::DBuf rpk;  // [n_steps] running maximum of max |r_k|
     qhp::DBuf feat;  // ring of the last four feature vectors [4][nf]
     int64_t feat_n = 0;
-    ~qhp_ctx()
-    {
-        if (gm_host) (void)hipHostFree(gm_host);
-    }
+    ~qhp_ctx();
 };
 
 // make the context's caller allocator (if any) current for this entry point

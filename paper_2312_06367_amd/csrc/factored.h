@@ -1,0 +1,96 @@
+// The factored history sum (Sec. IV-A, IV-C): instead of the dense blocks
+// T_k = P_E W^E_k + P_M W^M_k, the raw lag matrices A_k, C_k (edge pairs)
+// and Sq_k, the q_0 combination of the shell moments (triangle pairs, B_k =
+// -T0 Sigma diag(1/A) Sq_k diag(1/A) Sigma^T), stored lag-banded, applied to
+// the histories of the current j and of the cell charges; the dense P_E, P_M
+// once per step.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "ctx.h"
+
+namespace qhp {
+
+// A work-group of the banded product: `waves` waves (16, 12, 8, 6 or 4,
+// chosen at build time with the size of the copy batches so that the staged x
+// and two batch buffers a wave fit the LDS), each taking kBandRowsPerWave
+// rows (one row block) over one split of the kBandChunk-column chunks.
+constexpr int kBandRowsPerWave = 16;
+constexpr int kBandChunk = 32;
+constexpr int kBandLdsBytes = 160 * 1024;
+constexpr int kBandMaxPieces = 16;  // 1 KB copy pieces of a batch, at most
+constexpr int kBandStep = 8;        // lags a lane takes per step of the walk
+
+// One lag-banded family of matrices X_k, k in [lag0, lag1], rows x cols.
+// Rows 2q, 2q + 1 and the chunk ch of kBandChunk columns form the group
+// g = q * nch + ch, 64 pairs (lane l: row 2q + l / kBandChunk, column
+// kBandChunk ch + l % kBandChunk): for each pair the lags from its first to
+// its last stored value.  A group is 64 words klo | len << 16, then the
+// values, pair by pair, lag by lag within a pair: FP64, or FP32 with the
+// rounding of each pair carried from lag to lag; padded to 16 bytes.  Groups
+// are stored by row block (waves * kBandRowsPerWave / 2 groups), then chunk,
+// then group, so a wave's groups in one chunk are one contiguous range, and
+// hdr is in the same order: off / 16 | (bytes / 16) << 40.
+// tile[rb * nch + ch] = tk0 | ntk << 16: the lags row block rb uses in chunk ch.
+struct Band {
+    int64_t rows = 0, cols = 0, nch = 0, nrb = 0, lag0 = 0, lag1 = 0;
+    int64_t nnz = 0;        // stored values (lags between a pair's first and last value)
+    size_t bytes = 0;       // stream bytes (words, values, alignment)
+    int tmax = 0;           // largest staged lag range of a tile
+    int lmax = 0;           // longest run of a pair
+    int nsplit = 1;         // chunk splits of the product (partial sums)
+    int waves = 16;         // waves per work-group
+    int np = 1;             // 1 KB copy pieces per batch (two batch buffers a wave)
+    DBuf hdr, tile, stream;
+};
+
+// Build a family from dense FP64 lag matrices, rows and columns in the
+// stored orders rp, cp (stored index -> matrix index): value (k, r, c) is
+// srcA[(k - lag0) * lag_stride + rp[r] * row_stride + cp[c]] for r < split and
+// srcB[(k - lag0) * lag_stride + rp[r - split] * row_stride + cp[c]] otherwise.
+// fp32: values rounded to FP32 with the rounding carried along each pair's lags.
+void build_band(hipStream_t s, int64_t rows, int64_t cols, int64_t lag0, int64_t lag1, const double *srcA,
+                const double *srcB, int64_t split, int64_t lag_stride, int64_t row_stride, const int32_t *rp,
+                const int32_t *cp, bool fp32, Band &out);
+
+// part[split][row] = sum over the split's chunks of sum_k X_k(row, .) x_k, x_k
+// the ring slot of lag k: slot0 for k = 0, else (head + k - 1) mod K, slots
+// [.][ldx] FP64
+void launch_band(hipStream_t s, const Band &b, bool fp32, const double *x, int64_t ldx, int64_t K, int64_t head,
+                 int64_t slot0, double *part);
+
+// Morton (Z-curve) order of the edge midpoints (cells = false) or the
+// triangle centroids: perm[stored index] = index, inv[index] = stored index
+void morton_order(const Mesh &m, bool cells, std::vector<int32_t> &perm, std::vector<int32_t> &inv);
+
+// E, M of the factored history into the two slots of em ([2][ld]), the band
+// products in stored order (einv, cinv: index -> stored index):
+// E_m = sum_s pac[s][m'] - T0 (ps(c+')/A(c+) - ps(c-')/A(c-)), M_m = sum_s pac[s][ne + m']
+void launch_fac_combine(hipStream_t s, int64_t ne, int64_t nc, const int32_t *cells, const double *area, double T0,
+                        const int32_t *einv, const int32_t *cinv, const double *pac, int nsac, const double *ps,
+                        int nss, double *em, int64_t ld);
+
+// after the solve of step i: sv = Sigma^T y (cells), cslot (stored order) = sv / A
+void launch_fac_post_a(hipStream_t s, int64_t nc, const int32_t *tri_edge, const int32_t *tri_sign,
+                       const double *area, const int32_t *cinv, const double *y, double *sv, double *cslot);
+// j = y + Sigma((1/dt~ - 1) zc - zp / dt~) into jslot (stored order) and
+// j_out (if not null); x0 (stored order) = -Sigma zc / dt~, lag 0 of the next step
+void launch_fac_post_b(hipStream_t s, int64_t ne, double dtn, const int32_t *cells, const int32_t *einv,
+                       const double *y, const double *zc, const double *zp, double *jslot, double *j_out, double *x0);
+
+}  // namespace qhp
+
+struct qhp_ctx::FacState {
+    qhp::Band ac64, ac32, sq64, sq32;  // rows [A_k; C_k] x edges, lags 0..K; Sq_k cells x cells, lags 1..K
+    qhp::DBuf pem64, pem32;            // [P_E; P_M] [2][ne][ld]
+    qhp::DBuf eperm, einv, cperm, cinv;  // stored orders of the edges and cells
+    qhp::DBuf jx, cq, zy, sv, em, pac, ps;
+    int zcur = 0;                      // which half of zy holds L_Sigma^+ Sigma^T y_{i-1}
+    int pem_variant = -1, pem_splits = 1;
+    // arithmetic of the [P_E P_M] product: QHP_F64, or QHP_F32A (FP32 P_E, P_M)
+    int32_t pem_prec = QHP_F64;
+};

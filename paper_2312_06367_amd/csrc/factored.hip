@@ -1,0 +1,632 @@
+// Lag-banded storage of the raw lag matrices and the factored history
+// product (see factored.h).
+#include "factored.h"
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+namespace qhp {
+
+static unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+namespace {
+
+constexpr int CW = kBandChunk;  // columns of a chunk
+constexpr int META = 4 * 64;    // bytes of a group's words
+
+// value (k, r, c) of a family in stored order: rows r < split from a, the
+// others from b (row r - split), through the row and column orders rp, cp
+struct Src {
+    const double *a, *b;
+    const int32_t *rp, *cp;
+    int64_t split, lag_stride, row_stride, lag0;
+    __device__ double at(int64_t k, int64_t r, int64_t c) const
+    {
+        const double *p = r < split ? a + (int64_t)rp[r] * row_stride : b + (int64_t)rp[r - split] * row_stride;
+        return p[(k - lag0) * lag_stride + cp[c]];
+    }
+};
+
+// stored value of a pair at one lag: FP64 as is, or FP32 of value + carry
+// with the rounding carried to the next lag
+__device__ __forceinline__ double store_value(double v, double &carry, bool fp32)
+{
+    if (!fp32) return v;
+    const double t = v + carry;
+    const float st = (float)t;
+    carry = t - (double)st;
+    return (double)st;
+}
+
+// lane l of group (q, ch): row 2q + l / CW, column CW ch + l % CW
+__device__ __forceinline__ bool group_pair(int64_t g, int64_t nch, int64_t rows, int64_t cols, int lane, int64_t &r,
+                                           int64_t &col)
+{
+    r = 2 * (g / nch) + lane / CW;
+    col = (g % nch) * CW + lane % CW;
+    return r < rows && col < cols;
+}
+
+}  // namespace
+
+// one wave per group: per pair (lane) the first stored lag and the number of
+// lags to the last stored value (word klo | len << 16); per group the values
+// stored, the lag range and the longest run
+__global__ __launch_bounds__(256) void k_band_scan(int64_t rows, int64_t cols, int64_t nch, int64_t ng, int64_t lag1,
+                                                   Src src, bool fp32, uint32_t *meta, int64_t *cnt_out,
+                                                   int32_t *kmin_out, int32_t *kmax_out, int32_t *lmax_out)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    if (g >= ng) return;
+    int64_t r, col;
+    const bool in = group_pair(g, nch, rows, cols, lane, r, col);
+    double carry = 0.0;
+    int64_t first = -1, last = -1;
+    if (in)
+        for (int64_t k = src.lag0; k <= lag1; ++k)
+            if (store_value(src.at(k, r, col), carry, fp32) != 0.0) {
+                if (first < 0) first = k;
+                last = k;
+            }
+    const int64_t len = first < 0 ? 0 : last - first + 1;
+    meta[g * 64 + lane] = (uint32_t)(first < 0 ? 0 : first) | ((uint32_t)len << 16);
+    int64_t c = len, lo = first < 0 ? (1 << 30) : first, hi = last, lm = len;
+    for (int off = 32; off > 0; off >>= 1) {
+        c += __shfl_xor(c, off, 64);
+        lo = min(lo, __shfl_xor(lo, off, 64));
+        hi = max(hi, __shfl_xor(hi, off, 64));
+        lm = max(lm, __shfl_xor(lm, off, 64));
+    }
+    if (lane == 0) {
+        cnt_out[g] = c;
+        kmin_out[g] = (int32_t)(hi < 0 ? 0 : lo);
+        kmax_out[g] = (int32_t)hi;
+        lmax_out[g] = (int32_t)lm;
+    }
+}
+
+// one wave per group: the 64 words, then each pair's values over its lags, at
+// the group's offset in stored order (row block of qpb groups, chunk, group)
+__global__ __launch_bounds__(256) void k_band_fill(int64_t rows, int64_t cols, int64_t nch, int64_t ng, int64_t qpb,
+                                                   Src src, bool fp32, const uint64_t *hdr, const uint32_t *meta,
+                                                   char *stream)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    if (g >= ng) return;
+    const int64_t q = g / nch, ch = g % nch;
+    const uint64_t h = hdr[((q / qpb) * nch + ch) * qpb + q % qpb];
+    if ((h >> 40) == 0) return;  // no stored value in the group
+    int64_t r, col;
+    group_pair(g, nch, rows, cols, lane, r, col);
+    char *base = stream + (h & ((1ull << 40) - 1)) * 16;
+    const uint32_t w = meta[g * 64 + lane];
+    const int64_t klo = w & 0xffff, len = w >> 16;
+    reinterpret_cast<uint32_t *>(base)[lane] = w;
+    int64_t start = len;  // exclusive prefix sum of the lengths over the lanes
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t t = __shfl_up(start, off, 64);
+        if (lane >= off) start += t;
+    }
+    start -= len;
+    double *v64 = reinterpret_cast<double *>(base + META) + start;
+    float *v32 = reinterpret_cast<float *>(base + META) + start;
+    double carry = 0.0;
+    for (int64_t k = src.lag0; k < klo + len; ++k) {
+        const double st = store_value(src.at(k, r, col), carry, fp32);
+        if (k < klo) continue;
+        if (fp32) v32[k - klo] = (float)st;
+        else v64[k - klo] = st;
+    }
+}
+
+// the work-group sizes (waves) the product kernel is built for
+static const int kBandWaves[] = {16, 12, 8, 6, 4};
+
+// rows of the staged x: the tile lags, then zero rows that a lane stepping
+// past its run may read (at most the longest run plus a step)
+static int band_xrows(int tmax, int lmax) { return tmax + lmax + kBandStep; }
+
+// LDS bytes of the product kernel: the staged x, two batch buffers a wave,
+// the values a lane may read past the last buffer
+static size_t band_lds(int tmax, int lmax, int waves, int np, bool fp32)
+{
+    return (size_t)band_xrows(tmax, lmax) * CW * sizeof(double) + (size_t)waves * 2 * np * 1024 +
+           (size_t)(lmax + kBandStep) * (fp32 ? 4 : 8);
+}
+
+void build_band(hipStream_t s, int64_t rows, int64_t cols, int64_t lag0, int64_t lag1, const double *srcA,
+                const double *srcB, int64_t split, int64_t lag_stride, int64_t row_stride, const int32_t *rp,
+                const int32_t *cp, bool fp32, Band &out)
+{
+    if (lag1 >= 65535) throw Fail{QHP_EINVAL, "the factored history takes at most 65534 lags"};
+    out.rows = rows;
+    out.cols = cols;
+    out.nch = (cols + CW - 1) / CW;
+    out.lag0 = lag0;
+    out.lag1 = lag1;
+    const int64_t nq = (rows + 1) / 2, nch = out.nch, ng = nq * nch;
+    const size_t vsz = fp32 ? 4 : 8;
+    Src src{srcA, srcB, rp, cp, split, lag_stride, row_stride, lag0};
+    DBuf meta, cnt, kmin, kmax, lmax;
+    meta.alloc(sizeof(uint32_t) * 64 * ng);
+    cnt.alloc(sizeof(int64_t) * ng);
+    kmin.alloc(sizeof(int32_t) * ng);
+    kmax.alloc(sizeof(int32_t) * ng);
+    lmax.alloc(sizeof(int32_t) * ng);
+    hipLaunchKernelGGL(k_band_scan, dim3(nblk(ng * 64, 256)), dim3(256), 0, s, rows, cols, nch, ng, lag1, src, fp32,
+                       meta.as<uint32_t>(), cnt.as<int64_t>(), kmin.as<int32_t>(), kmax.as<int32_t>(),
+                       lmax.as<int32_t>());
+    std::vector<int64_t> hc(ng);
+    std::vector<int32_t> hlo(ng), hhi(ng), hlm(ng);
+    hip_check(hipMemcpyAsync(hc.data(), cnt.p, sizeof(int64_t) * ng, hipMemcpyDeviceToHost, s), "band scan");
+    hip_check(hipMemcpyAsync(hlo.data(), kmin.p, sizeof(int32_t) * ng, hipMemcpyDeviceToHost, s), "band scan");
+    hip_check(hipMemcpyAsync(hhi.data(), kmax.p, sizeof(int32_t) * ng, hipMemcpyDeviceToHost, s), "band scan");
+    hip_check(hipMemcpyAsync(hlm.data(), lmax.p, sizeof(int32_t) * ng, hipMemcpyDeviceToHost, s), "band scan");
+    hip_check(hipStreamSynchronize(s), "band scan");
+    std::vector<size_t> gbytes(ng);
+    int64_t nnz = 0;
+    size_t gmax = 0;
+    int lm = 0;
+    for (int64_t g = 0; g < ng; ++g) {
+        gbytes[g] = hc[g] ? (META + hc[g] * vsz + 15) / 16 * 16 : 0;
+        nnz += hc[g];
+        gmax = std::max(gmax, gbytes[g]);
+        lm = std::max(lm, hlm[g]);
+    }
+    // the lags the groups of a row block of qpb groups use in each chunk
+    auto tiles = [&](int64_t qpb, std::vector<uint32_t> &tile) {
+        const int64_t nrb = (nq + qpb - 1) / qpb;
+        tile.assign(nrb * nch, 0u);
+        int tmax = 1;
+        for (int64_t rb = 0; rb < nrb; ++rb)
+            for (int64_t ch = 0; ch < nch; ++ch) {
+                int64_t lo = 1 << 30, hi = -1;
+                for (int64_t q = rb * qpb; q < std::min<int64_t>((rb + 1) * qpb, nq); ++q) {
+                    const int64_t g = q * nch + ch;
+                    if (hhi[g] < 0) continue;
+                    lo = std::min<int64_t>(lo, hlo[g]);
+                    hi = std::max<int64_t>(hi, hhi[g]);
+                }
+                if (hi < 0) continue;
+                tile[rb * nch + ch] = (uint32_t)lo | ((uint32_t)(hi - lo + 1) << 16);
+                tmax = std::max<int>(tmax, (int)(hi - lo + 1));
+            }
+        return tmax;
+    };
+    // work-group shape: the most bytes in flight (waves x 1 KB copy pieces
+    // per batch), then the most waves, whose buffers and staged x fit the LDS;
+    // a batch holds at least the largest group
+    const int npmin = (int)((gmax + 1023) / 1024);
+    std::vector<uint32_t> tile, tw;
+    int waves = 0, np = 0, tmax = 0;
+    for (int w : kBandWaves) {
+        const int tm = tiles((int64_t)w * kBandRowsPerWave / 2, tw);
+        int p = 0;
+        while (p < kBandMaxPieces && band_lds(tm, lm, w, p + 1, fp32) <= (size_t)kBandLdsBytes) ++p;
+        if (p < npmin) continue;
+        if (w * p > waves * np) {
+            waves = w;
+            np = p;
+            tmax = tm;
+            tile = tw;
+        }
+    }
+    if (std::getenv("QHP_VERBOSE")) {  // distribution of group sizes and tile lag ranges
+        std::vector<size_t> gs;
+        for (size_t b : gbytes)
+            if (b) gs.push_back(b);
+        std::sort(gs.begin(), gs.end());
+        std::vector<int> tr;
+        for (uint32_t t : tile)
+            if (t >> 16) tr.push_back((int)(t >> 16));
+        std::sort(tr.begin(), tr.end());
+        if (!gs.empty() && !tr.empty())
+            std::fprintf(stderr,
+                         "[qhp]   group bytes p50 %zu p99 %zu max %zu; longest run %d; tile lag range p50 %d p90 %d "
+                         "max %d\n",
+                         gs[gs.size() / 2], gs[gs.size() * 99 / 100], gs.back(), lm, tr[tr.size() / 2],
+                         tr[tr.size() * 9 / 10], tr.back());
+    }
+    if (!waves) throw Fail{QHP_EINVAL, "factored history: a band group does not fit the LDS"};
+    const int64_t qpb = (int64_t)waves * kBandRowsPerWave / 2;
+    out.nrb = (nq + qpb - 1) / qpb;
+    // offsets in stored order: row block, chunk, group (the headers of a
+    // wave's groups in one chunk are consecutive)
+    std::vector<uint64_t> hdr(out.nrb * nch * qpb, 0);
+    uint64_t off = 0;
+    for (int64_t rb = 0; rb < out.nrb; ++rb)
+        for (int64_t ch = 0; ch < nch; ++ch)
+            for (int64_t i = 0; i < qpb; ++i) {
+                const int64_t q = rb * qpb + i;
+                const size_t b = q < nq ? gbytes[q * nch + ch] : 0;
+                hdr[(rb * nch + ch) * qpb + i] = (off / 16) | ((uint64_t)(b / 16) << 40);
+                off += b;
+            }
+    if (off / 16 >= (1ull << 40)) throw Fail{QHP_ENOMEM, "factored history stream too large"};
+    out.bytes = off;
+    out.nnz = nnz;
+    out.tmax = tmax;
+    out.lmax = lm;
+    out.waves = waves;
+    out.np = np;
+    upload(out.hdr, hdr, s);
+    upload(out.tile, tile, s);
+    // a batch's copy reads np whole 1 KB pieces from its first group on
+    out.stream.alloc(off + (size_t)np * 1024 + 1024);
+    hip_check(hipMemsetAsync(out.stream.p, 0, off + (size_t)np * 1024 + 1024, s), "stream");
+    hipLaunchKernelGGL(k_band_fill, dim3(nblk(ng * 64, 256)), dim3(256), 0, s, rows, cols, nch, ng, qpb, src, fp32,
+                       out.hdr.as<uint64_t>(), meta.as<uint32_t>(), out.stream.as<char>());
+    hip_check(hipStreamSynchronize(s), "band fill");
+    // chunk splits: about four rounds of one work-group per CU
+    const int64_t want = (1024 + out.nrb - 1) / out.nrb;
+    out.nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(want, nch));
+}
+
+namespace {
+
+// inclusive sum and maximum over the wave's 64 lanes (DPP row shifts within
+// rows of 16 lanes, then the row broadcasts); all lanes active
+template <int CTRL, int RMASK>
+__device__ __forceinline__ int dpp_add(int v)
+{
+    return v + __builtin_amdgcn_update_dpp(0, v, CTRL, RMASK, 0xf, true);
+}
+__device__ __forceinline__ int wave_incl_sum(int v)
+{
+    v = dpp_add<0x111, 0xf>(v);  // row_shr:1
+    v = dpp_add<0x112, 0xf>(v);  // row_shr:2
+    v = dpp_add<0x114, 0xf>(v);  // row_shr:4
+    v = dpp_add<0x118, 0xf>(v);  // row_shr:8
+    v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 into rows 1, 3
+    v = dpp_add<0x143, 0xc>(v);  // row_bcast:31 into rows 2, 3
+    return v;
+}
+__device__ __forceinline__ int wave_max_nonneg(int v)
+{
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true));
+    const int a = max(__builtin_amdgcn_readlane(v, 15), __builtin_amdgcn_readlane(v, 31));
+    const int b = max(__builtin_amdgcn_readlane(v, 47), __builtin_amdgcn_readlane(v, 63));
+    return max(a, b);
+}
+
+// a stored value as FP64, or zero when !keep (an FP32 value is cleared as
+// bits, before the conversion: one 32-bit select; the empty asm keeps the
+// compiler from moving the select past the conversion, where it takes two)
+__device__ __forceinline__ double masked(float v, bool keep)
+{
+    uint32_t b = keep ? __float_as_uint(v) : 0u;
+    asm("" : "+v"(b));
+    return (double)__uint_as_float(b);
+}
+__device__ __forceinline__ double masked(double v, bool keep) { return keep ? v : 0.0; }
+
+__device__ __forceinline__ void wait_vm(int n)
+{
+    // s_waitcnt vmcnt(n), lgkmcnt and expcnt left alone; n is wave-uniform
+    switch (n) {
+#define QHP_VM(N) \
+    case N: __builtin_amdgcn_s_waitcnt((((N) & 15) | (7 << 4) | (15 << 8) | (((N) >> 4) << 14))); break;
+        QHP_VM(0) QHP_VM(1) QHP_VM(2) QHP_VM(3) QHP_VM(4) QHP_VM(5) QHP_VM(6) QHP_VM(7) QHP_VM(8)
+        QHP_VM(9) QHP_VM(10) QHP_VM(11) QHP_VM(12) QHP_VM(13) QHP_VM(14) QHP_VM(15) QHP_VM(16)
+#undef QHP_VM
+    default: __builtin_amdgcn_s_waitcnt((7 << 4) | (15 << 8)); break;
+    }
+}
+
+}  // namespace
+
+// The banded product.  A work-group is W waves; wave w takes the
+// kBandRowsPerWave / 2 groups (row pairs) rb * W * 8 + 8 w + [0, 8) of row
+// block rb, over one split of the chunks.  Per chunk the work-group stages x_k
+// of the chunk's CW columns for the tile's lags into LDS ([lag][column], FP64;
+// the rows past them zero).  Each wave streams its groups, chunk after chunk,
+// in batches: as many consecutive groups as fit np 1 KB pieces (one
+// contiguous range), copied straight into one of its two LDS batch buffers
+// (global_load_lds, 16 bytes a lane, always np pieces so the waits are
+// exact); while it walks one batch the next is in flight.  In a group lane l
+// takes pair l: its words give the run (klo, len), a wave prefix sum its
+// place among the values; the wave steps over the longest run kBandStep lags
+// at a time, a lane past its own run adding zero products.  FP64 sums per lane,
+// reduced over each half-wave (one row) at the end, one partial per split.
+template <typename T, int W>
+__global__ __launch_bounds__(64 * W) void k_band(int64_t rows, int64_t nch, int64_t cps, int np,
+                                                 const uint64_t *__restrict__ hdr, const uint32_t *__restrict__ tile,
+                                                 const char *__restrict__ stream, const double *__restrict__ x,
+                                                 int64_t ldx, int64_t K, int64_t head, int64_t slot0, int xrows,
+                                                 double *__restrict__ part)
+{
+    constexpr int GW = kBandRowsPerWave / 2;  // groups (row pairs) of a wave in a chunk
+    extern __shared__ double smem[];
+    double *X = smem;
+    // the wave index is uniform: group quantities below stay in scalar registers
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int col = lane & (CW - 1);
+    const int64_t batch = (int64_t)np * 1024;
+    char *bufs = reinterpret_cast<char *>(smem + (int64_t)xrows * CW) + (int64_t)wave * 2 * batch;
+    const int64_t rb = blockIdx.x, sp = blockIdx.y;
+    const int64_t c0 = sp * cps, c1 = (c0 + cps < nch) ? c0 + cps : nch;
+    const int64_t q0w = rb * W * GW + (int64_t)wave * GW;  // first group (row pair) of this wave
+    const int64_t nqt = (rows + 1) / 2;
+    const int ngw = nqt - q0w < GW ? (int)(nqt - q0w) : GW;  // groups of this wave (may be <= 0)
+    double acc[GW];
+#pragma unroll
+    for (int q = 0; q < GW; ++q) acc[q] = 0.0;
+    // headers and tiles read through the constant address space: scalar loads,
+    // whose waits (lgkmcnt) leave the copies in flight (vmcnt) alone; a wave's
+    // headers of one chunk are consecutive
+    typedef const __attribute__((address_space(4))) uint64_t *chdr_t;
+    typedef const __attribute__((address_space(4))) uint32_t *ctile_t;
+    const chdr_t H = (chdr_t)hdr;
+    const ctile_t TL = (ctile_t)tile;
+    const int64_t qpb = (int64_t)W * GW;
+    auto hidx = [&](int64_t ch, int q) { return (rb * nch + ch) * qpb + (int64_t)wave * GW + q; };
+    auto gsize = [&](int64_t ch, int q) { return q < ngw ? (int64_t)(H[hidx(ch, q)] >> 40) * 16 : 0; };
+    // the batch after groups [.., q0) of chunk ch: skip empty groups, then take
+    // consecutive groups while they fit the batch; false when none is left
+    auto next_batch = [&](int64_t &ch, int &q0, int &q1) {
+        while (ch < c1) {
+            while (q0 < ngw && gsize(ch, q0) == 0) ++q0;
+            if (q0 < ngw) break;
+            ++ch;
+            q0 = 0;
+        }
+        if (ch >= c1) return false;
+        int64_t total = 0;
+        q1 = q0;
+        while (q1 < ngw) {
+            const int64_t sz = gsize(ch, q1);
+            if (total + sz > batch) break;
+            total += sz;
+            ++q1;
+        }
+        return true;
+    };
+    auto issue = [&](int64_t ch, int q0, char *dst) {
+        const char *src = stream + (H[hidx(ch, q0)] & ((1ull << 40) - 1)) * 16;
+        for (int pc = 0; pc < np; ++pc)
+            __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(src + pc * 1024 + lane * 16),
+                                             (__attribute__((address_space(3))) void *)(dst + pc * 1024), 16, 0, 0);
+    };
+    // zero rows past any tile: read (and discarded) by lanes past their runs
+    for (int idx = threadIdx.x; idx < xrows * CW; idx += 64 * W) X[idx] = 0.0;
+    int64_t bch = c0;
+    int bq0 = 0, bq1 = 0, cur = 0;
+    bool have = ngw > 0 && next_batch(bch, bq0, bq1);
+    if (have) issue(bch, bq0, bufs);
+    for (int64_t ch = c0; ch < c1; ++ch) {
+        const uint32_t tl = TL[rb * nch + ch];
+        const int tk0 = (int)(tl & 0xffff), ntk = (int)(tl >> 16);
+        __syncthreads();  // every wave is done with the previous chunk's x
+        for (int idx = threadIdx.x; idx < ntk * CW; idx += 64 * W) {
+            const int l = idx / CW, c = idx % CW;
+            const int64_t k = tk0 + l, cc = ch * CW + c;
+            const int64_t slot = k == 0 ? slot0 : (head + k - 1) % K;
+            X[idx] = cc < ldx ? x[slot * ldx + cc] : 0.0;
+        }
+        __syncthreads();
+        while (have && bch == ch) {
+            int64_t nch_ = bch;
+            int nq0 = bq1, nq1 = 0;
+            const bool nhave = next_batch(nch_, nq0, nq1);
+            if (nhave) {
+                issue(nch_, nq0, bufs + (1 - cur) * batch);
+                wait_vm(np);
+            } else {
+                wait_vm(0);
+            }
+            const char *buf = bufs + cur * batch;
+            int64_t goff = 0;
+#pragma unroll
+            for (int q = 0; q < GW; ++q) {
+                if (q < bq0 || q >= bq1) continue;
+                const int64_t sz = gsize(ch, q);
+                if (sz == 0) continue;
+                const char *g = buf + goff;
+                goff += sz;
+                const uint32_t w = reinterpret_cast<const uint32_t *>(g)[lane];
+                const int len = (int)(w >> 16), klo = len ? (int)(w & 0xffff) : tk0;
+                const int start = wave_incl_sum(len) - len;
+                const int mx = wave_max_nonneg(len);
+                const T *vals = reinterpret_cast<const T *>(g + META) + start;
+                const double *xr = X + (klo - tk0) * CW + col;
+                double sum = 0.0;
+                // kBandStep lags a step, every read issued before the
+                // products; a lane past its run reads the values after it (in
+                // LDS) and zero or staged x rows, and adds zero products
+                for (int p = 0; p < mx; p += kBandStep) {
+                    T v[kBandStep];
+                    double xv[kBandStep];
+#pragma unroll
+                    for (int u = 0; u < kBandStep; ++u) {
+                        v[u] = vals[p + u];
+                        xv[u] = xr[(p + u) * CW];
+                    }
+#pragma unroll
+                    for (int u = 0; u < kBandStep; ++u) sum = fma(masked(v[u], p + u < len), xv[u], sum);
+                }
+                acc[q] += sum;
+            }
+            bch = nch_;
+            bq0 = nq0;
+            bq1 = nq1;
+            have = nhave;
+            cur = 1 - cur;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < GW; ++q) {
+        double v = acc[q];
+        for (int off = CW / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        acc[q] = v;
+    }
+    if (col == 0)
+#pragma unroll
+        for (int q = 0; q < GW; ++q) {
+            const int64_t r = 2 * (q0w + q) + lane / CW;
+            if (q < ngw && r < rows) part[sp * rows + r] = acc[q];
+        }
+}
+
+template <typename T, int W>
+static void band_launch(hipStream_t s, const Band &b, bool fp32, const double *x, int64_t ldx, int64_t K,
+                        int64_t head, int64_t slot0, double *part)
+{
+    const int64_t cps = (b.nch + b.nsplit - 1) / b.nsplit;
+    const size_t lds = band_lds(b.tmax, b.lmax, W, b.np, fp32);
+    static bool attr = false;
+    if (!attr) {
+        hip_check(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_band<T, W>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, kBandLdsBytes),
+                  "band kernel attribute");
+        attr = true;
+    }
+    const int xrows = band_xrows(b.tmax, b.lmax);
+    hipLaunchKernelGGL((k_band<T, W>), dim3((unsigned)b.nrb, (unsigned)b.nsplit), dim3(64 * W), lds, s, b.rows,
+                       b.nch, cps, b.np, b.hdr.as<uint64_t>(), b.tile.as<uint32_t>(), b.stream.as<char>(), x, ldx, K,
+                       head, slot0, xrows, part);
+}
+
+template <typename T>
+static void band_dispatch(hipStream_t s, const Band &b, bool fp32, const double *x, int64_t ldx, int64_t K,
+                          int64_t head, int64_t slot0, double *part)
+{
+    switch (b.waves) {
+    case 16: band_launch<T, 16>(s, b, fp32, x, ldx, K, head, slot0, part); return;
+    case 12: band_launch<T, 12>(s, b, fp32, x, ldx, K, head, slot0, part); return;
+    case 8: band_launch<T, 8>(s, b, fp32, x, ldx, K, head, slot0, part); return;
+    case 6: band_launch<T, 6>(s, b, fp32, x, ldx, K, head, slot0, part); return;
+    case 4: band_launch<T, 4>(s, b, fp32, x, ldx, K, head, slot0, part); return;
+    default: throw Fail{QHP_EINVAL, "band kernel shape not built"};
+    }
+}
+
+void launch_band(hipStream_t s, const Band &b, bool fp32, const double *x, int64_t ldx, int64_t K, int64_t head,
+                 int64_t slot0, double *part)
+{
+    if (b.np < 1 || b.np > kBandMaxPieces) throw Fail{QHP_EINVAL, "band batch size out of range"};
+    if (fp32) band_dispatch<float>(s, b, fp32, x, ldx, K, head, slot0, part);
+    else band_dispatch<double>(s, b, fp32, x, ldx, K, head, slot0, part);
+}
+
+__global__ void k_fac_combine(int64_t ne, int64_t nc, const int32_t *cells, const double *area, double T0,
+                              const int32_t *einv, const int32_t *cinv, const double *pac, int nsac,
+                              const double *ps, int nss, double *em, int64_t ld)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= ne) return;
+    const int64_t cp = cells[2 * m], cm = cells[2 * m + 1], ms = einv[m], cps = cinv[cp], cms = cinv[cm];
+    double a = 0.0, c = 0.0, sp = 0.0, sm = 0.0;
+    for (int q = 0; q < nsac; ++q) {
+        a += pac[q * 2 * ne + ms];
+        c += pac[q * 2 * ne + ne + ms];
+    }
+    for (int q = 0; q < nss; ++q) {
+        sp += ps[q * nc + cps];
+        sm += ps[q * nc + cms];
+    }
+    em[m] = a - T0 * (sp / area[cp] - sm / area[cm]);
+    em[ld + m] = c;
+}
+
+void launch_fac_combine(hipStream_t s, int64_t ne, int64_t nc, const int32_t *cells, const double *area, double T0,
+                        const int32_t *einv, const int32_t *cinv, const double *pac, int nsac, const double *ps,
+                        int nss, double *em, int64_t ld)
+{
+    hipLaunchKernelGGL(k_fac_combine, dim3(nblk(ne, 256)), dim3(256), 0, s, ne, nc, cells, area, T0, einv, cinv, pac,
+                       nsac, ps, nss, em, ld);
+}
+
+__global__ void k_fac_post_a(int64_t nc, const int32_t *tri_edge, const int32_t *tri_sign, const double *area,
+                             const int32_t *cinv, const double *y, double *sv, double *cslot)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    double a = 0.0;
+    for (int i = 0; i < 3; ++i) a += tri_sign[3 * c + i] * y[tri_edge[3 * c + i]];
+    sv[c] = a;
+    cslot[cinv[c]] = a / area[c];
+}
+
+void launch_fac_post_a(hipStream_t s, int64_t nc, const int32_t *tri_edge, const int32_t *tri_sign,
+                       const double *area, const int32_t *cinv, const double *y, double *sv, double *cslot)
+{
+    hipLaunchKernelGGL(k_fac_post_a, dim3(nblk(nc, 256)), dim3(256), 0, s, nc, tri_edge, tri_sign, area, cinv, y, sv,
+                       cslot);
+}
+
+__global__ void k_fac_post_b(int64_t ne, double dtn, const int32_t *cells, const int32_t *einv, const double *y,
+                             const double *zc, const double *zp, double *jslot, double *j_out, double *x0)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= ne) return;
+    const int64_t cp = cells[2 * m], cm = cells[2 * m + 1], ms = einv[m];
+    const double vc = zc[cp] - zc[cm], vp = zp[cp] - zp[cm];  // (P^Sigma y_i)_m, (P^Sigma y_{i-1})_m
+    const double j = y[m] + (1.0 / dtn - 1.0) * vc - vp / dtn;
+    jslot[ms] = j;
+    if (j_out) j_out[m] = j;
+    x0[ms] = -vc / dtn;
+}
+
+void launch_fac_post_b(hipStream_t s, int64_t ne, double dtn, const int32_t *cells, const int32_t *einv,
+                       const double *y, const double *zc, const double *zp, double *jslot, double *j_out, double *x0)
+{
+    hipLaunchKernelGGL(k_fac_post_b, dim3(nblk(ne, 256)), dim3(256), 0, s, ne, dtn, cells, einv, y, zc, zp, jslot,
+                       j_out, x0);
+}
+
+// 21 bits of each coordinate interleaved (x highest)
+static uint64_t morton3(double fx, double fy, double fz)
+{
+    auto spread = [](uint64_t v) {
+        v &= 0x1fffff;
+        v = (v | v << 32) & 0x1f00000000ffffull;
+        v = (v | v << 16) & 0x1f0000ff0000ffull;
+        v = (v | v << 8) & 0x100f00f00f00f00full;
+        v = (v | v << 4) & 0x10c30c30c30c30c3ull;
+        v = (v | v << 2) & 0x1249249249249249ull;
+        return v;
+    };
+    auto q = [](double f) { return (uint64_t)(std::min(std::max(f, 0.0), 1.0 - 1e-12) * 2097152.0); };
+    return spread(q(fx)) << 2 | spread(q(fy)) << 1 | spread(q(fz));
+}
+
+void morton_order(const Mesh &m, bool cells, std::vector<int32_t> &perm, std::vector<int32_t> &inv)
+{
+    const int64_t n = cells ? m.nc : m.ne;
+    std::vector<double> p(3 * n);
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < 3; ++k) {
+            if (cells)
+                p[3 * i + k] = (m.xyz[3 * m.tri[3 * i] + k] + m.xyz[3 * m.tri[3 * i + 1] + k] +
+                                m.xyz[3 * m.tri[3 * i + 2] + k]) / 3.0;
+            else
+                p[3 * i + k] = 0.5 * (m.xyz[3 * m.edges[2 * i] + k] + m.xyz[3 * m.edges[2 * i + 1] + k]);
+        }
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = std::min(lo[k], p[3 * i + k]);
+            hi[k] = std::max(hi[k], p[3 * i + k]);
+        }
+    const double span = std::max(std::max(hi[0] - lo[0], hi[1] - lo[1]), std::max(hi[2] - lo[2], 1e-300));
+    std::vector<std::pair<uint64_t, int32_t>> key(n);
+    for (int64_t i = 0; i < n; ++i)
+        key[i] = {morton3((p[3 * i] - lo[0]) / span, (p[3 * i + 1] - lo[1]) / span, (p[3 * i + 2] - lo[2]) / span),
+                  (int32_t)i};
+    std::sort(key.begin(), key.end());
+    perm.resize(n);
+    inv.resize(n);
+    for (int64_t i = 0; i < n; ++i) {
+        perm[i] = key[i].second;
+        inv[key[i].second] = (int32_t)i;
+    }
+}
+
+}  // namespace qhp

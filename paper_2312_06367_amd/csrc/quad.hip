@@ -658,6 +658,19 @@ __global__ void k_bk(AsmArgs g, const double *Sk, const double *Sk1, const doubl
         }
     B[idx] = -T0 * s;
 }
+// Sq_k[a][b] = q_0 of lag k on the shell moments of triangles a, b (shells
+// k, k-1, k-2; x = R/dt - j): (1-x)^2/2, 1/2 + x - x^2, x^2/2
+__global__ void k_sq(int64_t nc, const double *Sk, const double *Sk1, const double *Sk2, double *Sq)
+{
+    int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nc2 = nc * nc;
+    if (o >= nc2) return;
+    double sq = 0.0;
+    if (Sk) sq += 0.5 * (Sk[o] - 2.0 * Sk[nc2 + o] + Sk[2 * nc2 + o]);
+    if (Sk1) sq += 0.5 * Sk1[o] + Sk1[nc2 + o] - Sk1[2 * nc2 + o];
+    if (Sk2) sq += 0.5 * Sk2[2 * nc2 + o];
+    Sq[o] = sq;
+}
 // symmetrise the coarse shell moments S [3][nc][nc] in place
 __global__ void k_sym_s(int64_t nc, double *S)
 {
@@ -698,6 +711,10 @@ __global__ void k_lin3(int64_t n, double *X, double a, const double *Y, double b
 
 static unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+void launch_sq(hipStream_t s, int64_t nc, const double *Sk, const double *Sk1, const double *Sk2, double *Sq)
+{
+    hipLaunchKernelGGL(k_sq, dim3(nblk(nc * nc, 256)), dim3(256), 0, s, nc, Sk, Sk1, Sk2, Sq);
+}
 void launch_gram(hipStream_t s, const AsmArgs &g, double *G)
 {
     hipLaunchKernelGGL(k_gram, dim3(nblk(g.nf, 128)), dim3(128), 0, s, g, G);
