@@ -2,16 +2,21 @@
 """Benchmark of the qHP TD-CFIE marching-on-in-time hot path on one MI355X.
 
 Default workload: PEC sphere r = 1 m, icosphere level 4 (7680 edges),
-c*dt = 0.02 m (K = 101 lag blocks), one x-polarised wave along -z with a
-150 MHz modulated Gaussian pulse; synthetic, seeded, no dataset.
+c*dt = 0.02 m (K = 101 lags), one x-polarised wave along -z with a 150 MHz
+modulated Gaussian pulse; synthetic, seeded, no dataset.
 
-A step is one pass of the whole hot path: the history sum over T_1..T_K, the
-FP64 T_0 solve and the FP64 post-processing to the current j_i.  The FP64
-assembly is marched first with FP64 slabs (the plain FP64 path, LU
-back-solves and the inverse product), then re-stored in the requested
-precision (default FP32) and marched again; `value` is the steps/s of that
-march, `rel_err_vs_fp64` = max_i |j_i - j_i^{FP64}| / max_i |j_i^{FP64}|.
-Prints one JSON line.
+A step is one pass of the whole hot path: the history sum, the FP64 T_0
+solve and the FP64 post-processing to the current j_i.  The FP64 assembly is
+marched first with FP64 blocks (the plain FP64 path: LU back-solves, and the
+inverse product), then in FP32 blocks (FP64 y and sums); a second assembly
+keeps the raw lag matrices lag-banded and marches the factored history in
+FP64 and with FP32 band values (the default headline, `value`).  Every form
+is timed over --steps steps after --warmup, and marched again, untimed, over
+a window that holds the pulse and its decay (600 steps; the pulse peaks near
+step 145): `rel_err_vs_fp64` = max_i |j_i - j_i^FP64| / max_i |j_i^FP64| over
+that window, against the FP64 LU march.  The default run adds the batched
+form as `batched`: the 6000-edge torus with 128 waves, int8-digit blocks on
+the int8 matrix cores against FP64, 300 steps.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -29,6 +34,7 @@ HBM_PEAK_GBPS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 INT8_MFMA_PEAK_TOPS = 5000.0  # dense int8 matrix-core peak of the MI355X
+FP64_MFMA_PEAK_TFLOPS = 78.6
 
 
 def parse():
@@ -45,19 +51,25 @@ def parse():
     ap.add_argument("--epochs", type=int, default=8, help="warm-start training passes")
     ap.add_argument("--eval-dirs", type=int, default=2, help="warm-start held-out directions")
     ap.add_argument("--scatterers", type=int, default=32, help="uneven-batch: march the first N of the 32")
-    ap.add_argument("--precision", default=None, choices=["f32", "f32a", "bf16", "bf16x2", "i8x4", "f64"],
-                    help="slab storage / history arithmetic (default: f32a = FP32 blocks with FP64 y and "
-                         "sums, for one wave and for uneven-batch; i8x4 = int8 digit blocks on the int8 matrix "
-                         "cores for torus-batched)")
+    ap.add_argument("--precision", default=None,
+                    choices=["f32", "f32a", "bf16", "bf16x2", "i8x4", "f64", "fac64", "fac32"],
+                    help="history form (default: fac32 = factored history, FP32 lag-banded raw matrices with FP64 "
+                         "products and sums, for one wave; f32a = FP32 blocks with FP64 y and sums for "
+                         "uneven-batch; i8x4 = int8 digit blocks on the int8 matrix cores for torus-batched)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 4 GiB device copy first (reference for profiler byte counters)")
     ap.add_argument("--solver", default="inv", choices=["lu", "inv"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="only the FP64 reference and the headline march")
+    ap.add_argument("--err-steps", type=int, default=0,
+                    help="steps of the untimed error marches (default: 600 for sphere-large, 300 for the torus)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="sphere-large: leave out the batched torus sub-record")
     ap.add_argument("--n-dirs", type=int, default=64, help="directions for torus-batched")
     a = ap.parse_args()
     if a.precision is None:
-        a.precision = {"torus-batched": "i8x4"}.get(a.workload, "f32a")
+        a.precision = {"torus-batched": "i8x4", "sphere-large": "fac32", "sphere-small": "fac32"}.get(
+            a.workload, "f32a")
     return a
 
 
@@ -420,26 +432,24 @@ def bench_spectral(a):
     print(json.dumps(out), flush=True)
 
 
-def main():
-    a = parse()
-    if a.gpus != 1:
-        print("bench.py measures one GPU only: the marching solver runs on a single MI355X "
-              "(--gpus %d is not supported)" % a.gpus, file=sys.stderr)
-        sys.exit(2)
+DENSE_ESZ = {"f64": 8, "f32": 4, "f32a": 4, "bf16": 2, "bf16x2": 4, "i8x4": 4}
+DTYPE = {"f32": "f32", "bf16": "bf16-storage/f32", "f32a": "f32-storage/f64-accumulate", "f64": "f64",
+         "bf16x2": "bf16-pair-storage/bf16-mfma/f32-accumulate",
+         "i8x4": "int8-digit-storage/int8-mfma/exact-int32-per-lag/f64-across-lags",
+         "fac64": "f64 (factored, lag-banded)", "fac32": "f32-band-storage/f64-products-and-sums (factored)"}
+
+
+def bench_single(a, cfg, precision, steps, warmup, err_steps, quick, with_cpu):
+    """One workload marched in the requested form and beside it the plain
+    FP64 path (LU and inverse) and the other forms (unless quick).  Timed
+    marches: warmup + steps from the start of the excitation.  Errors: every
+    form marched again for err_steps steps (untimed), max over steps of
+    |j_i - j_i^FP64| / max_i |j_i^FP64|."""
     import torch
     import paper_2312_06367_amd as qhp
-
-    torch.cuda.set_device(0)
-    if a.workload == "uneven-batch":
-        return bench_uneven(a)
-    if a.workload == "warm-start":
-        return bench_warm(a)
-    if a.workload == "spectral":
-        return bench_spectral(a)
-    cfg = workload(a.workload, a.n_dirs)
     xyz, tri = cfg.mesh
     n_rhs = len(cfg.waves)
-    n_total = a.warmup + a.steps
+    n_total = warmup + steps
     t0 = time.perf_counter()
     s = qhp.Solver(cfg.dt, precision="f64", solver="lu")
     s.mesh(xyz, tri)
@@ -448,39 +458,235 @@ def main():
     t_asm = time.perf_counter() - t0
     inf = s.info()
     ne, K = inf["ne"], inf["K"]
-    state = {"s": s}
-    log("%s: ne=%d K=%d n_rhs=%d assembly %.1f s" % (cfg.name, ne, K, n_rhs, t_asm))
+    raw_nnz = inf["raw_nnz"]
+    peak_step = int(max(w.t0 for w in cfg.waves) / cfg.dt)
+    n_err = max(err_steps, n_total)
+    log("%s: ne=%d K=%d n_rhs=%d assembly %.1f s; pulse peak near step %d, errors over %d steps"
+        % (cfg.name, ne, K, n_rhs, t_asm, peak_step, n_err))
 
-    def march(tag, solver, sv=None):
-        s = sv if sv is not None else state["s"]
-        s.set_solver(solver)
-        s.set_incident(cfg.waves, n_total)
+    def march(tag, solver, sv):
+        sv.set_solver(solver)
+        sv.set_incident(cfg.waves, n_total)
         jh = torch.zeros((n_total, ne, n_rhs), dtype=torch.float64, device="cuda")
-        s.run(a.warmup, jh[: a.warmup])
+        sv.run(warmup, jh[:warmup])
         torch.cuda.synchronize()
-        s.profile(True)
+        sv.profile(True)
         torch.cuda.synchronize()
         tw0 = time.perf_counter()
-        s.run(a.steps, jh[a.warmup:])
+        sv.run(steps, jh[warmup:])
         torch.cuda.synchronize()
         wall = time.perf_counter() - tw0
-        ms_hist, launches = s.hist_time()
-        s.profile(False)
+        ms_hist, launches = sv.hist_time()
+        band = sv.band_time()
+        sv.profile(False)
         hist = ms_hist / max(launches, 1)
-        log("%-9s %-3s: %d steps %.3f s = %.1f steps/s; history kernel %.3f ms (variant %d, %d splits)"
-            % (tag, solver, a.steps, wall, a.steps / wall, hist, s.info()["hist_variant"], s.info()["hist_splits"]))
-        return {"j": jh, "steps_per_s": a.steps / wall, "wall": wall, "hist_ms": hist,
-                "variant": s.info()["hist_variant"]}
+        info = sv.info()
+        log("%-9s %-3s: %d steps %.3f s = %.1f steps/s; history %.3f ms (variant %d, %d splits)"
+            % (tag, solver, steps, wall, steps / wall, hist, info["hist_variant"], info["hist_splits"]))
+        rec = {"steps_per_s": steps / wall, "wall": wall, "hist_ms": hist, "variant": info["hist_variant"],
+               "info": info}
+        if band[2] > 0:
+            rec["band_ms"] = (band[0] / band[2], band[1] / band[2])
+            log("%-9s %-3s: banded products %.3f ms (edge pairs) + %.3f ms (triangle pairs)"
+                % (tag, solver, rec["band_ms"][0], rec["band_ms"][1]))
+        return rec
 
-    def rel(jx, jref):
-        d = torch.linalg.vector_norm(jx - jref, dim=1).max().item()
-        return d / torch.linalg.vector_norm(jref, dim=1).max().item()
+    def err_march(sv):
+        sv.set_incident(cfg.waves, n_err)
+        jh = torch.zeros((n_err, ne, n_rhs), dtype=torch.float64, device="cuda")
+        for c0 in range(0, n_err, 500):  # progress between chunks
+            sv.run(min(500, n_err - c0), jh[c0:c0 + 500])
+            torch.cuda.synchronize()
+        return jh
 
-    def gbps(prec, hist_ms):
-        esz = {"f64": 8, "f32": 4, "f32a": 4, "bf16": 2, "bf16x2": 4, "i8x4": 4}[prec]
-        ysz = 8 if prec in ("f64", "f32a") else 4
-        return (K * ne * ne * esz + K * ne * n_rhs * ysz) / (hist_ms * 1e-3) / 1e9
+    ref = {}
 
+    def rel(jx):
+        jr = ref["j"]
+        d = torch.linalg.vector_norm(jx - jr, dim=1).max().item()
+        return d / torch.linalg.vector_norm(jr, dim=1).max().item()
+
+    runs = {}
+    diverged = {}
+    other = {"lu": "inv", "inv": "lu"}[a.solver]
+    runs["f64_lu"] = march("f64", "lu", s)
+    ref["j"] = err_march(s)
+    runs["f64_lu"]["err"] = 0.0
+    if not quick or a.solver == "inv":
+        runs["f64_inv"] = march("f64", "inv", s)
+        runs["f64_inv"]["err"] = rel(err_march(s))
+    fac = precision.startswith("fac")
+    dense_forms = [] if (fac and quick) else ([precision] if not fac else ["f32a"])
+    if precision == "f64":
+        dense_forms = []
+    for p in dense_forms:
+        s.set_precision(p)
+        for sol in ([a.solver] if quick else [a.solver, other]):
+            key = "%s_%s" % (p, sol)
+            runs[key] = march(p, sol, s)
+            runs[key]["err"] = rel(err_march(s))
+        if not quick and p in ("f32", "f32a"):
+            twin = "f32" if p == "f32a" else "f32a"
+            s.set_precision(twin)
+            key = "%s_%s" % (twin, a.solver)
+            runs[key] = march(twin, a.solver, s)
+            runs[key]["err"] = rel(err_march(s))
+    if not quick and n_rhs > 1:  # the other multi-right-hand-side forms, each assembled in its own storage
+        for p in ("f32", "bf16", "bf16x2", "i8x4"):
+            if p == precision:
+                continue
+            sv = qhp.Solver(cfg.dt, precision=p, solver=a.solver)
+            sv.mesh(xyz, tri)
+            sv.assemble()
+            key = "%s_%s" % (p, a.solver)
+            try:
+                runs[key] = march(p, a.solver, sv)
+                runs[key]["err"] = rel(err_march(sv))
+            except qhp.QhpError as e:  # a form that does not stay finite on this workload
+                log("%-9s %-3s: %s" % (p, a.solver, e))
+                runs.pop(key, None)
+                diverged[p] = str(e)
+            sv.close()
+    s.close()
+    torch.cuda.empty_cache()
+    if fac:  # the factored forms: their own assembly (raw lag matrices, bands)
+        t0 = time.perf_counter()
+        sf = qhp.Solver(cfg.dt, precision="fac64", solver=a.solver)
+        sf.mesh(xyz, tri)
+        sf.assemble()
+        torch.cuda.synchronize()
+        log("factored assembly %.1f s" % (time.perf_counter() - t0))
+        for p in (["fac64", "fac32"] if precision == "fac32" else ["fac64"]) if not quick else [precision]:
+            if p != sf.precision:
+                sf.set_precision(p)
+            key = "%s_%s" % (p, a.solver)
+            runs[key] = march(p, a.solver, sf)
+            runs[key]["err"] = rel(err_march(sf))
+        sf.close()
+        torch.cuda.empty_cache()
+    key = "%s_%s" % (precision, a.solver) if precision != "f64" else "f64_" + a.solver
+    head = runs[key]
+    hinf = head["info"]
+    flops_per_launch = 2.0 * K * ne * ne * n_rhs
+    ysz = 8 if precision in ("f64", "f32a") else 4
+    bytes_per_launch = K * ne * ne * DENSE_ESZ.get(precision, 8) + K * ne * n_rhs * ysz
+    if fac:
+        # the dominant kernel: the banded product over the edge pairs
+        fp32 = precision == "fac32"
+        kname = "k_band<%s, %d>" % ("float" if fp32 else "double", hinf["band_waves_pairs"])
+        kb = hinf["band_bytes_pairs"]
+        achieved = kb / (head["band_ms"][0] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_from_profile(kname),
+                "kernel": kname, "algorithmic_bytes_per_launch": kb, "kernel_ms_avg": head["band_ms"][0],
+                "values_per_launch": hinf["band_nnz_pairs"],
+                "triangle_pair_band": {"kernel": "k_band<%s, %d>" % ("float" if fp32 else "double",
+                                                                      hinf["band_waves_cells"]),
+                                       "bytes": hinf["band_bytes_cells"], "ms_avg": head["band_ms"][1],
+                                       "gbps": hinf["band_bytes_cells"] / (head["band_ms"][1] * 1e-3) / 1e9}}
+    elif n_rhs == 1:
+        kname = {"f64": "k_hist_gemv<double,double,double>", "f32": "k_hist_gemv<float,float,float>",
+                 "f32a": "k_hist_gemv<float,double,double>", "bf16": "k_hist_gemv<unsigned short,float,float>"}[precision]
+        achieved = bytes_per_launch / (head["hist_ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_from_profile(kname),
+                "kernel": kname, "algorithmic_bytes_per_launch": bytes_per_launch,
+                "kernel_ms_avg": head["hist_ms"]}
+    elif precision in ("bf16", "bf16x2"):
+        # BF16 matrix cores: five (pair) or two BF16 products per term; the
+        # streamed block bytes bound the kernel
+        kname = "k_hist_mfma<%s>" % ("true" if precision == "bf16x2" else "false")
+        achieved = bytes_per_launch / (head["hist_ms"] * 1e-3) / 1e9
+        products = 5 if precision == "bf16x2" else 2
+        executed = products * flops_per_launch / (head["hist_ms"] * 1e-3) / 1e12
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_from_profile(kname),
+                "kernel": kname, "algorithmic_bytes_per_launch": bytes_per_launch,
+                "kernel_ms_avg": head["hist_ms"],
+                "bf16_mfma_executed_tflops": executed, "bf16_mfma_frac": executed / BF16_MFMA_PEAK_TFLOPS}
+    elif precision == "i8x4":
+        # int8 matrix cores: 13 digit products per term, exact int32 sums per lag;
+        # the kernel is the autotuned variant (the library's variant table, in order)
+        kname = ["k_hist_i8<2,2,4,2,2>", "k_hist_i8d<2,2,4,2,2>", "k_hist_i8d<2,2,4,2,3>"][head["variant"]]
+        ops = 13 * flops_per_launch
+        achieved = ops / (head["hist_ms"] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": INT8_MFMA_PEAK_TOPS, "unit": "TOP/s",
+                "frac": achieved / INT8_MFMA_PEAK_TOPS, "traffic": traffic_from_profile(kname),
+                "kernel": kname, "algorithmic_int8_ops_per_launch": ops,
+                "kernel_ms_avg": head["hist_ms"],
+                "hbm_gbps": bytes_per_launch / (head["hist_ms"] * 1e-3) / 1e9}
+    else:
+        kname = "k_hist_gemm<float>" if precision == "f32" else "k_hist_gemm<double>"
+        peak = FP32_MFMA_PEAK_TFLOPS if precision == "f32" else FP64_MFMA_PEAK_TFLOPS
+        achieved = flops_per_launch / (head["hist_ms"] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": traffic_from_profile(kname),
+                "kernel": kname, "algorithmic_flops_per_launch": flops_per_launch,
+                "kernel_ms_avg": head["hist_ms"]}
+
+    def hist_gbps(key, rr):
+        p = key.split("_")[0]
+        if p.startswith("fac"):
+            return rr["info"]["slab_bytes"] / (rr["hist_ms"] * 1e-3) / 1e9
+        ys = 8 if p in ("f64", "f32a") else 4
+        return (K * ne * ne * DENSE_ESZ[p] + K * ne * n_rhs * ys) / (rr["hist_ms"] * 1e-3) / 1e9
+
+    forms = {}
+    for key, rr in runs.items():
+        forms[key] = {"steps_per_s": rr["steps_per_s"], "history_ms": rr["hist_ms"],
+                      "history_gbps": hist_gbps(key, rr), "rel_err_vs_fp64_lu": rr["err"],
+                      "history_bytes": rr["info"]["slab_bytes"]}
+        if "band_ms" in rr:
+            forms[key]["band_ms"] = list(rr["band_ms"])
+    for p, msg in diverged.items():
+        forms["%s_%s" % (p, a.solver)] = {"diverged": msg}
+    out = {
+        "metric": "MOT steps/s & history-sum HBM GB/s, batched FP32 vs plain FP64, rel err",
+        "value": head["steps_per_s"],
+        "unit": "MOT steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": 1e3 * head["wall"] / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[precision],
+        "data": "synthetic",
+        "config": {"workload": cfg.name, "ne": ne, "K": K, "c_dt_m": cfg.dt, "n_rhs": n_rhs,
+                   "history": precision, "solve": "fp64-" + a.solver, "post_processing": "fp64"},
+        "history_gbps": hist_gbps(key, head),
+        "rel_err_vs_fp64": head["err"],
+        "rel_err_steps": n_err,
+        "pulse_peak_step": peak_step,
+        "fp64_steps_per_s": runs["f64_lu"]["steps_per_s"],
+        "fp64_inv_steps_per_s": runs["f64_inv"]["steps_per_s"] if "f64_inv" in runs else None,
+        "forms": forms,
+        "assembly_s": t_asm,
+        "roofline": roof,
+        "raw_nnz": raw_nnz,
+        "dense_slab_bytes_fp32": K * ne * ne * 4,
+    }
+    if with_cpu:
+        out["cpu_baseline"] = cpu_baseline(ne, K)
+    return out
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py measures one GPU only: the marching solver runs on a single MI355X "
+              "(--gpus %d is not supported)" % a.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    torch.cuda.set_device(0)
+    if a.workload == "uneven-batch":
+        return bench_uneven(a)
+    if a.workload == "warm-start":
+        return bench_warm(a)
+    if a.workload == "spectral":
+        return bench_spectral(a)
     if a.calibrate_copy:
         # plain device copy of known size, for scaling HBM counters of the profiler
         nbytes = 1 << 32
@@ -491,133 +697,17 @@ def main():
         log("calibration copy: %d bytes read, %d bytes written" % (nbytes, nbytes))
         del src, dst
         torch.cuda.empty_cache()
-
-    runs = {}
-    diverged = {}
-    other = {"lu": "inv", "inv": "lu"}[a.solver]
-    runs["f64_lu"] = march("f64", "lu")
-    if not a.quick or a.solver == "inv":
-        runs["f64_inv"] = march("f64", "inv")
-    if a.precision != "f64":
-        s.set_precision(a.precision)
-        runs["head"] = march(a.precision, a.solver)
-        runs["%s_%s" % (a.precision, a.solver)] = runs["head"]
-        if not a.quick:
-            runs["%s_%s" % (a.precision, other)] = march(a.precision, other)
-            if a.precision in ("f32", "f32a"):
-                twin = "f32" if a.precision == "f32a" else "f32a"
-                s.set_precision(twin)
-                runs["%s_%s" % (twin, a.solver)] = march(twin, a.solver)
-            if n_rhs > 1:  # the other multi-right-hand-side forms, each assembled in its own storage
-                for p in ("f32", "bf16", "bf16x2", "i8x4"):
-                    if p == a.precision:
-                        continue
-                    sv = qhp.Solver(cfg.dt, precision=p, solver=a.solver)
-                    sv.mesh(xyz, tri)
-                    sv.assemble()
-                    try:
-                        runs["%s_%s" % (p, a.solver)] = march(p, a.solver, sv)
-                    except qhp.QhpError as e:  # a form that does not stay finite on this workload
-                        log("%-9s %-3s: %s" % (p, a.solver, e))
-                        diverged[p] = str(e)
-                    sv.close()
-    else:
-        runs["head"] = runs["f64_" + a.solver]
-    head = runs["head"]
-    jref = runs["f64_lu"]["j"]
-    esz = {"f64": 8, "f32": 4, "f32a": 4, "bf16": 2, "bf16x2": 4, "i8x4": 4}[a.precision]
-    ysz = 8 if a.precision in ("f64", "f32a") else 4
-    bytes_per_launch = K * ne * ne * esz + K * ne * n_rhs * ysz
-    flops_per_launch = 2.0 * K * ne * ne * n_rhs
-    if n_rhs == 1:
-        kname = {"f64": "k_hist_gemv<double,double,double>", "f32": "k_hist_gemv<float,float,float>",
-                 "f32a": "k_hist_gemv<float,double,double>", "bf16": "k_hist_gemv<unsigned short,float,float>"}[a.precision]
-        achieved = bytes_per_launch / (head["hist_ms"] * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_from_profile(kname),
-                "kernel": kname, "algorithmic_bytes_per_launch": bytes_per_launch,
-                "kernel_ms_avg": head["hist_ms"]}
-    elif a.precision in ("bf16", "bf16x2"):
-        # BF16 matrix cores: five (pair) or two BF16 products per term; the
-        # streamed block bytes bound the kernel
-        kname = "k_hist_mfma<%s>" % ("true" if a.precision == "bf16x2" else "false")
-        achieved = bytes_per_launch / (head["hist_ms"] * 1e-3) / 1e9
-        products = 5 if a.precision == "bf16x2" else 2
-        executed = products * flops_per_launch / (head["hist_ms"] * 1e-3) / 1e12
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_from_profile(kname),
-                "kernel": kname, "algorithmic_bytes_per_launch": bytes_per_launch,
-                "kernel_ms_avg": head["hist_ms"],
-                "bf16_mfma_executed_tflops": executed, "bf16_mfma_frac": executed / BF16_MFMA_PEAK_TFLOPS,
-                "fp32_equivalent_tflops": flops_per_launch / (head["hist_ms"] * 1e-3) / 1e12}
-    elif a.precision == "i8x4":
-        # int8 matrix cores: 13 digit products per term, exact int32 sums per lag;
-        # the kernel is the autotuned variant (the library's variant table, in order)
-        kname = ["k_hist_i8<2,2,4,2,2>", "k_hist_i8d<2,2,4,2,2>", "k_hist_i8d<2,2,4,2,3>"][head["variant"]]
-        ops = 13 * flops_per_launch
-        achieved = ops / (head["hist_ms"] * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": achieved, "peak": INT8_MFMA_PEAK_TOPS, "unit": "TOP/s",
-                "frac": achieved / INT8_MFMA_PEAK_TOPS, "traffic": traffic_from_profile(kname),
-                "kernel": kname, "algorithmic_int8_ops_per_launch": ops,
-                "kernel_ms_avg": head["hist_ms"],
-                "hbm_gbps": bytes_per_launch / (head["hist_ms"] * 1e-3) / 1e9,
-                "fp32_equivalent_tflops": flops_per_launch / (head["hist_ms"] * 1e-3) / 1e12,
-                "fp32_equivalent_frac_of_fp32_mfma_peak":
-                    flops_per_launch / (head["hist_ms"] * 1e-3) / 1e12 / FP32_MFMA_PEAK_TFLOPS}
-    else:
-        kname = "k_hist_gemm<float>"
-        achieved = flops_per_launch / (head["hist_ms"] * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "traffic": traffic_from_profile(kname),
-                "kernel": kname, "algorithmic_flops_per_launch": flops_per_launch,
-                "kernel_ms_avg": head["hist_ms"]}
-    forms = {}
-    for key, rr in runs.items():
-        if key == "head" or key in forms:
-            continue
-        prec = key.split("_")[0]
-        forms[key] = {"steps_per_s": rr["steps_per_s"], "history_ms": rr["hist_ms"],
-                      "history_gbps": gbps(prec, rr["hist_ms"]), "rel_err_vs_fp64_lu": rel(rr["j"], jref)}
-    for p, msg in diverged.items():
-        forms["%s_%s" % (p, a.solver)] = {"diverged": msg}
-    out = {
-        "metric": "MOT steps/s & history-sum HBM GB/s, batched FP32 vs plain FP64, rel err",
-        "value": head["steps_per_s"],
-        "unit": "MOT steps/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": 1e3 * head["wall"] / a.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": {"f32": "f32", "bf16": "bf16-storage/f32", "f32a": "f32-storage/f64-accumulate", "f64": "f64",
-                  "bf16x2": "bf16-pair-storage/bf16-mfma/f32-accumulate",
-                  "i8x4": "int8-digit-storage/int8-mfma/exact-int32-per-lag/f64-across-lags"}[a.precision],
-        "data": "synthetic",
-        "config": {"workload": cfg.name, "ne": ne, "K": K, "c_dt_m": cfg.dt, "n_rhs": n_rhs,
-                   "slab_storage": a.precision, "solve": "fp64-" + a.solver, "post_processing": "fp64"},
-        "history_gbps": gbps(a.precision, head["hist_ms"]),
-        "rel_err_vs_fp64": rel(head["j"], jref),
-        "fp64_steps_per_s": runs["f64_lu"]["steps_per_s"],
-        "forms": forms,
-        "assembly_s": t_asm,
-        "roofline": roof,
-        # bytes per step of a history that streams the raw lag matrices
-        # instead of the dense blocks: with a 4-byte index per nonzero and
-        # the two preconditioner products, or lag-banded per edge pair (no
-        # index per nonzero) with the four dense products of that form
-        "factored_history_floor": {
-            "raw_nnz": inf["raw_nnz"],
-            "bytes_fp32": inf["raw_nnz"] * (4 + 4) + 2 * ne * ne * 4,
-            "bytes_fp32_lag_banded": inf["raw_nnz"] * 4 + 4 * ne * ne * 4,
-            "dense_slab_bytes_fp32": K * ne * ne * 4,
-            "dense_over_floor": K * ne * ne * 4 / (inf["raw_nnz"] * (4 + 4) + 2 * ne * ne * 4),
-            "dense_over_lag_banded": K * ne * ne * 4 / (inf["raw_nnz"] * 4 + 4 * ne * ne * 4)},
-    }
-    if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(ne, K)
-    s.close()
+    cfg = workload(a.workload, a.n_dirs)
+    err_steps = a.err_steps if a.err_steps else {"sphere-large": 600, "torus-batched": 300}.get(a.workload, 400)
+    out = bench_single(a, cfg, a.precision, a.steps, a.warmup, err_steps, a.quick, not a.no_cpu_baseline)
+    if a.workload == "sphere-large" and not a.no_batched:
+        # the batched form: torus 6000 edges x 128 waves, int8 digits against FP64
+        tor = workload("torus-batched", 64)
+        sub = bench_single(a, tor, "i8x4", min(a.steps, 300), min(a.warmup, 20), 300, True, False)
+        out["batched"] = {k: sub[k] for k in ("value", "unit", "steps", "warmup", "ms_per_step", "dtype", "config",
+                                              "history_gbps", "rel_err_vs_fp64", "rel_err_steps",
+                                              "pulse_peak_step", "fp64_steps_per_s", "fp64_inv_steps_per_s",
+                                              "forms", "roofline")}
     print(json.dumps(out), flush=True)
 
 

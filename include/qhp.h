@@ -180,6 +180,12 @@ typedef struct {
     int64_t raw_nnz;      /* nonzeros of the raw lag matrices A_k, B_k, C_k,
                              k = 1..K (Sec. IV-A): the shell-sparse operands
                              a factored history would stream instead of T_k */
+    /* factored history of the precision in use (zeros for dense storage):
+       the edge-pair band [A_k; C_k] and the triangle-pair band Sq_k */
+    size_t band_bytes_pairs, band_bytes_cells;  /* stream bytes (runs, words) */
+    int64_t band_nnz_pairs, band_nnz_cells;     /* values stored in the runs  */
+    int64_t band_waves_pairs, band_waves_cells; /* waves per work-group of
+                                                   their product kernels     */
 } qhp_info;
 
 /* Create a context (no device work beyond selecting params->device).
@@ -260,6 +266,12 @@ int qhp_release_assembly(qhp_ctx *ctx);
  * summed kernel time in ms and the number of timed launches since enabling. */
 int qhp_profile(qhp_ctx *ctx, int32_t enable);
 int qhp_hist_time(qhp_ctx *ctx, double *ms_total, int64_t *launches);
+/* Factored history (QHP_FAC64, QHP_FAC32) while profiling: the summed times
+ * (ms, HIP events on the context's stream) of the banded product over the
+ * edge pairs (A_k, C_k) and of the one over the triangle pairs (Sq_k), and the
+ * number of steps timed since profiling was enabled; zeros for dense storage.
+ * QHP_EINVAL on a null argument. */
+int qhp_band_time(qhp_ctx *ctx, double *ms_pairs, double *ms_cells, int64_t *launches);
 
 /* Right-hand sides r_k = -Z~ G^-T e~(t_k) + eta_c X~ G^-1 h(t_k), k = 1..n_steps
  * (Sec. IV-A), for n_rhs waves (host array).  Resets the march to step 0. */

@@ -90,11 +90,14 @@ class _Info(ctypes.Structure):
                 ("n_harmonic", ctypes.c_int64), ("K", ctypes.c_int64), ("n_rhs", ctypes.c_int64),
                 ("n_steps", ctypes.c_int64), ("step", ctypes.c_int64), ("ld", ctypes.c_int64),
                 ("diameter", ctypes.c_double), ("slab_bytes", ctypes.c_size_t),
-                ("hist_variant", ctypes.c_int64), ("hist_splits", ctypes.c_int64), ("raw_nnz", ctypes.c_int64)]
+                ("hist_variant", ctypes.c_int64), ("hist_splits", ctypes.c_int64), ("raw_nnz", ctypes.c_int64),
+                ("band_bytes_pairs", ctypes.c_size_t), ("band_bytes_cells", ctypes.c_size_t),
+                ("band_nnz_pairs", ctypes.c_int64), ("band_nnz_cells", ctypes.c_int64),
+                ("band_waves_pairs", ctypes.c_int64), ("band_waves_cells", ctypes.c_int64)]
 
 
 EXPORTS = ["qhp_create", "qhp_mesh", "qhp_assemble", "qhp_set_precision", "qhp_set_solver", "qhp_profile",
-           "qhp_hist_time", "qhp_set_incident", "qhp_step", "qhp_run", "qhp_query", "qhp_edges",
+           "qhp_hist_time", "qhp_band_time", "qhp_set_incident", "qhp_step", "qhp_run", "qhp_query", "qhp_edges",
            "qhp_get_matrix", "qhp_keep_raw", "qhp_history_sum", "qhp_history_sum_variant", "qhp_history_variants",
            "qhp_t0_condition", "qhp_batch_create", "qhp_batch_create_variant", "qhp_batch_variants", "qhp_batch_history_variant",
            "qhp_batch_run",
@@ -126,6 +129,8 @@ def lib():
         L.qhp_set_solver.argtypes = [vp, i32]
         L.qhp_profile.argtypes = [vp, i32]
         L.qhp_hist_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+        L.qhp_band_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(i64)]
         L.qhp_set_incident.argtypes = [vp, ctypes.POINTER(_Wave), i32, i32]
         L.qhp_step.argtypes = [vp, vp]
         L.qhp_run.argtypes = [vp, i32, vp, vp]
@@ -270,6 +275,14 @@ class Solver:
         n = ctypes.c_int64()
         self._check(self.L.qhp_hist_time(self.h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    def band_time(self):
+        """factored history: summed ms of the edge-pair and triangle-pair
+        banded products and the steps timed (qhp_band_time)"""
+        a, b = ctypes.c_double(), ctypes.c_double()
+        n = ctypes.c_int64()
+        self._check(self.L.qhp_band_time(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(n)))
+        return a.value, b.value, n.value
 
     def set_incident(self, waves, n_steps: int):
         arr = (_Wave * len(waves))(*[to_cwave(w) for w in waves])

@@ -917,9 +917,18 @@ static void do_step(qhp_ctx *c, double *j_out, double *y_out)
         qhp_ctx::FacState &f = *c->fac;
         const bool fp32 = c->p.precision == QHP_FAC32;
         const qhp::Band &bac = fp32 ? f.ac32 : f.ac64, &bsq = fp32 ? f.sq32 : f.sq64;
+        hipEvent_t eb[3] = {nullptr, nullptr, nullptr};
+        if (c->profiling)
+            for (hipEvent_t &e : eb) {
+                hip_check(hipEventCreate(&e), "event");
+                c->ev_band.push_back(e);
+            }
         if (e0) hip_check(hipEventRecord(e0, s), "event");
+        if (eb[0]) hip_check(hipEventRecord(eb[0], s), "event");
         qhp::launch_band(s, bac, fp32, f.jx.as<double>(), ld, K, c->head, K, f.pac.as<double>());
+        if (eb[1]) hip_check(hipEventRecord(eb[1], s), "event");
         qhp::launch_band(s, bsq, fp32, f.cq.as<double>(), nc, K, c->head, 0, f.ps.as<double>());
+        if (eb[2]) hip_check(hipEventRecord(eb[2], s), "event");
         qhp::launch_fac_combine(s, ne, nc, c->args.cells, c->args.area, c->T0, f.einv.as<int32_t>(),
                                 f.cinv.as<int32_t>(), f.pac.as<double>(), bac.nsplit, f.ps.as<double>(), bsq.nsplit,
                                 f.em.as<double>(), ld);
@@ -1016,6 +1025,17 @@ static void collect_events(qhp_ctx *c)
     }
     for (auto e : c->ev) (void)hipEventDestroy(e);
     c->ev.clear();
+    for (size_t q = 0; q + 2 < c->ev_band.size(); q += 3) {
+        float a = 0.f, b = 0.f;
+        if (hipEventElapsedTime(&a, c->ev_band[q], c->ev_band[q + 1]) == hipSuccess &&
+            hipEventElapsedTime(&b, c->ev_band[q + 1], c->ev_band[q + 2]) == hipSuccess) {
+            c->band_ms[0] += a;
+            c->band_ms[1] += b;
+            c->band_launches += 1;
+        }
+    }
+    for (auto e : c->ev_band) (void)hipEventDestroy(e);
+    c->ev_band.clear();
 }
 
 static int finish_run(qhp_ctx *c)
@@ -1151,6 +1171,17 @@ extern "C" int qhp_profile(qhp_ctx *ctx, int32_t enable)
     ctx->profiling = enable != 0;
     ctx->hist_ms = 0.0;
     ctx->hist_launches = 0;
+    ctx->band_ms[0] = ctx->band_ms[1] = 0.0;
+    ctx->band_launches = 0;
+    return QHP_OK;
+}
+
+extern "C" int qhp_band_time(qhp_ctx *ctx, double *ms_pairs, double *ms_cells, int64_t *launches)
+{
+    if (!ctx || !ms_pairs || !ms_cells || !launches) return QHP_EINVAL;
+    *ms_pairs = ctx->band_ms[0];
+    *ms_cells = ctx->band_ms[1];
+    *launches = ctx->band_launches;
     return QHP_OK;
 }
 
@@ -1232,8 +1263,14 @@ extern "C" int qhp_query(const qhp_ctx *ctx, qhp_info *info)
     if (ctx->fac) {  // the bands and [P_E P_M] of the precision in use
         const bool fp32 = ctx->p.precision == QHP_FAC32;
         const qhp_ctx::FacState &f = *ctx->fac;
-        info->slab_bytes = (fp32 ? f.ac32.bytes + f.sq32.bytes : f.ac64.bytes + f.sq64.bytes) +
-                           (size_t)2 * m.ne * ctx->ld * (fp32 ? 4 : 8);
+        const qhp::Band &ac = fp32 ? f.ac32 : f.ac64, &sq = fp32 ? f.sq32 : f.sq64;
+        info->slab_bytes = ac.bytes + sq.bytes + (size_t)2 * m.ne * ctx->ld * (f.pem_prec == QHP_F64 ? 8 : 4);
+        info->band_bytes_pairs = ac.bytes;
+        info->band_bytes_cells = sq.bytes;
+        info->band_nnz_pairs = ac.nnz;
+        info->band_nnz_cells = sq.nnz;
+        info->band_waves_pairs = ac.waves;
+        info->band_waves_cells = sq.waves;
     }
     info->n_rhs = ctx->nrhs;
     info->n_steps = ctx->n_steps;

@@ -144,6 +144,11 @@ struct qhp_ctx {
     std::vector<hipEvent_t> ev;
     double hist_ms = 0.0;
     int64_t hist_launches = 0;
+    // factored history: events before the edge-pair product, between it and
+    // the triangle-pair product, after that (triples); their summed times
+    std::vector<hipEvent_t> ev_band;
+    double band_ms[2] = {0.0, 0.0};
+    int64_t band_launches = 0;
     bool verbose = false;
     std::chrono::steady_clock::time_point t_stage;
     void stage(const char *name)

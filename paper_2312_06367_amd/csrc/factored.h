@@ -15,15 +15,15 @@
 
 namespace qhp {
 
-// A work-group of the banded product: `waves` waves (16, 12, 8, 6 or 4,
+// A work-group of the banded product: `waves` waves (16, 12, 8, 4 or 2,
 // chosen at build time with the size of the copy batches so that the staged x
 // and two batch buffers a wave fit the LDS), each taking kBandRowsPerWave
 // rows (one row block) over one split of the kBandChunk-column chunks.
 constexpr int kBandRowsPerWave = 16;
 constexpr int kBandChunk = 32;
 constexpr int kBandLdsBytes = 160 * 1024;
-constexpr int kBandMaxPieces = 16;  // 1 KB copy pieces of a batch, at most
 constexpr int kBandStep = 8;        // lags a lane takes per step of the walk
+constexpr int kBandPrefetchLags = 128;  // lags of a chunk's x loaded ahead through registers
 
 // One lag-banded family of matrices X_k, k in [lag0, lag1], rows x cols.
 // Rows 2q, 2q + 1 and the chunk ch of kBandChunk columns form the group

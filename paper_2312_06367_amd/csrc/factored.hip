@@ -123,8 +123,19 @@ __global__ __launch_bounds__(256) void k_band_fill(int64_t rows, int64_t cols, i
     }
 }
 
-// the work-group sizes (waves) the product kernel is built for
-static const int kBandWaves[] = {16, 12, 8, 6, 4};
+// the work-group shapes the product kernel is built for: waves, and 1 KB
+// copy pieces per batch (two batch buffers a wave, 160 KB of LDS at most);
+// the 2-wave shapes take the groups of very long runs (coarse meshes)
+static const int kBandWaves[] = {16, 12, 8, 4, 2};
+static const int kBandPieces[] = {2, 3, 4, 5, 6, 8, 10, 12, 14, 16, 20, 24, 32};
+static bool band_shape_built(int w, int p)
+{
+    bool listed = false;
+    for (int q : kBandPieces) listed = listed || q == p;
+    for (int v : kBandWaves)
+        if (v == w) return listed && 2 * w * p <= 160;
+    return false;
+}
 
 // rows of the staged x: the tile lags, then zero rows that a lane stepping
 // past its run may read (at most the longest run plus a step)
@@ -136,6 +147,32 @@ static size_t band_lds(int tmax, int lmax, int waves, int np, bool fp32)
 {
     return (size_t)band_xrows(tmax, lmax) * CW * sizeof(double) + (size_t)waves * 2 * np * 1024 +
            (size_t)(lmax + kBandStep) * (fp32 ? 4 : 8);
+}
+
+// chunk splits of the product: one work-group per CU (the LDS holds one), at
+// least four rounds of them over the 256 CUs, the last round as full as it
+// can be (fraction of busy work-group slots), then the fewest work-groups
+static int band_splits(int64_t nrb, int64_t nch)
+{
+    constexpr int64_t kCUs = 256;
+    if (nrb * nch <= 4 * kCUs) return (int)nch;
+    int best = 1;
+    double best_eff = -1.0;
+    int64_t best_n = 0;
+    for (int64_t ns = 1; ns <= nch; ++ns) {
+        const int64_t cps = (nch + ns - 1) / ns, real = (nch + cps - 1) / cps;  // splits that hold chunks
+        const int64_t n = nrb * real;
+        if (n < 4 * kCUs || real != ns) continue;
+        if (n > 8 * kCUs) break;
+        const double eff = (double)n / (double)(((n + kCUs - 1) / kCUs) * kCUs);
+        if (eff > best_eff + 1e-9 || (eff > best_eff - 1e-9 && n < best_n)) {
+            best = (int)ns;
+            best_eff = eff;
+            best_n = n;
+        }
+    }
+    if (best_eff < 0) return (int)std::max<int64_t>(1, std::min<int64_t>(nch, (4 * kCUs + nrb - 1) / nrb));
+    return best;
 }
 
 void build_band(hipStream_t s, int64_t rows, int64_t cols, int64_t lag0, int64_t lag1, const double *srcA,
@@ -205,8 +242,9 @@ void build_band(hipStream_t s, int64_t rows, int64_t cols, int64_t lag0, int64_t
     int waves = 0, np = 0, tmax = 0;
     for (int w : kBandWaves) {
         const int tm = tiles((int64_t)w * kBandRowsPerWave / 2, tw);
-        int p = 0;
-        while (p < kBandMaxPieces && band_lds(tm, lm, w, p + 1, fp32) <= (size_t)kBandLdsBytes) ++p;
+        int p = 0;  // the largest batch built for this size that fits
+        for (int q : kBandPieces)
+            if (band_shape_built(w, q) && band_lds(tm, lm, w, q, fp32) <= (size_t)kBandLdsBytes) p = q;
         if (p < npmin) continue;
         if (w * p > waves * np) {
             waves = w;
@@ -261,9 +299,7 @@ void build_band(hipStream_t s, int64_t rows, int64_t cols, int64_t lag0, int64_t
     hipLaunchKernelGGL(k_band_fill, dim3(nblk(ng * 64, 256)), dim3(256), 0, s, rows, cols, nch, ng, qpb, src, fp32,
                        out.hdr.as<uint64_t>(), meta.as<uint32_t>(), out.stream.as<char>());
     hip_check(hipStreamSynchronize(s), "band fill");
-    // chunk splits: about four rounds of one work-group per CU
-    const int64_t want = (1024 + out.nrb - 1) / out.nrb;
-    out.nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(want, nch));
+    out.nsplit = band_splits(out.nrb, nch);
 }
 
 namespace {
@@ -307,17 +343,23 @@ __device__ __forceinline__ double masked(float v, bool keep)
 }
 __device__ __forceinline__ double masked(double v, bool keep) { return keep ? v : 0.0; }
 
-__device__ __forceinline__ void wait_vm(int n)
+// work-group barrier for data shared through LDS only: the wave's LDS
+// accesses complete (lgkmcnt(0)), then s_barrier; global loads and copies in
+// flight stay in flight (a __syncthreads fence waits for them too).  The
+// empty asm statements keep the compiler from moving memory accesses across.
+__device__ __forceinline__ void lds_barrier()
 {
-    // s_waitcnt vmcnt(n), lgkmcnt and expcnt left alone; n is wave-uniform
-    switch (n) {
-#define QHP_VM(N) \
-    case N: __builtin_amdgcn_s_waitcnt((((N) & 15) | (7 << 4) | (15 << 8) | (((N) >> 4) << 14))); break;
-        QHP_VM(0) QHP_VM(1) QHP_VM(2) QHP_VM(3) QHP_VM(4) QHP_VM(5) QHP_VM(6) QHP_VM(7) QHP_VM(8)
-        QHP_VM(9) QHP_VM(10) QHP_VM(11) QHP_VM(12) QHP_VM(13) QHP_VM(14) QHP_VM(15) QHP_VM(16)
-#undef QHP_VM
-    default: __builtin_amdgcn_s_waitcnt((7 << 4) | (15 << 8)); break;
-    }
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt((15) | (7 << 4) | (0 << 8) | (3 << 14));  // lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// s_waitcnt vmcnt(N), lgkmcnt and expcnt left alone
+template <int N>
+__device__ __forceinline__ void wait_vm()
+{
+    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
 }
 
 }  // namespace
@@ -335,8 +377,8 @@ __device__ __forceinline__ void wait_vm(int n)
 // place among the values; the wave steps over the longest run kBandStep lags
 // at a time, a lane past its own run adding zero products.  FP64 sums per lane,
 // reduced over each half-wave (one row) at the end, one partial per split.
-template <typename T, int W>
-__global__ __launch_bounds__(64 * W) void k_band(int64_t rows, int64_t nch, int64_t cps, int np,
+template <typename T, int W, int NP>
+__global__ __launch_bounds__(64 * W) void k_band(int64_t rows, int64_t nch, int64_t cps,
                                                  const uint64_t *__restrict__ hdr, const uint32_t *__restrict__ tile,
                                                  const char *__restrict__ stream, const double *__restrict__ x,
                                                  int64_t ldx, int64_t K, int64_t head, int64_t slot0, int xrows,
@@ -348,7 +390,7 @@ __global__ __launch_bounds__(64 * W) void k_band(int64_t rows, int64_t nch, int6
     // the wave index is uniform: group quantities below stay in scalar registers
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int col = lane & (CW - 1);
-    const int64_t batch = (int64_t)np * 1024;
+    constexpr int64_t batch = (int64_t)NP * 1024;
     char *bufs = reinterpret_cast<char *>(smem + (int64_t)xrows * CW) + (int64_t)wave * 2 * batch;
     const int64_t rb = blockIdx.x, sp = blockIdx.y;
     const int64_t c0 = sp * cps, c1 = (c0 + cps < nch) ? c0 + cps : nch;
@@ -390,36 +432,59 @@ __global__ __launch_bounds__(64 * W) void k_band(int64_t rows, int64_t nch, int6
     };
     auto issue = [&](int64_t ch, int q0, char *dst) {
         const char *src = stream + (H[hidx(ch, q0)] & ((1ull << 40) - 1)) * 16;
-        for (int pc = 0; pc < np; ++pc)
+#pragma unroll
+        for (int pc = 0; pc < NP; ++pc)
             __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(src + pc * 1024 + lane * 16),
                                              (__attribute__((address_space(3))) void *)(dst + pc * 1024), 16, 0, 0);
     };
+    // x of a chunk's tile: element idx = lag row idx / CW, column idx % CW;
+    // the first XR * 64 W elements go through registers, loaded a chunk ahead
+    constexpr int XR = (kBandPrefetchLags * CW + 64 * W - 1) / (64 * W);
+    auto x_at = [&](int64_t ch, int tk0, int idx) {
+        const int64_t k = tk0 + idx / CW, cc = ch * CW + idx % CW;
+        const int64_t slot = k == 0 ? slot0 : (head + k - 1) % K;
+        return cc < ldx ? x[slot * ldx + cc] : 0.0;
+    };
+    double xpre[XR];
+    auto prefetch = [&](int64_t ch, int tk0, int ntk) {
+#pragma unroll
+        for (int r = 0; r < XR; ++r) {
+            const int idx = threadIdx.x + r * 64 * W;
+            xpre[r] = idx < ntk * CW ? x_at(ch, tk0, idx) : 0.0;
+        }
+    };
     // zero rows past any tile: read (and discarded) by lanes past their runs
     for (int idx = threadIdx.x; idx < xrows * CW; idx += 64 * W) X[idx] = 0.0;
+    uint32_t tl_next = c0 < c1 ? TL[rb * nch + c0] : 0u;
+    prefetch(c0, (int)(tl_next & 0xffff), (int)(tl_next >> 16));
     int64_t bch = c0;
     int bq0 = 0, bq1 = 0, cur = 0;
     bool have = ngw > 0 && next_batch(bch, bq0, bq1);
     if (have) issue(bch, bq0, bufs);
     for (int64_t ch = c0; ch < c1; ++ch) {
-        const uint32_t tl = TL[rb * nch + ch];
+        const uint32_t tl = tl_next;
         const int tk0 = (int)(tl & 0xffff), ntk = (int)(tl >> 16);
-        __syncthreads();  // every wave is done with the previous chunk's x
-        for (int idx = threadIdx.x; idx < ntk * CW; idx += 64 * W) {
-            const int l = idx / CW, c = idx % CW;
-            const int64_t k = tk0 + l, cc = ch * CW + c;
-            const int64_t slot = k == 0 ? slot0 : (head + k - 1) % K;
-            X[idx] = cc < ldx ? x[slot * ldx + cc] : 0.0;
+        lds_barrier();  // every wave is done with the previous chunk's x
+#pragma unroll
+        for (int r = 0; r < XR; ++r) {
+            const int idx = threadIdx.x + r * 64 * W;
+            if (idx < ntk * CW) X[idx] = xpre[r];
         }
-        __syncthreads();
+        for (int idx = threadIdx.x + XR * 64 * W; idx < ntk * CW; idx += 64 * W) X[idx] = x_at(ch, tk0, idx);
+        lds_barrier();
+        if (ch + 1 < c1) {  // the next chunk's x, in flight during this chunk's walk
+            tl_next = TL[rb * nch + ch + 1];
+            prefetch(ch + 1, (int)(tl_next & 0xffff), (int)(tl_next >> 16));
+        }
         while (have && bch == ch) {
             int64_t nch_ = bch;
             int nq0 = bq1, nq1 = 0;
             const bool nhave = next_batch(nch_, nq0, nq1);
             if (nhave) {
                 issue(nch_, nq0, bufs + (1 - cur) * batch);
-                wait_vm(np);
+                wait_vm<NP>();
             } else {
-                wait_vm(0);
+                wait_vm<0>();
             }
             const char *buf = bufs + cur * batch;
             int64_t goff = 0;
@@ -459,6 +524,9 @@ __global__ __launch_bounds__(64 * W) void k_band(int64_t rows, int64_t nch, int6
             have = nhave;
             cur = 1 - cur;
         }
+        // at most the batch in flight is outstanding (a no-op after a walk):
+        // the next chunk's x, loaded before it, is complete
+        wait_vm<NP>();
     }
 #pragma unroll
     for (int q = 0; q < GW; ++q) {
@@ -474,23 +542,36 @@ __global__ __launch_bounds__(64 * W) void k_band(int64_t rows, int64_t nch, int6
         }
 }
 
-template <typename T, int W>
+template <typename T, int W, int NP>
 static void band_launch(hipStream_t s, const Band &b, bool fp32, const double *x, int64_t ldx, int64_t K,
                         int64_t head, int64_t slot0, double *part)
 {
     const int64_t cps = (b.nch + b.nsplit - 1) / b.nsplit;
-    const size_t lds = band_lds(b.tmax, b.lmax, W, b.np, fp32);
+    const size_t lds = band_lds(b.tmax, b.lmax, W, NP, fp32);
     static bool attr = false;
     if (!attr) {
-        hip_check(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_band<T, W>),
+        hip_check(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_band<T, W, NP>),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, kBandLdsBytes),
                   "band kernel attribute");
         attr = true;
     }
     const int xrows = band_xrows(b.tmax, b.lmax);
-    hipLaunchKernelGGL((k_band<T, W>), dim3((unsigned)b.nrb, (unsigned)b.nsplit), dim3(64 * W), lds, s, b.rows,
-                       b.nch, cps, b.np, b.hdr.as<uint64_t>(), b.tile.as<uint32_t>(), b.stream.as<char>(), x, ldx, K,
+    hipLaunchKernelGGL((k_band<T, W, NP>), dim3((unsigned)b.nrb, (unsigned)b.nsplit), dim3(64 * W), lds, s, b.rows,
+                       b.nch, cps, b.hdr.as<uint64_t>(), b.tile.as<uint32_t>(), b.stream.as<char>(), x, ldx, K,
                        head, slot0, xrows, part);
+}
+
+template <typename T, int W>
+static void band_pieces(hipStream_t s, const Band &b, bool fp32, const double *x, int64_t ldx, int64_t K,
+                        int64_t head, int64_t slot0, double *part)
+{
+#define QHP_NP(P)                                                                    \
+    if constexpr (2 * W * P <= 160)                                                  \
+        if (b.np == P) return band_launch<T, W, P>(s, b, fp32, x, ldx, K, head, slot0, part);
+    QHP_NP(2) QHP_NP(3) QHP_NP(4) QHP_NP(5) QHP_NP(6) QHP_NP(8) QHP_NP(10) QHP_NP(12) QHP_NP(14) QHP_NP(16)
+    QHP_NP(20) QHP_NP(24) QHP_NP(32)
+#undef QHP_NP
+    throw Fail{QHP_EINVAL, "band kernel shape not built"};
 }
 
 template <typename T>
@@ -498,11 +579,11 @@ static void band_dispatch(hipStream_t s, const Band &b, bool fp32, const double 
                           int64_t head, int64_t slot0, double *part)
 {
     switch (b.waves) {
-    case 16: band_launch<T, 16>(s, b, fp32, x, ldx, K, head, slot0, part); return;
-    case 12: band_launch<T, 12>(s, b, fp32, x, ldx, K, head, slot0, part); return;
-    case 8: band_launch<T, 8>(s, b, fp32, x, ldx, K, head, slot0, part); return;
-    case 6: band_launch<T, 6>(s, b, fp32, x, ldx, K, head, slot0, part); return;
-    case 4: band_launch<T, 4>(s, b, fp32, x, ldx, K, head, slot0, part); return;
+    case 16: return band_pieces<T, 16>(s, b, fp32, x, ldx, K, head, slot0, part);
+    case 12: return band_pieces<T, 12>(s, b, fp32, x, ldx, K, head, slot0, part);
+    case 8: return band_pieces<T, 8>(s, b, fp32, x, ldx, K, head, slot0, part);
+    case 4: return band_pieces<T, 4>(s, b, fp32, x, ldx, K, head, slot0, part);
+    case 2: return band_pieces<T, 2>(s, b, fp32, x, ldx, K, head, slot0, part);
     default: throw Fail{QHP_EINVAL, "band kernel shape not built"};
     }
 }
@@ -510,7 +591,7 @@ static void band_dispatch(hipStream_t s, const Band &b, bool fp32, const double 
 void launch_band(hipStream_t s, const Band &b, bool fp32, const double *x, int64_t ldx, int64_t K, int64_t head,
                  int64_t slot0, double *part)
 {
-    if (b.np < 1 || b.np > kBandMaxPieces) throw Fail{QHP_EINVAL, "band batch size out of range"};
+    if (!band_shape_built(b.waves, b.np)) throw Fail{QHP_EINVAL, "band kernel shape not built"};
     if (fp32) band_dispatch<float>(s, b, fp32, x, ldx, K, head, slot0, part);
     else band_dispatch<double>(s, b, fp32, x, ldx, K, head, slot0, part);
 }

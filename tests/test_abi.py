@@ -54,6 +54,7 @@ def test_batch_tile_shape_counts():
 _HANDLE_CALLS = {
     "qhp_keep_raw": 1, "qhp_mesh": 4, "qhp_assemble": 0, "qhp_set_precision": 1, "qhp_t0_condition": 3,
     "qhp_set_solver": 1, "qhp_release_assembly": 0, "qhp_profile": 1, "qhp_hist_time": 2,
+    "qhp_band_time": 3,
     "qhp_set_incident": 3, "qhp_step": 1, "qhp_run": 3, "qhp_query": 1, "qhp_edges": 2, "qhp_get_matrix": 3,
     "qhp_batch_run": 2, "qhp_batch_step_times": 2, "qhp_set_gmres": 4, "qhp_gmres_stats": 4,
     "qhp_gmres_reset": 0, "qhp_mlp_create": 3, "qhp_mlp_dims": 3, "qhp_mlp_set_params": 1,
