@@ -573,15 +573,17 @@ def bench_single(a, cfg, precision, steps, warmup, err_steps, quick, with_cpu):
     if fac:
         # the dominant kernel: the banded product over the edge pairs
         fp32 = precision == "fac32"
-        kname = "k_band<%s, %d>" % ("float" if fp32 else "double", hinf["band_waves_pairs"])
+        kname = "k_band<%s, %d, %d>" % ("float" if fp32 else "double", hinf["band_waves_pairs"],
+                                         hinf["band_pieces_pairs"])
         kb = hinf["band_bytes_pairs"]
         achieved = kb / (head["band_ms"][0] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_from_profile(kname),
                 "kernel": kname, "algorithmic_bytes_per_launch": kb, "kernel_ms_avg": head["band_ms"][0],
                 "values_per_launch": hinf["band_nnz_pairs"],
-                "triangle_pair_band": {"kernel": "k_band<%s, %d>" % ("float" if fp32 else "double",
-                                                                      hinf["band_waves_cells"]),
+                "triangle_pair_band": {"kernel": "k_band<%s, %d, %d>" % ("float" if fp32 else "double",
+                                                                          hinf["band_waves_cells"],
+                                                                          hinf["band_pieces_cells"]),
                                        "bytes": hinf["band_bytes_cells"], "ms_avg": head["band_ms"][1],
                                        "gbps": hinf["band_bytes_cells"] / (head["band_ms"][1] * 1e-3) / 1e9}}
     elif n_rhs == 1:

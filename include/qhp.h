@@ -186,6 +186,8 @@ typedef struct {
     int64_t band_nnz_pairs, band_nnz_cells;     /* values stored in the runs  */
     int64_t band_waves_pairs, band_waves_cells; /* waves per work-group of
                                                    their product kernels     */
+    int64_t band_pieces_pairs, band_pieces_cells; /* 1 KB copy pieces per
+                                                     batch of those kernels  */
 } qhp_info;
 
 /* Create a context (no device work beyond selecting params->device).

@@ -93,7 +93,8 @@ class _Info(ctypes.Structure):
                 ("hist_variant", ctypes.c_int64), ("hist_splits", ctypes.c_int64), ("raw_nnz", ctypes.c_int64),
                 ("band_bytes_pairs", ctypes.c_size_t), ("band_bytes_cells", ctypes.c_size_t),
                 ("band_nnz_pairs", ctypes.c_int64), ("band_nnz_cells", ctypes.c_int64),
-                ("band_waves_pairs", ctypes.c_int64), ("band_waves_cells", ctypes.c_int64)]
+                ("band_waves_pairs", ctypes.c_int64), ("band_waves_cells", ctypes.c_int64),
+                ("band_pieces_pairs", ctypes.c_int64), ("band_pieces_cells", ctypes.c_int64)]
 
 
 EXPORTS = ["qhp_create", "qhp_mesh", "qhp_assemble", "qhp_set_precision", "qhp_set_solver", "qhp_profile",

@@ -1271,6 +1271,8 @@ extern "C" int qhp_query(const qhp_ctx *ctx, qhp_info *info)
         info->band_nnz_cells = sq.nnz;
         info->band_waves_pairs = ac.waves;
         info->band_waves_cells = sq.waves;
+        info->band_pieces_pairs = ac.np;
+        info->band_pieces_cells = sq.np;
     }
     info->n_rhs = ctx->nrhs;
     info->n_steps = ctx->n_steps;
