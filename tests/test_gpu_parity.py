@@ -526,6 +526,51 @@ def test_batch_uneven_graph_replay(precision, n_rhs, bound):
             s.close()
 
 
+@pytest.mark.parametrize("precision,bound", [("f64", 1e-10), ("f32a", 1e-6)])
+def test_batch_uneven_against_the_oracle(precision, bound):
+    """The uneven batch against the oracle (Sec. IV-B, eq. post_processing):
+    a sphere, a torus (two global loops) and a cube, four waves each (the
+    batch takes 1, 2, 4 or 8), marched together by graph replays in three chunks with
+    eager work between them; every step of every scatterer against the CPU
+    oracle's march, relative to the peak current.  F32A: FP32 blocks with the
+    rounding carried over lags, FP64 y and sums (stated bound 1e-6)."""
+    import paper_2312_06367_amd as qhp
+    from oracle import operators as O, excitation as E, mot
+    from workloads import meshes, waves
+    dt, n = 0.12, 90
+    cases = [("sphere", meshes.icosphere(1)), ("torus", meshes.torus(1.0, 0.4, 12, 6)), ("cube", meshes.cube(1.5, 2))]
+    solvers, refs = [], []
+    for name, (xyz, tri) in cases:
+        asm = O.Assembly(xyz, tri, dt)
+        asm.build()
+        ws = waves.batched_waves(2, 7, 0.1, 0.1, asm.D)
+        r = np.stack([E.rhs(asm, w, n) for w in ws], axis=-1)
+        refs.append(mot.currents(asm.proj.PLH, asm.proj.PS, asm.dtn, mot.march(asm.T, r)))
+        s = qhp.Solver(dt, precision="f64", solver="inv")
+        s.mesh(xyz, tri)
+        s.assemble()
+        if precision != "f64":
+            s.set_precision(precision)
+        s.set_incident(ws, n)
+        solvers.append(s)
+        _say("[batch vs oracle %s] %s: ne=%d, oracle marched" % (precision, name, asm.topo.ne))
+    outs = [torch.zeros((n, s.info()["ne"], 4), dtype=torch.float64, device="cuda") for s in solvers]
+    b = qhp.Batch(solvers)
+    for c0 in range(0, n, 30):
+        b.run(30, [o[c0:] for o in outs])
+        torch.cuda.synchronize()
+        _ = (torch.ones(1000, device="cuda") * 2).sum().item()  # eager work between replays
+    b.close()
+    for (name, _), o, ref in zip(cases, outs, refs):
+        j = o.cpu().numpy()
+        err = max(float(np.linalg.norm(j[:, :, q] - ref[:, :, q], axis=1).max()
+                        / np.linalg.norm(ref[:, :, q], axis=1).max()) for q in range(4))
+        _say("[batch vs oracle %s] %s: current err %.3e (bound %.0e)" % (precision, name, err, bound))
+        assert err < bound
+    for s in solvers:
+        s.close()
+
+
 @pytest.mark.parametrize("precision,bound", [("f32a", 1e-9), ("f32", 2e-4)])
 def test_batch_every_tile_shape(precision, bound):
     """Every history tile shape of the batch (register forms with 64 or 16
