@@ -138,8 +138,10 @@ static bool band_shape_built(int w, int p)
 }
 
 // rows of the staged x: the tile lags, then zero rows that a lane stepping
-// past its run may read (at most the longest run plus a step)
-static int band_xrows(int tmax, int lmax) { return tmax + lmax + kBandStep; }
+// past its run may read.  A lane reads rows klo - tk0 + p for p below the
+// longest run mx rounded up to a step; with klo - tk0 <= ntk - len (len >= 1)
+// or klo = tk0 (len = 0) the last row read is below tmax + lmax + kBandStep - 2
+static int band_xrows(int tmax, int lmax) { return tmax + lmax + kBandStep - 2; }
 
 // LDS bytes of the product kernel: the staged x, two batch buffers a wave,
 // the values a lane may read past the last buffer
@@ -235,8 +237,9 @@ void build_band(hipStream_t s, int64_t rows, int64_t cols, int64_t lag0, int64_t
         return tmax;
     };
     // work-group shape: the most bytes in flight (waves x 1 KB copy pieces
-    // per batch), then the most waves, whose buffers and staged x fit the LDS;
-    // a batch holds at least the largest group
+    // per batch), counted in full from 8 waves on and in proportion below
+    // (fewer waves hide less latency), then the most waves, whose buffers and
+    // staged x fit the LDS; a batch holds at least the largest group
     const int npmin = (int)((gmax + 1023) / 1024);
     std::vector<uint32_t> tile, tw;
     int waves = 0, np = 0, tmax = 0;
@@ -246,7 +249,8 @@ void build_band(hipStream_t s, int64_t rows, int64_t cols, int64_t lag0, int64_t
         for (int q : kBandPieces)
             if (band_shape_built(w, q) && band_lds(tm, lm, w, q, fp32) <= (size_t)kBandLdsBytes) p = q;
         if (p < npmin) continue;
-        if (w * p > waves * np) {
+        auto score = [](int w_, int p_) { return w_ * p_ * std::min(w_, 8); };
+        if (!waves || score(w, p) > score(waves, np)) {
             waves = w;
             np = p;
             tmax = tm;
