@@ -148,6 +148,13 @@ typedef struct {
     void *(*dev_alloc)(size_t bytes, void *user);
     void (*dev_free)(void *ptr, void *user);
     void *alloc_user;
+    /* Temporal basis pairs (h_i, q_i): 0 or 1 = the hat functions h_i and
+     * the q_i of Sec. IV-A; 2 = the shifted quadratic Lagrange interpolators
+     * of the Remark of Sec. IV-B (on [(m-1) dt, m dt), m = 0..2, the
+     * polynomial through the nodes (m-2) dt..m dt, 1 at 0) with q_i' =
+     * (h_i - h_{i+1})/dt.  Order 2 adds one lag (K = ceil(D/dt) + 2) and
+     * x-weighted shell moments to the assembly; other values: QHP_EINVAL. */
+    int32_t temporal_order;
 } qhp_params;
 
 /* One incident plane wave (Sec. V); u = t - t0 - k_hat . r

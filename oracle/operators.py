@@ -60,11 +60,12 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
-def n_lags(diameter: float, dt: float) -> int:
-    """K such that T_k = 0 for k > K: the support of q_0 reaches two shells
-    past the largest distance D.  A 1e-9 relative guard makes D/dt that is an
-    integer up to rounding give the same K on every platform."""
-    return int(math.ceil(diameter / dt - 1e-9)) + 1
+def n_lags(diameter: float, dt: float, order: int = 1) -> int:
+    """K such that T_k = 0 for k > K: q_0 of temporal order p spans p + 2
+    intervals, so it reaches p + 1 shells past the largest distance D.  A 1e-9
+    relative guard makes D/dt that is an integer up to rounding give the same
+    K on every platform."""
+    return int(math.ceil(diameter / dt - 1e-9)) + int(order)
 
 
 def pinv_laplacian(L: np.ndarray) -> np.ndarray:
@@ -116,7 +117,7 @@ class Assembly:
     """Everything the marching scheme needs, for one mesh and time step."""
 
     def __init__(self, xyz, tri, dt: float, spec: Q.Spec | None = None, eta_c: float = 1.0,
-                 K: int | None = None):
+                 K: int | None = None, order: int = 1):
         self.topo = t = Topology(xyz, tri)
         self.dt = float(dt)
         self.D = t.diameter
@@ -125,7 +126,10 @@ class Assembly:
         self.kappa = 1.0 / self.dt  # kappa = 1/(c dt)
         self.eta_c = float(eta_c)
         self.spec = spec or Q.Spec()
-        self.K = n_lags(self.D, self.dt) if K is None else int(K)
+        if order not in (1, 2):
+            raise ValueError("temporal order 1 (hat functions) or 2 (quadratic interpolators)")
+        self.order = int(order)
+        self.K = n_lags(self.D, self.dt, self.order) if K is None else int(K)
         self.n_shells = self.K
         self.proj = Projectors(t)
         self._bc_arrays()
@@ -237,36 +241,43 @@ class Assembly:
 
     # ------------------------------------------------------------ retarded
     def shells(self):
-        """Shell moments V_j, S_j^p (coarse) and N_j (BC x RWG), j < n_shells."""
+        """Shell moments V_j, S_j^p (coarse) and N_j (BC x RWG), j < n_shells.
+        Order 1: V [nsh][ne][ne], S [nsh][3][nc][nc], N [nsh][ne][ne].  Higher
+        orders p: the x^a moments V [nsh][p][ne][ne] (a < p), S [nsh][p+2] and
+        N [nsh][p+1][ne][ne] (see temporal.py)."""
         t, s = self.topo, self.spec
         L = Q.lib()
-        nsh = self.n_shells
-        V = np.zeros((nsh, t.ne, t.ne))
-        S = np.zeros((nsh, 3, t.nc, t.nc))
+        nsh, p = self.n_shells, self.order
+        V = np.zeros((nsh, p, t.ne, t.ne))
+        S = np.zeros((nsh, p + 2, t.nc, t.nc))
         cb, cw = _f64(s.coarse_rule[0]), _f64(s.coarse_rule[1])
         gx, gw = _f64(s.gx), _f64(s.gw)
         xyz, tri, te, ts = _f64(t.xyz), _i64(t.tri), _i64(t.tri_edge), _i64(t.tri_sign)
         L.orc_retarded_coarse.restype = None
         L.orc_retarded_coarse(_ptr(xyz), _ptr(tri), ctypes.c_long(t.nc), _ptr(te), _ptr(ts),
                               ctypes.c_long(t.ne), ctypes.c_double(self.dt), ctypes.c_long(nsh),
-                              ctypes.c_int(len(cw)), _ptr(cb), _ptr(cw), ctypes.c_int(len(gx)),
+                              ctypes.c_int(p), ctypes.c_int(len(cw)), _ptr(cb), _ptr(cw), ctypes.c_int(len(gx)),
                               _ptr(gx), _ptr(gw), _ptr(V), _ptr(S))
-        V = 0.5 * (V + V.transpose(0, 2, 1))
+        V = 0.5 * (V + V.transpose(0, 1, 3, 2))
         S = 0.5 * (S + S.transpose(0, 1, 3, 2))
-        N = np.zeros((nsh, t.ne, t.ne))
+        N = np.zeros((nsh, p + 1, t.ne, t.ne))
         fb, fw = _f64(s.fine_rule[0]), _f64(s.fine_rule[1])
         L.orc_retarded_bc.restype = None
         L.orc_retarded_bc(_ptr(_f64(t.fxyz)), _ptr(_i64(t.ftri)), ctypes.c_long(6 * t.nc),
                           _ptr(_i64(t.fparent)), _ptr(self.bc_off), _ptr(self.bc_edge),
                           _ptr(self.bc_flux), _ptr(xyz), _ptr(tri), ctypes.c_long(t.nc),
                           _ptr(te), _ptr(ts), ctypes.c_long(t.ne), ctypes.c_double(self.dt),
-                          ctypes.c_long(nsh), ctypes.c_int(len(fw)), _ptr(fb), _ptr(fw),
+                          ctypes.c_long(nsh), ctypes.c_int(p), ctypes.c_int(len(fw)), _ptr(fb), _ptr(fw),
                           ctypes.c_int(len(gx)), _ptr(gx), _ptr(gw),
                           ctypes.c_double(s.coplanar_tol), _ptr(N))
+        if p == 1:
+            return V[:, 0], S, N[:, 0]
         return V, S, N
 
     def lag_matrices(self, V, S, N, G):
         """Raw lag matrices A_k, B_k, C_k for k = 0..K (see module header)."""
+        if self.order != 1:
+            return self.lag_matrices_order(V, S, N, G)
         t = self.topo
         K = self.K
 
@@ -283,6 +294,44 @@ class Assembly:
             Ck = mfie_combine(sh(N, k), sh(N, k - 1), k)
             if k == 0:
                 Ck = Ck + 0.5 * G
+            C.append(Ck)
+        return A, B, C
+
+    def lag_matrices_order(self, V, S, N, G, order=None):
+        """Raw lag matrices for temporal bases of order p (temporal.py): sums
+        of the x^a shell moments with the coefficients of h_0', q_0 and
+        h_0 + R h_0' on the interval each shell falls in.  V [nsh][p], S
+        [nsh][p+2], N [nsh][p+1] moment-major (for p = 1 also the plain
+        arrays of `shells`)."""
+        from . import temporal
+        t = self.topo
+        K, p = self.K, int(order or self.order)
+        if V.ndim == 3:
+            V, N = V[:, None], N[:, None]
+        da, qa, ca = temporal.combos(p)
+        Sig = t.Sigma.toarray()
+        SA = Sig * (1.0 / t.area)[None, :]
+        zV, zS = np.zeros(V.shape[2:]), np.zeros(S.shape[2:])
+
+        def sh(X, j, a, z):
+            return X[j, a] if 0 <= j < X.shape[0] and a < X.shape[1] else z
+
+        A, B, C = [], [], []
+        for k in range(K + 1):
+            Ak = zV.copy()
+            Ck = 0.5 * G if k == 0 else zV.copy()
+            for m in range(p + 1):
+                cam = ca(k, m)
+                for a in range(p):
+                    Ak = Ak - (da[m][a] / self.dt) * sh(V, k - m, a, zV)
+                for a in range(p + 1):
+                    Ck = Ck + cam[a] * sh(N, k - m, a, zV)
+            Sq = zS.copy()
+            for m in range(p + 2):
+                for a in range(p + 2):
+                    Sq = Sq + qa[m][a] * sh(S, k - m, a, zS)
+            A.append(Ak)
+            B.append(-self.T0 * SA @ Sq @ SA.T)
             C.append(Ck)
         return A, B, C
 

@@ -45,38 +45,64 @@ static void cross3(const double *a, const double *b, double *c)
 }
 static double norm3(const double *a) { return sqrt(dot3(a, a)); }
 
-/* output of one inner integral */
+/* output of one inner integral; x = R/dt - j on shell j */
 typedef struct {
-    double I0;    /* int 1/R                 */
-    double Iu[3]; /* int (r' - p)/R          */
-    double Sx[3]; /* int x^p / R, p = 0,1,2  */
-    double W[3];  /* int (r - r')/R^3        */
+    double I0;      /* int 1/R                          */
+    double Iu[3];   /* int (r' - p)/R                   */
+    double Sx[4];   /* int x^a / R, a = 0..3            */
+    double W[3];    /* int (r - r')/R^3                 */
+    double I0x[2];  /* int x^a / R, a = 1, 2 (= Sx)     */
+    double Iux[3];  /* int x (r' - p)/R                 */
+    double Wx[2][3]; /* int x^a (r - r')/R^3, a = 1, 2  */
 } inner_t;
 
 /* closed-form radial pieces between R = lo and R = hi (lo >= |d|) */
+/* radial pieces between R = lo and R = hi (lo >= |d|) of the kernels over
+   the source plane (R dR = rho drho), x = R/dt - j running from xoff_lo to
+   xoff_hi:
+     P0  = int dR,  P1 = int rho dR,  X[a] = int x^a dR (a = 0..3)
+     dQ0 = d int dR/R^2,  Q1 = int rho/R^2 dR
+     P1x = int x rho dR;  dQx[a-1] = d int x^a/R^2 dR,  Qx[a-1] = int x^a rho/R^2 dR
+   (a = 1, 2), from x = R/dt - j and the antiderivatives of rho = sqrt(R^2 - d^2)
+   times 1, R, 1/R, 1/R^2: P1, rho^3/3, rho - |d| acos(|d|/R), Q1 */
+typedef struct {
+    double P0, P1, X[4], dQ0, Q1, P1x, dQx[2], Qx[2];
+} radial_t;
+
 static void radial(double lo, double hi, double d, double xoff_lo, double xoff_hi, double dt,
-                   int lo_is_plane, double *P0, double *P1, double *X, double *dQ0, double *Q1)
+                   int lo_is_plane, double jsh, radial_t *o)
 {
-    double d2 = d * d;
+    double d2 = d * d, ad = fabs(d);
     double slo = sqrt(fmax(lo * lo - d2, 0.0));
     double shi = sqrt(fmax(hi * hi - d2, 0.0));
-    *P0 = hi - lo;
+    o->P0 = hi - lo;
     double lg = 0.0;
     if (d2 > 0.0 && lo + slo > 0.0) lg = log((hi + shi) / (lo + slo));
-    *P1 = 0.5 * (hi * shi - lo * slo) - 0.5 * d2 * lg;
-    /* x = R/dt - j runs from xoff_lo to xoff_hi */
-    X[0] = dt * (xoff_hi - xoff_lo);
-    X[1] = dt * (xoff_hi * xoff_hi - xoff_lo * xoff_lo) / 2.0;
-    X[2] = dt * (xoff_hi * xoff_hi * xoff_hi - xoff_lo * xoff_lo * xoff_lo) / 3.0;
+    o->P1 = 0.5 * (hi * shi - lo * slo) - 0.5 * d2 * lg;
+    double xl = xoff_lo, xh = xoff_hi;
+    o->X[0] = dt * (xh - xl);
+    o->X[1] = dt * (xh * xh - xl * xl) / 2.0;
+    o->X[2] = dt * (xh * xh * xh - xl * xl * xl) / 3.0;
+    o->X[3] = dt * (xh * xh * xh * xh - xl * xl * xl * xl) / 4.0;
     /* d * int dR/R^2 and int sqrt(R^2-d^2)/R^2 dR */
     if (lo_is_plane) {
-        *dQ0 = (d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0)) - d / hi;
+        o->dQ0 = (d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0)) - d / hi;
         double lnlo = (lo > 0.0) ? log(lo) : 0.0; /* s_lo = 0 at R = |d| */
-        *Q1 = -shi / hi + log(hi + shi) - lnlo;
+        o->Q1 = -shi / hi + log(hi + shi) - lnlo;
     } else {
-        *dQ0 = d / lo - d / hi;
-        *Q1 = -shi / hi + slo / lo + log((hi + shi) / (lo + slo));
+        o->dQ0 = d / lo - d / hi;
+        o->Q1 = -shi / hi + slo / lo + log((hi + shi) / (lo + slo));
     }
+    /* x-weighted pieces (only where lo > 0: the plane's own shell starts at |d|) */
+    double inv = 1.0 / dt;
+    o->P1x = inv * (shi * shi * shi - slo * slo * slo) / 3.0 - jsh * o->P1;
+    double flog = (lo > 0.0) ? log(hi / lo) : 0.0;
+    double acl = (lo > 0.0) ? acos(fmin(1.0, ad / lo)) : 0.0, ach = acos(fmin(1.0, ad / hi));
+    double G1 = (shi - ad * ach) - (slo - ad * acl); /* int sqrt(R^2-d^2)/R dR */
+    o->dQx[0] = d * inv * flog - jsh * o->dQ0;
+    o->Qx[0] = inv * G1 - jsh * o->Q1;
+    o->dQx[1] = d * inv * inv * (hi - lo) - 2.0 * jsh * d * inv * flog + jsh * jsh * o->dQ0;
+    o->Qx[1] = inv * inv * o->P1 - 2.0 * jsh * inv * G1 + jsh * jsh * o->Q1;
 }
 
 static void sort_small(double *a, int n)
@@ -86,6 +112,23 @@ static void sort_small(double *a, int n)
         int k = i - 1;
         while (k >= 0 && a[k] > v) { a[k + 1] = a[k]; --k; }
         a[k + 1] = v;
+    }
+}
+
+/* add one radial piece: ws the angle weight, wv the angle-weighted in-plane
+   radial direction */
+static void accumulate(inner_t *out, const radial_t *o, double ws, const double *wv, const double *nrm,
+                       int coplanar)
+{
+    out->I0 += ws * o->P0;
+    for (int k = 0; k < 3; ++k) out->Iu[k] += o->P1 * wv[k];
+    for (int a = 0; a < 4; ++a) out->Sx[a] += ws * o->X[a];
+    for (int a = 0; a < 2; ++a) out->I0x[a] += ws * o->X[a + 1];
+    for (int k = 0; k < 3; ++k) out->Iux[k] += o->P1x * wv[k];
+    if (!coplanar) {
+        for (int k = 0; k < 3; ++k) out->W[k] += ws * o->dQ0 * nrm[k] - o->Q1 * wv[k];
+        for (int a = 0; a < 2; ++a)
+            for (int k = 0; k < 3; ++k) out->Wx[a][k] += ws * o->dQx[a] * nrm[k] - o->Qx[a] * wv[k];
     }
 }
 
@@ -163,19 +206,14 @@ static void inner_integral(const double P[3][3], const double *r, double s_lo, d
             if (Rm >= s_hi) {
                 /* the whole shell lies inside the edge's wedge here: the radial
                    pieces are constants and the angular integrals are exact */
-                double P0, P1, X[3], dQ0, Q1;
-                radial(R_lo, s_hi, d, R_lo / dt - jsh, s_hi / dt - jsh, dt, lo_is_plane,
-                       &P0, &P1, X, &dQ0, &Q1);
+                radial_t o;
+                radial(R_lo, s_hi, d, R_lo / dt - jsh, s_hi / dt - jsh, dt, lo_is_plane, jsh, &o);
                 double dpsi = atan(sinh(hi)) - atan(sinh(lo));
                 double cu = tanh(hi) - tanh(lo);           /* int sin(psi) dpsi ... */
                 double su = 1.0 / cosh(hi) - 1.0 / cosh(lo); /* ... and -int cos(psi) */
                 double du[3];
-                for (int k = 0; k < 3; ++k) du[k] = cu * eh[k] - su * et[k];
-                out->I0 += sig * P0 * dpsi;
-                for (int k = 0; k < 3; ++k) out->Iu[k] += sig * P1 * du[k];
-                for (int k = 0; k < 3; ++k) out->Sx[k] += sig * X[k] * dpsi;
-                if (!coplanar)
-                    for (int k = 0; k < 3; ++k) out->W[k] += sig * (dQ0 * nrm[k] * dpsi - Q1 * du[k]);
+                for (int k = 0; k < 3; ++k) du[k] = sig * (cu * eh[k] - su * et[k]);
+                accumulate(out, &o, sig * dpsi, du, nrm, coplanar);
                 continue;
             }
             for (int g = 0; g < ng; ++g) {
@@ -185,14 +223,11 @@ static void inner_integral(const double P[3][3], const double *r, double s_lo, d
                 double wgt = sig * half * gw[g] / ch;
                 double u[3];
                 for (int k = 0; k < 3; ++k) u[k] = (eh[k] + sh * et[k]) / ch;
-                double P0, P1, X[3], dQ0, Q1;
-                radial(R_lo, Rhi, d, R_lo / dt - jsh, Rhi / dt - jsh, dt, lo_is_plane,
-                       &P0, &P1, X, &dQ0, &Q1);
-                out->I0 += wgt * P0;
-                for (int k = 0; k < 3; ++k) out->Iu[k] += wgt * P1 * u[k];
-                for (int k = 0; k < 3; ++k) out->Sx[k] += wgt * X[k];
-                if (!coplanar)
-                    for (int k = 0; k < 3; ++k) out->W[k] += wgt * (dQ0 * nrm[k] - Q1 * u[k]);
+                radial_t o;
+                radial(R_lo, Rhi, d, R_lo / dt - jsh, Rhi / dt - jsh, dt, lo_is_plane, jsh, &o);
+                double wu[3];
+                for (int k = 0; k < 3; ++k) wu[k] = wgt * u[k];
+                accumulate(out, &o, wgt, wu, nrm, coplanar);
             }
         }
     }
@@ -213,6 +248,27 @@ void orc_inner(const double *P, const double *r, double s_lo, double s_hi, doubl
         out10[4 + k] = o.Sx[k];
         out10[7 + k] = o.W[k];
     }
+}
+
+/* the x-weighted moments of one inner integral (pins of the higher-order
+   temporal bases): out13 = Sx[3], Iux[0..2], Wx[0][0..2], Wx[1][0..2] */
+void orc_inner_x(const double *P, const double *r, double s_lo, double s_hi, double jsh, double dt,
+                 int ng, const double *gx, const double *gw, double coplanar_tol, double *out13)
+{
+    double PP[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k) PP[i][k] = P[3 * i + k];
+    inner_t o;
+    inner_integral(PP, r, s_lo, s_hi, jsh, dt, ng, gx, gw, coplanar_tol, &o);
+    out13[0] = o.Sx[3];
+    for (int k = 0; k < 3; ++k) {
+        out13[1 + k] = o.Iux[k];
+        out13[4 + k] = o.Wx[0][k];
+        out13[7 + k] = o.Wx[1][k];
+    }
+    out13[10] = o.I0x[0];
+    out13[11] = o.I0x[1];
+    out13[12] = 0.0;
 }
 
 static void load_tri(const double *xyz, const long *tri, long c, double P[3][3])
@@ -288,12 +344,13 @@ static void shell_range(double dmin, double dmax, double dt, long n_shells, long
 }
 
 /*
- * Retarded coarse-coarse shell moments.
- *   V  [n_shells][ne][ne]   (accumulated, not symmetrised)
- *   S  [n_shells][3][nc][nc]
+ * Retarded coarse-coarse shell moments for temporal bases of order `order`
+ * (1 or 2):
+ *   V  [n_shells][order][ne][ne]   x^a weights, a < order (accumulated, not symmetrised)
+ *   S  [n_shells][order + 2][nc][nc]   a <= order + 1
  */
 void orc_retarded_coarse(const double *xyz, const long *tri, long nc, const long *tri_edge,
-                         const long *tri_sign, long ne, double dt, long n_shells, int nq,
+                         const long *tri_sign, long ne, double dt, long n_shells, int order, int nq,
                          const double *qbary, const double *qw, int ng, const double *gx,
                          const double *gw, double *V, double *S)
 {
@@ -329,10 +386,10 @@ void orc_retarded_coarse(const double *xyz, const long *tri, long nc, const long
                 for (long j = j0; j <= j1; ++j) {
                     inner_t o;
                     inner_integral(Q, r, j * dt, (j + 1) * dt, (double)j, dt, ng, gx, gw, 1e-12, &o);
-                    for (int p = 0; p < 3; ++p) {
+                    for (int p = 0; p < order + 2; ++p) {
                         double val = wq * o.Sx[p] / FOUR_PI;
 #pragma omp atomic
-                        S[((j * 3 + p) * nc + c) * nc + cs] += val;
+                        S[((j * (order + 2) + p) * nc + c) * nc + cs] += val;
                     }
                     for (int a = 0; a < 3; ++a) {
                         long m = tri_edge[3 * c + a];
@@ -340,11 +397,15 @@ void orc_retarded_coarse(const double *xyz, const long *tri, long nc, const long
                         for (int k = 0; k < 3; ++k) fa[k] = tri_sign[3 * c + a] * (r[k] - P[a][k]) / (2.0 * A);
                         for (int b = 0; b < 3; ++b) {
                             long nidx = tri_edge[3 * cs + b];
-                            double vb[3];
-                            for (int k = 0; k < 3; ++k) vb[k] = o.Iu[k] + (pp[k] - Q[b][k]) * o.I0;
-                            double val = wq * tri_sign[3 * cs + b] / (2.0 * As) * dot3(fa, vb) / FOUR_PI;
+                            for (int xa = 0; xa < order; ++xa) {
+                                const double *iu = xa == 0 ? o.Iu : o.Iux;
+                                double i0 = xa == 0 ? o.I0 : o.I0x[0];
+                                double vb[3];
+                                for (int k = 0; k < 3; ++k) vb[k] = iu[k] + (pp[k] - Q[b][k]) * i0;
+                                double val = wq * tri_sign[3 * cs + b] / (2.0 * As) * dot3(fa, vb) / FOUR_PI;
 #pragma omp atomic
-                            V[(j * ne + m) * ne + nidx] += val;
+                                V[((j * order + xa) * ne + m) * ne + nidx] += val;
+                            }
                         }
                     }
                 }
@@ -362,14 +423,15 @@ static void rt0_eval(const double P[3][3], double A, const double *F, const doub
 }
 
 /*
- * Retarded BC-RWG shell moments of the MFIE kernel.
- *   N [n_shells][ne][ne]
+ * Retarded BC-RWG shell moments of the MFIE kernel for temporal bases of
+ * order `order` (1 or 2):
+ *   N [n_shells][order + 1][ne][ne]   x^a weights, a <= order
  * bc_off[t]..bc_off[t+1] index bc_edge / bc_flux (3 per entry) for fine t.
  */
 void orc_retarded_bc(const double *fxyz, const long *ftri, long nf, const long *fparent,
                      const long *bc_off, const long *bc_edge, const double *bc_flux,
                      const double *xyz, const long *tri, long nc, const long *tri_edge,
-                     const long *tri_sign, long ne, double dt, long n_shells, int nq,
+                     const long *tri_sign, long ne, double dt, long n_shells, int order, int nq,
                      const double *qbary, const double *qw, int ng, const double *gx,
                      const double *gw, double coplanar_tol, double *N)
 {
@@ -397,16 +459,19 @@ void orc_retarded_bc(const double *fxyz, const long *ftri, long nf, const long *
                     inner_integral(Q, r, j * dt, (j + 1) * dt, (double)j, dt, ng, gx, gw, coplanar_tol, &o);
                     for (int b = 0; b < 3; ++b) {
                         long nidx = tri_edge[3 * cs + b];
-                        double rb[3], wx[3];
+                        double rb[3];
                         for (int k = 0; k < 3; ++k) rb[k] = r[k] - Q[b][k];
-                        cross3(o.W, rb, wx);
                         double sb = tri_sign[3 * cs + b] / (2.0 * As);
-                        for (long e = bc_off[t]; e < bc_off[t + 1]; ++e) {
-                            double g[3];
-                            rt0_eval(P, A, bc_flux + 3 * e, r, g);
-                            double val = wq * sb * dot3(wx, g) / FOUR_PI;
+                        for (int xa = 0; xa <= order; ++xa) {
+                            double wx[3];
+                            cross3(xa == 0 ? o.W : o.Wx[xa - 1], rb, wx);
+                            for (long e = bc_off[t]; e < bc_off[t + 1]; ++e) {
+                                double g[3];
+                                rt0_eval(P, A, bc_flux + 3 * e, r, g);
+                                double val = wq * sb * dot3(wx, g) / FOUR_PI;
 #pragma omp atomic
-                            N[(j * ne + bc_edge[e]) * ne + nidx] += val;
+                                N[((j * (order + 1) + xa) * ne + bc_edge[e]) * ne + nidx] += val;
+                            }
                         }
                     }
                 }

@@ -41,7 +41,7 @@ class _Params(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("eta_c", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("solver", ctypes.c_int32), ("n_psi", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("dev_alloc", _ALLOC_FN), ("dev_free", _FREE_FN),
-                ("alloc_user", ctypes.c_void_p)]
+                ("alloc_user", ctypes.c_void_p), ("temporal_order", ctypes.c_int32)]
 
 
 class TorchAllocator:
@@ -214,9 +214,10 @@ class Solver:
     """One scatterer and time step on one GPU (see include/qhp.h)."""
 
     def __init__(self, dt: float, precision: str = "f64", solver: str = "lu", n_psi: int = 10,
-                 eta_c: float = 1.0, device: int = 0, stream=None, allocator: str = "hip"):
+                 eta_c: float = 1.0, device: int = 0, stream=None, allocator: str = "hip", order: int = 1):
         """allocator: "hip" (the library's hipMalloc) or "torch" (PyTorch's
-        caching allocator through the dev_alloc / dev_free hook)."""
+        caching allocator through the dev_alloc / dev_free hook); order: the
+        temporal basis pairs, 1 (hat functions) or 2 (quadratic interpolators)."""
         import torch
         self.L = lib()
         torch.cuda.set_device(device)
@@ -227,6 +228,7 @@ class Solver:
                     int(device), stream if stream is not None else _stream())
         if self.allocator is not None:
             p.dev_alloc, p.dev_free = self.allocator.alloc_fn, self.allocator.free_fn
+        p.temporal_order = int(order)
         self._p = p
         h = ctypes.c_void_p()
         self._check(self.L.qhp_create(ctypes.byref(p), ctypes.byref(h)), None)

@@ -19,6 +19,7 @@
 #include "solve.h"
 #include "ctx.h"
 #include "factored.h"
+#include "temporal.h"
 
 using qhp::DBuf;
 using qhp::Fail;
@@ -74,6 +75,7 @@ extern "C" int qhp_create(const qhp_params *params, qhp_ctx **out)
 {
     if (!params || !out) return QHP_EINVAL;
     if (!(params->dt > 0.0) || params->precision < QHP_F64 || params->precision > QHP_FAC32 ||
+        params->temporal_order < 0 || params->temporal_order > 2 ||
         params->solver < QHP_SOLVE_LU || params->solver > QHP_SOLVE_INV || params->n_psi > 32 ||
         (!params->dev_alloc) != (!params->dev_free))
         return QHP_EINVAL;
@@ -83,6 +85,7 @@ extern "C" int qhp_create(const qhp_params *params, qhp_ctx **out)
     qhp_ctx *c = new qhp_ctx();
     c->p = *params;
     if (c->p.n_psi <= 0) c->p.n_psi = 10;
+    if (c->p.temporal_order <= 0) c->p.temporal_order = 1;
     if (!(c->p.eta_c > 0.0)) c->p.eta_c = 1.0;
     c->s = (hipStream_t)params->stream;
     c->allocator = qhp::Allocator{params->dev_alloc, params->dev_free, params->alloc_user};
@@ -282,7 +285,7 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
     const qhp::Mesh &m = c->mesh;
     const int64_t ne = m.ne, nc = m.nc, nv = m.nv;
     const size_t nn = (size_t)ne * ne;
-    c->K = qhp::n_lags(m.diameter, c->p.dt);
+    c->K = qhp::n_lags(m.diameter, c->p.dt, c->p.temporal_order);
     c->T0 = m.diameter;
     c->dtn = c->p.dt / c->T0;
     c->kappa = 1.0 / c->p.dt;
@@ -395,14 +398,20 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
         c->rawC.assign(K + 1, {});
     }
     {
-        const size_t per_shell = sizeof(double) * (2 * nn + 3 * (size_t)nc * nc);
+        // temporal order p: shells carry p (V), p + 1 (N) and p + 2 (S)
+        // x-weighted moments; lag k combines shells k - p - 1 .. k
+        const int ord = c->p.temporal_order, VP = ord, NP = ord + 1, SP = ord + 2;
+        const qhp::TemporalBasis tb(ord);
+        const size_t nc2 = (size_t)nc * nc;
+        const size_t per_shell = sizeof(double) * ((VP + NP) * nn + SP * nc2);
         const size_t budget = (size_t)24 << 30;
-        int64_t ch = (int64_t)(budget / per_shell) - 2;
+        int64_t ch = (int64_t)(budget / per_shell) - (ord + 1);
         ch = std::max<int64_t>(1, std::min<int64_t>(ch, K + 1));
-        DBuf V, N, S, Ak, Ck, Ap, Cp, Bk, E, Wst, Tt, amax;
-        V.alloc(sizeof(double) * nn * (ch + 2));
-        N.alloc(sizeof(double) * nn * (ch + 2));
-        S.alloc(sizeof(double) * 3 * (size_t)nc * nc * (ch + 2));
+        DBuf V, N, S, Ak, Ck, Ap, Cp, Bk, E, Wst, Tt, amax, Sqk;
+        V.alloc(sizeof(double) * nn * VP * (ch + ord + 1));
+        N.alloc(sizeof(double) * nn * NP * (ch + ord + 1));
+        S.alloc(sizeof(double) * SP * nc2 * (ch + ord + 1));
+        if (ord > 1) Sqk.alloc(sizeof(double) * nc2);
         Ak.alloc(sizeof(double) * nn); Ck.alloc(sizeof(double) * nn);
         Ap.alloc(sizeof(double) * nn); Cp.alloc(sizeof(double) * nn);
         Bk.alloc(sizeof(double) * nn); E.alloc(sizeof(double) * nn);
@@ -420,40 +429,55 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
         zero(Cp, s);
         for (int64_t k0 = 0; k0 <= K; k0 += ch) {
             int64_t k1 = std::min<int64_t>(k0 + ch - 1, K);
-            int64_t j0 = std::max<int64_t>(k0 - 2, 0), j1 = std::min<int64_t>(k1, K - 1);
+            int64_t j0 = std::max<int64_t>(k0 - (ord + 1), 0), j1 = std::min<int64_t>(k1, K - 1);
             zero(V, s);
             zero(N, s);
             zero(S, s);
             if (j1 >= j0) {
-                qhp::launch_ret_coarse(s, a, j0, j1, V.as<double>(), S.as<double>());
-                qhp::launch_ret_bc(s, a, j0, j1, N.as<double>());
+                qhp::launch_ret_coarse(s, a, ord, j0, j1, V.as<double>(), S.as<double>());
+                qhp::launch_ret_bc(s, a, ord, j0, j1, N.as<double>());
                 for (int64_t j = j0; j <= j1; ++j) {
-                    qhp::symmetrize(s, ne, V.as<double>() + (j - j0) * nn);
-                    qhp::launch_sym_s(s, nc, S.as<double>() + (j - j0) * 3 * (size_t)nc * nc);
+                    for (int x = 0; x < VP; ++x) qhp::symmetrize(s, ne, V.as<double>() + ((j - j0) * VP + x) * nn);
+                    qhp::launch_sym_s(s, nc, SP, S.as<double>() + (j - j0) * SP * nc2);
                 }
             }
             c->stage("retarded shell quadrature");
-            auto shellV = [&](int64_t j) -> const double * {
-                return (j >= j0 && j <= j1) ? V.as<double>() + (j - j0) * nn : nullptr;
+            // moment x^a of shell j (nullptr outside the chunk's shells)
+            auto shellV = [&](int64_t j, int x = 0) -> const double * {
+                return (j >= j0 && j <= j1) ? V.as<double>() + ((j - j0) * VP + x) * nn : nullptr;
             };
-            auto shellN = [&](int64_t j) -> const double * {
-                return (j >= j0 && j <= j1) ? N.as<double>() + (j - j0) * nn : nullptr;
+            auto shellN = [&](int64_t j, int x = 0) -> const double * {
+                return (j >= j0 && j <= j1) ? N.as<double>() + ((j - j0) * NP + x) * nn : nullptr;
             };
-            auto shellS = [&](int64_t j) -> const double * {
-                return (j >= j0 && j <= j1) ? S.as<double>() + (j - j0) * 3 * (size_t)nc * nc : nullptr;
+            auto shellS = [&](int64_t j, int x = 0) -> const double * {
+                return (j >= j0 && j <= j1) ? S.as<double>() + ((j - j0) * SP + x) * nc2 : nullptr;
             };
             for (int64_t k = k0; k <= k1; ++k) {
-                qhp::launch_lag_ac(s, (int64_t)nn, k, c->p.dt, shellV(k), shellV(k - 1), shellN(k), shellN(k - 1),
-                                   c->G.as<double>(), Ak.as<double>(), Ck.as<double>());
-                qhp::launch_bk(s, a, shellS(k), shellS(k - 1), shellS(k - 2), c->T0, Bk.as<double>());
+                double *sq_k = fac && k >= 1 ? Sqfull.as<double>() + (k - 1) * nc2 : nullptr;
+                if (ord == 1) {  // hat functions: the closed combinations
+                    qhp::launch_lag_ac(s, (int64_t)nn, k, c->p.dt, shellV(k), shellV(k - 1), shellN(k),
+                                       shellN(k - 1), c->G.as<double>(), Ak.as<double>(), Ck.as<double>());
+                    qhp::launch_bk(s, a, shellS(k), shellS(k - 1), shellS(k - 2), c->T0, Bk.as<double>());
+                    if (sq_k) qhp::launch_sq(s, nc, shellS(k), shellS(k - 1), shellS(k - 2), sq_k);
+                } else {  // the x^a moments of every interval the bases span, with their coefficients
+                    qhp::LinTerms tA, tC, tS;
+                    for (int m = 0; m <= ord; ++m) {
+                        for (int x = 0; x < VP; ++x) tA.add(shellV(k - m, x), -tb.dh[m][x] / c->p.dt);
+                        for (int x = 0; x < NP; ++x) tC.add(shellN(k - m, x), tb.mf((int)k, m, x));
+                    }
+                    for (int m = 0; m <= ord + 1; ++m)
+                        for (int x = 0; x < SP; ++x) tS.add(shellS(k - m, x), tb.q[m][x]);
+                    qhp::launch_lincomb(s, (int64_t)nn, tA, 0.0, nullptr, Ak.as<double>());
+                    qhp::launch_lincomb(s, (int64_t)nn, tC, 0.5, k == 0 ? c->G.as<double>() : nullptr,
+                                        Ck.as<double>());
+                    qhp::launch_lincomb(s, (int64_t)nc2, tS, 0.0, nullptr, sq_k ? sq_k : Sqk.as<double>());
+                    qhp::launch_bk_sq(s, a, sq_k ? sq_k : Sqk.as<double>(), c->T0, Bk.as<double>());
+                }
                 if (fac) {
                     hip_check(hipMemcpyAsync(Afull.as<double>() + k * nn, Ak.p, sizeof(double) * nn,
                                              hipMemcpyDeviceToDevice, s), "raw A");
                     hip_check(hipMemcpyAsync(Cfull.as<double>() + k * nn, Ck.p, sizeof(double) * nn,
                                              hipMemcpyDeviceToDevice, s), "raw C");
-                    if (k >= 1)
-                        qhp::launch_sq(s, nc, shellS(k), shellS(k - 1), shellS(k - 2),
-                                       Sqfull.as<double>() + (k - 1) * (size_t)nc * nc);
                 }
                 if (k >= 1)
                     for (const DBuf *m : {&Ak, &Bk, &Ck})
@@ -1257,7 +1281,7 @@ extern "C" int qhp_query(const qhp_ctx *ctx, qhp_info *info)
     info->nc = m.nc;
     info->n_harmonic = m.n_harmonic;
     info->diameter = m.diameter;
-    info->K = qhp::n_lags(m.diameter, ctx->p.dt);
+    info->K = qhp::n_lags(m.diameter, ctx->p.dt, ctx->p.temporal_order);
     info->ld = ctx->ld;
     info->slab_bytes = ctx->slabs.p ? ctx->slabs.bytes : 0;
     if (ctx->fac) {  // the bands and [P_E P_M] of the precision in use

@@ -24,9 +24,11 @@
 
 namespace qhp {
 
-int64_t n_lags(double diameter, double dt)
+// q_0 of temporal order p spans p + 2 intervals: it reaches p + 1 shells past
+// the largest distance (the 1e-9 guard keeps an integer D/dt stable)
+int64_t n_lags(double diameter, double dt, int order)
 {
-    return (int64_t)std::ceil(diameter / dt - 1e-9) + 1;
+    return (int64_t)std::ceil(diameter / dt - 1e-9) + (order > 1 ? order : 1);
 }
 
 static int fail(std::string &err, const std::string &msg)

@@ -45,6 +45,6 @@ int build_mesh(const double *xyz, int64_t nv, const int32_t *tri, int64_t nc, Me
                std::string &err);
 
 // Lags: T_k = 0 for k > K (q_0 reaches two shells past the diameter).
-int64_t n_lags(double diameter, double dt);
+int64_t n_lags(double diameter, double dt, int order = 1);
 
 }  // namespace qhp

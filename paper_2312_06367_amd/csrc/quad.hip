@@ -85,29 +85,53 @@ __device__ __forceinline__ V3 point(const Tri &T, double l0, double l1, double l
 struct Mom {
     double I0;     // int 1/R
     V3 Iu;         // int (r' - p)/R
-    double Sx[3];  // int x^p/R, x = R/dt - j
+    double Sx[4];  // int x^p/R, x = R/dt - j (p = 3 with the x-moments only)
     V3 W;          // int (r - r')/R^3
+    V3 Iux;        // int x (r' - p)/R          (x-moments: quadratic temporal bases)
+    V3 Wx[2];      // int x^a (r - r')/R^3, a = 1, 2
 };
 
-// Radial closed forms between R = lo and R = hi (lo >= |d|).
-template <bool WA, bool WS, bool WW>
+__device__ __forceinline__ void mom_zero(Mom &m)
+{
+    m.I0 = 0.0;
+    m.Iu = mk(0, 0, 0);
+    m.Sx[0] = m.Sx[1] = m.Sx[2] = m.Sx[3] = 0.0;
+    m.W = mk(0, 0, 0);
+    m.Iux = mk(0, 0, 0);
+    m.Wx[0] = m.Wx[1] = mk(0, 0, 0);
+}
+
+// Radial closed forms between R = lo and R = hi (lo >= |d|), rho =
+// sqrt(R^2 - d^2): int dR, int rho dR, int x^a dR, d int dR/R^2, int rho/R^2 dR;
+// with XM also int x rho dR, d int x^a/R^2 dR and int x^a rho/R^2 dR (a = 1,
+// 2) from x = R/dt - j and the antiderivatives of rho R (rho^3/3) and rho/R
+// (rho - |d| acos(|d|/R)).
+template <bool WA, bool WS, bool WW, bool XM>
 __device__ __forceinline__ void radial_add(double lo, double hi, double d, double d2, bool lo_plane,
                                            double jsh, double inv_dt, double dt, double wscal,
                                            V3 wvec, V3 nrm, bool coplanar, Mom &m)
 {
     double slo = sqrt(fmax(lo * lo - d2, 0.0));
     double shi = sqrt(fmax(hi * hi - d2, 0.0));
+    double P1 = 0.0;
+    if (WA || (WW && XM)) {
+        double lg = (d2 > 0.0 && lo + slo > 0.0) ? log((hi + shi) / (lo + slo)) : 0.0;
+        P1 = 0.5 * (hi * shi - lo * slo) - 0.5 * d2 * lg;
+    }
     if (WA) {
         m.I0 += wscal * (hi - lo);
-        double lg = (d2 > 0.0 && lo + slo > 0.0) ? log((hi + shi) / (lo + slo)) : 0.0;
-        double P1 = 0.5 * (hi * shi - lo * slo) - 0.5 * d2 * lg;
         m.Iu = m.Iu + P1 * wvec;
+        if (XM) {
+            const double P1x = inv_dt * (shi * shi * shi - slo * slo * slo) * (1.0 / 3.0) - jsh * P1;
+            m.Iux = m.Iux + P1x * wvec;
+        }
     }
     if (WS) {
         double xl = lo * inv_dt - jsh, xh = hi * inv_dt - jsh;
         m.Sx[0] += wscal * dt * (xh - xl);
         m.Sx[1] += wscal * dt * (xh * xh - xl * xl) * 0.5;
         m.Sx[2] += wscal * dt * (xh * xh * xh - xl * xl * xl) * (1.0 / 3.0);
+        if (XM) m.Sx[3] += wscal * dt * (xh * xh * xh * xh - xl * xl * xl * xl) * 0.25;
     }
     if (WW && !coplanar) {
         double dQ0, Q1;
@@ -119,18 +143,27 @@ __device__ __forceinline__ void radial_add(double lo, double hi, double d, doubl
             Q1 = -shi / hi + slo / lo + log((hi + shi) / (lo + slo));
         }
         m.W = m.W + (wscal * dQ0) * nrm - Q1 * wvec;
+        if (XM) {
+            const double ad = fabs(d);
+            const double flog = lo > 0.0 ? log(hi / lo) : 0.0;
+            const double acl = lo > 0.0 ? acos(fmin(1.0, ad / lo)) : 0.0, ach = acos(fmin(1.0, ad / hi));
+            const double G1 = (shi - ad * ach) - (slo - ad * acl);
+            const double dQx1 = d * inv_dt * flog - jsh * dQ0, Qx1 = inv_dt * G1 - jsh * Q1;
+            const double dQx2 = d * inv_dt * inv_dt * (hi - lo) - 2.0 * jsh * d * inv_dt * flog + jsh * jsh * dQ0;
+            const double Qx2 = inv_dt * inv_dt * P1 - 2.0 * jsh * inv_dt * G1 + jsh * jsh * Q1;
+            m.Wx[0] = m.Wx[0] + (wscal * dQx1) * nrm - Qx1 * wvec;
+            m.Wx[1] = m.Wx[1] + (wscal * dQx2) * nrm - Qx2 * wvec;
+        }
     }
 }
 
-// Integral over source triangle T from test point r on s_lo < R <= s_hi.
-template <bool WA, bool WS, bool WW>
+// Integral over source triangle T from test point r on s_lo < R <= s_hi
+// (XM: also the x-moments of the quadratic temporal bases).
+template <bool WA, bool WS, bool WW, bool XM = false>
 __device__ void inner(const Tri &T, V3 r, double s_lo, double s_hi, double jsh, double dt, int ng,
                       double coplanar_tol, Mom &m)
 {
-    m.I0 = 0.0;
-    m.Iu = mk(0, 0, 0);
-    m.Sx[0] = m.Sx[1] = m.Sx[2] = 0.0;
-    m.W = mk(0, 0, 0);
+    mom_zero(m);
     V3 e1 = T.a[1] - T.a[0], e2 = T.a[2] - T.a[0];
     V3 nrm = cross(e1, e2);
     nrm = (1.0 / len(nrm)) * nrm;
@@ -190,17 +223,17 @@ __device__ void inner(const Tri &T, V3 r, double s_lo, double s_hi, double jsh, 
                 double su = 1.0 / cosh(hi) - 1.0 / cosh(lo);
                 V3 du = cu * eh - su * et;
                 Mom tmp;
-                tmp.I0 = 0.0;
-                tmp.Iu = mk(0, 0, 0);
-                tmp.Sx[0] = tmp.Sx[1] = tmp.Sx[2] = 0.0;
-                tmp.W = mk(0, 0, 0);
+                mom_zero(tmp);
                 // constant radial pieces times the exact angular integrals
-                radial_add<WA, WS, WW>(R_lo, s_hi, d, d2, lo_plane, jsh, inv_dt, dt, sig * dpsi,
-                                       sig * du, nrm, coplanar, tmp);
+                radial_add<WA, WS, WW, XM>(R_lo, s_hi, d, d2, lo_plane, jsh, inv_dt, dt, sig * dpsi,
+                                           sig * du, nrm, coplanar, tmp);
                 m.I0 += tmp.I0;
                 m.Iu = m.Iu + tmp.Iu;
-                for (int k = 0; k < 3; ++k) m.Sx[k] += tmp.Sx[k];
+                for (int k = 0; k < 4; ++k) m.Sx[k] += tmp.Sx[k];
                 m.W = m.W + tmp.W;
+                m.Iux = m.Iux + tmp.Iux;
+                m.Wx[0] = m.Wx[0] + tmp.Wx[0];
+                m.Wx[1] = m.Wx[1] + tmp.Wx[1];
                 continue;
             }
             for (int g = 0; g < ng; ++g) {
@@ -209,8 +242,8 @@ __device__ void inner(const Tri &T, V3 r, double s_lo, double s_hi, double jsh, 
                 double Rhi = sqrt(h * h * ch * ch + d2);
                 double wgt = sig * half * c_gw[g] / ch;
                 V3 u = (1.0 / ch) * (eh + sh * et);
-                radial_add<WA, WS, WW>(R_lo, Rhi, d, d2, lo_plane, jsh, inv_dt, dt, wgt, wgt * u, nrm,
-                                       coplanar, m);
+                radial_add<WA, WS, WW, XM>(R_lo, Rhi, d, d2, lo_plane, jsh, inv_dt, dt, wgt, wgt * u, nrm,
+                                           coplanar, m);
             }
         }
     }
@@ -289,10 +322,14 @@ __global__ void k_gram(AsmArgs g, double *G)
 }
 
 // --------------------------------------------------- retarded, coarse x coarse
-// thread per (test c, source cs); shells [j0, j1]; V[(j-j0)][m][n],
-// S[(j-j0)][p][c][cs] (x-moments of 1/(4 pi R)).
+// thread per (test c, source cs); shells [j0, j1]; temporal bases of order
+// OR (1: hat functions, 2: quadratic): V[(j-j0)][a][m][n] (x^a, a < OR),
+// S[(j-j0)][p][c][cs] (x^p/(4 pi R), p < OR + 2).
+template <int OR>
 __global__ __launch_bounds__(128) void k_ret_coarse(AsmArgs g, int64_t j0, int64_t j1, double *V, double *S)
 {
+    constexpr int VP = OR, SP = OR + 2;
+    constexpr bool XM = OR > 1;
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= g.nc * g.nc) return;
     int64_t c = idx / g.nc, cs = idx % g.nc;
@@ -320,8 +357,12 @@ __global__ __launch_bounds__(128) void k_ret_coarse(AsmArgs g, int64_t j0, int64
         ns_[a] = g.tri_sign[3 * cs + a];
     }
     for (int64_t j = jlo; j <= jhi; ++j) {
-        double vacc[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-        double sacc[3] = {0, 0, 0};
+        double vacc[VP][3][3];
+        double sacc[SP];
+        for (int x = 0; x < VP; ++x)
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) vacc[x][a][b] = 0.0;
+        for (int p = 0; p < SP; ++p) sacc[p] = 0.0;
         bool any = false;
         for (int q = 0; q < 7; ++q) {
             double l0, l1, l2, w;
@@ -332,34 +373,42 @@ __global__ __launch_bounds__(128) void k_ret_coarse(AsmArgs g, int64_t j0, int64
             int64_t qlo = (int64_t)floor(dmin / g.dt) - 1, qhi = (int64_t)floor(dmax / g.dt);
             if (j < qlo || j > qhi) continue;
             Mom mo;
-            inner<true, true, false>(Q, r, j * g.dt, (j + 1) * g.dt, (double)j, g.dt, g.ng, 1e-12, mo);
+            inner<true, true, false, XM>(Q, r, j * g.dt, (j + 1) * g.dt, (double)j, g.dt, g.ng, 1e-12, mo);
             any = true;
             double wq = w * A;
-            for (int p = 0; p < 3; ++p) sacc[p] += wq * mo.Sx[p];
+            for (int p = 0; p < SP; ++p) sacc[p] += wq * mo.Sx[p];
             V3 pp = r - dot(r - Q.a[0], nq) * nq;
             for (int b = 0; b < 3; ++b) {
-                V3 vb = mo.Iu + mo.I0 * (pp - Q.a[b]);
                 double sb = wq * ns_[b] / (2.0 * As);
-                for (int a = 0; a < 3; ++a) {
-                    V3 fa = (ms[a] / (2.0 * A)) * (r - P.a[a]);
-                    vacc[a][b] += sb * dot(fa, vb);
+                for (int x = 0; x < VP; ++x) {
+                    // x^0: int (r' - p)/R + (p - Q_b) int 1/R; x^1: the same with x-weights
+                    V3 vb = x == 0 ? mo.Iu + mo.I0 * (pp - Q.a[b]) : mo.Iux + mo.Sx[1] * (pp - Q.a[b]);
+                    for (int a = 0; a < 3; ++a) {
+                        V3 fa = (ms[a] / (2.0 * A)) * (r - P.a[a]);
+                        vacc[x][a][b] += sb * dot(fa, vb);
+                    }
                 }
             }
         }
         if (!any) continue;
         int64_t jj = j - j0;
-        for (int p = 0; p < 3; ++p) S[((jj * 3 + p) * g.nc + c) * g.nc + cs] = sacc[p] / kFourPi;
-        for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b)
-                atomicAdd(&V[(jj * g.ne + me[a]) * g.ne + ne_[b]], vacc[a][b] / kFourPi);
+        for (int p = 0; p < SP; ++p) S[((jj * SP + p) * g.nc + c) * g.nc + cs] = sacc[p] / kFourPi;
+        for (int x = 0; x < VP; ++x)
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b)
+                    atomicAdd(&V[((jj * VP + x) * g.ne + me[a]) * g.ne + ne_[b]], vacc[x][a][b] / kFourPi);
     }
     (void)nsh;
 }
 
 // ---------------------------------------------- retarded, BC x RWG (MFIE K)
-// thread per (coarse vertex v: test dual cell, source triangle cs)
+// thread per (coarse vertex v: test dual cell, source triangle cs);
+// N[(j-j0)][a][m][n] (x^a, a <= OR)
+template <int OR>
 __global__ __launch_bounds__(128) void k_ret_bc(AsmArgs g, int64_t j0, int64_t j1, double *N)
 {
+    constexpr int NP = OR + 1;
+    constexpr bool XM = OR > 1;
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= g.nv * g.nc) return;
     int64_t v = idx / g.nc, cs = idx % g.nc;
@@ -387,8 +436,9 @@ __global__ __launch_bounds__(128) void k_ret_bc(AsmArgs g, int64_t j0, int64_t j
         sb_[b] = g.tri_sign[3 * cs + b];
     }
     for (int64_t j = jlo; j <= jhi; ++j) {
-        double acc[kMaxValence][3];
-        for (int i = 0; i < kMaxValence; ++i) acc[i][0] = acc[i][1] = acc[i][2] = 0.0;
+        double acc[NP][kMaxValence][3];
+        for (int x = 0; x < NP; ++x)
+            for (int i = 0; i < kMaxValence; ++i) acc[x][i][0] = acc[x][i][1] = acc[x][i][2] = 0.0;
         bool any = false;
         for (int k = g.vcell_off[v]; k < g.vcell_off[v + 1]; ++k) {
             int64_t t = g.vcell_tri[k];
@@ -404,26 +454,30 @@ __global__ __launch_bounds__(128) void k_ret_bc(AsmArgs g, int64_t j0, int64_t j
                 int64_t qlo = (int64_t)floor(dmin / g.dt) - 1, qhi = (int64_t)floor(dmax / g.dt);
                 if (j < qlo || j > qhi) continue;
                 Mom mo;
-                inner<false, false, true>(Q, r, j * g.dt, (j + 1) * g.dt, (double)j, g.dt, g.ng,
-                                          g.coplanar_tol, mo);
+                inner<false, false, true, XM>(Q, r, j * g.dt, (j + 1) * g.dt, (double)j, g.dt, g.ng,
+                                              g.coplanar_tol, mo);
                 any = true;
                 double wq = w * A;
-                V3 wx[3];
-                for (int b = 0; b < 3; ++b) wx[b] = (wq * sb_[b] / (2.0 * As)) * cross(mo.W, r - Q.a[b]);
-                for (int e = g.bc_off[t]; e < g.bc_off[t + 1]; ++e) {
-                    V3 gv = rt0(P, A, g.bc_flux + 3 * e, r);
-                    int li = g.bc_local[e];
-                    for (int b = 0; b < 3; ++b) acc[li][b] += dot(wx[b], gv);
+                for (int x = 0; x < NP; ++x) {
+                    const V3 W = x == 0 ? mo.W : mo.Wx[x - 1];
+                    V3 wx[3];
+                    for (int b = 0; b < 3; ++b) wx[b] = (wq * sb_[b] / (2.0 * As)) * cross(W, r - Q.a[b]);
+                    for (int e = g.bc_off[t]; e < g.bc_off[t + 1]; ++e) {
+                        V3 gv = rt0(P, A, g.bc_flux + 3 * e, r);
+                        int li = g.bc_local[e];
+                        for (int b = 0; b < 3; ++b) acc[x][li][b] += dot(wx[b], gv);
+                    }
                 }
             }
         }
         if (!any) continue;
         int64_t jj = j - j0;
-        for (int i = 0; i < nval; ++i) {
-            int64_t m = g.vedge[g.vedge_off[v] + i];
-            for (int b = 0; b < 3; ++b)
-                atomicAdd(&N[(jj * g.ne + m) * g.ne + nb_[b]], acc[i][b] / kFourPi);
-        }
+        for (int x = 0; x < NP; ++x)
+            for (int i = 0; i < nval; ++i) {
+                int64_t m = g.vedge[g.vedge_off[v] + i];
+                for (int b = 0; b < 3; ++b)
+                    atomicAdd(&N[((jj * NP + x) * g.ne + m) * g.ne + nb_[b]], acc[x][i][b] / kFourPi);
+            }
     }
 }
 
@@ -671,14 +725,14 @@ __global__ void k_sq(int64_t nc, const double *Sk, const double *Sk1, const doub
     if (Sk2) sq += 0.5 * Sk2[2 * nc2 + o];
     Sq[o] = sq;
 }
-// symmetrise the coarse shell moments S [3][nc][nc] in place
-__global__ void k_sym_s(int64_t nc, double *S)
+// symmetrise the coarse shell moments S [np][nc][nc] in place
+__global__ void k_sym_s(int64_t nc, int np, double *S)
 {
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= nc * nc) return;
     int64_t i = idx / nc, j = idx % nc;
     if (j <= i) return;
-    for (int p = 0; p < 3; ++p) {
+    for (int p = 0; p < np; ++p) {
         double *X = S + p * nc * nc;
         double v = 0.5 * (X[i * nc + j] + X[j * nc + i]);
         X[i * nc + j] = v;
@@ -698,6 +752,32 @@ __global__ void k_lag_ac(int64_t nn, int64_t k, double dt, const double *Vk, con
     if (k == 0) c += 0.5 * G[i];
     C[i] = c;
 }
+// out = base_c * base + sum_t c[t] * p[t] (elementwise; null terms skipped):
+// the lag combinations of temporal bases of higher order
+__global__ void k_lincomb(int64_t n, LinTerms t, double base_c, const double *base, double *out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double v = base ? base_c * base[i] : 0.0;
+    for (int q = 0; q < t.n; ++q)
+        if (t.p[q]) v += t.c[q] * t.p[q][i];
+    out[i] = v;
+}
+// B_k[m][n] = -T0 sum Sig_ma Sig_nb Sq[a][b] / (A_a A_b) from a formed Sq_k
+__global__ void k_bk_sq(AsmArgs g, const double *Sq, double T0, double *B)
+{
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= g.ne * g.ne) return;
+    int64_t m = idx / g.ne, n = idx % g.ne;
+    int64_t am[2] = {g.cells[2 * m], g.cells[2 * m + 1]}, an[2] = {g.cells[2 * n], g.cells[2 * n + 1]};
+    double sg[2] = {1.0, -1.0};
+    double s = 0.0;
+    for (int i = 0; i < 2; ++i)
+        for (int k = 0; k < 2; ++k)
+            s += sg[i] * sg[k] * Sq[am[i] * g.nc + an[k]] / (g.area[am[i]] * g.area[an[k]]);
+    B[idx] = -T0 * s;
+}
+
 // X = alpha X + beta Y + gamma Z (elementwise)
 __global__ void k_lin3(int64_t n, double *X, double a, const double *Y, double b, const double *Z, double c)
 {
@@ -719,13 +799,19 @@ void launch_gram(hipStream_t s, const AsmArgs &g, double *G)
 {
     hipLaunchKernelGGL(k_gram, dim3(nblk(g.nf, 128)), dim3(128), 0, s, g, G);
 }
-void launch_ret_coarse(hipStream_t s, const AsmArgs &g, int64_t j0, int64_t j1, double *V, double *S)
+void launch_ret_coarse(hipStream_t s, const AsmArgs &g, int order, int64_t j0, int64_t j1, double *V, double *S)
 {
-    hipLaunchKernelGGL(k_ret_coarse, dim3(nblk(g.nc * g.nc, 128)), dim3(128), 0, s, g, j0, j1, V, S);
+    if (order == 2)
+        hipLaunchKernelGGL(k_ret_coarse<2>, dim3(nblk(g.nc * g.nc, 128)), dim3(128), 0, s, g, j0, j1, V, S);
+    else
+        hipLaunchKernelGGL(k_ret_coarse<1>, dim3(nblk(g.nc * g.nc, 128)), dim3(128), 0, s, g, j0, j1, V, S);
 }
-void launch_ret_bc(hipStream_t s, const AsmArgs &g, int64_t j0, int64_t j1, double *N)
+void launch_ret_bc(hipStream_t s, const AsmArgs &g, int order, int64_t j0, int64_t j1, double *N)
 {
-    hipLaunchKernelGGL(k_ret_bc, dim3(nblk(g.nv * g.nc, 128)), dim3(128), 0, s, g, j0, j1, N);
+    if (order == 2)
+        hipLaunchKernelGGL(k_ret_bc<2>, dim3(nblk(g.nv * g.nc, 128)), dim3(128), 0, s, g, j0, j1, N);
+    else
+        hipLaunchKernelGGL(k_ret_bc<1>, dim3(nblk(g.nv * g.nc, 128)), dim3(128), 0, s, g, j0, j1, N);
 }
 void launch_yuk_bcbc(hipStream_t s, const AsmArgs &g, double kappa, double *Zs, double *D)
 {
@@ -757,14 +843,22 @@ void launch_bk(hipStream_t s, const AsmArgs &g, const double *Sk, const double *
 {
     hipLaunchKernelGGL(k_bk, dim3(nblk(g.ne * g.ne, 256)), dim3(256), 0, s, g, Sk, Sk1, Sk2, T0, B);
 }
-void launch_sym_s(hipStream_t s, int64_t nc, double *S)
+void launch_sym_s(hipStream_t s, int64_t nc, int np, double *S)
 {
-    hipLaunchKernelGGL(k_sym_s, dim3(nblk(nc * nc, 256)), dim3(256), 0, s, nc, S);
+    hipLaunchKernelGGL(k_sym_s, dim3(nblk(nc * nc, 256)), dim3(256), 0, s, nc, np, S);
 }
 void launch_lag_ac(hipStream_t s, int64_t nn, int64_t k, double dt, const double *Vk, const double *Vk1,
                    const double *Nk, const double *Nk1, const double *G, double *A, double *C)
 {
     hipLaunchKernelGGL(k_lag_ac, dim3(nblk(nn, 256)), dim3(256), 0, s, nn, k, dt, Vk, Vk1, Nk, Nk1, G, A, C);
+}
+void launch_lincomb(hipStream_t s, int64_t n, const LinTerms &t, double base_c, const double *base, double *out)
+{
+    hipLaunchKernelGGL(k_lincomb, dim3(nblk(n, 256)), dim3(256), 0, s, n, t, base_c, base, out);
+}
+void launch_bk_sq(hipStream_t s, const AsmArgs &g, const double *Sq, double T0, double *B)
+{
+    hipLaunchKernelGGL(k_bk_sq, dim3(nblk(g.ne * g.ne, 256)), dim3(256), 0, s, g, Sq, T0, B);
 }
 void launch_lin3(hipStream_t s, int64_t n, double *X, double a, const double *Y, double b, const double *Z, double c)
 {

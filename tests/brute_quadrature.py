@@ -247,9 +247,17 @@ class Mesh:
         return out
 
 
-def v_shell(mesh, m, n, lo, hi, rule=None):
-    """int int_{lo < R <= hi} f_m(r) . f_n(r') / (4 pi R), f_m tested with the
-    outer rule on its triangles (the orientation m outer, n inner)."""
+def _xw(R, lo, dt, xa):
+    """the weight x^a, x = R/dt - lo/dt (1 without a time step)"""
+    if not xa:
+        return np.ones_like(R)
+    return (R / dt - round(lo / dt)) ** xa
+
+
+def v_shell(mesh, m, n, lo, hi, rule=None, dt=None, xa=0):
+    """int int_{lo < R <= hi} f_m(r) . f_n(r') x^a / (4 pi R), f_m tested with
+    the outer rule on its triangles (the orientation m outer, n inner); x =
+    R/dt - j on shell j = lo/dt (a = 0: no weight)."""
     rule = rule or radon7_rule()
     tot = 0.0
     for c, fm in mesh.rwg_on(m):
@@ -261,7 +269,8 @@ def v_shell(mesh, m, n, lo, hi, rule=None):
                 r = pts[q]
 
                 def f(rp, r=r, fn=fn):
-                    return fn(rp) / (FOUR_PI * np.linalg.norm(r - rp, axis=1))[:, None]
+                    R = np.linalg.norm(r - rp, axis=1)
+                    return fn(rp) * (_xw(R, lo, dt, xa) / (FOUR_PI * R))[:, None]
 
                 I = inner(Q, r, lo, hi, f)
                 if I is not None:
@@ -270,18 +279,18 @@ def v_shell(mesh, m, n, lo, hi, rule=None):
 
 
 def s_shell(mesh, c, cs, j, dt, rule=None):
-    """int_c int_{c', shell j} x^p / (4 pi R), x = R/dt - j, p = 0, 1, 2."""
+    """int_c int_{c', shell j} x^p / (4 pi R), x = R/dt - j, p = 0, 1, 2, 3."""
     rule = rule or radon7_rule()
     pts, w = rule_points(mesh.coarse(c), rule)
     Q = mesh.coarse(cs)
-    tot = np.zeros(3)
+    tot = np.zeros(4)
     for q in range(len(w)):
         r = pts[q]
 
         def f(rp, r=r):
             R = np.linalg.norm(r - rp, axis=1)
             x = R / dt - j
-            return np.stack([np.ones_like(x), x, x * x], axis=1) / (FOUR_PI * R)[:, None]
+            return np.stack([np.ones_like(x), x, x * x, x * x * x], axis=1) / (FOUR_PI * R)[:, None]
 
         I = inner(Q, r, j * dt, (j + 1) * dt, f)
         if I is not None:
@@ -289,11 +298,11 @@ def s_shell(mesh, c, cs, j, dt, rule=None):
     return tot
 
 
-def n_shell(mesh, m, n, lo, hi, rule=None):
-    """int int_{lo < R <= hi} g_m(r) . ((r - r') x f_n(r')) / (4 pi R^3), g_m
-    tested with the 3-point rule on its fine triangles; pairs whose fine test
-    triangle lies in the source triangle are coplanar, where the integrand
-    vanishes identically."""
+def n_shell(mesh, m, n, lo, hi, rule=None, dt=None, xa=0):
+    """int int_{lo < R <= hi} g_m(r) . ((r - r') x f_n(r')) x^a / (4 pi R^3),
+    g_m tested with the 3-point rule on its fine triangles; pairs whose fine
+    test triangle lies in the source triangle are coplanar, where the
+    integrand vanishes identically; x = R/dt - lo/dt (a = 0: no weight)."""
     rule = rule or three_point_rule()
     tot = 0.0
     for f, gm in mesh.bc_on(m):
@@ -309,7 +318,7 @@ def n_shell(mesh, m, n, lo, hi, rule=None):
                 def k(rp, r=r, fn=fn):
                     d = r[None, :] - rp
                     R = np.linalg.norm(d, axis=1)
-                    return np.cross(d, fn(rp)) / (FOUR_PI * R ** 3)[:, None]
+                    return np.cross(d, fn(rp)) * (_xw(R, lo, dt, xa) / (FOUR_PI * R ** 3))[:, None]
 
                 I = inner(Q, r, lo, hi, k)
                 if I is not None:

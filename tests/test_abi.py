@@ -190,6 +190,19 @@ def test_allocator_hook_and_growth_limit_argument_checks():
     assert L.qhp_set_growth_limit(None, 1.0) == -1
 
 
+def test_temporal_order_argument_check():
+    """Host logic, no device: qhp_create takes temporal order 0 / 1 (hat
+    functions) and 2 (quadratic interpolators) and refuses others."""
+    pkg = _lib_or_skip()
+    L = pkg.lib()
+    for bad in (-1, 3, 7):
+        p = pkg._Params(0.1, 1.0, 0, 0, 10, 0, None)
+        p.temporal_order = bad
+        h = ctypes.c_void_p()
+        assert L.qhp_create(ctypes.byref(p), ctypes.byref(h)) == -1
+        assert not h.value
+
+
 def test_noalloc_history_sum_refuses_before_any_device_work():
     """qhp_history_sum_noalloc (host logic, no device): partial sums beyond
     its fixed array, and the argument errors of the allocating call, return
