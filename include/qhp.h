@@ -99,7 +99,13 @@ enum {
  * each block carried into the next one (c_k = T_k + c_{k-1} - stored_k), so
  * every prefix sum over lags is within one rounding of the FP64 one. */
 enum { QHP_F64 = 0, QHP_F32 = 1, QHP_BF16 = 2, QHP_F32A = 3, QHP_BF16X2 = 4, QHP_I8X4 = 5, QHP_FAC64 = 6,
-       QHP_FAC32 = 7 };
+       QHP_FAC32 = 7, QHP_FP8E4M3 = 8 };
+/* QHP_FP8E4M3 (qhp_set_precision from QHP_F64 only; not a qhp_create
+ * precision): the blocks' values rounded to FP8 E4M3 (OCP: 3 mantissa bits,
+ * exponent bias 7) after scaling each block row to a largest magnitude of
+ * 240, with the rounding carried from lag to lag, and kept in FP32 words; the
+ * context then marches as QHP_F32A (FP64 y and sums).  It measures what FP8
+ * storage does to the march; there is no FP8 history kernel. */
 
 /* per-step solve with T_0 (the paper writes only T_0^{-1}, Sec. IV-B) */
 enum {

@@ -16,6 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqhp.so")
 
 QHP_F64, QHP_F32, QHP_BF16, QHP_F32A, QHP_BF16X2, QHP_I8X4, QHP_FAC64, QHP_FAC32 = 0, 1, 2, 3, 4, 5, 6, 7
+QHP_FP8E4M3 = 8  # qhp_set_precision only: FP8 values in FP32 words, marched as F32A
 QHP_SOLVE_LU, QHP_SOLVE_INV, QHP_SOLVE_GMRES = 0, 1, 2
 WARM = {"cold": 0, "prev": 1, "extrap": 2, "quad": 3, "mlp": 4, "best": 5}
 MAT = {"gram": 0, "zs": 1, "zh": 2, "m": 3, "psigma": 4, "plambda": 5, "pe": 6, "pm": 7,
@@ -23,7 +24,7 @@ MAT = {"gram": 0, "zs": 1, "zh": 2, "m": 3, "psigma": 4, "plambda": 5, "pe": 6, 
 ERRORS = {0: "OK", -1: "EINVAL", -2: "EMESH", -3: "ESTATE", -4: "ENOMEM", -5: "EDEVICE",
           -6: "ESINGULAR", -7: "ENOCONV", -8: "EUNSTABLE"}
 PRECISIONS = {"f64": QHP_F64, "f32": QHP_F32, "bf16": QHP_BF16, "f32a": QHP_F32A, "bf16x2": QHP_BF16X2,
-              "i8x4": QHP_I8X4, "fac64": QHP_FAC64, "fac32": QHP_FAC32}
+              "i8x4": QHP_I8X4, "fac64": QHP_FAC64, "fac32": QHP_FAC32, "fp8": QHP_FP8E4M3}
 SOLVERS = {"lu": QHP_SOLVE_LU, "inv": QHP_SOLVE_INV, "gmres": QHP_SOLVE_GMRES}
 
 

@@ -1243,9 +1243,33 @@ extern "C" int qhp_set_precision(qhp_ctx *ctx, int32_t precision)
         return QHP_OK;
     }
     if (ctx->p.precision != QHP_F64 || (precision != QHP_F32 && precision != QHP_BF16 && precision != QHP_F32A &&
-                                        precision != QHP_BF16X2 && precision != QHP_I8X4))
-        return guard(ctx, QHP_EINVAL, "only FP64 slabs can be re-stored, as FP32, BF16, BF16 pairs or int8 digits");
+                                        precision != QHP_BF16X2 && precision != QHP_I8X4 && precision != QHP_FP8E4M3))
+        return guard(ctx, QHP_EINVAL,
+                     "only FP64 slabs can be re-stored, as FP32, BF16, BF16 pairs, int8 digits or FP8 values");
     API_TRY
+    if (precision == QHP_FP8E4M3) {  // FP8 values in FP32 words; the march then runs as QHP_F32A
+        hipStream_t s = ctx->s;
+        const int64_t ne = ctx->mesh.ne, ld = ctx->ld, K = ctx->K;
+        const size_t per = (size_t)ne * ld;
+        DBuf out, carry, rs;
+        out.alloc(sizeof(float) * per * K);
+        carry.alloc(sizeof(double) * ne * ne);
+        rs.alloc(sizeof(double) * ne);
+        zero(carry, s);
+        for (int64_t k = 0; k < K; ++k)
+            qhp::launch_quantise_fp8(s, ne, ld, ctx->slabs.as<double>() + k * per, ld, carry.as<double>(),
+                                     rs.as<double>(), out.as<float>() + k * per);
+        hip_check(hipStreamSynchronize(s), "FP8 slabs");
+        ctx->slabs.swap(out);
+        ctx->scales.assign(K, 1.0f);
+        upload(ctx->scales_d, ctx->scales, s);
+        ctx->p.precision = QHP_F32A;
+        ctx->ring32.release();
+        ctx->ringb.release();
+        ctx->ring8.release();
+        ctx->state = 2;
+        return QHP_OK;
+    }
     hipStream_t s = ctx->s;
     const int64_t ne = ctx->mesh.ne, ld = ctx->ld, K = ctx->K;
     const size_t per = (size_t)ne * ld;                               // FP64 source block

@@ -58,6 +58,10 @@ void launch_post_b(hipStream_t s, int64_t ne, int64_t nrhs, const int32_t *cells
 // lag-carried rounding of T_k (rows of stride ldt) into the stored block [ne][ld]
 void launch_quantise_slab(hipStream_t s, int64_t ne, int64_t ld, const double *T, int64_t ldt, double *carry,
                           int32_t precision, float scale, void *out);
+// FP32 blocks holding FP8 E4M3 values times a per-row scale (largest |value|
+// of the row at 240), lag-carried rounding (carry [ne][ne] FP64)
+void launch_quantise_fp8(hipStream_t s, int64_t ne, int64_t ld, const double *T, int64_t ldt, double *carry,
+                         double *row_scale, float *out);
 void launch_absmax(hipStream_t s, int64_t ne, const double *T, int64_t ldt, const double *carry,
                    unsigned long long *out);
 void launch_load_slab(hipStream_t s, int64_t ne, int64_t ld, const void *in, int32_t precision, float scale,

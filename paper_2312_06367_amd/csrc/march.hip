@@ -1055,6 +1055,58 @@ void launch_quantise_slab(hipStream_t s, int64_t ne, int64_t ld, const double *T
     hipLaunchKernelGGL(k_quantise_slab, dim3(nblk(slab_rows(precision, ne) * ld, 256)), dim3(256), 0, s, ne, ld, T,
                        ldt, carry, precision, scale, 1.0f / scale, out);
 }
+// FP8 E4M3 (OCP: 3 mantissa bits, exponent bias 7, subnormal quantum 2^-9,
+// largest 448) rounding of y, to nearest even
+__device__ __forceinline__ double round_e4m3(double y)
+{
+    const double ay = fabs(y);
+    if (ay == 0.0) return 0.0;
+    int e;
+    frexp(ay, &e);  // ay = f 2^e, f in [0.5, 1): leading bit 2^(e-1)
+    const double q = ldexp(1.0, (e - 1 < -6 ? -6 : e - 1) - 3);
+    const double r = fmin(rint(ay / q) * q, 448.0);
+    return y < 0.0 ? -r : r;
+}
+// per row of an [ne] x [ne] block (rows of stride ldt): the scale that maps
+// max_j |T[i][j] + carry[i][j]| to 240 (1 for a zero row)
+__global__ void k_fp8_rowscale(int64_t ne, const double *T, int64_t ldt, const double *carry, double *scale)
+{
+    const int64_t i = blockIdx.x;
+    double v = 0.0;
+    for (int64_t j = threadIdx.x; j < ne; j += blockDim.x) v = fmax(v, fabs(T[i * ldt + j] + carry[i * ne + j]));
+    __shared__ double red[256];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) scale[i] = red[0] > 0.0 ? red[0] / 240.0 : 1.0;
+}
+// FP32 words holding FP8 E4M3 values times the row scale, with the rounding
+// carried to the next lag (carry = T + carry - stored); padding columns 0
+__global__ void k_quantise_fp8(int64_t ne, int64_t ld, const double *T, int64_t ldt, double *carry,
+                               const double *scale, float *out)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= ne * ld) return;
+    const int64_t i = idx / ld, j = idx % ld;
+    if (j >= ne) {
+        out[idx] = 0.0f;
+        return;
+    }
+    const double v = T[i * ldt + j] + carry[i * ne + j];
+    const float kept = (float)(round_e4m3(v / scale[i]) * scale[i]);
+    out[idx] = kept;
+    carry[i * ne + j] = v - (double)kept;
+}
+void launch_quantise_fp8(hipStream_t s, int64_t ne, int64_t ld, const double *T, int64_t ldt, double *carry,
+                         double *row_scale, float *out)
+{
+    hipLaunchKernelGGL(k_fp8_rowscale, dim3((unsigned)ne), dim3(256), 0, s, ne, T, ldt, carry, row_scale);
+    hipLaunchKernelGGL(k_quantise_fp8, dim3(nblk(ne * ld, 256)), dim3(256), 0, s, ne, ld, T, ldt, carry, row_scale,
+                       out);
+}
 // max |T + carry| over an [ne] x [ne] block whose rows have stride ldt
 __global__ void k_absmax(int64_t ne, const double *T, int64_t ldt, const double *carry, unsigned long long *out)
 {
