@@ -194,13 +194,20 @@ typedef struct {
                              k = 1..K (Sec. IV-A): the shell-sparse operands
                              a factored history would stream instead of T_k */
     /* factored history of the precision in use (zeros for dense storage):
-       the edge-pair band [A_k; C_k] and the triangle-pair band Sq_k */
+       the edge-pair band [A_k; C_k] and the triangle-pair band Sq_k of the
+       far lags k >= band_block, applied in passes of band_block steps (one
+       pass at the first step of each block of a qhp_run call), and the near
+       lags, applied every step; slab_bytes is then the bytes a step streams on
+       average: far bands / band_block + near bands + [P_E P_M] */
     size_t band_bytes_pairs, band_bytes_cells;  /* stream bytes (runs, words) */
     int64_t band_nnz_pairs, band_nnz_cells;     /* values stored in the runs  */
     int64_t band_waves_pairs, band_waves_cells; /* waves per work-group of
                                                    their product kernels     */
     int64_t band_pieces_pairs, band_pieces_cells; /* 1 KB copy pieces per
                                                      batch of those kernels  */
+    int64_t band_block;                         /* steps of a far pass (0: the
+                                                   lags are all near)        */
+    size_t band_bytes_near_pairs, band_bytes_near_cells; /* near bands' bytes */
 } qhp_info;
 
 /* Create a context (no device work beyond selecting params->device).
@@ -282,10 +289,11 @@ int qhp_release_assembly(qhp_ctx *ctx);
 int qhp_profile(qhp_ctx *ctx, int32_t enable);
 int qhp_hist_time(qhp_ctx *ctx, double *ms_total, int64_t *launches);
 /* Factored history (QHP_FAC64, QHP_FAC32) while profiling: the summed times
- * (ms, HIP events on the context's stream) of the banded product over the
- * edge pairs (A_k, C_k) and of the one over the triangle pairs (Sq_k), and the
- * number of steps timed since profiling was enabled; zeros for dense storage.
- * QHP_EINVAL on a null argument. */
+ * (ms, HIP events on the context's stream) of the far passes' banded product
+ * over the edge pairs (A_k, C_k) and of the one over the triangle pairs
+ * (Sq_k), and the number of passes timed since profiling was enabled (one per
+ * qhp_info.band_block steps); zeros for dense storage.  QHP_EINVAL on a null
+ * argument. */
 int qhp_band_time(qhp_ctx *ctx, double *ms_pairs, double *ms_cells, int64_t *launches);
 
 /* Right-hand sides r_k = -Z~ G^-T e~(t_k) + eta_c X~ G^-1 h(t_k), k = 1..n_steps

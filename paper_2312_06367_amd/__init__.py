@@ -95,7 +95,9 @@ class _Info(ctypes.Structure):
                 ("band_bytes_pairs", ctypes.c_size_t), ("band_bytes_cells", ctypes.c_size_t),
                 ("band_nnz_pairs", ctypes.c_int64), ("band_nnz_cells", ctypes.c_int64),
                 ("band_waves_pairs", ctypes.c_int64), ("band_waves_cells", ctypes.c_int64),
-                ("band_pieces_pairs", ctypes.c_int64), ("band_pieces_cells", ctypes.c_int64)]
+                ("band_pieces_pairs", ctypes.c_int64), ("band_pieces_cells", ctypes.c_int64),
+                ("band_block", ctypes.c_int64), ("band_bytes_near_pairs", ctypes.c_size_t),
+                ("band_bytes_near_cells", ctypes.c_size_t)]
 
 
 EXPORTS = ["qhp_create", "qhp_mesh", "qhp_assemble", "qhp_set_precision", "qhp_set_solver", "qhp_profile",

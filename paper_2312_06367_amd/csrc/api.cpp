@@ -541,11 +541,24 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
             upload(f.einv, einv, s);
             upload(f.cperm, cperm, s);
             upload(f.cinv, cinv, s);
+            // near lags (A, C: 0..B-1; Sq: 1..B-1) applied every step, far lags (B..K) in
+            // passes of B steps; the rounding of both is carried from the first lag on,
+            // so together they hold exactly the values of one band over all lags
+            constexpr int64_t B = qhp::kBandBlock;
+            f.has_far = K >= B;
+            const int64_t kn = std::min<int64_t>(B - 1, K);
             for (int fp32 = 0; fp32 < 2; ++fp32) {
+                qhp::build_band(s, 2 * ne, ne, 0, kn, Afull.as<double>(), Cfull.as<double>(), ne, (int64_t)nn, ne,
+                                f.eperm.as<int32_t>(), f.eperm.as<int32_t>(), fp32 != 0, fp32 ? f.ac32n : f.ac64n);
+                qhp::build_band(s, nc, nc, 1, kn, Sqfull.as<double>(), Sqfull.as<double>(), nc, nc * nc, nc,
+                                f.cperm.as<int32_t>(), f.cperm.as<int32_t>(), fp32 != 0, fp32 ? f.sq32n : f.sq64n);
+                if (!f.has_far) continue;
                 qhp::build_band(s, 2 * ne, ne, 0, K, Afull.as<double>(), Cfull.as<double>(), ne, (int64_t)nn, ne,
-                                f.eperm.as<int32_t>(), f.eperm.as<int32_t>(), fp32 != 0, fp32 ? f.ac32 : f.ac64);
+                                f.eperm.as<int32_t>(), f.eperm.as<int32_t>(), fp32 != 0, fp32 ? f.ac32 : f.ac64, B,
+                                (int)B);
                 qhp::build_band(s, nc, nc, 1, K, Sqfull.as<double>(), Sqfull.as<double>(), nc, nc * nc, nc,
-                                f.cperm.as<int32_t>(), f.cperm.as<int32_t>(), fp32 != 0, fp32 ? f.sq32 : f.sq64);
+                                f.cperm.as<int32_t>(), f.cperm.as<int32_t>(), fp32 != 0, fp32 ? f.sq32 : f.sq64, B,
+                                (int)B);
             }
             // [P_E; P_M] as two padded blocks, FP64 and FP32
             const int64_t ld = c->ld;
@@ -560,10 +573,13 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
             }
             hip_check(hipStreamSynchronize(s), "factored bands");
             if (c->verbose)
-                for (const qhp::Band *b : {&f.ac64, &f.sq64, &f.ac32, &f.sq32})
-                    std::fprintf(stderr, "[qhp] band %lld x %lld: %.3f GB, %lld values, %d waves, 2 x %d KB a wave, "
-                                 "%d lags staged, %d splits\n", (long long)b->rows, (long long)b->cols, b->bytes / 1e9,
-                                 (long long)b->nnz, b->waves, b->np, b->tmax, b->nsplit);
+                for (const qhp::Band *b : {&f.ac64n, &f.sq64n, &f.ac64, &f.sq64, &f.ac32n, &f.sq32n, &f.ac32, &f.sq32})
+                    if (b->rows)
+                        std::fprintf(stderr, "[qhp] band %lld x %lld, lags %lld..%lld, passes of %d steps: %.3f GB, "
+                                     "%lld values, %d waves, 2 x %d KB a wave, %d lags staged, %d splits\n",
+                                     (long long)b->rows, (long long)b->cols, (long long)b->lag0, (long long)b->lag1,
+                                     b->block, b->bytes / 1e9, (long long)b->nnz, b->waves, b->np, b->tmax,
+                                     b->nsplit);
             c->stage("factored bands");
         }
     }
@@ -903,8 +919,13 @@ extern "C" int qhp_set_incident(qhp_ctx *ctx, const qhp_wave *waves, int32_t n_r
         f.zy.alloc(sizeof(double) * 2 * nc);
         f.sv.alloc(sizeof(double) * nc);
         f.em.alloc(sizeof(double) * 2 * ld);
-        f.pac.alloc(sizeof(double) * std::max(f.ac64.nsplit, f.ac32.nsplit) * 2 * ne);
-        f.ps.alloc(sizeof(double) * std::max(f.sq64.nsplit, f.sq32.nsplit) * nc);
+        f.pac.alloc(sizeof(double) * std::max(f.ac64n.nsplit, f.ac32n.nsplit) * 2 * ne);
+        f.ps.alloc(sizeof(double) * std::max(f.sq64n.nsplit, f.sq32n.nsplit) * nc);
+        if (f.has_far) {
+            f.pacf.alloc(sizeof(double) * std::max(f.ac64.nsplit, f.ac32.nsplit) * qhp::kBandBlock * 2 * ne);
+            f.psf.alloc(sizeof(double) * std::max(f.sq64.nsplit, f.sq32.nsplit) * qhp::kBandBlock * nc);
+        }
+        f.far_valid = false;
         for (qhp::DBuf *b : {&f.jx, &f.cq, &f.zy, &f.em}) zero(*b, s);
         f.zcur = 0;
         if (c->partial.bytes < sizeof(double) * 2 * ne)  // the [P_E P_M] product: at most two splits
@@ -941,20 +962,31 @@ static void do_step(qhp_ctx *c, double *j_out, double *y_out)
         qhp_ctx::FacState &f = *c->fac;
         const bool fp32 = c->p.precision == QHP_FAC32;
         const qhp::Band &bac = fp32 ? f.ac32 : f.ac64, &bsq = fp32 ? f.sq32 : f.sq64;
-        hipEvent_t eb[3] = {nullptr, nullptr, nullptr};
-        if (c->profiling)
-            for (hipEvent_t &e : eb) {
-                hip_check(hipEventCreate(&e), "event");
-                c->ev_band.push_back(e);
-            }
+        const qhp::Band &bacn = fp32 ? f.ac32n : f.ac64n, &bsqn = fp32 ? f.sq32n : f.sq64n;
+        constexpr int B = qhp::kBandBlock;
         if (e0) hip_check(hipEventRecord(e0, s), "event");
-        if (eb[0]) hip_check(hipEventRecord(eb[0], s), "event");
-        qhp::launch_band(s, bac, fp32, f.jx.as<double>(), ld, K, c->head, K, f.pac.as<double>());
-        if (eb[1]) hip_check(hipEventRecord(eb[1], s), "event");
-        qhp::launch_band(s, bsq, fp32, f.cq.as<double>(), nc, K, c->head, 0, f.ps.as<double>());
-        if (eb[2]) hip_check(hipEventRecord(eb[2], s), "event");
+        if (f.has_far && (!f.far_valid || i >= f.far_start + B)) {
+            // the far lags of steps i .. i + B - 1 in one pass (ring slots of steps <= i - 1)
+            hipEvent_t eb[3] = {nullptr, nullptr, nullptr};
+            if (c->profiling)
+                for (hipEvent_t &e : eb) {
+                    hip_check(hipEventCreate(&e), "event");
+                    c->ev_band.push_back(e);
+                }
+            if (eb[0]) hip_check(hipEventRecord(eb[0], s), "event");
+            qhp::launch_band(s, bac, fp32, f.jx.as<double>(), ld, K, c->head, K, f.pacf.as<double>());
+            if (eb[1]) hip_check(hipEventRecord(eb[1], s), "event");
+            qhp::launch_band(s, bsq, fp32, f.cq.as<double>(), nc, K, c->head, 0, f.psf.as<double>());
+            if (eb[2]) hip_check(hipEventRecord(eb[2], s), "event");
+            f.far_start = i;
+            f.far_valid = true;
+        }
+        qhp::launch_band(s, bacn, fp32, f.jx.as<double>(), ld, K, c->head, K, f.pac.as<double>());
+        qhp::launch_band(s, bsqn, fp32, f.cq.as<double>(), nc, K, c->head, 0, f.ps.as<double>());
         qhp::launch_fac_combine(s, ne, nc, c->args.cells, c->args.area, c->T0, f.einv.as<int32_t>(),
-                                f.cinv.as<int32_t>(), f.pac.as<double>(), bac.nsplit, f.ps.as<double>(), bsq.nsplit,
+                                f.cinv.as<int32_t>(), f.pac.as<double>(), bacn.nsplit, f.ps.as<double>(), bsqn.nsplit,
+                                f.has_far ? f.pacf.as<double>() : nullptr, bac.nsplit,
+                                f.has_far ? f.psf.as<double>() : nullptr, bsq.nsplit, (int)(i - f.far_start), B,
                                 f.em.as<double>(), ld);
         qhp::launch_history(s, f.pem_prec, ne, ld, 1, 2, f.pem_prec == QHP_F64 ? f.pem64.p : f.pem32.p, nullptr,
                             f.em.p, 2, 0, r_i, c->bvec.as<double>(), c->partial.p, f.pem_splits, nullptr, e1,
@@ -1091,6 +1123,7 @@ extern "C" int qhp_step(qhp_ctx *ctx, double *j_out)
     if (ctx->state != 3 || ctx->broken) return guard(ctx, QHP_ESTATE, "set_incident first");
     if (ctx->step >= ctx->n_steps) return guard(ctx, QHP_ESTATE, "no right-hand side left");
     API_TRY
+    if (ctx->fac) ctx->fac->far_valid = false;  // far passes live within one call
     do_step(ctx, j_out, nullptr);
     return finish_run(ctx);
     API_CATCH(ctx)
@@ -1104,6 +1137,7 @@ extern "C" int qhp_run(qhp_ctx *ctx, int32_t n_steps, double *j_hist, double *y_
     if (n_steps < 0 || ctx->step + n_steps > ctx->n_steps) return guard(ctx, QHP_EINVAL, "past the last right-hand side");
     API_TRY
     const int64_t stride = ctx->mesh.ne * ctx->nrhs;
+    if (ctx->fac) ctx->fac->far_valid = false;  // far passes live within one call
     for (int32_t t = 0; t < n_steps; ++t)
         do_step(ctx, j_hist ? j_hist + t * stride : nullptr, y_hist ? y_hist + t * stride : nullptr);
     return finish_run(ctx);
@@ -1312,7 +1346,13 @@ extern "C" int qhp_query(const qhp_ctx *ctx, qhp_info *info)
         const bool fp32 = ctx->p.precision == QHP_FAC32;
         const qhp_ctx::FacState &f = *ctx->fac;
         const qhp::Band &ac = fp32 ? f.ac32 : f.ac64, &sq = fp32 ? f.sq32 : f.sq64;
-        info->slab_bytes = ac.bytes + sq.bytes + (size_t)2 * m.ne * ctx->ld * (f.pem_prec == QHP_F64 ? 8 : 4);
+        const qhp::Band &acn = fp32 ? f.ac32n : f.ac64n, &sqn = fp32 ? f.sq32n : f.sq64n;
+        // bytes a step streams on average: the far pass once per kBandBlock steps
+        info->slab_bytes = (ac.bytes + sq.bytes) / qhp::kBandBlock + acn.bytes + sqn.bytes +
+                           (size_t)2 * m.ne * ctx->ld * (f.pem_prec == QHP_F64 ? 8 : 4);
+        info->band_block = f.has_far ? qhp::kBandBlock : 0;
+        info->band_bytes_near_pairs = acn.bytes;
+        info->band_bytes_near_cells = sqn.bytes;
         info->band_bytes_pairs = ac.bytes;
         info->band_bytes_cells = sq.bytes;
         info->band_nnz_pairs = ac.nnz;

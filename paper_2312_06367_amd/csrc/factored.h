@@ -24,6 +24,11 @@ constexpr int kBandChunk = 32;
 constexpr int kBandLdsBytes = 160 * 1024;
 constexpr int kBandStep = 8;        // lags a lane takes per step of the walk
 constexpr int kBandPrefetchLags = 128;  // lags of a chunk's x loaded ahead through registers
+// steps of one pass over the far lags (k >= kBandBlock): their terms for steps
+// i .. i + kBandBlock - 1 use only the currents of steps <= i - 1, so one pass
+// over the values at step i gives all of them (each value serves kBandBlock
+// products); the near lags (k < kBandBlock) are applied every step
+constexpr int kBandBlock = 4;
 
 // One lag-banded family of matrices X_k, k in [lag0, lag1], rows x cols.
 // Rows 2q, 2q + 1 and the chunk ch of kBandChunk columns form the group
@@ -45,6 +50,7 @@ struct Band {
     int nsplit = 1;         // chunk splits of the product (partial sums)
     int waves = 16;         // waves per work-group
     int np = 1;             // 1 KB copy pieces per batch (two batch buffers a wave)
+    int block = 1;          // steps of one pass (products per value); 1: one step
     DBuf hdr, tile, stream;
 };
 
@@ -52,14 +58,20 @@ struct Band {
 // stored orders rp, cp (stored index -> matrix index): value (k, r, c) is
 // srcA[(k - lag0) * lag_stride + rp[r] * row_stride + cp[c]] for r < split and
 // srcB[(k - lag0) * lag_stride + rp[r - split] * row_stride + cp[c]] otherwise.
-// fp32: values rounded to FP32 with the rounding carried along each pair's lags.
+// fp32: values rounded to FP32 with the rounding carried along each pair's lags
+// from lag0.  Only the lags kfirst..lag1 are stored (kfirst < 0: lag0), so the
+// bands of two adjacent lag ranges hold exactly the values of the band of both.
+// block: the steps of one pass of the product (1, or kBandBlock for lags
+// >= kBandBlock).
 void build_band(hipStream_t s, int64_t rows, int64_t cols, int64_t lag0, int64_t lag1, const double *srcA,
                 const double *srcB, int64_t split, int64_t lag_stride, int64_t row_stride, const int32_t *rp,
-                const int32_t *cp, bool fp32, Band &out);
+                const int32_t *cp, bool fp32, Band &out, int64_t kfirst = -1, int block = 1);
 
-// part[split][row] = sum over the split's chunks of sum_k X_k(row, .) x_k, x_k
-// the ring slot of lag k: slot0 for k = 0, else (head + k - 1) mod K, slots
-// [.][ldx] FP64
+// block 1: part[split][row] = sum over the split's chunks of sum_k X_k(row, .)
+// x_k, x_k the ring slot of lag k: slot0 for k = 0, else (head + k - 1) mod K,
+// slots [.][ldx] FP64.  block B > 1 (lags >= B): part[split][b][row] for
+// b = 0..B-1, the sum for the step b after the current one, whose lag k is
+// the current step's lag k - b (slot (head + k - b - 1) mod K)
 void launch_band(hipStream_t s, const Band &b, bool fp32, const double *x, int64_t ldx, int64_t K, int64_t head,
                  int64_t slot0, double *part);
 
@@ -69,10 +81,13 @@ void morton_order(const Mesh &m, bool cells, std::vector<int32_t> &perm, std::ve
 
 // E, M of the factored history into the two slots of em ([2][ld]), the band
 // products in stored order (einv, cinv: index -> stored index):
-// E_m = sum_s pac[s][m'] - T0 (ps(c+')/A(c+) - ps(c-')/A(c-)), M_m = sum_s pac[s][ne + m']
+// E_m = sum_s pac[s][m'] - T0 (ps(c+')/A(c+) - ps(c-')/A(c-)), M_m = sum_s pac[s][ne + m'],
+// pac and ps summed with the far partials pacf[s][b], psf[s][b] of a pass of
+// nb steps (b: the step within the pass; pacf null: none)
 void launch_fac_combine(hipStream_t s, int64_t ne, int64_t nc, const int32_t *cells, const double *area, double T0,
                         const int32_t *einv, const int32_t *cinv, const double *pac, int nsac, const double *ps,
-                        int nss, double *em, int64_t ld);
+                        int nss, const double *pacf, int nsacf, const double *psf, int nssf, int b, int nb,
+                        double *em, int64_t ld);
 
 // after the solve of step i: sv = Sigma^T y (cells), cslot (stored order) = sv / A
 void launch_fac_post_a(hipStream_t s, int64_t nc, const int32_t *tri_edge, const int32_t *tri_sign,
@@ -85,10 +100,16 @@ void launch_fac_post_b(hipStream_t s, int64_t ne, double dtn, const int32_t *cel
 }  // namespace qhp
 
 struct qhp_ctx::FacState {
-    qhp::Band ac64, ac32, sq64, sq32;  // rows [A_k; C_k] x edges, lags 0..K; Sq_k cells x cells, lags 1..K
+    // rows [A_k; C_k] x edges and Sq_k cells x cells: the far lags k >= kBandBlock
+    // (passes of kBandBlock steps) and the near lags (A, C: 0.., Sq: 1..kBandBlock - 1)
+    qhp::Band ac64, ac32, sq64, sq32;
+    qhp::Band ac64n, ac32n, sq64n, sq32n;
+    bool has_far = false;              // K >= kBandBlock
+    int64_t far_start = 0;             // step whose pass the far partials hold
+    bool far_valid = false;            // within one qhp_run / qhp_step call
     qhp::DBuf pem64, pem32;            // [P_E; P_M] [2][ne][ld]
     qhp::DBuf eperm, einv, cperm, cinv;  // stored orders of the edges and cells
-    qhp::DBuf jx, cq, zy, sv, em, pac, ps;
+    qhp::DBuf jx, cq, zy, sv, em, pac, ps, pacf, psf;
     int zcur = 0;                      // which half of zy holds L_Sigma^+ Sigma^T y_{i-1}
     int pem_variant = -1, pem_splits = 1;
     // arithmetic of the [P_E P_M] product: QHP_F64, or QHP_F32A (FP32 P_E, P_M)

@@ -52,11 +52,13 @@ __device__ __forceinline__ bool group_pair(int64_t g, int64_t nch, int64_t rows,
 }  // namespace
 
 // one wave per group: per pair (lane) the first stored lag and the number of
-// lags to the last stored value (word klo | len << 16); per group the values
-// stored, the lag range and the longest run
+// lags to the last stored value (word klo | len << 16; lags kfirst..lag1, the
+// carried rounding from lag0 on); per group the values stored, the lag range
+// and the longest run
 __global__ __launch_bounds__(256) void k_band_scan(int64_t rows, int64_t cols, int64_t nch, int64_t ng, int64_t lag1,
-                                                   Src src, bool fp32, uint32_t *meta, int64_t *cnt_out,
-                                                   int32_t *kmin_out, int32_t *kmax_out, int32_t *lmax_out)
+                                                   int64_t kfirst, Src src, bool fp32, uint32_t *meta,
+                                                   int64_t *cnt_out, int32_t *kmin_out, int32_t *kmax_out,
+                                                   int32_t *lmax_out)
 {
     const int lane = threadIdx.x & 63;
     const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
@@ -67,7 +69,7 @@ __global__ __launch_bounds__(256) void k_band_scan(int64_t rows, int64_t cols, i
     int64_t first = -1, last = -1;
     if (in)
         for (int64_t k = src.lag0; k <= lag1; ++k)
-            if (store_value(src.at(k, r, col), carry, fp32) != 0.0) {
+            if (store_value(src.at(k, r, col), carry, fp32) != 0.0 && k >= kfirst) {
                 if (first < 0) first = k;
                 last = k;
             }
@@ -137,17 +139,19 @@ static bool band_shape_built(int w, int p)
     return false;
 }
 
-// rows of the staged x: the tile lags, then zero rows that a lane stepping
-// past its run may read.  A lane reads rows klo - tk0 + p for p below the
-// longest run mx rounded up to a step; with klo - tk0 <= ntk - len (len >= 1)
-// or klo = tk0 (len = 0) the last row read is below tmax + lmax + kBandStep - 2
-static int band_xrows(int tmax, int lmax) { return tmax + lmax + kBandStep - 2; }
+// rows of the staged x: the tile lags (and for a pass of `block` steps the
+// block - 1 lags before them), then zero rows that a lane stepping past its
+// run may read.  A lane reads rows klo - tk0 + p + j for p below the longest
+// run mx rounded up to a step and j < kBandStep + block - 1; with
+// klo - tk0 <= ntk - len (len >= 1) or klo = tk0 (len = 0) the last row read
+// is below tmax + lmax + kBandStep + block - 3
+static int band_xrows(int tmax, int lmax, int block) { return tmax + lmax + kBandStep + block - 3; }
 
 // LDS bytes of the product kernel: the staged x, two batch buffers a wave,
 // the values a lane may read past the last buffer
-static size_t band_lds(int tmax, int lmax, int waves, int np, bool fp32)
+static size_t band_lds(int tmax, int lmax, int waves, int np, bool fp32, int block)
 {
-    return (size_t)band_xrows(tmax, lmax) * CW * sizeof(double) + (size_t)waves * 2 * np * 1024 +
+    return (size_t)band_xrows(tmax, lmax, block) * CW * sizeof(double) + (size_t)waves * 2 * np * 1024 +
            (size_t)(lmax + kBandStep) * (fp32 ? 4 : 8);
 }
 
@@ -179,14 +183,18 @@ static int band_splits(int64_t nrb, int64_t nch)
 
 void build_band(hipStream_t s, int64_t rows, int64_t cols, int64_t lag0, int64_t lag1, const double *srcA,
                 const double *srcB, int64_t split, int64_t lag_stride, int64_t row_stride, const int32_t *rp,
-                const int32_t *cp, bool fp32, Band &out)
+                const int32_t *cp, bool fp32, Band &out, int64_t kfirst, int block)
 {
     if (lag1 >= 65535) throw Fail{QHP_EINVAL, "the factored history takes at most 65534 lags"};
+    if (block != 1 && block != kBandBlock) throw Fail{QHP_EINVAL, "band pass of an unsupported step count"};
+    if (kfirst < 0) kfirst = lag0;
+    if (block > 1 && kfirst < block) throw Fail{QHP_EINVAL, "a pass of several steps takes lags >= its steps"};
     out.rows = rows;
     out.cols = cols;
     out.nch = (cols + CW - 1) / CW;
-    out.lag0 = lag0;
+    out.lag0 = kfirst;
     out.lag1 = lag1;
+    out.block = block;
     const int64_t nq = (rows + 1) / 2, nch = out.nch, ng = nq * nch;
     const size_t vsz = fp32 ? 4 : 8;
     Src src{srcA, srcB, rp, cp, split, lag_stride, row_stride, lag0};
@@ -196,8 +204,8 @@ void build_band(hipStream_t s, int64_t rows, int64_t cols, int64_t lag0, int64_t
     kmin.alloc(sizeof(int32_t) * ng);
     kmax.alloc(sizeof(int32_t) * ng);
     lmax.alloc(sizeof(int32_t) * ng);
-    hipLaunchKernelGGL(k_band_scan, dim3(nblk(ng * 64, 256)), dim3(256), 0, s, rows, cols, nch, ng, lag1, src, fp32,
-                       meta.as<uint32_t>(), cnt.as<int64_t>(), kmin.as<int32_t>(), kmax.as<int32_t>(),
+    hipLaunchKernelGGL(k_band_scan, dim3(nblk(ng * 64, 256)), dim3(256), 0, s, rows, cols, nch, ng, lag1, kfirst, src,
+                       fp32, meta.as<uint32_t>(), cnt.as<int64_t>(), kmin.as<int32_t>(), kmax.as<int32_t>(),
                        lmax.as<int32_t>());
     std::vector<int64_t> hc(ng);
     std::vector<int32_t> hlo(ng), hhi(ng), hlm(ng);
@@ -244,10 +252,11 @@ void build_band(hipStream_t s, int64_t rows, int64_t cols, int64_t lag0, int64_t
     std::vector<uint32_t> tile, tw;
     int waves = 0, np = 0, tmax = 0;
     for (int w : kBandWaves) {
+        if (block > 1 && w > 12) continue;  // the pass's kBandBlock sums a row need the registers of <= 12 waves
         const int tm = tiles((int64_t)w * kBandRowsPerWave / 2, tw);
         int p = 0;  // the largest batch built for this size that fits
         for (int q : kBandPieces)
-            if (band_shape_built(w, q) && band_lds(tm, lm, w, q, fp32) <= (size_t)kBandLdsBytes) p = q;
+            if (band_shape_built(w, q) && band_lds(tm, lm, w, q, fp32, block) <= (size_t)kBandLdsBytes) p = q;
         if (p < npmin) continue;
         auto score = [](int w_, int p_) { return w_ * p_ * std::min(w_, 8); };
         if (!waves || score(w, p) > score(waves, np)) {
@@ -381,7 +390,10 @@ __device__ __forceinline__ void wait_vm()
 // place among the values; the wave steps over the longest run kBandStep lags
 // at a time, a lane past its own run adding zero products.  FP64 sums per lane,
 // reduced over each half-wave (one row) at the end, one partial per split.
-template <typename T, int W, int NP>
+// A pass of BB steps stages the BB - 1 lags before the tile too and forms, for
+// each value of lag k, its products with the staged lags k - b (b < BB): the
+// sums of the steps b after the current one.
+template <typename T, int W, int NP, int BB>
 __global__ __launch_bounds__(64 * W) void k_band(int64_t rows, int64_t nch, int64_t cps,
                                                  const uint64_t *__restrict__ hdr, const uint32_t *__restrict__ tile,
                                                  const char *__restrict__ stream, const double *__restrict__ x,
@@ -401,9 +413,11 @@ __global__ __launch_bounds__(64 * W) void k_band(int64_t rows, int64_t nch, int6
     const int64_t q0w = rb * W * GW + (int64_t)wave * GW;  // first group (row pair) of this wave
     const int64_t nqt = (rows + 1) / 2;
     const int ngw = nqt - q0w < GW ? (int)(nqt - q0w) : GW;  // groups of this wave (may be <= 0)
-    double acc[GW];
+    double acc[GW][BB];
 #pragma unroll
-    for (int q = 0; q < GW; ++q) acc[q] = 0.0;
+    for (int q = 0; q < GW; ++q)
+#pragma unroll
+        for (int b = 0; b < BB; ++b) acc[q][b] = 0.0;
     // headers and tiles read through the constant address space: scalar loads,
     // whose waits (lgkmcnt) leave the copies in flight (vmcnt) alone; a wave's
     // headers of one chunk are consecutive
@@ -441,20 +455,23 @@ __global__ __launch_bounds__(64 * W) void k_band(int64_t rows, int64_t nch, int6
             __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(src + pc * 1024 + lane * 16),
                                              (__attribute__((address_space(3))) void *)(dst + pc * 1024), 16, 0, 0);
     };
-    // x of a chunk's tile: element idx = lag row idx / CW, column idx % CW;
-    // the first XR * 64 W elements go through registers, loaded a chunk ahead
+    // x of a chunk's tile: element idx = lag row idx / CW (lag tk0 - BB + 1 +
+    // row), column idx % CW; the first XR * 64 W elements go through
+    // registers, loaded a chunk ahead
     constexpr int XR = (kBandPrefetchLags * CW + 64 * W - 1) / (64 * W);
     auto x_at = [&](int64_t ch, int tk0, int idx) {
-        const int64_t k = tk0 + idx / CW, cc = ch * CW + idx % CW;
+        const int64_t k = tk0 - (BB - 1) + idx / CW, cc = ch * CW + idx % CW;
         const int64_t slot = k == 0 ? slot0 : (head + k - 1) % K;
         return cc < ldx ? x[slot * ldx + cc] : 0.0;
     };
     double xpre[XR];
+    // staged rows of a tile (none for an empty one: its lags would be <= 0)
+    auto nrows = [&](int ntk) { return ntk ? ntk + BB - 1 : 0; };
     auto prefetch = [&](int64_t ch, int tk0, int ntk) {
 #pragma unroll
         for (int r = 0; r < XR; ++r) {
             const int idx = threadIdx.x + r * 64 * W;
-            xpre[r] = idx < ntk * CW ? x_at(ch, tk0, idx) : 0.0;
+            xpre[r] = idx < nrows(ntk) * CW ? x_at(ch, tk0, idx) : 0.0;
         }
     };
     // zero rows past any tile: read (and discarded) by lanes past their runs
@@ -472,9 +489,9 @@ __global__ __launch_bounds__(64 * W) void k_band(int64_t rows, int64_t nch, int6
 #pragma unroll
         for (int r = 0; r < XR; ++r) {
             const int idx = threadIdx.x + r * 64 * W;
-            if (idx < ntk * CW) X[idx] = xpre[r];
+            if (idx < nrows(ntk) * CW) X[idx] = xpre[r];
         }
-        for (int idx = threadIdx.x + XR * 64 * W; idx < ntk * CW; idx += 64 * W) X[idx] = x_at(ch, tk0, idx);
+        for (int idx = threadIdx.x + XR * 64 * W; idx < nrows(ntk) * CW; idx += 64 * W) X[idx] = x_at(ch, tk0, idx);
         lds_barrier();
         if (ch + 1 < c1) {  // the next chunk's x, in flight during this chunk's walk
             tl_next = TL[rb * nch + ch + 1];
@@ -504,23 +521,30 @@ __global__ __launch_bounds__(64 * W) void k_band(int64_t rows, int64_t nch, int6
                 const int start = wave_incl_sum(len) - len;
                 const int mx = wave_max_nonneg(len);
                 const T *vals = reinterpret_cast<const T *>(g + META) + start;
+                // row of the lag klo - b + u for the step b after the current one: u + BB - 1 - b
                 const double *xr = X + (klo - tk0) * CW + col;
-                double sum = 0.0;
+                double sum[BB];
+#pragma unroll
+                for (int b = 0; b < BB; ++b) sum[b] = 0.0;
                 // kBandStep lags a step, every read issued before the
                 // products; a lane past its run reads the values after it (in
                 // LDS) and zero or staged x rows, and adds zero products
                 for (int p = 0; p < mx; p += kBandStep) {
                     T v[kBandStep];
-                    double xv[kBandStep];
+                    double xv[kBandStep + BB - 1];
+#pragma unroll
+                    for (int u = 0; u < kBandStep; ++u) v[u] = vals[p + u];
+#pragma unroll
+                    for (int j = 0; j < kBandStep + BB - 1; ++j) xv[j] = xr[(p + j) * CW];
 #pragma unroll
                     for (int u = 0; u < kBandStep; ++u) {
-                        v[u] = vals[p + u];
-                        xv[u] = xr[(p + u) * CW];
-                    }
+                        const double mv = masked(v[u], p + u < len);
 #pragma unroll
-                    for (int u = 0; u < kBandStep; ++u) sum = fma(masked(v[u], p + u < len), xv[u], sum);
+                        for (int b = 0; b < BB; ++b) sum[b] = fma(mv, xv[u + BB - 1 - b], sum[b]);
+                    }
                 }
-                acc[q] += sum;
+#pragma unroll
+                for (int b = 0; b < BB; ++b) acc[q][b] += sum[b];
             }
             bch = nch_;
             bq0 = nq0;
@@ -533,76 +557,91 @@ __global__ __launch_bounds__(64 * W) void k_band(int64_t rows, int64_t nch, int6
         wait_vm<NP>();
     }
 #pragma unroll
-    for (int q = 0; q < GW; ++q) {
-        double v = acc[q];
-        for (int off = CW / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        acc[q] = v;
-    }
+    for (int q = 0; q < GW; ++q)
+#pragma unroll
+        for (int b = 0; b < BB; ++b) {
+            double v = acc[q][b];
+            for (int off = CW / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            acc[q][b] = v;
+        }
     if (col == 0)
 #pragma unroll
         for (int q = 0; q < GW; ++q) {
             const int64_t r = 2 * (q0w + q) + lane / CW;
-            if (q < ngw && r < rows) part[sp * rows + r] = acc[q];
+            if (q < ngw && r < rows)
+#pragma unroll
+                for (int b = 0; b < BB; ++b) part[(sp * BB + b) * rows + r] = acc[q][b];
         }
 }
 
-template <typename T, int W, int NP>
+template <typename T, int W, int NP, int BB>
 static void band_launch(hipStream_t s, const Band &b, bool fp32, const double *x, int64_t ldx, int64_t K,
                         int64_t head, int64_t slot0, double *part)
 {
     const int64_t cps = (b.nch + b.nsplit - 1) / b.nsplit;
-    const size_t lds = band_lds(b.tmax, b.lmax, W, NP, fp32);
+    const size_t lds = band_lds(b.tmax, b.lmax, W, NP, fp32, BB);
     static bool attr = false;
     if (!attr) {
-        hip_check(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_band<T, W, NP>),
+        hip_check(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_band<T, W, NP, BB>),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, kBandLdsBytes),
                   "band kernel attribute");
         attr = true;
     }
-    const int xrows = band_xrows(b.tmax, b.lmax);
-    hipLaunchKernelGGL((k_band<T, W, NP>), dim3((unsigned)b.nrb, (unsigned)b.nsplit), dim3(64 * W), lds, s, b.rows,
-                       b.nch, cps, b.hdr.as<uint64_t>(), b.tile.as<uint32_t>(), b.stream.as<char>(), x, ldx, K,
-                       head, slot0, xrows, part);
+    const int xrows = band_xrows(b.tmax, b.lmax, BB);
+    hipLaunchKernelGGL((k_band<T, W, NP, BB>), dim3((unsigned)b.nrb, (unsigned)b.nsplit), dim3(64 * W), lds, s,
+                       b.rows, b.nch, cps, b.hdr.as<uint64_t>(), b.tile.as<uint32_t>(), b.stream.as<char>(), x, ldx,
+                       K, head, slot0, xrows, part);
 }
 
-template <typename T, int W>
+template <typename T, int W, int BB>
 static void band_pieces(hipStream_t s, const Band &b, bool fp32, const double *x, int64_t ldx, int64_t K,
                         int64_t head, int64_t slot0, double *part)
 {
 #define QHP_NP(P)                                                                    \
     if constexpr (2 * W * P <= 160)                                                  \
-        if (b.np == P) return band_launch<T, W, P>(s, b, fp32, x, ldx, K, head, slot0, part);
+        if (b.np == P) return band_launch<T, W, P, BB>(s, b, fp32, x, ldx, K, head, slot0, part);
     QHP_NP(2) QHP_NP(3) QHP_NP(4) QHP_NP(5) QHP_NP(6) QHP_NP(8) QHP_NP(10) QHP_NP(12) QHP_NP(14) QHP_NP(16)
     QHP_NP(20) QHP_NP(24) QHP_NP(32)
 #undef QHP_NP
     throw Fail{QHP_EINVAL, "band kernel shape not built"};
 }
 
-template <typename T>
+template <typename T, int BB>
 static void band_dispatch(hipStream_t s, const Band &b, bool fp32, const double *x, int64_t ldx, int64_t K,
                           int64_t head, int64_t slot0, double *part)
 {
     switch (b.waves) {
-    case 16: return band_pieces<T, 16>(s, b, fp32, x, ldx, K, head, slot0, part);
-    case 12: return band_pieces<T, 12>(s, b, fp32, x, ldx, K, head, slot0, part);
-    case 8: return band_pieces<T, 8>(s, b, fp32, x, ldx, K, head, slot0, part);
-    case 4: return band_pieces<T, 4>(s, b, fp32, x, ldx, K, head, slot0, part);
-    case 2: return band_pieces<T, 2>(s, b, fp32, x, ldx, K, head, slot0, part);
-    default: throw Fail{QHP_EINVAL, "band kernel shape not built"};
+    case 16:
+        if constexpr (BB == 1) return band_pieces<T, 16, BB>(s, b, fp32, x, ldx, K, head, slot0, part);
+        break;
+    case 12: return band_pieces<T, 12, BB>(s, b, fp32, x, ldx, K, head, slot0, part);
+    case 8: return band_pieces<T, 8, BB>(s, b, fp32, x, ldx, K, head, slot0, part);
+    case 4: return band_pieces<T, 4, BB>(s, b, fp32, x, ldx, K, head, slot0, part);
+    case 2: return band_pieces<T, 2, BB>(s, b, fp32, x, ldx, K, head, slot0, part);
+    default: break;
     }
+    throw Fail{QHP_EINVAL, "band kernel shape not built"};
 }
 
 void launch_band(hipStream_t s, const Band &b, bool fp32, const double *x, int64_t ldx, int64_t K, int64_t head,
                  int64_t slot0, double *part)
 {
     if (!band_shape_built(b.waves, b.np)) throw Fail{QHP_EINVAL, "band kernel shape not built"};
-    if (fp32) band_dispatch<float>(s, b, fp32, x, ldx, K, head, slot0, part);
-    else band_dispatch<double>(s, b, fp32, x, ldx, K, head, slot0, part);
+    if (b.block == 1) {
+        if (fp32) band_dispatch<float, 1>(s, b, fp32, x, ldx, K, head, slot0, part);
+        else band_dispatch<double, 1>(s, b, fp32, x, ldx, K, head, slot0, part);
+    } else if (b.block == kBandBlock) {
+        if (fp32) band_dispatch<float, kBandBlock>(s, b, fp32, x, ldx, K, head, slot0, part);
+        else band_dispatch<double, kBandBlock>(s, b, fp32, x, ldx, K, head, slot0, part);
+    } else {
+        throw Fail{QHP_EINVAL, "band pass of an unsupported step count"};
+    }
 }
 
 __global__ void k_fac_combine(int64_t ne, int64_t nc, const int32_t *cells, const double *area, double T0,
                               const int32_t *einv, const int32_t *cinv, const double *pac, int nsac,
-                              const double *ps, int nss, double *em, int64_t ld)
+                              const double *ps, int nss, const double *pacf, int nsacf, const double *psf, int nssf,
+                              int b, int nb, double *em, int64_t ld)
 {
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= ne) return;
@@ -616,16 +655,27 @@ __global__ void k_fac_combine(int64_t ne, int64_t nc, const int32_t *cells, cons
         sp += ps[q * nc + cps];
         sm += ps[q * nc + cms];
     }
+    if (pacf) {  // the far lags, from the pass's partials of this step
+        for (int q = 0; q < nsacf; ++q) {
+            a += pacf[((int64_t)q * nb + b) * 2 * ne + ms];
+            c += pacf[((int64_t)q * nb + b) * 2 * ne + ne + ms];
+        }
+        for (int q = 0; q < nssf; ++q) {
+            sp += psf[((int64_t)q * nb + b) * nc + cps];
+            sm += psf[((int64_t)q * nb + b) * nc + cms];
+        }
+    }
     em[m] = a - T0 * (sp / area[cp] - sm / area[cm]);
     em[ld + m] = c;
 }
 
 void launch_fac_combine(hipStream_t s, int64_t ne, int64_t nc, const int32_t *cells, const double *area, double T0,
                         const int32_t *einv, const int32_t *cinv, const double *pac, int nsac, const double *ps,
-                        int nss, double *em, int64_t ld)
+                        int nss, const double *pacf, int nsacf, const double *psf, int nssf, int b, int nb,
+                        double *em, int64_t ld)
 {
     hipLaunchKernelGGL(k_fac_combine, dim3(nblk(ne, 256)), dim3(256), 0, s, ne, nc, cells, area, T0, einv, cinv, pac,
-                       nsac, ps, nss, em, ld);
+                       nsac, ps, nss, pacf, nsacf, psf, nssf, b, nb, em, ld);
 }
 
 __global__ void k_fac_post_a(int64_t nc, const int32_t *tri_edge, const int32_t *tri_sign, const double *area,
