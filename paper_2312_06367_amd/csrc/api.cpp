@@ -924,6 +924,8 @@ extern "C" int qhp_set_incident(qhp_ctx *ctx, const qhp_wave *waves, int32_t n_r
         if (f.has_far) {
             f.pacf.alloc(sizeof(double) * std::max(f.ac64.nsplit, f.ac32.nsplit) * qhp::kBandBlock * 2 * ne);
             f.psf.alloc(sizeof(double) * std::max(f.sq64.nsplit, f.sq32.nsplit) * qhp::kBandBlock * nc);
+            f.pacr.alloc(sizeof(double) * qhp::kBandBlock * 2 * ne);
+            f.psr.alloc(sizeof(double) * qhp::kBandBlock * nc);
         }
         f.far_valid = false;
         for (qhp::DBuf *b : {&f.jx, &f.cq, &f.zy, &f.em}) zero(*b, s);
@@ -978,6 +980,8 @@ static void do_step(qhp_ctx *c, double *j_out, double *y_out)
             if (eb[1]) hip_check(hipEventRecord(eb[1], s), "event");
             qhp::launch_band(s, bsq, fp32, f.cq.as<double>(), nc, K, c->head, 0, f.psf.as<double>());
             if (eb[2]) hip_check(hipEventRecord(eb[2], s), "event");
+            qhp::launch_sum_splits(s, 2 * ne, bac.nsplit, B, f.pacf.as<double>(), f.pacr.as<double>());
+            qhp::launch_sum_splits(s, nc, bsq.nsplit, B, f.psf.as<double>(), f.psr.as<double>());
             f.far_start = i;
             f.far_valid = true;
         }
@@ -985,9 +989,8 @@ static void do_step(qhp_ctx *c, double *j_out, double *y_out)
         qhp::launch_band(s, bsqn, fp32, f.cq.as<double>(), nc, K, c->head, 0, f.ps.as<double>());
         qhp::launch_fac_combine(s, ne, nc, c->args.cells, c->args.area, c->T0, f.einv.as<int32_t>(),
                                 f.cinv.as<int32_t>(), f.pac.as<double>(), bacn.nsplit, f.ps.as<double>(), bsqn.nsplit,
-                                f.has_far ? f.pacf.as<double>() : nullptr, bac.nsplit,
-                                f.has_far ? f.psf.as<double>() : nullptr, bsq.nsplit, (int)(i - f.far_start), B,
-                                f.em.as<double>(), ld);
+                                f.has_far ? f.pacr.as<double>() : nullptr, 1, f.has_far ? f.psr.as<double>() : nullptr,
+                                1, (int)(i - f.far_start), B, f.em.as<double>(), ld);
         qhp::launch_history(s, f.pem_prec, ne, ld, 1, 2, f.pem_prec == QHP_F64 ? f.pem64.p : f.pem32.p, nullptr,
                             f.em.p, 2, 0, r_i, c->bvec.as<double>(), c->partial.p, f.pem_splits, nullptr, e1,
                             f.pem_variant);

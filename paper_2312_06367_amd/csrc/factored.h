@@ -51,7 +51,9 @@ struct Band {
     int waves = 16;         // waves per work-group
     int np = 1;             // 1 KB copy pieces per batch (two batch buffers a wave)
     int block = 1;          // steps of one pass (products per value); 1: one step
+    int64_t cmax = 0;       // most chunks holding values in one row block
     DBuf hdr, tile, stream;
+    DBuf clist, clen;       // clist[rb][j], j < clen[rb]: the chunks of row block rb that hold values
 };
 
 // Build a family from dense FP64 lag matrices, rows and columns in the
@@ -89,6 +91,9 @@ void launch_fac_combine(hipStream_t s, int64_t ne, int64_t nc, const int32_t *ce
                         int nss, const double *pacf, int nsacf, const double *psf, int nssf, int b, int nb,
                         double *em, int64_t ld);
 
+// out[b][e] = sum over the splits s of part[s][b][e] (e < n, b < nb)
+void launch_sum_splits(hipStream_t s, int64_t n, int nsplit, int nb, const double *part, double *out);
+
 // after the solve of step i: sv = Sigma^T y (cells), cslot (stored order) = sv / A
 void launch_fac_post_a(hipStream_t s, int64_t nc, const int32_t *tri_edge, const int32_t *tri_sign,
                        const double *area, const int32_t *cinv, const double *y, double *sv, double *cslot);
@@ -110,6 +115,7 @@ struct qhp_ctx::FacState {
     qhp::DBuf pem64, pem32;            // [P_E; P_M] [2][ne][ld]
     qhp::DBuf eperm, einv, cperm, cinv;  // stored orders of the edges and cells
     qhp::DBuf jx, cq, zy, sv, em, pac, ps, pacf, psf;
+    qhp::DBuf pacr, psr;               // the far partials summed over splits: [kBandBlock][2 ne], [kBandBlock][nc]
     int zcur = 0;                      // which half of zy holds L_Sigma^+ Sigma^T y_{i-1}
     int pem_variant = -1, pem_splits = 1;
     // arithmetic of the [P_E P_M] product: QHP_F64, or QHP_F32A (FP32 P_E, P_M)

@@ -216,12 +216,13 @@ void build_band(hipStream_t s, int64_t rows, int64_t cols, int64_t lag0, int64_t
     hip_check(hipStreamSynchronize(s), "band scan");
     std::vector<size_t> gbytes(ng);
     int64_t nnz = 0;
-    size_t gmax = 0;
+    size_t gmax = 0, gsum = 0;
     int lm = 0;
     for (int64_t g = 0; g < ng; ++g) {
         gbytes[g] = hc[g] ? (META + hc[g] * vsz + 15) / 16 * 16 : 0;
         nnz += hc[g];
         gmax = std::max(gmax, gbytes[g]);
+        gsum += gbytes[g];
         lm = std::max(lm, hlm[g]);
     }
     // the lags the groups of a row block of qpb groups use in each chunk
@@ -249,16 +250,34 @@ void build_band(hipStream_t s, int64_t rows, int64_t cols, int64_t lag0, int64_t
     // (fewer waves hide less latency), then the most waves, whose buffers and
     // staged x fit the LDS; a batch holds at least the largest group
     const int npmin = (int)((gmax + 1023) / 1024);
+    // a small band (a few hundred KB a CU) is bound by each work-group's
+    // latency, not by bytes in flight: 8 waves and the smallest batch that
+    // holds the largest group, so that several work-groups share a CU
+    const bool small = gsum < ((size_t)64 << 20);
     std::vector<uint32_t> tile, tw;
     int waves = 0, np = 0, tmax = 0;
     for (int w : kBandWaves) {
         if (block > 1 && w > 12) continue;  // the pass's kBandBlock sums a row need the registers of <= 12 waves
+        if (small && w != 8 && waves) continue;
         const int tm = tiles((int64_t)w * kBandRowsPerWave / 2, tw);
-        int p = 0;  // the largest batch built for this size that fits
+        int p = 0;  // the largest batch built for this size that fits (small: the smallest that holds a group)
         for (int q : kBandPieces)
-            if (band_shape_built(w, q) && band_lds(tm, lm, w, q, fp32, block) <= (size_t)kBandLdsBytes) p = q;
+            if (band_shape_built(w, q) && band_lds(tm, lm, w, q, fp32, block) <= (size_t)kBandLdsBytes &&
+                (!small || !p || p < npmin))
+                p = q;
         if (p < npmin) continue;
-        auto score = [](int w_, int p_) { return w_ * p_ * std::min(w_, 8); };
+        if (small) {
+            if (!waves || w == 8) {
+                waves = w;
+                np = p;
+                tmax = tm;
+                tile = tw;
+            }
+            continue;
+        }
+        // a pass of several steps does several products per value: its walk
+        // needs more waves to hide, counted in full up to 12
+        auto score = [&](int w_, int p_) { return w_ * p_ * std::min(w_, block > 1 ? 12 : 8); };
         if (!waves || score(w, p) > score(waves, np)) {
             waves = w;
             np = p;
@@ -306,13 +325,23 @@ void build_band(hipStream_t s, int64_t rows, int64_t cols, int64_t lag0, int64_t
     out.np = np;
     upload(out.hdr, hdr, s);
     upload(out.tile, tile, s);
+    // per row block the chunks whose tile holds lags (the others have no value)
+    std::vector<int32_t> clist(out.nrb * nch, 0), clen(out.nrb, 0);
+    out.cmax = 0;
+    for (int64_t rb = 0; rb < out.nrb; ++rb) {
+        for (int64_t ch = 0; ch < nch; ++ch)
+            if (tile[rb * nch + ch] >> 16) clist[rb * nch + clen[rb]++] = (int32_t)ch;
+        out.cmax = std::max<int64_t>(out.cmax, clen[rb]);
+    }
+    upload(out.clist, clist, s);
+    upload(out.clen, clen, s);
     // a batch's copy reads np whole 1 KB pieces from its first group on
     out.stream.alloc(off + (size_t)np * 1024 + 1024);
     hip_check(hipMemsetAsync(out.stream.p, 0, off + (size_t)np * 1024 + 1024, s), "stream");
     hipLaunchKernelGGL(k_band_fill, dim3(nblk(ng * 64, 256)), dim3(256), 0, s, rows, cols, nch, ng, qpb, src, fp32,
                        out.hdr.as<uint64_t>(), meta.as<uint32_t>(), out.stream.as<char>());
     hip_check(hipStreamSynchronize(s), "band fill");
-    out.nsplit = band_splits(out.nrb, nch);
+    out.nsplit = out.cmax ? band_splits(out.nrb, out.cmax) : 1;
 }
 
 namespace {
@@ -396,6 +425,7 @@ __device__ __forceinline__ void wait_vm()
 template <typename T, int W, int NP, int BB>
 __global__ __launch_bounds__(64 * W) void k_band(int64_t rows, int64_t nch, int64_t cps,
                                                  const uint64_t *__restrict__ hdr, const uint32_t *__restrict__ tile,
+                                                 const int32_t *__restrict__ clist, const int32_t *__restrict__ clen,
                                                  const char *__restrict__ stream, const double *__restrict__ x,
                                                  int64_t ldx, int64_t K, int64_t head, int64_t slot0, int xrows,
                                                  double *__restrict__ part)
@@ -409,7 +439,13 @@ __global__ __launch_bounds__(64 * W) void k_band(int64_t rows, int64_t nch, int6
     constexpr int64_t batch = (int64_t)NP * 1024;
     char *bufs = reinterpret_cast<char *>(smem + (int64_t)xrows * CW) + (int64_t)wave * 2 * batch;
     const int64_t rb = blockIdx.x, sp = blockIdx.y;
-    const int64_t c0 = sp * cps, c1 = (c0 + cps < nch) ? c0 + cps : nch;
+    // chunk positions below index the row block's list of chunks that hold
+    // values (CLk: position -> chunk); the split takes cps of them
+    typedef const __attribute__((address_space(4))) int32_t *cint_t;
+    const cint_t CL = (cint_t)clist, CN = (cint_t)clen;
+    auto CLk = [&](int64_t j) { return (int64_t)CL[rb * nch + j]; };
+    const int64_t nlist = CN[rb];
+    const int64_t c0 = sp * cps, c1 = (c0 + cps < nlist) ? c0 + cps : nlist;
     const int64_t q0w = rb * W * GW + (int64_t)wave * GW;  // first group (row pair) of this wave
     const int64_t nqt = (rows + 1) / 2;
     const int ngw = nqt - q0w < GW ? (int)(nqt - q0w) : GW;  // groups of this wave (may be <= 0)
@@ -426,7 +462,7 @@ __global__ __launch_bounds__(64 * W) void k_band(int64_t rows, int64_t nch, int6
     const chdr_t H = (chdr_t)hdr;
     const ctile_t TL = (ctile_t)tile;
     const int64_t qpb = (int64_t)W * GW;
-    auto hidx = [&](int64_t ch, int q) { return (rb * nch + ch) * qpb + (int64_t)wave * GW + q; };
+    auto hidx = [&](int64_t ch, int q) { return (rb * nch + CLk(ch)) * qpb + (int64_t)wave * GW + q; };
     auto gsize = [&](int64_t ch, int q) { return q < ngw ? (int64_t)(H[hidx(ch, q)] >> 40) * 16 : 0; };
     // the batch after groups [.., q0) of chunk ch: skip empty groups, then take
     // consecutive groups while they fit the batch; false when none is left
@@ -460,7 +496,7 @@ __global__ __launch_bounds__(64 * W) void k_band(int64_t rows, int64_t nch, int6
     // registers, loaded a chunk ahead
     constexpr int XR = (kBandPrefetchLags * CW + 64 * W - 1) / (64 * W);
     auto x_at = [&](int64_t ch, int tk0, int idx) {
-        const int64_t k = tk0 - (BB - 1) + idx / CW, cc = ch * CW + idx % CW;
+        const int64_t k = tk0 - (BB - 1) + idx / CW, cc = CLk(ch) * CW + idx % CW;
         const int64_t slot = k == 0 ? slot0 : (head + k - 1) % K;
         return cc < ldx ? x[slot * ldx + cc] : 0.0;
     };
@@ -476,7 +512,7 @@ __global__ __launch_bounds__(64 * W) void k_band(int64_t rows, int64_t nch, int6
     };
     // zero rows past any tile: read (and discarded) by lanes past their runs
     for (int idx = threadIdx.x; idx < xrows * CW; idx += 64 * W) X[idx] = 0.0;
-    uint32_t tl_next = c0 < c1 ? TL[rb * nch + c0] : 0u;
+    uint32_t tl_next = c0 < c1 ? TL[rb * nch + CLk(c0)] : 0u;
     prefetch(c0, (int)(tl_next & 0xffff), (int)(tl_next >> 16));
     int64_t bch = c0;
     int bq0 = 0, bq1 = 0, cur = 0;
@@ -494,7 +530,7 @@ __global__ __launch_bounds__(64 * W) void k_band(int64_t rows, int64_t nch, int6
         for (int idx = threadIdx.x + XR * 64 * W; idx < nrows(ntk) * CW; idx += 64 * W) X[idx] = x_at(ch, tk0, idx);
         lds_barrier();
         if (ch + 1 < c1) {  // the next chunk's x, in flight during this chunk's walk
-            tl_next = TL[rb * nch + ch + 1];
+            tl_next = TL[rb * nch + CLk(ch + 1)];
             prefetch(ch + 1, (int)(tl_next & 0xffff), (int)(tl_next >> 16));
         }
         while (have && bch == ch) {
@@ -578,7 +614,7 @@ template <typename T, int W, int NP, int BB>
 static void band_launch(hipStream_t s, const Band &b, bool fp32, const double *x, int64_t ldx, int64_t K,
                         int64_t head, int64_t slot0, double *part)
 {
-    const int64_t cps = (b.nch + b.nsplit - 1) / b.nsplit;
+    const int64_t cps = (b.cmax + b.nsplit - 1) / b.nsplit;
     const size_t lds = band_lds(b.tmax, b.lmax, W, NP, fp32, BB);
     static bool attr = false;
     if (!attr) {
@@ -589,8 +625,8 @@ static void band_launch(hipStream_t s, const Band &b, bool fp32, const double *x
     }
     const int xrows = band_xrows(b.tmax, b.lmax, BB);
     hipLaunchKernelGGL((k_band<T, W, NP, BB>), dim3((unsigned)b.nrb, (unsigned)b.nsplit), dim3(64 * W), lds, s,
-                       b.rows, b.nch, cps, b.hdr.as<uint64_t>(), b.tile.as<uint32_t>(), b.stream.as<char>(), x, ldx,
-                       K, head, slot0, xrows, part);
+                       b.rows, b.nch, cps, b.hdr.as<uint64_t>(), b.tile.as<uint32_t>(), b.clist.as<int32_t>(),
+                       b.clen.as<int32_t>(), b.stream.as<char>(), x, ldx, K, head, slot0, xrows, part);
 }
 
 template <typename T, int W, int BB>
@@ -676,6 +712,22 @@ void launch_fac_combine(hipStream_t s, int64_t ne, int64_t nc, const int32_t *ce
 {
     hipLaunchKernelGGL(k_fac_combine, dim3(nblk(ne, 256)), dim3(256), 0, s, ne, nc, cells, area, T0, einv, cinv, pac,
                        nsac, ps, nss, pacf, nsacf, psf, nssf, b, nb, em, ld);
+}
+
+// out[b][e] = sum_s part[s][b][e] (e < n, b < nb), splits summed in order
+__global__ void k_sum_splits(int64_t n, int nsplit, int nb, const double *part, double *out)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * nb) return;
+    const int64_t b = e / n, i = e % n;
+    double a = 0.0;
+    for (int q = 0; q < nsplit; ++q) a += part[((int64_t)q * nb + b) * n + i];
+    out[b * n + i] = a;
+}
+
+void launch_sum_splits(hipStream_t s, int64_t n, int nsplit, int nb, const double *part, double *out)
+{
+    hipLaunchKernelGGL(k_sum_splits, dim3(nblk(n * nb, 256)), dim3(256), 0, s, n, nsplit, nb, part, out);
 }
 
 __global__ void k_fac_post_a(int64_t nc, const int32_t *tri_edge, const int32_t *tri_sign, const double *area,

@@ -915,8 +915,37 @@ __global__ __launch_bounds__(256) void k_gemv_f64(int64_t n, const double *__res
     const int lane = threadIdx.x & 63;
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (row >= n) return;
+    const double *a = A + row * n;
     double s = 0.0;
-    for (int64_t c = lane; c < n; c += 64) s += A[row * n + c] * x[c];
+    int64_t c0 = 0;  // columns before c0 done by the 16-byte loads
+    if ((n & 1) == 0 && ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(x)) & 15) == 0) {
+        // rows 16-byte aligned: chunks of 128 columns, 16 bytes a lane, four chunks in flight
+        typedef double d2 __attribute__((ext_vector_type(2)));
+        const int64_t nfull = n / 128;
+        double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int64_t t = 0;
+        for (; t + 4 <= nfull; t += 4) {
+            d2 v[4], w[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t c = (t + u) * 128 + 2 * lane;
+                v[u] = *reinterpret_cast<const d2 *>(a + c);
+                w[u] = *reinterpret_cast<const d2 *>(x + c);
+            }
+            s = fma(v[0].x, w[0].x, fma(v[0].y, w[0].y, s));
+            s1 = fma(v[1].x, w[1].x, fma(v[1].y, w[1].y, s1));
+            s2 = fma(v[2].x, w[2].x, fma(v[2].y, w[2].y, s2));
+            s3 = fma(v[3].x, w[3].x, fma(v[3].y, w[3].y, s3));
+        }
+        for (; t < nfull; ++t) {
+            const int64_t c = t * 128 + 2 * lane;
+            const d2 v = *reinterpret_cast<const d2 *>(a + c), w = *reinterpret_cast<const d2 *>(x + c);
+            s = fma(v.x, w.x, fma(v.y, w.y, s));
+        }
+        s += (s1 + s2) + s3;
+        c0 = nfull * 128;
+    }
+    for (int64_t c = c0 + lane; c < n; c += 64) s += a[c] * x[c];
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
     if (lane == 0) y[row] = s;
 }
