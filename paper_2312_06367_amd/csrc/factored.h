@@ -28,7 +28,10 @@ constexpr int kBandPrefetchLags = 128;  // lags of a chunk's x loaded ahead thro
 // i .. i + kBandBlock - 1 use only the currents of steps <= i - 1, so one pass
 // over the values at step i gives all of them (each value serves kBandBlock
 // products); the near lags (k < kBandBlock) are applied every step
-constexpr int kBandBlock = 4;
+constexpr int kBandBlock = 8;
+// groups (row pairs) a wave takes in a chunk: fewer in a pass of several
+// steps, whose sums per row multiply with the steps
+constexpr int band_groups_per_wave(int block) { return block > 4 ? 4 : kBandRowsPerWave / 2; }
 
 // One lag-banded family of matrices X_k, k in [lag0, lag1], rows x cols.
 // Rows 2q, 2q + 1 and the chunk ch of kBandChunk columns form the group

@@ -259,7 +259,7 @@ void build_band(hipStream_t s, int64_t rows, int64_t cols, int64_t lag0, int64_t
     for (int w : kBandWaves) {
         if (block > 1 && w > 12) continue;  // the pass's kBandBlock sums a row need the registers of <= 12 waves
         if (small && w != 8 && waves) continue;
-        const int tm = tiles((int64_t)w * kBandRowsPerWave / 2, tw);
+        const int tm = tiles((int64_t)w * band_groups_per_wave(block), tw);
         int p = 0;  // the largest batch built for this size that fits (small: the smallest that holds a group)
         for (int q : kBandPieces)
             if (band_shape_built(w, q) && band_lds(tm, lm, w, q, fp32, block) <= (size_t)kBandLdsBytes &&
@@ -302,7 +302,7 @@ void build_band(hipStream_t s, int64_t rows, int64_t cols, int64_t lag0, int64_t
                          tr[tr.size() * 9 / 10], tr.back());
     }
     if (!waves) throw Fail{QHP_EINVAL, "factored history: a band group does not fit the LDS"};
-    const int64_t qpb = (int64_t)waves * kBandRowsPerWave / 2;
+    const int64_t qpb = (int64_t)waves * band_groups_per_wave(block);
     out.nrb = (nq + qpb - 1) / qpb;
     // offsets in stored order: row block, chunk, group (the headers of a
     // wave's groups in one chunk are consecutive)
@@ -430,7 +430,7 @@ __global__ __launch_bounds__(64 * W) void k_band(int64_t rows, int64_t nch, int6
                                                  int64_t ldx, int64_t K, int64_t head, int64_t slot0, int xrows,
                                                  double *__restrict__ part)
 {
-    constexpr int GW = kBandRowsPerWave / 2;  // groups (row pairs) of a wave in a chunk
+    constexpr int GW = band_groups_per_wave(BB);  // groups (row pairs) of a wave in a chunk
     extern __shared__ double smem[];
     double *X = smem;
     // the wave index is uniform: group quantities below stay in scalar registers

@@ -126,6 +126,7 @@ def test_factored_passes_in_pieces(precision):
     not multiples of the pass (7, 5, then single steps) equals one run of the
     same steps to rounding (Sec. IV-B march; the sums are the same, grouped
     differently)."""
+    # K = 15 on this mesh: several passes of band_block steps in 24 steps
     import paper_2312_06367_amd as qhp
     from workloads import meshes, waves
     xyz, tri = meshes.icosphere(1)
@@ -143,7 +144,7 @@ def test_factored_passes_in_pieces(precision):
 
     s = solver()
     inf = s.info()
-    assert inf["band_block"] == 4 and inf["K"] > 4
+    assert inf["band_block"] > 1 and inf["K"] > inf["band_block"]
     ne = inf["ne"]
     one = torch.zeros((n, ne, 1), dtype=torch.float64, device="cuda")
     s.run(n, one)
