@@ -55,6 +55,7 @@ struct Band {
     int np = 1;             // 1 KB copy pieces per batch (two batch buffers a wave)
     int block = 1;          // steps of one pass (products per value); 1: one step
     int64_t cmax = 0;       // most chunks holding values in one row block
+    bool direct = false;    // runs of at most kBandStep lags: the direct product (no LDS staging)
     DBuf hdr, tile, stream;
     DBuf clist, clen;       // clist[rb][j], j < clen[rb]: the chunks of row block rb that hold values
 };

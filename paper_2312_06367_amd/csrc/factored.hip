@@ -342,6 +342,9 @@ void build_band(hipStream_t s, int64_t rows, int64_t cols, int64_t lag0, int64_t
                        out.hdr.as<uint64_t>(), meta.as<uint32_t>(), out.stream.as<char>());
     hip_check(hipStreamSynchronize(s), "band fill");
     out.nsplit = out.cmax ? band_splits(out.nrb, out.cmax) : 1;
+    // runs of at most kBandStep lags (a near band): the direct product, one partial
+    out.direct = block == 1 && lag1 - kfirst + 1 <= kBandStep;
+    if (out.direct) out.nsplit = 1;
 }
 
 namespace {
@@ -610,6 +613,47 @@ __global__ __launch_bounds__(64 * W) void k_band(int64_t rows, int64_t nch, int6
         }
 }
 
+// The product of a band of short runs (at most kBandStep lags, the near
+// lags): one wave per row pair, over the groups of its row block's chunks
+// that hold values, values and x read straight from memory (the few ring
+// slots stay in L2), no LDS and no barrier; lane l takes pair l of a group.
+// FP64 sums per lane, reduced over each half-wave (one row); one partial.
+template <typename T>
+__global__ __launch_bounds__(256) void k_band_direct(int64_t rows, int64_t nch, int64_t qpb,
+                                                     const uint64_t *__restrict__ hdr,
+                                                     const int32_t *__restrict__ clist,
+                                                     const int32_t *__restrict__ clen, const char *__restrict__ stream,
+                                                     const double *__restrict__ x, int64_t ldx, int64_t K,
+                                                     int64_t head, int64_t slot0, double *__restrict__ part)
+{
+    const int lane = threadIdx.x & 63, col = lane & (CW - 1);
+    const int64_t q = __builtin_amdgcn_readfirstlane((int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    if (q >= (rows + 1) / 2) return;  // whole waves
+    const int64_t rb = q / qpb, i = q % qpb;
+    const int n = clen[rb];
+    double acc = 0.0;
+    for (int j = 0; j < n; ++j) {
+        const int64_t ch = clist[rb * nch + j];
+        const uint64_t h = hdr[(rb * nch + ch) * qpb + i];
+        if ((h >> 40) == 0) continue;
+        const char *g = stream + (h & ((1ull << 40) - 1)) * 16;
+        const uint32_t w = reinterpret_cast<const uint32_t *>(g)[lane];
+        const int len = (int)(w >> 16), klo = (int)(w & 0xffff);
+        const int start = wave_incl_sum(len) - len;
+        const T *vals = reinterpret_cast<const T *>(g + META) + start;
+        const int64_t cc = ch * CW + col;
+        for (int p = 0; p < len; ++p) {
+            const int64_t k = klo + p;
+            int64_t slot = k == 0 ? slot0 : head + k - 1;
+            if (k != 0 && slot >= K) slot -= K;
+            acc = fma((double)vals[p], cc < ldx ? x[slot * ldx + cc] : 0.0, acc);
+        }
+    }
+    for (int off = CW / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    const int64_t r = 2 * q + lane / CW;
+    if (col == 0 && r < rows) part[r] = acc;
+}
+
 template <typename T, int W, int NP, int BB>
 static void band_launch(hipStream_t s, const Band &b, bool fp32, const double *x, int64_t ldx, int64_t K,
                         int64_t head, int64_t slot0, double *part)
@@ -662,6 +706,19 @@ static void band_dispatch(hipStream_t s, const Band &b, bool fp32, const double 
 void launch_band(hipStream_t s, const Band &b, bool fp32, const double *x, int64_t ldx, int64_t K, int64_t head,
                  int64_t slot0, double *part)
 {
+    if (b.direct) {
+        const int64_t qpb = (int64_t)b.waves * band_groups_per_wave(b.block);
+        const unsigned grid = nblk((b.rows + 1) / 2 * 64, 256);
+        if (fp32)
+            hipLaunchKernelGGL(k_band_direct<float>, dim3(grid), dim3(256), 0, s, b.rows, b.nch, qpb,
+                               b.hdr.as<uint64_t>(), b.clist.as<int32_t>(), b.clen.as<int32_t>(), b.stream.as<char>(),
+                               x, ldx, K, head, slot0, part);
+        else
+            hipLaunchKernelGGL(k_band_direct<double>, dim3(grid), dim3(256), 0, s, b.rows, b.nch, qpb,
+                               b.hdr.as<uint64_t>(), b.clist.as<int32_t>(), b.clen.as<int32_t>(), b.stream.as<char>(),
+                               x, ldx, K, head, slot0, part);
+        return;
+    }
     if (!band_shape_built(b.waves, b.np)) throw Fail{QHP_EINVAL, "band kernel shape not built"};
     if (b.block == 1) {
         if (fp32) band_dispatch<float, 1>(s, b, fp32, x, ldx, K, head, slot0, part);
