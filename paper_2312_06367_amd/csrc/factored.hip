@@ -15,6 +15,7 @@ namespace {
 
 constexpr int CW = kBandChunk;  // columns of a chunk
 constexpr int META = 4 * 64;    // bytes of a group's words
+constexpr int kDirectChunks = 4;  // chunks of a row pair one wave of the direct product takes
 
 // value (k, r, c) of a family in stored order: rows r < split from a, the
 // others from b (row r - split), through the row and column orders rp, cp
@@ -344,7 +345,7 @@ void build_band(hipStream_t s, int64_t rows, int64_t cols, int64_t lag0, int64_t
     out.nsplit = out.cmax ? band_splits(out.nrb, out.cmax) : 1;
     // runs of at most kBandStep lags (a near band): the direct product, one partial
     out.direct = block == 1 && lag1 - kfirst + 1 <= kBandStep;
-    if (out.direct) out.nsplit = 1;
+    if (out.direct) out.nsplit = (int)std::max<int64_t>(1, (out.cmax + kDirectChunks - 1) / kDirectChunks);
 }
 
 namespace {
@@ -614,12 +615,13 @@ __global__ __launch_bounds__(64 * W) void k_band(int64_t rows, int64_t nch, int6
 }
 
 // The product of a band of short runs (at most kBandStep lags, the near
-// lags): one wave per row pair, over the groups of its row block's chunks
-// that hold values, values and x read straight from memory (the few ring
-// slots stay in L2), no LDS and no barrier; lane l takes pair l of a group.
-// FP64 sums per lane, reduced over each half-wave (one row); one partial.
+// lags): one wave per row pair and split of its row block's list of chunks
+// that hold values (cps chunks a split, so the chains of dependent loads stay
+// short), values and x read straight from memory (the few ring slots stay in
+// L2), no LDS and no barrier; lane l takes pair l of a group.  FP64 sums per
+// lane, reduced over each half-wave (one row), one partial per split.
 template <typename T>
-__global__ __launch_bounds__(256) void k_band_direct(int64_t rows, int64_t nch, int64_t qpb,
+__global__ __launch_bounds__(256) void k_band_direct(int64_t rows, int64_t nch, int64_t qpb, int64_t cps,
                                                      const uint64_t *__restrict__ hdr,
                                                      const int32_t *__restrict__ clist,
                                                      const int32_t *__restrict__ clen, const char *__restrict__ stream,
@@ -629,10 +631,10 @@ __global__ __launch_bounds__(256) void k_band_direct(int64_t rows, int64_t nch, 
     const int lane = threadIdx.x & 63, col = lane & (CW - 1);
     const int64_t q = __builtin_amdgcn_readfirstlane((int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6));
     if (q >= (rows + 1) / 2) return;  // whole waves
-    const int64_t rb = q / qpb, i = q % qpb;
-    const int n = clen[rb];
+    const int64_t rb = q / qpb, i = q % qpb, sp = blockIdx.y;
+    const int64_t j0 = sp * cps, n = clen[rb], j1 = j0 + cps < n ? j0 + cps : n;
     double acc = 0.0;
-    for (int j = 0; j < n; ++j) {
+    for (int64_t j = j0; j < j1; ++j) {
         const int64_t ch = clist[rb * nch + j];
         const uint64_t h = hdr[(rb * nch + ch) * qpb + i];
         if ((h >> 40) == 0) continue;
@@ -651,7 +653,7 @@ __global__ __launch_bounds__(256) void k_band_direct(int64_t rows, int64_t nch, 
     }
     for (int off = CW / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
     const int64_t r = 2 * q + lane / CW;
-    if (col == 0 && r < rows) part[r] = acc;
+    if (col == 0 && r < rows) part[sp * rows + r] = acc;
 }
 
 template <typename T, int W, int NP, int BB>
@@ -708,13 +710,14 @@ void launch_band(hipStream_t s, const Band &b, bool fp32, const double *x, int64
 {
     if (b.direct) {
         const int64_t qpb = (int64_t)b.waves * band_groups_per_wave(b.block);
-        const unsigned grid = nblk((b.rows + 1) / 2 * 64, 256);
+        const int64_t cps = (b.cmax + b.nsplit - 1) / b.nsplit;
+        const dim3 grid(nblk((b.rows + 1) / 2 * 64, 256), (unsigned)b.nsplit);
         if (fp32)
-            hipLaunchKernelGGL(k_band_direct<float>, dim3(grid), dim3(256), 0, s, b.rows, b.nch, qpb,
+            hipLaunchKernelGGL(k_band_direct<float>, grid, dim3(256), 0, s, b.rows, b.nch, qpb, cps,
                                b.hdr.as<uint64_t>(), b.clist.as<int32_t>(), b.clen.as<int32_t>(), b.stream.as<char>(),
                                x, ldx, K, head, slot0, part);
         else
-            hipLaunchKernelGGL(k_band_direct<double>, dim3(grid), dim3(256), 0, s, b.rows, b.nch, qpb,
+            hipLaunchKernelGGL(k_band_direct<double>, grid, dim3(256), 0, s, b.rows, b.nch, qpb, cps,
                                b.hdr.as<uint64_t>(), b.clist.as<int32_t>(), b.clen.as<int32_t>(), b.stream.as<char>(),
                                x, ldx, K, head, slot0, part);
         return;
