@@ -597,6 +597,11 @@ def bench_single(a, cfg, precision, steps, warmup, err_steps, quick, with_cpu):
                 "kernel": kname, "algorithmic_bytes_per_launch": kb, "kernel_ms_avg": head["band_ms"][0],
                 "values_per_launch": hinf["band_nnz_pairs"],
                 "steps_per_pass": hinf["band_block"],
+                # one pass serves band_block steps: band_block FP64 products per value
+                "fp64_tflops": 2.0 * hinf["band_nnz_pairs"] * max(hinf["band_block"], 1)
+                / (head["band_ms"][0] * 1e-3) / 1e12,
+                "fp64_peak_tflops": 78.6,
+                "band_bytes_per_step": kb / max(hinf["band_block"], 1) + hinf["band_bytes_near_pairs"],
                 "triangle_pair_band": {"kernel": "k_band<%s, %d, %d, %d>" % ("float" if fp32 else "double",
                                                                               hinf["band_waves_cells"],
                                                                               hinf["band_pieces_cells"],
