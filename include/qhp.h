@@ -114,7 +114,13 @@ enum {
                            blocks inverted, and the off-diagonal blocks multiplied by
                            those inverses, on the first LU step; device memory: n^2
                            doubles plus 2 x 1024^2 per started 1024 rows)            */
-    QHP_SOLVE_INV = 1,  /* inverse formed once from that LU, one product per step       */
+    QHP_SOLVE_INV = 1,  /* inverse formed once from that LU, one product per step;
+                           with QHP_FAC64 / QHP_FAC32 the product is folded into the
+                           history's last one: y_i = T_0^{-1} r_i - T_0^{-1} [P_E P_M]
+                           [E; M], with T_0^{-1} [P_E P_M] formed at assembly (2 N_E^2
+                           doubles more) and T_0^{-1} r_i for every step by
+                           qhp_set_incident (FP64, the same values up to rounding
+                           order)                                                  */
     QHP_SOLVE_GMRES = 2 /* restarted GMRES, FP32 Arnoldi inside FP64 residual
                            refinement, started from a warm-start guess (set with
                            qhp_set_gmres after assembly; one right-hand side)     */

@@ -560,17 +560,12 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
                                 f.cperm.as<int32_t>(), f.cperm.as<int32_t>(), fp32 != 0, fp32 ? f.sq32 : f.sq64, B,
                                 (int)B);
             }
-            // [P_E; P_M] as two padded blocks, FP64 and FP32
+            // [P_E; P_M] as two padded FP64 blocks
             const int64_t ld = c->ld;
             f.pem64.alloc(sizeof(double) * 2 * ne * ld);
-            f.pem32.alloc(sizeof(float) * 2 * ne * ld);
-            for (int h = 0; h < 2; ++h) {
-                const double *src = c->Pcat.as<double>() + h * ne;
-                qhp::launch_quantise_slab(s, ne, ld, src, 2 * ne, nullptr, QHP_F64, 1.0f,
+            for (int h = 0; h < 2; ++h)
+                qhp::launch_quantise_slab(s, ne, ld, c->Pcat.as<double>() + h * ne, 2 * ne, nullptr, QHP_F64, 1.0f,
                                           f.pem64.as<double>() + h * ne * ld);
-                qhp::launch_quantise_slab(s, ne, ld, src, 2 * ne, nullptr, QHP_F32, 1.0f,
-                                          f.pem32.as<float>() + h * ne * ld);
-            }
             hip_check(hipStreamSynchronize(s), "factored bands");
             if (c->verbose)
                 for (const qhp::Band *b : {&f.ac64n, &f.sq64n, &f.ac64, &f.sq64, &f.ac32n, &f.sq32n, &f.ac32, &f.sq32})
@@ -602,6 +597,15 @@ extern "C" int qhp_assemble(qhp_ctx *ctx)
         c->Tinv.alloc(sizeof(double) * nn);
         qhp::eye_plus(s, ne, 1.0, 0.0, c->LU0.as<double>(), c->Tinv.as<double>());
         qhp::getrs_f64(s, false, ne, ne, c->LU0.as<double>(), ne, c->ipiv0.as<int32_t>(), c->Tinv.as<double>(), ne);
+        if (c->fac) {  // the inverse solve folded into the factored history's last product
+            const int64_t ld = c->ld;
+            qhp_ctx::FacState &f = *c->fac;
+            f.tq64.alloc(sizeof(double) * 2 * ne * ld);
+            zero(f.tq64, s);
+            for (int h = 0; h < 2; ++h)
+                qhp::gemm_f64(s, false, false, ne, ne, ne, 1.0, c->Tinv.as<double>(), ne,
+                              c->Pcat.as<double>() + h * ne, 2 * ne, 0.0, f.tq64.as<double>() + h * ne * ld, ld);
+        }
         hip_check(hipStreamSynchronize(s), "T_0 factorisation");
     }
     c->stage("T_0 LU");
@@ -718,8 +722,6 @@ static void autotune_fac(qhp_ctx *c)
 {
     qhp_ctx::FacState &f = *c->fac;
     hipStream_t s = c->s;
-    const int32_t pp = f.pem_prec;
-    const void *pem = pp == QHP_F64 ? f.pem64.p : f.pem32.p;
     hipEvent_t e0, e1;
     hip_check(hipEventCreate(&e0), "event");
     hip_check(hipEventCreate(&e1), "event");
@@ -727,8 +729,8 @@ static void autotune_fac(qhp_ctx *c)
     for (int v = 0; v < qhp::gemv_variant_count(); ++v)
         for (int ns = 1; ns <= 2; ++ns) {
             auto run = [&]() {
-                qhp::launch_history(s, pp, c->mesh.ne, c->ld, 1, 2, pem, nullptr, f.em.p, 2, 0, c->rhs.as<double>(),
-                                    c->bvec.as<double>(), c->partial.p, ns, nullptr, nullptr, v);
+                qhp::launch_history(s, QHP_F64, c->mesh.ne, c->ld, 1, 2, f.pem64.p, nullptr, f.em.p, 2, 0,
+                                    c->rhs.as<double>(), c->bvec.as<double>(), c->partial.p, ns, nullptr, nullptr, v);
             };
             run();
             hip_check(hipEventRecord(e0, s), "event");
@@ -838,11 +840,16 @@ extern "C" int qhp_set_incident(qhp_ctx *ctx, const qhp_wave *waves, int32_t n_r
         int64_t ns_chunk = std::max<int64_t>(1, ncols_max / n_rhs);
         ns_chunk = std::min<int64_t>(ns_chunk, n_steps);
         int64_t ncols = ns_chunk * n_rhs;
-        DBuf eloc, hloc, EH, R;
+        DBuf eloc, hloc, EH, R, RT;
         eloc.alloc(sizeof(double) * ncols * nc * 3);
         hloc.alloc(sizeof(double) * ncols * nf * 3);
         EH.alloc(sizeof(double) * ncols * 2 * ne);
         R.alloc(sizeof(double) * ncols * ne);
+        c->rhst.release();
+        if (c->fac) {  // T_0^{-1} r_i of every step, for the inverse solve folded into the history
+            c->rhst.alloc(sizeof(double) * (size_t)n_steps * ne * n_rhs);
+            RT.alloc(sizeof(double) * ncols * ne);
+        }
         for (int64_t s0 = 0; s0 < n_steps; s0 += ns_chunk) {
             int64_t ns = std::min<int64_t>(ns_chunk, n_steps - s0);
             int64_t nco = ns * n_rhs;
@@ -856,6 +863,11 @@ extern "C" int qhp_set_incident(qhp_ctx *ctx, const qhp_wave *waves, int32_t n_r
             qhp::gemm_f64(s, false, true, nco, ne, 2 * ne, 1.0, EH.as<double>(), 2 * ne, c->Pcat.as<double>(),
                           2 * ne, 0.0, R.as<double>(), ne);
             qhp::launch_permute_rhs(s, ne, ns, n_rhs, R.as<double>(), c->rhs.as<double>() + s0 * ne * n_rhs);
+            if (c->rhst.p) {
+                qhp::gemm_f64(s, false, true, nco, ne, ne, 1.0, R.as<double>(), ne, c->Tinv.as<double>(), ne, 0.0,
+                              RT.as<double>(), ne);
+                qhp::launch_permute_rhs(s, ne, ns, n_rhs, RT.as<double>(), c->rhst.as<double>() + s0 * ne * n_rhs);
+            }
         }
         // bound of the growth trip: running maximum over the steps of max |r_k|
         std::vector<double> pk(n_steps);
@@ -960,6 +972,8 @@ static void do_step(qhp_ctx *c, double *j_out, double *y_out)
         c->ev.push_back(e0);
         c->ev.push_back(e1);
     }
+    double *y = c->yvec.as<double>();
+    bool solved = false;
     if (c->fac) {  // factored history: banded products, E and M, then [P_E P_M]
         qhp_ctx::FacState &f = *c->fac;
         const bool fp32 = c->p.precision == QHP_FAC32;
@@ -991,9 +1005,11 @@ static void do_step(qhp_ctx *c, double *j_out, double *y_out)
                                 f.cinv.as<int32_t>(), f.pac.as<double>(), bacn.nsplit, f.ps.as<double>(), bsqn.nsplit,
                                 f.has_far ? f.pacr.as<double>() : nullptr, 1, f.has_far ? f.psr.as<double>() : nullptr,
                                 1, (int)(i - f.far_start), B, f.em.as<double>(), ld);
-        qhp::launch_history(s, f.pem_prec, ne, ld, 1, 2, f.pem_prec == QHP_F64 ? f.pem64.p : f.pem32.p, nullptr,
-                            f.em.p, 2, 0, r_i, c->bvec.as<double>(), c->partial.p, f.pem_splits, nullptr, e1,
-                            f.pem_variant);
+        // with the inverse solve: y = T_0^{-1} r_i - T_0^{-1} [P_E P_M] [E; M], both factors formed ahead
+        solved = c->p.solver == QHP_SOLVE_INV && f.tq64.p && c->rhst.p;
+        qhp::launch_history(s, QHP_F64, ne, ld, 1, 2, solved ? f.tq64.p : f.pem64.p, nullptr, f.em.p, 2, 0,
+                            solved ? c->rhst.as<double>() + (i - 1) * ne : r_i, solved ? y : c->bvec.as<double>(),
+                            c->partial.p, f.pem_splits, nullptr, e1, f.pem_variant);
     } else if (c->mr_desc.p) {  // FP32 blocks, FP64 y and sums, several right-hand sides: the grouped kernel
         qhp::launch_set_i64(s, c->mr_head.as<int64_t>(), c->head);
         if (e0) hip_check(hipEventRecord(e0, s), "event");
@@ -1008,8 +1024,9 @@ static void do_step(qhp_ctx *c, double *j_out, double *y_out)
                                        : (c->ringb.p ? c->ringb.p : (c->ring32.p ? c->ring32.p : c->ring64.p)),
                             K, c->head, r_i, c->bvec.as<double>(), c->partial.p, c->nsplit, e0, e1, c->hv);
     }
-    double *y = c->yvec.as<double>();
-    if (c->p.solver == QHP_SOLVE_GMRES) {
+    if (solved) {
+        // y came out of the factored history's last product
+    } else if (c->p.solver == QHP_SOLVE_GMRES) {
         qhp::warm_start(c, c->bvec.as<double>(), y);
         int32_t it = 0;
         float r0 = 0.f;
@@ -1352,7 +1369,7 @@ extern "C" int qhp_query(const qhp_ctx *ctx, qhp_info *info)
         const qhp::Band &acn = fp32 ? f.ac32n : f.ac64n, &sqn = fp32 ? f.sq32n : f.sq64n;
         // bytes a step streams on average: the far pass once per kBandBlock steps
         info->slab_bytes = (ac.bytes + sq.bytes) / qhp::kBandBlock + acn.bytes + sqn.bytes +
-                           (size_t)2 * m.ne * ctx->ld * (f.pem_prec == QHP_F64 ? 8 : 4);
+                           (size_t)2 * m.ne * ctx->ld * 8;
         info->band_block = f.has_far ? qhp::kBandBlock : 0;
         info->band_bytes_near_pairs = acn.bytes;
         info->band_bytes_near_cells = sqn.bytes;

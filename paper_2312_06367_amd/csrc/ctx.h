@@ -132,6 +132,7 @@ struct qhp_ctx {
     int64_t n_steps = 0, step = 0, head = 0;
     bool broken = false;
     qhp::DBuf waves_d, rhs, ring64, ring32, ringb, ring8, bvec, zvec, yvec, partial, sv, zc, errflag;
+    qhp::DBuf rhst;  // factored history: T_0^{-1} r_i of every step [n_steps][ne] (the inverse solve)
     // FP32 blocks with FP64 y and sums for 2, 4 or 8 right-hand sides: one
     // group of the grouped work-queue kernel (descriptor, device head, counter)
     qhp::DBuf mr_desc, mr_head, mr_counter, ring64t;  // ring64t: [K][nrhs][ld] FP64 copy of the ring

@@ -116,12 +116,11 @@ struct qhp_ctx::FacState {
     bool has_far = false;              // K >= kBandBlock
     int64_t far_start = 0;             // step whose pass the far partials hold
     bool far_valid = false;            // within one qhp_run / qhp_step call
-    qhp::DBuf pem64, pem32;            // [P_E; P_M] [2][ne][ld]
+    qhp::DBuf pem64;                   // [P_E; P_M] [2][ne][ld]
+    qhp::DBuf tq64;                    // T_0^{-1} [P_E; P_M] [2][ne][ld], for the inverse solve
     qhp::DBuf eperm, einv, cperm, cinv;  // stored orders of the edges and cells
     qhp::DBuf jx, cq, zy, sv, em, pac, ps, pacf, psf;
     qhp::DBuf pacr, psr;               // the far partials summed over splits: [kBandBlock][2 ne], [kBandBlock][nc]
     int zcur = 0;                      // which half of zy holds L_Sigma^+ Sigma^T y_{i-1}
-    int pem_variant = -1, pem_splits = 1;
-    // arithmetic of the [P_E P_M] product: QHP_F64, or QHP_F32A (FP32 P_E, P_M)
-    int32_t pem_prec = QHP_F64;
+    int pem_variant = -1, pem_splits = 1;  // of the FP64 [P_E P_M] product (also T_0^{-1} [P_E P_M])
 };

@@ -48,7 +48,7 @@ def _march(xyz, tri, dt, waves_, n, precision, solver="lu"):
     return out, inf
 
 
-# stated bound of the FP32 band values (carried rounding) and FP32 P_E, P_M
+# stated bound of the FP32 band values (carried rounding)
 FAC32_BOUND = {"sphere120": 1e-6, "sphere480": 1e-6, "torus": 5e-6}
 
 
@@ -69,11 +69,13 @@ def test_factored_march_against_the_oracle(case):
     _say("[%s] oracle" % case)
     jref = _oracle(xyz, tri, dt, ws, n)[:, :, 0]
     for prec in ("fac64", "fac32"):
-        j, inf = _march(xyz, tri, dt, ws, n, prec)
-        err = _err(j[:, :, 0], jref)
-        _say("[%s] %s: current err vs oracle %.3e (ne=%d K=%d, %d band bytes)"
-             % (case, prec, err, inf["ne"], inf["K"], inf["slab_bytes"]))
-        assert err < (1e-10 if prec == "fac64" else FAC32_BOUND[case])
+        # LU back-solves, and the inverse folded into the [P_E P_M] product
+        for solver in ("lu", "inv"):
+            j, inf = _march(xyz, tri, dt, ws, n, prec, solver)
+            err = _err(j[:, :, 0], jref)
+            _say("[%s] %s %s: current err vs oracle %.3e (ne=%d K=%d, %d band bytes)"
+                 % (case, prec, solver, err, inf["ne"], inf["K"], inf["slab_bytes"]))
+            assert err < (1e-10 if prec == "fac64" else FAC32_BOUND[case])
 
 
 def test_factored_equals_dense_blocks_at_101_lags():
