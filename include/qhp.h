@@ -213,7 +213,10 @@ typedef struct {
                                                      batch of those kernels  */
     int64_t band_block;                         /* steps of a far pass (0: the
                                                    lags are all near)        */
-    size_t band_bytes_near_pairs, band_bytes_near_cells; /* near bands' bytes */
+    size_t band_bytes_near_pairs, band_bytes_near_cells; /* near bands' bytes:
+                                                   row lists (values, a 4-byte
+                                                   column-and-lag word each,
+                                                   row starts)              */
 } qhp_info;
 
 /* Create a context (no device work beyond selecting params->device).

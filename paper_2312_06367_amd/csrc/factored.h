@@ -55,9 +55,13 @@ struct Band {
     int np = 1;             // 1 KB copy pieces per batch (two batch buffers a wave)
     int block = 1;          // steps of one pass (products per value); 1: one step
     int64_t cmax = 0;       // most chunks holding values in one row block
-    bool direct = false;    // runs of at most kBandStep lags: the direct product (no LDS staging)
+    bool direct = false;    // runs of at most kBandStep lags: stored as row lists, the row product
     DBuf hdr, tile, stream;
     DBuf clist, clen;       // clist[rb][j], j < clen[rb]: the chunks of row block rb that hold values
+    // row lists (direct bands): row r holds entries rptr[r] .. rptr[r + 1] - 1,
+    // each a value (FP32 or FP64, the group stream's) and col << 4 | k, in
+    // column then lag order; the group stream is freed
+    DBuf rptr, rval, rcode;
 };
 
 // Build a family from dense FP64 lag matrices, rows and columns in the

@@ -15,7 +15,6 @@ namespace {
 
 constexpr int CW = kBandChunk;  // columns of a chunk
 constexpr int META = 4 * 64;    // bytes of a group's words
-constexpr int kDirectChunks = 4;  // chunks of a row pair one wave of the direct product takes
 
 // value (k, r, c) of a family in stored order: rows r < split from a, the
 // others from b (row r - split), through the row and column orders rp, cp
@@ -182,6 +181,59 @@ static int band_splits(int64_t nrb, int64_t nch)
     return best;
 }
 
+// The group stream of a band read back and rewritten as row lists: row r =
+// 2q + h takes, chunk by chunk, the runs of lanes 32h .. 32h + 31 of group
+// (q, chunk), lag by lag; the values are copied unchanged.
+static void to_row_lists(hipStream_t s, Band &b, bool fp32, const std::vector<uint64_t> &hdr, int64_t qpb)
+{
+    const int64_t nq = (b.rows + 1) / 2, nch = b.nch;
+    const size_t vsz = fp32 ? 4 : 8;
+    std::vector<char> st(b.bytes);
+    if (b.bytes)
+        hip_check(hipMemcpyAsync(st.data(), b.stream.p, b.bytes, hipMemcpyDeviceToHost, s), "band stream");
+    hip_check(hipStreamSynchronize(s), "band stream");
+    std::vector<int64_t> rptr(b.rows + 1, 0);
+    std::vector<char> val;
+    std::vector<uint32_t> code;
+    val.reserve((size_t)b.nnz * vsz);
+    code.reserve((size_t)b.nnz);
+    for (int64_t q = 0; q < nq; ++q)
+        for (int hf = 0; hf < 2; ++hf) {
+            const int64_t r = 2 * q + hf;
+            if (r >= b.rows) break;
+            for (int64_t ch = 0; ch < nch; ++ch) {
+                const uint64_t h = hdr[((q / qpb) * nch + ch) * qpb + q % qpb];
+                if ((h >> 40) == 0) continue;
+                const char *g = st.data() + (h & ((1ull << 40) - 1)) * 16;
+                const uint32_t *w = reinterpret_cast<const uint32_t *>(g);
+                int64_t start = 0;
+                for (int l = 0; l < 64; ++l) {
+                    const int64_t klo = w[l] & 0xffff, len = w[l] >> 16;
+                    if (l / CW == hf)
+                        for (int64_t p = 0; p < len; ++p) {
+                            const char *v = g + META + (start + p) * vsz;
+                            val.insert(val.end(), v, v + vsz);
+                            code.push_back((uint32_t)((ch * CW + l % CW) << 4 | (klo + p)));
+                        }
+                    start += len;
+                }
+            }
+            rptr[r + 1] = (int64_t)code.size();
+        }
+    if ((int64_t)code.size() != b.nnz) throw Fail{QHP_EINVAL, "near band: row lists do not hold every value"};
+    b.stream.release();
+    b.hdr.release();
+    b.clist.release();
+    b.clen.release();
+    upload(b.rptr, rptr, s);
+    b.rval.alloc(std::max<size_t>(val.size(), 16));
+    if (!val.empty())
+        hip_check(hipMemcpyAsync(b.rval.p, val.data(), val.size(), hipMemcpyHostToDevice, s), "row lists");
+    upload(b.rcode, code, s);
+    hip_check(hipStreamSynchronize(s), "row lists");
+    b.bytes = val.size() + code.size() * 4 + rptr.size() * 8;
+}
+
 void build_band(hipStream_t s, int64_t rows, int64_t cols, int64_t lag0, int64_t lag1, const double *srcA,
                 const double *srcB, int64_t split, int64_t lag_stride, int64_t row_stride, const int32_t *rp,
                 const int32_t *cp, bool fp32, Band &out, int64_t kfirst, int block)
@@ -343,9 +395,13 @@ void build_band(hipStream_t s, int64_t rows, int64_t cols, int64_t lag0, int64_t
                        out.hdr.as<uint64_t>(), meta.as<uint32_t>(), out.stream.as<char>());
     hip_check(hipStreamSynchronize(s), "band fill");
     out.nsplit = out.cmax ? band_splits(out.nrb, out.cmax) : 1;
-    // runs of at most kBandStep lags (a near band): the direct product, one partial
+    // runs of at most kBandStep lags (a near band): row lists, one partial
     out.direct = block == 1 && lag1 - kfirst + 1 <= kBandStep;
-    if (out.direct) out.nsplit = (int)std::max<int64_t>(1, (out.cmax + kDirectChunks - 1) / kDirectChunks);
+    if (out.direct) {
+        if (lag1 >= 16 || cols >= (1ll << 28)) throw Fail{QHP_EINVAL, "near band too wide for its row lists"};
+        out.nsplit = 1;
+        to_row_lists(s, out, fp32, hdr, qpb);
+    }
 }
 
 namespace {
@@ -615,45 +671,49 @@ __global__ __launch_bounds__(64 * W) void k_band(int64_t rows, int64_t nch, int6
 }
 
 // The product of a band of short runs (at most kBandStep lags, the near
-// lags): one wave per row pair and split of its row block's list of chunks
-// that hold values (cps chunks a split, so the chains of dependent loads stay
-// short), values and x read straight from memory (the few ring slots stay in
-// L2), no LDS and no barrier; lane l takes pair l of a group.  FP64 sums per
-// lane, reduced over each half-wave (one row), one partial per split.
+// lags) from its row lists: one wave per row, the lanes over its entries
+// (kRowUnroll entries a lane in flight: the values and words, then the x
+// they name, which the few ring slots keep in L2), FP64 sums per lane
+// reduced over the wave, one partial per row.
+constexpr int kRowUnroll = 4;
 template <typename T>
-__global__ __launch_bounds__(256) void k_band_direct(int64_t rows, int64_t nch, int64_t qpb, int64_t cps,
-                                                     const uint64_t *__restrict__ hdr,
-                                                     const int32_t *__restrict__ clist,
-                                                     const int32_t *__restrict__ clen, const char *__restrict__ stream,
-                                                     const double *__restrict__ x, int64_t ldx, int64_t K,
-                                                     int64_t head, int64_t slot0, double *__restrict__ part)
+__global__ __launch_bounds__(256) void k_band_rows(int64_t rows, const int64_t *__restrict__ rptr,
+                                                   const T *__restrict__ val, const uint32_t *__restrict__ code,
+                                                   const double *__restrict__ x, int64_t ldx, int64_t K,
+                                                   int64_t head, int64_t slot0, double *__restrict__ part)
 {
-    const int lane = threadIdx.x & 63, col = lane & (CW - 1);
-    const int64_t q = __builtin_amdgcn_readfirstlane((int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6));
-    if (q >= (rows + 1) / 2) return;  // whole waves
-    const int64_t rb = q / qpb, i = q % qpb, sp = blockIdx.y;
-    const int64_t j0 = sp * cps, n = clen[rb], j1 = j0 + cps < n ? j0 + cps : n;
+    const int lane = threadIdx.x & 63;
+    const int64_t r = __builtin_amdgcn_readfirstlane((int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    if (r >= rows) return;  // whole waves
+    const int64_t beg = rptr[r], end = rptr[r + 1];
     double acc = 0.0;
-    for (int64_t j = j0; j < j1; ++j) {
-        const int64_t ch = clist[rb * nch + j];
-        const uint64_t h = hdr[(rb * nch + ch) * qpb + i];
-        if ((h >> 40) == 0) continue;
-        const char *g = stream + (h & ((1ull << 40) - 1)) * 16;
-        const uint32_t w = reinterpret_cast<const uint32_t *>(g)[lane];
-        const int len = (int)(w >> 16), klo = (int)(w & 0xffff);
-        const int start = wave_incl_sum(len) - len;
-        const T *vals = reinterpret_cast<const T *>(g + META) + start;
-        const int64_t cc = ch * CW + col;
-        for (int p = 0; p < len; ++p) {
-            const int64_t k = klo + p;
+    for (int64_t t0 = beg; t0 < end; t0 += 64 * kRowUnroll) {
+        T v[kRowUnroll];
+        uint32_t c[kRowUnroll];
+        // no branch between the loads: an entry past the row's end loads the
+        // row's last one (t0 < end) and is masked to value 0, word 0 (lag 0,
+        // column 0: an x inside the ring)
+#pragma unroll
+        for (int u = 0; u < kRowUnroll; ++u) {
+            const int64_t t = t0 + 64 * u + lane, tc = t < end ? t : end - 1;
+            const T vv = val[tc];
+            const uint32_t cc = code[tc];
+            v[u] = t < end ? vv : T(0);
+            c[u] = t < end ? cc : 0u;
+        }
+        double xv[kRowUnroll];
+#pragma unroll
+        for (int u = 0; u < kRowUnroll; ++u) {
+            const int64_t k = c[u] & 15, col = c[u] >> 4;
             int64_t slot = k == 0 ? slot0 : head + k - 1;
             if (k != 0 && slot >= K) slot -= K;
-            acc = fma((double)vals[p], cc < ldx ? x[slot * ldx + cc] : 0.0, acc);
+            xv[u] = x[slot * ldx + col];
         }
+#pragma unroll
+        for (int u = 0; u < kRowUnroll; ++u) acc = fma((double)v[u], xv[u], acc);
     }
-    for (int off = CW / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    const int64_t r = 2 * q + lane / CW;
-    if (col == 0 && r < rows) part[sp * rows + r] = acc;
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) part[r] = acc;
 }
 
 template <typename T, int W, int NP, int BB>
@@ -709,17 +769,13 @@ void launch_band(hipStream_t s, const Band &b, bool fp32, const double *x, int64
                  int64_t slot0, double *part)
 {
     if (b.direct) {
-        const int64_t qpb = (int64_t)b.waves * band_groups_per_wave(b.block);
-        const int64_t cps = (b.cmax + b.nsplit - 1) / b.nsplit;
-        const dim3 grid(nblk((b.rows + 1) / 2 * 64, 256), (unsigned)b.nsplit);
+        const dim3 grid(nblk(b.rows * 64, 256));
         if (fp32)
-            hipLaunchKernelGGL(k_band_direct<float>, grid, dim3(256), 0, s, b.rows, b.nch, qpb, cps,
-                               b.hdr.as<uint64_t>(), b.clist.as<int32_t>(), b.clen.as<int32_t>(), b.stream.as<char>(),
-                               x, ldx, K, head, slot0, part);
+            hipLaunchKernelGGL(k_band_rows<float>, grid, dim3(256), 0, s, b.rows, b.rptr.as<int64_t>(),
+                               b.rval.as<float>(), b.rcode.as<uint32_t>(), x, ldx, K, head, slot0, part);
         else
-            hipLaunchKernelGGL(k_band_direct<double>, grid, dim3(256), 0, s, b.rows, b.nch, qpb, cps,
-                               b.hdr.as<uint64_t>(), b.clist.as<int32_t>(), b.clen.as<int32_t>(), b.stream.as<char>(),
-                               x, ldx, K, head, slot0, part);
+            hipLaunchKernelGGL(k_band_rows<double>, grid, dim3(256), 0, s, b.rows, b.rptr.as<int64_t>(),
+                               b.rval.as<double>(), b.rcode.as<uint32_t>(), x, ldx, K, head, slot0, part);
         return;
     }
     if (!band_shape_built(b.waves, b.np)) throw Fail{QHP_EINVAL, "band kernel shape not built"};
