@@ -180,3 +180,47 @@ def test_factored_few_lags_against_the_oracle(dt):
     err = _err(j[:, :, 0], jref[:, :, 0])
     _say("[few lags] c dt %.2f: K = %d, band_block %d: fac64 vs oracle %.3e" % (dt, inf["K"], inf["band_block"], err))
     assert err < 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fac64", "fac32"])
+def test_factored_solver_switch_mid_march(precision):
+    """A factored context changes solver between calls: the inverse solve
+    (y_i = T_0^{-1} r_i - T_0^{-1} [P_E P_M] [E; M], both factors formed
+    ahead) and the LU back-solves of r_i - [P_E P_M] [E; M] (Sec. IV-B, the
+    one solve per step) alternate over 10 + 9 + 11 steps and equal one LU
+    run of the 30 steps to rounding."""
+    import paper_2312_06367_amd as qhp
+    from workloads import meshes, waves
+    xyz, tri = meshes.icosphere(1)
+    ws = waves.batched_waves(1, 0, 0.1, 0.1, 2.0)
+    n = 30
+
+    def solver():
+        s = qhp.Solver(0.15, precision="fac64", solver="lu")
+        s.mesh(xyz, tri)
+        s.assemble()
+        if precision != "fac64":
+            s.set_precision(precision)
+        s.set_incident(ws[:1], n)
+        return s
+
+    s = solver()
+    ne = s.info()["ne"]
+    one = torch.zeros((n, ne, 1), dtype=torch.float64, device="cuda")
+    s.run(n, one)
+    s.close()
+    s = solver()
+    mixed = torch.zeros_like(one)
+    s.set_solver("inv")
+    s.run(10, mixed[:10])
+    s.set_solver("lu")
+    s.run(9, mixed[10:19])
+    s.set_solver("inv")
+    s.run(11, mixed[19:])
+    s.close()
+    a, b = one.cpu().numpy(), mixed.cpu().numpy()
+    err = float(np.abs(a - b).max() / np.abs(a).max())
+    _say("[solver switch] %s: inv 10 + lu 9 + inv 11 vs one lu run of 30: %.3e" % (precision, err))
+    # the two solves differ by the rounding order of FP64 sums (3e-13 over a
+    # whole 7680-edge march)
+    assert err < 1e-11
