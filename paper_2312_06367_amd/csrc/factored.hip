@@ -555,9 +555,11 @@ __global__ __launch_bounds__(64 * W) void k_band(int64_t rows, int64_t nch, int6
     // row), column idx % CW; the first XR * 64 W elements go through
     // registers, loaded a chunk ahead
     constexpr int XR = (kBandPrefetchLags * CW + 64 * W - 1) / (64 * W);
+    // lags 1 .. K: head + k - 1 < 2K, one subtraction wraps the ring
     auto x_at = [&](int64_t ch, int tk0, int idx) {
         const int64_t k = tk0 - (BB - 1) + idx / CW, cc = CLk(ch) * CW + idx % CW;
-        const int64_t slot = k == 0 ? slot0 : (head + k - 1) % K;
+        int64_t slot = k == 0 ? slot0 : head + k - 1;
+        if (k != 0 && slot >= K) slot -= K;
         return cc < ldx ? x[slot * ldx + cc] : 0.0;
     };
     double xpre[XR];
@@ -624,20 +626,26 @@ __global__ __launch_bounds__(64 * W) void k_band(int64_t rows, int64_t nch, int6
                 for (int b = 0; b < BB; ++b) sum[b] = 0.0;
                 // kBandStep lags a step, every read issued before the
                 // products; a lane past its run reads the values after it (in
-                // LDS) and zero or staged x rows, and adds zero products
+                // LDS) and zero or staged x rows, and adds zero products.  The
+                // x window (rows p .. p + kBandStep + BB - 2) keeps its last
+                // BB - 1 rows for the next step, which reads kBandStep new ones
+                double xv[kBandStep + BB - 1];
+#pragma unroll
+                for (int j = 0; j < BB - 1; ++j) xv[j] = xr[j * CW];
                 for (int p = 0; p < mx; p += kBandStep) {
                     T v[kBandStep];
-                    double xv[kBandStep + BB - 1];
 #pragma unroll
                     for (int u = 0; u < kBandStep; ++u) v[u] = vals[p + u];
 #pragma unroll
-                    for (int j = 0; j < kBandStep + BB - 1; ++j) xv[j] = xr[(p + j) * CW];
+                    for (int j = BB - 1; j < kBandStep + BB - 1; ++j) xv[j] = xr[(p + j) * CW];
 #pragma unroll
                     for (int u = 0; u < kBandStep; ++u) {
                         const double mv = masked(v[u], p + u < len);
 #pragma unroll
                         for (int b = 0; b < BB; ++b) sum[b] = fma(mv, xv[u + BB - 1 - b], sum[b]);
                     }
+#pragma unroll
+                    for (int j = 0; j < BB - 1; ++j) xv[j] = xv[j + kBandStep];
                 }
 #pragma unroll
                 for (int b = 0; b < BB; ++b) acc[q][b] += sum[b];
