@@ -30,8 +30,13 @@ constexpr int kBandPrefetchLags = 128;  // lags of a chunk's x loaded ahead thro
 // products); the near lags (k < kBandBlock) are applied every step
 constexpr int kBandBlock = 8;
 // groups (row pairs) a wave takes in a chunk: fewer in a pass of several
-// steps, whose sums per row multiply with the steps
-constexpr int band_groups_per_wave(int block) { return block > 4 ? 4 : kBandRowsPerWave / 2; }
+// steps, whose sums per row multiply with the steps, and fewer again from 12
+// waves a work-group on (at 16 waves, four waves a SIMD: at most 128
+// registers a lane)
+constexpr int band_groups_per_wave(int block, int waves)
+{
+    return block > 4 ? (waves >= 12 ? 2 : 4) : kBandRowsPerWave / 2;
+}
 
 // One lag-banded family of matrices X_k, k in [lag0, lag1], rows x cols.
 // Rows 2q, 2q + 1 and the chunk ch of kBandChunk columns form the group

@@ -310,9 +310,8 @@ void build_band(hipStream_t s, int64_t rows, int64_t cols, int64_t lag0, int64_t
     std::vector<uint32_t> tile, tw;
     int waves = 0, np = 0, tmax = 0;
     for (int w : kBandWaves) {
-        if (block > 1 && w > 12) continue;  // the pass's kBandBlock sums a row need the registers of <= 12 waves
         if (small && w != 8 && waves) continue;
-        const int tm = tiles((int64_t)w * band_groups_per_wave(block), tw);
+        const int tm = tiles((int64_t)w * band_groups_per_wave(block, w), tw);
         int p = 0;  // the largest batch built for this size that fits (small: the smallest that holds a group)
         for (int q : kBandPieces)
             if (band_shape_built(w, q) && band_lds(tm, lm, w, q, fp32, block) <= (size_t)kBandLdsBytes &&
@@ -329,8 +328,9 @@ void build_band(hipStream_t s, int64_t rows, int64_t cols, int64_t lag0, int64_t
             continue;
         }
         // a pass of several steps does several products per value: its walk
-        // needs more waves to hide, counted in full up to 12
-        auto score = [&](int w_, int p_) { return w_ * p_ * std::min(w_, block > 1 ? 12 : 8); };
+        // needs more waves to hide, counted in full up to 16 (two groups a wave
+        // at 16 waves keep the kBandBlock sums a row within 128 registers)
+        auto score = [&](int w_, int p_) { return w_ * p_ * std::min(w_, block > 1 ? 16 : 8); };
         if (!waves || score(w, p) > score(waves, np)) {
             waves = w;
             np = p;
@@ -355,7 +355,7 @@ void build_band(hipStream_t s, int64_t rows, int64_t cols, int64_t lag0, int64_t
                          tr[tr.size() * 9 / 10], tr.back());
     }
     if (!waves) throw Fail{QHP_EINVAL, "factored history: a band group does not fit the LDS"};
-    const int64_t qpb = (int64_t)waves * band_groups_per_wave(block);
+    const int64_t qpb = (int64_t)waves * band_groups_per_wave(block, waves);
     out.nrb = (nq + qpb - 1) / qpb;
     // offsets in stored order: row block, chunk, group (the headers of a
     // wave's groups in one chunk are consecutive)
@@ -490,7 +490,7 @@ __global__ __launch_bounds__(64 * W) void k_band(int64_t rows, int64_t nch, int6
                                                  int64_t ldx, int64_t K, int64_t head, int64_t slot0, int xrows,
                                                  double *__restrict__ part)
 {
-    constexpr int GW = band_groups_per_wave(BB);  // groups (row pairs) of a wave in a chunk
+    constexpr int GW = band_groups_per_wave(BB, W);  // groups (row pairs) of a wave in a chunk
     extern __shared__ double smem[];
     double *X = smem;
     // the wave index is uniform: group quantities below stay in scalar registers
@@ -762,7 +762,7 @@ static void band_dispatch(hipStream_t s, const Band &b, bool fp32, const double 
 {
     switch (b.waves) {
     case 16:
-        if constexpr (BB == 1) return band_pieces<T, 16, BB>(s, b, fp32, x, ldx, K, head, slot0, part);
+        return band_pieces<T, 16, BB>(s, b, fp32, x, ldx, K, head, slot0, part);
         break;
     case 12: return band_pieces<T, 12, BB>(s, b, fp32, x, ldx, K, head, slot0, part);
     case 8: return band_pieces<T, 8, BB>(s, b, fp32, x, ldx, K, head, slot0, part);
