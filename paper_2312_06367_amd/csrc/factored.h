@@ -60,7 +60,7 @@ struct Band {
     int np = 1;             // 1 KB copy pieces per batch (two batch buffers a wave)
     int block = 1;          // steps of one pass (products per value); 1: one step
     int64_t cmax = 0;       // most chunks holding values in one row block
-    bool direct = false;    // runs of at most kBandStep lags: stored as row lists, the row product
+    bool direct = false;    // a one-step band (block 1): stored as row lists, the row product
     DBuf hdr, tile, stream;
     DBuf clist, clen;       // clist[rb][j], j < clen[rb]: the chunks of row block rb that hold values
     // row lists (direct bands): row r holds entries rptr[r] .. rptr[r + 1] - 1,
@@ -76,8 +76,9 @@ struct Band {
 // fp32: values rounded to FP32 with the rounding carried along each pair's lags
 // from lag0.  Only the lags kfirst..lag1 are stored (kfirst < 0: lag0), so the
 // bands of two adjacent lag ranges hold exactly the values of the band of both.
-// block: the steps of one pass of the product (1, or kBandBlock for lags
-// >= kBandBlock).
+// block: the steps of one pass of the product: kBandBlock for lags >=
+// kBandBlock, or 1 for a one-step band (lags < 16), which is then rewritten
+// as row lists.
 void build_band(hipStream_t s, int64_t rows, int64_t cols, int64_t lag0, int64_t lag1, const double *srcA,
                 const double *srcB, int64_t split, int64_t lag_stride, int64_t row_stride, const int32_t *rp,
                 const int32_t *cp, bool fp32, Band &out, int64_t kfirst = -1, int block = 1);

@@ -395,8 +395,8 @@ void build_band(hipStream_t s, int64_t rows, int64_t cols, int64_t lag0, int64_t
                        out.hdr.as<uint64_t>(), meta.as<uint32_t>(), out.stream.as<char>());
     hip_check(hipStreamSynchronize(s), "band fill");
     out.nsplit = out.cmax ? band_splits(out.nrb, out.cmax) : 1;
-    // runs of at most kBandStep lags (a near band): row lists, one partial
-    out.direct = block == 1 && lag1 - kfirst + 1 <= kBandStep;
+    // a one-step band (the near lags): row lists, one partial
+    out.direct = block == 1;
     if (out.direct) {
         if (lag1 >= 16 || cols >= (1ll << 28)) throw Fail{QHP_EINVAL, "near band too wide for its row lists"};
         out.nsplit = 1;
@@ -787,10 +787,7 @@ void launch_band(hipStream_t s, const Band &b, bool fp32, const double *x, int64
         return;
     }
     if (!band_shape_built(b.waves, b.np)) throw Fail{QHP_EINVAL, "band kernel shape not built"};
-    if (b.block == 1) {
-        if (fp32) band_dispatch<float, 1>(s, b, fp32, x, ldx, K, head, slot0, part);
-        else band_dispatch<double, 1>(s, b, fp32, x, ldx, K, head, slot0, part);
-    } else if (b.block == kBandBlock) {
+    if (b.block == kBandBlock) {
         if (fp32) band_dispatch<float, kBandBlock>(s, b, fp32, x, ldx, K, head, slot0, part);
         else band_dispatch<double, kBandBlock>(s, b, fp32, x, ldx, K, head, slot0, part);
     } else {
