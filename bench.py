@@ -82,9 +82,10 @@ def workload(name, n_dirs):
     return waves.torus_batched(n_dirs)
 
 
-def traffic_from_profile(kernel_name):
+def traffic_from_profile(kernel_name, variant=None):
     """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel source (else None)."""
+    taken on the current kernel source and, for an autotuned kernel, on the
+    variant in use (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -92,6 +93,8 @@ def traffic_from_profile(kernel_name):
         rec = json.load(open(path))
         ent = rec.get("kernels", {}).get(kernel_name)
         if not ent:
+            return None
+        if variant is not None and ent.get("variant_index") is not None and ent["variant_index"] != variant:
             return None
         src = open(os.path.join(ROOT, "paper_2312_06367_amd", "csrc", ent["source"]), "rb").read()
         if ent.get("source_sha256") != hashlib.sha256(src).hexdigest():
@@ -614,8 +617,8 @@ def bench_single(a, cfg, precision, steps, warmup, err_steps, quick, with_cpu):
                  "bf16": "k_hist_gemv<unsigned short,float,float>"}[precision]
         achieved = bytes_per_launch / (head["hist_ms"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_from_profile(kname),
-                "kernel": kname, "algorithmic_bytes_per_launch": bytes_per_launch,
+                "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_from_profile(kname, head["variant"]),
+                "kernel": kname, "variant": head["variant"], "algorithmic_bytes_per_launch": bytes_per_launch,
                 "kernel_ms_avg": head["hist_ms"]}
     elif precision in ("bf16", "bf16x2"):
         # BF16 matrix cores: five (pair) or two BF16 products per term; the
